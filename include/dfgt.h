@@ -1,0 +1,177 @@
+/*
+ * dfgt.h - C ABI of the MI355X dual-tree fast Gauss transform library (libdfgt.so).
+ *
+ * The library computes the Gaussian kernel sums of Section 1.1,
+ * eq. (gaussian_kernel_sums), of "Dual-Tree Fast Gauss Transforms"
+ * (Lee, Gray, Moore):
+ *
+ *     G(q_i, R) = sum_{r_j in R} exp(-||q_i - r_j||^2 / (2 h^2))
+ *
+ * with the hard per-query relative error bound |G~ - G| <= eps * G of the
+ * paper's Definition (bounding the relative error) and its global-error
+ * theorem (Section 3.10), by the hierarchical DFGT of Section 3.9.
+ *
+ * Conventions shared by every entry point
+ *   - Plain C types only.  Pointers named *_dev are device (HIP) pointers,
+ *     *_host are host pointers.  The caller owns every buffer it passes; the
+ *     library owns tree handles and its internal workspace.
+ *   - Points are float64, row-major [n][d].
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on that stream.  Entry points that return host results
+ *     (lscv, backward h-gradients, stats, exports) synchronise the stream.
+ *   - Every call returns a dfgt_status; on failure dfgt_last_error() returns a
+ *     message for the calling thread.  No C++ exception crosses the ABI.
+ *   - Handles are not thread-safe: use one handle from one thread at a time.
+ */
+#ifndef DFGT_H
+#define DFGT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dfgt_status {
+    DFGT_OK = 0,
+    DFGT_EINVAL = 1, /* an argument is out of range (message says which) */
+    DFGT_ENOMEM = 2, /* device or host allocation failed */
+    DFGT_EHIP = 3,   /* a HIP runtime call failed */
+    DFGT_EBOUND = 5  /* the error guarantee cannot be certified for this input */
+} dfgt_status;
+
+/* Precision of the exhaustive leaf-leaf sums (DFGTBase, Section 3.9). */
+enum {
+    DFGT_PREC_MIXED = 0, /* FP64 coordinate differences, FP32 exp, FP64 per-query sums */
+    DFGT_PREC_FP64 = 1   /* FP64 throughout */
+};
+
+/* Restriction of the summarisation methods (Section 3.2's E, F(c,p), D(c,p),
+ * T(c,p)); anything other than DFGT_FORCE_NONE is a test and ablation knob. */
+enum {
+    DFGT_FORCE_NONE = 0,
+    DFGT_FORCE_F = 1,        /* only far-field evaluation may prune */
+    DFGT_FORCE_D = 2,        /* only direct local accumulation */
+    DFGT_FORCE_T = 3,        /* only far-to-local translation (incl. centroid form) */
+    DFGT_FORCE_CENTROID = 4, /* only the centroid T(c,1) with the finite-difference bound */
+    DFGT_FORCE_EXACT = 5     /* no pruning at all: every leaf pair is exhaustive */
+};
+
+typedef struct dfgt_options {
+    int32_t leaf_size;    /* kd-tree leaf threshold (Alg. BuildKdTree); 0 = 32 */
+    int32_t p_max;        /* terms per dimension kept in every expansion; 0 = the
+                             paper's experimental table (Section 3.9): 6 for D<=2,
+                             4 for D=3, 2 for D=4,5, 1 for D>=6 */
+    int32_t precision;    /* DFGT_PREC_* */
+    int32_t force_method; /* DFGT_FORCE_* */
+    int32_t reserved[4];  /* must be zero */
+} dfgt_options;
+
+/* Counters of one gauss_sum call (summed over its bandwidths). */
+typedef struct dfgt_stats {
+    int64_t node_pairs;     /* node pairs visited by the traversal */
+    int64_t prune_f;        /* pairs summarised by far-field evaluation */
+    int64_t prune_d;        /* ... by direct local accumulation */
+    int64_t prune_t;        /* ... by far-to-local translation, order >= 2 */
+    int64_t prune_centroid; /* ... by the centroid form T(c,1) */
+    int64_t base_leaf_pairs;  /* exhaustive leaf-leaf pairs */
+    int64_t base_point_pairs; /* exhaustive point pairs */
+    int64_t levels;         /* traversal levels executed */
+    int64_t max_order;      /* largest expansion order used */
+    int64_t fp64_groups;    /* exhaustive groups computed in FP64 by the underflow guard */
+    int64_t reserved[6];
+} dfgt_stats;
+
+typedef struct dfgt_tree_s *dfgt_tree;
+
+/* Last error message of the calling thread ("" if none). */
+const char *dfgt_last_error(void);
+
+/* Library version string. */
+const char *dfgt_version(void);
+
+/*
+ * Builds the mid-point kd-tree of Section 2.1, Alg. BuildKdTree, on the GPU.
+ *   pts_dev  n x d float64, row-major; read during the call only (the tree
+ *            keeps its own permuted copy).
+ *   opt      NULL for defaults.  leaf_size and the tree's permutation follow
+ *            the algorithm exactly: boxes are the exact min/max of the node's
+ *            points, the split dimension is the widest one (lowest index on
+ *            ties), the split coordinate is the FP64 mid-point, points with
+ *            x[sd] <= sc go left, the partition is stable, and a node is a leaf
+ *            when it holds <= leaf_size points, has zero width, or one side
+ *            would be empty.
+ *   out      receives the handle; free it with dfgt_tree_free.
+ * The call also computes the node's raw far-field moments (Alg. DFGTInitR:
+ * AccumulateFarFieldMoment at leaves, TransFarToFar upwards).
+ * Errors: n < 1, d < 1 or d > 32, p_max^d > 8192, non-finite input, a
+ * non-zero reserved field -> DFGT_EINVAL.  Synchronises the stream.
+ */
+dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const dfgt_options *opt,
+                            void *stream, dfgt_tree *out);
+
+/* Frees a tree handle (NULL is allowed). */
+dfgt_status dfgt_tree_free(dfgt_tree t);
+
+/* Sizes of a tree: points, dimension, nodes, levels, p_max. Any pointer may be NULL. */
+dfgt_status dfgt_tree_info(dfgt_tree t, int64_t *n, int32_t *d, int64_t *n_nodes, int32_t *depth,
+                           int32_t *p_max);
+
+/*
+ * Copies the tree to host arrays (test hook).  Nodes are in breadth-first
+ * order (root = 0; children of level-l nodes follow level l in parent order,
+ * left before right).  Sizes: perm[n]; lo, hi[n_nodes*d] (node-major);
+ * begin, end, left, right, split_dim[n_nodes]; split_coord[n_nodes].
+ * perm[k] is the caller's index of the k-th point in tree order; begin/end
+ * index tree order; left/right are -1 for leaves, split_dim is -1 for leaves.
+ * Any pointer may be NULL.
+ */
+dfgt_status dfgt_tree_export(dfgt_tree t, int32_t *perm_host, double *lo_host, double *hi_host,
+                             int32_t *begin_host, int32_t *end_host, int32_t *left_host,
+                             int32_t *right_host, int32_t *split_dim_host,
+                             double *split_coord_host);
+
+/*
+ * Raw (bandwidth-free) far-field moments of every node (test hook):
+ *     mu_alpha(N) = sum_{x in N} (x - N.c)^alpha / alpha!,  alpha < p_max,
+ * N.c the box centre.  The paper's moments of Section 3.3,
+ * eq. (far_field_moments), are M_alpha = (2h^2)^(-|alpha|/2) mu_alpha.
+ * mu_host: n_nodes x p_max^d float64, breadth-first node order, each vector
+ * radix p_max with the last dimension fastest (Appendix, linear layout).
+ */
+dfgt_status dfgt_tree_moments(dfgt_tree t, double *mu_host);
+
+/*
+ * Brute-force Gaussian sums, Alg. NaiveKDE (Section 1), as a tiled GPU kernel:
+ *     G_dev[k*nq + i] = sum_j exp(-||q_i - r_j||^2 / (2 h_k^2)).
+ *   q_dev nq x d, r_dev nr x d (float64 row-major), h_host[n_h] > 0,
+ *   precision DFGT_PREC_*, G_dev n_h x nq float64 (caller-allocated).
+ * Asynchronous on stream.
+ */
+dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev, int64_t nr,
+                           int32_t d, const double *h_host, int32_t n_h, int32_t precision,
+                           double *G_dev, void *stream);
+
+/*
+ * Dual-tree fast Gauss transform, Section 3.9 (DFGTMain):
+ *     G_dev[k*NQ + i] ~= sum_j exp(-||q_i - r_j||^2 / (2 h_k^2))
+ * for every query i in the caller's order, with |G~ - G| <= eps * G for every
+ * i and k (the global-error theorem of Section 3.10).
+ *   Q, R     tree handles of the same dimension (Q == R is the monochromatic
+ *            cross-validation case; the self term is included).
+ *   h_host   n_h bandwidths > 0; all are processed in one traversal.
+ *   eps      in [0, 1).  eps = 0 prunes only where the bound is exactly zero.
+ *   opt      NULL for the options R was built with (precision, force_method
+ *            are read from here; leaf_size / p_max are the trees').
+ *   G_dev    n_h x NQ float64, caller-allocated.
+ *   stats    NULL, or counters (forces a stream synchronisation).
+ * Errors: mismatched dimensions or p_max, h <= 0, eps outside [0,1) -> EINVAL.
+ */
+dfgt_status dfgt_gauss_sum(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                           const dfgt_options *opt, double *G_dev, dfgt_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DFGT_H */

@@ -1,0 +1,215 @@
+// C ABI of libdfgt: argument validation, error strings, handle ownership.
+// Every entry point catches C++ exceptions so none crosses the ABI.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "dfgt_internal.h"
+
+namespace dfgt {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+int default_pmax(int d) {
+    // p_max of the paper's experiments (Section 3.9)
+    if (d <= 2) return 6;
+    if (d == 3) return 4;
+    if (d <= 5) return 2;
+    return 1;
+}
+
+}  // namespace dfgt
+
+using namespace dfgt;
+
+#define DFGT_GUARD_BEGIN \
+    clear_error();       \
+    try {
+#define DFGT_GUARD_END                                               \
+    }                                                                \
+    catch (const std::bad_alloc &) {                                 \
+        set_error("host allocation failed");                         \
+        return DFGT_ENOMEM;                                          \
+    }                                                                \
+    catch (const std::exception &e) {                                \
+        set_error(std::string("internal error: ") + e.what());       \
+        return DFGT_EHIP;                                            \
+    }                                                                \
+    catch (...) {                                                    \
+        set_error("internal error");                                 \
+        return DFGT_EHIP;                                            \
+    }
+
+extern "C" {
+
+const char *dfgt_last_error(void) { return g_err.c_str(); }
+
+const char *dfgt_version(void) { return "dfgt-mi355x 0.1 (gfx950)"; }
+
+dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const dfgt_options *opt, void *stream,
+                            dfgt_tree *out) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(out != nullptr, "dfgt_build_tree: out is NULL");
+    *out = nullptr;
+    DFGT_REQUIRE(pts_dev != nullptr, "dfgt_build_tree: pts_dev is NULL");
+    DFGT_REQUIRE(n >= 1 && n < (int64_t(1) << 30), "dfgt_build_tree: n must be in [1, 2^30)");
+    DFGT_REQUIRE(d >= 1 && d <= kMaxD, "dfgt_build_tree: d must be in [1, 32]");
+    dfgt_options o{};
+    if (opt) o = *opt;
+    for (int i = 0; i < 4; ++i) DFGT_REQUIRE(o.reserved[i] == 0, "dfgt_build_tree: reserved option field set");
+    DFGT_REQUIRE(o.leaf_size >= 0 && o.leaf_size <= 4096, "dfgt_build_tree: leaf_size must be in [0, 4096]");
+    DFGT_REQUIRE(o.p_max >= 0 && o.p_max <= 16, "dfgt_build_tree: p_max must be in [0, 16]");
+    DFGT_REQUIRE(o.precision == DFGT_PREC_MIXED || o.precision == DFGT_PREC_FP64,
+                 "dfgt_build_tree: unknown precision");
+    DFGT_REQUIRE(o.force_method >= 0 && o.force_method <= 5, "dfgt_build_tree: unknown force_method");
+    const int pmax = o.p_max ? o.p_max : default_pmax(d);
+    double P = std::pow((double)pmax, (double)d);
+    DFGT_REQUIRE(P <= kMaxP, "dfgt_build_tree: p_max^d exceeds 8192 coefficients");
+    auto *t = new dfgt_tree_s();
+    t->n = n;
+    t->d = d;
+    t->leaf = o.leaf_size ? o.leaf_size : 32;
+    t->pmax = pmax;
+    t->P = (int)P;
+    t->precision = o.precision;
+    t->force = o.force_method;
+    hipStream_t st = (hipStream_t)stream;
+    dfgt_status s = build_tree_device(t, pts_dev, st);
+    if (s == DFGT_OK) s = compute_moments(t, st);
+    if (s == DFGT_OK) {
+        DevTree v{};
+        v.n = (int32_t)t->n;
+        v.d = t->d;
+        v.m = (int32_t)t->m;
+        v.pmax = t->pmax;
+        v.P = t->P;
+        v.depth = t->depth;
+        v.nleaves = (int32_t)t->nleaves;
+        v.lo = t->lo.as<double>();
+        v.hi = t->hi.as<double>();
+        v.ctr = t->ctr.as<double>();
+        v.begin = t->begin.as<int32_t>();
+        v.end = t->end.as<int32_t>();
+        v.left = t->left.as<int32_t>();
+        v.right = t->right.as<int32_t>();
+        v.parent = t->parent.as<int32_t>();
+        v.leaves = t->leaves.as<int32_t>();
+        v.x = t->x.as<double>();
+        v.perm = t->perm.as<int32_t>();
+        v.mu = t->mu.as<double>();
+        t->host_view = v;
+        s = t->view.reserve(sizeof(DevTree));
+        if (s == DFGT_OK) {
+            if (hipMemcpyAsync(t->view.p, &v, sizeof(DevTree), hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                set_error("dfgt_build_tree: copying the tree view failed");
+                s = DFGT_EHIP;
+            }
+        }
+    }
+    if (s != DFGT_OK) {
+        delete t;
+        return s;
+    }
+    *out = t;
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_tree_free(dfgt_tree t) {
+    DFGT_GUARD_BEGIN
+    delete t;
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_tree_info(dfgt_tree t, int64_t *n, int32_t *d, int64_t *n_nodes, int32_t *depth, int32_t *p_max) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(t != nullptr, "dfgt_tree_info: tree is NULL");
+    if (n) *n = t->n;
+    if (d) *d = t->d;
+    if (n_nodes) *n_nodes = t->m;
+    if (depth) *depth = t->depth;
+    if (p_max) *p_max = t->pmax;
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_tree_export(dfgt_tree t, int32_t *perm, double *lo, double *hi, int32_t *begin, int32_t *end,
+                             int32_t *left, int32_t *right, int32_t *split_dim, double *split_coord) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(t != nullptr, "dfgt_tree_export: tree is NULL");
+    const size_t m = (size_t)t->m, d = (size_t)t->d;
+    struct Item {
+        void *dst;
+        const DevBuf *src;
+        size_t bytes;
+    } items[] = {
+        {perm, &t->perm, sizeof(int32_t) * (size_t)t->n}, {lo, &t->lo, sizeof(double) * m * d},
+        {hi, &t->hi, sizeof(double) * m * d},             {begin, &t->begin, sizeof(int32_t) * m},
+        {end, &t->end, sizeof(int32_t) * m},              {left, &t->left, sizeof(int32_t) * m},
+        {right, &t->right, sizeof(int32_t) * m},          {split_dim, &t->sdim, sizeof(int32_t) * m},
+        {split_coord, &t->scoord, sizeof(double) * m},
+    };
+    for (auto &it : items)
+        if (it.dst) DFGT_HIP(hipMemcpy(it.dst, it.src->p, it.bytes, hipMemcpyDeviceToHost));
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_tree_moments(dfgt_tree t, double *mu_host) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(t != nullptr && mu_host != nullptr, "dfgt_tree_moments: NULL argument");
+    DFGT_HIP(hipMemcpy(mu_host, t->mu.p, sizeof(double) * (size_t)t->m * t->P, hipMemcpyDeviceToHost));
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+static dfgt_status check_bandwidths(const double *h, int32_t n_h, const char *who) {
+    DFGT_REQUIRE(h != nullptr, std::string(who) + ": h_host is NULL");
+    DFGT_REQUIRE(n_h >= 1 && n_h <= 65535, std::string(who) + ": n_h must be in [1, 65535]");
+    for (int i = 0; i < n_h; ++i)
+        DFGT_REQUIRE(std::isfinite(h[i]) && h[i] > 0.0, std::string(who) + ": bandwidths must be finite and > 0");
+    return DFGT_OK;
+}
+
+dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev, int64_t nr, int32_t d,
+                           const double *h_host, int32_t n_h, int32_t precision, double *G_dev, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(q_dev && r_dev && G_dev, "dfgt_naive_sum: NULL device pointer");
+    DFGT_REQUIRE(nq >= 1 && nq < (int64_t(1) << 30) && nr >= 1 && nr < (int64_t(1) << 30),
+                 "dfgt_naive_sum: nq and nr must be in [1, 2^30)");
+    DFGT_REQUIRE(d >= 1 && d <= kMaxD, "dfgt_naive_sum: d must be in [1, 32]");
+    DFGT_REQUIRE(precision == DFGT_PREC_MIXED || precision == DFGT_PREC_FP64, "dfgt_naive_sum: unknown precision");
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_naive_sum"));
+    return launch_naive(q_dev, nq, r_dev, nr, d, h_host, n_h, precision, G_dev, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_gauss_sum(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                           const dfgt_options *opt, double *G_dev, dfgt_stats *stats, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(Q && R && G_dev, "dfgt_gauss_sum: NULL argument");
+    DFGT_REQUIRE(Q->d == R->d, "dfgt_gauss_sum: query and reference dimensions differ");
+    DFGT_REQUIRE(Q->pmax == R->pmax, "dfgt_gauss_sum: query and reference trees use different p_max");
+    DFGT_REQUIRE(std::isfinite(eps) && eps >= 0.0 && eps < 1.0, "dfgt_gauss_sum: eps must be in [0, 1)");
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum"));
+    int precision = R->precision, force = R->force;
+    if (opt) {
+        for (int i = 0; i < 4; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, "dfgt_gauss_sum: reserved option field set");
+        DFGT_REQUIRE(opt->precision == DFGT_PREC_MIXED || opt->precision == DFGT_PREC_FP64,
+                     "dfgt_gauss_sum: unknown precision");
+        DFGT_REQUIRE(opt->force_method >= 0 && opt->force_method <= 5, "dfgt_gauss_sum: unknown force_method");
+        precision = opt->precision;
+        force = opt->force_method;
+    }
+    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, G_dev, stats, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations of libdfgt (HIP, gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dfgt.h"
+
+namespace dfgt {
+
+constexpr int kMaxD = 32;
+constexpr int kMaxP = 8192;   // largest p_max^D coefficient vector
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+void clear_error();
+
+struct Status {
+    dfgt_status code = DFGT_OK;
+    bool ok() const { return code == DFGT_OK; }
+};
+
+#define DFGT_HIP(expr)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            ::dfgt::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));            \
+            return DFGT_EHIP;                                                                \
+        }                                                                                    \
+    } while (0)
+
+#define DFGT_TRY(expr)                                                                       \
+    do {                                                                                     \
+        dfgt_status s_ = (expr);                                                             \
+        if (s_ != DFGT_OK) return s_;                                                        \
+    } while (0)
+
+#define DFGT_REQUIRE(cond, msg)                                                              \
+    do {                                                                                     \
+        if (!(cond)) {                                                                       \
+            ::dfgt::set_error(msg);                                                          \
+            return DFGT_EINVAL;                                                              \
+        }                                                                                    \
+    } while (0)
+
+// ---------------------------------------------------------------- device buffers
+// A device allocation owned by host code; freed in the destructor.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Ensures at least `need` bytes (contents are not preserved on growth).
+    dfgt_status reserve(size_t need) {
+        if (need <= bytes) return DFGT_OK;
+        release();
+        size_t nb = need < 256 ? 256 : need;
+        if (hipMalloc(&p, nb) != hipSuccess) {
+            p = nullptr;
+            set_error("hipMalloc of " + std::to_string(nb) + " bytes failed");
+            return DFGT_ENOMEM;
+        }
+        bytes = nb;
+        return DFGT_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------- device views
+// Read-only device view of one kd-tree (breadth-first node order).
+struct DevTree {
+    int32_t n, d, m, pmax, P, depth, nleaves;
+    const double *lo, *hi, *ctr;          // [m][d]
+    const int32_t *begin, *end;           // [m] tree-order point ranges
+    const int32_t *left, *right, *parent; // [m], -1 = none
+    const int32_t *leaves;                // [nleaves] node ids of the leaves
+    const double *x;                      // [n][d] points in tree order (FP64)
+    const int32_t *perm;                  // [n] tree position -> caller index
+    const double *mu;                     // [m][P] raw far-field moments
+};
+
+}  // namespace dfgt
+
+// The opaque handle of the C ABI.
+struct dfgt_tree_s {
+    int64_t n = 0;
+    int32_t d = 0, leaf = 32, pmax = 1, P = 1, depth = 0, precision = 0, force = 0;
+    int64_t m = 0, nleaves = 0;
+    std::vector<int32_t> level_start;  // host copy: nodes of level l are [level_start[l], level_start[l+1])
+    dfgt::DevBuf lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu;
+    dfgt::DevBuf view;  // a DevTree in device memory
+    dfgt::DevTree host_view{};
+};
+
+namespace dfgt {
+
+// ---------------------------------------------------------------- shared device helpers
+__device__ __forceinline__ long long dbl_key(double v) {
+    long long b = __double_as_longlong(v);
+    return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+__device__ __forceinline__ double key_dbl(long long k) {
+    return __longlong_as_double(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL));
+}
+
+// Deterministic wave-wide sum (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- host entry points per file
+// naive.hip
+dfgt_status launch_naive(const double *q, int64_t nq, const double *r, int64_t nr, int d,
+                         const double *h, int nh, int precision, double *G, hipStream_t st);
+// tree.hip
+dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st);
+// moments.hip
+dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st);
+// dfgt.hip
+dfgt_status run_gauss_sum(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps,
+                          int precision, int force, double *G, dfgt_stats *stats, hipStream_t st);
+
+int default_pmax(int d);
+
+}  // namespace dfgt

@@ -1,0 +1,441 @@
+// Mid-point kd-tree (Section 2.1, Alg. BuildKdTree) built level by level on the GPU.
+//
+// The recursion of the algorithm is unrolled breadth-first: every level is one
+// pass over all points.  Per level:
+//   k_flag      each point of a splittable node evaluates x[sd] <= sc against
+//               its node's split (widest dimension, lowest index on ties, FP64
+//               mid-point) and counts the left side;
+//   k_finalize  one block decides which nodes split (non-empty sides) and
+//               allocates their children in breadth-first order;
+//   scan        exclusive prefix sum of the left flags (stable ranks);
+//   k_scatter   moves every point of a split node to its stable position in
+//               the left or right child and folds its coordinates into the
+//               child's bounding box (exact min / max through ordered-integer
+//               atomics, so the result does not depend on arrival order).
+// The result is bit-identical to the recursive algorithm (same boxes, split
+// dimensions, split coordinates and permutation); only node numbering differs
+// (breadth-first instead of pre-order).
+#include "dfgt_internal.h"
+
+namespace dfgt {
+namespace {
+
+constexpr int kTB = 256;
+constexpr long long kPosInfKey = 0x7ff0000000000000LL;                    // key of +inf
+constexpr long long kNegInfKey = (long long)0xfff0000000000000ULL ^ 0x7fffffffffffffffLL;  // key of -inf
+
+// Folds the coordinates of the active lanes into the boxes of their nodes.
+// Lanes sharing a node are reduced in-wave first; one lane per node issues the
+// atomics.  Min / max are exact, so the order of arrival does not matter.
+__device__ void wave_box_fold(bool active, int node, const double *v, int d, long long *lo_key,
+                              long long *hi_key) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int lead_node = __shfl(node, leader, 64);
+        const bool mine = active && node == lead_node;
+        for (int k = 0; k < d; ++k) {
+            long long kv = mine ? dbl_key(v[k]) : kPosInfKey;
+            long long kx = mine ? dbl_key(v[k]) : kNegInfKey;
+            for (int off = 32; off >= 1; off >>= 1) {
+                long long a = __shfl_xor(kv, off, 64);
+                long long b = __shfl_xor(kx, off, 64);
+                kv = a < kv ? a : kv;
+                kx = b > kx ? b : kx;
+            }
+            if (lane == leader) {
+                atomicMin(&lo_key[(size_t)lead_node * d + k], kv);
+                atomicMax(&hi_key[(size_t)lead_node * d + k], kx);
+            }
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
+__global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *perm, double *x, int32_t *pnode,
+                       int *bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    perm[i] = i;
+    pnode[i] = 0;
+    for (int k = 0; k < d; ++k) {
+        double v = pts[(size_t)i * d + k];
+        if (!isfinite(v)) *bad = 1;
+        x[(size_t)i * d + k] = v;
+    }
+}
+
+__global__ void k_init_root(long long *lo_key, long long *hi_key, int d, int32_t *begin, int32_t *end,
+                            int32_t *parent, int32_t *nleft, int n) {
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        lo_key[k] = kPosInfKey;
+        hi_key[k] = kNegInfKey;
+    }
+    if (threadIdx.x == 0) {
+        begin[0] = 0;
+        end[0] = n;
+        parent[0] = -1;
+        nleft[0] = 0;
+    }
+}
+
+__global__ void k_root_box(const double *__restrict__ x, int n, int d, long long *lo_key, long long *hi_key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[kMaxD];
+    const bool act = i < n;
+    if (act)
+        for (int k = 0; k < d; ++k) v[k] = x[(size_t)i * d + k];
+    wave_box_fold(act, 0, v, d, lo_key, hi_key);
+}
+
+// Split rule of one node; returns false if the node is a leaf before counting.
+__device__ __forceinline__ bool node_split(const long long *lo_key, const long long *hi_key, int node, int d,
+                                           int cnt, int leaf, int *sd_out, double *sc_out) {
+    if (cnt <= leaf) return false;
+    int sd = 0;
+    double lo0 = key_dbl(lo_key[(size_t)node * d]), hi0 = key_dbl(hi_key[(size_t)node * d]);
+    double wmax = hi0 - lo0;
+    for (int k = 1; k < d; ++k) {
+        double w = key_dbl(hi_key[(size_t)node * d + k]) - key_dbl(lo_key[(size_t)node * d + k]);
+        if (w > wmax) {
+            wmax = w;
+            sd = k;
+        }
+    }
+    if (!(wmax > 0.0)) return false;
+    *sd_out = sd;
+    *sc_out = (key_dbl(lo_key[(size_t)node * d + sd]) + key_dbl(hi_key[(size_t)node * d + sd])) / 2.0;
+    return true;
+}
+
+__global__ void k_flag(const double *__restrict__ x, const int32_t *__restrict__ pnode, int n, int d, int leaf,
+                       const long long *__restrict__ lo_key, const long long *__restrict__ hi_key,
+                       const int32_t *__restrict__ begin, const int32_t *__restrict__ end, int32_t *flag,
+                       int32_t *nleft) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int f = 0, node = -1;
+    if (i < n) {
+        node = pnode[i];
+        if (node >= 0) {
+            int sd;
+            double sc;
+            if (node_split(lo_key, hi_key, node, d, end[node] - begin[node], leaf, &sd, &sc))
+                f = x[(size_t)i * d + sd] <= sc ? 1 : 0;
+        }
+        flag[i] = f;
+    }
+    // wave-aggregated count of left points per node
+    unsigned long long pending = __ballot(f != 0);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int ln = __shfl(node, leader, 64);
+        unsigned long long same = __ballot(f != 0 && node == ln);
+        if ((threadIdx.x & 63) == leader) atomicAdd(&nleft[ln], __popcll(same));
+        pending &= ~same;
+    }
+}
+
+// One block: decide the splits of level nodes [lb, le) and allocate children
+// at le + 2 * (rank among splitting nodes).
+__global__ __launch_bounds__(1024) void k_finalize(int lb, int le, int d, int leaf, long long *lo_key,
+                                                   long long *hi_key, int32_t *begin, int32_t *end,
+                                                   int32_t *left, int32_t *right, int32_t *parent,
+                                                   int32_t *sdim, double *scoord, int32_t *nleft,
+                                                   int *new_count) {
+    __shared__ int warp_tot[16];
+    __shared__ int carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = lb; c0 < le; c0 += blockDim.x) {
+        const int node = c0 + threadIdx.x;
+        int split = 0, sd = -1;
+        double sc = 0.0;
+        if (node < le) {
+            const int cnt = end[node] - begin[node];
+            if (node_split(lo_key, hi_key, node, d, cnt, leaf, &sd, &sc)) {
+                const int nl = nleft[node];
+                split = (nl > 0 && nl < cnt) ? 1 : 0;
+            }
+        }
+        // block exclusive scan of split
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        int inc = wave_incl_scan(split);
+        if (lane == 63) warp_tot[w] = inc;
+        __syncthreads();
+        int wbase = 0;
+        for (int k = 0; k < w; ++k) wbase += warp_tot[k];
+        const int rank = carry_s + wbase + inc - split;
+        if (node < le) {
+            if (split) {
+                const int L = le + 2 * rank, R = L + 1;
+                const int b = begin[node], e = end[node], nl = nleft[node];
+                left[node] = L;
+                right[node] = R;
+                sdim[node] = sd;
+                scoord[node] = sc;
+                begin[L] = b;
+                end[L] = b + nl;
+                begin[R] = b + nl;
+                end[R] = e;
+                parent[L] = node;
+                parent[R] = node;
+                nleft[L] = 0;
+                nleft[R] = 0;
+                for (int k = 0; k < d; ++k) {
+                    lo_key[(size_t)L * d + k] = kPosInfKey;
+                    hi_key[(size_t)L * d + k] = kNegInfKey;
+                    lo_key[(size_t)R * d + k] = kPosInfKey;
+                    hi_key[(size_t)R * d + k] = kNegInfKey;
+                }
+            } else {
+                left[node] = -1;
+                right[node] = -1;
+                sdim[node] = -1;
+                scoord[node] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry_s = rank + split;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *new_count = 2 * carry_s;
+}
+
+// --- exclusive scan of int32 flags (three phases) -----------------------------------
+constexpr int kScanItems = 1024;  // per block: 256 threads x 4
+
+__global__ void k_scan_blocks(const int32_t *__restrict__ in, int n, int32_t *__restrict__ block_sums) {
+    __shared__ int wt[4];
+    const int base = blockIdx.x * kScanItems;
+    int s = 0;
+    for (int j = 0; j < 4; ++j) {
+        int i = base + threadIdx.x * 4 + j;
+        s += i < n ? in[i] : 0;
+    }
+    s = wave_sum_i(s);
+    if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = wt[0] + wt[1] + wt[2] + wt[3];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nb) {
+    __shared__ int wt[16];
+    __shared__ int carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nb; c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nb ? sums[i] : 0;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        int inc = wave_incl_scan(v);
+        if (lane == 63) wt[w] = inc;
+        __syncthreads();
+        int wb = 0;
+        for (int k = 0; k < w; ++k) wb += wt[k];
+        const int ex = carry_s + wb + inc - v;
+        __syncthreads();
+        if (i < nb) sums[i] = ex;
+        if (threadIdx.x == blockDim.x - 1) carry_s = ex + v;
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_final(const int32_t *__restrict__ in, int n, const int32_t *__restrict__ block_off,
+                             int32_t *__restrict__ out) {
+    __shared__ int wt[4];
+    const int base = blockIdx.x * kScanItems;
+    int v[4], s = 0;
+    for (int j = 0; j < 4; ++j) {
+        int i = base + threadIdx.x * 4 + j;
+        v[j] = i < n ? in[i] : 0;
+        s += v[j];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = wave_incl_scan(s);
+    if (lane == 63) wt[w] = inc;
+    __syncthreads();
+    int wb = 0;
+    for (int k = 0; k < w; ++k) wb += wt[k];
+    int run = block_off[blockIdx.x] + wb + inc - s;
+    for (int j = 0; j < 4; ++j) {
+        int i = base + threadIdx.x * 4 + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+__global__ void k_scatter(int n, int d, const int32_t *__restrict__ pnode_a, const int32_t *__restrict__ perm_a,
+                          const double *__restrict__ x_a, const int32_t *__restrict__ flag,
+                          const int32_t *__restrict__ scan, const int32_t *__restrict__ begin,
+                          const int32_t *__restrict__ nleft, const int32_t *__restrict__ left,
+                          const int32_t *__restrict__ right, int32_t *pnode_b, int32_t *perm_b, double *x_b,
+                          long long *lo_key, long long *hi_key) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[kMaxD];
+    int child = -1;
+    bool act = false;
+    if (i < n) {
+        const int node = pnode_a[i];
+        for (int k = 0; k < d; ++k) v[k] = x_a[(size_t)i * d + k];
+        int dst = i;
+        if (node >= 0 && left[node] >= 0) {
+            const int b = begin[node];
+            const int rl = scan[i] - scan[b];
+            if (flag[i]) {
+                dst = b + rl;
+                child = left[node];
+            } else {
+                dst = b + nleft[node] + (i - b - rl);
+                child = right[node];
+            }
+            act = true;
+        }
+        perm_b[dst] = perm_a[i];
+        pnode_b[dst] = child;
+        for (int k = 0; k < d; ++k) x_b[(size_t)dst * d + k] = v[k];
+    }
+    wave_box_fold(act, child, v, d, lo_key, hi_key);
+}
+
+__global__ void k_decode_boxes(int m, int d, const long long *__restrict__ lo_key,
+                               const long long *__restrict__ hi_key, double *lo, double *hi, double *ctr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m * d) return;
+    const double a = key_dbl(lo_key[i]), b = key_dbl(hi_key[i]);
+    lo[i] = a;
+    hi[i] = b;
+    ctr[i] = (a + b) / 2.0;
+}
+
+__global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_t *leaves, int *count) {
+    // single block, order-preserving compaction of leaf ids
+    __shared__ int wt[16];
+    __shared__ int carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < m; c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        const int is = (i < m && left[i] < 0) ? 1 : 0;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        int inc = wave_incl_scan(is);
+        if (lane == 63) wt[w] = inc;
+        __syncthreads();
+        int wb = 0;
+        for (int k = 0; k < w; ++k) wb += wt[k];
+        const int ex = carry_s + wb + inc - is;
+        if (is) leaves[ex] = i;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry_s = ex + is;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry_s;
+}
+
+}  // namespace
+
+dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st) {
+    const int n = (int)t->n, d = t->d, leaf = t->leaf;
+    const int cap = 2 * n + 1;
+    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, scan, bsums, lo_key, hi_key, nleft, counter;
+    DFGT_TRY(t->perm.reserve(sizeof(int32_t) * n));
+    DFGT_TRY(perm_b.reserve(sizeof(int32_t) * n));
+    DFGT_TRY(t->x.reserve(sizeof(double) * (size_t)n * d));
+    DFGT_TRY(x_b.reserve(sizeof(double) * (size_t)n * d));
+    DFGT_TRY(pnode_a.reserve(sizeof(int32_t) * n));
+    DFGT_TRY(pnode_b.reserve(sizeof(int32_t) * n));
+    DFGT_TRY(flag.reserve(sizeof(int32_t) * n));
+    DFGT_TRY(scan.reserve(sizeof(int32_t) * n));
+    const int nsb = (n + kScanItems - 1) / kScanItems;
+    DFGT_TRY(bsums.reserve(sizeof(int32_t) * (nsb + 1)));
+    DFGT_TRY(lo_key.reserve(sizeof(long long) * (size_t)cap * d));
+    DFGT_TRY(hi_key.reserve(sizeof(long long) * (size_t)cap * d));
+    DFGT_TRY(nleft.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(counter.reserve(sizeof(int) * 4));
+    DFGT_TRY(t->begin.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(t->end.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(t->left.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(t->right.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(t->parent.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(t->sdim.reserve(sizeof(int32_t) * cap));
+    DFGT_TRY(t->scoord.reserve(sizeof(double) * cap));
+
+    int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
+    double *xa = t->x.as<double>(), *xb = x_b.as<double>();
+    int32_t *na = pnode_a.as<int32_t>(), *nb = pnode_b.as<int32_t>();
+    int *cnt_d = counter.as<int>();
+    DFGT_HIP(hipMemsetAsync(cnt_d, 0, sizeof(int) * 4, st));
+    const int gb = (n + kTB - 1) / kTB;
+    hipLaunchKernelGGL(k_init, dim3(gb), dim3(kTB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
+    hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
+                       t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(),
+                       nleft.as<int32_t>(), n);
+    hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kTB), 0, st, xa, n, d, lo_key.as<long long>(),
+                       hi_key.as<long long>());
+    DFGT_HIP(hipGetLastError());
+    int host_cnt[2] = {0, 0};
+    DFGT_HIP(hipMemcpyAsync(host_cnt, cnt_d, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    if (host_cnt[1]) {
+        set_error("dfgt_build_tree: points contain a non-finite coordinate");
+        return DFGT_EINVAL;
+    }
+
+    t->level_start.assign(1, 0);
+    int lb = 0, le = 1;
+    while (true) {
+        t->level_start.push_back(le);
+        hipLaunchKernelGGL(k_flag, dim3(gb), dim3(kTB), 0, st, xa, na, n, d, leaf, lo_key.as<long long>(),
+                           hi_key.as<long long>(), t->begin.as<int32_t>(), t->end.as<int32_t>(),
+                           flag.as<int32_t>(), nleft.as<int32_t>());
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, lb, le, d, leaf, lo_key.as<long long>(),
+                           hi_key.as<long long>(), t->begin.as<int32_t>(), t->end.as<int32_t>(),
+                           t->left.as<int32_t>(), t->right.as<int32_t>(), t->parent.as<int32_t>(),
+                           t->sdim.as<int32_t>(), t->scoord.as<double>(), nleft.as<int32_t>(), cnt_d);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n, bsums.as<int32_t>());
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsums.as<int32_t>(), nsb);
+        hipLaunchKernelGGL(k_scan_final, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n, bsums.as<int32_t>(),
+                           scan.as<int32_t>());
+        hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kTB), 0, st, n, d, na, pa, xa, flag.as<int32_t>(),
+                           scan.as<int32_t>(), t->begin.as<int32_t>(), nleft.as<int32_t>(), t->left.as<int32_t>(),
+                           t->right.as<int32_t>(), nb, pb, xb, lo_key.as<long long>(), hi_key.as<long long>());
+        DFGT_HIP(hipGetLastError());
+        std::swap(pa, pb);
+        std::swap(xa, xb);
+        std::swap(na, nb);
+        int newc = 0;
+        DFGT_HIP(hipMemcpyAsync(&newc, cnt_d, sizeof(int), hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipStreamSynchronize(st));
+        if (newc == 0) break;
+        lb = le;
+        le += newc;
+        if (le > cap) {
+            set_error("dfgt_build_tree: node capacity exceeded (internal error)");
+            return DFGT_EHIP;
+        }
+    }
+    const int m = le;
+    t->m = m;
+    t->depth = (int)t->level_start.size() - 1;
+    // the final permutation / points live in pa / xa
+    if (pa != t->perm.as<int32_t>()) {
+        DFGT_HIP(hipMemcpyAsync(t->perm.p, pa, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+        DFGT_HIP(hipMemcpyAsync(t->x.p, xa, sizeof(double) * (size_t)n * d, hipMemcpyDeviceToDevice, st));
+    }
+    DFGT_TRY(t->lo.reserve(sizeof(double) * (size_t)m * d));
+    DFGT_TRY(t->hi.reserve(sizeof(double) * (size_t)m * d));
+    DFGT_TRY(t->ctr.reserve(sizeof(double) * (size_t)m * d));
+    DFGT_TRY(t->leaves.reserve(sizeof(int32_t) * m));
+    hipLaunchKernelGGL(k_decode_boxes, dim3((m * d + 255) / 256), dim3(256), 0, st, m, d, lo_key.as<long long>(),
+                       hi_key.as<long long>(), t->lo.as<double>(), t->hi.as<double>(), t->ctr.as<double>());
+    hipLaunchKernelGGL(k_collect_leaves, dim3(1), dim3(1024), 0, st, m, t->left.as<int32_t>(),
+                       t->leaves.as<int32_t>(), cnt_d + 2);
+    DFGT_HIP(hipGetLastError());
+    int nl = 0;
+    DFGT_HIP(hipMemcpyAsync(&nl, cnt_d + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    t->nleaves = nl;
+    return DFGT_OK;
+}
+
+}  // namespace dfgt

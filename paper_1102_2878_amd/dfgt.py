@@ -1,0 +1,182 @@
+"""Thin Python binding of libdfgt.so (the C ABI in include/dfgt.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch CUDA tensors (ROCm); work is enqueued on torch's current
+stream.  The library must have been built (``__graft_entry__.build()`` or
+``python paper_1102_2878_amd/build.py``); a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdfgt.so")
+
+PREC_MIXED, PREC_FP64 = 0, 1
+FORCE_NONE, FORCE_F, FORCE_D, FORCE_T, FORCE_CENTROID, FORCE_EXACT = range(6)
+
+
+class DfgtError(RuntimeError):
+    pass
+
+
+class Options(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("p_max", C.c_int32), ("precision", C.c_int32),
+                ("force_method", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(nm, C.c_int64) for nm in (
+        "node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid", "base_leaf_pairs",
+        "base_point_pairs", "levels", "max_order", "fp64_groups")] + [("reserved", C.c_int64 * 6)]
+
+    def as_dict(self):
+        return {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Loads libdfgt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DfgtError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.dfgt_last_error.restype = C.c_char_p
+        L.dfgt_version.restype = C.c_char_p
+        L.dfgt_build_tree.argtypes = [vp, i64, i32, C.POINTER(Options), vp, C.POINTER(vp)]
+        L.dfgt_tree_free.argtypes = [vp]
+        L.dfgt_tree_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
+                                     C.POINTER(i32)]
+        L.dfgt_tree_export.argtypes = [vp] + [vp] * 9
+        L.dfgt_tree_moments.argtypes = [vp, vp]
+        L.dfgt_naive_sum.argtypes = [vp, i64, vp, i64, i32, C.POINTER(dbl), i32, i32, vp, vp]
+        L.dfgt_gauss_sum.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp,
+                                     C.POINTER(Stats), vp]
+        for nm in ("dfgt_build_tree", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
+                   "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum"):
+            getattr(L, nm).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise DfgtError(f"libdfgt error {rc}: {lib().dfgt_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_points(x):
+    torch = _torch()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise DfgtError("points must be a CUDA (HIP) torch tensor")
+    if x.dtype != torch.float64 or x.dim() != 2:
+        raise DfgtError("points must be a 2-D float64 tensor")
+    return x.contiguous()
+
+
+def _hvec(h):
+    h = np.ascontiguousarray(np.atleast_1d(np.asarray(h, dtype=np.float64)))
+    return h, h.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _opts(leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE):
+    o = Options()
+    o.leaf_size, o.p_max, o.precision, o.force_method = int(leaf_size), int(p_max), int(precision), int(force_method)
+    return o
+
+
+class Tree:
+    """Owns a dfgt_tree handle."""
+
+    def __init__(self, handle, n, d):
+        self.handle = handle
+        self.n, self.d = n, d
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.dfgt_tree_free(h)
+            self.handle = None
+
+    def info(self):
+        return tree_info(self)
+
+
+def build_tree(points, leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE) -> Tree:
+    """dfgt_build_tree: kd-tree (+ raw moments) of an (n, d) float64 CUDA tensor."""
+    x = _dev_points(points)
+    o = _opts(leaf_size, p_max, precision, force_method)
+    h = C.c_void_p()
+    _check(lib().dfgt_build_tree(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(o), _stream(),
+                                 C.byref(h)))
+    return Tree(h, x.shape[0], x.shape[1])
+
+
+def tree_info(t: Tree):
+    n, d, m, dep, pm = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32()
+    _check(lib().dfgt_tree_info(t.handle, C.byref(n), C.byref(d), C.byref(m), C.byref(dep), C.byref(pm)))
+    return dict(n=n.value, d=d.value, n_nodes=m.value, depth=dep.value, p_max=pm.value)
+
+
+def tree_export(t: Tree):
+    """dfgt_tree_export: host copies of the breadth-first node arrays and the permutation."""
+    info = tree_info(t)
+    n, d, m = info["n"], info["d"], info["n_nodes"]
+    out = dict(perm=np.empty(n, np.int32), lo=np.empty((m, d)), hi=np.empty((m, d)),
+               begin=np.empty(m, np.int32), end=np.empty(m, np.int32), left=np.empty(m, np.int32),
+               right=np.empty(m, np.int32), split_dim=np.empty(m, np.int32), split_coord=np.empty(m))
+    order = ("perm", "lo", "hi", "begin", "end", "left", "right", "split_dim", "split_coord")
+    _check(lib().dfgt_tree_export(t.handle, *[out[k].ctypes.data_as(C.c_void_p) for k in order]))
+    out["n_nodes"] = m
+    return out
+
+
+def tree_moments(t: Tree):
+    """dfgt_tree_moments: raw moments, (n_nodes, p_max^d) float64 host array."""
+    info = tree_info(t)
+    mu = np.empty((info["n_nodes"], info["p_max"] ** info["d"]))
+    _check(lib().dfgt_tree_moments(t.handle, mu.ctypes.data_as(C.c_void_p)))
+    return mu
+
+
+def naive_sum(q, r, h, precision=PREC_MIXED, out=None):
+    """dfgt_naive_sum: brute-force sums, returns an (n_h, nq) float64 CUDA tensor."""
+    torch = _torch()
+    q, r = _dev_points(q), _dev_points(r)
+    hv, hp = _hvec(h)
+    if out is None:
+        out = torch.empty((hv.shape[0], q.shape[0]), dtype=torch.float64, device=q.device)
+    _check(lib().dfgt_naive_sum(C.c_void_p(q.data_ptr()), q.shape[0], C.c_void_p(r.data_ptr()), r.shape[0],
+                                q.shape[1], hp, hv.shape[0], int(precision), C.c_void_p(out.data_ptr()),
+                                _stream()))
+    return out
+
+
+def gauss_sum(Q: Tree, R: Tree, h, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, out=None):
+    """dfgt_gauss_sum: DFGT sums for every bandwidth, (n_h, NQ) float64 CUDA tensor [, stats dict]."""
+    torch = _torch()
+    hv, hp = _hvec(h)
+    if out is None:
+        out = torch.empty((hv.shape[0], Q.n), dtype=torch.float64, device="cuda")
+    o = _opts(precision=precision, force_method=force_method)
+    st = Stats() if stats else None
+    _check(lib().dfgt_gauss_sum(Q.handle, R.handle, hp, hv.shape[0], float(eps), C.byref(o),
+                                C.c_void_p(out.data_ptr()), C.byref(st) if st is not None else None, _stream()))
+    return (out, st.as_dict()) if stats else out
