@@ -1,0 +1,193 @@
+"""Benchmark of the MI355X dual-tree fast Gauss transform on one GPU.
+
+Workload (the 2-D clustered configuration): 50,000 points, D = 2, 32
+anisotropic Gaussian clusters + 10% uniform background, Q = R; seven
+bandwidths h* x 10^{-3..3} (h* = the LSCV optimum, tests/golden/hstar.json);
+relative error eps = 1e-2 on every query.
+
+One step = the whole hot path over that input, resident in HBM:
+  kd-tree build + raw moments (dfgt_build_tree)  ->  DFGT for all seven
+  bandwidths in one traversal (dfgt_gauss_sum).
+value = N_Q * N_R * 7 / (seconds per step)  [query x reference pairs / s].
+The plain tiled brute-force GPU sum (dfgt_naive_sum) over the same seven
+bandwidths is timed alongside.
+
+Prints ONE JSON line.  --gpus must be 1 (this build targets one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "query×ref pairs/s at rel-err 1e-2 (dual-tree vs brute-force GPU) + grad ms"
+SCALES = [1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0, 1000.0]
+EPS = 1e-2
+LEAF = 32
+
+# Exhaustive-tile roofline (bound "alu"): the algorithmic work per point pair is
+# 2D+1 FP32 VALU operations (D differences, D-1 fused multiply-adds + 1 multiply,
+# 1 add) and one v_exp_f32.  Peak pair rate = 256 CUs x 64 lanes x 2.4 GHz /
+# (2D+1 + EXP_SLOTS) VALU issue slots, EXP_SLOTS = issue cost of v_exp_f32 in
+# full-rate slots (transcendentals run at a quarter of the VALU rate).
+CUS, LANES, CLOCK = 256, 64, 2.4e9
+EXP_SLOTS = 4
+
+
+def base_peak_pairs(d):
+    return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1102_2878_amd import dfgt, synth
+
+    hstar = json.load(open(os.path.join(ROOT, "tests", "golden", "hstar.json")))["c2"]["h_star"]
+    hs = [hstar * s for s in SCALES]
+    x_host = synth.c2()
+    n, d = x_host.shape
+    x = torch.as_tensor(x_host, device="cuda")
+    torch.cuda.synchronize()
+
+    def step(profile):
+        t = dfgt.build_tree(x, leaf_size=LEAF)
+        G, st = dfgt.gauss_sum(t, t, hs, EPS, stats=True, profile=profile)
+        return G, st
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, HIP events recorded by the library on this stream
+    agg_ms = {}
+    agg_launch = {}
+    base_pairs = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        G, st = step(True)
+        for k, v in st["kernel_ms"].items():
+            agg_ms[k] = agg_ms.get(k, 0.0) + v
+            agg_launch[k] = agg_launch.get(k, 0) + st["kernel_launches"][k]
+        base_pairs += st["base_point_pairs"]
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    stats = st
+
+    # the same steps without event recording, for the event overhead
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(False)
+    torch.cuda.synchronize()
+    t_step_noev = (time.perf_counter() - t0) / args.steps
+
+    # build alone
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dfgt.build_tree(x, leaf_size=LEAF)
+    torch.cuda.synchronize()
+    t_build = (time.perf_counter() - t0) / args.steps
+
+    # brute-force comparator, same inputs and bandwidths
+    for _ in range(max(1, args.warmup)):
+        dfgt.naive_sum(x, x, hs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Gb = dfgt.naive_sum(x, x, hs)
+    torch.cuda.synchronize()
+    t_bf = (time.perf_counter() - t0) / args.steps
+
+    pairs = float(n) * n * len(hs)
+    value = pairs / t_step
+
+    base_ms = agg_ms.get("base", 0.0)
+    base_launches = max(agg_launch.get("base", 0), 1)
+    dominant = max(agg_ms, key=agg_ms.get) if agg_ms else None
+    achieved = (base_pairs / (base_ms * 1e-3)) if base_ms > 0 else 0.0
+    peak = base_peak_pairs(d)
+    roofline = {
+        "kernel": "k_base (exhaustive leaf-leaf tiles, DFGTBase)",
+        "bound": "alu",
+        "achieved": achieved / 1e9,
+        "peak": peak / 1e9,
+        "unit": "Gpair/s",
+        "frac": achieved / peak,
+        "traffic": None,
+        "avg_launch_ms": base_ms / base_launches,
+        "pairs_per_launch": base_pairs / base_launches,
+        "dominant_kernel_in_step": dominant,
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-exp/f64-sum",
+        "data": "synthetic",
+        "config": {
+            "workload": "2-D clustered mixture, 50,000 points (Q = R), 7 bandwidths h* x 10^-3..10^3, eps 1e-2",
+            "n": n, "d": d, "n_bandwidths": len(hs), "eps": EPS, "h_star": hstar, "leaf_size": LEAF,
+            "p_max": 6,
+        },
+        "bruteforce_gpu": {"value": pairs / t_bf, "unit": "pairs/s", "ms_per_sweep": t_bf * 1e3},
+        "speedup_vs_bruteforce": t_bf / t_step,
+        "phases_ms": {"build_tree": t_build * 1e3, "step_without_events": t_step_noev * 1e3,
+                      **{f"kernel_{k}": v / args.steps for k, v in agg_ms.items()}},
+        "traversal": {k: stats[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
+                                            "base_leaf_pairs", "base_point_pairs", "levels", "max_order")},
+        "roofline": roofline,
+        "grad_ms": None,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        rng_rows = synth.subsample(x_host, 64, 99)
+        t0 = time.perf_counter()
+        oracle.naive_kde_rows(x_host, rng_rows, x_host, hs[3])
+        rate = len(rng_rows) * n / max(time.perf_counter() - t0, 1e-6)
+        m = int(min(n, max(64, args.cpu_seconds * rate / (n * len(hs)))))
+        rows = synth.subsample(x_host, m, 100)
+        t0 = time.perf_counter()
+        ref = np.stack([oracle.naive_kde_rows(x_host, rows, x_host, h) for h in hs])
+        t_cpu = time.perf_counter() - t0
+        Gs = G.cpu().numpy()[:, rows]
+        Gbs = Gb.cpu().numpy()[:, rows]
+        out["cpu_baseline"] = {
+            "value": m * n * len(hs) / t_cpu, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{m} query rows x {n} references x {len(hs)} bandwidths (seeded subsample), {t_cpu:.1f} s",
+        }
+        out["max_rel_err_sampled"] = {"dfgt": float(np.max(np.abs(Gs - ref) / ref)),
+                                      "bruteforce_gpu": float(np.max(np.abs(Gbs - ref) / ref)),
+                                      "rows": m}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,11 @@ typedef struct dfgt_options {
                              4 for D=3, 2 for D=4,5, 1 for D>=6 */
     int32_t precision;    /* DFGT_PREC_* */
     int32_t force_method; /* DFGT_FORCE_* */
-    int32_t reserved[4];  /* must be zero */
+    int32_t profile;      /* 1: gauss_sum records HIP events around its kernel
+                             launches on the caller's stream and reports the
+                             per-kernel time in dfgt_stats (adds a few us per
+                             launch); 0: off */
+    int32_t reserved[3];  /* must be zero */
 } dfgt_options;
 
 /* Counters of one gauss_sum call (summed over its bandwidths). */
@@ -80,6 +84,12 @@ typedef struct dfgt_stats {
     int64_t max_order;      /* largest expansion order used */
     int64_t fp64_groups;    /* exhaustive groups computed in FP64 by the underflow guard */
     int64_t reserved[6];
+    /* With dfgt_options.profile = 1: summed event time (ms) and launch count
+     * per kernel: [0] traversal, [1] exhaustive leaf-leaf tiles (DFGTBase),
+     * [2] far-field evaluation, [3] local accumulation (D and T),
+     * [4] post-processing (L2L, local evaluation, combine). */
+    double kernel_ms[5];
+    int64_t kernel_launches[5];
 } dfgt_stats;
 
 typedef struct dfgt_tree_s *dfgt_tree;

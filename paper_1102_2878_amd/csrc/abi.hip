@@ -61,7 +61,7 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
     DFGT_REQUIRE(d >= 1 && d <= kMaxD, "dfgt_build_tree: d must be in [1, 32]");
     dfgt_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 4; ++i) DFGT_REQUIRE(o.reserved[i] == 0, "dfgt_build_tree: reserved option field set");
+    for (int i = 0; i < 3; ++i) DFGT_REQUIRE(o.reserved[i] == 0, "dfgt_build_tree: reserved option field set");
     DFGT_REQUIRE(o.leaf_size >= 0 && o.leaf_size <= 4096, "dfgt_build_tree: leaf_size must be in [0, 4096]");
     DFGT_REQUIRE(o.p_max >= 0 && o.p_max <= 16, "dfgt_build_tree: p_max must be in [0, 16]");
     DFGT_REQUIRE(o.precision == DFGT_PREC_MIXED || o.precision == DFGT_PREC_FP64,
@@ -199,16 +199,18 @@ dfgt_status dfgt_gauss_sum(dfgt_tree Q, dfgt_tree R, const double *h_host, int32
     DFGT_REQUIRE(Q->pmax == R->pmax, "dfgt_gauss_sum: query and reference trees use different p_max");
     DFGT_REQUIRE(std::isfinite(eps) && eps >= 0.0 && eps < 1.0, "dfgt_gauss_sum: eps must be in [0, 1)");
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum"));
-    int precision = R->precision, force = R->force;
+    int precision = R->precision, force = R->force, profile = 0;
     if (opt) {
-        for (int i = 0; i < 4; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, "dfgt_gauss_sum: reserved option field set");
+        for (int i = 0; i < 3; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, "dfgt_gauss_sum: reserved option field set");
         DFGT_REQUIRE(opt->precision == DFGT_PREC_MIXED || opt->precision == DFGT_PREC_FP64,
                      "dfgt_gauss_sum: unknown precision");
         DFGT_REQUIRE(opt->force_method >= 0 && opt->force_method <= 5, "dfgt_gauss_sum: unknown force_method");
         precision = opt->precision;
         force = opt->force_method;
+        profile = opt->profile;
     }
-    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, G_dev, stats, (hipStream_t)stream);
+    DFGT_REQUIRE(profile == 0 || stats != nullptr, "dfgt_gauss_sum: profile needs a stats pointer");
+    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, G_dev, stats, (hipStream_t)stream);
     DFGT_GUARD_END
 }
 

@@ -151,7 +151,8 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st);
 // dfgt.hip
 dfgt_status run_gauss_sum(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps,
-                          int precision, int force, double *G, dfgt_stats *stats, hipStream_t st);
+                          int precision, int force, int profile, double *G, dfgt_stats *stats,
+                          hipStream_t st);
 
 int default_pmax(int d);
 

@@ -26,16 +26,23 @@ class DfgtError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("p_max", C.c_int32), ("precision", C.c_int32),
-                ("force_method", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("force_method", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Stats(C.Structure):
     _fields_ = [(nm, C.c_int64) for nm in (
         "node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid", "base_leaf_pairs",
-        "base_point_pairs", "levels", "max_order", "fp64_groups")] + [("reserved", C.c_int64 * 6)]
+        "base_point_pairs", "levels", "max_order", "fp64_groups")] + [("reserved", C.c_int64 * 6),
+                                                                       ("kernel_ms", C.c_double * 5),
+                                                                       ("kernel_launches", C.c_int64 * 5)]
+    KERNELS = ("traverse", "base", "far", "local", "post")
 
     def as_dict(self):
-        return {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm != "reserved"}
+        d = {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm not in ("reserved", "kernel_ms",
+                                                                                 "kernel_launches")}
+        d["kernel_ms"] = dict(zip(self.KERNELS, list(self.kernel_ms)))
+        d["kernel_launches"] = dict(zip(self.KERNELS, [int(v) for v in self.kernel_launches]))
+        return d
 
 
 _lib = None
@@ -96,9 +103,10 @@ def _hvec(h):
     return h, h.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _opts(leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE):
+def _opts(leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE, profile=False):
     o = Options()
     o.leaf_size, o.p_max, o.precision, o.force_method = int(leaf_size), int(p_max), int(precision), int(force_method)
+    o.profile = int(bool(profile))
     return o
 
 
@@ -169,13 +177,15 @@ def naive_sum(q, r, h, precision=PREC_MIXED, out=None):
     return out
 
 
-def gauss_sum(Q: Tree, R: Tree, h, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, out=None):
+def gauss_sum(Q: Tree, R: Tree, h, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, out=None,
+              profile=False):
     """dfgt_gauss_sum: DFGT sums for every bandwidth, (n_h, NQ) float64 CUDA tensor [, stats dict]."""
     torch = _torch()
     hv, hp = _hvec(h)
     if out is None:
         out = torch.empty((hv.shape[0], Q.n), dtype=torch.float64, device="cuda")
-    o = _opts(precision=precision, force_method=force_method)
+    o = _opts(precision=precision, force_method=force_method, profile=profile)
+    stats = stats or profile
     st = Stats() if stats else None
     _check(lib().dfgt_gauss_sum(Q.handle, R.handle, hp, hv.shape[0], float(eps), C.byref(o),
                                 C.c_void_p(out.data_ptr()), C.byref(st) if st is not None else None, _stream()))

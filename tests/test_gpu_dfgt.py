@@ -1,0 +1,158 @@
+"""GPU parity of the dual-tree fast Gauss transform (dfgt_gauss_sum) against
+the oracle's exact FP64 sums.
+
+Several results are correct (any G~ with |G~ - G| <= eps G for every query,
+Definition of the relative error bound and the global-error theorem of
+Section 3.10), so the parity check is that inequality per query, element by
+element, plus exact equality where the method is exact (eps = 0 up to the
+leaf-sum rounding, coincident points)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1102_2878_amd import synth
+from tests.gpu_util import cuda, note
+
+pytestmark = pytest.mark.gpu
+
+HSTAR = os.path.join(os.path.dirname(__file__), "golden", "hstar.json")
+SCALES = [1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0, 1000.0]
+
+
+@pytest.fixture(scope="module")
+def dfgt():
+    from paper_1102_2878_amd import dfgt as m
+    return m
+
+
+def _rel_err(G, ref):
+    return np.abs(G - ref) / ref
+
+
+def _run(dfgt, x, q, hs, eps, leaf=32, precision=0, force=0, pmax=0):
+    R = dfgt.build_tree(cuda(x), leaf_size=leaf, p_max=pmax)
+    Q = R if q is None else dfgt.build_tree(cuda(q), leaf_size=leaf, p_max=pmax)
+    G, st = dfgt.gauss_sum(Q, R, hs, eps, precision=precision, force_method=force, stats=True)
+    return G.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_c1_guarantee(dfgt, precision, eps):
+    x = synth.c1()
+    hs = [synth.silverman_h(x) * s for s in (0.1, 1.0, 10.0)]
+    note(f"dfgt c1 precision={precision} eps={eps}")
+    G, st = _run(dfgt, x, None, hs, eps, precision=precision)
+    for k, h in enumerate(hs):
+        ref = oracle.naive_kde(x, x, h)
+        rel = _rel_err(G[k], ref)
+        assert rel.max() <= eps, (h, rel.max(), st)
+
+
+def test_clustered_sweep_all_scales(dfgt):
+    x = synth.c2(n=6000, seed=21)
+    hs = [synth.silverman_h(x) * s for s in SCALES]
+    note("dfgt clustered 6000 sweep")
+    G, st = _run(dfgt, x, None, hs, 1e-2)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+        assert rel.max() <= 1e-2, (h, rel.max())
+    assert st["prune_centroid"] > 0 and st["base_leaf_pairs"] > 0
+
+
+@pytest.mark.parametrize("d,pmax", [(1, 0), (3, 0), (5, 0), (5, 3), (3, 6)])
+def test_dimensions(dfgt, d, pmax):
+    x = synth.c3(n=4000, seed=22)[:, :d] if d <= 5 else None
+    hs = [synth.silverman_h(x) * s for s in (0.1, 1.0, 10.0, 100.0)]
+    note(f"dfgt d={d} pmax={pmax}")
+    G, st = _run(dfgt, x, None, hs, 1e-2, pmax=pmax)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+        assert rel.max() <= 1e-2, (h, rel.max())
+
+
+def test_bichromatic(dfgt):
+    x = synth.c1(n=3000, seed=23)
+    q = synth.bichromatic_queries(x, 23)[:1777]
+    hs = [synth.silverman_h(x) * s for s in (0.03, 0.3, 3.0, 30.0)]
+    note("dfgt bichromatic")
+    G, st = _run(dfgt, x, q, hs, 1e-2)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(q, x, h))
+        assert rel.max() <= 1e-2, (h, rel.max())
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-12), (0, 1e-5)])
+def test_eps_zero_is_exhaustive(dfgt, precision, tol):
+    x = synth.c1(n=1500, seed=24)
+    hs = [synth.silverman_h(x) * s for s in (0.1, 1.0, 10.0)]
+    note(f"dfgt eps=0 precision={precision}")
+    G, st = _run(dfgt, x, None, hs, 0.0, precision=precision)
+    for k, h in enumerate(hs):
+        np.testing.assert_allclose(G[k], oracle.naive_kde(x, x, h), rtol=tol)
+
+
+def test_coincident_points_exact(dfgt):
+    x = np.tile(np.array([[0.3, 0.7]]), (500, 1))
+    note("dfgt coincident")
+    G, st = _run(dfgt, x, None, [1e-3, 1.0], 0.0)
+    np.testing.assert_array_equal(G, np.full((2, 500), 500.0))
+    assert st["node_pairs"] == 2 and st["base_leaf_pairs"] == 0
+
+
+@pytest.mark.parametrize("force,key", [(1, "prune_f"), (2, "prune_d"), (3, "prune_t"), (4, "prune_centroid"),
+                                       (5, None)])
+def test_forced_single_method(dfgt, force, key):
+    x = synth.c1(n=2500, seed=25)
+    hs = [synth.silverman_h(x) * s for s in (0.3, 3.0, 30.0)]
+    note(f"dfgt force={force}")
+    G, st = _run(dfgt, x, None, hs, 1e-2, force=force)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+        assert rel.max() <= 1e-2, (force, h, rel.max())
+    if key:
+        assert st[key] > 0, st
+    else:
+        assert st["prune_f"] + st["prune_d"] + st["prune_t"] + st["prune_centroid"] == 0
+
+
+def test_ragged_leaf_sizes_and_tiny_inputs(dfgt):
+    rng = np.random.default_rng(26)
+    for n, leaf in ((1, 32), (2, 1), (33, 32), (257, 7), (1000, 100), (700, 300)):
+        x = rng.uniform(size=(n, 2))
+        hs = [0.01, 0.1, 1.0]
+        note(f"dfgt ragged n={n} leaf={leaf}")
+        G, st = _run(dfgt, x, None, hs, 1e-2, leaf=leaf)
+        for k, h in enumerate(hs):
+            rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+            assert rel.max() <= 1e-2, (n, leaf, h, rel.max())
+
+
+def test_deterministic_and_job_independent(dfgt):
+    x = synth.c2(n=5000, seed=27)
+    hs = [synth.silverman_h(x) * s for s in (0.1, 1.0, 10.0)]
+    note("dfgt determinism")
+    R = dfgt.build_tree(cuda(x))
+    G1 = dfgt.gauss_sum(R, R, hs, 1e-2).cpu().numpy()
+    G2 = dfgt.gauss_sum(R, R, hs, 1e-2).cpu().numpy()
+    assert np.array_equal(G1, G2)
+    for k, h in enumerate(hs):
+        Gk = dfgt.gauss_sum(R, R, [h], 1e-2).cpu().numpy()[0]
+        assert np.array_equal(Gk, G1[k])
+
+
+def test_full_size_c2_sweep_sampled(dfgt):
+    x = synth.c2()
+    h0 = json.load(open(HSTAR))["c2"]["h_star"] if os.path.exists(HSTAR) else synth.silverman_h(x)
+    hs = [h0 * s for s in SCALES]
+    rows = synth.subsample(x, 400, 28)
+    note("dfgt c2 50k sweep")
+    G, st = _run(dfgt, x, None, hs, 1e-2)
+    for k, h in enumerate(hs):
+        ref = oracle.naive_kde_rows(x, rows, x, h)
+        rel = _rel_err(G[k][rows], ref)
+        assert rel.max() <= 1e-2, (h, rel.max())
+        assert np.all(np.isfinite(G[k]))
