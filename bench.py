@@ -119,13 +119,13 @@ def main():
     pairs = float(n) * n * len(hs)
     value = pairs / t_step
 
-    base_ms = agg_ms.get("base", 0.0)
-    base_launches = max(agg_launch.get("base", 0), 1)
+    base_ms = agg_ms.get("leaf", 0.0)
+    base_launches = max(agg_launch.get("leaf", 0), 1)
     dominant = max(agg_ms, key=agg_ms.get) if agg_ms else None
     achieved = (base_pairs / (base_ms * 1e-3)) if base_ms > 0 else 0.0
     peak = base_peak_pairs(d)
     roofline = {
-        "kernel": "k_base (exhaustive leaf-leaf tiles, DFGTBase)",
+        "kernel": "k_leaf (exhaustive leaf-leaf tiles of DFGTBase + far-field evaluation + local evaluation)",
         "bound": "alu",
         "achieved": achieved / 1e9,
         "peak": peak / 1e9,
@@ -158,9 +158,10 @@ def main():
         "bruteforce_gpu": {"value": pairs / t_bf, "unit": "pairs/s", "ms_per_sweep": t_bf * 1e3},
         "speedup_vs_bruteforce": t_bf / t_step,
         "phases_ms": {"build_tree": t_build * 1e3, "step_without_events": t_step_noev * 1e3,
-                      **{f"kernel_{k}": v / args.steps for k, v in agg_ms.items()}},
+                      **{f"kernel_{k}": v / args.steps for k, v in agg_ms.items() if not k.startswith("unused")}},
         "traversal": {k: stats[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
-                                            "base_leaf_pairs", "base_point_pairs", "levels", "max_order")},
+                                            "base_leaf_pairs", "base_point_pairs", "levels", "max_order",
+                                            "segments", "max_segment", "local_nodes", "max_local_ops")},
         "roofline": roofline,
         "grad_ms": None,
     }

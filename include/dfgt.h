@@ -83,11 +83,16 @@ typedef struct dfgt_stats {
     int64_t levels;         /* traversal levels executed */
     int64_t max_order;      /* largest expansion order used */
     int64_t fp64_groups;    /* exhaustive groups computed in FP64 by the underflow guard */
-    int64_t reserved[6];
+    int64_t segments;       /* (query node, bandwidth) segments processed by the traversal */
+    int64_t max_segment;    /* most reference nodes in one segment */
+    int64_t local_nodes;    /* internal (node, bandwidth) pairs with local-moment ops */
+    int64_t max_local_ops;  /* most local-moment ops of one (node, bandwidth) */
+    int64_t reserved[2];
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
-     * per kernel: [0] traversal, [1] exhaustive leaf-leaf tiles (DFGTBase),
-     * [2] far-field evaluation, [3] local accumulation (D and T),
-     * [4] post-processing (L2L, local evaluation, combine). */
+     * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
+     * [1] per-query-leaf kernel (exhaustive leaf-leaf sums of DFGTBase,
+     * far-field evaluation, local-to-local walk, local evaluation, combine),
+     * [2] unused, [3] local-moment accumulation (D and T ops), [4] unused. */
     double kernel_ms[5];
     int64_t kernel_launches[5];
 } dfgt_stats;

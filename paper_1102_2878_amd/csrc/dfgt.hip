@@ -19,18 +19,19 @@
 //      groups, leaf-leaf E pairs an exhaustive group, and the rest split
 //      exactly as the recursion does (Q and R both when both are internal)
 //      into the next level's segments.
-// Execution per level, one block per (Q, job) group, so every accumulation
-// into a query's partial sums or a node's local moments happens in a fixed
-// order without atomics (results are bitwise reproducible):
-//   k_base    DFGTBase: exact leaf-leaf sums, and the refined lower bound
-//             min_q G_E(q) for the next level;
-//   k_far     EvalFarFieldExpansion for F ops;
-//   k_local   AccumulateDirectLocalMoment (D) and TransFarToLocal (T) into
-//             the node's local moments.
-// Post-processing (DFGTPost): per (query leaf, job) the local moments of
-// every node on the root-to-leaf path are shifted down by TransLocalToLocal
-// and added, the result is evaluated at the leaf's points and combined with
-// the far-field and exhaustive parts, in the caller's order.
+// Op groups are appended to lists that persist across levels, and each (node,
+// job) chains its groups (a node has at most one segment per level, so the
+// chain order is fixed).  After the traversal:
+//   k_local  one wave per (Q, job) with local ops: AccumulateDirectLocalMoment
+//            (D) and TransFarToLocal (T) into Q's local moments;
+//   k_leaf   one block per (query leaf, job) does everything its queries need:
+//            the exhaustive leaf-leaf sums of its E chain (DFGTBase), the
+//            far-field evaluations (EvalFarFieldExpansion) of the F chains of
+//            the leaf and all its ancestors, the TransLocalToLocal walk from
+//            the root to the leaf and EvalLocalExpansion (DFGTPost), and the
+//            combination G = G_E + G_F + G_L in the caller's order.
+// Every sum is taken in a fixed order without atomics, so results are
+// bitwise reproducible and independent of the other jobs in the batch.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -46,6 +47,7 @@ struct Job {
     double h, s, inv2h2, sig;  // s = 1/(sqrt2 h); sig = sqrt(log2 e) s
     double eps_eff;            // eps minus the rounding budget of the exhaustive sums
     double nR;                 // |R_total|
+    double prior;              // a known lower bound on every G(q) (1 when Q = R: the self term)
     int qt, rt;                // indices into the tree table
     long long qoff;            // offset of this job's per-query arrays
     long long noff;            // offset of this job's per-node arrays
@@ -61,14 +63,19 @@ struct Seg {
 
 struct Group {
     int q, job, start, count;
-    int flags;  // k_base: 1 = compute in FP64 (underflow guard)
-    int pad;
+    int flags;  // E groups: 1 = compute in FP64 (underflow guard)
+    int next;   // previous group of the same (node, job), -1 = none
 };
 
 struct Op {
     int r, meta;  // meta = order | (method << 8)
 };
 
+// counters: the first two are reset per level, the others accumulate.  Every
+// counter and statistic sits in its own 128-byte line (CP / SP stride), so the
+// atomics of different counters do not serialise on one L2 channel.
+constexpr int CP = 32;  // ints per counter line
+constexpr int SP = 16;  // u64 per statistics line
 enum {
     C_SEG = 0,
     C_PAIR,
@@ -78,6 +85,7 @@ enum {
     C_FOP,
     C_LGRP,
     C_LOP,
+    C_LNODE,
     C_N
 };
 
@@ -91,6 +99,9 @@ enum {
     S_BPTS,
     S_MAXORD,
     S_FP64,
+    S_SEGS,
+    S_MAXSEG,
+    S_MAXLOPS,
     S_N
 };
 
@@ -172,24 +183,40 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // ChooseBestMethod (Section 3.8) with costs c_F = D N_Q p_F^D, c_D = D N_R p_D^D,
 // c_T = D p_T^{2D}, c_E = D N_Q N_R; ties F, D, T, E.  T may also be chosen at
 // order 1 through the centroid bound |R| max(K(d^l)-K(d_c), K(d_c)-K(d^u)).
-__device__ int choose(const PairGeom &g, double h, double inv2h2, double nQ, double nR, double tau, int pmax,
-                      int D, int force, int *order) {
-    int pF = 0, pD = 0, pT = 0;
-    if (force != DFGT_FORCE_EXACT) {
-        pF = order_far(g.wR / (2.0 * h), nR, tau, pmax, D);
-        pD = order_far(g.wQ / (2.0 * h), nR, tau, pmax, D);
-        pT = order_f2l(fmax(g.wQ, g.wR) / (2.0 * h), nR, tau, pmax, D);
-        const double kl = exp(-g.sl * inv2h2), ku = exp(-g.su * inv2h2), kc = exp(-g.sc * inv2h2);
-        const double cb = nR * (fmax(kl - kc, kc - ku) + 1e-15 * kl);
-        const bool centroid = cb <= tau;
-        if (centroid) pT = 1;
-        if (force == DFGT_FORCE_F) pD = pT = 0;
-        if (force == DFGT_FORCE_D) pF = pT = 0;
-        if (force == DFGT_FORCE_T) pF = pD = 0;
-        if (force == DFGT_FORCE_CENTROID) {
-            pF = pD = 0;
-            pT = centroid ? 1 : 0;
+// When that bound holds c_T = D, the least any method can cost; only F at
+// order 1 with N_Q = 1 or D at order 1 with N_R = 1 can tie it (and win the
+// tie), so the order searches are skipped.  ku = K(d^u).
+__device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double tau,
+                      int pmax, int D, int force, int *order) {
+    if (force == DFGT_FORCE_EXACT) {
+        *order = 0;
+        return METH_E;
+    }
+    const double kl = exp(-g.sl * inv2h2), kc = exp(-g.sc * inv2h2);
+    const double cb = nR * (fmax(kl - kc, kc - ku) + 1e-15 * kl);
+    const bool centroid = cb <= tau;
+    if (centroid && force == DFGT_FORCE_NONE) {
+        if (nQ == 1.0 && order_far(g.wR / (2.0 * h), nR, tau, 1, D) == 1) {
+            *order = 1;
+            return METH_F;
         }
+        if (nR == 1.0 && order_far(g.wQ / (2.0 * h), nR, tau, 1, D) == 1) {
+            *order = 1;
+            return METH_D;
+        }
+        *order = 1;
+        return METH_T;
+    }
+    int pF = order_far(g.wR / (2.0 * h), nR, tau, pmax, D);
+    int pD = order_far(g.wQ / (2.0 * h), nR, tau, pmax, D);
+    int pT = order_f2l(fmax(g.wQ, g.wR) / (2.0 * h), nR, tau, pmax, D);
+    if (centroid) pT = 1;
+    if (force == DFGT_FORCE_F) pD = pT = 0;
+    if (force == DFGT_FORCE_D) pF = pT = 0;
+    if (force == DFGT_FORCE_T) pF = pD = 0;
+    if (force == DFGT_FORCE_CENTROID) {
+        pF = pD = 0;
+        pT = centroid ? 1 : 0;
     }
     const double inf = INFINITY;
     const double cF = pF ? D * nQ * powi((double)pF, D) : inf;
@@ -222,6 +249,8 @@ struct TravOut {
     Op *fops;
     Group *lgrp;
     Op *lops;
+    int *lnodes;  // (q, job) pairs with local ops, 2 ints each
+    int *headE, *headF, *headL;
     int *cnt;
     unsigned long long *stats;
 };
@@ -232,11 +261,12 @@ __device__ __forceinline__ int wave_excl(int v, int *total) {
     return inc - v;
 }
 
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
 // One wave per segment.
 __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                  const Seg *__restrict__ segs, const int *__restrict__ pairs,
-                                                 const double *__restrict__ glE, int force, int *dec,
-                                                 TravOut o) {
+                                                 int force, int leaf_local, int *dec, TravOut o) {
     const int lane = threadIdx.x;
     const Seg sg = segs[blockIdx.x];
     const Job jb = jobs[sg.job];
@@ -255,21 +285,22 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
         sl += (double)(R.end[r] - R.begin[r]) * exp(-g.su * jb.inv2h2);
     }
     sl = wave_sum(sl);
-    const double gl = (sg.gl + (qleaf ? glE[jb.noff + q] : 0.0) + sl) * (1.0 - 1e-12);
+    const double gl = fmax((sg.gl + sl) * (1.0 - 1e-12), jb.prior);
 
     // 2. decisions and counts
     int cE = 0, cF = 0, cL = 0, cN = 0, nT = 0, nC = 0, nD = 0, maxord = 0;
-    double plo = 0.0;
+    double plo = 0.0, ept = 0.0;
     for (int i = lane; i < sg.count; i += 64) {
         const int r = pairs[sg.start + i];
         const PairGeom g = pair_geom(Q, q, R, r);
         const double nR = (double)(R.end[r] - R.begin[r]);
         const double tau = jb.eps_eff * nR * gl / jb.nR;
+        const double ku = exp(-g.su * jb.inv2h2);
         int ord = 0;
-        const int m = choose(g, jb.h, jb.inv2h2, nQ, nR, tau, pmax, D, force, &ord);
+        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, &ord);
         const bool rleaf = R.left[r] < 0;
         if (m != METH_E) {
-            plo += nR * exp(-g.su * jb.inv2h2);
+            plo += nR * ku;
             if (m == METH_F) ++cF;
             else {
                 ++cL;
@@ -280,6 +311,7 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
             maxord = max(maxord, ord);
         } else if (qleaf && rleaf) {
             ++cE;
+            ept += nR;
         } else {
             cN += (qleaf || !rleaf) ? 2 : 1;
         }
@@ -291,39 +323,60 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
     wave_excl(cL, &tL);
     wave_excl(cN, &tN);
     plo = wave_sum(plo);
+    ept = wave_sum(ept);
     const double gl_child = sg.gl + plo * (1.0 - 1e-12);
     const int nFp = wave_sum_i(cF), nDp = wave_sum_i(nD), nTp = wave_sum_i(nT), nCp = wave_sum_i(nC);
     int mo = maxord;
     for (int off = 32; off >= 1; off >>= 1) mo = max(mo, __shfl_xor(mo, off, 64));
 
-    // reserve contiguous output ranges
-    int ebase = 0, fbase = 0, lbase = 0, cbase = 0, egi = 0, fgi = 0, lgi = 0, sgi = 0;
+    // reserve contiguous output ranges and link the new groups into their chains
+    int ebase = 0, fbase = 0, lbase = 0, cbase = 0, sgi = 0;
     const int npair_out = qleaf ? tN : 2 * tN;
     const int nseg_out = tN > 0 ? (qleaf ? 1 : 2) : 0;
+    const size_t hq = (size_t)jb.noff + q;
     if (lane == 0) {
         if (tE) {
-            ebase = atomicAdd(&o.cnt[C_EOP], tE);
-            egi = atomicAdd(&o.cnt[C_EGRP], 1);
+            ebase = atomicAdd(&o.cnt[C_EOP * CP], tE);
+            const int gi = atomicAdd(&o.cnt[C_EGRP * CP], 1);
+            // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
+            // absolute error below 2^-26 G by computing tiny sums in FP64.
+            const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
+            const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
+            o.egrp[gi] = Group{q, sg.job, ebase, tE, fp64, atomicExch(&o.headE[hq], gi)};
+            if (fp64) atomicAdd(&o.stats[S_FP64 * SP], 1ull);
         }
         if (tF) {
-            fbase = atomicAdd(&o.cnt[C_FOP], tF);
-            fgi = atomicAdd(&o.cnt[C_FGRP], 1);
+            fbase = atomicAdd(&o.cnt[C_FOP * CP], tF);
+            const int gi = atomicAdd(&o.cnt[C_FGRP * CP], 1);
+            o.fgrp[gi] = Group{q, sg.job, fbase, tF, 0, atomicExch(&o.headF[hq], gi)};
         }
         if (tL) {
-            lbase = atomicAdd(&o.cnt[C_LOP], tL);
-            lgi = atomicAdd(&o.cnt[C_LGRP], 1);
+            lbase = atomicAdd(&o.cnt[C_LOP * CP], tL);
+            const int gi = atomicAdd(&o.cnt[C_LGRP * CP], 1);
+            const int prev = atomicExch(&o.headL[hq], gi);
+            o.lgrp[gi] = Group{q, sg.job, lbase, tL, 0, prev};
+            if (prev < 0 && !(qleaf && leaf_local)) {  // a leaf's own local ops may run in k_leaf
+                const int li = atomicAdd(&o.cnt[C_LNODE * CP], 1);
+                o.lnodes[2 * li] = q;
+                o.lnodes[2 * li + 1] = sg.job;
+            }
         }
         if (npair_out) {
-            cbase = atomicAdd(&o.cnt[C_PAIR], npair_out);
-            sgi = atomicAdd(&o.cnt[C_SEG], nseg_out);
+            cbase = atomicAdd(&o.cnt[C_PAIR * CP], npair_out);
+            sgi = atomicAdd(&o.cnt[C_SEG * CP], nseg_out);
         }
-        atomicAdd(&o.stats[S_PAIRS], (unsigned long long)sg.count);
-        if (nFp) atomicAdd(&o.stats[S_F], (unsigned long long)nFp);
-        if (nDp) atomicAdd(&o.stats[S_D], (unsigned long long)nDp);
-        if (nTp) atomicAdd(&o.stats[S_T], (unsigned long long)nTp);
-        if (nCp) atomicAdd(&o.stats[S_C], (unsigned long long)nCp);
-        if (tE) atomicAdd(&o.stats[S_BLEAF], (unsigned long long)tE);
-        if (mo) atomicMax(&o.stats[S_MAXORD], (unsigned long long)mo);
+        atomicAdd(&o.stats[S_PAIRS * SP], (unsigned long long)sg.count);
+        atomicAdd(&o.stats[S_SEGS * SP], 1ull);
+        atomicMax(&o.stats[S_MAXSEG * SP], (unsigned long long)sg.count);
+        if (nFp) atomicAdd(&o.stats[S_F * SP], (unsigned long long)nFp);
+        if (nDp) atomicAdd(&o.stats[S_D * SP], (unsigned long long)nDp);
+        if (nTp) atomicAdd(&o.stats[S_T * SP], (unsigned long long)nTp);
+        if (nCp) atomicAdd(&o.stats[S_C * SP], (unsigned long long)nCp);
+        if (tE) {
+            atomicAdd(&o.stats[S_BLEAF * SP], (unsigned long long)tE);
+            atomicAdd(&o.stats[S_BPTS * SP], (unsigned long long)(nQ * ept));
+        }
+        if (mo) atomicMax(&o.stats[S_MAXORD * SP], (unsigned long long)mo);
     }
     ebase = __shfl(ebase, 0, 64);
     fbase = __shfl(fbase, 0, 64);
@@ -373,332 +426,500 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
         lo += tl;
         no += tn;
     }
-    if (lane == 0) {
-        if (tE) {
-            // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
-            // absolute error below 2^-26 G by computing tiny sums in FP64.
-            const double glb = jb.mono ? fmax(gl, 1.0) : gl;
-            const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
-            o.egrp[egi] = Group{q, sg.job, ebase, tE, fp64, 0};
-        }
-        if (tF) o.fgrp[fgi] = Group{q, sg.job, fbase, tF, 0, 0};
-        if (tL) o.lgrp[lgi] = Group{q, sg.job, lbase, tL, 0, 0};
-        if (tN) {
-            o.nsegs[sgi] = Seg{QL, sg.job, cbase, tN, gl_child};
-            if (!qleaf) o.nsegs[sgi + 1] = Seg{QR, sg.job, cbase + tN, tN, gl_child};
-        }
-    }
-}
-
-// ---------------------------------------------------------------- DFGTBase
-constexpr int kBaseBlock = 256;
-constexpr int kInner = 64;
-
-__global__ __launch_bounds__(kBaseBlock) void k_base(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                                     const Group *__restrict__ grp, const int *__restrict__ eops,
-                                                     int precision, double *GE, double *glE,
-                                                     unsigned long long *stats) {
-    __shared__ double red[kBaseBlock];
-    __shared__ double mn[kBaseBlock / 64];
-    const Group g = grp[blockIdx.x];
-    const Job jb = jobs[g.job];
-    const DevTree &Q = trees[jb.qt];
-    const DevTree &R = trees[jb.rt];
-    const int d = Q.d;
-    const int qb = Q.begin[g.q], nq = Q.end[g.q] - qb;
-    const bool fp64 = precision == DFGT_PREC_FP64 || g.flags;
-    int slots = 1;
-    while (slots < nq && slots < kBaseBlock) slots <<= 1;
-    const int ngr = kBaseBlock / slots;
-    const int qi = threadIdx.x % slots, gr = threadIdx.x / slots;
-    double gmin = INFINITY;
-    long long pts = 0;
-    for (int q0 = 0; q0 < nq; q0 += slots) {
-        const int qq = q0 + qi;
-        const bool act = qq < nq;
-        double acc = 0.0;
-        if (act) {
-            const double sc = fp64 ? jb.s : jb.sig;
-            double qs[kMaxD];
-            for (int k = 0; k < d; ++k) qs[k] = Q.x[(size_t)(qb + qq) * d + k] * sc;
-            for (int e = gr; e < g.count; e += ngr) {
-                const int r = eops[g.start + e];
-                const int rb = R.begin[r], re = R.end[r];
-                if (fp64) {
-                    for (int j = rb; j < re; ++j) {
-                        double t = 0.0;
-                        for (int k = 0; k < d; ++k) {
-                            const double dd = fma(R.x[(size_t)j * d + k], -sc, qs[k]);
-                            t = fma(dd, dd, t);
-                        }
-                        acc += exp(-t);
-                    }
-                } else {
-                    for (int j0 = rb; j0 < re; j0 += kInner) {
-                        const int j1 = min(re, j0 + kInner);
-                        float ps = 0.0f;
-                        for (int j = j0; j < j1; ++j) {
-                            double t = 0.0;
-                            for (int k = 0; k < d; ++k) {
-                                const double dd = fma(R.x[(size_t)j * d + k], -sc, qs[k]);
-                                t = fma(dd, dd, t);
-                            }
-                            ps += __builtin_amdgcn_exp2f(-(float)t);
-                        }
-                        acc += (double)ps;
-                    }
-                }
-                if (qi == 0 && q0 == 0) pts += (long long)(re - rb);
-            }
-        }
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        if (gr == 0 && act) {
-            double s = 0.0;
-            for (int k = 0; k < ngr; ++k) s += red[k * slots + qi];
-            const size_t gi = (size_t)jb.qoff + qb + qq;
-            const double v = GE[gi] + s;
-            GE[gi] = v;
-            gmin = fmin(gmin, v);
-        }
-        __syncthreads();
-    }
-    gmin = wave_min(gmin);
-    if ((threadIdx.x & 63) == 0) mn[threadIdx.x >> 6] = gmin;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = mn[0];
-        for (int w = 1; w < kBaseBlock / 64; ++w) m = fmin(m, mn[w]);
-        glE[jb.noff + g.q] = m;
-    }
-    // point pairs: lanes with qi == 0 counted |R| per exhaustive leaf they handled
-    long long tot = pts;
-    for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
-    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(&stats[S_BPTS], (unsigned long long)(tot * nq));
-    if (threadIdx.x == 0 && fp64 && precision != DFGT_PREC_FP64) atomicAdd(&stats[S_FP64], 1ull);
-}
-
-// ---------------------------------------------------------------- EvalFarFieldExpansion
-// G_F(q) += sum_{alpha < p} M_alpha h_alpha((q - R.c) s),  M_alpha = s^|alpha| mu_alpha,
-// h_alpha(t) = e^{-|t|^2} prod_k H_{alpha_k}(t_k).
-__global__ __launch_bounds__(256) void k_far(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                             const Group *__restrict__ grp, const Op *__restrict__ fops,
-                                             double *GF) {
-    const Group g = grp[blockIdx.x];
-    const Job jb = jobs[g.job];
-    const DevTree &Q = trees[jb.qt];
-    const DevTree &R = trees[jb.rt];
-    const int d = Q.d, pmax = Q.pmax, P = Q.P;
-    const int qb = Q.begin[g.q], qe = Q.end[g.q];
-    const double s = jb.s;
-    for (int qi = qb + threadIdx.x; qi < qe; qi += blockDim.x) {
-        double sum = 0.0;
-        for (int o = 0; o < g.count; ++o) {
-            const Op op = fops[g.start + o];
-            const int r = op.r, p = op.meta & 255;
-            double t[kMaxD], tt = 0.0;
-            for (int k = 0; k < d; ++k) {
-                t[k] = (Q.x[(size_t)qi * d + k] - R.ctr[(size_t)r * d + k]) * s;
-                tt += t[k] * t[k];
-            }
-            if (tt > 745.0) continue;  // e^{-|t|^2} underflows: the expansion is 0
-            double H[kMaxD * 16];
-            for (int k = 0; k < d; ++k) hermite_polys(t[k], p, H + k * 16);
-            const double *mu = R.mu + (size_t)r * P;
-            double w = 0.0;
-            const int np = ipow_i(p, d);
-            for (int i = 0; i < np; ++i) {
-                int rem = i, pos = 0, stride = 1, asum = 0;
-                double prod = 1.0;
-                for (int k = d - 1; k >= 0; --k) {
-                    const int a = rem % p;
-                    rem /= p;
-                    pos += a * stride;
-                    stride *= pmax;
-                    asum += a;
-                    prod *= H[k * 16 + a];
-                }
-                w = fma(mu[pos] * powi(s, asum), prod, w);
-            }
-            sum += exp(-tt) * w;
-        }
-        GF[(size_t)jb.qoff + qi] += sum;
+    if (lane == 0 && tN) {
+        o.nsegs[sgi] = Seg{QL, sg.job, cbase, tN, gl_child};
+        if (!qleaf) o.nsegs[sgi + 1] = Seg{QR, sg.job, cbase + tN, tN, gl_child};
     }
 }
 
 // ---------------------------------------------------------------- local moments: D and T ops
-// Dynamic LDS layout: acc[P] | buf0[P] | buf1[P] | coef[pmax*pmax] | H[d * 2 pmax]
-// (buf0 / buf1 / acc in a global scratch slice when P is large).
+// One wave per (Q, job) with local ops; the node's chain of groups (all
+// levels) is walked in a fixed order and accumulated in the wave's LDS:
+//   D (AccumulateDirectLocalMoment):
+//     L_beta += ((-1)^|beta| / beta!) sum_{x in R} e^{-|t|^2} prod_k H_{beta_k}(t_k),  t = (Q.c - x) s;
+//     per chunk of 64 points each lane tabulates one point's H_b(t_k) (the
+//     exponential folded into the first dimension), then lanes over beta sum
+//     the chunk in point order.
+//   T (TransFarToLocal):
+//     L_beta += ((-1)^|beta| / beta!) e^{-|t0|^2} sum_{alpha<p} M_alpha prod_k H_{alpha_k+beta_k}(t0_k),
+//     t0 = (Q.c - R.c) s, M_alpha = s^|alpha| mu_alpha; at order 1 this is
+//     L_0 += |R| e^{-|t0|^2} (M_0 = mu_0 = |R|), the centroid form.
+// LDS: acc[P] | Ms[P] | Ht[D][2 pmax] | Hx[64][D][pmax]
+__device__ __forceinline__ double coef_beta(int i, int d, int pmax) {
+    int rem = i, bs = 0;
+    double f = 1.0;
+    for (int k = d - 1; k >= 0; --k) {
+        const int b = rem % pmax;
+        rem /= pmax;
+        bs += b;
+        f *= inv_factorial(b);
+    }
+    return (bs & 1) ? -f : f;
+}
+
+// One D or T op applied by one wave to the local moments acc[P] about qc.
+// Wave-private scratch: Ms[P] | Ht[D][2 pmax] | Hx[64][D][pmax].
+__device__ void wave_local_op(const DevTree &R, int r, int p, int m, const double *qc, double s, int d, int pmax,
+                              int P, const unsigned long long *dg, const unsigned short *mt, const double *cb,
+                              double *acc, double *Ms, double *Ht, double *Hx, int lane) {
+    if (m == METH_T) {
+        double tt = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * s;
+            tt += t * t;
+        }
+        if (tt > 745.0) return;  // e^{-|t0|^2} underflows: nothing to add
+        const double e0 = exp(-tt);
+        const double *mu = R.mu + (size_t)r * P;
+        if (p == 1) {
+            if (lane == 0) acc[0] += mu[0] * e0;
+            return;
+        }
+        for (int i = lane; i < P; i += 64) {
+            const int meta = mt[i];
+            Ms[i] = (meta >> 8) < p ? mu[i] * powi(s, meta & 255) : 0.0;
+        }
+        if (lane < d) hermite_polys((qc[lane] - R.ctr[(size_t)r * d + lane]) * s, 2 * p - 1, Ht + lane * 2 * pmax);
+        wave_sync();
+        for (int b = lane; b < P; b += 64) {
+            if ((mt[b] >> 8) >= p) continue;
+            const unsigned long long bd = dg[b];
+            double sum = 0.0;
+            for (int a = 0; a < P; ++a) {
+                if ((mt[a] >> 8) >= p) continue;
+                const unsigned long long ad = dg[a];
+                double prod = Ms[a];
+                for (int k = 0; k < d; ++k) prod *= Ht[k * 2 * pmax + dig_at(ad, k) + dig_at(bd, k)];
+                sum += prod;
+            }
+            acc[b] += cb[b] * e0 * sum;
+        }
+        wave_sync();
+        return;
+    }
+    const int rb = R.begin[r], re = R.end[r];
+    for (int x0 = rb; x0 < re; x0 += 64) {
+        const int cnt = min(64, re - x0);
+        if (lane < cnt) {
+            double *row = Hx + (size_t)lane * d * pmax;
+            double tt = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double t = (qc[k] - R.x[(size_t)(x0 + lane) * d + k]) * s;
+                tt += t * t;
+                hermite_polys(t, p, row + k * pmax);
+            }
+            const double e = tt > 745.0 ? 0.0 : exp(-tt);
+            for (int b = 0; b < p; ++b) row[b] *= e;
+        }
+        wave_sync();
+        for (int b = lane; b < P; b += 64) {
+            if ((mt[b] >> 8) >= p) continue;
+            const unsigned long long bd = dg[b];
+            double sum = 0.0;
+            for (int j = 0; j < cnt; ++j) {
+                const double *row = Hx + (size_t)j * d * pmax;
+                double prod = row[dig_at(bd, 0)];
+                for (int k = 1; k < d; ++k) prod *= row[k * pmax + dig_at(bd, k)];
+                sum += prod;
+            }
+            acc[b] += cb[b] * sum;
+        }
+        wave_sync();
+    }
+}
+
+constexpr int kMaxSeg = 256;
+
+// Applies every local op of the chain starting at group `head` to acc[P]
+// (block-wide, all threads must call it).  Centroid ops (T at order 1:
+// L_0 += |R| e^{-|t0|^2}) are taken by all threads in parallel, op i by
+// thread i mod nthr, and reduced in thread order; the other ops are dealt to
+// the waves round-robin in chain order, each wave accumulating into its own
+// partial vector; partials are added in wave order.  Chains are flattened in
+// batches of kMaxSeg groups into the segment table segS / segE (cumulative op
+// counts) by thread 0.
+// Scratch: red[nthr] | wacc[nwv][P] | wMs[nwv][P] | wHt[nwv][2 D pmax] | wHx[nwv][64][D][pmax]
+__device__ void block_local_ops(int head, const Group *__restrict__ grp, const Op *__restrict__ lops,
+                                const DevTree &R, const double *qc, double s, int d, int pmax, int P,
+                                const unsigned long long *dg, const unsigned short *mt, const double *cb, double *acc,
+                                double *red, double *wacc, double *wMs, double *wHt, double *wHx, int *segS,
+                                int *segE, int *state) {
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    double *wa = wacc + (size_t)wv * P;
+    for (int i = lane; i < P; i += 64) wa[i] = 0.0;
+    double csum = 0.0;
+    if (tid == 0) state[0] = head;
+    __syncthreads();
+    while (true) {
+        if (tid == 0) {
+            int n = 0, tot = 0, gi = state[0];
+            while (gi >= 0 && n < kMaxSeg) {
+                const Group g = grp[gi];
+                segS[n] = g.start;
+                tot += g.count;
+                segE[n++] = tot;
+                gi = g.next;
+            }
+            state[0] = gi;
+            state[1] = n;
+            state[2] = tot;
+        }
+        __syncthreads();
+        const int nseg = state[1], nops = state[2];
+        if (nseg == 0) break;
+        int sp = 0;
+        for (int idx = tid; idx < nops; idx += nthr) {
+            while (idx >= segE[sp]) ++sp;
+            const Op op = lops[segS[sp] + idx - (sp ? segE[sp - 1] : 0)];
+            if ((op.meta >> 8) != METH_T || (op.meta & 255) != 1) continue;
+            double tt = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double t = (qc[k] - R.ctr[(size_t)op.r * d + k]) * s;
+                tt += t * t;
+            }
+            if (tt <= 745.0) csum = fma(R.mu[(size_t)op.r * P], exp(-tt), csum);
+        }
+        sp = 0;
+        for (int idx = wv; idx < nops; idx += nwv) {
+            while (idx >= segE[sp]) ++sp;
+            const Op op = lops[segS[sp] + idx - (sp ? segE[sp - 1] : 0)];
+            const int m = op.meta >> 8, p = op.meta & 255;
+            if (m == METH_T && p == 1) continue;
+            wave_local_op(R, op.r, p, m, qc, s, d, pmax, P, dg, mt, cb, wa, wMs + (size_t)wv * P,
+                          wHt + (size_t)wv * 2 * d * pmax, wHx + (size_t)wv * 64 * d * pmax, lane);
+        }
+        __syncthreads();
+    }
+    red[tid] = csum;
+    __syncthreads();
+    for (int i = tid; i < P; i += nthr) {
+        double v = acc[i];
+        for (int w = 0; w < nwv; ++w) v += wacc[(size_t)w * P + i];
+        if (i == 0)
+            for (int t = 0; t < nthr; ++t) v += red[t];
+        acc[i] = v;
+    }
+    __syncthreads();
+}
+
+// One block per internal (Q, job) with local ops.
+// LDS: acc[P] | cb[P] | red[nthr] | wacc[nwv][P] | wMs[nwv][P] | wHt[nwv][2 D pmax] | wHx[nwv][64][D][pmax]
+//      | dg[P] (u64) | mt[P] (u16)
+__global__ __launch_bounds__(256) void k_local(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                               const int *__restrict__ lnodes, const int *__restrict__ headL,
+                                               const Group *__restrict__ grp, const Op *__restrict__ lops, double *L,
+                                               unsigned char *lflag, unsigned long long *stats) {
+    extern __shared__ double smem[];
+    __shared__ int segS[kMaxSeg], segE[kMaxSeg], state[3];
+    const int tid = threadIdx.x, nthr = blockDim.x, nwv = nthr >> 6;
+    const int q = lnodes[2 * blockIdx.x], job = lnodes[2 * blockIdx.x + 1];
+    const Job jb = jobs[job];
+    const DevTree &Q = trees[jb.qt];
+    const DevTree &R = trees[jb.rt];
+    const int d = Q.d, pmax = Q.pmax, P = Q.P;
+    double *acc = smem, *cb = acc + P, *red = cb + P, *wacc = red + nthr, *wMs = wacc + (size_t)nwv * P;
+    double *wHt = wMs + (size_t)nwv * P, *wHx = wHt + (size_t)nwv * 2 * d * pmax;
+    unsigned long long *dg = reinterpret_cast<unsigned long long *>(wHx + (size_t)nwv * 64 * d * pmax);
+    unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
+    build_digit_tables(dg, mt, P, d, pmax);
+    for (int i = tid; i < P; i += nthr) {
+        acc[i] = 0.0;
+        cb[i] = coef_beta(i, d, pmax);  // (-1)^|beta| / beta!
+    }
+    const size_t hq = (size_t)jb.noff + q;
+    if (tid == 0) {
+        int n = 0;
+        for (int gi = headL[hq]; gi >= 0; gi = grp[gi].next) n += grp[gi].count;
+        atomicMax(&stats[S_MAXLOPS * SP], (unsigned long long)n);
+    }
+    __syncthreads();
+    block_local_ops(headL[hq], grp, lops, R, Q.ctr + (size_t)q * d, jb.s, d, pmax, P, dg, mt, cb, acc, red, wacc,
+                    wMs, wHt, wHx, segS, segE, state);
+    double *Lq = L + hq * P;
+    for (int i = tid; i < P; i += nthr) Lq[i] = acc[i];
+    if (tid == 0) lflag[hq] = 1;
+}
+
+// Large coefficient vectors (P > 1024): T through D one-dimensional mode
+// products (block-wide, buffers in a global scratch slice), D and the order-1
+// form as in k_local.  LDS: coef[pmax^2] | Ht[D][2 pmax] | Hx[64][D][pmax]
 constexpr int kLocBlock = 256;
 
-__global__ __launch_bounds__(kLocBlock) void k_local(const DevTree *__restrict__ trees,
-                                                     const Job *__restrict__ jobs, const Group *__restrict__ grp,
-                                                     const Op *__restrict__ lops, int use_lds,
-                                                     double *__restrict__ gscratch, double *L,
-                                                     unsigned char *lflag) {
+__global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restrict__ trees,
+                                                         const Job *__restrict__ jobs, const int *__restrict__ lnodes,
+                                                         const int *__restrict__ headL, const Group *__restrict__ grp,
+                                                         const Op *__restrict__ lops, double *__restrict__ gscratch,
+                                                         double *L, unsigned char *lflag) {
     extern __shared__ double smem[];
-    const Group g = grp[blockIdx.x];
-    const Job jb = jobs[g.job];
+    const int q = lnodes[2 * blockIdx.x], job = lnodes[2 * blockIdx.x + 1];
+    const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
     const int d = Q.d, pmax = Q.pmax, P = Q.P;
     const double s = jb.s;
-    double *acc, *buf0, *buf1, *coef, *Ht;
-    if (use_lds) {
-        acc = smem;
-        buf0 = acc + P;
-        buf1 = buf0 + P;
-        coef = buf1 + P;
-    } else {
-        acc = gscratch + (size_t)blockIdx.x * 3 * P;
-        buf0 = acc + P;
-        buf1 = buf0 + P;
-        coef = smem;
-    }
-    Ht = coef + pmax * pmax;
-    const double *qc = Q.ctr + (size_t)g.q * d;
+    double *acc = gscratch + (size_t)blockIdx.x * 3 * P, *buf0 = acc + P, *buf1 = buf0 + P;
+    double *coef = smem, *Ht = coef + pmax * pmax, *Hx = Ht + 2 * d * pmax;
+    const double *qc = Q.ctr + (size_t)q * d;
     for (int i = threadIdx.x; i < P; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
-    for (int o = 0; o < g.count; ++o) {
-        const Op op = lops[g.start + o];
-        const int r = op.r, p = op.meta & 255, m = op.meta >> 8;
-        if (m == METH_D) {
-            // L_beta += sum_{x in R} ((-1)^|beta| / beta!) h_beta((Q.c - x) s)
-            const int rb = R.begin[r], re = R.end[r];
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                bool inside;
-                const int bs = digit_sum(i, d, pmax, p, &inside);
-                if (!inside) continue;
-                double cf = (bs & 1) ? -1.0 : 1.0;
-                for (int k = 0; k < d; ++k) cf *= inv_factorial(digit(i, k, d, pmax));
-                double sum = 0.0;
-                for (int j = rb; j < re; ++j) {
-                    double tt = 0.0, prod = 1.0;
-                    for (int k = 0; k < d; ++k) {
-                        const double t = (qc[k] - R.x[(size_t)j * d + k]) * s;
-                        tt += t * t;
-                        double Hk[16];
-                        const int b = digit(i, k, d, pmax);
-                        hermite_polys(t, b + 1, Hk);
-                        prod *= Hk[b];
+    for (int gi = headL[(size_t)jb.noff + q]; gi >= 0; gi = grp[gi].next) {
+        const Group g = grp[gi];
+        for (int o = 0; o < g.count; ++o) {
+            const Op op = lops[g.start + o];
+            const int r = op.r, p = op.meta & 255, m = op.meta >> 8;
+            if (m == METH_T) {
+                double tt = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * s;
+                    tt += t * t;
+                }
+                if (tt > 745.0) continue;  // uniform across the block
+                const double e0 = exp(-tt);
+                const double *mu = R.mu + (size_t)r * P;
+                if (p == 1) {
+                    if (threadIdx.x == 0) acc[0] += mu[0] * e0;
+                    __syncthreads();
+                    continue;
+                }
+                for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                    bool inside;
+                    const int as = digit_sum(i, d, pmax, p, &inside);
+                    buf0[i] = inside ? mu[i] * powi(s, as) : 0.0;
+                }
+                for (int k = threadIdx.x; k < d; k += blockDim.x)
+                    hermite_polys((qc[k] - R.ctr[(size_t)r * d + k]) * s, 2 * p - 1, Ht + k * 2 * pmax);
+                __syncthreads();
+                double *src = buf0, *dst = buf1;
+                for (int k = 0; k < d; ++k) {
+                    for (int i = threadIdx.x; i < pmax * pmax; i += blockDim.x) {
+                        const int b = i / pmax, a = i % pmax;
+                        coef[i] = (a < p && b < p) ? Ht[k * 2 * pmax + a + b] : 0.0;
                     }
-                    if (tt <= 745.0) sum = fma(exp(-tt), prod, sum);
+                    __syncthreads();
+                    mode_product(src, dst, coef, P, d, pmax, k, p);
+                    __syncthreads();
+                    double *tmp = src;
+                    src = dst;
+                    dst = tmp;
                 }
-                acc[i] += cf * sum;
-            }
-            __syncthreads();
-        } else {
-            // T: L_beta += ((-1)^|beta| / beta!) sum_{alpha<p} M_alpha h_{alpha+beta}((Q.c - R.c) s)
-            double tt = 0.0;
-            for (int k = 0; k < d; ++k) {
-                const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * s;
-                tt += t * t;
-            }
-            if (tt > 745.0) continue;  // uniform across the block
-            const double e0 = exp(-tt);
-            const double *mu = R.mu + (size_t)r * P;
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                bool inside;
-                const int as = digit_sum(i, d, pmax, p, &inside);
-                buf0[i] = inside ? mu[i] * powi(s, as) : 0.0;
-            }
-            // Hermite polynomials H_0 .. H_{2p-2} per dimension at t0
-            for (int k = threadIdx.x; k < d; k += blockDim.x) {
-                const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * s;
-                hermite_polys(t, 2 * p - 1, Ht + k * 2 * pmax);
-            }
-            __syncthreads();
-            double *src = buf0, *dst = buf1;
-            for (int k = 0; k < d; ++k) {
-                // coef[b][a] = H_{a+b}(t0_k) for a, b < p
-                for (int i = threadIdx.x; i < pmax * pmax; i += blockDim.x) {
-                    const int b = i / pmax, a = i % pmax;
-                    coef[i] = (a < p && b < p) ? Ht[k * 2 * pmax + a + b] : 0.0;
+                for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                    bool inside;
+                    digit_sum(i, d, pmax, p, &inside);
+                    if (inside) acc[i] += coef_beta(i, d, pmax) * e0 * src[i];
                 }
                 __syncthreads();
-                mode_product(src, dst, coef, P, d, pmax, k, p);
-                __syncthreads();
-                double *tmp = src;
-                src = dst;
-                dst = tmp;
+            } else {
+                const int rb = R.begin[r], re = R.end[r];
+                for (int x0 = rb; x0 < re; x0 += 64) {
+                    const int cnt = min(64, re - x0);
+                    if (threadIdx.x < cnt) {
+                        double *row = Hx + (size_t)threadIdx.x * d * pmax;
+                        double tt = 0.0;
+                        for (int k = 0; k < d; ++k) {
+                            const double t = (qc[k] - R.x[(size_t)(x0 + threadIdx.x) * d + k]) * s;
+                            tt += t * t;
+                            hermite_polys(t, p, row + k * pmax);
+                        }
+                        const double e = tt > 745.0 ? 0.0 : exp(-tt);
+                        for (int b = 0; b < p; ++b) row[b] *= e;
+                    }
+                    __syncthreads();
+                    for (int b = threadIdx.x; b < P; b += blockDim.x) {
+                        bool inside;
+                        digit_sum(b, d, pmax, p, &inside);
+                        if (!inside) continue;
+                        double sum = 0.0;
+                        for (int j = 0; j < cnt; ++j) {
+                            const double *row = Hx + (size_t)j * d * pmax;
+                            int bi = b;
+                            double prod = 1.0;
+                            for (int k = d - 1; k >= 0; --k) {
+                                prod *= row[k * pmax + bi % pmax];
+                                bi /= pmax;
+                            }
+                            sum += prod;
+                        }
+                        acc[b] += coef_beta(b, d, pmax) * sum;
+                    }
+                    __syncthreads();
+                }
             }
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                bool inside;
-                const int bs = digit_sum(i, d, pmax, p, &inside);
-                if (!inside) continue;
-                double cf = (bs & 1) ? -e0 : e0;
-                for (int k = 0; k < d; ++k) cf *= inv_factorial(digit(i, k, d, pmax));
-                acc[i] += cf * src[i];
-            }
-            __syncthreads();
         }
     }
-    double *Lq = L + ((size_t)jb.noff + g.q) * P;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) Lq[i] += acc[i];
-    if (threadIdx.x == 0) lflag[jb.noff + g.q] = 1;
+    __syncthreads();
+    double *Lq = L + ((size_t)jb.noff + q) * P;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) Lq[i] = acc[i];
+    if (threadIdx.x == 0) lflag[jb.noff + q] = 1;
 }
 
-// ---------------------------------------------------------------- DFGTPost
-// One block per (query leaf, job).  LDS: acc[P] | tmp[P] | coef[pmax^2] (global when large).
-__global__ __launch_bounds__(256) void k_post(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                              int nleaves, const double *__restrict__ L,
-                                              const unsigned char *__restrict__ lflag, const double *__restrict__ GE,
-                                              const double *__restrict__ GF, int use_lds,
-                                              double *__restrict__ gscratch) {
+// ---------------------------------------------------------------- per query leaf
+// One block per (query leaf, job).
+//   1. TransLocalToLocal from the root down the path to the leaf (each step
+//      one axis at a time: child L_a += sum_{b >= a} C(b, a) L_b X^{b-a},
+//      X = (child.c - parent.c) s), adding every path node's own moments;
+//      then the leaf's own D / T ops, dealt to the block's waves round-robin
+//      (wave partials added in wave order).
+//   2. Threads form ngr groups of `slots` lanes, one lane per query.  Thread 0
+//      flattens the leaf's E chain and the F chains of all path nodes into a
+//      segment table; ops are then processed in rounds, op = round * ngr +
+//      group, so groups sharing a wave work in lock step:
+//        E (DFGTBase): the reference leaf is staged in the group's LDS slice
+//           and sum_r exp(-|q - r|^2 / 2h^2) taken over it (mixed: exp2 of the
+//           FP64 squared scaled distance rounded to FP32, FP32 partial over
+//           <= 64 points, FP64 sums; or FP64 throughout);
+//        F (EvalFarFieldExpansion): e^{-|t|^2} sum_{alpha<p} s^|alpha| mu_alpha prod_k H_{alpha_k}(t_k),
+//           t = (q - R.c) s, Hermite polynomials in the lane's LDS rows.
+//   3. Group partials are added in group order, the local expansion is
+//      evaluated (EvalLocalExpansion) and G = G_L + G_E + G_F is written in the
+//      caller's order.
+constexpr int kInner = 64;
+
+template <int D>
+__device__ __forceinline__ double e_chunk(const double *__restrict__ xs, int cnt, const double *__restrict__ qg,
+                                          double sc, bool fp64) {
+    double qs[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) qs[k] = qg[k] * sc;
+    if (fp64) {
+        double acc = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double dd = fma(xs[j * D + k], -sc, qs[k]);
+                t = fma(dd, dd, t);
+            }
+            acc += exp(-t);
+        }
+        return acc;
+    }
+    float ps = 0.0f;
+    for (int j = 0; j < cnt; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double dd = fma(xs[j * D + k], -sc, qs[k]);
+            t = fma(dd, dd, t);
+        }
+        ps += __builtin_amdgcn_exp2f(-(float)t);
+    }
+    return (double)ps;
+}
+
+__device__ double e_chunk_any(const double *__restrict__ xs, int cnt, int d, const double *__restrict__ qg, double sc,
+                              bool fp64) {
+    double acc = 0.0;
+    float ps = 0.0f;
+    for (int j = 0; j < cnt; ++j) {
+        double t = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double dd = fma(xs[j * d + k], -sc, qg[k] * sc);
+            t = fma(dd, dd, t);
+        }
+        if (fp64) acc += exp(-t);
+        else ps += __builtin_amdgcn_exp2f(-(float)t);
+    }
+    return fp64 ? acc : (double)ps;
+}
+
+__device__ __forceinline__ double e_chunk_dispatch(const double *xs, int cnt, int d, const double *qg, double sc,
+                                                   bool fp64) {
+    switch (d) {
+    case 1: return e_chunk<1>(xs, cnt, qg, sc, fp64);
+    case 2: return e_chunk<2>(xs, cnt, qg, sc, fp64);
+    case 3: return e_chunk<3>(xs, cnt, qg, sc, fp64);
+    case 4: return e_chunk<4>(xs, cnt, qg, sc, fp64);
+    case 5: return e_chunk<5>(xs, cnt, qg, sc, fp64);
+    case 8: return e_chunk<8>(xs, cnt, qg, sc, fp64);
+    case 16: return e_chunk<16>(xs, cnt, qg, sc, fp64);
+    default: return e_chunk_any(xs, cnt, d, qg, sc, fp64);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                              const Group *__restrict__ egrp, const int *__restrict__ eops,
+                                              const Group *__restrict__ fgrp, const Op *__restrict__ fops,
+                                              const Group *__restrict__ lgrp, const Op *__restrict__ lops,
+                                              const int *__restrict__ headE, const int *__restrict__ headF,
+                                              const int *__restrict__ headL, const double *__restrict__ L,
+                                              const unsigned char *__restrict__ lflag, int precision, int acc_in_lds,
+                                              int leaf_local, double *__restrict__ gscratch) {
     extern __shared__ double smem[];
     __shared__ int path[256];
-    __shared__ int plen_s, any_s;
+    __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg];
+    __shared__ int plen_s, any_s, nsg_s, nops_s, st_phase, st_gi, st_pi, lstate[3];
     const int job = blockIdx.y;
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
+    const DevTree &R = trees[jb.rt];
     const int leaf = Q.leaves[blockIdx.x];
     const int d = Q.d, pmax = Q.pmax, P = Q.P;
+    const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
     const double s = jb.s;
+    const int ns = d * (pmax - 1) + 1;
+    const size_t hq = (size_t)jb.noff + leaf;
+    // LDS: red[nthr] | spow[ns] | Hq[nthr][D][pmax] | xs[nthr][D] | cb[P] | wacc[nwv][P] | wMs[nwv][P]
+    //      | wHt[nwv][2 D pmax] | acc[P] | tmp[P] | coef[pmax^2] | dg[P] (u64) | mt[P] (u16)
+    double *red = smem;
+    double *spow = red + nthr;
+    double *Hq_all = spow + ns;
+    double *Hq = Hq_all + (size_t)tid * d * pmax;
+    double *xs = Hq_all + (size_t)nthr * d * pmax;
+    const int nwl = leaf_local ? nwv : 0;  // per-wave local-op scratch only when used
+    double *cb = xs + (size_t)nthr * d;
+    double *wacc = cb + (leaf_local ? P : 0);
+    double *wMs = wacc + (size_t)nwl * P;
+    double *wHt = wMs + (size_t)nwl * P;
+    double *tail = wHt + (size_t)nwl * 2 * d * pmax;
     double *acc, *tmp, *coef;
-    if (use_lds) {
-        acc = smem;
+    if (acc_in_lds) {
+        acc = tail;
         tmp = acc + P;
         coef = tmp + P;
     } else {
         const size_t slot = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
         acc = gscratch + slot * 2 * P;
         tmp = acc + P;
-        coef = smem;
+        coef = tail;
     }
-    if (threadIdx.x == 0) {
-        int n = 0, v = leaf;
-        int any = 0;
+    unsigned long long *dg = reinterpret_cast<unsigned long long *>(coef + pmax * pmax);
+    unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
+    build_digit_tables(dg, mt, P, d, pmax);
+    if (tid == 0) {
+        int n = 0, v = leaf, any = 0;
         while (v >= 0 && n < 256) {
             path[n++] = v;
             any |= lflag[jb.noff + v];
             v = Q.parent[v];
         }
         plen_s = (v >= 0) ? -1 : n;
-        any_s = any;
+        any_s = any | (leaf_local && headL[hq] >= 0 ? 1 : 0);
     }
+    for (int i = tid; i < ns; i += nthr) spow[i] = powi(s, i);
+    if (leaf_local)
+        for (int i = tid; i < P; i += nthr) cb[i] = coef_beta(i, d, pmax);
     __syncthreads();
     const int plen = plen_s;
-    const int qb = Q.begin[leaf], qe = Q.end[leaf];
+    const int qb = Q.begin[leaf], nq = Q.end[leaf] - qb;
     if (plen < 0) {
-        // a path deeper than 256 levels cannot be walked here; signal NaN
-        for (int qi = qb + threadIdx.x; qi < qe; qi += blockDim.x) jb.out[Q.perm[qi]] = NAN;
+        // a root-to-leaf path deeper than 256 levels is not walked: flag it
+        for (int qi = tid; qi < nq; qi += nthr) jb.out[Q.perm[qb + qi]] = NAN;
         return;
     }
+    // 1. local moments at the leaf
     const bool any = any_s != 0;
     if (any) {
-        for (int i = threadIdx.x; i < P; i += blockDim.x) acc[i] = 0.0;
+        for (int i = tid; i < P; i += nthr) acc[i] = 0.0;
         bool nonzero = false;
         for (int pi = plen - 1; pi >= 0; --pi) {
             const int v = path[pi];
             if (pi != plen - 1 && nonzero) {
-                // TransLocalToLocal from the parent path[pi+1] to v, one axis at a time:
-                // child L_a += sum_{b >= a} C(b, a) L_b X^{b-a},  X = (v.c - parent.c) s
                 const int u = path[pi + 1];
                 double *src = acc, *dst = tmp;
                 for (int k = 0; k < d; ++k) {
                     const double X = (Q.ctr[(size_t)v * d + k] - Q.ctr[(size_t)u * d + k]) * s;
                     __syncthreads();
-                    for (int i = threadIdx.x; i < pmax * pmax; i += blockDim.x) {
+                    for (int i = tid; i < pmax * pmax; i += nthr) {
                         const int a = i / pmax, b = i % pmax;
                         double c = 0.0;
                         if (b >= a) {
@@ -715,38 +936,153 @@ __global__ __launch_bounds__(256) void k_post(const DevTree *__restrict__ trees,
                 }
                 __syncthreads();
                 if (src != acc)
-                    for (int i = threadIdx.x; i < P; i += blockDim.x) acc[i] = src[i];
+                    for (int i = tid; i < P; i += nthr) acc[i] = src[i];
                 __syncthreads();
             }
             if (lflag[jb.noff + v]) {
                 const double *Lv = L + ((size_t)jb.noff + v) * P;
-                for (int i = threadIdx.x; i < P; i += blockDim.x) acc[i] += Lv[i];
+                for (int i = tid; i < P; i += nthr) acc[i] += Lv[i];
                 nonzero = true;
             }
             __syncthreads();
         }
+        if (leaf_local && headL[hq] >= 0)
+            block_local_ops(headL[hq], lgrp, lops, R, Q.ctr + (size_t)leaf * d, s, d, pmax, P, dg, mt, cb, acc, red,
+                            wacc, wMs, wHt, Hq_all, segS, segE, lstate);
     }
-    // EvalLocalExpansion at the leaf's points, then G = G_L + G_F + G_E
-    const double *c = Q.ctr + (size_t)leaf * d;
-    for (int qi = qb + threadIdx.x; qi < qe; qi += blockDim.x) {
-        double gl = 0.0;
-        if (any) {
-            double y[kMaxD];
-            for (int k = 0; k < d; ++k) y[k] = (Q.x[(size_t)qi * d + k] - c[k]) * s;
-            for (int i = 0; i < P; ++i) {
-                const double a = acc[i];
-                if (a == 0.0) continue;
-                int rem = i;
-                double prod = 1.0;
-                for (int k = d - 1; k >= 0; --k) {
-                    prod *= powi(y[k], rem % pmax);
-                    rem /= pmax;
-                }
-                gl = fma(a, prod, gl);
-            }
+    // 2. exhaustive and far-field parts
+    int slots = 1;
+    while (slots < nq && slots < nthr) slots <<= 1;
+    const int ngr = nthr / slots;
+    const int qi = tid % slots, tg = tid / slots;
+    const bool staged = slots <= 64;
+    double *xg = xs + (size_t)tg * slots * d;  // the group's staging slice
+    const double *lc = Q.ctr + (size_t)leaf * d;
+    for (int q0 = 0; q0 < nq; q0 += slots) {
+        const int qq = q0 + qi;
+        const bool act = qq < nq;
+        const int qpos = qb + (act ? qq : 0);
+        const double *qg = Q.x + (size_t)qpos * d;
+        double part = 0.0;
+        if (tid == 0) {
+            st_phase = 0;
+            st_gi = headE[hq];
+            st_pi = plen - 1;
         }
-        const size_t gi = (size_t)jb.qoff + qi;
-        jb.out[Q.perm[qi]] = gl + GF[gi] + GE[gi];
+        __syncthreads();
+        while (true) {
+            if (tid == 0) {
+                // flatten the next batch of op groups: the leaf's E chain, then
+                // the F chains of the path nodes from the root down
+                int n = 0, tot = 0, ph = st_phase, gi = st_gi, pi = st_pi;
+                while (n < kMaxSeg) {
+                    if (ph == 0) {
+                        if (gi < 0) {
+                            ph = 1;
+                            gi = pi >= 0 ? headF[(size_t)jb.noff + path[pi]] : -1;
+                            continue;
+                        }
+                        const Group g = egrp[gi];
+                        segT[n] = g.flags ? 2 : 0;
+                        segS[n] = g.start;
+                        tot += g.count;
+                        segE[n++] = tot;
+                        gi = g.next;
+                    } else {
+                        if (gi < 0) {
+                            if (--pi < 0) break;
+                            gi = headF[(size_t)jb.noff + path[pi]];
+                            continue;
+                        }
+                        const Group g = fgrp[gi];
+                        segT[n] = 1;
+                        segS[n] = g.start;
+                        tot += g.count;
+                        segE[n++] = tot;
+                        gi = g.next;
+                    }
+                }
+                st_phase = ph;
+                st_gi = gi;
+                st_pi = pi;
+                nsg_s = n;
+                nops_s = tot;
+            }
+            __syncthreads();
+            const int nops = nops_s;
+            if (nsg_s == 0) break;
+            int sp = 0;
+            for (int base = 0; base < nops; base += ngr) {
+                const int idx = base + tg;
+                if (idx >= nops) continue;
+                while (idx >= segE[sp]) ++sp;
+                const int off = idx - (sp ? segE[sp - 1] : 0);
+                const int type = segT[sp];
+                if (type != 1) {
+                    const bool fp64 = precision == DFGT_PREC_FP64 || type == 2;
+                    const double sc = fp64 ? jb.s : jb.sig;
+                    const int r = eops[segS[sp] + off];
+                    const int rb = R.begin[r], re = R.end[r];
+                    if (staged) {
+                        for (int j0 = rb; j0 < re; j0 += slots) {
+                            const int cnt = min(slots, re - j0);
+                            if (qi < cnt)
+                                for (int k = 0; k < d; ++k) xg[qi * d + k] = R.x[(size_t)(j0 + qi) * d + k];
+                            wave_sync();
+                            if (act) part += e_chunk_dispatch(xg, cnt, d, qg, sc, fp64);
+                            wave_sync();
+                        }
+                    } else if (act) {
+                        for (int j0 = rb; j0 < re; j0 += kInner)
+                            part += e_chunk_dispatch(R.x + (size_t)j0 * d, min(kInner, re - j0), d, qg, sc, fp64);
+                    }
+                } else if (act) {
+                    const Op op = fops[segS[sp] + off];
+                    const int r = op.r, p = op.meta & 255;
+                    const double *mu = R.mu + (size_t)r * P;
+                    double tt = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        const double t = (qg[k] - R.ctr[(size_t)r * d + k]) * s;
+                        tt += t * t;
+                        hermite_polys(t, p, Hq + k * pmax);
+                    }
+                    if (tt <= 745.0) {  // else e^{-|t|^2} underflows: the expansion is 0
+                        double w = 0.0;
+                        for (int i = 0; i < P; ++i) {
+                            const int meta = mt[i];
+                            if ((meta >> 8) >= p) continue;
+                            const unsigned long long ad = dg[i];
+                            double prod = mu[i] * spow[meta & 255];
+                            for (int k = 0; k < d; ++k) prod *= Hq[k * pmax + dig_at(ad, k)];
+                            w += prod;
+                        }
+                        part = fma(exp(-tt), w, part);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        red[tid] = part;
+        __syncthreads();
+        if (tg == 0 && act) {
+            double gsum = 0.0;
+            for (int k = 0; k < ngr; ++k) gsum += red[k * slots + qi];
+            double gl = 0.0;
+            if (any) {
+                double y[kMaxD];
+                for (int k = 0; k < d; ++k) y[k] = (qg[k] - lc[k]) * s;
+                for (int i = 0; i < P; ++i) {
+                    const double a = acc[i];
+                    if (a == 0.0) continue;
+                    const unsigned long long ad = dg[i];
+                    double prod = a;
+                    for (int k = 0; k < d; ++k) prod *= powi(y[k], dig_at(ad, k));
+                    gl += prod;
+                }
+            }
+            jb.out[Q.perm[qpos]] = gl + gsum;
+        }
+        __syncthreads();
     }
 }
 
@@ -804,15 +1140,28 @@ struct Profiler {
 };
 thread_local Profiler g_prof;
 
-enum { K_TRAV = 0, K_BASE, K_FAR, K_LOCAL, K_POST };
+// kernel_ms slots of dfgt_stats
+enum { K_TRAV = 0, K_LEAF = 1, K_LOCAL = 3, K_POST = 4 };
 
 struct Workspace {
-    DevBuf jobs, trees, GE, GF, glE, L, lflag, segA, segB, pairA, pairB, dec, egrp, eops, fgrp, fops, lgrp, lops,
+    DevBuf jobs, trees, L, lflag, heads, segA, segB, pairA, pairB, dec, egrp, eops, fgrp, fops, lgrp, lops, lnodes,
         cnt, stats, lscr, pscr;
 };
 thread_local Workspace g_ws;
 
 template <class T> dfgt_status grow(DevBuf &b, size_t n) { return b.reserve(sizeof(T) * std::max<size_t>(n, 1)); }
+
+// Grows an append-only device array, keeping its first `used` elements.
+template <class T> dfgt_status grow_keep(DevBuf &b, size_t need, size_t used, hipStream_t st) {
+    if (sizeof(T) * need <= b.bytes) return DFGT_OK;
+    DevBuf nb;
+    DFGT_TRY(nb.reserve(sizeof(T) * std::max<size_t>(2 * need, 1024)));
+    if (used) DFGT_HIP(hipMemcpyAsync(nb.p, b.p, sizeof(T) * used, hipMemcpyDeviceToDevice, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    std::swap(b.p, nb.p);
+    std::swap(b.bytes, nb.bytes);
+    return DFGT_OK;
+}
 
 }  // namespace
 
@@ -822,12 +1171,13 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     Profiler &prof = g_prof;
     prof.begin_call(profile != 0);
     const DevTree &Qv = Qh->host_view;
-    const int NQ = (int)Qh->n, MQ = (int)Qh->m, P = Qh->P, pmax = Qh->pmax, d = Qh->d;
+    const int MQ = (int)Qh->m, P = Qh->P, pmax = Qh->pmax, d = Qh->d;
+    const int NQ = (int)Qh->n;
     const bool mono = Qh == Rh;
     // A tolerance below the mixed-precision rounding budget needs FP64 leaf sums.
     if (precision == DFGT_PREC_MIXED && eps > 0.0 && eps < 2e-5) precision = DFGT_PREC_FP64;
-    // Rounding budget of the exhaustive sums (Theorem of Section 3.10 assumes
-    // them exact): mixed precision <= 1e-5 relative, FP64 ~1e-13.
+    // Rounding budget of the exhaustive sums (the global-error theorem takes
+    // them as exact): mixed precision <= 1e-5 relative, FP64 ~1e-13.
     const double eps_round = precision == DFGT_PREC_FP64 ? 1e-12 : 1e-5;
     const double eps_eff = eps > 2.0 * eps_round ? eps - eps_round : 0.0;
 
@@ -840,6 +1190,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         j.sig = 1.2011224087864498 * j.s;  // sqrt(log2 e) s: e^{-x^2/2h^2} = 2^{-(sig x)^2}
         j.eps_eff = eps_eff;
         j.nR = (double)Rh->n;
+        j.prior = 0.0;
         j.qt = 0;
         j.rt = 1;
         j.qoff = (long long)k * NQ;
@@ -853,20 +1204,17 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     DFGT_TRY(grow<DevTree>(w.trees, 2));
     DFGT_HIP(hipMemcpyAsync(w.jobs.p, jobs.data(), sizeof(Job) * nh, hipMemcpyHostToDevice, st));
     DFGT_HIP(hipMemcpyAsync(w.trees.p, tv, sizeof(tv), hipMemcpyHostToDevice, st));
-    const size_t nqa = (size_t)nh * NQ, nna = (size_t)nh * MQ;
-    DFGT_TRY(grow<double>(w.GE, nqa));
-    DFGT_TRY(grow<double>(w.GF, nqa));
-    DFGT_TRY(grow<double>(w.glE, nna));
+    const size_t nna = (size_t)nh * MQ;
     DFGT_TRY(grow<double>(w.L, nna * P));
     DFGT_TRY(grow<unsigned char>(w.lflag, nna));
-    DFGT_TRY(grow<int>(w.cnt, C_N));
-    DFGT_TRY(grow<unsigned long long>(w.stats, S_N));
-    DFGT_HIP(hipMemsetAsync(w.GE.p, 0, sizeof(double) * nqa, st));
-    DFGT_HIP(hipMemsetAsync(w.GF.p, 0, sizeof(double) * nqa, st));
-    DFGT_HIP(hipMemsetAsync(w.glE.p, 0, sizeof(double) * nna, st));
-    DFGT_HIP(hipMemsetAsync(w.L.p, 0, sizeof(double) * nna * P, st));
+    DFGT_TRY(grow<int>(w.heads, 3 * nna));
+    DFGT_TRY(grow<int>(w.cnt, C_N * CP));
+    DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
     DFGT_HIP(hipMemsetAsync(w.lflag.p, 0, nna, st));
-    DFGT_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(unsigned long long) * S_N, st));
+    DFGT_HIP(hipMemsetAsync(w.heads.p, 0xff, sizeof(int) * 3 * nna, st));
+    DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * C_N * CP, st));
+    DFGT_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(unsigned long long) * S_N * SP, st));
+    int *headE = w.heads.as<int>(), *headF = headE + nna, *headL = headF + nna;
 
     // level 0: (Q_root, {R_root}) for every job
     int nseg = nh, npair = nh;
@@ -880,87 +1228,101 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         DFGT_HIP(hipMemcpyAsync(w.pairA.p, p0.data(), sizeof(int) * nh, hipMemcpyHostToDevice, st));
         DFGT_HIP(hipStreamSynchronize(st));
     }
-    const size_t lds_local = sizeof(double) * (3 * (size_t)P + pmax * pmax + 2 * pmax * d);
-    const bool local_lds = lds_local <= 60 * 1024;
-    const size_t lds_post = sizeof(double) * (2 * (size_t)P + pmax * pmax);
-    const bool post_lds = lds_post <= 60 * 1024;
     const DevTree *td = w.trees.as<DevTree>();
     const Job *jd = w.jobs.as<Job>();
+    // a query leaf's own local ops are applied inside k_leaf when its
+    // per-wave scratch fits; otherwise they go through the node kernels
+    const bool leaf_local = P <= 512;
     int levels = 0;
+    int c[C_N] = {0};
+    std::vector<int> craw((size_t)C_N * CP);
     DevBuf *segCur = &w.segA, *segNext = &w.segB, *pairCur = &w.pairA, *pairNext = &w.pairB;
     while (nseg > 0) {
         ++levels;
         DFGT_TRY(grow<Seg>(*segNext, 2 * (size_t)nseg));
         DFGT_TRY(grow<int>(*pairNext, 4 * (size_t)npair));
         DFGT_TRY(grow<int>(w.dec, npair));
-        DFGT_TRY(grow<Group>(w.egrp, nseg));
-        DFGT_TRY(grow<Group>(w.fgrp, nseg));
-        DFGT_TRY(grow<Group>(w.lgrp, nseg));
-        DFGT_TRY(grow<int>(w.eops, npair));
-        DFGT_TRY(grow<Op>(w.fops, npair));
-        DFGT_TRY(grow<Op>(w.lops, npair));
-        DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * C_N, st));
-        TravOut o{segNext->as<Seg>(),       pairNext->as<int>(), w.egrp.as<Group>(), w.eops.as<int>(),
-                  w.fgrp.as<Group>(),       w.fops.as<Op>(),     w.lgrp.as<Group>(), w.lops.as<Op>(),
-                  w.cnt.as<int>(),          w.stats.as<unsigned long long>()};
+        DFGT_TRY(grow_keep<Group>(w.egrp, (size_t)c[C_EGRP] + nseg, c[C_EGRP], st));
+        DFGT_TRY(grow_keep<Group>(w.fgrp, (size_t)c[C_FGRP] + nseg, c[C_FGRP], st));
+        DFGT_TRY(grow_keep<Group>(w.lgrp, (size_t)c[C_LGRP] + nseg, c[C_LGRP], st));
+        DFGT_TRY(grow_keep<int>(w.lnodes, 2 * ((size_t)c[C_LNODE] + nseg), 2 * (size_t)c[C_LNODE], st));
+        DFGT_TRY(grow_keep<int>(w.eops, (size_t)c[C_EOP] + npair, c[C_EOP], st));
+        DFGT_TRY(grow_keep<Op>(w.fops, (size_t)c[C_FOP] + npair, c[C_FOP], st));
+        DFGT_TRY(grow_keep<Op>(w.lops, (size_t)c[C_LOP] + npair, c[C_LOP], st));
+        DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * 2 * CP, st));  // per-level counters
+        TravOut o{segNext->as<Seg>(), pairNext->as<int>(), w.egrp.as<Group>(), w.eops.as<int>(),
+                  w.fgrp.as<Group>(), w.fops.as<Op>(),     w.lgrp.as<Group>(), w.lops.as<Op>(),
+                  w.lnodes.as<int>(), headE,               headF,              headL,
+                  w.cnt.as<int>(),    w.stats.as<unsigned long long>()};
         hipEvent_t ev = prof.start(st);
         hipLaunchKernelGGL(k_traverse, dim3(nseg), dim3(64), 0, st, td, jd, segCur->as<Seg>(), pairCur->as<int>(),
-                           w.glE.as<double>(), force, w.dec.as<int>(), o);
+                           force, leaf_local ? 1 : 0, w.dec.as<int>(), o);
         DFGT_HIP(hipGetLastError());
         prof.stop(K_TRAV, ev, st);
-        int c[C_N];
-        DFGT_HIP(hipMemcpyAsync(c, w.cnt.p, sizeof(int) * C_N, hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipMemcpyAsync(craw.data(), w.cnt.p, sizeof(int) * C_N * CP, hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
-        if (c[C_EGRP]) {
-            ev = prof.start(st);
-            hipLaunchKernelGGL(k_base, dim3(c[C_EGRP]), dim3(kBaseBlock), 0, st, td, jd, w.egrp.as<Group>(),
-                               w.eops.as<int>(), precision, w.GE.as<double>(), w.glE.as<double>(),
-                               w.stats.as<unsigned long long>());
-            prof.stop(K_BASE, ev, st);
-        }
-        if (c[C_FGRP]) {
-            ev = prof.start(st);
-            hipLaunchKernelGGL(k_far, dim3(c[C_FGRP]), dim3(256), 0, st, td, jd, w.fgrp.as<Group>(),
-                               w.fops.as<Op>(), w.GF.as<double>());
-            prof.stop(K_FAR, ev, st);
-        }
-        if (c[C_LGRP]) {
-            ev = prof.start(st);
-            double *scr = nullptr;
-            if (!local_lds) {
-                DFGT_TRY(grow<double>(w.lscr, (size_t)c[C_LGRP] * 3 * P));
-                scr = w.lscr.as<double>();
-            }
-            const size_t sh = local_lds ? lds_local : sizeof(double) * (pmax * pmax + 2 * pmax * d);
-            hipLaunchKernelGGL(k_local, dim3(c[C_LGRP]), dim3(kLocBlock), sh, st, td, jd, w.lgrp.as<Group>(),
-                               w.lops.as<Op>(), local_lds ? 1 : 0, scr, w.L.as<double>(),
-                               w.lflag.as<unsigned char>());
-            prof.stop(K_LOCAL, ev, st);
-        }
-        DFGT_HIP(hipGetLastError());
+        for (int k = 0; k < C_N; ++k) c[k] = craw[(size_t)k * CP];
         nseg = c[C_SEG];
         npair = c[C_PAIR];
         std::swap(segCur, segNext);
         std::swap(pairCur, pairNext);
     }
+    // local moments of every node with D / T ops
+    if (c[C_LNODE]) {
+        hipEvent_t ev = prof.start(st);
+        if (P <= 512) {
+            const size_t sh = sizeof(double) * (2 * (size_t)P + 256 + 4 * (2 * (size_t)P + 2 * (size_t)d * pmax +
+                                                                        64 * (size_t)d * pmax)) +
+                              (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
+            hipLaunchKernelGGL(k_local, dim3(c[C_LNODE]), dim3(256), sh, st, td, jd, w.lnodes.as<int>(), headL,
+                               w.lgrp.as<Group>(), w.lops.as<Op>(), w.L.as<double>(), w.lflag.as<unsigned char>(),
+                               w.stats.as<unsigned long long>());
+        } else {
+            DFGT_TRY(grow<double>(w.lscr, (size_t)c[C_LNODE] * 3 * P));
+            const size_t sh = sizeof(double) * ((size_t)pmax * pmax + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax);
+            hipLaunchKernelGGL(k_local_big, dim3(c[C_LNODE]), dim3(kLocBlock), sh, st, td, jd, w.lnodes.as<int>(),
+                               headL, w.lgrp.as<Group>(), w.lops.as<Op>(), w.lscr.as<double>(), w.L.as<double>(),
+                               w.lflag.as<unsigned char>());
+        }
+        DFGT_HIP(hipGetLastError());
+        prof.stop(K_LOCAL, ev, st);
+    }
+    // everything per query leaf
     {
+        int nthr = 256;
+        while (nthr > 64 && sizeof(double) * (size_t)nthr * d * (pmax + 1) > 40 * 1024) nthr >>= 1;
+        const int nwl = leaf_local ? nthr / 64 : 0;
+        const size_t base = sizeof(double) * ((size_t)nthr + d * (pmax - 1) + 1 + (size_t)nthr * d * pmax +
+                                              (size_t)nthr * d + (leaf_local ? P : 0) + 2 * (size_t)nwl * P +
+                                              (size_t)nwl * 2 * d * pmax);
+        const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
+        const size_t lds_acc = sizeof(double) * (2 * (size_t)P + (size_t)pmax * pmax);
+        const bool acc_lds = base + lds_acc + lds_dig <= 64 * 1024;
         double *scr = nullptr;
-        if (!post_lds) {
+        if (!acc_lds) {
             DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 2 * P));
             scr = w.pscr.as<double>();
         }
-        const size_t sh = post_lds ? lds_post : sizeof(double) * pmax * pmax;
+        const size_t sh = base + (acc_lds ? lds_acc : sizeof(double) * (size_t)pmax * pmax) + lds_dig;
+        if (sh > 64 * 1024) {
+            set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
+            return DFGT_EINVAL;
+        }
         hipEvent_t ev = prof.start(st);
-        hipLaunchKernelGGL(k_post, dim3(Qv.nleaves, nh), dim3(256), sh, st, td, jd, Qv.nleaves, w.L.as<double>(),
-                           w.lflag.as<unsigned char>(), w.GE.as<double>(), w.GF.as<double>(), post_lds ? 1 : 0,
-                           scr);
+        hipLaunchKernelGGL(k_leaf, dim3(Qv.nleaves, nh), dim3(nthr), sh, st, td, jd, w.egrp.as<Group>(),
+                           w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
+                           w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
+                           precision, acc_lds ? 1 : 0, leaf_local ? 1 : 0, scr);
         DFGT_HIP(hipGetLastError());
-        prof.stop(K_POST, ev, st);
+        prof.stop(K_LEAF, ev, st);
     }
     if (stats_out) {
-        unsigned long long sv[S_N];
-        DFGT_HIP(hipMemcpyAsync(sv, w.stats.p, sizeof(sv), hipMemcpyDeviceToHost, st));
+        std::vector<unsigned long long> sraw((size_t)S_N * SP);
+        DFGT_HIP(hipMemcpyAsync(sraw.data(), w.stats.p, sizeof(unsigned long long) * S_N * SP,
+                                hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
+        unsigned long long sv[S_N];
+        for (int k = 0; k < S_N; ++k) sv[k] = sraw[(size_t)k * SP];
         std::memset(stats_out, 0, sizeof(*stats_out));
         stats_out->node_pairs = (int64_t)sv[S_PAIRS];
         stats_out->prune_f = (int64_t)sv[S_F];
@@ -972,6 +1334,10 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         stats_out->levels = levels;
         stats_out->max_order = (int64_t)sv[S_MAXORD];
         stats_out->fp64_groups = (int64_t)sv[S_FP64];
+        stats_out->segments = (int64_t)sv[S_SEGS];
+        stats_out->max_segment = (int64_t)sv[S_MAXSEG];
+        stats_out->local_nodes = c[C_LNODE];
+        stats_out->max_local_ops = (int64_t)sv[S_MAXLOPS];
         if (prof.on) prof.collect(stats_out);
     }
     return DFGT_OK;

@@ -63,6 +63,30 @@ __device__ __forceinline__ void hermite_polys(double t, int n, double *H) {
     for (int m = 1; m + 1 < n; ++m) H[m + 1] = 2.0 * t * H[m] - 2.0 * m * H[m - 1];
 }
 
+// Digit tables for coefficient positions i < P (radix pmax <= 16, so a digit
+// fits 4 bits and a position with any non-zero digit has d <= 13):
+//   dg[i] = digits packed 4 bits per axis (axis k at bits 4k),
+//   mt[i] = |alpha| | (max digit << 8).
+__device__ __forceinline__ void build_digit_tables(unsigned long long *dg, unsigned short *mt, int P, int d,
+                                                   int pmax) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        int rem = i, sum = 0, mx = 0;
+        unsigned long long packed = 0;
+        for (int k = d - 1; k >= 0; --k) {
+            const int a = rem % pmax;
+            rem /= pmax;
+            if (a) packed |= (unsigned long long)a << (4 * k);
+            sum += a;
+            mx = a > mx ? a : mx;
+        }
+        dg[i] = packed;
+        mt[i] = (unsigned short)(sum | (mx << 8));
+    }
+}
+__device__ __forceinline__ int dig_at(unsigned long long packed, int k) {
+    return k < 16 ? (int)((packed >> (4 * k)) & 15) : 0;  // k >= 16 only occurs with p_max = 1
+}
+
 __device__ __forceinline__ double inv_factorial(int n) {
     double f = 1.0;
     for (int i = 2; i <= n; ++i) f *= (double)i;

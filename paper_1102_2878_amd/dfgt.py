@@ -32,10 +32,11 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(nm, C.c_int64) for nm in (
         "node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid", "base_leaf_pairs",
-        "base_point_pairs", "levels", "max_order", "fp64_groups")] + [("reserved", C.c_int64 * 6),
+        "base_point_pairs", "levels", "max_order", "fp64_groups", "segments", "max_segment", "local_nodes",
+        "max_local_ops")] + [("reserved", C.c_int64 * 2),
                                                                        ("kernel_ms", C.c_double * 5),
                                                                        ("kernel_launches", C.c_int64 * 5)]
-    KERNELS = ("traverse", "base", "far", "local", "post")
+    KERNELS = ("traverse", "leaf", "unused2", "local", "unused4")
 
     def as_dict(self):
         d = {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm not in ("reserved", "kernel_ms",
