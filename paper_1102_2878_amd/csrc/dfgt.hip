@@ -77,9 +77,9 @@ struct Op {
 constexpr int CP = 32;  // ints per counter line
 constexpr int SP = 16;  // u64 per statistics line
 enum {
-    C_SEG = 0,
+    C_SEG = 0,  // per level: segments and pairs of the next level
     C_PAIR,
-    C_EGRP,
+    C_EGRP,     // cumulative over the call
     C_EOP,
     C_FGRP,
     C_FOP,
@@ -87,6 +87,12 @@ enum {
     C_LOP,
     C_LNODE,
     C_N
+};
+
+// Capacities of the traversal's output arrays.  Reservations beyond them set
+// the overflow flag and write nothing; the host then grows and reruns.
+struct Caps {
+    int seg, pair, eop, fop, lop, grp, lnode;
 };
 
 enum {
@@ -251,8 +257,11 @@ struct TravOut {
     Op *lops;
     int *lnodes;  // (q, job) pairs with local ops, 2 ints each
     int *headE, *headF, *headL;
-    int *cnt;
+    int *cnt;       // cumulative counters
+    int *lvl_next;  // per-level counters written by this level
+    int *overflow;
     unsigned long long *stats;
+    Caps cap;
 };
 
 __device__ __forceinline__ int wave_excl(int v, int *total) {
@@ -264,11 +273,10 @@ __device__ __forceinline__ int wave_excl(int v, int *total) {
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // One wave per segment.
-__global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                                 const Seg *__restrict__ segs, const int *__restrict__ pairs,
-                                                 int force, int leaf_local, int *dec, TravOut o) {
+__device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Seg sg,
+                                 const int *__restrict__ pairs, int force, int leaf_local, int *dec,
+                                 const TravOut &o) {
     const int lane = threadIdx.x;
-    const Seg sg = segs[blockIdx.x];
     const Job jb = jobs[sg.job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
@@ -303,7 +311,8 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
             plo += nR * ku;
             if (m == METH_F) ++cF;
             else {
-                ++cL;
+                // a D op is emitted as one op per chunk of <= 64 reference points
+                cL += m == METH_D ? (int)((nR + 63.0) / 64.0) : 1;
                 if (m == METH_D) ++nD;
                 else if (ord == 1) ++nC;
                 else ++nT;
@@ -330,41 +339,64 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
     for (int off = 32; off >= 1; off >>= 1) mo = max(mo, __shfl_xor(mo, off, 64));
 
     // reserve contiguous output ranges and link the new groups into their chains
-    int ebase = 0, fbase = 0, lbase = 0, cbase = 0, sgi = 0;
+    int ebase = 0, fbase = 0, lbase = 0, cbase = 0, sgi = 0, okmask = 0;
     const int npair_out = qleaf ? tN : 2 * tN;
     const int nseg_out = tN > 0 ? (qleaf ? 1 : 2) : 0;
     const size_t hq = (size_t)jb.noff + q;
     if (lane == 0) {
+        bool over = false;
         if (tE) {
             ebase = atomicAdd(&o.cnt[C_EOP * CP], tE);
             const int gi = atomicAdd(&o.cnt[C_EGRP * CP], 1);
-            // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
-            // absolute error below 2^-26 G by computing tiny sums in FP64.
-            const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
-            const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
-            o.egrp[gi] = Group{q, sg.job, ebase, tE, fp64, atomicExch(&o.headE[hq], gi)};
-            if (fp64) atomicAdd(&o.stats[S_FP64 * SP], 1ull);
+            if (ebase + tE <= o.cap.eop && gi < o.cap.grp) {
+                // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
+                // absolute error below 2^-26 G by computing tiny sums in FP64.
+                const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
+                const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
+                o.egrp[gi] = Group{q, sg.job, ebase, tE, fp64, atomicExch(&o.headE[hq], gi)};
+                if (fp64) atomicAdd(&o.stats[S_FP64 * SP], 1ull);
+                okmask |= 1;
+            } else {
+                over = true;
+            }
         }
         if (tF) {
             fbase = atomicAdd(&o.cnt[C_FOP * CP], tF);
             const int gi = atomicAdd(&o.cnt[C_FGRP * CP], 1);
-            o.fgrp[gi] = Group{q, sg.job, fbase, tF, 0, atomicExch(&o.headF[hq], gi)};
+            if (fbase + tF <= o.cap.fop && gi < o.cap.grp) {
+                o.fgrp[gi] = Group{q, sg.job, fbase, tF, 0, atomicExch(&o.headF[hq], gi)};
+                okmask |= 2;
+            } else {
+                over = true;
+            }
         }
         if (tL) {
             lbase = atomicAdd(&o.cnt[C_LOP * CP], tL);
             const int gi = atomicAdd(&o.cnt[C_LGRP * CP], 1);
-            const int prev = atomicExch(&o.headL[hq], gi);
-            o.lgrp[gi] = Group{q, sg.job, lbase, tL, 0, prev};
-            if (prev < 0 && !(qleaf && leaf_local)) {  // a leaf's own local ops may run in k_leaf
-                const int li = atomicAdd(&o.cnt[C_LNODE * CP], 1);
-                o.lnodes[2 * li] = q;
-                o.lnodes[2 * li + 1] = sg.job;
+            if (lbase + tL <= o.cap.lop && gi < o.cap.grp) {
+                const int prev = atomicExch(&o.headL[hq], gi);
+                o.lgrp[gi] = Group{q, sg.job, lbase, tL, 0, prev};
+                okmask |= 4;
+                if (prev < 0 && !(qleaf && leaf_local)) {  // a leaf's own local ops may run in k_leaf
+                    const int li = atomicAdd(&o.cnt[C_LNODE * CP], 1);
+                    if (li < o.cap.lnode) {
+                        o.lnodes[2 * li] = q;
+                        o.lnodes[2 * li + 1] = sg.job;
+                    } else {
+                        over = true;
+                    }
+                }
+            } else {
+                over = true;
             }
         }
         if (npair_out) {
-            cbase = atomicAdd(&o.cnt[C_PAIR * CP], npair_out);
-            sgi = atomicAdd(&o.cnt[C_SEG * CP], nseg_out);
+            cbase = atomicAdd(&o.lvl_next[C_PAIR * CP], npair_out);
+            sgi = atomicAdd(&o.lvl_next[C_SEG * CP], nseg_out);
+            if (cbase + npair_out <= o.cap.pair && sgi + nseg_out <= o.cap.seg) okmask |= 8;
+            else over = true;
         }
+        if (over) atomicExch(o.overflow, 1);
         atomicAdd(&o.stats[S_PAIRS * SP], (unsigned long long)sg.count);
         atomicAdd(&o.stats[S_SEGS * SP], 1ull);
         atomicMax(&o.stats[S_MAXSEG * SP], (unsigned long long)sg.count);
@@ -382,6 +414,8 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
     fbase = __shfl(fbase, 0, 64);
     lbase = __shfl(lbase, 0, 64);
     cbase = __shfl(cbase, 0, 64);
+    okmask = __shfl(okmask, 0, 64);
+    const bool okE = okmask & 1, okF = okmask & 2, okL = okmask & 4, okN = okmask & 8;
 
     // 3. write outputs in pair order
     int eo = 0, fo = 0, lo = 0, no = 0;
@@ -397,16 +431,17 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
             ord = v >> 4;
             rleaf = R.left[r] < 0;
             if (m == METH_F) f = 1;
-            else if (m != METH_E) l = 1;
+            else if (m != METH_E) l = m == METH_D ? (R.end[r] - R.begin[r] + 63) / 64 : 1;
             else if (qleaf && rleaf) e = 1;
             else n = (qleaf || !rleaf) ? 2 : 1;
         }
         int te, tf, tl, tn;
         const int xe = wave_excl(e, &te), xf = wave_excl(f, &tf), xl = wave_excl(l, &tl), xn = wave_excl(n, &tn);
-        if (e) o.eops[ebase + eo + xe] = r;
-        if (f) o.fops[fbase + fo + xf] = Op{r, ord | (METH_F << 8)};
-        if (l) o.lops[lbase + lo + xl] = Op{r, ord | (m << 8)};
-        if (n) {
+        if (e && okE) o.eops[ebase + eo + xe] = r;
+        if (f && okF) o.fops[fbase + fo + xf] = Op{r, ord | (METH_F << 8)};
+        if (okL)
+            for (int ch = 0; ch < l; ++ch) o.lops[lbase + lo + xl + ch] = Op{r, ord | (m << 8) | (ch << 12)};
+        if (n && okN) {
             const int p0 = cbase + no + xn;
             if (qleaf) {
                 o.npairs[p0] = R.left[r];
@@ -426,10 +461,22 @@ __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ tre
         lo += tl;
         no += tn;
     }
-    if (lane == 0 && tN) {
+    if (lane == 0 && tN && okN) {
         o.nsegs[sgi] = Seg{QL, sg.job, cbase, tN, gl_child};
         if (!qleaf) o.nsegs[sgi + 1] = Seg{QR, sg.job, cbase + tN, tN, gl_child};
     }
+}
+
+// One level of the traversal; the segment count comes from the previous
+// level's counters (or nseg0 at level 0), so no host round trip is needed.
+__global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                                 const Seg *__restrict__ segs, const int *__restrict__ pairs,
+                                                 const int *__restrict__ lvl_in, int nseg0, int force,
+                                                 int leaf_local, int *dec, TravOut o) {
+    if (*o.overflow) return;
+    const int nseg = lvl_in ? min(lvl_in[C_SEG * CP], o.cap.seg) : nseg0;
+    for (int si = blockIdx.x; si < nseg; si += gridDim.x)
+        traverse_segment(trees, jobs, segs[si], pairs, force, leaf_local, dec, o);
 }
 
 // ---------------------------------------------------------------- local moments: D and T ops
@@ -457,11 +504,12 @@ __device__ __forceinline__ double coef_beta(int i, int d, int pmax) {
     return (bs & 1) ? -f : f;
 }
 
-// One D or T op applied by one wave to the local moments acc[P] about qc.
+// One D or T op applied by one wave to the local moments acc[P] about qc; a D
+// op covers reference points [rb, re) of node r.
 // Wave-private scratch: Ms[P] | Ht[D][2 pmax] | Hx[64][D][pmax].
-__device__ void wave_local_op(const DevTree &R, int r, int p, int m, const double *qc, double s, int d, int pmax,
-                              int P, const unsigned long long *dg, const unsigned short *mt, const double *cb,
-                              double *acc, double *Ms, double *Ht, double *Hx, int lane) {
+__device__ void wave_local_op(const DevTree &R, int r, int p, int m, int rb, int re, const double *qc, double s,
+                              int d, int pmax, int P, const unsigned long long *dg, const unsigned short *mt,
+                              const double *cb, double *acc, double *Ms, double *Ht, double *Hx, int lane) {
     if (m == METH_T) {
         double tt = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -497,7 +545,6 @@ __device__ void wave_local_op(const DevTree &R, int r, int p, int m, const doubl
         wave_sync();
         return;
     }
-    const int rb = R.begin[r], re = R.end[r];
     for (int x0 = rb; x0 < re; x0 += 64) {
         const int cnt = min(64, re - x0);
         if (lane < cnt) {
@@ -530,114 +577,113 @@ __device__ void wave_local_op(const DevTree &R, int r, int p, int m, const doubl
 
 constexpr int kMaxSeg = 256;
 
-// Applies every local op of the chain starting at group `head` to acc[P]
-// (block-wide, all threads must call it).  Centroid ops (T at order 1:
-// L_0 += |R| e^{-|t0|^2}) are taken by all threads in parallel, op i by
-// thread i mod nthr, and reduced in thread order; the other ops are dealt to
-// the waves round-robin in chain order, each wave accumulating into its own
-// partial vector; partials are added in wave order.  Chains are flattened in
-// batches of kMaxSeg groups into the segment table segS / segE (cumulative op
-// counts) by thread 0.
-// Scratch: red[nthr] | wacc[nwv][P] | wMs[nwv][P] | wHt[nwv][2 D pmax] | wHx[nwv][64][D][pmax]
-__device__ void block_local_ops(int head, const Group *__restrict__ grp, const Op *__restrict__ lops,
-                                const DevTree &R, const double *qc, double s, int d, int pmax, int P,
-                                const unsigned long long *dg, const unsigned short *mt, const double *cb, double *acc,
-                                double *red, double *wacc, double *wMs, double *wHt, double *wHx, int *segS,
-                                int *segE, int *state) {
-    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
-    double *wa = wacc + (size_t)wv * P;
-    for (int i = lane; i < P; i += 64) wa[i] = 0.0;
-    double csum = 0.0;
-    if (tid == 0) state[0] = head;
+// Local ops run fully in parallel: one wave per op (a D op is one chunk of
+// <= 64 reference points), each writing its contribution to Q's local
+// moments into its own row of `part`; per-node sums then add the rows in
+// chain order.  An order-1 T op (the centroid form) only has a zeroth term.
+// LDS per block: cb[P] | dg[P] (u64) | mt[P] (u16) | per wave: acc[P] | Ms[P] | Ht[2 D pmax] | Hx[64][D][pmax]
+__global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                              const Group *__restrict__ lgrp, const Op *__restrict__ lops,
+                                              const int *__restrict__ lop_node, const int *__restrict__ cnt,
+                                              const int *__restrict__ overflow, double *__restrict__ part) {
+    extern __shared__ double smem[];
+    if (*overflow) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+    const DevTree &Q0 = trees[jobs[0].qt];
+    const int d = Q0.d, pmax = Q0.pmax, P = Q0.P;
+    double *cb = smem;
+    unsigned long long *dg = reinterpret_cast<unsigned long long *>(cb + P);
+    unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
+    const size_t wstride = 2 * (size_t)P + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax;
+    double *wbase = cb + P + (10 * (size_t)P + 7) / 8 + (size_t)wv * wstride;
+    double *acc = wbase, *Ms = acc + P, *Ht = Ms + P, *Hx = Ht + 2 * d * pmax;
+    build_digit_tables(dg, mt, P, d, pmax);
+    for (int i = tid; i < P; i += blockDim.x) cb[i] = coef_beta(i, d, pmax);
     __syncthreads();
-    while (true) {
-        if (tid == 0) {
-            int n = 0, tot = 0, gi = state[0];
-            while (gi >= 0 && n < kMaxSeg) {
-                const Group g = grp[gi];
-                segS[n] = g.start;
-                tot += g.count;
-                segE[n++] = tot;
-                gi = g.next;
+    const int nops = min(cnt[C_LOP * CP], 0x7fffffff);
+    for (int oi = blockIdx.x * nwv + wv; oi < nops; oi += gridDim.x * nwv) {
+        const Op op = lops[oi];
+        const Group g = lgrp[lop_node[oi]];
+        const Job jb = jobs[g.job];
+        const DevTree &Q = trees[jb.qt];
+        const DevTree &R = trees[jb.rt];
+        const int r = op.r, p = op.meta & 255, m = (op.meta >> 8) & 15, ch = op.meta >> 12;
+        double *dst = part + (size_t)oi * P;
+        const double *qc = Q.ctr + (size_t)g.q * d;
+        if (m == METH_T && p == 1) {
+            if (lane == 0) {
+                double tt = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * jb.s;
+                    tt += t * t;
+                }
+                dst[0] = tt > 745.0 ? 0.0 : R.mu[(size_t)r * P] * exp(-tt);
             }
-            state[0] = gi;
-            state[1] = n;
-            state[2] = tot;
+            continue;
         }
-        __syncthreads();
-        const int nseg = state[1], nops = state[2];
-        if (nseg == 0) break;
-        int sp = 0;
-        for (int idx = tid; idx < nops; idx += nthr) {
-            while (idx >= segE[sp]) ++sp;
-            const Op op = lops[segS[sp] + idx - (sp ? segE[sp - 1] : 0)];
-            if ((op.meta >> 8) != METH_T || (op.meta & 255) != 1) continue;
-            double tt = 0.0;
-            for (int k = 0; k < d; ++k) {
-                const double t = (qc[k] - R.ctr[(size_t)op.r * d + k]) * s;
-                tt += t * t;
-            }
-            if (tt <= 745.0) csum = fma(R.mu[(size_t)op.r * P], exp(-tt), csum);
-        }
-        sp = 0;
-        for (int idx = wv; idx < nops; idx += nwv) {
-            while (idx >= segE[sp]) ++sp;
-            const Op op = lops[segS[sp] + idx - (sp ? segE[sp - 1] : 0)];
-            const int m = op.meta >> 8, p = op.meta & 255;
-            if (m == METH_T && p == 1) continue;
-            wave_local_op(R, op.r, p, m, qc, s, d, pmax, P, dg, mt, cb, wa, wMs + (size_t)wv * P,
-                          wHt + (size_t)wv * 2 * d * pmax, wHx + (size_t)wv * 64 * d * pmax, lane);
-        }
-        __syncthreads();
+        for (int i = lane; i < P; i += 64) acc[i] = 0.0;
+        wave_sync();
+        const int rb = R.begin[r] + 64 * ch, re = min(R.end[r], rb + 64);
+        wave_local_op(R, r, p, m, rb, re, qc, jb.s, d, pmax, P, dg, mt, cb, acc, Ms, Ht, Hx, lane);
+        wave_sync();
+        for (int i = lane; i < P; i += 64) dst[i] = acc[i];
+        wave_sync();
     }
-    red[tid] = csum;
-    __syncthreads();
-    for (int i = tid; i < P; i += nthr) {
-        double v = acc[i];
-        for (int w = 0; w < nwv; ++w) v += wacc[(size_t)w * P + i];
-        if (i == 0)
-            for (int t = 0; t < nthr; ++t) v += red[t];
-        acc[i] = v;
-    }
-    __syncthreads();
 }
 
-// One block per internal (Q, job) with local ops.
-// LDS: acc[P] | cb[P] | red[nthr] | wacc[nwv][P] | wMs[nwv][P] | wHt[nwv][2 D pmax] | wHx[nwv][64][D][pmax]
-//      | dg[P] (u64) | mt[P] (u16)
-__global__ __launch_bounds__(256) void k_local(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                               const int *__restrict__ lnodes, const int *__restrict__ headL,
-                                               const Group *__restrict__ grp, const Op *__restrict__ lops, double *L,
-                                               unsigned char *lflag, unsigned long long *stats) {
+// Adds the op rows of one node's chain in chain order: acc += part[op] (the
+// zeroth term only for order-1 T ops).  Threads over coefficients.
+__device__ __forceinline__ void sum_chain_parts(int head, const Group *__restrict__ lgrp, const Op *__restrict__ lops,
+                                                const double *__restrict__ part, int P, double *acc) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        double v = acc[i];
+        for (int gi = head; gi >= 0; gi = lgrp[gi].next) {
+            const Group g = lgrp[gi];
+            for (int o = g.start; o < g.start + g.count; ++o) {
+                const int meta = lops[o].meta;
+                if (((meta >> 8) & 15) == METH_T && (meta & 255) == 1) {
+                    if (i == 0) v += part[(size_t)o * P];
+                } else {
+                    v += part[(size_t)o * P + i];
+                }
+            }
+        }
+        acc[i] = v;
+    }
+}
+
+// One wave per internal (Q, job) with local ops.
+__global__ __launch_bounds__(64) void k_lreduce(const Job *__restrict__ jobs, const DevTree *__restrict__ trees,
+                                                const int *__restrict__ lnodes, const int *__restrict__ cnt,
+                                                const int *__restrict__ overflow, const int *__restrict__ headL,
+                                                const Group *__restrict__ lgrp, const Op *__restrict__ lops,
+                                                const double *__restrict__ part, double *L, unsigned char *lflag) {
     extern __shared__ double smem[];
-    __shared__ int segS[kMaxSeg], segE[kMaxSeg], state[3];
-    const int tid = threadIdx.x, nthr = blockDim.x, nwv = nthr >> 6;
-    const int q = lnodes[2 * blockIdx.x], job = lnodes[2 * blockIdx.x + 1];
-    const Job jb = jobs[job];
-    const DevTree &Q = trees[jb.qt];
-    const DevTree &R = trees[jb.rt];
-    const int d = Q.d, pmax = Q.pmax, P = Q.P;
-    double *acc = smem, *cb = acc + P, *red = cb + P, *wacc = red + nthr, *wMs = wacc + (size_t)nwv * P;
-    double *wHt = wMs + (size_t)nwv * P, *wHx = wHt + (size_t)nwv * 2 * d * pmax;
-    unsigned long long *dg = reinterpret_cast<unsigned long long *>(wHx + (size_t)nwv * 64 * d * pmax);
-    unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
-    build_digit_tables(dg, mt, P, d, pmax);
-    for (int i = tid; i < P; i += nthr) {
-        acc[i] = 0.0;
-        cb[i] = coef_beta(i, d, pmax);  // (-1)^|beta| / beta!
+    if (*overflow) return;
+    const int nl = cnt[C_LNODE * CP];
+    const int P = trees[jobs[0].qt].P;
+    for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+        const int q = lnodes[2 * li], job = lnodes[2 * li + 1];
+        const size_t hq = (size_t)jobs[job].noff + q;
+        wave_sync();
+        for (int i = threadIdx.x; i < P; i += blockDim.x) smem[i] = 0.0;
+        wave_sync();
+        sum_chain_parts(headL[hq], lgrp, lops, part, P, smem);
+        wave_sync();
+        for (int i = threadIdx.x; i < P; i += blockDim.x) L[hq * P + i] = smem[i];
+        if (threadIdx.x == 0) lflag[hq] = 1;
     }
-    const size_t hq = (size_t)jb.noff + q;
-    if (tid == 0) {
-        int n = 0;
-        for (int gi = headL[hq]; gi >= 0; gi = grp[gi].next) n += grp[gi].count;
-        atomicMax(&stats[S_MAXLOPS * SP], (unsigned long long)n);
+}
+
+// Marks, for every local op, the group it belongs to (k_lops needs the node).
+__global__ void k_lop_owner(const Group *__restrict__ lgrp, const int *__restrict__ cnt,
+                            const int *__restrict__ overflow, int *lop_node) {
+    if (*overflow) return;
+    const int ng = cnt[C_LGRP * CP];
+    for (int gi = blockIdx.x; gi < ng; gi += gridDim.x) {
+        const Group g = lgrp[gi];
+        for (int o = threadIdx.x; o < g.count; o += blockDim.x) lop_node[g.start + o] = gi;
     }
-    __syncthreads();
-    block_local_ops(headL[hq], grp, lops, R, Q.ctr + (size_t)q * d, jb.s, d, pmax, P, dg, mt, cb, acc, red, wacc,
-                    wMs, wHt, wHx, segS, segE, state);
-    double *Lq = L + hq * P;
-    for (int i = tid; i < P; i += nthr) Lq[i] = acc[i];
-    if (tid == 0) lflag[hq] = 1;
 }
 
 // Large coefficient vectors (P > 1024): T through D one-dimensional mode
@@ -647,17 +693,22 @@ constexpr int kLocBlock = 256;
 
 __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restrict__ trees,
                                                          const Job *__restrict__ jobs, const int *__restrict__ lnodes,
+                                                         const int *__restrict__ cnt, const int *__restrict__ overflow,
                                                          const int *__restrict__ headL, const Group *__restrict__ grp,
                                                          const Op *__restrict__ lops, double *__restrict__ gscratch,
                                                          double *L, unsigned char *lflag) {
     extern __shared__ double smem[];
-    const int q = lnodes[2 * blockIdx.x], job = lnodes[2 * blockIdx.x + 1];
+    if (*overflow) return;
+    const int nl = cnt[C_LNODE * CP];
+    for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+    __syncthreads();
+    const int q = lnodes[2 * li], job = lnodes[2 * li + 1];
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
     const int d = Q.d, pmax = Q.pmax, P = Q.P;
     const double s = jb.s;
-    double *acc = gscratch + (size_t)blockIdx.x * 3 * P, *buf0 = acc + P, *buf1 = buf0 + P;
+    double *acc = gscratch + (size_t)blockIdx.x * 3 * P, *buf0 = acc + P, *buf1 = buf0 + P;  // one slice per block
     double *coef = smem, *Ht = coef + pmax * pmax, *Hx = Ht + 2 * d * pmax;
     const double *qc = Q.ctr + (size_t)q * d;
     for (int i = threadIdx.x; i < P; i += blockDim.x) acc[i] = 0.0;
@@ -666,7 +717,7 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
         const Group g = grp[gi];
         for (int o = 0; o < g.count; ++o) {
             const Op op = lops[g.start + o];
-            const int r = op.r, p = op.meta & 255, m = op.meta >> 8;
+            const int r = op.r, p = op.meta & 255, m = (op.meta >> 8) & 15, ch = op.meta >> 12;
             if (m == METH_T) {
                 double tt = 0.0;
                 for (int k = 0; k < d; ++k) {
@@ -709,7 +760,7 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
                 }
                 __syncthreads();
             } else {
-                const int rb = R.begin[r], re = R.end[r];
+                const int rb = R.begin[r] + 64 * ch, re = min(R.end[r], rb + 64);
                 for (int x0 = rb; x0 < re; x0 += 64) {
                     const int cnt = min(64, re - x0);
                     if (threadIdx.x < cnt) {
@@ -750,6 +801,7 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
     double *Lq = L + ((size_t)jb.noff + q) * P;
     for (int i = threadIdx.x; i < P; i += blockDim.x) Lq[i] = acc[i];
     if (threadIdx.x == 0) lflag[jb.noff + q] = 1;
+    }
 }
 
 // ---------------------------------------------------------------- per query leaf
@@ -757,8 +809,7 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
 //   1. TransLocalToLocal from the root down the path to the leaf (each step
 //      one axis at a time: child L_a += sum_{b >= a} C(b, a) L_b X^{b-a},
 //      X = (child.c - parent.c) s), adding every path node's own moments;
-//      then the leaf's own D / T ops, dealt to the block's waves round-robin
-//      (wave partials added in wave order).
+//      then the leaf's own D / T ops from their partial rows (chain order).
 //   2. Threads form ngr groups of `slots` lanes, one lane per query.  Thread 0
 //      flattens the leaf's E chain and the F chains of all path nodes into a
 //      segment table; ops are then processed in rounds, op = round * ngr +
@@ -843,11 +894,13 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const int *__restrict__ headE, const int *__restrict__ headF,
                                               const int *__restrict__ headL, const double *__restrict__ L,
                                               const unsigned char *__restrict__ lflag, int precision, int acc_in_lds,
-                                              int leaf_local, double *__restrict__ gscratch) {
+                                              int leaf_local, const int *__restrict__ overflow,
+                                              const double *__restrict__ part, double *__restrict__ gscratch) {
     extern __shared__ double smem[];
+    if (*overflow) return;
     __shared__ int path[256];
     __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg];
-    __shared__ int plen_s, any_s, nsg_s, nops_s, st_phase, st_gi, st_pi, lstate[3];
+    __shared__ int plen_s, any_s, nsg_s, nops_s, st_phase, st_gi, st_pi;
     const int job = blockIdx.y;
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
@@ -858,19 +911,14 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const double s = jb.s;
     const int ns = d * (pmax - 1) + 1;
     const size_t hq = (size_t)jb.noff + leaf;
-    // LDS: red[nthr] | spow[ns] | Hq[nthr][D][pmax] | xs[nthr][D] | cb[P] | wacc[nwv][P] | wMs[nwv][P]
-    //      | wHt[nwv][2 D pmax] | acc[P] | tmp[P] | coef[pmax^2] | dg[P] (u64) | mt[P] (u16)
+    // LDS: red[nthr] | spow[ns] | Hq[nthr][D][pmax] | xs[nthr][D] | acc[P] | tmp[P] | coef[pmax^2]
+    //      | dg[P] (u64) | mt[P] (u16)     (acc / tmp in a global scratch slice when P is large)
     double *red = smem;
     double *spow = red + nthr;
     double *Hq_all = spow + ns;
     double *Hq = Hq_all + (size_t)tid * d * pmax;
     double *xs = Hq_all + (size_t)nthr * d * pmax;
-    const int nwl = leaf_local ? nwv : 0;  // per-wave local-op scratch only when used
-    double *cb = xs + (size_t)nthr * d;
-    double *wacc = cb + (leaf_local ? P : 0);
-    double *wMs = wacc + (size_t)nwl * P;
-    double *wHt = wMs + (size_t)nwl * P;
-    double *tail = wHt + (size_t)nwl * 2 * d * pmax;
+    double *tail = xs + (size_t)nthr * d;
     double *acc, *tmp, *coef;
     if (acc_in_lds) {
         acc = tail;
@@ -896,8 +944,6 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         any_s = any | (leaf_local && headL[hq] >= 0 ? 1 : 0);
     }
     for (int i = tid; i < ns; i += nthr) spow[i] = powi(s, i);
-    if (leaf_local)
-        for (int i = tid; i < P; i += nthr) cb[i] = coef_beta(i, d, pmax);
     __syncthreads();
     const int plen = plen_s;
     const int qb = Q.begin[leaf], nq = Q.end[leaf] - qb;
@@ -946,9 +992,11 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             }
             __syncthreads();
         }
-        if (leaf_local && headL[hq] >= 0)
-            block_local_ops(headL[hq], lgrp, lops, R, Q.ctr + (size_t)leaf * d, s, d, pmax, P, dg, mt, cb, acc, red,
-                            wacc, wMs, wHt, Hq_all, segS, segE, lstate);
+        if (leaf_local && headL[hq] >= 0) {  // the leaf's own local ops, from their partial rows
+            __syncthreads();
+            sum_chain_parts(headL[hq], lgrp, lops, part, P, acc);
+            __syncthreads();
+        }
     }
     // 2. exhaustive and far-field parts
     int slots = 1;
@@ -1145,23 +1193,15 @@ enum { K_TRAV = 0, K_LEAF = 1, K_LOCAL = 3, K_POST = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, L, lflag, heads, segA, segB, pairA, pairB, dec, egrp, eops, fgrp, fops, lgrp, lops, lnodes,
-        cnt, stats, lscr, pscr;
+        cnt, lvl, flag, stats, lscr, pscr, lopnode, part;
+    Caps cap{0, 0, 0, 0, 0, 0, 0};
 };
 thread_local Workspace g_ws;
 
 template <class T> dfgt_status grow(DevBuf &b, size_t n) { return b.reserve(sizeof(T) * std::max<size_t>(n, 1)); }
 
-// Grows an append-only device array, keeping its first `used` elements.
-template <class T> dfgt_status grow_keep(DevBuf &b, size_t need, size_t used, hipStream_t st) {
-    if (sizeof(T) * need <= b.bytes) return DFGT_OK;
-    DevBuf nb;
-    DFGT_TRY(nb.reserve(sizeof(T) * std::max<size_t>(2 * need, 1024)));
-    if (used) DFGT_HIP(hipMemcpyAsync(nb.p, b.p, sizeof(T) * used, hipMemcpyDeviceToDevice, st));
-    DFGT_HIP(hipStreamSynchronize(st));
-    std::swap(b.p, nb.p);
-    std::swap(b.bytes, nb.bytes);
-    return DFGT_OK;
-}
+constexpr int kTravGrid = 8192;  // waves per traversal level (grid-stride over segments)
+constexpr int kLocalGrid = 2048;
 
 }  // namespace
 
@@ -1169,7 +1209,6 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                           int force, int profile, double *G, dfgt_stats *stats_out, hipStream_t st) {
     Workspace &w = g_ws;
     Profiler &prof = g_prof;
-    prof.begin_call(profile != 0);
     const DevTree &Qv = Qh->host_view;
     const int MQ = (int)Qh->m, P = Qh->P, pmax = Qh->pmax, d = Qh->d;
     const int NQ = (int)Qh->n;
@@ -1209,112 +1248,156 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     DFGT_TRY(grow<unsigned char>(w.lflag, nna));
     DFGT_TRY(grow<int>(w.heads, 3 * nna));
     DFGT_TRY(grow<int>(w.cnt, C_N * CP));
+    DFGT_TRY(grow<int>(w.flag, 1));
     DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
-    DFGT_HIP(hipMemsetAsync(w.lflag.p, 0, nna, st));
-    DFGT_HIP(hipMemsetAsync(w.heads.p, 0xff, sizeof(int) * 3 * nna, st));
-    DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * C_N * CP, st));
-    DFGT_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(unsigned long long) * S_N * SP, st));
     int *headE = w.heads.as<int>(), *headF = headE + nna, *headL = headF + nna;
-
-    // level 0: (Q_root, {R_root}) for every job
-    int nseg = nh, npair = nh;
-    {
-        std::vector<Seg> s0(nh);
-        std::vector<int> p0(nh, 0);
-        for (int k = 0; k < nh; ++k) s0[k] = Seg{0, k, k, 1, 0.0};
-        DFGT_TRY(grow<Seg>(w.segA, nseg));
-        DFGT_TRY(grow<int>(w.pairA, npair));
-        DFGT_HIP(hipMemcpyAsync(w.segA.p, s0.data(), sizeof(Seg) * nh, hipMemcpyHostToDevice, st));
-        DFGT_HIP(hipMemcpyAsync(w.pairA.p, p0.data(), sizeof(int) * nh, hipMemcpyHostToDevice, st));
-        DFGT_HIP(hipStreamSynchronize(st));
-    }
     const DevTree *td = w.trees.as<DevTree>();
     const Job *jd = w.jobs.as<Job>();
-    // a query leaf's own local ops are applied inside k_leaf when its
-    // per-wave scratch fits; otherwise they go through the node kernels
+    // a query leaf's own local ops are applied inside k_leaf when its per-wave
+    // scratch fits; otherwise they go through the node kernels
     const bool leaf_local = P <= 512;
-    int levels = 0;
+    // every level splits Q and R wherever they can split, so no pair survives
+    // more levels than the deeper tree has
+    const int nlev = std::max(Qh->depth, Rh->depth);
+    DFGT_TRY(grow<int>(w.lvl, (size_t)(nlev + 1) * 2 * CP));
+
+    Caps &cap = w.cap;
+    if (cap.pair == 0) cap = Caps{1 << 19, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 18, 1 << 18};
+    cap.pair = std::max(cap.pair, 4 * nh);
+    cap.seg = std::max(cap.seg, 4 * nh);
+    std::vector<Seg> s0(nh);
+    std::vector<int> p0(nh, 0);
+    for (int k = 0; k < nh; ++k) s0[k] = Seg{0, k, k, 1, 0.0};
     int c[C_N] = {0};
-    std::vector<int> craw((size_t)C_N * CP);
-    DevBuf *segCur = &w.segA, *segNext = &w.segB, *pairCur = &w.pairA, *pairNext = &w.pairB;
-    while (nseg > 0) {
-        ++levels;
-        DFGT_TRY(grow<Seg>(*segNext, 2 * (size_t)nseg));
-        DFGT_TRY(grow<int>(*pairNext, 4 * (size_t)npair));
-        DFGT_TRY(grow<int>(w.dec, npair));
-        DFGT_TRY(grow_keep<Group>(w.egrp, (size_t)c[C_EGRP] + nseg, c[C_EGRP], st));
-        DFGT_TRY(grow_keep<Group>(w.fgrp, (size_t)c[C_FGRP] + nseg, c[C_FGRP], st));
-        DFGT_TRY(grow_keep<Group>(w.lgrp, (size_t)c[C_LGRP] + nseg, c[C_LGRP], st));
-        DFGT_TRY(grow_keep<int>(w.lnodes, 2 * ((size_t)c[C_LNODE] + nseg), 2 * (size_t)c[C_LNODE], st));
-        DFGT_TRY(grow_keep<int>(w.eops, (size_t)c[C_EOP] + npair, c[C_EOP], st));
-        DFGT_TRY(grow_keep<Op>(w.fops, (size_t)c[C_FOP] + npair, c[C_FOP], st));
-        DFGT_TRY(grow_keep<Op>(w.lops, (size_t)c[C_LOP] + npair, c[C_LOP], st));
-        DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * 2 * CP, st));  // per-level counters
-        TravOut o{segNext->as<Seg>(), pairNext->as<int>(), w.egrp.as<Group>(), w.eops.as<int>(),
-                  w.fgrp.as<Group>(), w.fops.as<Op>(),     w.lgrp.as<Group>(), w.lops.as<Op>(),
-                  w.lnodes.as<int>(), headE,               headF,              headL,
-                  w.cnt.as<int>(),    w.stats.as<unsigned long long>()};
-        hipEvent_t ev = prof.start(st);
-        hipLaunchKernelGGL(k_traverse, dim3(nseg), dim3(64), 0, st, td, jd, segCur->as<Seg>(), pairCur->as<int>(),
-                           force, leaf_local ? 1 : 0, w.dec.as<int>(), o);
-        DFGT_HIP(hipGetLastError());
-        prof.stop(K_TRAV, ev, st);
-        DFGT_HIP(hipMemcpyAsync(craw.data(), w.cnt.p, sizeof(int) * C_N * CP, hipMemcpyDeviceToHost, st));
+    int overflow = 1;
+    for (int attempt = 0; attempt < 12 && overflow; ++attempt) {
+        prof.begin_call(profile != 0);
+        DFGT_TRY(grow<Seg>(w.segA, cap.seg));
+        DFGT_TRY(grow<Seg>(w.segB, cap.seg));
+        DFGT_TRY(grow<int>(w.pairA, cap.pair));
+        DFGT_TRY(grow<int>(w.pairB, cap.pair));
+        DFGT_TRY(grow<int>(w.dec, cap.pair));
+        DFGT_TRY(grow<Group>(w.egrp, cap.grp));
+        DFGT_TRY(grow<Group>(w.fgrp, cap.grp));
+        DFGT_TRY(grow<Group>(w.lgrp, cap.grp));
+        DFGT_TRY(grow<int>(w.lnodes, 2 * (size_t)cap.lnode));
+        DFGT_TRY(grow<int>(w.eops, cap.eop));
+        DFGT_TRY(grow<Op>(w.fops, cap.fop));
+        DFGT_TRY(grow<Op>(w.lops, cap.lop));
+        if (leaf_local) {
+            DFGT_TRY(grow<int>(w.lopnode, cap.lop));
+            DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * P));
+        }
+        DFGT_HIP(hipMemsetAsync(w.lflag.p, 0, nna, st));
+        DFGT_HIP(hipMemsetAsync(w.heads.p, 0xff, sizeof(int) * 3 * nna, st));
+        DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * C_N * CP, st));
+        DFGT_HIP(hipMemsetAsync(w.lvl.p, 0, sizeof(int) * (nlev + 1) * 2 * CP, st));
+        DFGT_HIP(hipMemsetAsync(w.flag.p, 0, sizeof(int), st));
+        DFGT_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(unsigned long long) * S_N * SP, st));
+        DFGT_HIP(hipMemcpyAsync(w.segA.p, s0.data(), sizeof(Seg) * nh, hipMemcpyHostToDevice, st));
+        DFGT_HIP(hipMemcpyAsync(w.pairA.p, p0.data(), sizeof(int) * nh, hipMemcpyHostToDevice, st));
+        int *lvl = w.lvl.as<int>();
+        for (int k = 0; k < nlev; ++k) {
+            DevBuf &sin = (k & 1) ? w.segB : w.segA, &sout = (k & 1) ? w.segA : w.segB;
+            DevBuf &pin = (k & 1) ? w.pairB : w.pairA, &pout = (k & 1) ? w.pairA : w.pairB;
+            TravOut o{sout.as<Seg>(),   pout.as<int>(),    w.egrp.as<Group>(), w.eops.as<int>(),
+                      w.fgrp.as<Group>(), w.fops.as<Op>(),  w.lgrp.as<Group>(), w.lops.as<Op>(),
+                      w.lnodes.as<int>(), headE,            headF,              headL,
+                      w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
+                      w.stats.as<unsigned long long>(),     cap};
+            hipEvent_t ev = prof.start(st);
+            hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
+                               k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, nh, force,
+                               leaf_local ? 1 : 0, w.dec.as<int>(), o);
+            DFGT_HIP(hipGetLastError());
+            prof.stop(K_TRAV, ev, st);
+        }
+        // local moments: every D / T op in parallel, then per internal node
+        {
+            hipEvent_t ev = prof.start(st);
+            if (leaf_local) {
+                hipLaunchKernelGGL(k_lop_owner, dim3(kLocalGrid), dim3(64), 0, st, w.lgrp.as<Group>(), w.cnt.as<int>(),
+                                   w.flag.as<int>(), w.lopnode.as<int>());
+                const size_t wstride = 2 * (size_t)P + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax;
+                const size_t sh = sizeof(double) * ((size_t)P + (10 * (size_t)P + 7) / 8 + 4 * wstride);
+                hipLaunchKernelGGL(k_lops, dim3(kLocalGrid), dim3(256), sh, st, td, jd, w.lgrp.as<Group>(),
+                                   w.lops.as<Op>(), w.lopnode.as<int>(), w.cnt.as<int>(), w.flag.as<int>(),
+                                   w.part.as<double>());
+                hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(64), sizeof(double) * P, st, jd, td,
+                                   w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
+                                   w.lops.as<Op>(), w.part.as<double>(), w.L.as<double>(),
+                                   w.lflag.as<unsigned char>());
+            } else {
+                DFGT_TRY(grow<double>(w.lscr, (size_t)kLocalGrid * 3 * P));
+                const size_t sh = sizeof(double) * ((size_t)pmax * pmax + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax);
+                hipLaunchKernelGGL(k_local_big, dim3(kLocalGrid), dim3(kLocBlock), sh, st, td, jd, w.lnodes.as<int>(),
+                                   w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(), w.lops.as<Op>(),
+                                   w.lscr.as<double>(), w.L.as<double>(), w.lflag.as<unsigned char>());
+            }
+            DFGT_HIP(hipGetLastError());
+            prof.stop(K_LOCAL, ev, st);
+        }
+        // everything per query leaf
+        {
+            int nthr = 256;
+            while (nthr > 64 && sizeof(double) * (size_t)nthr * d * (pmax + 1) > 40 * 1024) nthr >>= 1;
+            const size_t base = sizeof(double) * ((size_t)nthr + d * (pmax - 1) + 1 + (size_t)nthr * d * pmax +
+                                                  (size_t)nthr * d);
+            const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
+            const size_t lds_acc = sizeof(double) * (2 * (size_t)P + (size_t)pmax * pmax);
+            const bool acc_lds = base + lds_acc + lds_dig <= 64 * 1024;
+            double *scr = nullptr;
+            if (!acc_lds) {
+                DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 2 * P));
+                scr = w.pscr.as<double>();
+            }
+            const size_t sh = base + (acc_lds ? lds_acc : sizeof(double) * (size_t)pmax * pmax) + lds_dig;
+            if (sh > 64 * 1024) {
+                set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
+                return DFGT_EINVAL;
+            }
+            hipEvent_t ev = prof.start(st);
+            hipLaunchKernelGGL(k_leaf, dim3(Qv.nleaves, nh), dim3(nthr), sh, st, td, jd, w.egrp.as<Group>(),
+                               w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
+                               w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
+                               precision, acc_lds ? 1 : 0, leaf_local ? 1 : 0, w.flag.as<int>(),
+                               leaf_local ? w.part.as<double>() : (const double *)nullptr, scr);
+            DFGT_HIP(hipGetLastError());
+            prof.stop(K_LEAF, ev, st);
+        }
+        // one readback: overflow flag and the counters that size a rerun
+        std::vector<int> hc((size_t)C_N * CP), hl((size_t)(nlev + 1) * 2 * CP);
+        DFGT_HIP(hipMemcpyAsync(&overflow, w.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipMemcpyAsync(hc.data(), w.cnt.p, sizeof(int) * hc.size(), hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipMemcpyAsync(hl.data(), w.lvl.p, sizeof(int) * hl.size(), hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
-        for (int k = 0; k < C_N; ++k) c[k] = craw[(size_t)k * CP];
-        nseg = c[C_SEG];
-        npair = c[C_PAIR];
-        std::swap(segCur, segNext);
-        std::swap(pairCur, pairNext);
+        for (int k = 0; k < C_N; ++k) c[k] = hc[(size_t)k * CP];
+        if (!overflow && hl[((size_t)nlev * 2 + C_SEG) * CP] != 0) {
+            set_error("dfgt_gauss_sum: internal error, node pairs left after the last level");
+            return DFGT_EHIP;
+        }
+        if (overflow) {
+            int mseg = 0, mpair = 0;
+            for (int k = 1; k <= nlev; ++k) {
+                mseg = std::max(mseg, hl[((size_t)k * 2 + C_SEG) * CP]);
+                mpair = std::max(mpair, hl[((size_t)k * 2 + C_PAIR) * CP]);
+            }
+            auto up = [](int cur, long long need) {
+                long long v = std::max<long long>(2LL * cur, 2LL * need);
+                return (int)std::min<long long>(v, (1LL << 30));
+            };
+            cap.seg = up(cap.seg, mseg);
+            cap.pair = up(cap.pair, mpair);
+            cap.eop = up(cap.eop, c[C_EOP]);
+            cap.fop = up(cap.fop, c[C_FOP]);
+            cap.lop = up(cap.lop, c[C_LOP]);
+            cap.grp = up(cap.grp, std::max(c[C_EGRP], std::max(c[C_FGRP], c[C_LGRP])));
+            cap.lnode = up(cap.lnode, c[C_LNODE]);
+        }
     }
-    // local moments of every node with D / T ops
-    if (c[C_LNODE]) {
-        hipEvent_t ev = prof.start(st);
-        if (P <= 512) {
-            const size_t sh = sizeof(double) * (2 * (size_t)P + 256 + 4 * (2 * (size_t)P + 2 * (size_t)d * pmax +
-                                                                        64 * (size_t)d * pmax)) +
-                              (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
-            hipLaunchKernelGGL(k_local, dim3(c[C_LNODE]), dim3(256), sh, st, td, jd, w.lnodes.as<int>(), headL,
-                               w.lgrp.as<Group>(), w.lops.as<Op>(), w.L.as<double>(), w.lflag.as<unsigned char>(),
-                               w.stats.as<unsigned long long>());
-        } else {
-            DFGT_TRY(grow<double>(w.lscr, (size_t)c[C_LNODE] * 3 * P));
-            const size_t sh = sizeof(double) * ((size_t)pmax * pmax + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax);
-            hipLaunchKernelGGL(k_local_big, dim3(c[C_LNODE]), dim3(kLocBlock), sh, st, td, jd, w.lnodes.as<int>(),
-                               headL, w.lgrp.as<Group>(), w.lops.as<Op>(), w.lscr.as<double>(), w.L.as<double>(),
-                               w.lflag.as<unsigned char>());
-        }
-        DFGT_HIP(hipGetLastError());
-        prof.stop(K_LOCAL, ev, st);
-    }
-    // everything per query leaf
-    {
-        int nthr = 256;
-        while (nthr > 64 && sizeof(double) * (size_t)nthr * d * (pmax + 1) > 40 * 1024) nthr >>= 1;
-        const int nwl = leaf_local ? nthr / 64 : 0;
-        const size_t base = sizeof(double) * ((size_t)nthr + d * (pmax - 1) + 1 + (size_t)nthr * d * pmax +
-                                              (size_t)nthr * d + (leaf_local ? P : 0) + 2 * (size_t)nwl * P +
-                                              (size_t)nwl * 2 * d * pmax);
-        const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
-        const size_t lds_acc = sizeof(double) * (2 * (size_t)P + (size_t)pmax * pmax);
-        const bool acc_lds = base + lds_acc + lds_dig <= 64 * 1024;
-        double *scr = nullptr;
-        if (!acc_lds) {
-            DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 2 * P));
-            scr = w.pscr.as<double>();
-        }
-        const size_t sh = base + (acc_lds ? lds_acc : sizeof(double) * (size_t)pmax * pmax) + lds_dig;
-        if (sh > 64 * 1024) {
-            set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
-            return DFGT_EINVAL;
-        }
-        hipEvent_t ev = prof.start(st);
-        hipLaunchKernelGGL(k_leaf, dim3(Qv.nleaves, nh), dim3(nthr), sh, st, td, jd, w.egrp.as<Group>(),
-                           w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
-                           w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
-                           precision, acc_lds ? 1 : 0, leaf_local ? 1 : 0, scr);
-        DFGT_HIP(hipGetLastError());
-        prof.stop(K_LEAF, ev, st);
+    if (overflow) {
+        set_error("dfgt_gauss_sum: traversal buffers could not be sized");
+        return DFGT_ENOMEM;
     }
     if (stats_out) {
         std::vector<unsigned long long> sraw((size_t)S_N * SP);
@@ -1331,7 +1414,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         stats_out->prune_centroid = (int64_t)sv[S_C];
         stats_out->base_leaf_pairs = (int64_t)sv[S_BLEAF];
         stats_out->base_point_pairs = (int64_t)sv[S_BPTS];
-        stats_out->levels = levels;
+        stats_out->levels = nlev;
         stats_out->max_order = (int64_t)sv[S_MAXORD];
         stats_out->fp64_groups = (int64_t)sv[S_FP64];
         stats_out->segments = (int64_t)sv[S_SEGS];
