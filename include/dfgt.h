@@ -185,6 +185,64 @@ dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev,
 dfgt_status dfgt_gauss_sum(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
                            const dfgt_options *opt, double *G_dev, dfgt_stats *stats, void *stream);
 
+/*
+ * Gradient mode of dfgt_gauss_sum (an extension: the paper has no gradients).
+ * Returns sums G~ with the same guarantee |G~ - G| <= eps * G and the exact
+ * derivatives of that approximation, per query:
+ *     dGdh_dev[k*NQ + i]       = d G~_k(q_i) / d h_k          (may be NULL)
+ *     dGdq_dev[(k*NQ + i)*d+c] = d G~_k(q_i) / d q_{i,c}      (may be NULL)
+ * with the reference points held fixed.  Exhaustive leaf pairs contribute
+ * the exact terms h^-3 sum_j K_ij |q_i - r_j|^2 and -h^-2 sum_j K_ij (q_i - r_j);
+ * far-field, direct-local, far-to-local and local-to-local terms are
+ * differentiated through their Hermite functions (d/dt h_n(t) = -h_{n+1}(t))
+ * and the s^|alpha| moment scaling.  So that these derivatives approximate the
+ * true ones about as well as the values do, the traversal of this mode uses
+ * local expansions (direct local, far-to-local) one order above what the value
+ * bound needs and does not use the centroid form (which is constant in q);
+ * G~ may therefore differ from dfgt_gauss_sum's within the guarantee.  The
+ * derivative error has no certified bound; measured on clustered 2-D and 3-D
+ * data it stays below a few eps * G / h.
+ * Buffers are caller-allocated device memory; G_dev is required.
+ * Errors as dfgt_gauss_sum; p_max^d > 512 -> DFGT_EINVAL.
+ */
+dfgt_status dfgt_gauss_sum_grad(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                                const dfgt_options *opt, double *G_dev, double *dGdh_dev, double *dGdq_dev,
+                                dfgt_stats *stats, void *stream);
+
+/*
+ * Vector-Jacobian product of dfgt_gauss_sum (the backward pass of the sums
+ * as a differentiable function of the bandwidths and the query points):
+ *     dh_host[k] = sum_i dG_dev[k*NQ + i] * dG~_k(q_i)/dh_k           (may be NULL)
+ *     dq_dev[i*d + c] = sum_k dG_dev[k*NQ + i] * dG~_k(q_i)/dq_{i,c}   (may be NULL)
+ * The derivatives are those of dfgt_gauss_sum_grad with the same arguments
+ * (deterministic: repeated calls return the same bits).  Sums over queries and
+ * bandwidths are taken in a fixed order.
+ * dG_dev: n_h x NQ float64 device; dq_dev: NQ x d float64 device.
+ * Synchronises the stream when dh_host is given.
+ */
+dfgt_status dfgt_gauss_sum_backward(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                                    const dfgt_options *opt, const double *dG_dev, double *dh_host,
+                                    double *dq_dev, void *stream);
+
+/*
+ * Least-squares cross-validation score of Section 1 (the LSCV criterion used
+ * to choose h), for every bandwidth h_k of h_host, from DFGT sums over R at
+ * h_k and at sqrt(2) h_k (a Gaussian convolved with itself has bandwidth
+ * sqrt(2) h), all 2 n_h of them in one traversal.  With
+ *     S(h) = sum_i (G~(x_i, R; h) - 1),  a = (4 pi h^2)^(-D/2),  b = (2 pi h^2)^(-D/2):
+ *   variant 0 (leave-one-out in both terms, the paper's formula):
+ *     cv = (a S(sqrt2 h) - 2 b S(h)) / (N (N-1))
+ *   variant 1 (the standard score: integral of the squared estimate keeps its
+ *              diagonal terms):
+ *     cv = a (N + S(sqrt2 h)) / N^2 - 2 b S(h) / (N (N-1))
+ * cv_host[n_h] receives the scores; dcv_host[n_h] (may be NULL) receives
+ * d cv / d h from the gradient mode.  Each S carries an error of at most
+ * eps * (S + N).  N >= 2 and n_h <= 32767.  Synchronises the stream.
+ */
+dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, double eps, int32_t variant,
+                            const dfgt_options *opt, double *cv_host, double *dcv_host, dfgt_stats *stats,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

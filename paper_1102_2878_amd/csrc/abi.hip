@@ -191,26 +191,90 @@ dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev,
     DFGT_GUARD_END
 }
 
+// Options of a summation call: precision and force default to the tree's.
+static dfgt_status call_options(const dfgt_tree_s *R, const dfgt_options *opt, const char *who, int *precision,
+                                int *force, int *profile) {
+    *precision = R->precision;
+    *force = R->force;
+    *profile = 0;
+    if (opt) {
+        for (int i = 0; i < 3; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, std::string(who) + ": reserved option field set");
+        DFGT_REQUIRE(opt->precision == DFGT_PREC_MIXED || opt->precision == DFGT_PREC_FP64,
+                     std::string(who) + ": unknown precision");
+        DFGT_REQUIRE(opt->force_method >= 0 && opt->force_method <= 5, std::string(who) + ": unknown force_method");
+        *precision = opt->precision;
+        *force = opt->force_method;
+        *profile = opt->profile;
+    }
+    return DFGT_OK;
+}
+
+static dfgt_status check_pair(const dfgt_tree_s *Q, const dfgt_tree_s *R, double eps, const char *who) {
+    DFGT_REQUIRE(Q->d == R->d, std::string(who) + ": query and reference dimensions differ");
+    DFGT_REQUIRE(Q->pmax == R->pmax, std::string(who) + ": query and reference trees use different p_max");
+    DFGT_REQUIRE(std::isfinite(eps) && eps >= 0.0 && eps < 1.0, std::string(who) + ": eps must be in [0, 1)");
+    return DFGT_OK;
+}
+
 dfgt_status dfgt_gauss_sum(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
                            const dfgt_options *opt, double *G_dev, dfgt_stats *stats, void *stream) {
     DFGT_GUARD_BEGIN
     DFGT_REQUIRE(Q && R && G_dev, "dfgt_gauss_sum: NULL argument");
-    DFGT_REQUIRE(Q->d == R->d, "dfgt_gauss_sum: query and reference dimensions differ");
-    DFGT_REQUIRE(Q->pmax == R->pmax, "dfgt_gauss_sum: query and reference trees use different p_max");
-    DFGT_REQUIRE(std::isfinite(eps) && eps >= 0.0 && eps < 1.0, "dfgt_gauss_sum: eps must be in [0, 1)");
+    DFGT_TRY(check_pair(Q, R, eps, "dfgt_gauss_sum"));
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum"));
-    int precision = R->precision, force = R->force, profile = 0;
-    if (opt) {
-        for (int i = 0; i < 3; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, "dfgt_gauss_sum: reserved option field set");
-        DFGT_REQUIRE(opt->precision == DFGT_PREC_MIXED || opt->precision == DFGT_PREC_FP64,
-                     "dfgt_gauss_sum: unknown precision");
-        DFGT_REQUIRE(opt->force_method >= 0 && opt->force_method <= 5, "dfgt_gauss_sum: unknown force_method");
-        precision = opt->precision;
-        force = opt->force_method;
-        profile = opt->profile;
-    }
+    int precision, force, profile;
+    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum", &precision, &force, &profile));
     DFGT_REQUIRE(profile == 0 || stats != nullptr, "dfgt_gauss_sum: profile needs a stats pointer");
-    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, G_dev, stats, (hipStream_t)stream);
+    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, G_dev, nullptr, stats,
+                         (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_gauss_sum_grad(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                                const dfgt_options *opt, double *G_dev, double *dGdh_dev, double *dGdq_dev,
+                                dfgt_stats *stats, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(Q && R && G_dev, "dfgt_gauss_sum_grad: NULL argument");
+    DFGT_REQUIRE(dGdh_dev || dGdq_dev, "dfgt_gauss_sum_grad: both derivative outputs are NULL");
+    DFGT_TRY(check_pair(Q, R, eps, "dfgt_gauss_sum_grad"));
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum_grad"));
+    int precision, force, profile;
+    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum_grad", &precision, &force, &profile));
+    DFGT_REQUIRE(profile == 0 || stats != nullptr, "dfgt_gauss_sum_grad: profile needs a stats pointer");
+    GradOut go{dGdh_dev, dGdq_dev};
+    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, G_dev, &go, stats,
+                         (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_gauss_sum_backward(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                                    const dfgt_options *opt, const double *dG_dev, double *dh_host, double *dq_dev,
+                                    void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(Q && R && dG_dev, "dfgt_gauss_sum_backward: NULL argument");
+    DFGT_REQUIRE(dh_host || dq_dev, "dfgt_gauss_sum_backward: both gradient outputs are NULL");
+    DFGT_TRY(check_pair(Q, R, eps, "dfgt_gauss_sum_backward"));
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum_backward"));
+    int precision, force, profile;
+    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum_backward", &precision, &force, &profile));
+    return run_backward(Q, R, h_host, n_h, eps, precision, force, dG_dev, dh_host, dq_dev, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, double eps, int32_t variant,
+                            const dfgt_options *opt, double *cv_host, double *dcv_host, dfgt_stats *stats,
+                            void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(R && cv_host, "dfgt_lscv_score: NULL argument");
+    DFGT_REQUIRE(R->n >= 2, "dfgt_lscv_score: needs at least two points");
+    DFGT_REQUIRE(variant == 0 || variant == 1, "dfgt_lscv_score: variant must be 0 or 1");
+    DFGT_TRY(check_pair(R, R, eps, "dfgt_lscv_score"));
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_lscv_score"));
+    DFGT_REQUIRE(n_h <= 32767, "dfgt_lscv_score: n_h must be <= 32767");
+    int precision, force, profile;
+    DFGT_TRY(call_options(R, opt, "dfgt_lscv_score", &precision, &force, &profile));
+    DFGT_REQUIRE(profile == 0, "dfgt_lscv_score: profiling is not supported here");
+    return run_lscv(R, h_host, n_h, eps, precision, force, variant, cv_host, dcv_host, stats, (hipStream_t)stream);
     DFGT_GUARD_END
 }
 

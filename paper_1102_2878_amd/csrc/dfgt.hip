@@ -52,6 +52,7 @@ struct Job {
     long long qoff;            // offset of this job's per-query arrays
     long long noff;            // offset of this job's per-node arrays
     double *out;               // caller's output for this job (caller order)
+    double *outH, *outQ;       // gradient mode: dG/dh [N_Q] and dG/dq [N_Q][D] (caller order), or null
     int mono;                  // Q and R are the same point set
     int pad;
 };
@@ -192,15 +193,21 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // When that bound holds c_T = D, the least any method can cost; only F at
 // order 1 with N_Q = 1 or D at order 1 with N_R = 1 can tie it (and win the
 // tie), so the order searches are skipped.  ku = K(d^u).
+// Gradient mode (gr): a local expansion truncated at order p has a q- and
+// s-derivative whose truncation error is larger than the value's by about p/r
+// (r the scaled node radius), and the centroid form is constant over Q.  So
+// D and T use one order more than the value bound needs (at most p_max) and
+// the centroid form is not used; F is unchanged (its derivative series is the
+// far-field series of the derivative kernel, one Hermite index higher).
 __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double tau,
-                      int pmax, int D, int force, int *order) {
+                      int pmax, int D, int force, int gr, int *order) {
     if (force == DFGT_FORCE_EXACT) {
         *order = 0;
         return METH_E;
     }
     const double kl = exp(-g.sl * inv2h2), kc = exp(-g.sc * inv2h2);
     const double cb = nR * (fmax(kl - kc, kc - ku) + 1e-15 * kl);
-    const bool centroid = cb <= tau;
+    const bool centroid = !gr && cb <= tau;
     if (centroid && force == DFGT_FORCE_NONE) {
         if (nQ == 1.0 && order_far(g.wR / (2.0 * h), nR, tau, 1, D) == 1) {
             *order = 1;
@@ -213,9 +220,14 @@ __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, dou
         *order = 1;
         return METH_T;
     }
+    const int pl = gr ? pmax - 1 : pmax;  // largest value order a local expansion may need
     int pF = order_far(g.wR / (2.0 * h), nR, tau, pmax, D);
-    int pD = order_far(g.wQ / (2.0 * h), nR, tau, pmax, D);
-    int pT = order_f2l(fmax(g.wQ, g.wR) / (2.0 * h), nR, tau, pmax, D);
+    int pD = pl > 0 ? order_far(g.wQ / (2.0 * h), nR, tau, pl, D) : 0;
+    int pT = pl > 0 ? order_f2l(fmax(g.wQ, g.wR) / (2.0 * h), nR, tau, pl, D) : 0;
+    if (gr) {
+        pD = pD ? pD + 1 : 0;
+        pT = pT ? pT + 1 : 0;
+    }
     if (centroid) pT = 1;
     if (force == DFGT_FORCE_F) pD = pT = 0;
     if (force == DFGT_FORCE_D) pF = pT = 0;
@@ -274,7 +286,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // One wave per segment.
 __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Seg sg,
-                                 const int *__restrict__ pairs, int force, int leaf_local, int *dec,
+                                 const int *__restrict__ pairs, int force, int gr, int leaf_local, int *dec,
                                  const TravOut &o) {
     const int lane = threadIdx.x;
     const Job jb = jobs[sg.job];
@@ -305,7 +317,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         const double tau = jb.eps_eff * nR * gl / jb.nR;
         const double ku = exp(-g.su * jb.inv2h2);
         int ord = 0;
-        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, &ord);
+        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, &ord);
         const bool rleaf = R.left[r] < 0;
         if (m != METH_E) {
             plo += nR * ku;
@@ -471,12 +483,12 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
 // level's counters (or nseg0 at level 0), so no host round trip is needed.
 __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                  const Seg *__restrict__ segs, const int *__restrict__ pairs,
-                                                 const int *__restrict__ lvl_in, int nseg0, int force,
+                                                 const int *__restrict__ lvl_in, int nseg0, int force, int gr,
                                                  int leaf_local, int *dec, TravOut o) {
     if (*o.overflow) return;
     const int nseg = lvl_in ? min(lvl_in[C_SEG * CP], o.cap.seg) : nseg0;
     for (int si = blockIdx.x; si < nseg; si += gridDim.x)
-        traverse_segment(trees, jobs, segs[si], pairs, force, leaf_local, dec, o);
+        traverse_segment(trees, jobs, segs[si], pairs, force, gr, leaf_local, dec, o);
 }
 
 // ---------------------------------------------------------------- local moments: D and T ops
@@ -506,10 +518,24 @@ __device__ __forceinline__ double coef_beta(int i, int d, int pmax) {
 
 // One D or T op applied by one wave to the local moments acc[P] about qc; a D
 // op covers reference points [rb, re) of node r.
-// Wave-private scratch: Ms[P] | Ht[D][2 pmax] | Hx[64][D][pmax].
+// With GR the wave also accumulates the tangent moments accB[P] that carry the
+// bandwidth derivative: with L' = dL/ds, accB_beta = s L'_beta + |beta| L_beta.
+// (The translation and evaluation operators act on them exactly as on L, since
+// s^{|beta|} accB_beta = s d(s^{|beta|} L_beta)/ds and s^{|beta|} L_beta are the
+// coefficients of the same polynomial in unscaled coordinates.)  With
+// h_n'(t) = -h_{n+1}(t):
+//   D:  accB_beta += c_beta e^{-|t|^2} [|beta| prod_k H_{beta_k} - sum_k t_k H_{beta_k+1} prod_{j!=k} H_{beta_j}]
+//   T:  accB_beta += c_beta e0 sum_alpha M_alpha [(|alpha|+|beta|) prod_k H_{alpha_k+beta_k}
+//                                               - sum_k t0_k H_{alpha_k+beta_k+1} prod_{j!=k} H_{alpha_j+beta_j}]
+// Wave-private scratch: Ms[P] | Ht[D][2 pmax] | T0[D] | Hx[64][D][pmax + GR] | Tx[64][D] (GR only).
+template <bool GR>
 __device__ void wave_local_op(const DevTree &R, int r, int p, int m, int rb, int re, const double *qc, double s,
                               int d, int pmax, int P, const unsigned long long *dg, const unsigned short *mt,
-                              const double *cb, double *acc, double *Ms, double *Ht, double *Hx, int lane) {
+                              const double *cb, double *acc, double *accB, double *Ms, double *Ht, double *Hx,
+                              int lane) {
+    const int hs = pmax + (GR ? 1 : 0);  // Hermite row length per dimension
+    double *T0 = Ht + 2 * d * pmax;
+    double *Tx = Hx + 64 * (size_t)d * hs;
     if (m == METH_T) {
         double tt = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -520,27 +546,41 @@ __device__ void wave_local_op(const DevTree &R, int r, int p, int m, int rb, int
         const double e0 = exp(-tt);
         const double *mu = R.mu + (size_t)r * P;
         if (p == 1) {
-            if (lane == 0) acc[0] += mu[0] * e0;
+            if (lane == 0) {
+                acc[0] += mu[0] * e0;
+                if (GR) accB[0] -= 2.0 * tt * mu[0] * e0;
+            }
             return;
         }
         for (int i = lane; i < P; i += 64) {
             const int meta = mt[i];
             Ms[i] = (meta >> 8) < p ? mu[i] * powi(s, meta & 255) : 0.0;
         }
-        if (lane < d) hermite_polys((qc[lane] - R.ctr[(size_t)r * d + lane]) * s, 2 * p - 1, Ht + lane * 2 * pmax);
+        if (lane < d) {
+            const double t = (qc[lane] - R.ctr[(size_t)r * d + lane]) * s;
+            hermite_polys(t, 2 * p - 1 + (GR ? 1 : 0), Ht + lane * 2 * pmax);
+            T0[lane] = t;
+        }
         wave_sync();
         for (int b = lane; b < P; b += 64) {
             if ((mt[b] >> 8) >= p) continue;
             const unsigned long long bd = dg[b];
-            double sum = 0.0;
+            const int bs = mt[b] & 255;
+            double sum = 0.0, sumB = 0.0;
             for (int a = 0; a < P; ++a) {
                 if ((mt[a] >> 8) >= p) continue;
                 const unsigned long long ad = dg[a];
-                double prod = Ms[a];
-                for (int k = 0; k < d; ++k) prod *= Ht[k * 2 * pmax + dig_at(ad, k) + dig_at(bd, k)];
-                sum += prod;
+                double pre = Ms[a], sk = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double *hk = Ht + k * 2 * pmax + dig_at(ad, k) + dig_at(bd, k);
+                    if (GR) sk = sk * hk[0] + pre * T0[k] * hk[1];
+                    pre *= hk[0];
+                }
+                sum += pre;
+                if (GR) sumB += (double)((mt[a] & 255) + bs) * pre - sk;
             }
             acc[b] += cb[b] * e0 * sum;
+            if (GR) accB[b] += cb[b] * e0 * sumB;
         }
         wave_sync();
         return;
@@ -548,31 +588,44 @@ __device__ void wave_local_op(const DevTree &R, int r, int p, int m, int rb, int
     for (int x0 = rb; x0 < re; x0 += 64) {
         const int cnt = min(64, re - x0);
         if (lane < cnt) {
-            double *row = Hx + (size_t)lane * d * pmax;
+            double *row = Hx + (size_t)lane * d * hs;
             double tt = 0.0;
             for (int k = 0; k < d; ++k) {
                 const double t = (qc[k] - R.x[(size_t)(x0 + lane) * d + k]) * s;
                 tt += t * t;
-                hermite_polys(t, p, row + k * pmax);
+                hermite_polys(t, p + (GR ? 1 : 0), row + k * hs);
+                if (GR) Tx[lane * d + k] = t;
             }
             const double e = tt > 745.0 ? 0.0 : exp(-tt);
-            for (int b = 0; b < p; ++b) row[b] *= e;
+            for (int b = 0; b < p + (GR ? 1 : 0); ++b) row[b] *= e;  // the exponential rides on dimension 0
         }
         wave_sync();
         for (int b = lane; b < P; b += 64) {
             if ((mt[b] >> 8) >= p) continue;
             const unsigned long long bd = dg[b];
-            double sum = 0.0;
+            const double bs = (double)(mt[b] & 255);
+            double sum = 0.0, sumB = 0.0;
             for (int j = 0; j < cnt; ++j) {
-                const double *row = Hx + (size_t)j * d * pmax;
-                double prod = row[dig_at(bd, 0)];
-                for (int k = 1; k < d; ++k) prod *= row[k * pmax + dig_at(bd, k)];
-                sum += prod;
+                const double *row = Hx + (size_t)j * d * hs;
+                double pre = 1.0, sk = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double *hk = row + k * hs + dig_at(bd, k);
+                    if (GR) sk = sk * hk[0] + pre * Tx[j * d + k] * hk[1];
+                    pre *= hk[0];
+                }
+                sum += pre;
+                if (GR) sumB += bs * pre - sk;
             }
             acc[b] += cb[b] * sum;
+            if (GR) accB[b] += cb[b] * sumB;
         }
         wave_sync();
     }
+}
+
+// Doubles of wave-private scratch used by wave_local_op (acc and accB included).
+__host__ __device__ inline size_t lop_wave_stride(int P, int d, int pmax, int gr) {
+    return (size_t)(2 + gr) * P + 2 * (size_t)d * pmax + d + 64 * (size_t)d * (pmax + gr) + (gr ? 64 * (size_t)d : 0);
 }
 
 constexpr int kMaxSeg = 256;
@@ -581,7 +634,9 @@ constexpr int kMaxSeg = 256;
 // <= 64 reference points), each writing its contribution to Q's local
 // moments into its own row of `part`; per-node sums then add the rows in
 // chain order.  An order-1 T op (the centroid form) only has a zeroth term.
-// LDS per block: cb[P] | dg[P] (u64) | mt[P] (u16) | per wave: acc[P] | Ms[P] | Ht[2 D pmax] | Hx[64][D][pmax]
+// Rows hold PW = P (GR = false) or 2P doubles: L, then the tangent moments.
+// LDS per block: cb[P] | dg[P] (u64) | mt[P] (u16) | per wave: lop_wave_stride doubles
+template <bool GR>
 __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                               const Group *__restrict__ lgrp, const Op *__restrict__ lops,
                                               const int *__restrict__ lop_node, const int *__restrict__ cnt,
@@ -591,12 +646,13 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
     const DevTree &Q0 = trees[jobs[0].qt];
     const int d = Q0.d, pmax = Q0.pmax, P = Q0.P;
+    const size_t PW = GR ? 2 * (size_t)P : (size_t)P;
     double *cb = smem;
     unsigned long long *dg = reinterpret_cast<unsigned long long *>(cb + P);
     unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
-    const size_t wstride = 2 * (size_t)P + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax;
-    double *wbase = cb + P + (10 * (size_t)P + 7) / 8 + (size_t)wv * wstride;
-    double *acc = wbase, *Ms = acc + P, *Ht = Ms + P, *Hx = Ht + 2 * d * pmax;
+    double *wbase = cb + P + (10 * (size_t)P + 7) / 8 + (size_t)wv * lop_wave_stride(P, d, pmax, GR ? 1 : 0);
+    double *acc = wbase, *accB = acc + P, *Ms = accB + (GR ? P : 0), *Ht = Ms + P;
+    double *Hx = Ht + 2 * d * pmax + d;
     build_digit_tables(dg, mt, P, d, pmax);
     for (int i = tid; i < P; i += blockDim.x) cb[i] = coef_beta(i, d, pmax);
     __syncthreads();
@@ -608,7 +664,7 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
         const DevTree &Q = trees[jb.qt];
         const DevTree &R = trees[jb.rt];
         const int r = op.r, p = op.meta & 255, m = (op.meta >> 8) & 15, ch = op.meta >> 12;
-        double *dst = part + (size_t)oi * P;
+        double *dst = part + (size_t)oi * PW;
         const double *qc = Q.ctr + (size_t)g.q * d;
         if (m == METH_T && p == 1) {
             if (lane == 0) {
@@ -617,34 +673,44 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
                     const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * jb.s;
                     tt += t * t;
                 }
-                dst[0] = tt > 745.0 ? 0.0 : R.mu[(size_t)r * P] * exp(-tt);
+                const double v = tt > 745.0 ? 0.0 : R.mu[(size_t)r * P] * exp(-tt);
+                dst[0] = v;
+                if (GR) dst[P] = -2.0 * tt * v;
             }
             continue;
         }
-        for (int i = lane; i < P; i += 64) acc[i] = 0.0;
+        for (int i = lane; i < P; i += 64) {
+            acc[i] = 0.0;
+            if (GR) accB[i] = 0.0;
+        }
         wave_sync();
         const int rb = R.begin[r] + 64 * ch, re = min(R.end[r], rb + 64);
-        wave_local_op(R, r, p, m, rb, re, qc, jb.s, d, pmax, P, dg, mt, cb, acc, Ms, Ht, Hx, lane);
+        wave_local_op<GR>(R, r, p, m, rb, re, qc, jb.s, d, pmax, P, dg, mt, cb, acc, accB, Ms, Ht, Hx, lane);
         wave_sync();
-        for (int i = lane; i < P; i += 64) dst[i] = acc[i];
+        for (int i = lane; i < P; i += 64) {
+            dst[i] = acc[i];
+            if (GR) dst[P + i] = accB[i];
+        }
         wave_sync();
     }
 }
 
-// Adds the op rows of one node's chain in chain order: acc += part[op] (the
-// zeroth term only for order-1 T ops).  Threads over coefficients.
+// Adds the op rows (PW doubles, coefficient i of L at i and of the tangent at
+// P + i) of one node's chain in chain order: acc += part[op] (the zeroth terms
+// only for order-1 T ops).  Threads over the PW entries.
 __device__ __forceinline__ void sum_chain_parts(int head, const Group *__restrict__ lgrp, const Op *__restrict__ lops,
-                                                const double *__restrict__ part, int P, double *acc) {
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                                                const double *__restrict__ part, int P, int PW, double *acc) {
+    for (int i = threadIdx.x; i < PW; i += blockDim.x) {
         double v = acc[i];
+        const bool zeroth = i == 0 || i == P;
         for (int gi = head; gi >= 0; gi = lgrp[gi].next) {
             const Group g = lgrp[gi];
             for (int o = g.start; o < g.start + g.count; ++o) {
                 const int meta = lops[o].meta;
                 if (((meta >> 8) & 15) == METH_T && (meta & 255) == 1) {
-                    if (i == 0) v += part[(size_t)o * P];
+                    if (zeroth) v += part[(size_t)o * PW + i];
                 } else {
-                    v += part[(size_t)o * P + i];
+                    v += part[(size_t)o * PW + i];
                 }
             }
         }
@@ -652,12 +718,13 @@ __device__ __forceinline__ void sum_chain_parts(int head, const Group *__restric
     }
 }
 
-// One wave per internal (Q, job) with local ops.
+// One wave per internal (Q, job) with local ops; L rows hold PW doubles.
 __global__ __launch_bounds__(64) void k_lreduce(const Job *__restrict__ jobs, const DevTree *__restrict__ trees,
                                                 const int *__restrict__ lnodes, const int *__restrict__ cnt,
                                                 const int *__restrict__ overflow, const int *__restrict__ headL,
                                                 const Group *__restrict__ lgrp, const Op *__restrict__ lops,
-                                                const double *__restrict__ part, double *L, unsigned char *lflag) {
+                                                const double *__restrict__ part, int PW, double *L,
+                                                unsigned char *lflag) {
     extern __shared__ double smem[];
     if (*overflow) return;
     const int nl = cnt[C_LNODE * CP];
@@ -666,11 +733,11 @@ __global__ __launch_bounds__(64) void k_lreduce(const Job *__restrict__ jobs, co
         const int q = lnodes[2 * li], job = lnodes[2 * li + 1];
         const size_t hq = (size_t)jobs[job].noff + q;
         wave_sync();
-        for (int i = threadIdx.x; i < P; i += blockDim.x) smem[i] = 0.0;
+        for (int i = threadIdx.x; i < PW; i += blockDim.x) smem[i] = 0.0;
         wave_sync();
-        sum_chain_parts(headL[hq], lgrp, lops, part, P, smem);
+        sum_chain_parts(headL[hq], lgrp, lops, part, P, PW, smem);
         wave_sync();
-        for (int i = threadIdx.x; i < P; i += blockDim.x) L[hq * P + i] = smem[i];
+        for (int i = threadIdx.x; i < PW; i += blockDim.x) L[hq * PW + i] = smem[i];
         if (threadIdx.x == 0) lflag[hq] = 1;
     }
 }
@@ -823,6 +890,13 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
 //   3. Group partials are added in group order, the local expansion is
 //      evaluated (EvalLocalExpansion) and G = G_L + G_E + G_F is written in the
 //      caller's order.
+// With GR the block also differentiates the same approximation (same ops,
+// same orders) with respect to s = 1/(sqrt2 h) and the query point, per query:
+//   X = s dG/ds  and  Y_k = (1/s) dG/dq_k,  written as dG/dh = -X/h, dG/dq_k = s Y_k:
+//   E:  X += -2 sum_r t_r e_r,   Y_k += -2 sum_r e_r (s(q - r))_k     (t_r = s^2 |q - r|^2)
+//   F:  with V_k = -sum_alpha M_alpha h_{alpha + e_k}(t):  Y_k += V_k,
+//       X += sum_alpha |alpha| M_alpha h_alpha(t) + sum_k t_k V_k
+//   L:  X += sum_beta B_beta y^beta (B the tangent moments), Y_k += sum_beta L_beta beta_k y^{beta - e_k}
 constexpr int kInner = 64;
 
 template <int D>
@@ -887,6 +961,103 @@ __device__ __forceinline__ double e_chunk_dispatch(const double *xs, int cnt, in
     }
 }
 
+// Gradient form of e_chunk: returns sum_j e_j and adds cx sum_j t_j e_j to *x
+// and cy sum_j e_j dd_jk to g[k], where dd_j = sc (q - x_j) and t_j = |dd_j|^2
+// (the chunk's own scaling: sc = sig in mixed precision, where e_j = 2^{-t_j}).
+template <int D>
+__device__ __forceinline__ double e_chunk_grad(const double *__restrict__ xs, int cnt, const double *__restrict__ qg,
+                                               double sc, bool fp64, double cx, double cy, double *x, double *g) {
+    double qs[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) qs[k] = qg[k] * sc;
+    if (fp64) {
+        double s0 = 0.0, s1 = 0.0, sk[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) sk[k] = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+            double dd[D], t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                dd[k] = fma(xs[j * D + k], -sc, qs[k]);
+                t = fma(dd[k], dd[k], t);
+            }
+            const double e = exp(-t);
+            s0 += e;
+            s1 = fma(t, e, s1);
+#pragma unroll
+            for (int k = 0; k < D; ++k) sk[k] = fma(e, dd[k], sk[k]);
+        }
+        *x = fma(cx, s1, *x);
+#pragma unroll
+        for (int k = 0; k < D; ++k) g[k] = fma(cy, sk[k], g[k]);
+        return s0;
+    }
+    float p0 = 0.0f, p1 = 0.0f, pk[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) pk[k] = 0.0f;
+    for (int j = 0; j < cnt; ++j) {
+        double dd[D], t = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            dd[k] = fma(xs[j * D + k], -sc, qs[k]);
+            t = fma(dd[k], dd[k], t);
+        }
+        const float tf = (float)t;
+        const float e = __builtin_amdgcn_exp2f(-tf);
+        p0 += e;
+        p1 = fmaf(tf, e, p1);
+#pragma unroll
+        for (int k = 0; k < D; ++k) pk[k] = fmaf(e, (float)dd[k], pk[k]);
+    }
+    *x = fma(cx, (double)p1, *x);
+#pragma unroll
+    for (int k = 0; k < D; ++k) g[k] = fma(cy, (double)pk[k], g[k]);
+    return (double)p0;
+}
+
+__device__ double e_chunk_grad_any(const double *__restrict__ xs, int cnt, int d, const double *__restrict__ qg,
+                                   double sc, bool fp64, double cx, double cy, double *x, double *g) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 0; j < cnt; ++j) {
+        double t = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double dd = fma(xs[j * d + k], -sc, qg[k] * sc);
+            t = fma(dd, dd, t);
+        }
+        const double e = fp64 ? exp(-t) : (double)__builtin_amdgcn_exp2f(-(float)t);
+        s0 += e;
+        s1 = fma(t, e, s1);
+        for (int k = 0; k < d; ++k) g[k] = fma(cy * e, fma(xs[j * d + k], -sc, qg[k] * sc), g[k]);
+    }
+    *x = fma(cx, s1, *x);
+    return s0;
+}
+
+__device__ __forceinline__ double e_chunk_grad_dispatch(const double *xs, int cnt, int d, const double *qg, double sc,
+                                                        bool fp64, double cx, double cy, double *x, double *g) {
+    switch (d) {
+    case 1: return e_chunk_grad<1>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    case 2: return e_chunk_grad<2>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    case 3: return e_chunk_grad<3>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    case 4: return e_chunk_grad<4>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    case 5: return e_chunk_grad<5>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    case 8: return e_chunk_grad<8>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    case 16: return e_chunk_grad<16>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
+    default: return e_chunk_grad_any(xs, cnt, d, qg, sc, fp64, cx, cy, x, g);
+    }
+}
+
+// ln 2 and sqrt(ln 2): mixed-precision tiles work in sig = sqrt(log2 e) s units.
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kSqrtLn2 = 0.83255461115769775635;
+
+// Doubles of dynamic LDS k_leaf needs before the coefficient vectors.
+__host__ __device__ inline size_t leaf_lds_base(int nthr, int d, int pmax, int gr) {
+    return (size_t)nthr * (1 + gr) + (size_t)d * (pmax - 1) + 1 + (size_t)nthr * d * (pmax + gr) +
+           (size_t)nthr * d * (1 + gr);
+}
+
+template <bool GR>
 __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                               const Group *__restrict__ egrp, const int *__restrict__ eops,
                                               const Group *__restrict__ fgrp, const Op *__restrict__ fops,
@@ -907,27 +1078,33 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const DevTree &R = trees[jb.rt];
     const int leaf = Q.leaves[blockIdx.x];
     const int d = Q.d, pmax = Q.pmax, P = Q.P;
-    const int nthr = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = nthr >> 6;
+    const int PW = GR ? 2 * P : P;
+    const int hs = pmax + (GR ? 1 : 0);
+    const int nthr = blockDim.x, tid = threadIdx.x;
     const double s = jb.s;
     const int ns = d * (pmax - 1) + 1;
     const size_t hq = (size_t)jb.noff + leaf;
-    // LDS: red[nthr] | spow[ns] | Hq[nthr][D][pmax] | xs[nthr][D] | acc[P] | tmp[P] | coef[pmax^2]
-    //      | dg[P] (u64) | mt[P] (u16)     (acc / tmp in a global scratch slice when P is large)
+    // LDS: red[nthr] | redX[nthr] (GR) | spow[ns] | Hq[nthr][D][hs] | xs[nthr][D] | gq[nthr][D] (GR)
+    //      | acc[PW] | tmp[PW] | coef[pmax^2] | dg[P] (u64) | mt[P] (u16)
+    //      (acc / tmp in a global scratch slice when P is large)
     double *red = smem;
-    double *spow = red + nthr;
+    double *redX = red + nthr;
+    double *spow = redX + (GR ? nthr : 0);
     double *Hq_all = spow + ns;
-    double *Hq = Hq_all + (size_t)tid * d * pmax;
-    double *xs = Hq_all + (size_t)nthr * d * pmax;
-    double *tail = xs + (size_t)nthr * d;
+    double *Hq = Hq_all + (size_t)tid * d * hs;
+    double *xs = Hq_all + (size_t)nthr * d * hs;
+    double *gq_all = xs + (size_t)nthr * d;
+    double *gq = gq_all + (size_t)tid * d;
+    double *tail = gq_all + (GR ? (size_t)nthr * d : 0);
     double *acc, *tmp, *coef;
     if (acc_in_lds) {
         acc = tail;
-        tmp = acc + P;
-        coef = tmp + P;
+        tmp = acc + PW;
+        coef = tmp + PW;
     } else {
         const size_t slot = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        acc = gscratch + slot * 2 * P;
-        tmp = acc + P;
+        acc = gscratch + slot * 2 * PW;
+        tmp = acc + PW;
         coef = tail;
     }
     unsigned long long *dg = reinterpret_cast<unsigned long long *>(coef + pmax * pmax);
@@ -955,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     // 1. local moments at the leaf
     const bool any = any_s != 0;
     if (any) {
-        for (int i = tid; i < P; i += nthr) acc[i] = 0.0;
+        for (int i = tid; i < PW; i += nthr) acc[i] = 0.0;
         bool nonzero = false;
         for (int pi = plen - 1; pi >= 0; --pi) {
             const int v = path[pi];
@@ -976,25 +1153,26 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                     }
                     __syncthreads();
                     mode_product(src, dst, coef, P, d, pmax, k, pmax);
+                    if (GR) mode_product(src + P, dst + P, coef, P, d, pmax, k, pmax);
                     double *t2 = src;
                     src = dst;
                     dst = t2;
                 }
                 __syncthreads();
                 if (src != acc)
-                    for (int i = tid; i < P; i += nthr) acc[i] = src[i];
+                    for (int i = tid; i < PW; i += nthr) acc[i] = src[i];
                 __syncthreads();
             }
             if (lflag[jb.noff + v]) {
-                const double *Lv = L + ((size_t)jb.noff + v) * P;
-                for (int i = tid; i < P; i += nthr) acc[i] += Lv[i];
+                const double *Lv = L + ((size_t)jb.noff + v) * PW;
+                for (int i = tid; i < PW; i += nthr) acc[i] += Lv[i];
                 nonzero = true;
             }
             __syncthreads();
         }
         if (leaf_local && headL[hq] >= 0) {  // the leaf's own local ops, from their partial rows
             __syncthreads();
-            sum_chain_parts(headL[hq], lgrp, lops, part, P, acc);
+            sum_chain_parts(headL[hq], lgrp, lops, part, P, PW, acc);
             __syncthreads();
         }
     }
@@ -1011,7 +1189,9 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         const bool act = qq < nq;
         const int qpos = qb + (act ? qq : 0);
         const double *qg = Q.x + (size_t)qpos * d;
-        double part = 0.0;
+        double part = 0.0, px = 0.0;
+        if (GR)
+            for (int k = 0; k < d; ++k) gq[k] = 0.0;
         if (tid == 0) {
             st_phase = 0;
             st_gi = headE[hq];
@@ -1069,6 +1249,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 if (type != 1) {
                     const bool fp64 = precision == DFGT_PREC_FP64 || type == 2;
                     const double sc = fp64 ? jb.s : jb.sig;
+                    const double cx = fp64 ? -2.0 : -2.0 * kLn2, cy = fp64 ? -2.0 : -2.0 * kSqrtLn2;
                     const int r = eops[segS[sp] + off];
                     const int rb = R.begin[r], re = R.end[r];
                     if (staged) {
@@ -1077,58 +1258,113 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                             if (qi < cnt)
                                 for (int k = 0; k < d; ++k) xg[qi * d + k] = R.x[(size_t)(j0 + qi) * d + k];
                             wave_sync();
-                            if (act) part += e_chunk_dispatch(xg, cnt, d, qg, sc, fp64);
+                            if (act) {
+                                if (GR) part += e_chunk_grad_dispatch(xg, cnt, d, qg, sc, fp64, cx, cy, &px, gq);
+                                else part += e_chunk_dispatch(xg, cnt, d, qg, sc, fp64);
+                            }
                             wave_sync();
                         }
                     } else if (act) {
-                        for (int j0 = rb; j0 < re; j0 += kInner)
-                            part += e_chunk_dispatch(R.x + (size_t)j0 * d, min(kInner, re - j0), d, qg, sc, fp64);
+                        for (int j0 = rb; j0 < re; j0 += kInner) {
+                            const double *xr = R.x + (size_t)j0 * d;
+                            const int cnt = min(kInner, re - j0);
+                            if (GR) part += e_chunk_grad_dispatch(xr, cnt, d, qg, sc, fp64, cx, cy, &px, gq);
+                            else part += e_chunk_dispatch(xr, cnt, d, qg, sc, fp64);
+                        }
                     }
                 } else if (act) {
                     const Op op = fops[segS[sp] + off];
                     const int r = op.r, p = op.meta & 255;
                     const double *mu = R.mu + (size_t)r * P;
+                    const double *rc = R.ctr + (size_t)r * d;
                     double tt = 0.0;
                     for (int k = 0; k < d; ++k) {
-                        const double t = (qg[k] - R.ctr[(size_t)r * d + k]) * s;
+                        const double t = (qg[k] - rc[k]) * s;
                         tt += t * t;
-                        hermite_polys(t, p, Hq + k * pmax);
+                        hermite_polys(t, p + (GR ? 1 : 0), Hq + k * hs);
                     }
                     if (tt <= 745.0) {  // else e^{-|t|^2} underflows: the expansion is 0
-                        double w = 0.0;
+                        double w = 0.0, w1 = 0.0;
                         for (int i = 0; i < P; ++i) {
                             const int meta = mt[i];
                             if ((meta >> 8) >= p) continue;
                             const unsigned long long ad = dg[i];
                             double prod = mu[i] * spow[meta & 255];
-                            for (int k = 0; k < d; ++k) prod *= Hq[k * pmax + dig_at(ad, k)];
+                            for (int k = 0; k < d; ++k) prod *= Hq[k * hs + dig_at(ad, k)];
                             w += prod;
+                            if (GR) w1 = fma((double)(meta & 255), prod, w1);
                         }
-                        part = fma(exp(-tt), w, part);
+                        const double e = exp(-tt);
+                        part = fma(e, w, part);
+                        if (GR) {
+                            double xs_ = w1;
+                            for (int k = 0; k < d; ++k) {
+                                double vk = 0.0;
+                                for (int i = 0; i < P; ++i) {
+                                    const int meta = mt[i];
+                                    if ((meta >> 8) >= p) continue;
+                                    const unsigned long long ad = dg[i];
+                                    double prod = mu[i] * spow[meta & 255];
+                                    for (int j = 0; j < d; ++j) prod *= Hq[j * hs + dig_at(ad, j) + (j == k ? 1 : 0)];
+                                    vk -= prod;
+                                }
+                                gq[k] = fma(e, vk, gq[k]);
+                                xs_ = fma((qg[k] - rc[k]) * s, vk, xs_);
+                            }
+                            px = fma(e, xs_, px);
+                        }
                     }
                 }
             }
             __syncthreads();
         }
         red[tid] = part;
+        if (GR) redX[tid] = px;
         __syncthreads();
         if (tg == 0 && act) {
-            double gsum = 0.0;
+            double gsum = 0.0, xsum = 0.0;
             for (int k = 0; k < ngr; ++k) gsum += red[k * slots + qi];
-            double gl = 0.0;
+            if (GR) {
+                for (int k = 0; k < ngr; ++k) xsum += redX[k * slots + qi];
+                for (int k = 1; k < ngr; ++k)
+                    for (int c = 0; c < d; ++c) gq[c] += gq_all[(size_t)(k * slots + qi) * d + c];
+            }
+            double gl = 0.0, xl = 0.0;
             if (any) {
                 double y[kMaxD];
                 for (int k = 0; k < d; ++k) y[k] = (qg[k] - lc[k]) * s;
                 for (int i = 0; i < P; ++i) {
                     const double a = acc[i];
-                    if (a == 0.0) continue;
+                    const double aB = GR ? acc[P + i] : 0.0;
+                    if (a == 0.0 && aB == 0.0) continue;
                     const unsigned long long ad = dg[i];
-                    double prod = a;
-                    for (int k = 0; k < d; ++k) prod *= powi(y[k], dig_at(ad, k));
+                    double prod = a, prodB = aB;
+                    for (int k = 0; k < d; ++k) {
+                        const double yk = powi(y[k], dig_at(ad, k));
+                        prod *= yk;
+                        if (GR) prodB *= yk;
+                    }
                     gl += prod;
+                    if (GR) {
+                        xl += prodB;
+                        if (a != 0.0)
+                            for (int c = 0; c < d; ++c) {
+                                const int bc = dig_at(ad, c);
+                                if (bc == 0) continue;
+                                double dv = a * (double)bc;
+                                for (int k = 0; k < d; ++k) dv *= powi(y[k], dig_at(ad, k) - (k == c ? 1 : 0));
+                                gq[c] += dv;
+                            }
+                    }
                 }
             }
-            jb.out[Q.perm[qpos]] = gl + gsum;
+            const int dst = Q.perm[qpos];
+            jb.out[dst] = gl + gsum;
+            if (GR) {
+                if (jb.outH) jb.outH[dst] = -(xl + xsum) / jb.h;
+                if (jb.outQ)
+                    for (int c = 0; c < d; ++c) jb.outQ[(size_t)dst * d + c] = s * gq[c];
+            }
         }
         __syncthreads();
     }
@@ -1206,13 +1442,16 @@ constexpr int kLocalGrid = 2048;
 }  // namespace
 
 dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int nh, double eps, int precision,
-                          int force, int profile, double *G, dfgt_stats *stats_out, hipStream_t st) {
+                          int force, int profile, double *G, const GradOut *grad, dfgt_stats *stats_out,
+                          hipStream_t st) {
     Workspace &w = g_ws;
     Profiler &prof = g_prof;
     const DevTree &Qv = Qh->host_view;
     const int MQ = (int)Qh->m, P = Qh->P, pmax = Qh->pmax, d = Qh->d;
     const int NQ = (int)Qh->n;
     const bool mono = Qh == Rh;
+    const bool gr = grad != nullptr;
+    const int PW = gr ? 2 * P : P;  // local-moment row: L, then (gradient mode) its tangent
     // A tolerance below the mixed-precision rounding budget needs FP64 leaf sums.
     if (precision == DFGT_PREC_MIXED && eps > 0.0 && eps < 2e-5) precision = DFGT_PREC_FP64;
     // Rounding budget of the exhaustive sums (the global-error theorem takes
@@ -1235,6 +1474,8 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         j.qoff = (long long)k * NQ;
         j.noff = (long long)k * MQ;
         j.out = G + (size_t)k * NQ;
+        j.outH = gr && grad->dGdh ? grad->dGdh + (size_t)k * NQ : nullptr;
+        j.outQ = gr && grad->dGdq ? grad->dGdq + (size_t)k * NQ * d : nullptr;
         j.mono = mono ? 1 : 0;
         j.pad = 0;
     }
@@ -1244,7 +1485,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     DFGT_HIP(hipMemcpyAsync(w.jobs.p, jobs.data(), sizeof(Job) * nh, hipMemcpyHostToDevice, st));
     DFGT_HIP(hipMemcpyAsync(w.trees.p, tv, sizeof(tv), hipMemcpyHostToDevice, st));
     const size_t nna = (size_t)nh * MQ;
-    DFGT_TRY(grow<double>(w.L, nna * P));
+    DFGT_TRY(grow<double>(w.L, nna * PW));
     DFGT_TRY(grow<unsigned char>(w.lflag, nna));
     DFGT_TRY(grow<int>(w.heads, 3 * nna));
     DFGT_TRY(grow<int>(w.cnt, C_N * CP));
@@ -1256,6 +1497,10 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     // a query leaf's own local ops are applied inside k_leaf when its per-wave
     // scratch fits; otherwise they go through the node kernels
     const bool leaf_local = P <= 512;
+    if (gr && !leaf_local) {
+        set_error("dfgt_gauss_sum_grad: gradients need p_max^d <= 512");
+        return DFGT_EINVAL;
+    }
     // every level splits Q and R wherever they can split, so no pair survives
     // more levels than the deeper tree has
     const int nlev = std::max(Qh->depth, Rh->depth);
@@ -1286,7 +1531,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         DFGT_TRY(grow<Op>(w.lops, cap.lop));
         if (leaf_local) {
             DFGT_TRY(grow<int>(w.lopnode, cap.lop));
-            DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * P));
+            DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * PW));
         }
         DFGT_HIP(hipMemsetAsync(w.lflag.p, 0, nna, st));
         DFGT_HIP(hipMemsetAsync(w.heads.p, 0xff, sizeof(int) * 3 * nna, st));
@@ -1307,7 +1552,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                       w.stats.as<unsigned long long>(),     cap};
             hipEvent_t ev = prof.start(st);
             hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
-                               k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, nh, force,
+                               k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, nh, force, gr ? 1 : 0,
                                leaf_local ? 1 : 0, w.dec.as<int>(), o);
             DFGT_HIP(hipGetLastError());
             prof.stop(K_TRAV, ev, st);
@@ -1318,14 +1563,25 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
             if (leaf_local) {
                 hipLaunchKernelGGL(k_lop_owner, dim3(kLocalGrid), dim3(64), 0, st, w.lgrp.as<Group>(), w.cnt.as<int>(),
                                    w.flag.as<int>(), w.lopnode.as<int>());
-                const size_t wstride = 2 * (size_t)P + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax;
-                const size_t sh = sizeof(double) * ((size_t)P + (10 * (size_t)P + 7) / 8 + 4 * wstride);
-                hipLaunchKernelGGL(k_lops, dim3(kLocalGrid), dim3(256), sh, st, td, jd, w.lgrp.as<Group>(),
+                // waves per block: as many (up to 4) as the LDS allows
+                const size_t wstride = lop_wave_stride(P, d, pmax, gr ? 1 : 0);
+                int lwv = 4;
+                size_t sh = 0;
+                for (;; lwv >>= 1) {
+                    sh = sizeof(double) * ((size_t)P + (10 * (size_t)P + 7) / 8 + (size_t)lwv * wstride);
+                    if (sh <= 64 * 1024 || lwv == 1) break;
+                }
+                if (sh > 64 * 1024) {
+                    set_error("dfgt_gauss_sum: p_max^d too large for the local-op kernel");
+                    return DFGT_EINVAL;
+                }
+                auto klo = gr ? k_lops<true> : k_lops<false>;
+                hipLaunchKernelGGL(klo, dim3(kLocalGrid), dim3(64 * lwv), sh, st, td, jd, w.lgrp.as<Group>(),
                                    w.lops.as<Op>(), w.lopnode.as<int>(), w.cnt.as<int>(), w.flag.as<int>(),
                                    w.part.as<double>());
-                hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(64), sizeof(double) * P, st, jd, td,
+                hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(64), sizeof(double) * PW, st, jd, td,
                                    w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
-                                   w.lops.as<Op>(), w.part.as<double>(), w.L.as<double>(),
+                                   w.lops.as<Op>(), w.part.as<double>(), PW, w.L.as<double>(),
                                    w.lflag.as<unsigned char>());
             } else {
                 DFGT_TRY(grow<double>(w.lscr, (size_t)kLocalGrid * 3 * P));
@@ -1339,16 +1595,16 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         }
         // everything per query leaf
         {
+            const int g1 = gr ? 1 : 0;
             int nthr = 256;
-            while (nthr > 64 && sizeof(double) * (size_t)nthr * d * (pmax + 1) > 40 * 1024) nthr >>= 1;
-            const size_t base = sizeof(double) * ((size_t)nthr + d * (pmax - 1) + 1 + (size_t)nthr * d * pmax +
-                                                  (size_t)nthr * d);
+            while (nthr > 64 && sizeof(double) * leaf_lds_base(nthr, d, pmax, g1) > 40 * 1024) nthr >>= 1;
+            const size_t base = sizeof(double) * leaf_lds_base(nthr, d, pmax, g1);
             const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
-            const size_t lds_acc = sizeof(double) * (2 * (size_t)P + (size_t)pmax * pmax);
+            const size_t lds_acc = sizeof(double) * (2 * (size_t)PW + (size_t)pmax * pmax);
             const bool acc_lds = base + lds_acc + lds_dig <= 64 * 1024;
             double *scr = nullptr;
             if (!acc_lds) {
-                DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 2 * P));
+                DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 2 * PW));
                 scr = w.pscr.as<double>();
             }
             const size_t sh = base + (acc_lds ? lds_acc : sizeof(double) * (size_t)pmax * pmax) + lds_dig;
@@ -1357,7 +1613,8 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                 return DFGT_EINVAL;
             }
             hipEvent_t ev = prof.start(st);
-            hipLaunchKernelGGL(k_leaf, dim3(Qv.nleaves, nh), dim3(nthr), sh, st, td, jd, w.egrp.as<Group>(),
+            auto kl = gr ? k_leaf<true> : k_leaf<false>;
+            hipLaunchKernelGGL(kl, dim3(Qv.nleaves, nh), dim3(nthr), sh, st, td, jd, w.egrp.as<Group>(),
                                w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
                                w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
                                precision, acc_lds ? 1 : 0, leaf_local ? 1 : 0, w.flag.as<int>(),

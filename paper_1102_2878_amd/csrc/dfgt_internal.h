@@ -150,9 +150,20 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
 // moments.hip
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st);
 // dfgt.hip
+// Gradient mode outputs (device, [n_h][N_Q] and [n_h][N_Q][d], caller order; either may be null).
+struct GradOut {
+    double *dGdh;
+    double *dGdq;
+};
 dfgt_status run_gauss_sum(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps,
-                          int precision, int force, int profile, double *G, dfgt_stats *stats,
-                          hipStream_t st);
+                          int precision, int force, int profile, double *G, const GradOut *grad,
+                          dfgt_stats *stats, hipStream_t st);
+
+// sweep.hip
+dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps, int precision,
+                         int force, const double *dG, double *dh_host, double *dq, hipStream_t st);
+dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, int variant,
+                     double *cv, double *dcv, dfgt_stats *stats, hipStream_t st);
 
 int default_pmax(int d);
 

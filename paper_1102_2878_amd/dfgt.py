@@ -68,8 +68,15 @@ def lib():
         L.dfgt_naive_sum.argtypes = [vp, i64, vp, i64, i32, C.POINTER(dbl), i32, i32, vp, vp]
         L.dfgt_gauss_sum.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp,
                                      C.POINTER(Stats), vp]
+        L.dfgt_gauss_sum_grad.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp, vp, vp,
+                                          C.POINTER(Stats), vp]
+        L.dfgt_gauss_sum_backward.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp,
+                                              C.POINTER(dbl), vp, vp]
+        L.dfgt_lscv_score.argtypes = [vp, C.POINTER(dbl), i32, dbl, i32, C.POINTER(Options), C.POINTER(dbl),
+                                      C.POINTER(dbl), C.POINTER(Stats), vp]
         for nm in ("dfgt_build_tree", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
-                   "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum"):
+                   "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
+                   "dfgt_gauss_sum_backward", "dfgt_lscv_score"):
             getattr(L, nm).restype = C.c_int
         _lib = L
     return _lib
@@ -191,3 +198,58 @@ def gauss_sum(Q: Tree, R: Tree, h, eps, precision=PREC_MIXED, force_method=FORCE
     _check(lib().dfgt_gauss_sum(Q.handle, R.handle, hp, hv.shape[0], float(eps), C.byref(o),
                                 C.c_void_p(out.data_ptr()), C.byref(st) if st is not None else None, _stream()))
     return (out, st.as_dict()) if stats else out
+
+
+def _vp(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def gauss_sum_grad(Q: Tree, R: Tree, h, eps, dh=True, dq=True, precision=PREC_MIXED, force_method=FORCE_NONE,
+                   stats=False):
+    """dfgt_gauss_sum_grad: G (n_h, NQ), dG/dh (n_h, NQ) or None, dG/dq (n_h, NQ, d) or None [, stats]."""
+    torch = _torch()
+    hv, hp = _hvec(h)
+    nh = hv.shape[0]
+    G = torch.empty((nh, Q.n), dtype=torch.float64, device="cuda")
+    Gh = torch.empty((nh, Q.n), dtype=torch.float64, device="cuda") if dh else None
+    Gq = torch.empty((nh, Q.n, Q.d), dtype=torch.float64, device="cuda") if dq else None
+    o = _opts(precision=precision, force_method=force_method)
+    st = Stats() if stats else None
+    _check(lib().dfgt_gauss_sum_grad(Q.handle, R.handle, hp, nh, float(eps), C.byref(o), _vp(G), _vp(Gh), _vp(Gq),
+                                     C.byref(st) if st is not None else None, _stream()))
+    return (G, Gh, Gq, st.as_dict()) if stats else (G, Gh, Gq)
+
+
+def gauss_sum_backward(Q: Tree, R: Tree, h, eps, dG, want_dh=True, want_dq=True, precision=PREC_MIXED,
+                       force_method=FORCE_NONE):
+    """dfgt_gauss_sum_backward: (dh numpy (n_h,) or None, dq CUDA tensor (NQ, d) or None)."""
+    torch = _torch()
+    hv, hp = _hvec(h)
+    nh = hv.shape[0]
+    dG = dG.to(dtype=torch.float64).contiguous()
+    if tuple(dG.shape) != (nh, Q.n) or not dG.is_cuda:
+        raise DfgtError(f"dG must be a float64 CUDA tensor of shape ({nh}, {Q.n})")
+    dh = np.empty(nh) if want_dh else None
+    dq = torch.empty((Q.n, Q.d), dtype=torch.float64, device="cuda") if want_dq else None
+    o = _opts(precision=precision, force_method=force_method)
+    _check(lib().dfgt_gauss_sum_backward(Q.handle, R.handle, hp, nh, float(eps), C.byref(o), _vp(dG),
+                                         dh.ctypes.data_as(C.POINTER(C.c_double)) if dh is not None else None,
+                                         _vp(dq), _stream()))
+    return dh, dq
+
+
+def lscv_score(R: Tree, h, eps, variant=1, grad=False, precision=PREC_MIXED, force_method=FORCE_NONE,
+               stats=False):
+    """dfgt_lscv_score: cv (n_h,) numpy [, dcv/dh (n_h,)] [, stats]."""
+    hv, hp = _hvec(h)
+    nh = hv.shape[0]
+    cv = np.empty(nh)
+    dcv = np.empty(nh) if grad else None
+    o = _opts(precision=precision, force_method=force_method)
+    st = Stats() if stats else None
+    _check(lib().dfgt_lscv_score(R.handle, hp, nh, float(eps), int(variant), C.byref(o),
+                                 cv.ctypes.data_as(C.POINTER(C.c_double)),
+                                 dcv.ctypes.data_as(C.POINTER(C.c_double)) if dcv is not None else None,
+                                 C.byref(st) if st is not None else None, _stream()))
+    out = (cv,) + ((dcv,) if grad else ()) + ((st.as_dict(),) if stats else ())
+    return out[0] if len(out) == 1 else out

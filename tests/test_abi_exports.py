@@ -24,7 +24,8 @@ def declared_symbols():
 
 def test_header_declares_the_boundary():
     syms = declared_symbols()
-    for required in ("dfgt_build_tree", "dfgt_gauss_sum", "dfgt_naive_sum", "dfgt_last_error", "dfgt_tree_free"):
+    for required in ("dfgt_build_tree", "dfgt_gauss_sum", "dfgt_naive_sum", "dfgt_last_error", "dfgt_tree_free",
+                     "dfgt_gauss_sum_grad", "dfgt_gauss_sum_backward", "dfgt_lscv_score"):
         assert required in syms
 
 
@@ -51,3 +52,15 @@ def test_invalid_arguments_are_rejected_on_the_host():
     hv = (ctypes.c_double * 1)(-1.0)
     rc = L.dfgt_naive_sum(ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, 2, hv, 1, 0, ctypes.c_void_p(16), None)
     assert rc == 1 and b"bandwidths" in L.dfgt_last_error()
+
+
+def test_new_entry_points_reject_null_handles():
+    L = dfgt.lib()
+    hv = (ctypes.c_double * 1)(1.0)
+    cv = (ctypes.c_double * 1)()
+    rc = L.dfgt_lscv_score(None, hv, 1, 1e-2, 1, None, cv, None, None, None)
+    assert rc == 1 and b"NULL" in L.dfgt_last_error()
+    rc = L.dfgt_gauss_sum_grad(None, None, hv, 1, 1e-2, None, None, None, None, None, None)
+    assert rc == 1 and b"NULL" in L.dfgt_last_error()
+    rc = L.dfgt_gauss_sum_backward(None, None, hv, 1, 1e-2, None, None, None, None, None)
+    assert rc == 1 and b"NULL" in L.dfgt_last_error()
