@@ -92,7 +92,9 @@ typedef struct dfgt_stats {
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (exhaustive leaf-leaf sums of DFGTBase,
      * far-field evaluation, local-to-local walk, local evaluation, combine),
-     * [2] unused, [3] local-moment accumulation (D and T ops), [4] unused. */
+     * [2] exhaustive leaf-leaf sums on the matrix cores (D >= 8, mixed
+     * precision; [1] then skips them), [3] local-moment accumulation (D and T
+     * ops), [4] unused. */
     double kernel_ms[5];
     int64_t kernel_launches[5];
 } dfgt_stats;

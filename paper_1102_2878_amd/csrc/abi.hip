@@ -102,6 +102,7 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
         v.x = t->x.as<double>();
         v.perm = t->perm.as<int32_t>();
         v.mu = t->mu.as<double>();
+        v.nrm = t->nrm.as<double>();
         t->host_view = v;
         s = t->view.reserve(sizeof(DevTree));
         if (s == DFGT_OK) {

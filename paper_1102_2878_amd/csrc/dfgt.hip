@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "etile.h"
 #include "series.h"
 
 namespace dfgt {
@@ -1066,7 +1067,9 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const int *__restrict__ headL, const double *__restrict__ L,
                                               const unsigned char *__restrict__ lflag, int precision, int acc_in_lds,
                                               int leaf_local, const int *__restrict__ overflow,
-                                              const double *__restrict__ part, double *__restrict__ gscratch) {
+                                              const double *__restrict__ part, double *__restrict__ gscratch,
+                                              const double *__restrict__ extE, const double *__restrict__ extX,
+                                              const double *__restrict__ extY) {
     extern __shared__ double smem[];
     if (*overflow) return;
     __shared__ int path[256];
@@ -1194,7 +1197,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             for (int k = 0; k < d; ++k) gq[k] = 0.0;
         if (tid == 0) {
             st_phase = 0;
-            st_gi = headE[hq];
+            st_gi = extE ? -1 : headE[hq];  // exhaustive sums computed by k_emfma
             st_pi = plen - 1;
         }
         __syncthreads();
@@ -1359,11 +1362,237 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 }
             }
             const int dst = Q.perm[qpos];
+            const size_t ei = (size_t)job * Q.n + qpos;
+            if (extE) gsum += extE[ei];
             jb.out[dst] = gl + gsum;
             if (GR) {
+                if (extE) {
+                    xsum += extX[ei];
+                    for (int c = 0; c < d; ++c) gq[c] += extY[ei * d + c];
+                }
                 if (jb.outH) jb.outH[dst] = -(xl + xsum) / jb.h;
                 if (jb.outQ)
                     for (int c = 0; c < d; ++c) jb.outQ[(size_t)dst * d + c] = s * gq[c];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- exhaustive tiles on the matrix cores
+// D >= 8, mixed precision (see etile.h).  One block of 4 waves per (query
+// leaf, job): the leaf's E chain is flattened 256 ops at a time (in parallel,
+// with a block-wide scan of their 16-point block counts); the waves take the
+// reference blocks round-robin and hold up to 4 query blocks of 16 as MFMA
+// fragments (larger leaves repeat the walk per group of 64 queries).  Per
+// query (tree order) it writes G_E = sum e, and with GR also X_E and Y_E (the
+// quantities k_leaf defines) to GE, GX, GY, which k_leaf adds to the rest.
+// Groups flagged by the underflow guard take FP64 exponentials.
+constexpr int kEChunk = 256;
+constexpr int kMaxEGrp = 256;
+
+template <bool GR, int NC>
+__global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                               const Group *__restrict__ egrp, const int *__restrict__ eops,
+                                               const int *__restrict__ headE, const int *__restrict__ overflow,
+                                               double *__restrict__ GE, double *__restrict__ GX,
+                                               double *__restrict__ GY) {
+    constexpr int NT = (NC + 3) / 4;  // 16-dimension tiles of the gradient product
+    __shared__ int gS[kMaxEGrp], gC[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
+    __shared__ int oB[kEChunk], oN[kEChunk], oF[kEChunk], oCum[kEChunk];
+    __shared__ int wsum[4], ngrp_s, nops_s;
+    __shared__ double red[4][2][64];
+    __shared__ double redY[GR ? 4 * NT * 256 : 1];
+    if (*overflow) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4;
+    const int job = blockIdx.y;
+    const Job jb = jobs[job];
+    const DevTree &Q = trees[jb.qt];
+    const DevTree &R = trees[jb.rt];
+    const int leaf = Q.leaves[blockIdx.x];
+    const int d = Q.d, NQ = Q.n;
+    const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
+    const size_t hq = (size_t)jb.noff + leaf;
+    const double sc2 = jb.sig * jb.sig;  // t = sc2 |q - r|^2, e = 2^-t
+    if (tid == 0) {
+        int n = 0, tot = 0;
+        for (int gi = headE[hq]; gi >= 0 && n < kMaxEGrp; gi = egrp[gi].next) {
+            const Group gg = egrp[gi];
+            gS[n] = gg.start;
+            gC[n] = gg.count;
+            gF[n] = gg.flags;
+            tot += gg.count;
+            gCum[n++] = tot;
+        }
+        ngrp_s = n;
+        nops_s = tot;
+    }
+    __syncthreads();
+    const int nops = nops_s;
+    for (int qg = 0; qg < nq; qg += 64) {
+        double qf[4][NC], qnv[4];
+        bool qok[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int nv = min(16, nq - qg - 16 * b);
+            qok[b] = nv > 0;
+            if (qok[b]) {
+                load_frag<NC>(Q.x, qb0 + qg + 16 * b, nv, d, qf[b]);
+                qnv[b] = Q.nrm[qb0 + qg + 16 * b + min(lane & 15, nv - 1)];
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) qf[b][c] = 0.0;
+                qnv[b] = 0.0;
+            }
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0}, at[4] = {0.0, 0.0, 0.0, 0.0};
+        float ps[4] = {0.0f, 0.0f, 0.0f, 0.0f}, pt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        v4d accY[4][NT];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) accY[b][nt] = v4d{0.0, 0.0, 0.0, 0.0};
+        int nblk = 0;
+        for (int o0 = 0; o0 < nops; o0 += kEChunk) {
+            __syncthreads();
+            // flatten ops o0 .. o0 + 255: reference range and 16-point block count
+            const int o = o0 + tid;
+            int nb = 0;
+            if (o < nops) {
+                int gi = 0;
+                while (o >= gCum[gi]) ++gi;
+                const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
+                const int rb = R.begin[r], rn = R.end[r] - rb;
+                oB[tid] = rb;
+                oN[tid] = rn;
+                oF[tid] = gF[gi];
+                nb = (rn + 15) >> 4;
+            }
+            const int inc = wave_incl_scan(nb);
+            if (lane == 63) wsum[wv] = inc;
+            __syncthreads();
+            int pre = 0;
+            for (int w = 0; w < wv; ++w) pre += wsum[w];
+            oCum[tid] = pre + inc;
+            __syncthreads();
+            const int nopc = min(kEChunk, nops - o0);
+            const int tb = oCum[nopc - 1];
+            int op = 0;
+            for (int blk = wv; blk < tb; blk += 4) {
+                while (blk >= oCum[op]) ++op;
+                const int lb = blk - (op ? oCum[op - 1] : 0);
+                const int r0 = oB[op] + 16 * lb, nv = min(16, oN[op] - 16 * lb);
+                const bool f64 = oF[op] != 0;
+                double rf[NC];
+                load_frag<NC>(R.x, r0, nv, d, rf);
+                double rnv[4];
+                bool rok[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int j = 4 * k + g;
+                    rok[k] = j < nv;
+                    rnv[k] = R.nrm[r0 + min(j, nv - 1)];
+                }
+                double b2[NT][4];
+                if (GR) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int c2 = 0; c2 < 4; ++c2) {
+                            const int row = r0 + min(4 * c2 + g, nv - 1), dim = 16 * nt + (lane & 15);
+                            b2[nt][c2] = dim < d ? R.x[(size_t)row * d + dim] : 0.0;
+                        }
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (!qok[b]) continue;
+                    const v4d dt = block_dots<NC>(rf, qf[b]);
+                    double ev[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double t = fmax(fma(-2.0, dt[k], qnv[b] + rnv[k]), 0.0) * sc2;
+                        if (f64) {
+                            const double e = rok[k] ? exp(-t * kLn2) : 0.0;
+                            acc[b] += e;
+                            if (GR) at[b] = fma(t, e, at[b]);
+                            ev[k] = e;
+                        } else {
+                            const float e = rok[k] ? __builtin_amdgcn_exp2f(-(float)t) : 0.0f;
+                            // gradient mode: the sum of the kernel values multiplies x_q
+                            // in Y = x_q sum e - sum e x_r, so it is taken in FP64 like
+                            // the matrix-core sums of e x_r (FP32 partials would leave a
+                            // mismatch amplified by |x_q| / |q - r|)
+                            if (GR) acc[b] += (double)e;
+                            else ps[b] += e;
+                            if (GR) pt[b] = fmaf((float)t, e, pt[b]);
+                            ev[k] = (double)e;
+                        }
+                    }
+                    if (GR) {
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                            for (int c2 = 0; c2 < 4; ++c2)
+                                accY[b][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ev[c2], b2[nt][c2], accY[b][nt],
+                                                                                   0, 0, 0);
+                    }
+                }
+                if (++nblk == 16) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        acc[b] += (double)ps[b];
+                        ps[b] = 0.0f;
+                        at[b] += (double)pt[b];
+                        pt[b] = 0.0f;
+                    }
+                    nblk = 0;
+                }
+            }
+        }
+        // this query group: lane groups, then waves, in a fixed order
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            double v = acc[b] + (double)ps[b], vt = at[b] + (double)pt[b];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            vt += __shfl_xor(vt, 16, 64);
+            vt += __shfl_xor(vt, 32, 64);
+            if (g == 0) {
+                red[wv][0][16 * b + lane] = v;
+                red[wv][1][16 * b + lane] = vt;
+            }
+        }
+        if (GR) {
+            for (int w = 0; w < 4; ++w) {
+                if (wv == w) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double &dst = redY[(b * NT + nt) * 256 + r * 64 + lane];
+                                dst = w == 0 ? accY[b][nt][r] : dst + accY[b][nt][r];
+                            }
+                }
+                __syncthreads();
+            }
+        } else {
+            __syncthreads();
+        }
+        if (tid < 64 && qg + tid < nq) {
+            const int pos = qb0 + qg + tid;
+            const double ge = ((red[0][0][tid] + red[1][0][tid]) + red[2][0][tid]) + red[3][0][tid];
+            GE[(size_t)job * NQ + pos] = ge;
+            if (GR) {
+                const double gt = ((red[0][1][tid] + red[1][1][tid]) + red[2][1][tid]) + red[3][1][tid];
+                GX[(size_t)job * NQ + pos] = -2.0 * kLn2 * gt;
+                const int b = tid >> 4, i = tid & 15;
+                const double *xq = Q.x + (size_t)pos * d;
+                for (int k = 0; k < d; ++k) {
+                    const double sy = redY[(b * NT + (k >> 4)) * 256 + (i >> 2) * 64 + 16 * (i & 3) + (k & 15)];
+                    GY[((size_t)job * NQ + pos) * d + k] = -2.0 * jb.s * fma(xq[k], ge, -sy);
+                }
             }
         }
         __syncthreads();
@@ -1425,11 +1654,11 @@ struct Profiler {
 thread_local Profiler g_prof;
 
 // kernel_ms slots of dfgt_stats
-enum { K_TRAV = 0, K_LEAF = 1, K_LOCAL = 3, K_POST = 4 };
+enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_POST = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, L, lflag, heads, segA, segB, pairA, pairB, dec, egrp, eops, fgrp, fops, lgrp, lops, lnodes,
-        cnt, lvl, flag, stats, lscr, pscr, lopnode, part;
+        cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
 };
 thread_local Workspace g_ws;
@@ -1438,6 +1667,24 @@ template <class T> dfgt_status grow(DevBuf &b, size_t n) { return b.reserve(size
 
 constexpr int kTravGrid = 8192;  // waves per traversal level (grid-stride over segments)
 constexpr int kLocalGrid = 2048;
+
+template <bool GR>
+void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd, const Group *egrp,
+                  const int *eops, const int *headE, const int *flag, double *GE, double *GX, double *GY) {
+#define DFGT_EMFMA(NCV)                                                                                         \
+    hipLaunchKernelGGL((k_emfma<GR, NCV>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, GE, GX, GY); \
+    break;
+    switch (nc) {
+    case 2: DFGT_EMFMA(2)
+    case 3: DFGT_EMFMA(3)
+    case 4: DFGT_EMFMA(4)
+    case 5: DFGT_EMFMA(5)
+    case 6: DFGT_EMFMA(6)
+    case 7: DFGT_EMFMA(7)
+    default: DFGT_EMFMA(8)
+    }
+#undef DFGT_EMFMA
+}
 
 }  // namespace
 
@@ -1505,6 +1752,19 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     // more levels than the deeper tree has
     const int nlev = std::max(Qh->depth, Rh->depth);
     DFGT_TRY(grow<int>(w.lvl, (size_t)(nlev + 1) * 2 * CP));
+    // exhaustive leaf sums on the matrix cores: mixed precision, D >= 8, and
+    // s^2 (|q|^2 + |r|^2) <= 2^26 for every bandwidth (rounding of the
+    // expanded squared distance below ~1e-7)
+    bool emfma = precision == DFGT_PREC_MIXED && d >= 8 && d <= 32 && nlev <= kMaxEGrp;
+    for (int k = 0; k < nh && emfma; ++k)
+        emfma = jobs[k].sig * jobs[k].sig * (Qh->max_nrm + Rh->max_nrm) <= 67108864.0;
+    if (emfma) {
+        DFGT_TRY(grow<double>(w.extE, (size_t)nh * NQ));
+        if (gr) {
+            DFGT_TRY(grow<double>(w.extX, (size_t)nh * NQ));
+            DFGT_TRY(grow<double>(w.extY, (size_t)nh * NQ * d));
+        }
+    }
 
     Caps &cap = w.cap;
     if (cap.pair == 0) cap = Caps{1 << 19, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 18, 1 << 18};
@@ -1556,6 +1816,15 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                                leaf_local ? 1 : 0, w.dec.as<int>(), o);
             DFGT_HIP(hipGetLastError());
             prof.stop(K_TRAV, ev, st);
+        }
+        if (emfma) {
+            hipEvent_t ev = prof.start(st);
+            auto fn = gr ? launch_emfma<true> : launch_emfma<false>;
+            fn((d + 3) / 4, dim3(Qv.nleaves, nh), st, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
+               w.flag.as<int>(), w.extE.as<double>(), gr ? w.extX.as<double>() : nullptr,
+               gr ? w.extY.as<double>() : nullptr);
+            DFGT_HIP(hipGetLastError());
+            prof.stop(K_EMFMA, ev, st);
         }
         // local moments: every D / T op in parallel, then per internal node
         {
@@ -1618,7 +1887,10 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                                w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
                                w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
                                precision, acc_lds ? 1 : 0, leaf_local ? 1 : 0, w.flag.as<int>(),
-                               leaf_local ? w.part.as<double>() : (const double *)nullptr, scr);
+                               leaf_local ? w.part.as<double>() : (const double *)nullptr, scr,
+                               emfma ? w.extE.as<double>() : (const double *)nullptr,
+                               emfma && gr ? w.extX.as<double>() : (const double *)nullptr,
+                               emfma && gr ? w.extY.as<double>() : (const double *)nullptr);
             DFGT_HIP(hipGetLastError());
             prof.stop(K_LEAF, ev, st);
         }

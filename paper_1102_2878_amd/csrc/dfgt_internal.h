@@ -88,6 +88,7 @@ struct DevTree {
     const double *x;                      // [n][d] points in tree order (FP64)
     const int32_t *perm;                  // [n] tree position -> caller index
     const double *mu;                     // [m][P] raw far-field moments
+    const double *nrm;                    // [n] squared norms |x|^2 in tree order
 };
 
 }  // namespace dfgt
@@ -98,7 +99,8 @@ struct dfgt_tree_s {
     int32_t d = 0, leaf = 32, pmax = 1, P = 1, depth = 0, precision = 0, force = 0;
     int64_t m = 0, nleaves = 0;
     std::vector<int32_t> level_start;  // host copy: nodes of level l are [level_start[l], level_start[l+1])
-    dfgt::DevBuf lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu;
+    dfgt::DevBuf lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max;
+    double max_nrm = 0.0;  // max |x|^2 (valid after dfgt_build_tree returns)
     dfgt::DevBuf view;  // a DevTree in device memory
     dfgt::DevTree host_view{};
 };

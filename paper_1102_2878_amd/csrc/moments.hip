@@ -93,7 +93,31 @@ __global__ __launch_bounds__(256) void k_f2f(int lb, int le, const int32_t *__re
 
 }  // namespace
 
+// Squared norms of the points (tree order) and their maximum (ordered-int max
+// of non-negative doubles); the matrix-core exhaustive tiles read them.
+__global__ void k_tree_sqnorm(const double *__restrict__ x, int n, int d, double *__restrict__ out,
+                              unsigned long long *__restrict__ mx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        for (int k = 0; k < d; ++k) v = fma(x[(size_t)i * d + k], x[(size_t)i * d + k], v);
+        out[i] = v;
+    }
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, (unsigned long long)__double_as_longlong(v));
+}
+
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
+    {
+        const int n = (int)t->n;
+        DFGT_TRY(t->nrm.reserve(sizeof(double) * (size_t)n));
+        DFGT_TRY(t->nrm_max.reserve(sizeof(unsigned long long)));
+        DFGT_HIP(hipMemsetAsync(t->nrm_max.p, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_tree_sqnorm, dim3((n + 255) / 256), dim3(256), 0, st, t->x.as<double>(), n, t->d,
+                           t->nrm.as<double>(), t->nrm_max.as<unsigned long long>());
+        DFGT_HIP(hipGetLastError());
+        DFGT_HIP(hipMemcpyAsync(&t->max_nrm, t->nrm_max.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     const int d = t->d, pmax = t->pmax, P = t->P;
     const int64_t m = t->m;
     DFGT_TRY(t->mu.reserve(sizeof(double) * (size_t)m * P));

@@ -8,7 +8,11 @@
 // once to FP32 for the hardware exp2, summed in FP32 over at most 64 points and
 // then in FP64.  Partial sums per chunk are reduced in chunk order, so results
 // are bitwise reproducible.
-#include "dfgt_internal.h"
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "etile.h"
 
 namespace dfgt {
 namespace {
@@ -154,6 +158,104 @@ __global__ __launch_bounds__(kBlock) void k_naive_fp64(const double *__restrict_
     if (qi < nq) part[((size_t)hz * nchunks + blockIdx.y) * nq + qi] = acc;
 }
 
+// Matrix-core kernel for D >= 8 (see etile.h): a block of 4 waves holds 64
+// queries (4 blocks of 16) as MFMA fragments; its waves take the 16-point
+// reference blocks of the block's chunk round-robin.  Per lane: query
+// l % 16 of each query block against references 4r + g of each reference
+// block; FP32 partials over 16 reference blocks (64 terms), then FP64; the
+// lane groups and the waves are added in a fixed order.
+template <int NC>
+__global__ __launch_bounds__(256) void k_naive_mfma(const double *__restrict__ q, const double *__restrict__ qn,
+                                                    int nq, const double *__restrict__ r,
+                                                    const double *__restrict__ rn, int nr, int d,
+                                                    const double *__restrict__ hs, int fp64, int chunk_len,
+                                                    int nchunks, double *__restrict__ part) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4;
+    const int hz = blockIdx.z;
+    const double s = 1.0 / (1.4142135623730951 * hs[hz]);
+    const double sc = fp64 ? s : 1.2011224087864498 * s;  // mixed: 2^{-(sc |q-r|)^2}
+    const double sc2 = sc * sc;
+    const int q0 = blockIdx.x * 64;
+    double qf[4][NC], qnv[4];
+    bool qok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int rb = q0 + 16 * b, nv = min(16, nq - rb);
+        qok[b] = nv > 0;
+        if (qok[b]) {
+            load_frag<NC>(q, rb, nv, d, qf[b]);
+            qnv[b] = qn[rb + min(lane & 15, nv - 1)];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qf[b][c] = 0.0;
+            qnv[b] = 0.0;
+        }
+    }
+    const int rbeg = blockIdx.y * chunk_len;
+    const int rend = min(nr, rbeg + chunk_len);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    float ps[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int nblk = 0;
+    for (int r0 = rbeg + 16 * wv; r0 < rend; r0 += 64) {
+        const int nv = min(16, rend - r0);
+        double rf[NC];
+        load_frag<NC>(r, r0, nv, d, rf);
+        double rnv[4];
+        bool rok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = 4 * k + g;
+            rok[k] = j < nv;
+            rnv[k] = rn[r0 + min(j, nv - 1)];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (!qok[b]) continue;
+            const v4d dt = block_dots<NC>(rf, qf[b]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double t = fmax(fma(-2.0, dt[k], qnv[b] + rnv[k]), 0.0) * sc2;
+                if (fp64) acc[b] += rok[k] ? exp(-t) : 0.0;
+                else ps[b] += rok[k] ? __builtin_amdgcn_exp2f(-(float)t) : 0.0f;
+            }
+        }
+        if (++nblk == 16) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                acc[b] += (double)ps[b];
+                ps[b] = 0.0f;
+            }
+            nblk = 0;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        double v = acc[b] + (double)ps[b];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (g == 0) red[wv][16 * b + lane] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int qi = q0 + threadIdx.x;
+        const double v = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+        if (qi < nq) part[((size_t)hz * nchunks + blockIdx.y) * nq + qi] = v;
+    }
+}
+
+// Squared norms of n points and their maximum (ordered-int max of non-negative doubles).
+__global__ void k_sqnorm(const double *__restrict__ x, int n, int d, double *__restrict__ out,
+                         unsigned long long *__restrict__ mx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < n)
+        for (int k = 0; k < d; ++k) v = fma(x[(size_t)i * d + k], x[(size_t)i * d + k], v);
+    if (i < n) out[i] = v;
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, (unsigned long long)__double_as_longlong(v));
+}
+
 __global__ void k_reduce_chunks(const double *__restrict__ part, int nq, int nchunks, int nh,
                                 double *__restrict__ G) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -166,7 +268,43 @@ __global__ void k_reduce_chunks(const double *__restrict__ part, int nq, int nch
 
 // Workspace reused across calls on this thread (the brute force is a comparator,
 // called from one host thread at a time).
-thread_local DevBuf g_part, g_h;
+thread_local DevBuf g_part, g_h, g_qn, g_rn, g_mx;
+
+template <int NC>
+void launch_mfma(dim3 grid, hipStream_t st, const double *q, const double *qn, int nq, const double *r,
+                 const double *rn, int nr, int d, const double *hd, int fp64, int chunk_len, int nchunks,
+                 double *part) {
+    hipLaunchKernelGGL(k_naive_mfma<NC>, grid, dim3(256), 0, st, q, qn, nq, r, rn, nr, d, hd, fp64, chunk_len,
+                       nchunks, part);
+}
+
+// Norm tables for the matrix-core path (mixed precision only: FP64 sums keep
+// the exact-difference VALU kernels); *use is false when s^2 (|q|^2 + |r|^2)
+// could exceed 2^26 for the smallest bandwidth (rounding of the expanded
+// squared distance then above ~1e-7).
+dfgt_status prepare_mfma(const double *q, int nq, const double *r, int nr, int d, const double *h_host, int nh,
+                         int precision, hipStream_t st, bool *use) {
+    *use = false;
+    if (d < 8 || d > 32 || precision != DFGT_PREC_MIXED) return DFGT_OK;
+    DFGT_TRY(g_qn.reserve(sizeof(double) * nq));
+    DFGT_TRY(g_rn.reserve(sizeof(double) * nr));
+    DFGT_TRY(g_mx.reserve(2 * sizeof(unsigned long long)));
+    DFGT_HIP(hipMemsetAsync(g_mx.p, 0, 2 * sizeof(unsigned long long), st));
+    unsigned long long *mx = g_mx.as<unsigned long long>();
+    hipLaunchKernelGGL(k_sqnorm, dim3((nq + 255) / 256), dim3(256), 0, st, q, nq, d, g_qn.as<double>(), mx);
+    hipLaunchKernelGGL(k_sqnorm, dim3((nr + 255) / 256), dim3(256), 0, st, r, nr, d, g_rn.as<double>(), mx + 1);
+    DFGT_HIP(hipGetLastError());
+    unsigned long long hm[2];
+    DFGT_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    double hmin = h_host[0];
+    for (int k = 1; k < nh; ++k) hmin = std::fmin(hmin, h_host[k]);
+    double m0, m1;
+    std::memcpy(&m0, &hm[0], sizeof(double));
+    std::memcpy(&m1, &hm[1], sizeof(double));
+    *use = (m0 + m1) / (2.0 * hmin * hmin) * 1.5 <= 67108864.0;
+    return DFGT_OK;
+}
 
 }  // namespace
 
@@ -191,6 +329,35 @@ dfgt_status launch_naive(const double *q, int64_t nq64, const double *r, int64_t
     double *part = g_part.as<double>();
     const double *hd = g_h.as<double>();
     dim3 grid(bx, nchunks, nh);
+    bool mfma = false;
+    DFGT_TRY(prepare_mfma(q, nq, r, nr, d, h_host, nh, precision, st, &mfma));
+    if (mfma) {
+        const int mbx = (nq + 63) / 64;
+        int mch = (4096 + mbx * nh - 1) / (mbx * nh);
+        const int mmax = (nr + 63) / 64;
+        mch = std::max(1, std::min(mch, mmax));
+        int mlen = (nr + mch - 1) / mch;
+        mlen = (mlen + 63) / 64 * 64;
+        mch = (nr + mlen - 1) / mlen;
+        DFGT_TRY(g_part.reserve(sizeof(double) * (size_t)mch * nq * nh));
+        dim3 mg(mbx, mch, nh);
+        const int fp = precision == DFGT_PREC_FP64 ? 1 : 0;
+        const double *qn = g_qn.as<double>(), *rn = g_rn.as<double>();
+        double *mp = g_part.as<double>();
+        switch ((d + 3) / 4) {
+        case 2: launch_mfma<2>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        case 3: launch_mfma<3>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        case 4: launch_mfma<4>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        case 5: launch_mfma<5>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        case 6: launch_mfma<6>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        case 7: launch_mfma<7>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        default: launch_mfma<8>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
+        }
+        DFGT_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce_chunks, dim3((nq + 255) / 256, nh), dim3(256), 0, st, mp, nq, mch, nh, G);
+        DFGT_HIP(hipGetLastError());
+        return DFGT_OK;
+    }
     if (precision == DFGT_PREC_FP64) {
         size_t lds = sizeof(double) * (4096 / d) * d;
         hipLaunchKernelGGL(k_naive_fp64, grid, dim3(kBlock), lds, st, q, nq, r, nr, d, hd, chunk_len,

@@ -36,7 +36,7 @@ class Stats(C.Structure):
         "max_local_ops")] + [("reserved", C.c_int64 * 2),
                                                                        ("kernel_ms", C.c_double * 5),
                                                                        ("kernel_launches", C.c_int64 * 5)]
-    KERNELS = ("traverse", "leaf", "unused2", "local", "unused4")
+    KERNELS = ("traverse", "leaf", "emfma", "local", "unused4")
 
     def as_dict(self):
         d = {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm not in ("reserved", "kernel_ms",

@@ -156,3 +156,41 @@ def test_full_size_c2_sweep_sampled(dfgt):
         rel = _rel_err(G[k][rows], ref)
         assert rel.max() <= 1e-2, (h, rel.max())
         assert np.all(np.isfinite(G[k]))
+
+
+@pytest.mark.parametrize("d", [8, 12, 16, 20])
+def test_high_dimensions_matrix_core_tiles(dfgt, d):
+    """D >= 8 in mixed precision takes the exhaustive sums through the FP64
+    matrix cores (stats kernel slot 2); bandwidths from where nothing prunes
+    to where everything does, a ragged leaf size, and eps = 0."""
+    x = synth.c5(n=3000, seed=40 + d)
+    if d != 16:
+        rng = np.random.default_rng(d)
+        x = x[:, :min(d, 16)] if d < 16 else np.hstack([x, 0.1 * rng.standard_normal((x.shape[0], d - 16))])
+    x = np.ascontiguousarray(x)
+    hs = [synth.silverman_h(x) * s for s in (0.5, 1.0, 3.0, 30.0)]
+    for eps, leaf in ((1e-2, 32), (1e-4, 37), (0.0, 64)):
+        note(f"dfgt high-d d={d} eps={eps} leaf={leaf}")
+        R = dfgt.build_tree(cuda(x), leaf_size=leaf)
+        G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True, profile=True)
+        assert st["kernel_launches"]["emfma"] == 1
+        G = G.cpu().numpy()
+        for k, h in enumerate(hs):
+            rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+            assert rel.max() <= max(eps, 1e-5), (d, eps, h, rel.max())
+
+
+def test_high_dimension_bichromatic_and_fp64(dfgt):
+    x = synth.c5(n=2500, seed=51)
+    q = synth.bichromatic_queries(x, 51)[:1300]
+    hs = [synth.silverman_h(x) * s for s in (0.7, 2.0, 8.0)]
+    for precision, tol in ((0, 1e-4), (1, 1e-4)):
+        note(f"dfgt high-d bichromatic precision={precision}")
+        R = dfgt.build_tree(cuda(x), leaf_size=40)
+        Q = dfgt.build_tree(cuda(q), leaf_size=40)
+        G, st = dfgt.gauss_sum(Q, R, hs, tol, precision=precision, stats=True, profile=True)
+        assert st["kernel_launches"]["emfma"] == (1 if precision == 0 else 0)
+        G = G.cpu().numpy()
+        for k, h in enumerate(hs):
+            rel = _rel_err(G[k], oracle.naive_kde(q, x, h))
+            assert rel.max() <= tol, (precision, h, rel.max())

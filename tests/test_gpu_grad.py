@@ -247,3 +247,20 @@ def test_lscv_minimum_near_hstar(dfgt):
     assert 0 < k < len(hs) - 1
     assert hs[k - 1] <= hstar <= hs[k + 1]
     assert dcv[k - 1] <= 0.0 <= dcv[k + 1]
+
+
+@pytest.mark.parametrize("d", [8, 16, 20])
+def test_grad_high_dimensions(dfgt, d):
+    """Gradient mode with the matrix-core exhaustive tiles (their q-gradient
+    product E^T X on the matrix cores too), against the oracle."""
+    x = synth.c5(n=2500, seed=60 + d)
+    if d != 16:
+        rng = np.random.default_rng(d)
+        x = x[:, :d] if d < 16 else np.hstack([x, 0.1 * rng.standard_normal((x.shape[0], d - 16))])
+    x = np.ascontiguousarray(x)
+    hs = [synth.silverman_h(x) * s for s in (1.0, 3.0)]
+    note(f"grad high-d d={d}")
+    G, Gh, Gq, st = _grad(dfgt, x, None, hs, 0.0, 0, leaf=48)
+    _check(x, None, hs, G, Gh, Gq, 0.0, 0, f"d={d} eps=0")
+    G, Gh, Gq, st = _grad(dfgt, x, None, hs, 1e-4, 0, leaf=48)
+    _check(x, None, hs, G, Gh, Gq, 1e-4, 0, f"d={d} eps=1e-4")
