@@ -12,6 +12,13 @@ value = N_Q * N_R * 7 / (seconds per step)  [query x reference pairs / s].
 The plain tiled brute-force GPU sum (dfgt_naive_sum) over the same seven
 bandwidths is timed alongside.
 
+grad_ms (the metric's second part): the backward pass on the 16-D workload,
+200,000 points (8 latent clusters embedded + N(0, 0.01 I) noise), eps 1e-4,
+bandwidths {h_S, h*} (h* of its seeded 5,000-point subsample,
+tests/golden/hstar.json): dfgt_lscv_score with dCV/dh (sums at h and sqrt(2) h
+with their h-derivatives) plus dfgt_gauss_sum_backward for dG/dq, tree built
+once outside the timed region.
+
 Prints ONE JSON line.  --gpus must be 1 (this build targets one GPU).
 """
 from __future__ import annotations
@@ -45,6 +52,51 @@ def base_peak_pairs(d):
     return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
 
 
+def grad_bench(args, torch, dfgt, synth):
+    """Backward on the 16-D workload; returns (ms, details)."""
+    hj = json.load(open(os.path.join(ROOT, "tests", "golden", "hstar.json")))
+    x5 = synth.c5()
+    n5, d5 = x5.shape
+    hs5 = [synth.silverman_h(x5), hj["c5_sub5k"]["h_star"]]
+    eps5 = 1e-4
+    xd = torch.as_tensor(x5, device="cuda")
+    R = dfgt.build_tree(xd, leaf_size=args.grad_leaf)
+    dG = torch.full((len(hs5), n5), 1.0 / n5, dtype=torch.float64, device="cuda")
+
+    def one():
+        cv, dcv = dfgt.lscv_score(R, hs5, eps5, variant=1, grad=True)
+        dh, dq = dfgt.gauss_sum_backward(R, R, hs5, eps5, dG)
+        return cv, dcv, dq
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.grad_steps):
+        cv, dcv, dq = one()
+    torch.cuda.synchronize()
+    t_grad = (time.perf_counter() - t0) / args.grad_steps
+    # where the time goes: one profiled gradient-mode call over the four LSCV sums
+    hh = hs5 + [np.sqrt(2.0) * h for h in hs5]
+    _, _, _, st = dfgt.gauss_sum_grad(R, R, hh, eps5, dq=False, stats=True, profile=True)
+    em_ms = st["kernel_ms"]["emfma"]
+    pairs = st["base_point_pairs"]
+    # matrix-core roofline of the exhaustive tiles in gradient mode: per pair
+    # 2 D flops for q.r plus 2 D for the kernel-weighted reference sums
+    flops = pairs * 4.0 * d5
+    peak = 78.6e12
+    det = {
+        "workload": f"16-D clustered, {n5} points (Q = R), bandwidths h_S, h* (+ sqrt2 h for LSCV), eps {eps5}",
+        "h": hs5, "leaf_size": args.grad_leaf, "steps": args.grad_steps,
+        "cv": [float(v) for v in cv], "dcv_dh": [float(v) for v in dcv],
+        "lscv_grad_call": {"kernel_ms": st["kernel_ms"], "base_point_pairs": pairs, "node_pairs": st["node_pairs"]},
+        "roofline_emfma": {"bound": "mfma", "achieved": flops / (em_ms * 1e-3) / 1e12 if em_ms > 0 else None,
+                           "peak": peak / 1e12, "unit": "TFLOP/s",
+                           "frac": flops / (em_ms * 1e-3) / peak if em_ms > 0 else None,
+                           "flops_per_pair": 4 * d5, "dtype": "f64"},
+    }
+    return t_grad * 1e3, det
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +104,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the 16-D backward timing")
+    ap.add_argument("--grad-steps", type=int, default=3)
+    ap.add_argument("--grad-leaf", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -70,34 +125,35 @@ def main():
 
     def step(profile):
         t = dfgt.build_tree(x, leaf_size=LEAF)
-        G, st = dfgt.gauss_sum(t, t, hs, EPS, stats=True, profile=profile)
-        return G, st
+        if not profile:
+            return dfgt.gauss_sum(t, t, hs, EPS), None
+        return dfgt.gauss_sum(t, t, hs, EPS, stats=True, profile=True)
 
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
 
-    # timed region: K steps, HIP events recorded by the library on this stream
+    # timed region: K steps exactly as a caller runs them (no events, no stats)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        G, _ = step(False)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+
+    # the same steps with HIP events around every launch, for the per-kernel breakdown
     agg_ms = {}
     agg_launch = {}
     base_pairs = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        G, st = step(True)
+        _, st = step(True)
         for k, v in st["kernel_ms"].items():
             agg_ms[k] = agg_ms.get(k, 0.0) + v
             agg_launch[k] = agg_launch.get(k, 0) + st["kernel_launches"][k]
         base_pairs += st["base_point_pairs"]
     torch.cuda.synchronize()
-    t_step = (time.perf_counter() - t0) / args.steps
+    t_step_prof = (time.perf_counter() - t0) / args.steps
     stats = st
-
-    # the same steps without event recording, for the event overhead
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(False)
-    torch.cuda.synchronize()
-    t_step_noev = (time.perf_counter() - t0) / args.steps
 
     # build alone
     t0 = time.perf_counter()
@@ -157,7 +213,7 @@ def main():
         },
         "bruteforce_gpu": {"value": pairs / t_bf, "unit": "pairs/s", "ms_per_sweep": t_bf * 1e3},
         "speedup_vs_bruteforce": t_bf / t_step,
-        "phases_ms": {"build_tree": t_build * 1e3, "step_without_events": t_step_noev * 1e3,
+        "phases_ms": {"build_tree": t_build * 1e3, "step_with_events_and_stats": t_step_prof * 1e3,
                       **{f"kernel_{k}": v / args.steps for k, v in agg_ms.items() if not k.startswith("unused")}},
         "traversal": {k: stats[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
                                             "base_leaf_pairs", "base_point_pairs", "levels", "max_order",
@@ -165,6 +221,9 @@ def main():
         "roofline": roofline,
         "grad_ms": None,
     }
+
+    if not args.no_grad:
+        out["grad_ms"], out["grad"] = grad_bench(args, torch, dfgt, synth)
 
     if not args.no_cpu_baseline:
         import oracle

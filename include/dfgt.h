@@ -68,7 +68,14 @@ typedef struct dfgt_options {
                              launches on the caller's stream and reports the
                              per-kernel time in dfgt_stats (adds a few us per
                              launch); 0: off */
-    int32_t reserved[3];  /* must be zero */
+    float cost_exhaustive; /* weight of the exhaustive cost c_E = D N_Q N_R in
+                              ChooseBestMethod (Section 3.8) relative to the
+                              series costs; 0 = 1, the paper's model.  Smaller
+                              values reflect that an exhaustive pair costs less
+                              on the GPU than a series term.  Any value keeps
+                              the error guarantee (it only picks among methods
+                              whose bounds hold) */
+    int32_t reserved[2];  /* must be zero */
 } dfgt_options;
 
 /* Counters of one gauss_sum call (summed over its bandwidths). */

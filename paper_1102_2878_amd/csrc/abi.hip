@@ -61,7 +61,7 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
     DFGT_REQUIRE(d >= 1 && d <= kMaxD, "dfgt_build_tree: d must be in [1, 32]");
     dfgt_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 3; ++i) DFGT_REQUIRE(o.reserved[i] == 0, "dfgt_build_tree: reserved option field set");
+    for (int i = 0; i < 2; ++i) DFGT_REQUIRE(o.reserved[i] == 0, "dfgt_build_tree: reserved option field set");
     DFGT_REQUIRE(o.leaf_size >= 0 && o.leaf_size <= 4096, "dfgt_build_tree: leaf_size must be in [0, 4096]");
     DFGT_REQUIRE(o.p_max >= 0 && o.p_max <= 16, "dfgt_build_tree: p_max must be in [0, 16]");
     DFGT_REQUIRE(o.precision == DFGT_PREC_MIXED || o.precision == DFGT_PREC_FP64,
@@ -103,6 +103,8 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
         v.perm = t->perm.as<int32_t>();
         v.mu = t->mu.as<double>();
         v.nrm = t->nrm.as<double>();
+        v.lpath = t->lpath.as<int32_t>();
+        v.lplen = t->lplen.as<int32_t>();
         t->host_view = v;
         s = t->view.reserve(sizeof(DevTree));
         if (s == DFGT_OK) {
@@ -194,12 +196,16 @@ dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev,
 
 // Options of a summation call: precision and force default to the tree's.
 static dfgt_status call_options(const dfgt_tree_s *R, const dfgt_options *opt, const char *who, int *precision,
-                                int *force, int *profile) {
+                                int *force, int *profile, double *cost_e) {
     *precision = R->precision;
     *force = R->force;
     *profile = 0;
+    *cost_e = 1.0;
     if (opt) {
-        for (int i = 0; i < 3; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, std::string(who) + ": reserved option field set");
+        for (int i = 0; i < 2; ++i) DFGT_REQUIRE(opt->reserved[i] == 0, std::string(who) + ": reserved option field set");
+        DFGT_REQUIRE(std::isfinite(opt->cost_exhaustive) && opt->cost_exhaustive >= 0.0f,
+                     std::string(who) + ": cost_exhaustive must be finite and >= 0");
+        if (opt->cost_exhaustive > 0.0f) *cost_e = opt->cost_exhaustive;
         DFGT_REQUIRE(opt->precision == DFGT_PREC_MIXED || opt->precision == DFGT_PREC_FP64,
                      std::string(who) + ": unknown precision");
         DFGT_REQUIRE(opt->force_method >= 0 && opt->force_method <= 5, std::string(who) + ": unknown force_method");
@@ -224,9 +230,10 @@ dfgt_status dfgt_gauss_sum(dfgt_tree Q, dfgt_tree R, const double *h_host, int32
     DFGT_TRY(check_pair(Q, R, eps, "dfgt_gauss_sum"));
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum"));
     int precision, force, profile;
-    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum", &precision, &force, &profile));
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum", &precision, &force, &profile, &cost_e));
     DFGT_REQUIRE(profile == 0 || stats != nullptr, "dfgt_gauss_sum: profile needs a stats pointer");
-    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, G_dev, nullptr, stats,
+    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, cost_e, G_dev, nullptr, stats,
                          (hipStream_t)stream);
     DFGT_GUARD_END
 }
@@ -240,10 +247,11 @@ dfgt_status dfgt_gauss_sum_grad(dfgt_tree Q, dfgt_tree R, const double *h_host, 
     DFGT_TRY(check_pair(Q, R, eps, "dfgt_gauss_sum_grad"));
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum_grad"));
     int precision, force, profile;
-    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum_grad", &precision, &force, &profile));
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum_grad", &precision, &force, &profile, &cost_e));
     DFGT_REQUIRE(profile == 0 || stats != nullptr, "dfgt_gauss_sum_grad: profile needs a stats pointer");
     GradOut go{dGdh_dev, dGdq_dev};
-    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, G_dev, &go, stats,
+    return run_gauss_sum(Q, R, h_host, n_h, eps, precision, force, profile, cost_e, G_dev, &go, stats,
                          (hipStream_t)stream);
     DFGT_GUARD_END
 }
@@ -257,8 +265,10 @@ dfgt_status dfgt_gauss_sum_backward(dfgt_tree Q, dfgt_tree R, const double *h_ho
     DFGT_TRY(check_pair(Q, R, eps, "dfgt_gauss_sum_backward"));
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_gauss_sum_backward"));
     int precision, force, profile;
-    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum_backward", &precision, &force, &profile));
-    return run_backward(Q, R, h_host, n_h, eps, precision, force, dG_dev, dh_host, dq_dev, (hipStream_t)stream);
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_gauss_sum_backward", &precision, &force, &profile, &cost_e));
+    return run_backward(Q, R, h_host, n_h, eps, precision, force, cost_e, dG_dev, dh_host, dq_dev,
+                        (hipStream_t)stream);
     DFGT_GUARD_END
 }
 
@@ -273,9 +283,11 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_lscv_score"));
     DFGT_REQUIRE(n_h <= 32767, "dfgt_lscv_score: n_h must be <= 32767");
     int precision, force, profile;
-    DFGT_TRY(call_options(R, opt, "dfgt_lscv_score", &precision, &force, &profile));
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_lscv_score", &precision, &force, &profile, &cost_e));
     DFGT_REQUIRE(profile == 0, "dfgt_lscv_score: profiling is not supported here");
-    return run_lscv(R, h_host, n_h, eps, precision, force, variant, cv_host, dcv_host, stats, (hipStream_t)stream);
+    return run_lscv(R, h_host, n_h, eps, precision, force, cost_e, variant, cv_host, dcv_host, stats,
+                    (hipStream_t)stream);
     DFGT_GUARD_END
 }
 

@@ -54,6 +54,7 @@ struct Job {
     long long noff;            // offset of this job's per-node arrays
     double *out;               // caller's output for this job (caller order)
     double *outH, *outQ;       // gradient mode: dG/dh [N_Q] and dG/dq [N_Q][D] (caller order), or null
+    double cost_e;             // weight of the exhaustive cost in ChooseBestMethod
     int mono;                  // Q and R are the same point set
     int pad;
 };
@@ -201,7 +202,7 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // the centroid form is not used; F is unchanged (its derivative series is the
 // far-field series of the derivative kernel, one Hermite index higher).
 __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double tau,
-                      int pmax, int D, int force, int gr, int *order) {
+                      int pmax, int D, int force, int gr, double cost_e, int *order) {
     if (force == DFGT_FORCE_EXACT) {
         *order = 0;
         return METH_E;
@@ -241,7 +242,7 @@ __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, dou
     const double cF = pF ? D * nQ * powi((double)pF, D) : inf;
     const double cD = pD ? D * nR * powi((double)pD, D) : inf;
     const double cT = pT ? D * powi((double)pT, 2 * D) : inf;
-    const double cE = D * nQ * nR;
+    const double cE = cost_e * D * nQ * nR;
     const double mn = fmin(fmin(cF, cD), fmin(cT, cE));
     if (pF && cF == mn) {
         *order = pF;
@@ -274,6 +275,7 @@ struct TravOut {
     int *lvl_next;  // per-level counters written by this level
     int *overflow;
     unsigned long long *stats;
+    int want_stats;  // collect dfgt_stats counters
     Caps cap;
 };
 
@@ -318,7 +320,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         const double tau = jb.eps_eff * nR * gl / jb.nR;
         const double ku = exp(-g.su * jb.inv2h2);
         int ord = 0;
-        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, &ord);
+        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, jb.cost_e, &ord);
         const bool rleaf = R.left[r] < 0;
         if (m != METH_E) {
             plo += nR * ku;
@@ -351,84 +353,71 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     int mo = maxord;
     for (int off = 32; off >= 1; off >>= 1) mo = max(mo, __shfl_xor(mo, off, 64));
 
-    // reserve contiguous output ranges and link the new groups into their chains
-    int ebase = 0, fbase = 0, lbase = 0, cbase = 0, sgi = 0, okmask = 0;
+    // reserve contiguous output ranges and link the new groups into their
+    // chains.  The independent reservations go out from different lanes at
+    // once, then the chain links, then the group records: three round trips.
     const int npair_out = qleaf ? tN : 2 * tN;
     const int nseg_out = tN > 0 ? (qleaf ? 1 : 2) : 0;
     const size_t hq = (size_t)jb.noff + q;
+    int r1 = 0;
+    if (lane == 0 && tE) r1 = atomicAdd(&o.cnt[C_EOP * CP], tE);
+    if (lane == 1 && tE) r1 = atomicAdd(&o.cnt[C_EGRP * CP], 1);
+    if (lane == 2 && tF) r1 = atomicAdd(&o.cnt[C_FOP * CP], tF);
+    if (lane == 3 && tF) r1 = atomicAdd(&o.cnt[C_FGRP * CP], 1);
+    if (lane == 4 && tL) r1 = atomicAdd(&o.cnt[C_LOP * CP], tL);
+    if (lane == 5 && tL) r1 = atomicAdd(&o.cnt[C_LGRP * CP], 1);
+    if (lane == 6 && npair_out) r1 = atomicAdd(&o.lvl_next[C_PAIR * CP], npair_out);
+    if (lane == 7 && npair_out) r1 = atomicAdd(&o.lvl_next[C_SEG * CP], nseg_out);
+    const int ebase = __shfl(r1, 0, 64), gE = __shfl(r1, 1, 64);
+    const int fbase = __shfl(r1, 2, 64), gF = __shfl(r1, 3, 64);
+    const int lbase = __shfl(r1, 4, 64), gL = __shfl(r1, 5, 64);
+    const int cbase = __shfl(r1, 6, 64), sgi = __shfl(r1, 7, 64);
+    const bool okE = tE && ebase + tE <= o.cap.eop && gE < o.cap.grp;
+    const bool okF = tF && fbase + tF <= o.cap.fop && gF < o.cap.grp;
+    const bool okL = tL && lbase + tL <= o.cap.lop && gL < o.cap.grp;
+    const bool okN = npair_out && cbase + npair_out <= o.cap.pair && sgi + nseg_out <= o.cap.seg;
+    int prev = -1;
+    if (lane == 0 && okE) prev = atomicExch(&o.headE[hq], gE);
+    if (lane == 1 && okF) prev = atomicExch(&o.headF[hq], gF);
+    if (lane == 2 && okL) prev = atomicExch(&o.headL[hq], gL);
+    const int prevE = __shfl(prev, 0, 64), prevF = __shfl(prev, 1, 64), prevL = __shfl(prev, 2, 64);
     if (lane == 0) {
-        bool over = false;
-        if (tE) {
-            ebase = atomicAdd(&o.cnt[C_EOP * CP], tE);
-            const int gi = atomicAdd(&o.cnt[C_EGRP * CP], 1);
-            if (ebase + tE <= o.cap.eop && gi < o.cap.grp) {
-                // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
-                // absolute error below 2^-26 G by computing tiny sums in FP64.
-                const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
-                const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
-                o.egrp[gi] = Group{q, sg.job, ebase, tE, fp64, atomicExch(&o.headE[hq], gi)};
-                if (fp64) atomicAdd(&o.stats[S_FP64 * SP], 1ull);
-                okmask |= 1;
-            } else {
-                over = true;
-            }
+        bool over = (tE && !okE) || (tF && !okF) || (tL && !okL) || (npair_out && !okN);
+        if (okE) {
+            // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
+            // absolute error below 2^-26 G by computing tiny sums in FP64.
+            const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
+            const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
+            o.egrp[gE] = Group{q, sg.job, ebase, tE, fp64, prevE};
+            if (fp64 && o.want_stats) atomicAdd(&o.stats[S_FP64 * SP], 1ull);
         }
-        if (tF) {
-            fbase = atomicAdd(&o.cnt[C_FOP * CP], tF);
-            const int gi = atomicAdd(&o.cnt[C_FGRP * CP], 1);
-            if (fbase + tF <= o.cap.fop && gi < o.cap.grp) {
-                o.fgrp[gi] = Group{q, sg.job, fbase, tF, 0, atomicExch(&o.headF[hq], gi)};
-                okmask |= 2;
-            } else {
-                over = true;
-            }
-        }
-        if (tL) {
-            lbase = atomicAdd(&o.cnt[C_LOP * CP], tL);
-            const int gi = atomicAdd(&o.cnt[C_LGRP * CP], 1);
-            if (lbase + tL <= o.cap.lop && gi < o.cap.grp) {
-                const int prev = atomicExch(&o.headL[hq], gi);
-                o.lgrp[gi] = Group{q, sg.job, lbase, tL, 0, prev};
-                okmask |= 4;
-                if (prev < 0 && !(qleaf && leaf_local)) {  // a leaf's own local ops may run in k_leaf
-                    const int li = atomicAdd(&o.cnt[C_LNODE * CP], 1);
-                    if (li < o.cap.lnode) {
-                        o.lnodes[2 * li] = q;
-                        o.lnodes[2 * li + 1] = sg.job;
-                    } else {
-                        over = true;
-                    }
+        if (okF) o.fgrp[gF] = Group{q, sg.job, fbase, tF, 0, prevF};
+        if (okL) {
+            o.lgrp[gL] = Group{q, sg.job, lbase, tL, 0, prevL};
+            if (prevL < 0 && !(qleaf && leaf_local)) {  // a leaf's own local ops may run in k_leaf
+                const int li = atomicAdd(&o.cnt[C_LNODE * CP], 1);
+                if (li < o.cap.lnode) {
+                    o.lnodes[2 * li] = q;
+                    o.lnodes[2 * li + 1] = sg.job;
+                } else {
+                    over = true;
                 }
-            } else {
-                over = true;
             }
-        }
-        if (npair_out) {
-            cbase = atomicAdd(&o.lvl_next[C_PAIR * CP], npair_out);
-            sgi = atomicAdd(&o.lvl_next[C_SEG * CP], nseg_out);
-            if (cbase + npair_out <= o.cap.pair && sgi + nseg_out <= o.cap.seg) okmask |= 8;
-            else over = true;
         }
         if (over) atomicExch(o.overflow, 1);
-        atomicAdd(&o.stats[S_PAIRS * SP], (unsigned long long)sg.count);
-        atomicAdd(&o.stats[S_SEGS * SP], 1ull);
-        atomicMax(&o.stats[S_MAXSEG * SP], (unsigned long long)sg.count);
-        if (nFp) atomicAdd(&o.stats[S_F * SP], (unsigned long long)nFp);
-        if (nDp) atomicAdd(&o.stats[S_D * SP], (unsigned long long)nDp);
-        if (nTp) atomicAdd(&o.stats[S_T * SP], (unsigned long long)nTp);
-        if (nCp) atomicAdd(&o.stats[S_C * SP], (unsigned long long)nCp);
-        if (tE) {
-            atomicAdd(&o.stats[S_BLEAF * SP], (unsigned long long)tE);
-            atomicAdd(&o.stats[S_BPTS * SP], (unsigned long long)(nQ * ept));
-        }
-        if (mo) atomicMax(&o.stats[S_MAXORD * SP], (unsigned long long)mo);
     }
-    ebase = __shfl(ebase, 0, 64);
-    fbase = __shfl(fbase, 0, 64);
-    lbase = __shfl(lbase, 0, 64);
-    cbase = __shfl(cbase, 0, 64);
-    okmask = __shfl(okmask, 0, 64);
-    const bool okE = okmask & 1, okF = okmask & 2, okL = okmask & 4, okN = okmask & 8;
+    if (o.want_stats) {  // counters for dfgt_stats, one lane each (no return values)
+        if (lane == 8) atomicAdd(&o.stats[S_PAIRS * SP], (unsigned long long)sg.count);
+        if (lane == 9) atomicAdd(&o.stats[S_SEGS * SP], 1ull);
+        if (lane == 10) atomicMax(&o.stats[S_MAXSEG * SP], (unsigned long long)sg.count);
+        if (lane == 11 && nFp) atomicAdd(&o.stats[S_F * SP], (unsigned long long)nFp);
+        if (lane == 12 && nDp) atomicAdd(&o.stats[S_D * SP], (unsigned long long)nDp);
+        if (lane == 13 && nTp) atomicAdd(&o.stats[S_T * SP], (unsigned long long)nTp);
+        if (lane == 14 && nCp) atomicAdd(&o.stats[S_C * SP], (unsigned long long)nCp);
+        if (lane == 15 && tE) atomicAdd(&o.stats[S_BLEAF * SP], (unsigned long long)tE);
+        if (lane == 16 && tE) atomicAdd(&o.stats[S_BPTS * SP], (unsigned long long)(nQ * ept));
+        if (lane == 17 && mo) atomicMax(&o.stats[S_MAXORD * SP], (unsigned long long)mo);
+    }
 
     // 3. write outputs in pair order
     int eo = 0, fo = 0, lo = 0, no = 0;
@@ -630,6 +619,7 @@ __host__ __device__ inline size_t lop_wave_stride(int P, int d, int pmax, int gr
 }
 
 constexpr int kMaxSeg = 256;
+constexpr int kMaxDepth = 256;  // deepest tree the per-leaf kernel walks
 
 // Local ops run fully in parallel: one wave per op (a D op is one chunk of
 // <= 64 reference points), each writing its contribution to Q's local
@@ -1072,9 +1062,10 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const double *__restrict__ extY) {
     extern __shared__ double smem[];
     if (*overflow) return;
-    __shared__ int path[256];
-    __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg];
-    __shared__ int plen_s, any_s, nsg_s, nops_s, st_phase, st_gi, st_pi;
+    __shared__ int path[kMaxDepth];
+    __shared__ unsigned char lfl[kMaxDepth];
+    __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg], ccnt[kMaxDepth + 1];
+    __shared__ int nsg_s, nops_s, ntot_s, nops1_s, st_phase, st_gi, st_pi;
     const int job = blockIdx.y;
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
@@ -1088,8 +1079,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const int ns = d * (pmax - 1) + 1;
     const size_t hq = (size_t)jb.noff + leaf;
     // LDS: red[nthr] | redX[nthr] (GR) | spow[ns] | Hq[nthr][D][hs] | xs[nthr][D] | gq[nthr][D] (GR)
-    //      | acc[PW] | tmp[PW] | coef[pmax^2] | dg[P] (u64) | mt[P] (u16)
-    //      (acc / tmp in a global scratch slice when P is large)
+    //      | acc[PW] | tmp[PW] | tmp2[PW] | coef[D][pmax^2] | dg[P] (u64) | mt[P] (u16)
+    //      (acc / tmp / tmp2 in a global scratch slice when P is large)
     double *red = smem;
     double *redX = red + nthr;
     double *spow = redX + (GR ? nthr : 0);
@@ -1099,78 +1090,75 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     double *gq_all = xs + (size_t)nthr * d;
     double *gq = gq_all + (size_t)tid * d;
     double *tail = gq_all + (GR ? (size_t)nthr * d : 0);
-    double *acc, *tmp, *coef;
+    double *acc, *tmp, *tmp2, *coef;
     if (acc_in_lds) {
         acc = tail;
         tmp = acc + PW;
-        coef = tmp + PW;
+        tmp2 = tmp + PW;
+        coef = tmp2 + PW;
     } else {
         const size_t slot = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        acc = gscratch + slot * 2 * PW;
+        acc = gscratch + slot * 3 * PW;
         tmp = acc + PW;
+        tmp2 = tmp + PW;
         coef = tail;
     }
-    unsigned long long *dg = reinterpret_cast<unsigned long long *>(coef + pmax * pmax);
+    unsigned long long *dg = reinterpret_cast<unsigned long long *>(coef + d * pmax * pmax);
     unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
     build_digit_tables(dg, mt, P, d, pmax);
-    if (tid == 0) {
-        int n = 0, v = leaf, any = 0;
-        while (v >= 0 && n < 256) {
-            path[n++] = v;
-            any |= lflag[jb.noff + v];
-            v = Q.parent[v];
-        }
-        plen_s = (v >= 0) ? -1 : n;
-        any_s = any | (leaf_local && headL[hq] >= 0 ? 1 : 0);
+    // root path (precomputed with the tree: path[0] = the leaf, path[plen-1] = the root)
+    const int li = blockIdx.x;
+    const int plen = Q.lplen[li];
+    int mine = 0;
+    for (int k = tid; k < plen; k += nthr) {
+        const int v = Q.lpath[(size_t)li * Q.depth + k];
+        path[k] = v;
+        lfl[k] = lflag[jb.noff + v];
+        mine |= lfl[k];
     }
     for (int i = tid; i < ns; i += nthr) spow[i] = powi(s, i);
-    __syncthreads();
-    const int plen = plen_s;
+    const int anyl = __syncthreads_or(mine);
     const int qb = Q.begin[leaf], nq = Q.end[leaf] - qb;
-    if (plen < 0) {
-        // a root-to-leaf path deeper than 256 levels is not walked: flag it
-        for (int qi = tid; qi < nq; qi += nthr) jb.out[Q.perm[qb + qi]] = NAN;
-        return;
-    }
-    // 1. local moments at the leaf
-    const bool any = any_s != 0;
+    // 1. local moments at the leaf: the moments of every ancestor v that has
+    //    any, translated straight to the leaf centre (TransLocalToLocal; the
+    //    translation of a polynomial is exact, so one step v -> leaf equals the
+    //    chain of parent -> child steps), added root first; each translation is
+    //    D one-axis mode products, child L_a = sum_{b >= a} C(b, a) L_b X^{b-a},
+    //    X = (leaf.c - v.c) s
+    const bool any = anyl != 0 || (leaf_local && headL[hq] >= 0);
     if (any) {
         for (int i = tid; i < PW; i += nthr) acc[i] = 0.0;
-        bool nonzero = false;
         for (int pi = plen - 1; pi >= 0; --pi) {
+            if (!lfl[pi]) continue;  // uniform: LDS flag
             const int v = path[pi];
-            if (pi != plen - 1 && nonzero) {
-                const int u = path[pi + 1];
-                double *src = acc, *dst = tmp;
-                for (int k = 0; k < d; ++k) {
-                    const double X = (Q.ctr[(size_t)v * d + k] - Q.ctr[(size_t)u * d + k]) * s;
-                    __syncthreads();
-                    for (int i = tid; i < pmax * pmax; i += nthr) {
-                        const int a = i / pmax, b = i % pmax;
-                        double c = 0.0;
-                        if (b >= a) {
-                            c = 1.0;
-                            for (int t = 0; t < b - a; ++t) c *= X * (double)(b - t) / (double)(b - a - t);
-                        }
-                        coef[i] = c;
-                    }
-                    __syncthreads();
-                    mode_product(src, dst, coef, P, d, pmax, k, pmax);
-                    if (GR) mode_product(src + P, dst + P, coef, P, d, pmax, k, pmax);
-                    double *t2 = src;
-                    src = dst;
-                    dst = t2;
-                }
-                __syncthreads();
-                if (src != acc)
-                    for (int i = tid; i < PW; i += nthr) acc[i] = src[i];
-                __syncthreads();
-            }
-            if (lflag[jb.noff + v]) {
-                const double *Lv = L + ((size_t)jb.noff + v) * PW;
+            const double *Lv = L + ((size_t)jb.noff + v) * PW;
+            if (pi == 0) {  // the leaf's own moments: no translation
                 for (int i = tid; i < PW; i += nthr) acc[i] += Lv[i];
-                nonzero = true;
+                __syncthreads();
+                continue;
             }
+            for (int i = tid; i < d * pmax * pmax; i += nthr) {
+                const int k = i / (pmax * pmax), a = (i / pmax) % pmax, b = i % pmax;
+                const double X = (Q.ctr[(size_t)leaf * d + k] - Q.ctr[(size_t)v * d + k]) * s;
+                double c = 0.0;
+                if (b >= a) {
+                    c = 1.0;
+                    for (int t = 0; t < b - a; ++t) c *= X * (double)(b - t) / (double)(b - a - t);
+                }
+                coef[i] = c;
+            }
+            for (int i = tid; i < PW; i += nthr) tmp[i] = Lv[i];
+            __syncthreads();
+            double *src = tmp, *dst = tmp2;
+            for (int k = 0; k < d; ++k) {
+                mode_product(src, dst, coef + k * pmax * pmax, P, d, pmax, k, pmax);
+                if (GR) mode_product(src + P, dst + P, coef + k * pmax * pmax, P, d, pmax, k, pmax);
+                __syncthreads();
+                double *t2 = src;
+                src = dst;
+                dst = t2;
+            }
+            for (int i = tid; i < PW; i += nthr) acc[i] += src[i];
             __syncthreads();
         }
         if (leaf_local && headL[hq] >= 0) {  // the leaf's own local ops, from their partial rows
@@ -1187,6 +1175,63 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const bool staged = slots <= 64;
     double *xg = xs + (size_t)tg * slots * d;  // the group's staging slice
     const double *lc = Q.ctr + (size_t)leaf * d;
+    // op groups: the leaf's E chain, then the F chains of the path nodes from
+    // the root down, each chain in its own order.  One thread per chain counts
+    // and then copies its groups; if more than kMaxSeg groups result they are
+    // flattened serially in batches instead.
+    for (int ch = tid; ch <= plen; ch += nthr) {
+        int c = 0;
+        if (ch == 0) {
+            for (int gi = extE ? -1 : headE[hq]; gi >= 0; gi = egrp[gi].next) ++c;
+        } else {
+            for (int gi = headF[(size_t)jb.noff + path[plen - ch]]; gi >= 0; gi = fgrp[gi].next) ++c;
+        }
+        ccnt[ch] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int t = 0;
+        for (int k = 0; k <= plen; ++k) {
+            const int c = ccnt[k];
+            ccnt[k] = t;
+            t += c;
+        }
+        ntot_s = t;
+    }
+    __syncthreads();
+    const bool single = ntot_s <= kMaxSeg;
+    if (single) {
+        for (int ch = tid; ch <= plen; ch += nthr) {
+            int o = ccnt[ch];
+            if (ch == 0) {
+                for (int gi = extE ? -1 : headE[hq]; gi >= 0;) {
+                    const Group g = egrp[gi];
+                    segT[o] = g.flags ? 2 : 0;
+                    segS[o] = g.start;
+                    segE[o++] = g.count;
+                    gi = g.next;
+                }
+            } else {
+                for (int gi = headF[(size_t)jb.noff + path[plen - ch]]; gi >= 0;) {
+                    const Group g = fgrp[gi];
+                    segT[o] = 1;
+                    segS[o] = g.start;
+                    segE[o++] = g.count;
+                    gi = g.next;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int t = 0;
+            for (int k = 0; k < ntot_s; ++k) {
+                t += segE[k];
+                segE[k] = t;
+            }
+            nops1_s = t;
+        }
+        __syncthreads();
+    }
     for (int q0 = 0; q0 < nq; q0 += slots) {
         const int qq = q0 + qi;
         const bool act = qq < nq;
@@ -1201,8 +1246,9 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             st_pi = plen - 1;
         }
         __syncthreads();
-        while (true) {
-            if (tid == 0) {
+        for (int round = 0;; ++round) {
+            if (single && round > 0) break;
+            if (!single && tid == 0) {
                 // flatten the next batch of op groups: the leaf's E chain, then
                 // the F chains of the path nodes from the root down
                 int n = 0, tot = 0, ph = st_phase, gi = st_gi, pi = st_pi;
@@ -1240,8 +1286,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 nops_s = tot;
             }
             __syncthreads();
-            const int nops = nops_s;
-            if (nsg_s == 0) break;
+            const int nops = single ? nops1_s : nops_s;
+            if (!single && nsg_s == 0) break;
             int sp = 0;
             for (int base = 0; base < nops; base += ngr) {
                 const int idx = base + tg;
@@ -1689,8 +1735,8 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
 }  // namespace
 
 dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int nh, double eps, int precision,
-                          int force, int profile, double *G, const GradOut *grad, dfgt_stats *stats_out,
-                          hipStream_t st) {
+                          int force, int profile, double cost_e, double *G, const GradOut *grad,
+                          dfgt_stats *stats_out, hipStream_t st) {
     Workspace &w = g_ws;
     Profiler &prof = g_prof;
     const DevTree &Qv = Qh->host_view;
@@ -1724,6 +1770,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         j.outH = gr && grad->dGdh ? grad->dGdh + (size_t)k * NQ : nullptr;
         j.outQ = gr && grad->dGdq ? grad->dGdq + (size_t)k * NQ * d : nullptr;
         j.mono = mono ? 1 : 0;
+        j.cost_e = cost_e;
         j.pad = 0;
     }
     DevTree tv[2] = {Qh->host_view, Rh->host_view};
@@ -1746,6 +1793,10 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     const bool leaf_local = P <= 512;
     if (gr && !leaf_local) {
         set_error("dfgt_gauss_sum_grad: gradients need p_max^d <= 512");
+        return DFGT_EINVAL;
+    }
+    if (Qh->depth > kMaxDepth) {
+        set_error("dfgt_gauss_sum: query tree deeper than 256 levels");
         return DFGT_EINVAL;
     }
     // every level splits Q and R wherever they can split, so no pair survives
@@ -1809,7 +1860,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                       w.fgrp.as<Group>(), w.fops.as<Op>(),  w.lgrp.as<Group>(), w.lops.as<Op>(),
                       w.lnodes.as<int>(), headE,            headF,              headL,
                       w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
-                      w.stats.as<unsigned long long>(),     cap};
+                      w.stats.as<unsigned long long>(),     stats_out != nullptr ? 1 : 0, cap};
             hipEvent_t ev = prof.start(st);
             hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
                                k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, nh, force, gr ? 1 : 0,
@@ -1869,15 +1920,17 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
             while (nthr > 64 && sizeof(double) * leaf_lds_base(nthr, d, pmax, g1) > 40 * 1024) nthr >>= 1;
             const size_t base = sizeof(double) * leaf_lds_base(nthr, d, pmax, g1);
             const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
-            const size_t lds_acc = sizeof(double) * (2 * (size_t)PW + (size_t)pmax * pmax);
-            const bool acc_lds = base + lds_acc + lds_dig <= 64 * 1024;
+            const size_t lds_coef = sizeof(double) * (size_t)d * pmax * pmax;
+            const size_t lds_acc = sizeof(double) * 3 * (size_t)PW + lds_coef;
+            // dynamic LDS up to 56 KB: the kernel's static arrays take ~6 KB of the 64 KB
+            const bool acc_lds = base + lds_acc + lds_dig <= 56 * 1024;
             double *scr = nullptr;
             if (!acc_lds) {
-                DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 2 * PW));
+                DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 3 * PW));
                 scr = w.pscr.as<double>();
             }
-            const size_t sh = base + (acc_lds ? lds_acc : sizeof(double) * (size_t)pmax * pmax) + lds_dig;
-            if (sh > 64 * 1024) {
+            const size_t sh = base + (acc_lds ? lds_acc : lds_coef) + lds_dig;
+            if (sh > 56 * 1024) {
                 set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
                 return DFGT_EINVAL;
             }

@@ -89,6 +89,8 @@ struct DevTree {
     const int32_t *perm;                  // [n] tree position -> caller index
     const double *mu;                     // [m][P] raw far-field moments
     const double *nrm;                    // [n] squared norms |x|^2 in tree order
+    const int32_t *lpath;                 // [nleaves][depth] ancestors of each leaf, the leaf first
+    const int32_t *lplen;                 // [nleaves] path lengths
 };
 
 }  // namespace dfgt
@@ -99,7 +101,8 @@ struct dfgt_tree_s {
     int32_t d = 0, leaf = 32, pmax = 1, P = 1, depth = 0, precision = 0, force = 0;
     int64_t m = 0, nleaves = 0;
     std::vector<int32_t> level_start;  // host copy: nodes of level l are [level_start[l], level_start[l+1])
-    dfgt::DevBuf lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max;
+    dfgt::DevBuf lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max,
+        lpath, lplen;
     double max_nrm = 0.0;  // max |x|^2 (valid after dfgt_build_tree returns)
     dfgt::DevBuf view;  // a DevTree in device memory
     dfgt::DevTree host_view{};
@@ -157,15 +160,16 @@ struct GradOut {
     double *dGdh;
     double *dGdq;
 };
+// cost_e: weight of the exhaustive cost in ChooseBestMethod (1 = the paper's model).
 dfgt_status run_gauss_sum(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps,
-                          int precision, int force, int profile, double *G, const GradOut *grad,
+                          int precision, int force, int profile, double cost_e, double *G, const GradOut *grad,
                           dfgt_stats *stats, hipStream_t st);
 
 // sweep.hip
 dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps, int precision,
-                         int force, const double *dG, double *dh_host, double *dq, hipStream_t st);
-dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, int variant,
-                     double *cv, double *dcv, dfgt_stats *stats, hipStream_t st);
+                         int force, double cost_e, const double *dG, double *dh_host, double *dq, hipStream_t st);
+dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,
+                     int variant, double *cv, double *dcv, dfgt_stats *stats, hipStream_t st);
 
 int default_pmax(int d);
 

@@ -81,14 +81,14 @@ dfgt_status row_sums(const double *a, const double *b, double bias, long long n,
 }  // namespace
 
 dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps, int precision,
-                         int force, const double *dG, double *dh_host, double *dq, hipStream_t st) {
+                         int force, double cost_e, const double *dG, double *dh_host, double *dq, hipStream_t st) {
     SweepWs &w = g_sw;
     const size_t nq = (size_t)Q->n, d = (size_t)Q->d;
     DFGT_TRY(w.G.reserve(sizeof(double) * nh * nq));
     if (dh_host) DFGT_TRY(w.dGdh.reserve(sizeof(double) * nh * nq));
     if (dq) DFGT_TRY(w.dGdq.reserve(sizeof(double) * nh * nq * d));
     GradOut go{dh_host ? w.dGdh.as<double>() : nullptr, dq ? w.dGdq.as<double>() : nullptr};
-    DFGT_TRY(run_gauss_sum(Q, R, h, nh, eps, precision, force, 0, w.G.as<double>(), &go, nullptr, st));
+    DFGT_TRY(run_gauss_sum(Q, R, h, nh, eps, precision, force, 0, cost_e, w.G.as<double>(), &go, nullptr, st));
     if (dq) {
         const long long tot = (long long)(nq * d);
         hipLaunchKernelGGL(k_dq, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dG, w.dGdq.as<double>(), nh,
@@ -99,8 +99,8 @@ dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh
     return DFGT_OK;
 }
 
-dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, int variant,
-                     double *cv, double *dcv, dfgt_stats *stats, hipStream_t st) {
+dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,
+                     int variant, double *cv, double *dcv, dfgt_stats *stats, hipStream_t st) {
     SweepWs &w = g_sw;
     const size_t n = (size_t)R->n;
     const int nj = 2 * nh;
@@ -114,8 +114,8 @@ dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int pr
     DFGT_TRY(w.G.reserve(sizeof(double) * nj * n));
     if (dcv) DFGT_TRY(w.dGdh.reserve(sizeof(double) * nj * n));
     GradOut go{dcv ? w.dGdh.as<double>() : nullptr, nullptr};
-    DFGT_TRY(run_gauss_sum(R, R, hh.data(), nj, eps, precision, force, 0, w.G.as<double>(), dcv ? &go : nullptr,
-                           stats, st));
+    DFGT_TRY(run_gauss_sum(R, R, hh.data(), nj, eps, precision, force, 0, cost_e, w.G.as<double>(),
+                           dcv ? &go : nullptr, stats, st));
     // S_j = sum_i (G_j(x_i) - 1): the sums without their self terms
     std::vector<double> S(nj), dS(nj, 0.0);
     DFGT_TRY(row_sums(w.G.as<double>(), nullptr, 1.0, (long long)n, nj, S.data(), st));

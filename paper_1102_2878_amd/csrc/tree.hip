@@ -15,6 +15,9 @@
 // The result is bit-identical to the recursive algorithm (same boxes, split
 // dimensions, split coordinates and permutation); only node numbering differs
 // (breadth-first instead of pre-order).
+#include <algorithm>
+#include <vector>
+
 #include "dfgt_internal.h"
 
 namespace dfgt {
@@ -112,7 +115,8 @@ __device__ __forceinline__ bool node_split(const long long *lo_key, const long l
 __global__ void k_flag(const double *__restrict__ x, const int32_t *__restrict__ pnode, int n, int d, int leaf,
                        const long long *__restrict__ lo_key, const long long *__restrict__ hi_key,
                        const int32_t *__restrict__ begin, const int32_t *__restrict__ end, int32_t *flag,
-                       int32_t *nleft) {
+                       int32_t *nleft, const int *__restrict__ done) {
+    if (*done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int f = 0, node = -1;
     if (i < n) {
@@ -138,13 +142,17 @@ __global__ void k_flag(const double *__restrict__ x, const int32_t *__restrict__
 
 // One block: decide the splits of level nodes [lb, le) and allocate children
 // at le + 2 * (rank among splitting nodes).
-__global__ __launch_bounds__(1024) void k_finalize(int lb, int le, int d, int leaf, long long *lo_key,
-                                                   long long *hi_key, int32_t *begin, int32_t *end,
-                                                   int32_t *left, int32_t *right, int32_t *parent,
-                                                   int32_t *sdim, double *scoord, int32_t *nleft,
-                                                   int *new_count) {
+// Level bounds live on the device: level k is [lvs[2k], lvs[2k+1]); the
+// kernel writes level k+1's bounds, or sets *done when nothing splits (the
+// per-level kernels that follow then return at once).
+__global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs, int *done, int d, int leaf,
+                                                   long long *lo_key, long long *hi_key, int32_t *begin,
+                                                   int32_t *end, int32_t *left, int32_t *right, int32_t *parent,
+                                                   int32_t *sdim, double *scoord, int32_t *nleft) {
     __shared__ int warp_tot[16];
     __shared__ int carry_s;
+    if (*done) return;
+    const int lb = lvs[2 * level], le = lvs[2 * level + 1];
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     for (int c0 = lb; c0 < le; c0 += blockDim.x) {
@@ -199,14 +207,21 @@ __global__ __launch_bounds__(1024) void k_finalize(int lb, int le, int d, int le
         if (threadIdx.x == blockDim.x - 1) carry_s = rank + split;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *new_count = 2 * carry_s;
+    if (threadIdx.x == 0) {
+        const int newc = 2 * carry_s;
+        lvs[2 * level + 2] = le;
+        lvs[2 * level + 3] = le + newc;
+        if (newc == 0 || le + newc > cap) *done = newc == 0 ? 1 : 2;  // 2: capacity exceeded (internal error)
+    }
 }
 
 // --- exclusive scan of int32 flags (three phases) -----------------------------------
 constexpr int kScanItems = 1024;  // per block: 256 threads x 4
 
-__global__ void k_scan_blocks(const int32_t *__restrict__ in, int n, int32_t *__restrict__ block_sums) {
+__global__ void k_scan_blocks(const int32_t *__restrict__ in, int n, int32_t *__restrict__ block_sums,
+                              const int *__restrict__ done) {
     __shared__ int wt[4];
+    if (*done) return;
     const int base = blockIdx.x * kScanItems;
     int s = 0;
     for (int j = 0; j < 4; ++j) {
@@ -219,7 +234,8 @@ __global__ void k_scan_blocks(const int32_t *__restrict__ in, int n, int32_t *__
     if (threadIdx.x == 0) block_sums[blockIdx.x] = wt[0] + wt[1] + wt[2] + wt[3];
 }
 
-__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nb) {
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nb, const int *__restrict__ done) {
+    if (*done) return;
     __shared__ int wt[16];
     __shared__ int carry_s;
     if (threadIdx.x == 0) carry_s = 0;
@@ -242,8 +258,9 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nb) {
 }
 
 __global__ void k_scan_final(const int32_t *__restrict__ in, int n, const int32_t *__restrict__ block_off,
-                             int32_t *__restrict__ out) {
+                             int32_t *__restrict__ out, const int *__restrict__ done) {
     __shared__ int wt[4];
+    if (*done) return;
     const int base = blockIdx.x * kScanItems;
     int v[4], s = 0;
     for (int j = 0; j < 4; ++j) {
@@ -270,7 +287,8 @@ __global__ void k_scatter(int n, int d, const int32_t *__restrict__ pnode_a, con
                           const int32_t *__restrict__ scan, const int32_t *__restrict__ begin,
                           const int32_t *__restrict__ nleft, const int32_t *__restrict__ left,
                           const int32_t *__restrict__ right, int32_t *pnode_b, int32_t *perm_b, double *x_b,
-                          long long *lo_key, long long *hi_key) {
+                          long long *lo_key, long long *hi_key, const int *__restrict__ done) {
+    if (*done) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[kMaxD];
     int child = -1;
@@ -308,6 +326,20 @@ __global__ void k_decode_boxes(int m, int d, const long long *__restrict__ lo_ke
     ctr[i] = (a + b) / 2.0;
 }
 
+// Root paths of the leaves: lpath[i][k] = k-th ancestor of leaf i (k = 0 is
+// the leaf), lplen[i] = path length.
+__global__ void k_leaf_paths(const int32_t *__restrict__ leaves, int nleaves, const int32_t *__restrict__ parent,
+                             int depth, int32_t *__restrict__ lpath, int32_t *__restrict__ lplen) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaves) return;
+    int v = leaves[i], k = 0;
+    while (v >= 0 && k < depth) {
+        lpath[(size_t)i * depth + k++] = v;
+        v = parent[v];
+    }
+    lplen[i] = k;
+}
+
 __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_t *leaves, int *count) {
     // single block, order-preserving compaction of leaf ids
     __shared__ int wt[16];
@@ -337,7 +369,7 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
 dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st) {
     const int n = (int)t->n, d = t->d, leaf = t->leaf;
     const int cap = 2 * n + 1;
-    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, scan, bsums, lo_key, hi_key, nleft, counter;
+    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, scan, bsums, lo_key, hi_key, nleft, counter, lvs_b;
     DFGT_TRY(t->perm.reserve(sizeof(int32_t) * n));
     DFGT_TRY(perm_b.reserve(sizeof(int32_t) * n));
     DFGT_TRY(t->x.reserve(sizeof(double) * (size_t)n * d));
@@ -352,6 +384,10 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     DFGT_TRY(hi_key.reserve(sizeof(long long) * (size_t)cap * d));
     DFGT_TRY(nleft.reserve(sizeof(int32_t) * cap));
     DFGT_TRY(counter.reserve(sizeof(int) * 4));
+    // level bounds: a tree on n points has at most n levels (every split
+    // leaves fewer points on each side)
+    const int max_levels = n + 1;
+    DFGT_TRY(lvs_b.reserve(sizeof(int) * 2 * ((size_t)max_levels + 1)));
     DFGT_TRY(t->begin.reserve(sizeof(int32_t) * cap));
     DFGT_TRY(t->end.reserve(sizeof(int32_t) * cap));
     DFGT_TRY(t->left.reserve(sizeof(int32_t) * cap));
@@ -363,8 +399,11 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
     double *xa = t->x.as<double>(), *xb = x_b.as<double>();
     int32_t *na = pnode_a.as<int32_t>(), *nb = pnode_b.as<int32_t>();
-    int *cnt_d = counter.as<int>();
+    int *cnt_d = counter.as<int>();  // [0] done flag, [1] non-finite flag, [2] leaf count
+    int *lvs = lvs_b.as<int>();
+    const int lvs0[2] = {0, 1};
     DFGT_HIP(hipMemsetAsync(cnt_d, 0, sizeof(int) * 4, st));
+    DFGT_HIP(hipMemcpyAsync(lvs, lvs0, sizeof(lvs0), hipMemcpyHostToDevice, st));
     const int gb = (n + kTB - 1) / kTB;
     hipLaunchKernelGGL(k_init, dim3(gb), dim3(kTB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
     hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
@@ -373,46 +412,69 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kTB), 0, st, xa, n, d, lo_key.as<long long>(),
                        hi_key.as<long long>());
     DFGT_HIP(hipGetLastError());
-    int host_cnt[2] = {0, 0};
-    DFGT_HIP(hipMemcpyAsync(host_cnt, cnt_d, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipStreamSynchronize(st));
-    if (host_cnt[1]) {
-        set_error("dfgt_build_tree: points contain a non-finite coordinate");
-        return DFGT_EINVAL;
-    }
 
-    t->level_start.assign(1, 0);
-    int lb = 0, le = 1;
-    while (true) {
-        t->level_start.push_back(le);
-        hipLaunchKernelGGL(k_flag, dim3(gb), dim3(kTB), 0, st, xa, na, n, d, leaf, lo_key.as<long long>(),
-                           hi_key.as<long long>(), t->begin.as<int32_t>(), t->end.as<int32_t>(),
-                           flag.as<int32_t>(), nleft.as<int32_t>());
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, lb, le, d, leaf, lo_key.as<long long>(),
-                           hi_key.as<long long>(), t->begin.as<int32_t>(), t->end.as<int32_t>(),
-                           t->left.as<int32_t>(), t->right.as<int32_t>(), t->parent.as<int32_t>(),
-                           t->sdim.as<int32_t>(), t->scoord.as<double>(), nleft.as<int32_t>(), cnt_d);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n, bsums.as<int32_t>());
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsums.as<int32_t>(), nsb);
-        hipLaunchKernelGGL(k_scan_final, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n, bsums.as<int32_t>(),
-                           scan.as<int32_t>());
-        hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kTB), 0, st, n, d, na, pa, xa, flag.as<int32_t>(),
-                           scan.as<int32_t>(), t->begin.as<int32_t>(), nleft.as<int32_t>(), t->left.as<int32_t>(),
-                           t->right.as<int32_t>(), nb, pb, xb, lo_key.as<long long>(), hi_key.as<long long>());
-        DFGT_HIP(hipGetLastError());
-        std::swap(pa, pb);
-        std::swap(xa, xb);
-        std::swap(na, nb);
-        int newc = 0;
-        DFGT_HIP(hipMemcpyAsync(&newc, cnt_d, sizeof(int), hipMemcpyDeviceToHost, st));
+    // Levels are enqueued in batches without host round trips: the first
+    // batch covers the depth of a balanced tree (+6), later ones 4 levels;
+    // levels after the last split return at once.  Level k moves the points
+    // between the two buffers, so after K splitting levels they sit in buffer
+    // K % 2.
+    int level = 0, done = 0;
+    int batch = 6;
+    for (int q = n / std::max(leaf, 1); q > 1; q >>= 1) ++batch;
+    while (!done && level < max_levels) {
+        const int stop = std::min(max_levels, level + batch);
+        for (; level < stop; ++level) {
+            int32_t *pin = (level & 1) ? pb : pa, *pout = (level & 1) ? pa : pb;
+            double *xin = (level & 1) ? xb : xa, *xout = (level & 1) ? xa : xb;
+            int32_t *nin = (level & 1) ? nb : na, *nout = (level & 1) ? na : nb;
+            hipLaunchKernelGGL(k_flag, dim3(gb), dim3(kTB), 0, st, xin, nin, n, d, leaf, lo_key.as<long long>(),
+                               hi_key.as<long long>(), t->begin.as<int32_t>(), t->end.as<int32_t>(),
+                               flag.as<int32_t>(), nleft.as<int32_t>(), cnt_d);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, level, cap, lvs, cnt_d, d, leaf,
+                               lo_key.as<long long>(), hi_key.as<long long>(), t->begin.as<int32_t>(),
+                               t->end.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(),
+                               t->parent.as<int32_t>(), t->sdim.as<int32_t>(), t->scoord.as<double>(),
+                               nleft.as<int32_t>());
+            hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n,
+                               bsums.as<int32_t>(), cnt_d);
+            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsums.as<int32_t>(), nsb, cnt_d);
+            hipLaunchKernelGGL(k_scan_final, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n,
+                               bsums.as<int32_t>(), scan.as<int32_t>(), cnt_d);
+            hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kTB), 0, st, n, d, nin, pin, xin, flag.as<int32_t>(),
+                               scan.as<int32_t>(), t->begin.as<int32_t>(), nleft.as<int32_t>(),
+                               t->left.as<int32_t>(), t->right.as<int32_t>(), nout, pout, xout,
+                               lo_key.as<long long>(), hi_key.as<long long>(), cnt_d);
+            DFGT_HIP(hipGetLastError());
+        }
+        int flags[2] = {0, 0};
+        DFGT_HIP(hipMemcpyAsync(flags, cnt_d, sizeof(flags), hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
-        if (newc == 0) break;
-        lb = le;
-        le += newc;
-        if (le > cap) {
+        if (flags[1]) {
+            set_error("dfgt_build_tree: points contain a non-finite coordinate");
+            return DFGT_EINVAL;
+        }
+        if (flags[0] == 2) {
             set_error("dfgt_build_tree: node capacity exceeded (internal error)");
             return DFGT_EHIP;
         }
+        done = flags[0];
+        batch = 4;
+    }
+    if (!done) {
+        set_error("dfgt_build_tree: level limit reached (internal error)");
+        return DFGT_EHIP;
+    }
+    // level bounds: levels 0 .. K, K the first level without a split
+    std::vector<int> hl(2 * (size_t)(level + 1));
+    DFGT_HIP(hipMemcpy(hl.data(), lvs, sizeof(int) * hl.size(), hipMemcpyDeviceToHost));
+    int K = 0;
+    while (K + 1 <= level && hl[2 * (size_t)K + 3] > hl[2 * (size_t)K + 1]) ++K;
+    t->level_start.assign(1, 0);
+    for (int k = 0; k <= K; ++k) t->level_start.push_back(hl[2 * (size_t)k + 1]);
+    const int le = hl[2 * (size_t)K + 1];
+    if (K & 1) {
+        pa = perm_b.as<int32_t>();
+        xa = x_b.as<double>();
     }
     const int m = le;
     t->m = m;
@@ -435,6 +497,11 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     DFGT_HIP(hipMemcpyAsync(&nl, cnt_d + 2, sizeof(int), hipMemcpyDeviceToHost, st));
     DFGT_HIP(hipStreamSynchronize(st));
     t->nleaves = nl;
+    DFGT_TRY(t->lpath.reserve(sizeof(int32_t) * (size_t)nl * t->depth));
+    DFGT_TRY(t->lplen.reserve(sizeof(int32_t) * (size_t)nl));
+    hipLaunchKernelGGL(k_leaf_paths, dim3((nl + 255) / 256), dim3(256), 0, st, t->leaves.as<int32_t>(), nl,
+                       t->parent.as<int32_t>(), t->depth, t->lpath.as<int32_t>(), t->lplen.as<int32_t>());
+    DFGT_HIP(hipGetLastError());
     return DFGT_OK;
 }
 

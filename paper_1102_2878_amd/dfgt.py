@@ -26,7 +26,8 @@ class DfgtError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("p_max", C.c_int32), ("precision", C.c_int32),
-                ("force_method", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("force_method", C.c_int32), ("profile", C.c_int32), ("cost_exhaustive", C.c_float),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):
@@ -111,10 +112,11 @@ def _hvec(h):
     return h, h.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _opts(leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE, profile=False):
+def _opts(leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE, profile=False, cost_exhaustive=0.0):
     o = Options()
     o.leaf_size, o.p_max, o.precision, o.force_method = int(leaf_size), int(p_max), int(precision), int(force_method)
     o.profile = int(bool(profile))
+    o.cost_exhaustive = float(cost_exhaustive)
     return o
 
 
@@ -186,13 +188,13 @@ def naive_sum(q, r, h, precision=PREC_MIXED, out=None):
 
 
 def gauss_sum(Q: Tree, R: Tree, h, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, out=None,
-              profile=False):
+              profile=False, cost_exhaustive=0.0):
     """dfgt_gauss_sum: DFGT sums for every bandwidth, (n_h, NQ) float64 CUDA tensor [, stats dict]."""
     torch = _torch()
     hv, hp = _hvec(h)
     if out is None:
         out = torch.empty((hv.shape[0], Q.n), dtype=torch.float64, device="cuda")
-    o = _opts(precision=precision, force_method=force_method, profile=profile)
+    o = _opts(precision=precision, force_method=force_method, profile=profile, cost_exhaustive=cost_exhaustive)
     stats = stats or profile
     st = Stats() if stats else None
     _check(lib().dfgt_gauss_sum(Q.handle, R.handle, hp, hv.shape[0], float(eps), C.byref(o),
@@ -205,7 +207,7 @@ def _vp(t):
 
 
 def gauss_sum_grad(Q: Tree, R: Tree, h, eps, dh=True, dq=True, precision=PREC_MIXED, force_method=FORCE_NONE,
-                   stats=False):
+                   stats=False, profile=False):
     """dfgt_gauss_sum_grad: G (n_h, NQ), dG/dh (n_h, NQ) or None, dG/dq (n_h, NQ, d) or None [, stats]."""
     torch = _torch()
     hv, hp = _hvec(h)
@@ -213,7 +215,8 @@ def gauss_sum_grad(Q: Tree, R: Tree, h, eps, dh=True, dq=True, precision=PREC_MI
     G = torch.empty((nh, Q.n), dtype=torch.float64, device="cuda")
     Gh = torch.empty((nh, Q.n), dtype=torch.float64, device="cuda") if dh else None
     Gq = torch.empty((nh, Q.n, Q.d), dtype=torch.float64, device="cuda") if dq else None
-    o = _opts(precision=precision, force_method=force_method)
+    o = _opts(precision=precision, force_method=force_method, profile=profile)
+    stats = stats or profile
     st = Stats() if stats else None
     _check(lib().dfgt_gauss_sum_grad(Q.handle, R.handle, hp, nh, float(eps), C.byref(o), _vp(G), _vp(Gh), _vp(Gq),
                                      C.byref(st) if st is not None else None, _stream()))

@@ -11,7 +11,11 @@ pairs dominate): a log-spaced grid over
 h_S * [1e-2, 10] (h_S = Silverman's rule), then golden-section search on log h
 to 1e-3 relative.
 
-    python tests/golden/make_hstar.py c2 [c3 ...]
+    python tests/golden/make_hstar.py c2 [c3 c5_sub5k ...]
+
+c5_sub5k is the 16-D workload's seeded 5,000-point subsample: its h* stands
+for the full set's (the LSCV sums over 200,000 points are out of the
+oracle's reach).
 """
 import json
 import math
@@ -28,7 +32,16 @@ import oracle  # noqa: E402
 from paper_1102_2878_amd import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "hstar.json")
-GENERATORS = {"c1": synth.c1, "c2": synth.c2, "c3": synth.c3}
+
+
+def c5_sub5k():
+    """The 16-D workload's seeded 5,000-point subsample (its h* is estimated there)."""
+    x = synth.c5()
+    return x[synth.subsample(x, 5000, 5)]
+
+
+GENERATORS = {"c1": synth.c1, "c2": synth.c2, "c3": synth.c3, "c5_sub5k": c5_sub5k}
+GEN_NAMES = {"c5_sub5k": "tests/golden/make_hstar.py:c5_sub5k() = synth.c5()[synth.subsample(x, 5000, 5)]"}
 
 
 def cv(x, h):
@@ -64,7 +77,8 @@ def main(names):
         t = time.time()
         h, hs, v = hstar(x)
         data[nm] = {"h_star": h, "h_silverman": hs, "cv_ls": v, "lscv_variant": 1, "n": int(x.shape[0]), "d": int(x.shape[1]),
-                    "generator": f"paper_1102_2878_amd.synth.{nm}()", "seconds": round(time.time() - t, 1)}
+                    "generator": GEN_NAMES.get(nm, f"paper_1102_2878_amd.synth.{nm}()"),
+                    "seconds": round(time.time() - t, 1)}
         print(nm, data[nm], flush=True)
         json.dump(data, open(OUT, "w"), indent=2, sort_keys=True)
 
