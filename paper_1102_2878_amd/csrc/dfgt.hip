@@ -121,47 +121,59 @@ __device__ __forceinline__ double powi(double x, int e) {
     return r;
 }
 
-// sum_{k<D} C(D,k) a^k b^{D-k}
-__device__ double binom_mix(double a, double b, int D) {
-    double c = 1.0, sum = 0.0;
-    for (int k = 0; k < D; ++k) {
-        sum += c * powi(a, k) * powi(b, D - k);
-        c = c * (double)(D - k) / (double)(k + 1);
+// 1/sqrt(p!) for p = 0..16 (p_max <= 16), the factor of Szasz's inequality in
+// the truncation bounds.
+__constant__ double kInvSqrtFact[17] = {
+    1.0, 1.0, 0.7071067811865476, 0.408248290463863, 0.2041241452319315, 0.09128709291752768,
+    0.037267799624996496, 0.014085904245475277, 0.004980119205559973, 0.0016600397351866577,
+    0.00052495065695726, 0.00015827857841616382, 4.569108992776174e-05, 1.2672428274337011e-05,
+    3.3868489186454308e-06, 8.744806305356235e-07, 2.1862015763390587e-07};
+
+// sum_{k<D} C(D,k) a^k b^{D-k} = (a+b)^D - a^D = b sum_{k<D} (a+b)^k a^{D-1-k},
+// evaluated in the last form: positive terms only, so no cancellation when
+// b << a (the bound stays an upper bound to a few ulps).
+__device__ __forceinline__ double binom_tail(double a, double b, int D) {
+    const double c = a + b;
+    double t = 1.0, aj = 1.0;
+    for (int j = 1; j < D; ++j) {
+        aj *= a;
+        t = fma(c, t, aj);
     }
-    return sum;
-}
-
-// Far-field / local lemma bound, eqs. (error_bound_far_field), (error_bound_local).
-__device__ double bound_far(double r, int p, int D, double nR) {
-    const double rp = powi(r, p);
-    const double b = rp * sqrt(inv_factorial(p));
-    return nR * binom_mix(1.0 - rp, b, D) / powi(1.0 - r, D);
-}
-
-// Far-to-local lemma bound, eq. (error_bound_far_to_local) (its formula holds 2r).
-__device__ double bound_f2l(double r, int p, int D, double nR) {
-    const double tp = powi(2.0 * r, p);
-    const double a = (1.0 - tp) * (1.0 - tp);
-    const double b = tp * (2.0 - tp) * sqrt(inv_factorial(p));
-    return nR * binom_mix(a, b, D) / powi(1.0 - 2.0 * r, 2 * D);
+    return b * t;
 }
 
 // Bounds are compared with a small relative slack on the safe side.
 constexpr double kSlack = 1.0 + 1e-10;
 
-// Alg. FarFieldOrder / LocalAccumulationOrder: r = width / (2h); 0 = infinity.
+// Alg. FarFieldOrder / LocalAccumulationOrder with the far-field / local lemma
+// bound, eqs. (error_bound_far_field), (error_bound_local):
+//   nR sum_{k<D} C(D,k) (1 - r^p)^k (r^p / sqrt(p!))^{D-k} / (1 - r)^D <= tau,
+// r = width / (2h); returns the least such p <= pmax, 0 = none (r >= 1: no bound).
+// r^p runs incrementally and the division is multiplied out.
 __device__ int order_far(double r, double nR, double tau, int pmax, int D) {
     if (r >= 1.0) return 0;
-    for (int p = 1; p <= pmax; ++p)
-        if (bound_far(r, p, D, nR) * kSlack <= tau) return p;
+    const double lim = tau * powi(1.0 - r, D);
+    double rp = 1.0;
+    for (int p = 1; p <= pmax; ++p) {
+        rp *= r;
+        if (nR * binom_tail(1.0 - rp, rp * kInvSqrtFact[p], D) * kSlack <= lim) return p;
+    }
     return 0;
 }
 
-// Alg. ConvertFarFieldToLocalOrder, read with the lemma's radius r = width / (2h) < 1/2.
+// Alg. ConvertFarFieldToLocalOrder with the far-to-local lemma bound, eq.
+// (error_bound_far_to_local), read with the lemma's radius r = width / (2h) < 1/2
+// (its formula holds 2r):
+//   nR sum_{k<D} C(D,k) ((1 - (2r)^p)^2)^k ((2r)^p (2 - (2r)^p) / sqrt(p!))^{D-k} / (1 - 2r)^{2D} <= tau.
 __device__ int order_f2l(double r, double nR, double tau, int pmax, int D) {
     if (r >= 0.5) return 0;
-    for (int p = 1; p <= pmax; ++p)
-        if (bound_f2l(r, p, D, nR) * kSlack <= tau) return p;
+    const double lim = tau * powi(1.0 - 2.0 * r, 2 * D);
+    double tp = 1.0;
+    for (int p = 1; p <= pmax; ++p) {
+        tp *= 2.0 * r;
+        const double a = (1.0 - tp) * (1.0 - tp);
+        if (nR * binom_tail(a, tp * (2.0 - tp) * kInvSqrtFact[p], D) * kSlack <= lim) return p;
+    }
     return 0;
 }
 
@@ -202,12 +214,13 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // the centroid form is not used; F is unchanged (its derivative series is the
 // far-field series of the derivative kernel, one Hermite index higher).
 __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double tau,
-                      int pmax, int D, int force, int gr, double cost_e, int *order) {
+                      int pmax, int D, int force, int gr, double cost_e, int *order, double *kc_out) {
     if (force == DFGT_FORCE_EXACT) {
         *order = 0;
         return METH_E;
     }
     const double kl = exp(-g.sl * inv2h2), kc = exp(-g.sc * inv2h2);
+    *kc_out = kc;
     const double cb = nR * (fmax(kl - kc, kc - ku) + 1e-15 * kl);
     const bool centroid = !gr && cb <= tau;
     if (centroid && force == DFGT_FORCE_NONE) {
@@ -275,6 +288,7 @@ struct TravOut {
     int *lvl_next;  // per-level counters written by this level
     int *overflow;
     unsigned long long *stats;
+    double *cval;    // [job][node] constant local terms from order-1 translations
     int want_stats;  // collect dfgt_stats counters
     Caps cap;
 };
@@ -290,7 +304,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 // One wave per segment.
 __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Seg sg,
                                  const int *__restrict__ pairs, int force, int gr, int leaf_local, int *dec,
-                                 const TravOut &o) {
+                                 double *kus, const TravOut &o) {
     const int lane = threadIdx.x;
     const Job jb = jobs[sg.job];
     const DevTree &Q = trees[jb.qt];
@@ -305,31 +319,39 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     for (int i = lane; i < sg.count; i += 64) {
         const int r = pairs[sg.start + i];
         const PairGeom g = pair_geom(Q, q, R, r);
-        sl += (double)(R.end[r] - R.begin[r]) * exp(-g.su * jb.inv2h2);
+        const double ku = exp(-g.su * jb.inv2h2);
+        kus[sg.start + i] = ku;  // reused by the decisions below
+        sl += (double)(R.end[r] - R.begin[r]) * ku;
     }
     sl = wave_sum(sl);
     const double gl = fmax((sg.gl + sl) * (1.0 - 1e-12), jb.prior);
 
     // 2. decisions and counts
     int cE = 0, cF = 0, cL = 0, cN = 0, nT = 0, nC = 0, nD = 0, maxord = 0;
-    double plo = 0.0, ept = 0.0;
+    double plo = 0.0, ept = 0.0, ccon = 0.0;
     for (int i = lane; i < sg.count; i += 64) {
         const int r = pairs[sg.start + i];
         const PairGeom g = pair_geom(Q, q, R, r);
         const double nR = (double)(R.end[r] - R.begin[r]);
         const double tau = jb.eps_eff * nR * gl / jb.nR;
-        const double ku = exp(-g.su * jb.inv2h2);
+        const double ku = kus[sg.start + i];
         int ord = 0;
-        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, jb.cost_e, &ord);
+        double kc = 0.0;
+        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, jb.cost_e, &ord, &kc);
         const bool rleaf = R.left[r] < 0;
         if (m != METH_E) {
             plo += nR * ku;
             if (m == METH_F) ++cF;
-            else {
+            else if (m == METH_T && ord == 1) {
+                // order-1 far-to-local translation (the centroid form): its only
+                // term is L_0 += mu_0 e^{-|t0|^2} = |R| K(|Q.c - R.c|), a scalar
+                // added to Q's constant term right here (no op)
+                ccon += nR * kc;
+                ++nC;
+            } else {
                 // a D op is emitted as one op per chunk of <= 64 reference points
                 cL += m == METH_D ? (int)((nR + 63.0) / 64.0) : 1;
                 if (m == METH_D) ++nD;
-                else if (ord == 1) ++nC;
                 else ++nT;
             }
             maxord = max(maxord, ord);
@@ -348,6 +370,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     wave_excl(cN, &tN);
     plo = wave_sum(plo);
     ept = wave_sum(ept);
+    ccon = wave_sum(ccon);
     const double gl_child = sg.gl + plo * (1.0 - 1e-12);
     const int nFp = wave_sum_i(cF), nDp = wave_sum_i(nD), nTp = wave_sum_i(nT), nCp = wave_sum_i(nC);
     int mo = maxord;
@@ -405,6 +428,9 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
             }
         }
         if (over) atomicExch(o.overflow, 1);
+        // one segment per (node, job) per level and levels run in order: a
+        // plain read-modify-write, deterministic
+        if (ccon != 0.0) o.cval[hq] += ccon;
     }
     if (o.want_stats) {  // counters for dfgt_stats, one lane each (no return values)
         if (lane == 8) atomicAdd(&o.stats[S_PAIRS * SP], (unsigned long long)sg.count);
@@ -433,7 +459,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
             ord = v >> 4;
             rleaf = R.left[r] < 0;
             if (m == METH_F) f = 1;
-            else if (m != METH_E) l = m == METH_D ? (R.end[r] - R.begin[r] + 63) / 64 : 1;
+            else if (m != METH_E) l = m == METH_D ? (R.end[r] - R.begin[r] + 63) / 64 : (ord == 1 ? 0 : 1);
             else if (qleaf && rleaf) e = 1;
             else n = (qleaf || !rleaf) ? 2 : 1;
         }
@@ -474,11 +500,11 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
 __global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                  const Seg *__restrict__ segs, const int *__restrict__ pairs,
                                                  const int *__restrict__ lvl_in, int nseg0, int force, int gr,
-                                                 int leaf_local, int *dec, TravOut o) {
+                                                 int leaf_local, int *dec, double *kus, TravOut o) {
     if (*o.overflow) return;
     const int nseg = lvl_in ? min(lvl_in[C_SEG * CP], o.cap.seg) : nseg0;
     for (int si = blockIdx.x; si < nseg; si += gridDim.x)
-        traverse_segment(trees, jobs, segs[si], pairs, force, gr, leaf_local, dec, o);
+        traverse_segment(trees, jobs, segs[si], pairs, force, gr, leaf_local, dec, kus, o);
 }
 
 // ---------------------------------------------------------------- local moments: D and T ops
@@ -624,7 +650,8 @@ constexpr int kMaxDepth = 256;  // deepest tree the per-leaf kernel walks
 // Local ops run fully in parallel: one wave per op (a D op is one chunk of
 // <= 64 reference points), each writing its contribution to Q's local
 // moments into its own row of `part`; per-node sums then add the rows in
-// chain order.  An order-1 T op (the centroid form) only has a zeroth term.
+// chain order.  (Order-1 translations never reach here: the traversal adds
+// their single term to the node's constant.)
 // Rows hold PW = P (GR = false) or 2P doubles: L, then the tangent moments.
 // LDS per block: cb[P] | dg[P] (u64) | mt[P] (u16) | per wave: lop_wave_stride doubles
 template <bool GR>
@@ -657,19 +684,6 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
         const int r = op.r, p = op.meta & 255, m = (op.meta >> 8) & 15, ch = op.meta >> 12;
         double *dst = part + (size_t)oi * PW;
         const double *qc = Q.ctr + (size_t)g.q * d;
-        if (m == METH_T && p == 1) {
-            if (lane == 0) {
-                double tt = 0.0;
-                for (int k = 0; k < d; ++k) {
-                    const double t = (qc[k] - R.ctr[(size_t)r * d + k]) * jb.s;
-                    tt += t * t;
-                }
-                const double v = tt > 745.0 ? 0.0 : R.mu[(size_t)r * P] * exp(-tt);
-                dst[0] = v;
-                if (GR) dst[P] = -2.0 * tt * v;
-            }
-            continue;
-        }
         for (int i = lane; i < P; i += 64) {
             acc[i] = 0.0;
             if (GR) accB[i] = 0.0;
@@ -687,23 +701,15 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
 }
 
 // Adds the op rows (PW doubles, coefficient i of L at i and of the tangent at
-// P + i) of one node's chain in chain order: acc += part[op] (the zeroth terms
-// only for order-1 T ops).  Threads over the PW entries.
+// P + i) of one node's chain in chain order: acc += part[op].  Threads over
+// the PW entries.
 __device__ __forceinline__ void sum_chain_parts(int head, const Group *__restrict__ lgrp, const Op *__restrict__ lops,
                                                 const double *__restrict__ part, int P, int PW, double *acc) {
     for (int i = threadIdx.x; i < PW; i += blockDim.x) {
         double v = acc[i];
-        const bool zeroth = i == 0 || i == P;
         for (int gi = head; gi >= 0; gi = lgrp[gi].next) {
             const Group g = lgrp[gi];
-            for (int o = g.start; o < g.start + g.count; ++o) {
-                const int meta = lops[o].meta;
-                if (((meta >> 8) & 15) == METH_T && (meta & 255) == 1) {
-                    if (zeroth) v += part[(size_t)o * PW + i];
-                } else {
-                    v += part[(size_t)o * PW + i];
-                }
-            }
+            for (int o = g.start; o < g.start + g.count; ++o) v += part[(size_t)o * PW + i];
         }
         acc[i] = v;
     }
@@ -1059,9 +1065,10 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               int leaf_local, const int *__restrict__ overflow,
                                               const double *__restrict__ part, double *__restrict__ gscratch,
                                               const double *__restrict__ extE, const double *__restrict__ extX,
-                                              const double *__restrict__ extY) {
+                                              const double *__restrict__ extY, const double *__restrict__ cval) {
     extern __shared__ double smem[];
     if (*overflow) return;
+    __shared__ double cs_s;
     __shared__ int path[kMaxDepth];
     __shared__ unsigned char lfl[kMaxDepth];
     __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg], ccnt[kMaxDepth + 1];
@@ -1118,6 +1125,15 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     }
     for (int i = tid; i < ns; i += nthr) spow[i] = powi(s, i);
     const int anyl = __syncthreads_or(mine);
+    // constant local terms (order-1 translations) of the path nodes, root first:
+    // translating a constant expansion leaves it unchanged
+    if (tid == 0) {
+        double c = 0.0;
+        for (int k = plen - 1; k >= 0; --k) c += cval[jb.noff + path[k]];
+        cs_s = c;
+    }
+    __syncthreads();
+    const double csum = cs_s;
     const int qb = Q.begin[leaf], nq = Q.end[leaf] - qb;
     // 1. local moments at the leaf: the moments of every ancestor v that has
     //    any, translated straight to the leaf centre (TransLocalToLocal; the
@@ -1410,7 +1426,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             const int dst = Q.perm[qpos];
             const size_t ei = (size_t)job * Q.n + qpos;
             if (extE) gsum += extE[ei];
-            jb.out[dst] = gl + gsum;
+            jb.out[dst] = (gl + csum) + gsum;
             if (GR) {
                 if (extE) {
                     xsum += extX[ei];
@@ -1704,7 +1720,7 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_POST = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, L, lflag, heads, segA, segB, pairA, pairB, dec, egrp, eops, fgrp, fops, lgrp, lops, lnodes,
-        cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY;
+        cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, kus, cval;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
 };
 thread_local Workspace g_ws;
@@ -1781,6 +1797,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
     const size_t nna = (size_t)nh * MQ;
     DFGT_TRY(grow<double>(w.L, nna * PW));
     DFGT_TRY(grow<unsigned char>(w.lflag, nna));
+    DFGT_TRY(grow<double>(w.cval, nna));
     DFGT_TRY(grow<int>(w.heads, 3 * nna));
     DFGT_TRY(grow<int>(w.cnt, C_N * CP));
     DFGT_TRY(grow<int>(w.flag, 1));
@@ -1833,6 +1850,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
         DFGT_TRY(grow<int>(w.pairA, cap.pair));
         DFGT_TRY(grow<int>(w.pairB, cap.pair));
         DFGT_TRY(grow<int>(w.dec, cap.pair));
+        DFGT_TRY(grow<double>(w.kus, cap.pair));
         DFGT_TRY(grow<Group>(w.egrp, cap.grp));
         DFGT_TRY(grow<Group>(w.fgrp, cap.grp));
         DFGT_TRY(grow<Group>(w.lgrp, cap.grp));
@@ -1845,6 +1863,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
             DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * PW));
         }
         DFGT_HIP(hipMemsetAsync(w.lflag.p, 0, nna, st));
+        DFGT_HIP(hipMemsetAsync(w.cval.p, 0, sizeof(double) * nna, st));
         DFGT_HIP(hipMemsetAsync(w.heads.p, 0xff, sizeof(int) * 3 * nna, st));
         DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * C_N * CP, st));
         DFGT_HIP(hipMemsetAsync(w.lvl.p, 0, sizeof(int) * (nlev + 1) * 2 * CP, st));
@@ -1860,11 +1879,11 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                       w.fgrp.as<Group>(), w.fops.as<Op>(),  w.lgrp.as<Group>(), w.lops.as<Op>(),
                       w.lnodes.as<int>(), headE,            headF,              headL,
                       w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
-                      w.stats.as<unsigned long long>(),     stats_out != nullptr ? 1 : 0, cap};
+                      w.stats.as<unsigned long long>(),     w.cval.as<double>(), stats_out != nullptr ? 1 : 0, cap};
             hipEvent_t ev = prof.start(st);
             hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
                                k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, nh, force, gr ? 1 : 0,
-                               leaf_local ? 1 : 0, w.dec.as<int>(), o);
+                               leaf_local ? 1 : 0, w.dec.as<int>(), w.kus.as<double>(), o);
             DFGT_HIP(hipGetLastError());
             prof.stop(K_TRAV, ev, st);
         }
@@ -1943,7 +1962,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
                                leaf_local ? w.part.as<double>() : (const double *)nullptr, scr,
                                emfma ? w.extE.as<double>() : (const double *)nullptr,
                                emfma && gr ? w.extX.as<double>() : (const double *)nullptr,
-                               emfma && gr ? w.extY.as<double>() : (const double *)nullptr);
+                               emfma && gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>());
             DFGT_HIP(hipGetLastError());
             prof.stop(K_LEAF, ev, st);
         }
