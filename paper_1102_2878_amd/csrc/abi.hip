@@ -106,8 +106,7 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
         v.lpath = t->lpath.as<int32_t>();
         v.lplen = t->lplen.as<int32_t>();
         t->host_view = v;
-        s = t->view.reserve(sizeof(DevTree));
-        if (s == DFGT_OK) {
+        {  // the view's storage was carved out with the moments
             if (hipMemcpyAsync(t->view.p, &v, sizeof(DevTree), hipMemcpyHostToDevice, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess) {
                 set_error("dfgt_build_tree: copying the tree view failed");
@@ -150,7 +149,7 @@ dfgt_status dfgt_tree_export(dfgt_tree t, int32_t *perm, double *lo, double *hi,
     const size_t m = (size_t)t->m, d = (size_t)t->d;
     struct Item {
         void *dst;
-        const DevBuf *src;
+        const DevSpan *src;
         size_t bytes;
     } items[] = {
         {perm, &t->perm, sizeof(int32_t) * (size_t)t->n}, {lo, &t->lo, sizeof(double) * m * d},

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <initializer_list>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dfgt.h"
@@ -77,6 +79,29 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// A typed view into device memory owned elsewhere (an arena).
+struct DevSpan {
+    void *p = nullptr;
+    size_t bytes = 0;
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Carves several spans out of one allocation (256-byte aligned pieces), so a
+// tree costs a few hipMalloc calls instead of one per array.
+inline dfgt_status alloc_spans(DevBuf &arena, std::initializer_list<std::pair<DevSpan *, size_t>> items) {
+    size_t total = 0;
+    for (auto &it : items) total += (it.second + 255) / 256 * 256;
+    DFGT_TRY(arena.reserve(total));
+    char *base = static_cast<char *>(arena.p);
+    size_t off = 0;
+    for (auto &it : items) {
+        it.first->p = base + off;
+        it.first->bytes = it.second;
+        off += (it.second + 255) / 256 * 256;
+    }
+    return DFGT_OK;
+}
+
 // ---------------------------------------------------------------- device views
 // Read-only device view of one kd-tree (breadth-first node order).
 struct DevTree {
@@ -101,10 +126,13 @@ struct dfgt_tree_s {
     int32_t d = 0, leaf = 32, pmax = 1, P = 1, depth = 0, precision = 0, force = 0;
     int64_t m = 0, nleaves = 0;
     std::vector<int32_t> level_start;  // host copy: nodes of level l are [level_start[l], level_start[l+1])
-    dfgt::DevBuf lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max,
+    // arena0: point and node-capacity arrays; arena1: per-node and per-leaf
+    // arrays sized after the build; arena2: moments, norms and the device view
+    dfgt::DevBuf arena0, arena1, arena2;
+    dfgt::DevSpan lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max,
         lpath, lplen;
     double max_nrm = 0.0;  // max |x|^2 (valid after dfgt_build_tree returns)
-    dfgt::DevBuf view;  // a DevTree in device memory
+    dfgt::DevSpan view;    // a DevTree in device memory
     dfgt::DevTree host_view{};
 };
 

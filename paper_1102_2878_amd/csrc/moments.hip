@@ -110,8 +110,10 @@ __global__ void k_tree_sqnorm(const double *__restrict__ x, int n, int d, double
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     {
         const int n = (int)t->n;
-        DFGT_TRY(t->nrm.reserve(sizeof(double) * (size_t)n));
-        DFGT_TRY(t->nrm_max.reserve(sizeof(unsigned long long)));
+        DFGT_TRY(alloc_spans(t->arena2, {{&t->nrm, sizeof(double) * (size_t)n},
+                                         {&t->nrm_max, sizeof(unsigned long long)},
+                                         {&t->mu, sizeof(double) * (size_t)t->m * t->P},
+                                         {&t->view, sizeof(DevTree)}}));
         DFGT_HIP(hipMemsetAsync(t->nrm_max.p, 0, sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_tree_sqnorm, dim3((n + 255) / 256), dim3(256), 0, st, t->x.as<double>(), n, t->d,
                            t->nrm.as<double>(), t->nrm_max.as<unsigned long long>());
@@ -120,13 +122,12 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     }
     const int d = t->d, pmax = t->pmax, P = t->P;
     const int64_t m = t->m;
-    DFGT_TRY(t->mu.reserve(sizeof(double) * (size_t)m * P));
     hipLaunchKernelGGL(k_p2m, dim3((unsigned)t->nleaves), dim3(64), 0, st, t->x.as<double>(), t->ctr.as<double>(),
                        t->begin.as<int32_t>(), t->end.as<int32_t>(), t->leaves.as<int32_t>(), d, pmax, P,
                        t->mu.as<double>());
     DFGT_HIP(hipGetLastError());
     const bool lds = (size_t)(2 * P + pmax * pmax) * sizeof(double) <= 48 * 1024;
-    DevBuf scratch;
+    static thread_local DevBuf scratch;  // reused across builds (freeing it would stall the device)
     int maxw = 0;
     for (int l = 0; l + 1 < (int)t->level_start.size(); ++l)
         maxw = std::max(maxw, t->level_start[l + 1] - t->level_start[l]);

@@ -366,13 +366,29 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
 
 }  // namespace
 
+// Scratch of the build, kept per host thread and reused across builds.
+struct BuildWs {
+    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, scan, bsums, lo_key, hi_key, nleft, counter, lvs;
+};
+thread_local BuildWs g_build;
+
 dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st) {
     const int n = (int)t->n, d = t->d, leaf = t->leaf;
     const int cap = 2 * n + 1;
-    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, scan, bsums, lo_key, hi_key, nleft, counter, lvs_b;
-    DFGT_TRY(t->perm.reserve(sizeof(int32_t) * n));
+    BuildWs &w = g_build;
+    DevBuf &perm_b = w.perm_b, &x_b = w.x_b, &pnode_a = w.pnode_a, &pnode_b = w.pnode_b, &flag = w.flag,
+           &scan = w.scan, &bsums = w.bsums, &lo_key = w.lo_key, &hi_key = w.hi_key, &nleft = w.nleft,
+           &counter = w.counter, &lvs_b = w.lvs;
+    DFGT_TRY(alloc_spans(t->arena0, {{&t->perm, sizeof(int32_t) * n},
+                                     {&t->x, sizeof(double) * (size_t)n * d},
+                                     {&t->begin, sizeof(int32_t) * cap},
+                                     {&t->end, sizeof(int32_t) * cap},
+                                     {&t->left, sizeof(int32_t) * cap},
+                                     {&t->right, sizeof(int32_t) * cap},
+                                     {&t->parent, sizeof(int32_t) * cap},
+                                     {&t->sdim, sizeof(int32_t) * cap},
+                                     {&t->scoord, sizeof(double) * cap}}));
     DFGT_TRY(perm_b.reserve(sizeof(int32_t) * n));
-    DFGT_TRY(t->x.reserve(sizeof(double) * (size_t)n * d));
     DFGT_TRY(x_b.reserve(sizeof(double) * (size_t)n * d));
     DFGT_TRY(pnode_a.reserve(sizeof(int32_t) * n));
     DFGT_TRY(pnode_b.reserve(sizeof(int32_t) * n));
@@ -388,13 +404,6 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     // leaves fewer points on each side)
     const int max_levels = n + 1;
     DFGT_TRY(lvs_b.reserve(sizeof(int) * 2 * ((size_t)max_levels + 1)));
-    DFGT_TRY(t->begin.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(t->end.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(t->left.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(t->right.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(t->parent.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(t->sdim.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(t->scoord.reserve(sizeof(double) * cap));
 
     int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
     double *xa = t->x.as<double>(), *xb = x_b.as<double>();
@@ -484,10 +493,15 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
         DFGT_HIP(hipMemcpyAsync(t->perm.p, pa, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
         DFGT_HIP(hipMemcpyAsync(t->x.p, xa, sizeof(double) * (size_t)n * d, hipMemcpyDeviceToDevice, st));
     }
-    DFGT_TRY(t->lo.reserve(sizeof(double) * (size_t)m * d));
-    DFGT_TRY(t->hi.reserve(sizeof(double) * (size_t)m * d));
-    DFGT_TRY(t->ctr.reserve(sizeof(double) * (size_t)m * d));
-    DFGT_TRY(t->leaves.reserve(sizeof(int32_t) * m));
+    // per-node arrays, and the leaves' root paths (at most m leaves; only for
+    // trees of <= 256 levels, the deepest the summation kernels walk)
+    const size_t pstride = t->depth <= 256 ? (size_t)t->depth : 0;
+    DFGT_TRY(alloc_spans(t->arena1, {{&t->lo, sizeof(double) * (size_t)m * d},
+                                     {&t->hi, sizeof(double) * (size_t)m * d},
+                                     {&t->ctr, sizeof(double) * (size_t)m * d},
+                                     {&t->leaves, sizeof(int32_t) * m},
+                                     {&t->lpath, sizeof(int32_t) * (size_t)m * pstride},
+                                     {&t->lplen, sizeof(int32_t) * (size_t)m}}));
     hipLaunchKernelGGL(k_decode_boxes, dim3((m * d + 255) / 256), dim3(256), 0, st, m, d, lo_key.as<long long>(),
                        hi_key.as<long long>(), t->lo.as<double>(), t->hi.as<double>(), t->ctr.as<double>());
     hipLaunchKernelGGL(k_collect_leaves, dim3(1), dim3(1024), 0, st, m, t->left.as<int32_t>(),
@@ -497,11 +511,11 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     DFGT_HIP(hipMemcpyAsync(&nl, cnt_d + 2, sizeof(int), hipMemcpyDeviceToHost, st));
     DFGT_HIP(hipStreamSynchronize(st));
     t->nleaves = nl;
-    DFGT_TRY(t->lpath.reserve(sizeof(int32_t) * (size_t)nl * t->depth));
-    DFGT_TRY(t->lplen.reserve(sizeof(int32_t) * (size_t)nl));
-    hipLaunchKernelGGL(k_leaf_paths, dim3((nl + 255) / 256), dim3(256), 0, st, t->leaves.as<int32_t>(), nl,
-                       t->parent.as<int32_t>(), t->depth, t->lpath.as<int32_t>(), t->lplen.as<int32_t>());
-    DFGT_HIP(hipGetLastError());
+    if (pstride > 0) {
+        hipLaunchKernelGGL(k_leaf_paths, dim3((nl + 255) / 256), dim3(256), 0, st, t->leaves.as<int32_t>(), nl,
+                           t->parent.as<int32_t>(), t->depth, t->lpath.as<int32_t>(), t->lplen.as<int32_t>());
+        DFGT_HIP(hipGetLastError());
+    }
     return DFGT_OK;
 }
 
