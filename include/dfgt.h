@@ -252,6 +252,45 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
                             const dfgt_options *opt, double *cv_host, double *dcv_host, dfgt_stats *stats,
                             void *stream);
 
+/* One problem of a batch: the sums over R for the queries of Q at n_h
+ * bandwidths, into G_dev (n_h x NQ float64, caller-allocated, caller order). */
+typedef struct dfgt_problem {
+    dfgt_tree Q;
+    dfgt_tree R;          /* Q == R: the monochromatic case, self terms included */
+    const double *h_host; /* n_h bandwidths > 0 */
+    int32_t n_h;
+    double *G_dev;
+} dfgt_problem;
+
+/*
+ * Several problems of the same dimension and p_max, every bandwidth of each,
+ * in one traversal (Alg. DFGTMain per (problem, bandwidth); the jobs share the
+ * level-synchronous launches).  Same guarantee as dfgt_gauss_sum for every
+ * query of every problem and bandwidth; results do not depend on the other
+ * jobs of the batch (bitwise).  Options and errors as dfgt_gauss_sum; at most
+ * 2^20 (problem, bandwidth) jobs.
+ */
+dfgt_status dfgt_gauss_sum_batched(const dfgt_problem *probs, int32_t n_probs, double eps,
+                                   const dfgt_options *opt, dfgt_stats *stats, void *stream);
+
+/*
+ * A batch captured as a HIP graph, for callers that repeat the same sweep (or
+ * must not pay per-launch host overhead): dfgt_batch_create runs the batch
+ * once eagerly (which sizes every internal buffer; stats, if given, are that
+ * run's), then captures the whole launch sequence of one run into a graph
+ * that owns its workspace.  dfgt_batch_run replays it asynchronously on
+ * stream, rewriting every G_dev.  The trees, bandwidths and output buffers are
+ * fixed at creation: keep them alive and unchanged until dfgt_batch_free.
+ * dfgt_batch_check synchronises the stream and reports DFGT_EBOUND if the
+ * last run overflowed its buffers (which unchanged inputs cannot cause).
+ */
+typedef struct dfgt_batch_s *dfgt_batch;
+dfgt_status dfgt_batch_create(const dfgt_problem *probs, int32_t n_probs, double eps, const dfgt_options *opt,
+                              dfgt_stats *stats, void *stream, dfgt_batch *out);
+dfgt_status dfgt_batch_run(dfgt_batch b, void *stream);
+dfgt_status dfgt_batch_check(dfgt_batch b, void *stream);
+dfgt_status dfgt_batch_free(dfgt_batch b);
+
 #ifdef __cplusplus
 }
 #endif

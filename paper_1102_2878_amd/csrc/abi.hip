@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "dfgt_internal.h"
 
@@ -290,4 +291,66 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
     DFGT_GUARD_END
 }
 
+static dfgt_status collect_problems(const dfgt_problem *probs, int32_t n, double eps, const char *who,
+                                    std::vector<Problem> &out) {
+    DFGT_REQUIRE(probs != nullptr && n >= 1, std::string(who) + ": need at least one problem");
+    long long jobs = 0;
+    for (int i = 0; i < n; ++i) {
+        const dfgt_problem &p = probs[i];
+        DFGT_REQUIRE(p.Q && p.R && p.G_dev, std::string(who) + ": NULL tree or output in a problem");
+        DFGT_TRY(check_pair(p.Q, p.R, eps, who));
+        DFGT_TRY(check_bandwidths(p.h_host, p.n_h, who));
+        DFGT_REQUIRE(p.Q->d == probs[0].Q->d && p.Q->pmax == probs[0].Q->pmax,
+                     std::string(who) + ": all problems must share the dimension and p_max");
+        jobs += p.n_h;
+        out.push_back(Problem{p.Q, p.R, p.h_host, p.n_h, p.G_dev});
+    }
+    DFGT_REQUIRE(jobs <= (1 << 20), std::string(who) + ": more than 2^20 (problem, bandwidth) jobs");
+    return DFGT_OK;
+}
+
+dfgt_status dfgt_gauss_sum_batched(const dfgt_problem *probs, int32_t n_probs, double eps,
+                                   const dfgt_options *opt, dfgt_stats *stats, void *stream) {
+    DFGT_GUARD_BEGIN
+    std::vector<Problem> pr;
+    DFGT_TRY(collect_problems(probs, n_probs, eps, "dfgt_gauss_sum_batched", pr));
+    int precision, force, profile;
+    double cost_e;
+    DFGT_TRY(call_options(probs[0].R, opt, "dfgt_gauss_sum_batched", &precision, &force, &profile, &cost_e));
+    DFGT_REQUIRE(profile == 0 || stats != nullptr, "dfgt_gauss_sum_batched: profile needs a stats pointer");
+    return run_gauss_multi(pr.data(), (int)pr.size(), eps, precision, force, profile, cost_e, nullptr, stats,
+                           (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_batch_create(const dfgt_problem *probs, int32_t n_probs, double eps, const dfgt_options *opt,
+                              dfgt_stats *stats, void *stream, dfgt_batch *out) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(out != nullptr, "dfgt_batch_create: out is NULL");
+    *out = nullptr;
+    std::vector<Problem> pr;
+    DFGT_TRY(collect_problems(probs, n_probs, eps, "dfgt_batch_create", pr));
+    int precision, force, profile;
+    double cost_e;
+    DFGT_TRY(call_options(probs[0].R, opt, "dfgt_batch_create", &precision, &force, &profile, &cost_e));
+    DFGT_REQUIRE(profile == 0, "dfgt_batch_create: profiling is not supported for captured batches");
+    return batch_create(pr.data(), (int)pr.size(), eps, precision, force, cost_e, stats, (hipStream_t)stream, out);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_batch_run(dfgt_batch b, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(b != nullptr, "dfgt_batch_run: batch is NULL");
+    return batch_run(b, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_batch_check(dfgt_batch b, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(b != nullptr, "dfgt_batch_check: batch is NULL");
+    return batch_check(b, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
 }  // extern "C"
+// dfgt_batch_free is defined in dfgt.hip, where the batch type is complete.

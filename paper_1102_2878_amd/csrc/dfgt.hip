@@ -868,6 +868,33 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
     }
 }
 
+// Flattened (job, query leaf) items: job k owns items [jlstart[k], jlstart[k+1]).
+__device__ __forceinline__ void job_leaf(const int *__restrict__ jlstart, int njobs, int item, int *job, int *li) {
+    int lo = 0, hi = njobs;  // jlstart[lo] <= item < jlstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jlstart[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    *job = lo;
+    *li = item - jlstart[lo];
+}
+
+// Level-0 frontier: one segment (Q root, {R root}) per job.
+__global__ void k_seed(Seg *__restrict__ segs, int *__restrict__ pairs, int njobs) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= njobs) return;
+    segs[k] = Seg{0, k, k, 1, 0.0};
+    pairs[k] = 0;
+}
+
+// Fill with a 32-bit pattern (used instead of memset nodes, so the whole
+// launch sequence can be captured in a graph and replayed).
+__global__ void k_fill_u32(unsigned *__restrict__ p, size_t n, unsigned v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // ---------------------------------------------------------------- per query leaf
 // One block per (query leaf, job).
 //   1. TransLocalToLocal from the root down the path to the leaf (each step
@@ -1065,7 +1092,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               int leaf_local, const int *__restrict__ overflow,
                                               const double *__restrict__ part, double *__restrict__ gscratch,
                                               const double *__restrict__ extE, const double *__restrict__ extX,
-                                              const double *__restrict__ extY, const double *__restrict__ cval) {
+                                              const double *__restrict__ extY, const double *__restrict__ cval,
+                                              const int *__restrict__ jlstart, int njobs) {
     extern __shared__ double smem[];
     if (*overflow) return;
     __shared__ double cs_s;
@@ -1073,11 +1101,12 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     __shared__ unsigned char lfl[kMaxDepth];
     __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg], ccnt[kMaxDepth + 1];
     __shared__ int nsg_s, nops_s, ntot_s, nops1_s, st_phase, st_gi, st_pi;
-    const int job = blockIdx.y;
+    int job, li;
+    job_leaf(jlstart, njobs, blockIdx.x, &job, &li);
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
-    const int leaf = Q.leaves[blockIdx.x];
+    const int leaf = Q.leaves[li];
     const int d = Q.d, pmax = Q.pmax, P = Q.P;
     const int PW = GR ? 2 * P : P;
     const int hs = pmax + (GR ? 1 : 0);
@@ -1104,8 +1133,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         tmp2 = tmp + PW;
         coef = tmp2 + PW;
     } else {
-        const size_t slot = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        acc = gscratch + slot * 3 * PW;
+        acc = gscratch + (size_t)blockIdx.x * 3 * PW;
         tmp = acc + PW;
         tmp2 = tmp + PW;
         coef = tail;
@@ -1114,7 +1142,6 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
     build_digit_tables(dg, mt, P, d, pmax);
     // root path (precomputed with the tree: path[0] = the leaf, path[plen-1] = the root)
-    const int li = blockIdx.x;
     const int plen = Q.lplen[li];
     int mine = 0;
     for (int k = tid; k < plen; k += nthr) {
@@ -1424,7 +1451,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 }
             }
             const int dst = Q.perm[qpos];
-            const size_t ei = (size_t)job * Q.n + qpos;
+            const size_t ei = (size_t)jb.qoff + qpos;
             if (extE) gsum += extE[ei];
             jb.out[dst] = (gl + csum) + gsum;
             if (GR) {
@@ -1457,6 +1484,7 @@ template <bool GR, int NC>
 __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
                                                const int *__restrict__ headE, const int *__restrict__ overflow,
+                                               const int *__restrict__ jlstart, int njobs,
                                                double *__restrict__ GE, double *__restrict__ GX,
                                                double *__restrict__ GY) {
     constexpr int NT = (NC + 3) / 4;  // 16-dimension tiles of the gradient product
@@ -1467,12 +1495,13 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
     __shared__ double redY[GR ? 4 * NT * 256 : 1];
     if (*overflow) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4;
-    const int job = blockIdx.y;
+    int job, li;
+    job_leaf(jlstart, njobs, blockIdx.x, &job, &li);
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
-    const int leaf = Q.leaves[blockIdx.x];
-    const int d = Q.d, NQ = Q.n;
+    const int leaf = Q.leaves[li];
+    const int d = Q.d;
     const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
     const size_t hq = (size_t)jb.noff + leaf;
     const double sc2 = jb.sig * jb.sig;  // t = sc2 |q - r|^2, e = 2^-t
@@ -1645,15 +1674,15 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
         if (tid < 64 && qg + tid < nq) {
             const int pos = qb0 + qg + tid;
             const double ge = ((red[0][0][tid] + red[1][0][tid]) + red[2][0][tid]) + red[3][0][tid];
-            GE[(size_t)job * NQ + pos] = ge;
+            GE[(size_t)jb.qoff + pos] = ge;
             if (GR) {
                 const double gt = ((red[0][1][tid] + red[1][1][tid]) + red[2][1][tid]) + red[3][1][tid];
-                GX[(size_t)job * NQ + pos] = -2.0 * kLn2 * gt;
+                GX[(size_t)jb.qoff + pos] = -2.0 * kLn2 * gt;
                 const int b = tid >> 4, i = tid & 15;
                 const double *xq = Q.x + (size_t)pos * d;
                 for (int k = 0; k < d; ++k) {
                     const double sy = redY[(b * NT + (k >> 4)) * 256 + (i >> 2) * 64 + 16 * (i & 3) + (k & 15)];
-                    GY[((size_t)job * NQ + pos) * d + k] = -2.0 * jb.s * fma(xq[k], ge, -sy);
+                    GY[((size_t)jb.qoff + pos) * d + k] = -2.0 * jb.s * fma(xq[k], ge, -sy);
                 }
             }
         }
@@ -1719,8 +1748,8 @@ thread_local Profiler g_prof;
 enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_POST = 4 };
 
 struct Workspace {
-    DevBuf jobs, trees, L, lflag, heads, segA, segB, pairA, pairB, dec, egrp, eops, fgrp, fops, lgrp, lops, lnodes,
-        cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, kus, cval;
+    DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
+        lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
 };
 thread_local Workspace g_ws;
@@ -1732,9 +1761,11 @@ constexpr int kLocalGrid = 2048;
 
 template <bool GR>
 void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd, const Group *egrp,
-                  const int *eops, const int *headE, const int *flag, double *GE, double *GX, double *GY) {
-#define DFGT_EMFMA(NCV)                                                                                         \
-    hipLaunchKernelGGL((k_emfma<GR, NCV>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, GE, GX, GY); \
+                  const int *eops, const int *headE, const int *flag, const int *jls, int njobs, double *GE,
+                  double *GX, double *GY) {
+#define DFGT_EMFMA(NCV)                                                                                     \
+    hipLaunchKernelGGL((k_emfma<GR, NCV>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, jls, njobs, \
+                       GE, GX, GY);                                                                         \
     break;
     switch (nc) {
     case 2: DFGT_EMFMA(2)
@@ -1748,283 +1779,452 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
 #undef DFGT_EMFMA
 }
 
-}  // namespace
+// Everything about a call that does not depend on the traversal's output
+// sizes: the job and tree tables and the launch shapes.
+struct Plan {
+    std::vector<Job> jobs;
+    std::vector<DevTree> trees;
+    std::vector<int> jls;  // per-job prefix of (job, query leaf) items
+    int njobs = 0, nlev = 0, d = 0, pmax = 0, P = 0, PW = 0, precision = 0, force = 0, items = 0;
+    bool gr = false, leaf_local = true, emfma = false, acc_lds = true;
+    size_t nna = 0, nqa = 0;  // node slots and query slots over all jobs
+    int leaf_threads = 256, lop_waves = 4;
+    size_t leaf_sh = 0, lop_sh = 0, big_sh = 0;
+};
 
-dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int nh, double eps, int precision,
-                          int force, int profile, double cost_e, double *G, const GradOut *grad,
-                          dfgt_stats *stats_out, hipStream_t st) {
-    Workspace &w = g_ws;
-    Profiler &prof = g_prof;
-    const DevTree &Qv = Qh->host_view;
-    const int MQ = (int)Qh->m, P = Qh->P, pmax = Qh->pmax, d = Qh->d;
-    const int NQ = (int)Qh->n;
-    const bool mono = Qh == Rh;
-    const bool gr = grad != nullptr;
-    const int PW = gr ? 2 * P : P;  // local-moment row: L, then (gradient mode) its tangent
+dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int force, double cost_e,
+                      const GradOut *grad, Plan &pl) {
+    const dfgt_tree_s *t0 = pr[0].Q;
+    pl.d = t0->d;
+    pl.pmax = t0->pmax;
+    pl.P = t0->P;
+    pl.gr = grad != nullptr;
+    pl.PW = pl.gr ? 2 * pl.P : pl.P;
+    pl.force = force;
     // A tolerance below the mixed-precision rounding budget needs FP64 leaf sums.
     if (precision == DFGT_PREC_MIXED && eps > 0.0 && eps < 2e-5) precision = DFGT_PREC_FP64;
+    pl.precision = precision;
     // Rounding budget of the exhaustive sums (the global-error theorem takes
     // them as exact): mixed precision <= 1e-5 relative, FP64 ~1e-13.
     const double eps_round = precision == DFGT_PREC_FP64 ? 1e-12 : 1e-5;
     const double eps_eff = eps > 2.0 * eps_round ? eps - eps_round : 0.0;
-
-    std::vector<Job> jobs(nh);
-    for (int k = 0; k < nh; ++k) {
-        Job &j = jobs[k];
-        j.h = h[k];
-        j.s = 1.0 / (std::sqrt(2.0) * h[k]);
-        j.inv2h2 = 1.0 / (2.0 * h[k] * h[k]);
-        j.sig = 1.2011224087864498 * j.s;  // sqrt(log2 e) s: e^{-x^2/2h^2} = 2^{-(sig x)^2}
-        j.eps_eff = eps_eff;
-        j.nR = (double)Rh->n;
-        j.prior = 0.0;
-        j.qt = 0;
-        j.rt = 1;
-        j.qoff = (long long)k * NQ;
-        j.noff = (long long)k * MQ;
-        j.out = G + (size_t)k * NQ;
-        j.outH = gr && grad->dGdh ? grad->dGdh + (size_t)k * NQ : nullptr;
-        j.outQ = gr && grad->dGdq ? grad->dGdq + (size_t)k * NQ * d : nullptr;
-        j.mono = mono ? 1 : 0;
-        j.cost_e = cost_e;
-        j.pad = 0;
+    // a query leaf's own local ops are applied inside k_leaf when its per-wave
+    // scratch fits; otherwise they go through the node kernels
+    pl.leaf_local = pl.P <= 512;
+    if (pl.gr && !pl.leaf_local) {
+        set_error("dfgt_gauss_sum_grad: gradients need p_max^d <= 512");
+        return DFGT_EINVAL;
     }
-    DevTree tv[2] = {Qh->host_view, Rh->host_view};
-    DFGT_TRY(grow<Job>(w.jobs, nh));
-    DFGT_TRY(grow<DevTree>(w.trees, 2));
-    DFGT_HIP(hipMemcpyAsync(w.jobs.p, jobs.data(), sizeof(Job) * nh, hipMemcpyHostToDevice, st));
-    DFGT_HIP(hipMemcpyAsync(w.trees.p, tv, sizeof(tv), hipMemcpyHostToDevice, st));
-    const size_t nna = (size_t)nh * MQ;
-    DFGT_TRY(grow<double>(w.L, nna * PW));
-    DFGT_TRY(grow<unsigned char>(w.lflag, nna));
+    std::vector<const dfgt_tree_s *> th;
+    auto tree_index = [&](const dfgt_tree_s *t) {
+        for (size_t i = 0; i < th.size(); ++i)
+            if (th[i] == t) return (int)i;
+        th.push_back(t);
+        return (int)th.size() - 1;
+    };
+    pl.jls.assign(1, 0);
+    long long nna = 0, nqa = 0, items = 0;
+    for (int ip = 0; ip < np; ++ip) {
+        const Problem &q = pr[ip];
+        if (q.Q->depth > kMaxDepth) {
+            set_error("dfgt_gauss_sum: query tree deeper than 256 levels");
+            return DFGT_EINVAL;
+        }
+        const int qt = tree_index(q.Q), rt = tree_index(q.R);
+        for (int k = 0; k < q.nh; ++k) {
+            Job j{};
+            j.h = q.h[k];
+            j.s = 1.0 / (std::sqrt(2.0) * q.h[k]);
+            j.inv2h2 = 1.0 / (2.0 * q.h[k] * q.h[k]);
+            j.sig = 1.2011224087864498 * j.s;  // sqrt(log2 e) s: e^{-x^2/2h^2} = 2^{-(sig x)^2}
+            j.eps_eff = eps_eff;
+            j.nR = (double)q.R->n;
+            j.prior = 0.0;
+            j.qt = qt;
+            j.rt = rt;
+            j.qoff = nqa;
+            j.noff = nna;
+            j.out = q.G + (size_t)k * q.Q->n;
+            j.outH = pl.gr && grad->dGdh ? grad->dGdh + (size_t)k * q.Q->n : nullptr;
+            j.outQ = pl.gr && grad->dGdq ? grad->dGdq + (size_t)k * q.Q->n * pl.d : nullptr;
+            j.cost_e = cost_e;
+            j.mono = q.Q == q.R ? 1 : 0;
+            j.pad = 0;
+            pl.jobs.push_back(j);
+            nna += q.Q->m;
+            nqa += q.Q->n;
+            items += q.Q->nleaves;
+            if (items >= (1LL << 31)) {
+                set_error("dfgt_gauss_sum: too many (bandwidth, query leaf) items in one call");
+                return DFGT_EINVAL;
+            }
+            pl.jls.push_back((int)items);
+        }
+    }
+    pl.njobs = (int)pl.jobs.size();
+    pl.nna = (size_t)nna;
+    pl.nqa = (size_t)nqa;
+    pl.items = (int)items;
+    for (auto *t : th) {
+        pl.trees.push_back(t->host_view);
+        // every level splits Q and R wherever they can split, so no pair
+        // survives more levels than the deepest tree has
+        pl.nlev = std::max(pl.nlev, t->depth);
+    }
+    // exhaustive leaf sums on the matrix cores: mixed precision, D >= 8, and
+    // s^2 (|q|^2 + |r|^2) <= 2^26 for every bandwidth (rounding of the
+    // expanded squared distance below ~1e-7)
+    pl.emfma = precision == DFGT_PREC_MIXED && pl.d >= 8 && pl.d <= 32 && pl.nlev <= kMaxEGrp;
+    for (const Job &j : pl.jobs) {
+        if (!pl.emfma) break;
+        pl.emfma = j.sig * j.sig * (th[j.qt]->max_nrm + th[j.rt]->max_nrm) <= 67108864.0;
+    }
+    // launch shapes
+    const int d = pl.d, pmax = pl.pmax, P = pl.P, PW = pl.PW;
+    const int g1 = pl.gr ? 1 : 0;
+    if (pl.leaf_local) {
+        // waves per block of k_lops: as many (up to 4) as the LDS allows
+        const size_t wstride = lop_wave_stride(P, d, pmax, g1);
+        int lwv = 4;
+        for (;; lwv >>= 1) {
+            pl.lop_sh = sizeof(double) * ((size_t)P + (10 * (size_t)P + 7) / 8 + (size_t)lwv * wstride);
+            if (pl.lop_sh <= 64 * 1024 || lwv == 1) break;
+        }
+        if (pl.lop_sh > 64 * 1024) {
+            set_error("dfgt_gauss_sum: p_max^d too large for the local-op kernel");
+            return DFGT_EINVAL;
+        }
+        pl.lop_waves = lwv;
+    } else {
+        pl.big_sh = sizeof(double) * ((size_t)pmax * pmax + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax);
+    }
+    int nthr = 256;
+    while (nthr > 64 && sizeof(double) * leaf_lds_base(nthr, d, pmax, g1) > 40 * 1024) nthr >>= 1;
+    const size_t base = sizeof(double) * leaf_lds_base(nthr, d, pmax, g1);
+    const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
+    const size_t lds_coef = sizeof(double) * (size_t)d * pmax * pmax;
+    const size_t lds_acc = sizeof(double) * 3 * (size_t)PW + lds_coef;
+    // dynamic LDS up to 56 KB: the kernel's static arrays take ~6 KB of the 64 KB
+    pl.acc_lds = base + lds_acc + lds_dig <= 56 * 1024;
+    pl.leaf_sh = base + (pl.acc_lds ? lds_acc : lds_coef) + lds_dig;
+    pl.leaf_threads = nthr;
+    if (pl.leaf_sh > 56 * 1024) {
+        set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
+        return DFGT_EINVAL;
+    }
+    return DFGT_OK;
+}
+
+// Device buffers for the plan and the current capacities (no-op when large enough).
+dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
+    const Caps &cap = w.cap;
+    const size_t nna = pl.nna;
+    DFGT_TRY(grow<Job>(w.jobs, pl.njobs));
+    DFGT_TRY(grow<DevTree>(w.trees, pl.trees.size()));
+    DFGT_TRY(grow<int>(w.jls, pl.jls.size()));
+    DFGT_TRY(grow<double>(w.L, nna * pl.PW));
+    DFGT_TRY(grow<unsigned>(w.lflag, (nna + 3) / 4));
     DFGT_TRY(grow<double>(w.cval, nna));
     DFGT_TRY(grow<int>(w.heads, 3 * nna));
     DFGT_TRY(grow<int>(w.cnt, C_N * CP));
     DFGT_TRY(grow<int>(w.flag, 1));
     DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
+    DFGT_TRY(grow<int>(w.lvl, (size_t)(pl.nlev + 1) * 2 * CP));
+    if (pl.emfma) {
+        DFGT_TRY(grow<double>(w.extE, pl.nqa));
+        if (pl.gr) {
+            DFGT_TRY(grow<double>(w.extX, pl.nqa));
+            DFGT_TRY(grow<double>(w.extY, pl.nqa * pl.d));
+        }
+    }
+    DFGT_TRY(grow<Seg>(w.segA, cap.seg));
+    DFGT_TRY(grow<Seg>(w.segB, cap.seg));
+    DFGT_TRY(grow<int>(w.pairA, cap.pair));
+    DFGT_TRY(grow<int>(w.pairB, cap.pair));
+    DFGT_TRY(grow<int>(w.dec, cap.pair));
+    DFGT_TRY(grow<double>(w.kus, cap.pair));
+    DFGT_TRY(grow<Group>(w.egrp, cap.grp));
+    DFGT_TRY(grow<Group>(w.fgrp, cap.grp));
+    DFGT_TRY(grow<Group>(w.lgrp, cap.grp));
+    DFGT_TRY(grow<int>(w.lnodes, 2 * (size_t)cap.lnode));
+    DFGT_TRY(grow<int>(w.eops, cap.eop));
+    DFGT_TRY(grow<Op>(w.fops, cap.fop));
+    DFGT_TRY(grow<Op>(w.lops, cap.lop));
+    if (pl.leaf_local) {
+        DFGT_TRY(grow<int>(w.lopnode, cap.lop));
+        DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * pl.PW));
+    } else {
+        DFGT_TRY(grow<double>(w.lscr, (size_t)kLocalGrid * 3 * pl.P));
+    }
+    if (!pl.acc_lds) DFGT_TRY(grow<double>(w.pscr, (size_t)pl.items * 3 * pl.PW));
+    return DFGT_OK;
+}
+
+dfgt_status upload_plan(const Plan &pl, Workspace &w, hipStream_t st) {
+    DFGT_HIP(hipMemcpyAsync(w.jobs.p, pl.jobs.data(), sizeof(Job) * pl.njobs, hipMemcpyHostToDevice, st));
+    DFGT_HIP(hipMemcpyAsync(w.trees.p, pl.trees.data(), sizeof(DevTree) * pl.trees.size(), hipMemcpyHostToDevice,
+                            st));
+    DFGT_HIP(hipMemcpyAsync(w.jls.p, pl.jls.data(), sizeof(int) * pl.jls.size(), hipMemcpyHostToDevice, st));
+    return DFGT_OK;
+}
+
+void fill_u32(void *p, size_t words, unsigned v, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(std::max(blocks, 1u)), dim3(256), 0, st, (unsigned *)p, words, v);
+}
+
+// The whole launch sequence of one call: no host synchronisation, no
+// allocation, no memset or host copy, so it can be captured in a graph.
+void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
+    const size_t nna = pl.nna;
+    const int nlev = pl.nlev, njobs = pl.njobs, d = pl.d, pmax = pl.pmax, P = pl.P, PW = pl.PW;
     int *headE = w.heads.as<int>(), *headF = headE + nna, *headL = headF + nna;
     const DevTree *td = w.trees.as<DevTree>();
     const Job *jd = w.jobs.as<Job>();
-    // a query leaf's own local ops are applied inside k_leaf when its per-wave
-    // scratch fits; otherwise they go through the node kernels
-    const bool leaf_local = P <= 512;
-    if (gr && !leaf_local) {
-        set_error("dfgt_gauss_sum_grad: gradients need p_max^d <= 512");
-        return DFGT_EINVAL;
+    const int *jls = w.jls.as<int>();
+    int *lvl = w.lvl.as<int>();
+    fill_u32(w.lflag.p, (nna + 3) / 4, 0u, st);
+    fill_u32(w.cval.p, 2 * nna, 0u, st);
+    fill_u32(w.heads.p, 3 * nna, 0xffffffffu, st);
+    fill_u32(w.cnt.p, C_N * CP, 0u, st);
+    fill_u32(w.lvl.p, (size_t)(nlev + 1) * 2 * CP, 0u, st);
+    fill_u32(w.flag.p, 1, 0u, st);
+    fill_u32(w.stats.p, 2 * S_N * SP, 0u, st);
+    hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
+    for (int k = 0; k < nlev; ++k) {
+        DevBuf &sin = (k & 1) ? w.segB : w.segA, &sout = (k & 1) ? w.segA : w.segB;
+        DevBuf &pin = (k & 1) ? w.pairB : w.pairA, &pout = (k & 1) ? w.pairA : w.pairB;
+        TravOut o{sout.as<Seg>(),   pout.as<int>(),    w.egrp.as<Group>(), w.eops.as<int>(),
+                  w.fgrp.as<Group>(), w.fops.as<Op>(),  w.lgrp.as<Group>(), w.lops.as<Op>(),
+                  w.lnodes.as<int>(), headE,            headF,              headL,
+                  w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
+                  w.stats.as<unsigned long long>(),     w.cval.as<double>(), prof ? 1 : 0, w.cap};
+        hipEvent_t ev = prof ? prof->start(st) : nullptr;
+        hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
+                           k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, njobs, pl.force,
+                           pl.gr ? 1 : 0, pl.leaf_local ? 1 : 0, w.dec.as<int>(), w.kus.as<double>(), o);
+        if (prof) prof->stop(K_TRAV, ev, st);
     }
-    if (Qh->depth > kMaxDepth) {
-        set_error("dfgt_gauss_sum: query tree deeper than 256 levels");
-        return DFGT_EINVAL;
+    if (pl.emfma) {
+        hipEvent_t ev = prof ? prof->start(st) : nullptr;
+        auto fn = pl.gr ? launch_emfma<true> : launch_emfma<false>;
+        fn((d + 3) / 4, dim3(pl.items), st, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.flag.as<int>(),
+           jls, njobs, w.extE.as<double>(), pl.gr ? w.extX.as<double>() : nullptr,
+           pl.gr ? w.extY.as<double>() : nullptr);
+        if (prof) prof->stop(K_EMFMA, ev, st);
     }
-    // every level splits Q and R wherever they can split, so no pair survives
-    // more levels than the deeper tree has
-    const int nlev = std::max(Qh->depth, Rh->depth);
-    DFGT_TRY(grow<int>(w.lvl, (size_t)(nlev + 1) * 2 * CP));
-    // exhaustive leaf sums on the matrix cores: mixed precision, D >= 8, and
-    // s^2 (|q|^2 + |r|^2) <= 2^26 for every bandwidth (rounding of the
-    // expanded squared distance below ~1e-7)
-    bool emfma = precision == DFGT_PREC_MIXED && d >= 8 && d <= 32 && nlev <= kMaxEGrp;
-    for (int k = 0; k < nh && emfma; ++k)
-        emfma = jobs[k].sig * jobs[k].sig * (Qh->max_nrm + Rh->max_nrm) <= 67108864.0;
-    if (emfma) {
-        DFGT_TRY(grow<double>(w.extE, (size_t)nh * NQ));
-        if (gr) {
-            DFGT_TRY(grow<double>(w.extX, (size_t)nh * NQ));
-            DFGT_TRY(grow<double>(w.extY, (size_t)nh * NQ * d));
+    // local moments: every D / T op in parallel, then per internal node
+    {
+        hipEvent_t ev = prof ? prof->start(st) : nullptr;
+        if (pl.leaf_local) {
+            hipLaunchKernelGGL(k_lop_owner, dim3(kLocalGrid), dim3(64), 0, st, w.lgrp.as<Group>(), w.cnt.as<int>(),
+                               w.flag.as<int>(), w.lopnode.as<int>());
+            auto klo = pl.gr ? k_lops<true> : k_lops<false>;
+            hipLaunchKernelGGL(klo, dim3(kLocalGrid), dim3(64 * pl.lop_waves), pl.lop_sh, st, td, jd,
+                               w.lgrp.as<Group>(), w.lops.as<Op>(), w.lopnode.as<int>(), w.cnt.as<int>(),
+                               w.flag.as<int>(), w.part.as<double>());
+            hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(64), sizeof(double) * PW, st, jd, td,
+                               w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
+                               w.lops.as<Op>(), w.part.as<double>(), PW, w.L.as<double>(),
+                               w.lflag.as<unsigned char>());
+        } else {
+            hipLaunchKernelGGL(k_local_big, dim3(kLocalGrid), dim3(kLocBlock), pl.big_sh, st, td, jd,
+                               w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
+                               w.lops.as<Op>(), w.lscr.as<double>(), w.L.as<double>(),
+                               w.lflag.as<unsigned char>());
         }
+        if (prof) prof->stop(K_LOCAL, ev, st);
     }
+    // everything per (job, query leaf)
+    {
+        hipEvent_t ev = prof ? prof->start(st) : nullptr;
+        auto kl = pl.gr ? k_leaf<true> : k_leaf<false>;
+        hipLaunchKernelGGL(kl, dim3(pl.items), dim3(pl.leaf_threads), pl.leaf_sh, st, td, jd, w.egrp.as<Group>(),
+                           w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
+                           w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
+                           pl.precision, pl.acc_lds ? 1 : 0, pl.leaf_local ? 1 : 0, w.flag.as<int>(),
+                           pl.leaf_local ? w.part.as<double>() : (const double *)nullptr, w.pscr.as<double>(),
+                           pl.emfma ? w.extE.as<double>() : (const double *)nullptr,
+                           pl.emfma && pl.gr ? w.extX.as<double>() : (const double *)nullptr,
+                           pl.emfma && pl.gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>(),
+                           jls, njobs);
+        if (prof) prof->stop(K_LEAF, ev, st);
+    }
+}
 
+// Reads the overflow flag and the counters (synchronises); on overflow grows
+// the capacities for a rerun.
+dfgt_status read_back(const Plan &pl, Workspace &w, hipStream_t st, int *overflow, int *c) {
+    const int nlev = pl.nlev;
+    std::vector<int> hc((size_t)C_N * CP), hl((size_t)(nlev + 1) * 2 * CP);
+    DFGT_HIP(hipMemcpyAsync(overflow, w.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipMemcpyAsync(hc.data(), w.cnt.p, sizeof(int) * hc.size(), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipMemcpyAsync(hl.data(), w.lvl.p, sizeof(int) * hl.size(), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < C_N; ++k) c[k] = hc[(size_t)k * CP];
+    if (!*overflow && hl[((size_t)nlev * 2 + C_SEG) * CP] != 0) {
+        set_error("dfgt_gauss_sum: internal error, node pairs left after the last level");
+        return DFGT_EHIP;
+    }
+    if (*overflow) {
+        Caps &cap = w.cap;
+        int mseg = 0, mpair = 0;
+        for (int k = 1; k <= nlev; ++k) {
+            mseg = std::max(mseg, hl[((size_t)k * 2 + C_SEG) * CP]);
+            mpair = std::max(mpair, hl[((size_t)k * 2 + C_PAIR) * CP]);
+        }
+        auto up = [](int cur, long long need) {
+            long long v = std::max<long long>(2LL * cur, 2LL * need);
+            return (int)std::min<long long>(v, (1LL << 30));
+        };
+        cap.seg = up(cap.seg, mseg);
+        cap.pair = up(cap.pair, mpair);
+        cap.eop = up(cap.eop, c[C_EOP]);
+        cap.fop = up(cap.fop, c[C_FOP]);
+        cap.lop = up(cap.lop, c[C_LOP]);
+        cap.grp = up(cap.grp, std::max(c[C_EGRP], std::max(c[C_FGRP], c[C_LGRP])));
+        cap.lnode = up(cap.lnode, c[C_LNODE]);
+    }
+    return DFGT_OK;
+}
+
+dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *prof, dfgt_stats *out,
+                       hipStream_t st) {
+    std::vector<unsigned long long> sraw((size_t)S_N * SP);
+    DFGT_HIP(hipMemcpyAsync(sraw.data(), w.stats.p, sizeof(unsigned long long) * S_N * SP, hipMemcpyDeviceToHost,
+                            st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    unsigned long long sv[S_N];
+    for (int k = 0; k < S_N; ++k) sv[k] = sraw[(size_t)k * SP];
+    std::memset(out, 0, sizeof(*out));
+    out->node_pairs = (int64_t)sv[S_PAIRS];
+    out->prune_f = (int64_t)sv[S_F];
+    out->prune_d = (int64_t)sv[S_D];
+    out->prune_t = (int64_t)sv[S_T];
+    out->prune_centroid = (int64_t)sv[S_C];
+    out->base_leaf_pairs = (int64_t)sv[S_BLEAF];
+    out->base_point_pairs = (int64_t)sv[S_BPTS];
+    out->levels = pl.nlev;
+    out->max_order = (int64_t)sv[S_MAXORD];
+    out->fp64_groups = (int64_t)sv[S_FP64];
+    out->segments = (int64_t)sv[S_SEGS];
+    out->max_segment = (int64_t)sv[S_MAXSEG];
+    out->local_nodes = c[C_LNODE];
+    out->max_local_ops = (int64_t)sv[S_MAXLOPS];
+    if (prof && prof->on) prof->collect(out);
+    return DFGT_OK;
+}
+
+// Eager run: allocate, enqueue, read back, and on overflow grow and rerun.
+dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stats_out, hipStream_t st) {
+    Profiler &prof = g_prof;
     Caps &cap = w.cap;
     if (cap.pair == 0) cap = Caps{1 << 19, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 18, 1 << 18};
-    cap.pair = std::max(cap.pair, 4 * nh);
-    cap.seg = std::max(cap.seg, 4 * nh);
-    std::vector<Seg> s0(nh);
-    std::vector<int> p0(nh, 0);
-    for (int k = 0; k < nh; ++k) s0[k] = Seg{0, k, k, 1, 0.0};
+    cap.pair = std::max(cap.pair, 4 * pl.njobs);
+    cap.seg = std::max(cap.seg, 4 * pl.njobs);
     int c[C_N] = {0};
     int overflow = 1;
     for (int attempt = 0; attempt < 12 && overflow; ++attempt) {
+        DFGT_TRY(alloc_plan(pl, w));
+        DFGT_TRY(upload_plan(pl, w, st));
         prof.begin_call(profile != 0);
-        DFGT_TRY(grow<Seg>(w.segA, cap.seg));
-        DFGT_TRY(grow<Seg>(w.segB, cap.seg));
-        DFGT_TRY(grow<int>(w.pairA, cap.pair));
-        DFGT_TRY(grow<int>(w.pairB, cap.pair));
-        DFGT_TRY(grow<int>(w.dec, cap.pair));
-        DFGT_TRY(grow<double>(w.kus, cap.pair));
-        DFGT_TRY(grow<Group>(w.egrp, cap.grp));
-        DFGT_TRY(grow<Group>(w.fgrp, cap.grp));
-        DFGT_TRY(grow<Group>(w.lgrp, cap.grp));
-        DFGT_TRY(grow<int>(w.lnodes, 2 * (size_t)cap.lnode));
-        DFGT_TRY(grow<int>(w.eops, cap.eop));
-        DFGT_TRY(grow<Op>(w.fops, cap.fop));
-        DFGT_TRY(grow<Op>(w.lops, cap.lop));
-        if (leaf_local) {
-            DFGT_TRY(grow<int>(w.lopnode, cap.lop));
-            DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * PW));
-        }
-        DFGT_HIP(hipMemsetAsync(w.lflag.p, 0, nna, st));
-        DFGT_HIP(hipMemsetAsync(w.cval.p, 0, sizeof(double) * nna, st));
-        DFGT_HIP(hipMemsetAsync(w.heads.p, 0xff, sizeof(int) * 3 * nna, st));
-        DFGT_HIP(hipMemsetAsync(w.cnt.p, 0, sizeof(int) * C_N * CP, st));
-        DFGT_HIP(hipMemsetAsync(w.lvl.p, 0, sizeof(int) * (nlev + 1) * 2 * CP, st));
-        DFGT_HIP(hipMemsetAsync(w.flag.p, 0, sizeof(int), st));
-        DFGT_HIP(hipMemsetAsync(w.stats.p, 0, sizeof(unsigned long long) * S_N * SP, st));
-        DFGT_HIP(hipMemcpyAsync(w.segA.p, s0.data(), sizeof(Seg) * nh, hipMemcpyHostToDevice, st));
-        DFGT_HIP(hipMemcpyAsync(w.pairA.p, p0.data(), sizeof(int) * nh, hipMemcpyHostToDevice, st));
-        int *lvl = w.lvl.as<int>();
-        for (int k = 0; k < nlev; ++k) {
-            DevBuf &sin = (k & 1) ? w.segB : w.segA, &sout = (k & 1) ? w.segA : w.segB;
-            DevBuf &pin = (k & 1) ? w.pairB : w.pairA, &pout = (k & 1) ? w.pairA : w.pairB;
-            TravOut o{sout.as<Seg>(),   pout.as<int>(),    w.egrp.as<Group>(), w.eops.as<int>(),
-                      w.fgrp.as<Group>(), w.fops.as<Op>(),  w.lgrp.as<Group>(), w.lops.as<Op>(),
-                      w.lnodes.as<int>(), headE,            headF,              headL,
-                      w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
-                      w.stats.as<unsigned long long>(),     w.cval.as<double>(), stats_out != nullptr ? 1 : 0, cap};
-            hipEvent_t ev = prof.start(st);
-            hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
-                               k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, nh, force, gr ? 1 : 0,
-                               leaf_local ? 1 : 0, w.dec.as<int>(), w.kus.as<double>(), o);
-            DFGT_HIP(hipGetLastError());
-            prof.stop(K_TRAV, ev, st);
-        }
-        if (emfma) {
-            hipEvent_t ev = prof.start(st);
-            auto fn = gr ? launch_emfma<true> : launch_emfma<false>;
-            fn((d + 3) / 4, dim3(Qv.nleaves, nh), st, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
-               w.flag.as<int>(), w.extE.as<double>(), gr ? w.extX.as<double>() : nullptr,
-               gr ? w.extY.as<double>() : nullptr);
-            DFGT_HIP(hipGetLastError());
-            prof.stop(K_EMFMA, ev, st);
-        }
-        // local moments: every D / T op in parallel, then per internal node
-        {
-            hipEvent_t ev = prof.start(st);
-            if (leaf_local) {
-                hipLaunchKernelGGL(k_lop_owner, dim3(kLocalGrid), dim3(64), 0, st, w.lgrp.as<Group>(), w.cnt.as<int>(),
-                                   w.flag.as<int>(), w.lopnode.as<int>());
-                // waves per block: as many (up to 4) as the LDS allows
-                const size_t wstride = lop_wave_stride(P, d, pmax, gr ? 1 : 0);
-                int lwv = 4;
-                size_t sh = 0;
-                for (;; lwv >>= 1) {
-                    sh = sizeof(double) * ((size_t)P + (10 * (size_t)P + 7) / 8 + (size_t)lwv * wstride);
-                    if (sh <= 64 * 1024 || lwv == 1) break;
-                }
-                if (sh > 64 * 1024) {
-                    set_error("dfgt_gauss_sum: p_max^d too large for the local-op kernel");
-                    return DFGT_EINVAL;
-                }
-                auto klo = gr ? k_lops<true> : k_lops<false>;
-                hipLaunchKernelGGL(klo, dim3(kLocalGrid), dim3(64 * lwv), sh, st, td, jd, w.lgrp.as<Group>(),
-                                   w.lops.as<Op>(), w.lopnode.as<int>(), w.cnt.as<int>(), w.flag.as<int>(),
-                                   w.part.as<double>());
-                hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(64), sizeof(double) * PW, st, jd, td,
-                                   w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
-                                   w.lops.as<Op>(), w.part.as<double>(), PW, w.L.as<double>(),
-                                   w.lflag.as<unsigned char>());
-            } else {
-                DFGT_TRY(grow<double>(w.lscr, (size_t)kLocalGrid * 3 * P));
-                const size_t sh = sizeof(double) * ((size_t)pmax * pmax + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax);
-                hipLaunchKernelGGL(k_local_big, dim3(kLocalGrid), dim3(kLocBlock), sh, st, td, jd, w.lnodes.as<int>(),
-                                   w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(), w.lops.as<Op>(),
-                                   w.lscr.as<double>(), w.L.as<double>(), w.lflag.as<unsigned char>());
-            }
-            DFGT_HIP(hipGetLastError());
-            prof.stop(K_LOCAL, ev, st);
-        }
-        // everything per query leaf
-        {
-            const int g1 = gr ? 1 : 0;
-            int nthr = 256;
-            while (nthr > 64 && sizeof(double) * leaf_lds_base(nthr, d, pmax, g1) > 40 * 1024) nthr >>= 1;
-            const size_t base = sizeof(double) * leaf_lds_base(nthr, d, pmax, g1);
-            const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
-            const size_t lds_coef = sizeof(double) * (size_t)d * pmax * pmax;
-            const size_t lds_acc = sizeof(double) * 3 * (size_t)PW + lds_coef;
-            // dynamic LDS up to 56 KB: the kernel's static arrays take ~6 KB of the 64 KB
-            const bool acc_lds = base + lds_acc + lds_dig <= 56 * 1024;
-            double *scr = nullptr;
-            if (!acc_lds) {
-                DFGT_TRY(grow<double>(w.pscr, (size_t)Qv.nleaves * nh * 3 * PW));
-                scr = w.pscr.as<double>();
-            }
-            const size_t sh = base + (acc_lds ? lds_acc : lds_coef) + lds_dig;
-            if (sh > 56 * 1024) {
-                set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
-                return DFGT_EINVAL;
-            }
-            hipEvent_t ev = prof.start(st);
-            auto kl = gr ? k_leaf<true> : k_leaf<false>;
-            hipLaunchKernelGGL(kl, dim3(Qv.nleaves, nh), dim3(nthr), sh, st, td, jd, w.egrp.as<Group>(),
-                               w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
-                               w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
-                               precision, acc_lds ? 1 : 0, leaf_local ? 1 : 0, w.flag.as<int>(),
-                               leaf_local ? w.part.as<double>() : (const double *)nullptr, scr,
-                               emfma ? w.extE.as<double>() : (const double *)nullptr,
-                               emfma && gr ? w.extX.as<double>() : (const double *)nullptr,
-                               emfma && gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>());
-            DFGT_HIP(hipGetLastError());
-            prof.stop(K_LEAF, ev, st);
-        }
-        // one readback: overflow flag and the counters that size a rerun
-        std::vector<int> hc((size_t)C_N * CP), hl((size_t)(nlev + 1) * 2 * CP);
-        DFGT_HIP(hipMemcpyAsync(&overflow, w.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        DFGT_HIP(hipMemcpyAsync(hc.data(), w.cnt.p, sizeof(int) * hc.size(), hipMemcpyDeviceToHost, st));
-        DFGT_HIP(hipMemcpyAsync(hl.data(), w.lvl.p, sizeof(int) * hl.size(), hipMemcpyDeviceToHost, st));
-        DFGT_HIP(hipStreamSynchronize(st));
-        for (int k = 0; k < C_N; ++k) c[k] = hc[(size_t)k * CP];
-        if (!overflow && hl[((size_t)nlev * 2 + C_SEG) * CP] != 0) {
-            set_error("dfgt_gauss_sum: internal error, node pairs left after the last level");
-            return DFGT_EHIP;
-        }
-        if (overflow) {
-            int mseg = 0, mpair = 0;
-            for (int k = 1; k <= nlev; ++k) {
-                mseg = std::max(mseg, hl[((size_t)k * 2 + C_SEG) * CP]);
-                mpair = std::max(mpair, hl[((size_t)k * 2 + C_PAIR) * CP]);
-            }
-            auto up = [](int cur, long long need) {
-                long long v = std::max<long long>(2LL * cur, 2LL * need);
-                return (int)std::min<long long>(v, (1LL << 30));
-            };
-            cap.seg = up(cap.seg, mseg);
-            cap.pair = up(cap.pair, mpair);
-            cap.eop = up(cap.eop, c[C_EOP]);
-            cap.fop = up(cap.fop, c[C_FOP]);
-            cap.lop = up(cap.lop, c[C_LOP]);
-            cap.grp = up(cap.grp, std::max(c[C_EGRP], std::max(c[C_FGRP], c[C_LGRP])));
-            cap.lnode = up(cap.lnode, c[C_LNODE]);
-        }
+        // stats are gathered whenever a caller asks for them
+        enqueue(pl, w, st, (profile || stats_out) ? &prof : nullptr);
+        DFGT_HIP(hipGetLastError());
+        DFGT_TRY(read_back(pl, w, st, &overflow, c));
     }
     if (overflow) {
         set_error("dfgt_gauss_sum: traversal buffers could not be sized");
         return DFGT_ENOMEM;
     }
-    if (stats_out) {
-        std::vector<unsigned long long> sraw((size_t)S_N * SP);
-        DFGT_HIP(hipMemcpyAsync(sraw.data(), w.stats.p, sizeof(unsigned long long) * S_N * SP,
-                                hipMemcpyDeviceToHost, st));
-        DFGT_HIP(hipStreamSynchronize(st));
-        unsigned long long sv[S_N];
-        for (int k = 0; k < S_N; ++k) sv[k] = sraw[(size_t)k * SP];
-        std::memset(stats_out, 0, sizeof(*stats_out));
-        stats_out->node_pairs = (int64_t)sv[S_PAIRS];
-        stats_out->prune_f = (int64_t)sv[S_F];
-        stats_out->prune_d = (int64_t)sv[S_D];
-        stats_out->prune_t = (int64_t)sv[S_T];
-        stats_out->prune_centroid = (int64_t)sv[S_C];
-        stats_out->base_leaf_pairs = (int64_t)sv[S_BLEAF];
-        stats_out->base_point_pairs = (int64_t)sv[S_BPTS];
-        stats_out->levels = nlev;
-        stats_out->max_order = (int64_t)sv[S_MAXORD];
-        stats_out->fp64_groups = (int64_t)sv[S_FP64];
-        stats_out->segments = (int64_t)sv[S_SEGS];
-        stats_out->max_segment = (int64_t)sv[S_MAXSEG];
-        stats_out->local_nodes = c[C_LNODE];
-        stats_out->max_local_ops = (int64_t)sv[S_MAXLOPS];
-        if (prof.on) prof.collect(stats_out);
+    if (stats_out) DFGT_TRY(fill_stats(pl, w, c, &prof, stats_out, st));
+    return DFGT_OK;
+}
+
+}  // namespace
+
+dfgt_status run_gauss_multi(const Problem *pr, int np, double eps, int precision, int force, int profile,
+                            double cost_e, const GradOut *grad, dfgt_stats *stats_out, hipStream_t st) {
+    Plan pl;
+    DFGT_TRY(make_plan(pr, np, eps, precision, force, cost_e, grad, pl));
+    return run_plan(pl, g_ws, profile, stats_out, st);
+}
+
+dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int nh, double eps, int precision,
+                          int force, int profile, double cost_e, double *G, const GradOut *grad,
+                          dfgt_stats *stats_out, hipStream_t st) {
+    const Problem pr{Qh, Rh, h, nh, G};
+    return run_gauss_multi(&pr, 1, eps, precision, force, profile, cost_e, grad, stats_out, st);
+}
+
+}  // namespace dfgt
+
+// A captured batch: the plan, its own workspace (the graph holds pointers
+// into it) and the executable graph of one full launch sequence.
+struct dfgt_batch_s {
+    dfgt::Plan pl;
+    dfgt::Workspace w;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~dfgt_batch_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
+namespace dfgt {
+
+dfgt_status batch_create(const Problem *pr, int np, double eps, int precision, int force, double cost_e,
+                         dfgt_stats *stats_out, hipStream_t st, dfgt_batch_s **out) {
+    auto *b = new dfgt_batch_s();
+    dfgt_status s = make_plan(pr, np, eps, precision, force, cost_e, nullptr, b->pl);
+    // one eager run sizes the workspace (the inputs fix every list size)
+    if (s == DFGT_OK) s = run_plan(b->pl, b->w, 0, stats_out, st);
+    if (s == DFGT_OK && hipStreamSynchronize(st) != hipSuccess) s = DFGT_EHIP;
+    // capture on a stream of our own (the caller's may be the legacy default stream)
+    if (s == DFGT_OK && hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) s = DFGT_EHIP;
+    if (s == DFGT_OK && hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) s = DFGT_EHIP;
+    if (s == DFGT_OK) {
+        enqueue(b->pl, b->w, b->cs, nullptr);
+        const hipError_t le = hipGetLastError();
+        const hipError_t ce = hipStreamEndCapture(b->cs, &b->graph);
+        if (le != hipSuccess || ce != hipSuccess) s = DFGT_EHIP;
+    }
+    if (s == DFGT_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) s = DFGT_EHIP;
+    if (s != DFGT_OK) {
+        if (s == DFGT_EHIP) set_error("dfgt_batch_create: capturing the launch graph failed");
+        delete b;
+        return s;
+    }
+    *out = b;
+    return DFGT_OK;
+}
+
+dfgt_status batch_run(dfgt_batch_s *b, hipStream_t st) {
+    DFGT_HIP(hipGraphLaunch(b->exec, st));
+    return DFGT_OK;
+}
+
+dfgt_status batch_check(dfgt_batch_s *b, hipStream_t st) {
+    int overflow = 0;
+    DFGT_HIP(hipMemcpyAsync(&overflow, b->w.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    if (overflow) {
+        set_error("dfgt_batch: the last run overflowed its traversal buffers (were the trees changed?)");
+        return DFGT_EBOUND;
     }
     return DFGT_OK;
 }
 
 }  // namespace dfgt
+
+extern "C" dfgt_status dfgt_batch_free(dfgt_batch b) {
+    try {
+        delete b;
+    } catch (...) {
+        return DFGT_EHIP;
+    }
+    return DFGT_OK;
+}

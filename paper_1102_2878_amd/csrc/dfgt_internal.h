@@ -120,6 +120,8 @@ struct DevTree {
 
 }  // namespace dfgt
 
+struct dfgt_batch_s;  // a captured batch (dfgt.hip)
+
 // The opaque handle of the C ABI.
 struct dfgt_tree_s {
     int64_t n = 0;
@@ -188,6 +190,22 @@ struct GradOut {
     double *dGdh;
     double *dGdq;
 };
+// One summation problem of a call: sums over R for the queries of Q at n_h
+// bandwidths, written to G ([nh][Q->n], caller order).
+struct Problem {
+    dfgt_tree_s *Q, *R;
+    const double *h;
+    int nh;
+    double *G;
+};
+// Several problems (same D and p_max) and all their bandwidths in one traversal.
+dfgt_status run_gauss_multi(const Problem *pr, int np, double eps, int precision, int force, int profile,
+                            double cost_e, const GradOut *grad, dfgt_stats *stats, hipStream_t st);
+// Captured batches: an eager sizing run, then the launch sequence as a hipGraph.
+dfgt_status batch_create(const Problem *pr, int np, double eps, int precision, int force, double cost_e,
+                         dfgt_stats *stats, hipStream_t st, dfgt_batch_s **out);
+dfgt_status batch_run(dfgt_batch_s *b, hipStream_t st);
+dfgt_status batch_check(dfgt_batch_s *b, hipStream_t st);
 // cost_e: weight of the exhaustive cost in ChooseBestMethod (1 = the paper's model).
 dfgt_status run_gauss_sum(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps,
                           int precision, int force, int profile, double cost_e, double *G, const GradOut *grad,

@@ -47,6 +47,11 @@ class Stats(C.Structure):
         return d
 
 
+class Problem(C.Structure):
+    _fields_ = [("Q", C.c_void_p), ("R", C.c_void_p), ("h_host", C.POINTER(C.c_double)), ("n_h", C.c_int32),
+                ("G_dev", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -75,9 +80,16 @@ def lib():
                                               C.POINTER(dbl), vp, vp]
         L.dfgt_lscv_score.argtypes = [vp, C.POINTER(dbl), i32, dbl, i32, C.POINTER(Options), C.POINTER(dbl),
                                       C.POINTER(dbl), C.POINTER(Stats), vp]
+        L.dfgt_gauss_sum_batched.argtypes = [C.POINTER(Problem), i32, dbl, C.POINTER(Options), C.POINTER(Stats), vp]
+        L.dfgt_batch_create.argtypes = [C.POINTER(Problem), i32, dbl, C.POINTER(Options), C.POINTER(Stats), vp,
+                                        C.POINTER(vp)]
+        L.dfgt_batch_run.argtypes = [vp, vp]
+        L.dfgt_batch_check.argtypes = [vp, vp]
+        L.dfgt_batch_free.argtypes = [vp]
         for nm in ("dfgt_build_tree", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
                    "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
-                   "dfgt_gauss_sum_backward", "dfgt_lscv_score"):
+                   "dfgt_gauss_sum_backward", "dfgt_lscv_score", "dfgt_gauss_sum_batched", "dfgt_batch_create",
+                   "dfgt_batch_run", "dfgt_batch_check", "dfgt_batch_free"):
             getattr(L, nm).restype = C.c_int
         _lib = L
     return _lib
@@ -256,3 +268,59 @@ def lscv_score(R: Tree, h, eps, variant=1, grad=False, precision=PREC_MIXED, for
                                  C.byref(st) if st is not None else None, _stream()))
     out = (cv,) + ((dcv,) if grad else ()) + ((st.as_dict(),) if stats else ())
     return out[0] if len(out) == 1 else out
+
+
+def _problem_array(problems):
+    """[(Q, R, h)] -> (ctypes array, outputs, kept-alive host arrays)."""
+    torch = _torch()
+    arr = (Problem * len(problems))()
+    outs, keep = [], []
+    for i, (Q, R, h) in enumerate(problems):
+        hv, hp = _hvec(h)
+        G = torch.empty((hv.shape[0], Q.n), dtype=torch.float64, device="cuda")
+        arr[i] = Problem(Q.handle, R.handle, hp, hv.shape[0], G.data_ptr())
+        outs.append(G)
+        keep.append(hv)
+    return arr, outs, keep
+
+
+def gauss_sum_batched(problems, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, profile=False):
+    """dfgt_gauss_sum_batched over [(Q, R, h)]: list of (n_h, NQ) tensors [, stats]."""
+    arr, outs, keep = _problem_array(problems)
+    o = _opts(precision=precision, force_method=force_method, profile=profile)
+    stats = stats or profile
+    st = Stats() if stats else None
+    _check(lib().dfgt_gauss_sum_batched(arr, len(problems), float(eps), C.byref(o),
+                                        C.byref(st) if st is not None else None, _stream()))
+    return (outs, st.as_dict()) if stats else outs
+
+
+class Batch:
+    """dfgt_batch_create / run / check / free: a captured sweep over [(Q, R, h)].
+    ``G`` holds the output tensors, rewritten by every ``run()``."""
+
+    def __init__(self, problems, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False):
+        self.handle = None
+        self._trees = [t for p in problems for t in p[:2]]
+        arr, self.G, self._keep = _problem_array(problems)
+        self._arr = arr
+        o = _opts(precision=precision, force_method=force_method)
+        st = Stats() if stats else None
+        h = C.c_void_p()
+        _check(lib().dfgt_batch_create(arr, len(problems), float(eps), C.byref(o),
+                                       C.byref(st) if st is not None else None, _stream(), C.byref(h)))
+        self.handle = h
+        self.stats = st.as_dict() if st is not None else None
+
+    def run(self):
+        _check(lib().dfgt_batch_run(self.handle, _stream()))
+        return self.G
+
+    def check(self):
+        _check(lib().dfgt_batch_check(self.handle, _stream()))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.dfgt_batch_free(h)
+            self.handle = None
