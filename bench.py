@@ -12,6 +12,11 @@ value = N_Q * N_R * 7 / (seconds per step)  [query x reference pairs / s].
 The plain tiled brute-force GPU sum (dfgt_naive_sum) over the same seven
 bandwidths is timed alongside.
 
+batched: the 3-D batch, 8 clustered problems of 10k..200k points, each swept
+over 64 log-spaced bandwidths h_S x 10^{-3..3} at h and sqrt(2) h (the LSCV
+pair): 1024 sums in one traversal, eager and as a captured graph replay,
+beside the brute force over the same 1024 sums.
+
 grad_ms (the metric's second part): the backward pass on the 16-D workload,
 200,000 points (8 latent clusters embedded + N(0, 0.01 I) noise), eps 1e-4,
 bandwidths {h_S, h*} (h* of its seeded 5,000-point subsample,
@@ -50,6 +55,52 @@ EXP_SLOTS = 4
 
 def base_peak_pairs(d):
     return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
+
+
+def batched_bench(torch, dfgt, synth):
+    """The 3-D batch: eager call, graph replays, brute force; returns details."""
+    xs = [synth.c4_problem(k) for k in range(8)]
+    xd = [torch.as_tensor(x, device="cuda") for x in xs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trees = [dfgt.build_tree(x, leaf_size=LEAF) for x in xd]
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    probs = []
+    for x, t in zip(xs, trees):
+        base = synth.silverman_h(x) * np.geomspace(1e-3, 1e3, 64)
+        probs.append((t, t, np.concatenate([base, np.sqrt(2.0) * base])))
+    dfgt.gauss_sum_batched(probs, EPS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dfgt.gauss_sum_batched(probs, EPS)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    b = dfgt.Batch(probs, EPS, stats=True)
+    b.run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    b.check()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for x, (t, _, h), G in zip(xd, probs, b.G):
+        Gb = dfgt.naive_sum(x, x, h)
+        worst = max(worst, float(((G - Gb).abs() / Gb).max()))
+    torch.cuda.synchronize()
+    t_bf = time.perf_counter() - t0
+    pairs = float(sum(x.shape[0] ** 2 for x in xs)) * 128
+    return {
+        "workload": "3-D, 8 clustered problems N = 10k..200k (sum 690k), 64 log-spaced h x {1, sqrt2}, eps 1e-2",
+        "sums": 8 * 128, "build_ms": t_build * 1e3, "eager_ms": t_eager * 1e3, "graph_replay_ms": t_graph * 1e3,
+        "pairs_per_s_graph": pairs / t_graph, "bruteforce_ms": t_bf * 1e3, "bruteforce_pairs_per_s": pairs / t_bf,
+        "speedup_vs_bruteforce": t_bf / t_graph, "max_rel_err_vs_bruteforce": worst,
+        "node_pairs": b.stats["node_pairs"], "base_point_pairs": b.stats["base_point_pairs"],
+    }
 
 
 def grad_bench(args, torch, dfgt, synth):
@@ -105,6 +156,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the 16-D backward timing")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 3-D batched sweep")
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--grad-leaf", type=int, default=128)
     args = ap.parse_args()
@@ -222,6 +274,8 @@ def main():
         "grad_ms": None,
     }
 
+    if not args.no_batched:
+        out["batched"] = batched_bench(torch, dfgt, synth)
     if not args.no_grad:
         out["grad_ms"], out["grad"] = grad_bench(args, torch, dfgt, synth)
 

@@ -1751,6 +1751,7 @@ struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
         lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
+    int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
 };
 thread_local Workspace g_ws;
 
@@ -1790,7 +1791,50 @@ struct Plan {
     size_t nna = 0, nqa = 0;  // node slots and query slots over all jobs
     int leaf_threads = 256, lop_waves = 4;
     size_t leaf_sh = 0, lop_sh = 0, big_sh = 0;
+    size_t job_off = 0, jls_off = 0;  // where this plan's tables sit in the device arrays
 };
+
+// Jobs [j0, j1) of a plan as a plan of their own (jobs are independent).
+Plan sub_plan(const Plan &pl, int j0, int j1) {
+    Plan sp = pl;
+    sp.jobs.assign(pl.jobs.begin() + j0, pl.jobs.begin() + j1);
+    sp.njobs = j1 - j0;
+    sp.jls.assign(1, 0);
+    long long nna = 0, nqa = 0, items = 0;
+    for (Job &j : sp.jobs) {
+        const DevTree &Q = pl.trees[j.qt];
+        j.noff = nna;
+        j.qoff = nqa;
+        nna += Q.m;
+        nqa += Q.n;
+        items += Q.nleaves;
+        sp.jls.push_back((int)items);
+    }
+    sp.nna = (size_t)nna;
+    sp.nqa = (size_t)nqa;
+    sp.items = (int)items;
+    sp.job_off = sp.jls_off = 0;
+    return sp;
+}
+
+// Device bytes alloc_plan needs for a plan at the given capacities.
+size_t plan_bytes(const Plan &pl, const Caps &c) {
+    size_t b = pl.nna * (sizeof(double) * pl.PW + 1 + sizeof(double) + 3 * sizeof(int));
+    if (pl.emfma) b += pl.nqa * sizeof(double) * (pl.gr ? 2 + pl.d : 1);
+    b += (size_t)c.seg * 2 * sizeof(Seg) + (size_t)c.pair * (3 * sizeof(int) + sizeof(double));
+    b += (size_t)c.grp * 3 * sizeof(Group) + (size_t)c.lnode * 2 * sizeof(int) + (size_t)c.eop * sizeof(int);
+    b += (size_t)c.fop * sizeof(Op) + (size_t)c.lop * sizeof(Op);
+    if (pl.leaf_local) b += (size_t)c.lop * (sizeof(int) + sizeof(double) * pl.PW);
+    if (!pl.acc_lds) b += (size_t)pl.items * 3 * pl.PW * sizeof(double);
+    return b;
+}
+
+// Memory one call may size its traversal buffers to before it splits its jobs.
+size_t memory_budget() {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return (size_t)16 << 30;
+    return std::max<size_t>((size_t)1 << 30, std::min(tot / 8, fr / 2));
+}
 
 dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int force, double cost_e,
                       const GradOut *grad, Plan &pl) {
@@ -1961,10 +2005,12 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
 }
 
 dfgt_status upload_plan(const Plan &pl, Workspace &w, hipStream_t st) {
-    DFGT_HIP(hipMemcpyAsync(w.jobs.p, pl.jobs.data(), sizeof(Job) * pl.njobs, hipMemcpyHostToDevice, st));
+    DFGT_HIP(hipMemcpyAsync(w.jobs.as<Job>() + pl.job_off, pl.jobs.data(), sizeof(Job) * pl.njobs,
+                            hipMemcpyHostToDevice, st));
     DFGT_HIP(hipMemcpyAsync(w.trees.p, pl.trees.data(), sizeof(DevTree) * pl.trees.size(), hipMemcpyHostToDevice,
                             st));
-    DFGT_HIP(hipMemcpyAsync(w.jls.p, pl.jls.data(), sizeof(int) * pl.jls.size(), hipMemcpyHostToDevice, st));
+    DFGT_HIP(hipMemcpyAsync(w.jls.as<int>() + pl.jls_off, pl.jls.data(), sizeof(int) * pl.jls.size(),
+                            hipMemcpyHostToDevice, st));
     return DFGT_OK;
 }
 
@@ -1980,8 +2026,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
     const int nlev = pl.nlev, njobs = pl.njobs, d = pl.d, pmax = pl.pmax, P = pl.P, PW = pl.PW;
     int *headE = w.heads.as<int>(), *headF = headE + nna, *headL = headF + nna;
     const DevTree *td = w.trees.as<DevTree>();
-    const Job *jd = w.jobs.as<Job>();
-    const int *jls = w.jls.as<int>();
+    const Job *jd = w.jobs.as<Job>() + pl.job_off;
+    const int *jls = w.jls.as<int>() + pl.jls_off;
     int *lvl = w.lvl.as<int>();
     fill_u32(w.lflag.p, (nna + 3) / 4, 0u, st);
     fill_u32(w.cval.p, 2 * nna, 0u, st);
@@ -2116,12 +2162,17 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
 }
 
 // Eager run: allocate, enqueue, read back, and on overflow grow and rerun.
-dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stats_out, hipStream_t st) {
+// When the capacities a rerun would need exceed the memory budget and the
+// plan has more than one job, *too_big is set instead (capacities unchanged).
+dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stats_out, hipStream_t st,
+                     bool *too_big) {
     Profiler &prof = g_prof;
+    *too_big = false;
     Caps &cap = w.cap;
     if (cap.pair == 0) cap = Caps{1 << 19, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 18, 1 << 18};
     cap.pair = std::max(cap.pair, 4 * pl.njobs);
     cap.seg = std::max(cap.seg, 4 * pl.njobs);
+    const size_t budget = memory_budget();
     int c[C_N] = {0};
     int overflow = 1;
     for (int attempt = 0; attempt < 12 && overflow; ++attempt) {
@@ -2131,7 +2182,13 @@ dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stat
         // stats are gathered whenever a caller asks for them
         enqueue(pl, w, st, (profile || stats_out) ? &prof : nullptr);
         DFGT_HIP(hipGetLastError());
+        const Caps before = cap;
         DFGT_TRY(read_back(pl, w, st, &overflow, c));
+        if (overflow && pl.njobs > 1 && plan_bytes(pl, cap) > budget) {
+            cap = before;
+            *too_big = true;
+            return DFGT_OK;
+        }
     }
     if (overflow) {
         set_error("dfgt_gauss_sum: traversal buffers could not be sized");
@@ -2141,13 +2198,65 @@ dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stat
     return DFGT_OK;
 }
 
+void add_stats(dfgt_stats *a, const dfgt_stats &b) {
+    a->node_pairs += b.node_pairs;
+    a->prune_f += b.prune_f;
+    a->prune_d += b.prune_d;
+    a->prune_t += b.prune_t;
+    a->prune_centroid += b.prune_centroid;
+    a->base_leaf_pairs += b.base_leaf_pairs;
+    a->base_point_pairs += b.base_point_pairs;
+    a->levels = std::max(a->levels, b.levels);
+    a->max_order = std::max(a->max_order, b.max_order);
+    a->fp64_groups += b.fp64_groups;
+    a->segments += b.segments;
+    a->max_segment = std::max(a->max_segment, b.max_segment);
+    a->local_nodes += b.local_nodes;
+    a->max_local_ops = std::max(a->max_local_ops, b.max_local_ops);
+    for (int k = 0; k < 5; ++k) {
+        a->kernel_ms[k] += b.kernel_ms[k];
+        a->kernel_launches[k] += b.kernel_launches[k];
+    }
+}
+
+// Runs a plan, splitting its jobs in halves while a part does not fit the
+// memory budget; returns the parts that ran (in order).
+dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *stats_out, hipStream_t st,
+                       std::vector<Plan> *parts) {
+    std::vector<Plan> todo;
+    // start from the part size a previous call had to split to (a guess that
+    // is only ever refined: parts that still do not fit are halved again)
+    const int pj = w.part_jobs > 0 ? w.part_jobs : full.njobs;
+    for (int j0 = 0; j0 < full.njobs; j0 += pj) todo.push_back(sub_plan(full, j0, std::min(full.njobs, j0 + pj)));
+    if (stats_out) std::memset(stats_out, 0, sizeof(*stats_out));
+    parts->clear();
+    while (!todo.empty()) {
+        Plan pl = std::move(todo.front());
+        todo.erase(todo.begin());
+        bool too_big = false;
+        dfgt_stats one{};
+        DFGT_TRY(run_plan(pl, w, profile, stats_out ? &one : nullptr, st, &too_big));
+        if (too_big) {
+            const int mid = pl.njobs / 2;
+            w.part_jobs = w.part_jobs > 0 ? std::min(w.part_jobs, pl.njobs - mid) : pl.njobs - mid;
+            todo.insert(todo.begin(), sub_plan(pl, mid, pl.njobs));
+            todo.insert(todo.begin(), sub_plan(pl, 0, mid));
+            continue;
+        }
+        if (stats_out) add_stats(stats_out, one);
+        parts->push_back(std::move(pl));
+    }
+    return DFGT_OK;
+}
+
 }  // namespace
 
 dfgt_status run_gauss_multi(const Problem *pr, int np, double eps, int precision, int force, int profile,
                             double cost_e, const GradOut *grad, dfgt_stats *stats_out, hipStream_t st) {
     Plan pl;
     DFGT_TRY(make_plan(pr, np, eps, precision, force, cost_e, grad, pl));
-    return run_plan(pl, g_ws, profile, stats_out, st);
+    std::vector<Plan> parts;
+    return run_chunks(pl, g_ws, profile, stats_out, st, &parts);
 }
 
 dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int nh, double eps, int precision,
@@ -2162,7 +2271,7 @@ dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int
 // A captured batch: the plan, its own workspace (the graph holds pointers
 // into it) and the executable graph of one full launch sequence.
 struct dfgt_batch_s {
-    dfgt::Plan pl;
+    std::vector<dfgt::Plan> parts;  // the job chunks, replayed in order on one workspace
     dfgt::Workspace w;
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
@@ -2179,15 +2288,34 @@ namespace dfgt {
 dfgt_status batch_create(const Problem *pr, int np, double eps, int precision, int force, double cost_e,
                          dfgt_stats *stats_out, hipStream_t st, dfgt_batch_s **out) {
     auto *b = new dfgt_batch_s();
-    dfgt_status s = make_plan(pr, np, eps, precision, force, cost_e, nullptr, b->pl);
-    // one eager run sizes the workspace (the inputs fix every list size)
-    if (s == DFGT_OK) s = run_plan(b->pl, b->w, 0, stats_out, st);
+    Plan full;
+    dfgt_status s = make_plan(pr, np, eps, precision, force, cost_e, nullptr, full);
+    // one eager run sizes the workspace (the inputs fix every list size) and
+    // splits the jobs into parts that fit the memory budget
+    if (s == DFGT_OK) s = run_chunks(full, b->w, 0, stats_out, st, &b->parts);
+    if (s == DFGT_OK) {
+        // every part's tables at their own offsets, uploaded once; buffers at
+        // their final sizes before capture (the graph holds their addresses)
+        size_t jo = 0, lo = 0;
+        for (Plan &p : b->parts) {
+            p.job_off = jo;
+            p.jls_off = lo;
+            jo += p.njobs;
+            lo += p.jls.size();
+        }
+        for (const Plan &p : b->parts)
+            if (s == DFGT_OK) s = alloc_plan(p, b->w);
+        if (s == DFGT_OK) s = grow<Job>(b->w.jobs, jo);
+        if (s == DFGT_OK) s = grow<int>(b->w.jls, lo);
+        for (const Plan &p : b->parts)
+            if (s == DFGT_OK) s = upload_plan(p, b->w, st);
+    }
     if (s == DFGT_OK && hipStreamSynchronize(st) != hipSuccess) s = DFGT_EHIP;
     // capture on a stream of our own (the caller's may be the legacy default stream)
     if (s == DFGT_OK && hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) s = DFGT_EHIP;
     if (s == DFGT_OK && hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) s = DFGT_EHIP;
     if (s == DFGT_OK) {
-        enqueue(b->pl, b->w, b->cs, nullptr);
+        for (const Plan &p : b->parts) enqueue(p, b->w, b->cs, nullptr);
         const hipError_t le = hipGetLastError();
         const hipError_t ce = hipStreamEndCapture(b->cs, &b->graph);
         if (le != hipSuccess || ce != hipSuccess) s = DFGT_EHIP;
