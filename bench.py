@@ -52,6 +52,12 @@ LEAF = 32
 CUS, LANES, CLOCK = 256, 64, 2.4e9
 EXP_SLOTS = 4
 
+# HBM bytes per launch of k_leaf on this workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB device copy
+# (x2.0 and x1.0): profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
+# as profiled; set to None when k_leaf changes until the counters are retaken.
+K_LEAF_TRAFFIC_BYTES = 29.52e6 + 10.09e6
+
 
 def base_peak_pairs(d):
     return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
@@ -129,7 +135,7 @@ def grad_bench(args, torch, dfgt, synth):
     # where the time goes: one profiled gradient-mode call over the four LSCV sums
     hh = hs5 + [np.sqrt(2.0) * h for h in hs5]
     _, _, _, st = dfgt.gauss_sum_grad(R, R, hh, eps5, dq=False, stats=True, profile=True)
-    em_ms = st["kernel_ms"]["emfma"]
+    em_ms = st["kernel_ms"]["etile"]
     pairs = st["base_point_pairs"]
     # matrix-core roofline of the exhaustive tiles in gradient mode: per pair
     # 2 D flops for q.r plus 2 D for the kernel-weighted reference sums
@@ -157,6 +163,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the 16-D backward timing")
     ap.add_argument("--no-batched", action="store_true", help="skip the 3-D batched sweep")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a kernel of known traffic that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--grad-leaf", type=int, default=128)
     args = ap.parse_args()
@@ -174,6 +183,12 @@ def main():
     n, d = x_host.shape
     x = torch.as_tensor(x_host, device="cuda")
     torch.cuda.synchronize()
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(profile):
         t = dfgt.build_tree(x, leaf_size=LEAF)
@@ -207,6 +222,13 @@ def main():
     t_step_prof = (time.perf_counter() - t0) / args.steps
     stats = st
 
+    # base-case tiles inside the per-leaf kernel: every leaf pair exhaustive at h*
+    _, st_x = dfgt.gauss_sum(tree_x := dfgt.build_tree(x, leaf_size=LEAF), tree_x, [hstar], EPS,
+                             force_method=dfgt.FORCE_EXACT, stats=True, profile=True)
+    _, st_x = dfgt.gauss_sum(tree_x, tree_x, [hstar], EPS, force_method=dfgt.FORCE_EXACT, stats=True, profile=True)
+    base_case = {"pairs": st_x["base_point_pairs"], "k_etile_ms": st_x["kernel_ms"]["etile"]}
+    del tree_x
+
     # build alone
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -239,7 +261,8 @@ def main():
         "peak": peak / 1e9,
         "unit": "Gpair/s",
         "frac": achieved / peak,
-        "traffic": None,
+        "traffic": K_LEAF_TRAFFIC_BYTES,
+        "traffic_unit": "bytes per launch (HBM read + written)",
         "avg_launch_ms": base_ms / base_launches,
         "pairs_per_launch": base_pairs / base_launches,
         "dominant_kernel_in_step": dominant,
@@ -271,6 +294,12 @@ def main():
                                             "base_leaf_pairs", "base_point_pairs", "levels", "max_order",
                                             "segments", "max_segment", "local_nodes", "max_local_ops")},
         "roofline": roofline,
+        "base_case_tiles": {
+            "what": "one call with every leaf pair exhaustive (forced), bandwidth h*: the exhaustive-tile kernel",
+            "pairs": base_case["pairs"], "k_etile_ms": base_case["k_etile_ms"],
+            "pairs_per_s": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3),
+            "frac_of_alu_peak": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) / base_peak_pairs(d),
+        },
         "grad_ms": None,
     }
 

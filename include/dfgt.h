@@ -94,14 +94,16 @@ typedef struct dfgt_stats {
     int64_t max_segment;    /* most reference nodes in one segment */
     int64_t local_nodes;    /* internal (node, bandwidth) pairs with local-moment ops */
     int64_t max_local_ops;  /* most local-moment ops of one (node, bandwidth) */
-    int64_t reserved[2];
+    int64_t mfma_tiles;     /* parts of the call whose exhaustive sums ran on the
+                               matrix cores (D >= 8, mixed precision), else 0 */
+    int64_t reserved[1];
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
-     * [1] per-query-leaf kernel (exhaustive leaf-leaf sums of DFGTBase,
-     * far-field evaluation, local-to-local walk, local evaluation, combine),
-     * [2] exhaustive leaf-leaf sums on the matrix cores (D >= 8, mixed
-     * precision; [1] then skips them), [3] local-moment accumulation (D and T
-     * ops), [4] unused. */
+     * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,
+     * local evaluation, combine),
+     * [2] exhaustive leaf-leaf sums of DFGTBase (matrix cores for D >= 8 in
+     * mixed precision, vector ALUs otherwise; [1] adds their results),
+     * [3] local-moment accumulation (D and T ops), [4] unused. */
     double kernel_ms[5];
     int64_t kernel_launches[5];
 } dfgt_stats;

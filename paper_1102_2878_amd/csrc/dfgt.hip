@@ -869,7 +869,14 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
 }
 
 // Flattened (job, query leaf) items: job k owns items [jlstart[k], jlstart[k+1]).
-__device__ __forceinline__ void job_leaf(const int *__restrict__ jlstart, int njobs, int item, int *job, int *li) {
+// unl > 0: every job has unl items (one query tree), no search needed.
+__device__ __forceinline__ void job_leaf(const int *__restrict__ jlstart, int njobs, int unl, int item, int *job,
+                                         int *li) {
+    if (unl > 0) {
+        *job = item / unl;
+        *li = item - *job * unl;
+        return;
+    }
     int lo = 0, hi = njobs;  // jlstart[lo] <= item < jlstart[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -896,181 +903,27 @@ __global__ void k_fill_u32(unsigned *__restrict__ p, size_t n, unsigned v) {
 }
 
 // ---------------------------------------------------------------- per query leaf
-// One block per (query leaf, job).
-//   1. TransLocalToLocal from the root down the path to the leaf (each step
-//      one axis at a time: child L_a += sum_{b >= a} C(b, a) L_b X^{b-a},
-//      X = (child.c - parent.c) s), adding every path node's own moments;
-//      then the leaf's own D / T ops from their partial rows (chain order).
-//   2. Threads form ngr groups of `slots` lanes, one lane per query.  Thread 0
-//      flattens the leaf's E chain and the F chains of all path nodes into a
-//      segment table; ops are then processed in rounds, op = round * ngr +
-//      group, so groups sharing a wave work in lock step:
-//        E (DFGTBase): the reference leaf is staged in the group's LDS slice
-//           and sum_r exp(-|q - r|^2 / 2h^2) taken over it (mixed: exp2 of the
-//           FP64 squared scaled distance rounded to FP32, FP32 partial over
-//           <= 64 points, FP64 sums; or FP64 throughout);
+// One block per (job, query leaf).
+//   1. Local moments at the leaf: every ancestor's own moments translated to
+//      the leaf (TransLocalToLocal), then the leaf's own D / T ops from their
+//      partial rows (chain order), and the path's constant terms.
+//   2. Threads form ngr groups of `slots` lanes, one lane per query.  The F
+//      chains of all path nodes are flattened into a segment table; ops are
+//      processed in rounds, op = round * ngr + group, so groups sharing a
+//      wave work in lock step:
 //        F (EvalFarFieldExpansion): e^{-|t|^2} sum_{alpha<p} s^|alpha| mu_alpha prod_k H_{alpha_k}(t_k),
 //           t = (q - R.c) s, Hermite polynomials in the lane's LDS rows.
 //   3. Group partials are added in group order, the local expansion is
-//      evaluated (EvalLocalExpansion) and G = G_L + G_E + G_F is written in the
-//      caller's order.
+//      evaluated (EvalLocalExpansion) and G = G_L + G_F + G_E (G_E from the
+//      exhaustive-tile kernels) is written in the caller's order.
 // With GR the block also differentiates the same approximation (same ops,
 // same orders) with respect to s = 1/(sqrt2 h) and the query point, per query:
 //   X = s dG/ds  and  Y_k = (1/s) dG/dq_k,  written as dG/dh = -X/h, dG/dq_k = s Y_k:
-//   E:  X += -2 sum_r t_r e_r,   Y_k += -2 sum_r e_r (s(q - r))_k     (t_r = s^2 |q - r|^2)
+//   E:  X += -2 sum_r t_r e_r,   Y_k += -2 sum_r e_r (s(q - r))_k     (t_r = s^2 |q - r|^2),
+//       accumulated by the exhaustive-tile kernels
 //   F:  with V_k = -sum_alpha M_alpha h_{alpha + e_k}(t):  Y_k += V_k,
 //       X += sum_alpha |alpha| M_alpha h_alpha(t) + sum_k t_k V_k
 //   L:  X += sum_beta B_beta y^beta (B the tangent moments), Y_k += sum_beta L_beta beta_k y^{beta - e_k}
-constexpr int kInner = 64;
-
-template <int D>
-__device__ __forceinline__ double e_chunk(const double *__restrict__ xs, int cnt, const double *__restrict__ qg,
-                                          double sc, bool fp64) {
-    double qs[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) qs[k] = qg[k] * sc;
-    if (fp64) {
-        double acc = 0.0;
-        for (int j = 0; j < cnt; ++j) {
-            double t = 0.0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double dd = fma(xs[j * D + k], -sc, qs[k]);
-                t = fma(dd, dd, t);
-            }
-            acc += exp(-t);
-        }
-        return acc;
-    }
-    float ps = 0.0f;
-    for (int j = 0; j < cnt; ++j) {
-        double t = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const double dd = fma(xs[j * D + k], -sc, qs[k]);
-            t = fma(dd, dd, t);
-        }
-        ps += __builtin_amdgcn_exp2f(-(float)t);
-    }
-    return (double)ps;
-}
-
-__device__ double e_chunk_any(const double *__restrict__ xs, int cnt, int d, const double *__restrict__ qg, double sc,
-                              bool fp64) {
-    double acc = 0.0;
-    float ps = 0.0f;
-    for (int j = 0; j < cnt; ++j) {
-        double t = 0.0;
-        for (int k = 0; k < d; ++k) {
-            const double dd = fma(xs[j * d + k], -sc, qg[k] * sc);
-            t = fma(dd, dd, t);
-        }
-        if (fp64) acc += exp(-t);
-        else ps += __builtin_amdgcn_exp2f(-(float)t);
-    }
-    return fp64 ? acc : (double)ps;
-}
-
-__device__ __forceinline__ double e_chunk_dispatch(const double *xs, int cnt, int d, const double *qg, double sc,
-                                                   bool fp64) {
-    switch (d) {
-    case 1: return e_chunk<1>(xs, cnt, qg, sc, fp64);
-    case 2: return e_chunk<2>(xs, cnt, qg, sc, fp64);
-    case 3: return e_chunk<3>(xs, cnt, qg, sc, fp64);
-    case 4: return e_chunk<4>(xs, cnt, qg, sc, fp64);
-    case 5: return e_chunk<5>(xs, cnt, qg, sc, fp64);
-    case 8: return e_chunk<8>(xs, cnt, qg, sc, fp64);
-    case 16: return e_chunk<16>(xs, cnt, qg, sc, fp64);
-    default: return e_chunk_any(xs, cnt, d, qg, sc, fp64);
-    }
-}
-
-// Gradient form of e_chunk: returns sum_j e_j and adds cx sum_j t_j e_j to *x
-// and cy sum_j e_j dd_jk to g[k], where dd_j = sc (q - x_j) and t_j = |dd_j|^2
-// (the chunk's own scaling: sc = sig in mixed precision, where e_j = 2^{-t_j}).
-template <int D>
-__device__ __forceinline__ double e_chunk_grad(const double *__restrict__ xs, int cnt, const double *__restrict__ qg,
-                                               double sc, bool fp64, double cx, double cy, double *x, double *g) {
-    double qs[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) qs[k] = qg[k] * sc;
-    if (fp64) {
-        double s0 = 0.0, s1 = 0.0, sk[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) sk[k] = 0.0;
-        for (int j = 0; j < cnt; ++j) {
-            double dd[D], t = 0.0;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                dd[k] = fma(xs[j * D + k], -sc, qs[k]);
-                t = fma(dd[k], dd[k], t);
-            }
-            const double e = exp(-t);
-            s0 += e;
-            s1 = fma(t, e, s1);
-#pragma unroll
-            for (int k = 0; k < D; ++k) sk[k] = fma(e, dd[k], sk[k]);
-        }
-        *x = fma(cx, s1, *x);
-#pragma unroll
-        for (int k = 0; k < D; ++k) g[k] = fma(cy, sk[k], g[k]);
-        return s0;
-    }
-    float p0 = 0.0f, p1 = 0.0f, pk[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) pk[k] = 0.0f;
-    for (int j = 0; j < cnt; ++j) {
-        double dd[D], t = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            dd[k] = fma(xs[j * D + k], -sc, qs[k]);
-            t = fma(dd[k], dd[k], t);
-        }
-        const float tf = (float)t;
-        const float e = __builtin_amdgcn_exp2f(-tf);
-        p0 += e;
-        p1 = fmaf(tf, e, p1);
-#pragma unroll
-        for (int k = 0; k < D; ++k) pk[k] = fmaf(e, (float)dd[k], pk[k]);
-    }
-    *x = fma(cx, (double)p1, *x);
-#pragma unroll
-    for (int k = 0; k < D; ++k) g[k] = fma(cy, (double)pk[k], g[k]);
-    return (double)p0;
-}
-
-__device__ double e_chunk_grad_any(const double *__restrict__ xs, int cnt, int d, const double *__restrict__ qg,
-                                   double sc, bool fp64, double cx, double cy, double *x, double *g) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int j = 0; j < cnt; ++j) {
-        double t = 0.0;
-        for (int k = 0; k < d; ++k) {
-            const double dd = fma(xs[j * d + k], -sc, qg[k] * sc);
-            t = fma(dd, dd, t);
-        }
-        const double e = fp64 ? exp(-t) : (double)__builtin_amdgcn_exp2f(-(float)t);
-        s0 += e;
-        s1 = fma(t, e, s1);
-        for (int k = 0; k < d; ++k) g[k] = fma(cy * e, fma(xs[j * d + k], -sc, qg[k] * sc), g[k]);
-    }
-    *x = fma(cx, s1, *x);
-    return s0;
-}
-
-__device__ __forceinline__ double e_chunk_grad_dispatch(const double *xs, int cnt, int d, const double *qg, double sc,
-                                                        bool fp64, double cx, double cy, double *x, double *g) {
-    switch (d) {
-    case 1: return e_chunk_grad<1>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    case 2: return e_chunk_grad<2>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    case 3: return e_chunk_grad<3>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    case 4: return e_chunk_grad<4>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    case 5: return e_chunk_grad<5>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    case 8: return e_chunk_grad<8>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    case 16: return e_chunk_grad<16>(xs, cnt, qg, sc, fp64, cx, cy, x, g);
-    default: return e_chunk_grad_any(xs, cnt, d, qg, sc, fp64, cx, cy, x, g);
-    }
-}
-
 // ln 2 and sqrt(ln 2): mixed-precision tiles work in sig = sqrt(log2 e) s units.
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kSqrtLn2 = 0.83255461115769775635;
@@ -1078,7 +931,7 @@ constexpr double kSqrtLn2 = 0.83255461115769775635;
 // Doubles of dynamic LDS k_leaf needs before the coefficient vectors.
 __host__ __device__ inline size_t leaf_lds_base(int nthr, int d, int pmax, int gr) {
     return (size_t)nthr * (1 + gr) + (size_t)d * (pmax - 1) + 1 + (size_t)nthr * d * (pmax + gr) +
-           (size_t)nthr * d * (1 + gr);
+           (size_t)nthr * d * gr;
 }
 
 template <bool GR>
@@ -1093,7 +946,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const double *__restrict__ part, double *__restrict__ gscratch,
                                               const double *__restrict__ extE, const double *__restrict__ extX,
                                               const double *__restrict__ extY, const double *__restrict__ cval,
-                                              const int *__restrict__ jlstart, int njobs) {
+                                              const int *__restrict__ jlstart, int njobs, int unl) {
     extern __shared__ double smem[];
     if (*overflow) return;
     __shared__ double cs_s;
@@ -1102,7 +955,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg], ccnt[kMaxDepth + 1];
     __shared__ int nsg_s, nops_s, ntot_s, nops1_s, st_phase, st_gi, st_pi;
     int job, li;
-    job_leaf(jlstart, njobs, blockIdx.x, &job, &li);
+    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
@@ -1114,7 +967,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const double s = jb.s;
     const int ns = d * (pmax - 1) + 1;
     const size_t hq = (size_t)jb.noff + leaf;
-    // LDS: red[nthr] | redX[nthr] (GR) | spow[ns] | Hq[nthr][D][hs] | xs[nthr][D] | gq[nthr][D] (GR)
+    // LDS: red[nthr] | redX[nthr] (GR) | spow[ns] | Hq[nthr][D][hs] | gq[nthr][D] (GR)
     //      | acc[PW] | tmp[PW] | tmp2[PW] | coef[D][pmax^2] | dg[P] (u64) | mt[P] (u16)
     //      (acc / tmp / tmp2 in a global scratch slice when P is large)
     double *red = smem;
@@ -1122,8 +975,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     double *spow = redX + (GR ? nthr : 0);
     double *Hq_all = spow + ns;
     double *Hq = Hq_all + (size_t)tid * d * hs;
-    double *xs = Hq_all + (size_t)nthr * d * hs;
-    double *gq_all = xs + (size_t)nthr * d;
+    double *gq_all = Hq_all + (size_t)nthr * d * hs;
     double *gq = gq_all + (size_t)tid * d;
     double *tail = gq_all + (GR ? (size_t)nthr * d : 0);
     double *acc, *tmp, *tmp2, *coef;
@@ -1215,8 +1067,6 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     while (slots < nq && slots < nthr) slots <<= 1;
     const int ngr = nthr / slots;
     const int qi = tid % slots, tg = tid / slots;
-    const bool staged = slots <= 64;
-    double *xg = xs + (size_t)tg * slots * d;  // the group's staging slice
     const double *lc = Q.ctr + (size_t)leaf * d;
     // op groups: the leaf's E chain, then the F chains of the path nodes from
     // the root down, each chain in its own order.  One thread per chain counts
@@ -1225,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     for (int ch = tid; ch <= plen; ch += nthr) {
         int c = 0;
         if (ch == 0) {
-            for (int gi = extE ? -1 : headE[hq]; gi >= 0; gi = egrp[gi].next) ++c;
+            c = 0;  // exhaustive sums come from k_etile / k_emfma
         } else {
             for (int gi = headF[(size_t)jb.noff + path[plen - ch]]; gi >= 0; gi = fgrp[gi].next) ++c;
         }
@@ -1247,13 +1097,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         for (int ch = tid; ch <= plen; ch += nthr) {
             int o = ccnt[ch];
             if (ch == 0) {
-                for (int gi = extE ? -1 : headE[hq]; gi >= 0;) {
-                    const Group g = egrp[gi];
-                    segT[o] = g.flags ? 2 : 0;
-                    segS[o] = g.start;
-                    segE[o++] = g.count;
-                    gi = g.next;
-                }
+                // no E chain: exhaustive sums come from k_etile / k_emfma
             } else {
                 for (int gi = headF[(size_t)jb.noff + path[plen - ch]]; gi >= 0;) {
                     const Group g = fgrp[gi];
@@ -1285,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             for (int k = 0; k < d; ++k) gq[k] = 0.0;
         if (tid == 0) {
             st_phase = 0;
-            st_gi = extE ? -1 : headE[hq];  // exhaustive sums computed by k_emfma
+            st_gi = -1;  // exhaustive sums come from k_etile / k_emfma
             st_pi = plen - 1;
         }
         __syncthreads();
@@ -1338,33 +1182,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 while (idx >= segE[sp]) ++sp;
                 const int off = idx - (sp ? segE[sp - 1] : 0);
                 const int type = segT[sp];
-                if (type != 1) {
-                    const bool fp64 = precision == DFGT_PREC_FP64 || type == 2;
-                    const double sc = fp64 ? jb.s : jb.sig;
-                    const double cx = fp64 ? -2.0 : -2.0 * kLn2, cy = fp64 ? -2.0 : -2.0 * kSqrtLn2;
-                    const int r = eops[segS[sp] + off];
-                    const int rb = R.begin[r], re = R.end[r];
-                    if (staged) {
-                        for (int j0 = rb; j0 < re; j0 += slots) {
-                            const int cnt = min(slots, re - j0);
-                            if (qi < cnt)
-                                for (int k = 0; k < d; ++k) xg[qi * d + k] = R.x[(size_t)(j0 + qi) * d + k];
-                            wave_sync();
-                            if (act) {
-                                if (GR) part += e_chunk_grad_dispatch(xg, cnt, d, qg, sc, fp64, cx, cy, &px, gq);
-                                else part += e_chunk_dispatch(xg, cnt, d, qg, sc, fp64);
-                            }
-                            wave_sync();
-                        }
-                    } else if (act) {
-                        for (int j0 = rb; j0 < re; j0 += kInner) {
-                            const double *xr = R.x + (size_t)j0 * d;
-                            const int cnt = min(kInner, re - j0);
-                            if (GR) part += e_chunk_grad_dispatch(xr, cnt, d, qg, sc, fp64, cx, cy, &px, gq);
-                            else part += e_chunk_dispatch(xr, cnt, d, qg, sc, fp64);
-                        }
-                    }
-                } else if (act) {
+                if (act) {  // every op here is a far-field evaluation
                     const Op op = fops[segS[sp] + off];
                     const int r = op.r, p = op.meta & 255;
                     const double *mu = R.mu + (size_t)r * P;
@@ -1468,6 +1286,212 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     }
 }
 
+constexpr int kEChunk = 256;   // E ops flattened per round
+constexpr int kMaxEGrp = 256;  // E groups of one (job, node) chain (at most one per level)
+
+// ---------------------------------------------------------------- exhaustive tiles on the vector ALUs
+// DFGTBase for every dimension (the matrix-core kernel below takes D >= 8 in
+// mixed precision).  One block of 256 threads per (job, query leaf): the
+// leaf's E chain is flattened 256 ops at a time (reference range and point
+// count, block-wide scan), and the reference points stream through LDS 256
+// per round.  Threads form 256 / slots groups of `slots` lanes, one lane per
+// query; group g takes points [g slots, (g+1) slots) of each round.  Per pair:
+// the FP64 scaled difference, then (mixed) FP32 exp2 of the rounded square with
+// FP32 partial sums over <= 64 terms and FP64 beyond, or FP64 throughout
+// (precision FP64, or the op's group flagged by the underflow guard).  Group
+// partials are added in group order.  Writes G_E (and with GR X_E, Y_E) per
+// query in tree order, which k_leaf adds to the rest.
+constexpr int kEStage = 2048;  // doubles of staged reference coordinates per round
+
+// Accumulates the pairs of one query with staged points [j0, j1) (scaled by
+// sig: e = 2^{-|qs - xs|^2}), FP32 partials over 64 points, FP64 beyond.
+template <int DT, bool GR>
+__device__ __forceinline__ void etile_mixed(const double *__restrict__ stage, int j0, int j1, int d,
+                                            const double *qs, double &acc, double &xacc, double *yacc) {
+    constexpr int DS = DT > 0 ? DT : kMaxD;
+    for (int jb = j0; jb < j1; jb += 64) {
+        const int je = min(j1, jb + 64);
+        float ps = 0.0f, pt = 0.0f, py[DS];
+        if (GR)
+            for (int c = 0; c < d; ++c) py[c] = 0.0f;
+        for (int j = jb; j < je; ++j) {
+            const double *xr = stage + j * d;
+            double t = 0.0, dd[DS];
+            for (int c = 0; c < d; ++c) {
+                dd[c] = qs[c] - xr[c];
+                t = fma(dd[c], dd[c], t);
+            }
+            const float tf = (float)t;
+            const float e = __builtin_amdgcn_exp2f(-tf);
+            ps += e;
+            if (GR) {
+                pt = fmaf(tf, e, pt);
+                for (int c = 0; c < d; ++c) py[c] = fmaf(e, (float)dd[c], py[c]);
+            }
+        }
+        acc += (double)ps;
+        if (GR) {
+            xacc = fma(-2.0 * kLn2, (double)pt, xacc);
+            for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2, (double)py[c], yacc[c]);
+        }
+    }
+}
+
+template <int DT, bool GR>
+__global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                               const Group *__restrict__ egrp, const int *__restrict__ eops,
+                                               const int *__restrict__ headE, const int *__restrict__ overflow,
+                                               const int *__restrict__ jlstart, int njobs, int unl, int precision,
+                                               double *__restrict__ GE, double *__restrict__ GX,
+                                               double *__restrict__ GY) {
+    constexpr int DS = DT > 0 ? DT : kMaxD;  // register arrays (runtime d only in the DT = 0 form)
+    constexpr int kStage = DT > 0 ? 256 * DT : kEStage;
+    __shared__ int gS[kMaxEGrp], gC[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
+    __shared__ int oB[kEChunk], oN[kEChunk], oF[kEChunk], oCum[kEChunk];
+    __shared__ int wsum[4], nops_s, f64_s;
+    __shared__ double stage[kStage];
+    __shared__ unsigned char pflag[256];
+    __shared__ double red[256];
+    if (*overflow) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int job, li;
+    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
+    const Job jb = jobs[job];
+    const DevTree &Q = trees[jb.qt];
+    const DevTree &R = trees[jb.rt];
+    const int leaf = Q.leaves[li];
+    const int d = DT > 0 ? DT : Q.d;
+    const int RP = min(256, kStage / d);  // reference points per round
+    const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
+    const size_t hq = (size_t)jb.noff + leaf;
+    const int head = headE[hq];
+    if (head < 0) {  // no exhaustive pairs for this leaf
+        for (int i = tid; i < nq; i += blockDim.x) {
+            const size_t ei = (size_t)jb.qoff + qb0 + i;
+            GE[ei] = 0.0;
+            if (GR) {
+                GX[ei] = 0.0;
+                for (int c = 0; c < d; ++c) GY[ei * d + c] = 0.0;
+            }
+        }
+        return;
+    }
+    if (tid == 0) {
+        int n = 0, tot = 0;
+        for (int gi = head; gi >= 0 && n < kMaxEGrp; gi = egrp[gi].next) {
+            const Group gg = egrp[gi];
+            gS[n] = gg.start;
+            gC[n] = gg.count;
+            gF[n] = gg.flags;
+            tot += gg.count;
+            gCum[n++] = tot;
+        }
+        nops_s = tot;
+    }
+    __syncthreads();
+    const int nops = nops_s;
+    const bool all64 = precision == DFGT_PREC_FP64;
+    for (int qg = 0; qg < nq; qg += 256) {
+        const int nqg = min(256, nq - qg);
+        int slots = 1;
+        while (slots < nqg) slots <<= 1;
+        const int ngr = 256 / slots;
+        const int qi = tid % slots, grp = tid / slots;
+        const bool act = qi < nqg;
+        const int qpos = qb0 + qg + (act ? qi : 0);
+        double qs[DS];
+        for (int c = 0; c < d; ++c) qs[c] = Q.x[(size_t)qpos * d + c] * jb.sig;
+        double acc = 0.0, xacc = 0.0, yacc[DS];
+        if (GR)
+            for (int c = 0; c < d; ++c) yacc[c] = 0.0;
+        for (int o0 = 0; o0 < nops; o0 += kEChunk) {
+            __syncthreads();
+            const int o = o0 + tid;
+            int np = 0;
+            if (o < nops) {
+                int gi = 0;
+                while (o >= gCum[gi]) ++gi;
+                const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
+                oB[tid] = R.begin[r];
+                np = R.end[r] - R.begin[r];
+                oN[tid] = np;
+                oF[tid] = gF[gi];
+            }
+            const int inc = wave_incl_scan(np);
+            if (lane == 63) wsum[wv] = inc;
+            __syncthreads();
+            int pre = 0;
+            for (int w = 0; w < wv; ++w) pre += wsum[w];
+            oCum[tid] = pre + inc;
+            __syncthreads();
+            const int nopc = min(kEChunk, nops - o0);
+            const int tot = oCum[nopc - 1];
+            for (int p0 = 0; p0 < tot; p0 += RP) {
+                // stage this round's points, scaled by sig, and their precision flags
+                const int p = p0 + tid;
+                int fl = 0;
+                if (tid < RP && p < tot) {
+                    int lo = 0, hi = nopc - 1;  // first op with oCum > p
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (oCum[mid] > p) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    const int row = oB[lo] + p - (lo ? oCum[lo - 1] : 0);
+                    for (int c = 0; c < d; ++c) stage[tid * d + c] = R.x[(size_t)row * d + c] * jb.sig;
+                    fl = (all64 || oF[lo] != 0) ? 1 : 0;
+                    pflag[tid] = (unsigned char)fl;
+                }
+                const int any64 = __syncthreads_or(fl);
+                const int cnt = min(RP, tot - p0);
+                const int j0 = grp * slots, j1 = min(cnt, j0 + slots);
+                if (act && j0 < j1) {
+                    if (!any64) {
+                        etile_mixed<DT, GR>(stage, j0, j1, d, qs, acc, xacc, yacc);
+                    } else {
+                        // a round with FP64 points (precision FP64, or groups flagged by
+                        // the underflow guard): pair by pair; t is in sig units, e = 2^-t
+                        for (int j = j0; j < j1; ++j) {
+                            const double *xr = stage + j * d;
+                            double t = 0.0, dd[DS];
+                            for (int c = 0; c < d; ++c) {
+                                dd[c] = qs[c] - xr[c];
+                                t = fma(dd[c], dd[c], t);
+                            }
+                            if (pflag[j]) {
+                                const double e = exp(-t * kLn2);
+                                acc += e;
+                                if (GR) {
+                                    xacc = fma(-2.0 * kLn2 * t, e, xacc);
+                                    for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2 * e, dd[c], yacc[c]);
+                                }
+                            } else {
+                                etile_mixed<DT, GR>(stage, j, j + 1, d, qs, acc, xacc, yacc);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // groups in order, one quantity at a time through red[]
+        const size_t ei = (size_t)jb.qoff + qb0 + qg + qi;
+        const int nred = GR ? 2 + d : 1;
+        for (int v = 0; v < nred; ++v) {
+            red[tid] = v == 0 ? acc : (v == 1 ? xacc : yacc[v - 2]);
+            __syncthreads();
+            if (grp == 0 && act) {
+                double sum = 0.0;
+                for (int k = 0; k < ngr; ++k) sum += red[k * slots + qi];
+                if (v == 0) GE[ei] = sum;
+                else if (v == 1) GX[ei] = sum;
+                else GY[ei * d + (v - 2)] = sum;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- exhaustive tiles on the matrix cores
 // D >= 8, mixed precision (see etile.h).  One block of 4 waves per (query
 // leaf, job): the leaf's E chain is flattened 256 ops at a time (in parallel,
@@ -1477,14 +1501,11 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
 // query (tree order) it writes G_E = sum e, and with GR also X_E and Y_E (the
 // quantities k_leaf defines) to GE, GX, GY, which k_leaf adds to the rest.
 // Groups flagged by the underflow guard take FP64 exponentials.
-constexpr int kEChunk = 256;
-constexpr int kMaxEGrp = 256;
-
 template <bool GR, int NC>
 __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
                                                const int *__restrict__ headE, const int *__restrict__ overflow,
-                                               const int *__restrict__ jlstart, int njobs,
+                                               const int *__restrict__ jlstart, int njobs, int unl,
                                                double *__restrict__ GE, double *__restrict__ GX,
                                                double *__restrict__ GY) {
     constexpr int NT = (NC + 3) / 4;  // 16-dimension tiles of the gradient product
@@ -1496,7 +1517,7 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
     if (*overflow) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4;
     int job, li;
-    job_leaf(jlstart, njobs, blockIdx.x, &job, &li);
+    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
@@ -1752,6 +1773,24 @@ struct Workspace {
         lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
     int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
+    // the exhaustive tiles run on a side stream beside the local-moment ops
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    dfgt_status ensure_side() {
+        if (side) return DFGT_OK;
+        if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            set_error("creating the side stream failed");
+            return DFGT_EHIP;
+        }
+        return DFGT_OK;
+    }
+    ~Workspace() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 thread_local Workspace g_ws;
 
@@ -1762,11 +1801,11 @@ constexpr int kLocalGrid = 2048;
 
 template <bool GR>
 void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd, const Group *egrp,
-                  const int *eops, const int *headE, const int *flag, const int *jls, int njobs, double *GE,
-                  double *GX, double *GY) {
+                  const int *eops, const int *headE, const int *flag, const int *jls, int njobs, int unl,
+                  double *GE, double *GX, double *GY) {
 #define DFGT_EMFMA(NCV)                                                                                     \
     hipLaunchKernelGGL((k_emfma<GR, NCV>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, jls, njobs, \
-                       GE, GX, GY);                                                                         \
+                       unl, GE, GX, GY);                                                                    \
     break;
     switch (nc) {
     case 2: DFGT_EMFMA(2)
@@ -1778,6 +1817,25 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
     default: DFGT_EMFMA(8)
     }
 #undef DFGT_EMFMA
+}
+
+template <bool GR>
+void launch_etile(int d, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd, const Group *egrp,
+                  const int *eops, const int *headE, const int *flag, const int *jls, int njobs, int unl,
+                  int precision, double *GE, double *GX, double *GY) {
+#define DFGT_ETILE(DV)                                                                                              \
+    hipLaunchKernelGGL((k_etile<DV, GR>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, jls, njobs,      \
+                       unl, precision, GE, GX, GY);                                                                \
+    break;
+    switch (d) {
+    case 1: DFGT_ETILE(1)
+    case 2: DFGT_ETILE(2)
+    case 3: DFGT_ETILE(3)
+    case 4: DFGT_ETILE(4)
+    case 5: DFGT_ETILE(5)
+    default: DFGT_ETILE(0)
+    }
+#undef DFGT_ETILE
 }
 
 // Everything about a call that does not depend on the traversal's output
@@ -1792,7 +1850,18 @@ struct Plan {
     int leaf_threads = 256, lop_waves = 4;
     size_t leaf_sh = 0, lop_sh = 0, big_sh = 0;
     size_t job_off = 0, jls_off = 0;  // where this plan's tables sit in the device arrays
+    int unl = 0;                      // items per job when all jobs share one query leaf count, else 0
 };
+
+int uniform_leaves(const Plan &pl) {
+    int u = -1;
+    for (const Job &j : pl.jobs) {
+        const int nl = pl.trees[j.qt].nleaves;
+        if (u < 0) u = nl;
+        else if (u != nl) return 0;
+    }
+    return u > 0 ? u : 0;
+}
 
 // Jobs [j0, j1) of a plan as a plan of their own (jobs are independent).
 Plan sub_plan(const Plan &pl, int j0, int j1) {
@@ -1814,6 +1883,7 @@ Plan sub_plan(const Plan &pl, int j0, int j1) {
     sp.nqa = (size_t)nqa;
     sp.items = (int)items;
     sp.job_off = sp.jls_off = 0;
+    sp.unl = uniform_leaves(sp);
     return sp;
 }
 
@@ -1918,11 +1988,16 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     // exhaustive leaf sums on the matrix cores: mixed precision, D >= 8, and
     // s^2 (|q|^2 + |r|^2) <= 2^26 for every bandwidth (rounding of the
     // expanded squared distance below ~1e-7)
-    pl.emfma = precision == DFGT_PREC_MIXED && pl.d >= 8 && pl.d <= 32 && pl.nlev <= kMaxEGrp;
+    if (pl.nlev > kMaxEGrp) {  // an E chain holds at most one group per level
+        set_error("dfgt_gauss_sum: trees deeper than 256 levels");
+        return DFGT_EINVAL;
+    }
+    pl.emfma = precision == DFGT_PREC_MIXED && pl.d >= 8 && pl.d <= 32;
     for (const Job &j : pl.jobs) {
         if (!pl.emfma) break;
         pl.emfma = j.sig * j.sig * (th[j.qt]->max_nrm + th[j.rt]->max_nrm) <= 67108864.0;
     }
+    pl.unl = uniform_leaves(pl);
     // launch shapes
     const int d = pl.d, pmax = pl.pmax, P = pl.P, PW = pl.PW;
     const int g1 = pl.gr ? 1 : 0;
@@ -1961,6 +2036,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
 
 // Device buffers for the plan and the current capacities (no-op when large enough).
 dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
+    DFGT_TRY(w.ensure_side());
     const Caps &cap = w.cap;
     const size_t nna = pl.nna;
     DFGT_TRY(grow<Job>(w.jobs, pl.njobs));
@@ -1974,12 +2050,11 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<int>(w.flag, 1));
     DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
     DFGT_TRY(grow<int>(w.lvl, (size_t)(pl.nlev + 1) * 2 * CP));
-    if (pl.emfma) {
-        DFGT_TRY(grow<double>(w.extE, pl.nqa));
-        if (pl.gr) {
-            DFGT_TRY(grow<double>(w.extX, pl.nqa));
-            DFGT_TRY(grow<double>(w.extY, pl.nqa * pl.d));
-        }
+    // exhaustive sums per query (k_emfma or k_etile), added by k_leaf
+    DFGT_TRY(grow<double>(w.extE, pl.nqa));
+    if (pl.gr) {
+        DFGT_TRY(grow<double>(w.extX, pl.nqa));
+        DFGT_TRY(grow<double>(w.extY, pl.nqa * pl.d));
     }
     DFGT_TRY(grow<Seg>(w.segA, cap.seg));
     DFGT_TRY(grow<Seg>(w.segB, cap.seg));
@@ -2051,14 +2126,26 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                            pl.gr ? 1 : 0, pl.leaf_local ? 1 : 0, w.dec.as<int>(), w.kus.as<double>(), o);
         if (prof) prof->stop(K_TRAV, ev, st);
     }
-    if (pl.emfma) {
-        hipEvent_t ev = prof ? prof->start(st) : nullptr;
-        auto fn = pl.gr ? launch_emfma<true> : launch_emfma<false>;
-        fn((d + 3) / 4, dim3(pl.items), st, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.flag.as<int>(),
-           jls, njobs, w.extE.as<double>(), pl.gr ? w.extX.as<double>() : nullptr,
-           pl.gr ? w.extY.as<double>() : nullptr);
-        if (prof) prof->stop(K_EMFMA, ev, st);
+    // exhaustive leaf-leaf sums (DFGTBase) on the side stream, concurrent with
+    // the local-moment ops below (they share no buffers); joined before k_leaf
+    (void)hipEventRecord(w.fork, st);
+    (void)hipStreamWaitEvent(w.side, w.fork, 0);
+    {
+        hipStream_t ss = w.side;
+        hipEvent_t ev = prof ? prof->start(ss) : nullptr;
+        double *gx = pl.gr ? w.extX.as<double>() : nullptr, *gy = pl.gr ? w.extY.as<double>() : nullptr;
+        if (pl.emfma) {
+            auto fn = pl.gr ? launch_emfma<true> : launch_emfma<false>;
+            fn((d + 3) / 4, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
+               w.flag.as<int>(), jls, njobs, pl.unl, w.extE.as<double>(), gx, gy);
+        } else {
+            auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
+            fn(d, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.flag.as<int>(), jls,
+               njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
+        }
+        if (prof) prof->stop(K_EMFMA, ev, ss);
     }
+    (void)hipEventRecord(w.join, w.side);
     // local moments: every D / T op in parallel, then per internal node
     {
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
@@ -2082,6 +2169,7 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
         if (prof) prof->stop(K_LOCAL, ev, st);
     }
     // everything per (job, query leaf)
+    (void)hipStreamWaitEvent(st, w.join, 0);
     {
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
         auto kl = pl.gr ? k_leaf<true> : k_leaf<false>;
@@ -2090,10 +2178,9 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                            w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
                            pl.precision, pl.acc_lds ? 1 : 0, pl.leaf_local ? 1 : 0, w.flag.as<int>(),
                            pl.leaf_local ? w.part.as<double>() : (const double *)nullptr, w.pscr.as<double>(),
-                           pl.emfma ? w.extE.as<double>() : (const double *)nullptr,
-                           pl.emfma && pl.gr ? w.extX.as<double>() : (const double *)nullptr,
-                           pl.emfma && pl.gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>(),
-                           jls, njobs);
+                           w.extE.as<double>(), pl.gr ? w.extX.as<double>() : (const double *)nullptr,
+                           pl.gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>(), jls, njobs,
+                           pl.unl);
         if (prof) prof->stop(K_LEAF, ev, st);
     }
 }
@@ -2157,6 +2244,7 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
     out->max_segment = (int64_t)sv[S_MAXSEG];
     out->local_nodes = c[C_LNODE];
     out->max_local_ops = (int64_t)sv[S_MAXLOPS];
+    out->mfma_tiles = pl.emfma ? 1 : 0;
     if (prof && prof->on) prof->collect(out);
     return DFGT_OK;
 }
@@ -2213,6 +2301,7 @@ void add_stats(dfgt_stats *a, const dfgt_stats &b) {
     a->max_segment = std::max(a->max_segment, b.max_segment);
     a->local_nodes += b.local_nodes;
     a->max_local_ops = std::max(a->max_local_ops, b.max_local_ops);
+    a->mfma_tiles += b.mfma_tiles;
     for (int k = 0; k < 5; ++k) {
         a->kernel_ms[k] += b.kernel_ms[k];
         a->kernel_launches[k] += b.kernel_launches[k];

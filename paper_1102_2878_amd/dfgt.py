@@ -34,10 +34,10 @@ class Stats(C.Structure):
     _fields_ = [(nm, C.c_int64) for nm in (
         "node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid", "base_leaf_pairs",
         "base_point_pairs", "levels", "max_order", "fp64_groups", "segments", "max_segment", "local_nodes",
-        "max_local_ops")] + [("reserved", C.c_int64 * 2),
+        "max_local_ops", "mfma_tiles")] + [("reserved", C.c_int64 * 1),
                                                                        ("kernel_ms", C.c_double * 5),
                                                                        ("kernel_launches", C.c_int64 * 5)]
-    KERNELS = ("traverse", "leaf", "emfma", "local", "unused4")
+    KERNELS = ("traverse", "leaf", "etile", "local", "unused4")
 
     def as_dict(self):
         d = {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm not in ("reserved", "kernel_ms",

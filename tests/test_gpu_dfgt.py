@@ -173,7 +173,7 @@ def test_high_dimensions_matrix_core_tiles(dfgt, d):
         note(f"dfgt high-d d={d} eps={eps} leaf={leaf}")
         R = dfgt.build_tree(cuda(x), leaf_size=leaf)
         G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True, profile=True)
-        assert st["kernel_launches"]["emfma"] == 1
+        assert st["kernel_launches"]["etile"] == 1 and st["mfma_tiles"] == 1
         G = G.cpu().numpy()
         for k, h in enumerate(hs):
             rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
@@ -189,7 +189,7 @@ def test_high_dimension_bichromatic_and_fp64(dfgt):
         R = dfgt.build_tree(cuda(x), leaf_size=40)
         Q = dfgt.build_tree(cuda(q), leaf_size=40)
         G, st = dfgt.gauss_sum(Q, R, hs, tol, precision=precision, stats=True, profile=True)
-        assert st["kernel_launches"]["emfma"] == (1 if precision == 0 else 0)
+        assert st["mfma_tiles"] == (1 if precision == 0 else 0)
         G = G.cpu().numpy()
         for k, h in enumerate(hs):
             rel = _rel_err(G[k], oracle.naive_kde(q, x, h))
