@@ -887,6 +887,24 @@ __device__ __forceinline__ void job_leaf(const int *__restrict__ jlstart, int nj
     *li = item - jlstart[lo];
 }
 
+// Digit tables of every coefficient position in global memory (for p_max^d
+// too large for the per-leaf kernel's LDS); same layout as build_digit_tables.
+__global__ void k_digits(unsigned long long *dg, unsigned short *mt, int P, int d, int pmax) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x) {
+        int rem = i, sum = 0, mx = 0;
+        unsigned long long packed = 0;
+        for (int k = d - 1; k >= 0; --k) {
+            const int a = rem % pmax;
+            rem /= pmax;
+            if (a) packed |= (unsigned long long)a << (4 * k);
+            sum += a;
+            mx = a > mx ? a : mx;
+        }
+        dg[i] = packed;
+        mt[i] = (unsigned short)(sum | (mx << 8));
+    }
+}
+
 // Level-0 frontier: one segment (Q root, {R root}) per job.
 __global__ void k_seed(Seg *__restrict__ segs, int *__restrict__ pairs, int njobs) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -946,7 +964,9 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const double *__restrict__ part, double *__restrict__ gscratch,
                                               const double *__restrict__ extE, const double *__restrict__ extX,
                                               const double *__restrict__ extY, const double *__restrict__ cval,
-                                              const int *__restrict__ jlstart, int njobs, int unl) {
+                                              const int *__restrict__ jlstart, int njobs, int unl,
+                                              const unsigned long long *__restrict__ gdg,
+                                              const unsigned short *__restrict__ gmt) {
     extern __shared__ double smem[];
     if (*overflow) return;
     __shared__ double cs_s;
@@ -990,9 +1010,16 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         tmp2 = tmp + PW;
         coef = tail;
     }
-    unsigned long long *dg = reinterpret_cast<unsigned long long *>(coef + d * pmax * pmax);
-    unsigned short *mt = reinterpret_cast<unsigned short *>(dg + P);
-    build_digit_tables(dg, mt, P, d, pmax);
+    // digit tables: in LDS, or (large P) prepared in global memory by k_digits
+    const unsigned long long *dg = gdg;
+    const unsigned short *mt = gmt;
+    if (!gdg) {
+        unsigned long long *ldg = reinterpret_cast<unsigned long long *>(coef + d * pmax * pmax);
+        unsigned short *lmt = reinterpret_cast<unsigned short *>(ldg + P);
+        build_digit_tables(ldg, lmt, P, d, pmax);
+        dg = ldg;
+        mt = lmt;
+    }
     // root path (precomputed with the tree: path[0] = the leaf, path[plen-1] = the root)
     const int plen = Q.lplen[li];
     int mine = 0;
@@ -1770,7 +1797,7 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_POST = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
-        lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval;
+        lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval, gdg, gmt;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
     int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
     // the exhaustive tiles run on a side stream beside the local-moment ops
@@ -1845,7 +1872,7 @@ struct Plan {
     std::vector<DevTree> trees;
     std::vector<int> jls;  // per-job prefix of (job, query leaf) items
     int njobs = 0, nlev = 0, d = 0, pmax = 0, P = 0, PW = 0, precision = 0, force = 0, items = 0;
-    bool gr = false, leaf_local = true, emfma = false, acc_lds = true;
+    bool gr = false, leaf_local = true, emfma = false, acc_lds = true, dig_lds = true;
     size_t nna = 0, nqa = 0;  // node slots and query slots over all jobs
     int leaf_threads = 256, lop_waves = 4;
     size_t leaf_sh = 0, lop_sh = 0, big_sh = 0;
@@ -2025,7 +2052,8 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     const size_t lds_acc = sizeof(double) * 3 * (size_t)PW + lds_coef;
     // dynamic LDS up to 56 KB: the kernel's static arrays take ~6 KB of the 64 KB
     pl.acc_lds = base + lds_acc + lds_dig <= 56 * 1024;
-    pl.leaf_sh = base + (pl.acc_lds ? lds_acc : lds_coef) + lds_dig;
+    pl.dig_lds = base + (pl.acc_lds ? lds_acc : lds_coef) + lds_dig <= 56 * 1024;
+    pl.leaf_sh = base + (pl.acc_lds ? lds_acc : lds_coef) + (pl.dig_lds ? lds_dig : 0);
     pl.leaf_threads = nthr;
     if (pl.leaf_sh > 56 * 1024) {
         set_error("dfgt_gauss_sum: p_max^d too large for the per-leaf kernel");
@@ -2076,6 +2104,10 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
         DFGT_TRY(grow<double>(w.lscr, (size_t)kLocalGrid * 3 * pl.P));
     }
     if (!pl.acc_lds) DFGT_TRY(grow<double>(w.pscr, (size_t)pl.items * 3 * pl.PW));
+    if (!pl.dig_lds) {
+        DFGT_TRY(grow<unsigned long long>(w.gdg, pl.P));
+        DFGT_TRY(grow<unsigned short>(w.gmt, pl.P));
+    }
     return DFGT_OK;
 }
 
@@ -2112,6 +2144,9 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
     fill_u32(w.flag.p, 1, 0u, st);
     fill_u32(w.stats.p, 2 * S_N * SP, 0u, st);
     hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
+    if (!pl.dig_lds)
+        hipLaunchKernelGGL(k_digits, dim3((P + 255) / 256), dim3(256), 0, st, w.gdg.as<unsigned long long>(),
+                           w.gmt.as<unsigned short>(), P, d, pmax);
     for (int k = 0; k < nlev; ++k) {
         DevBuf &sin = (k & 1) ? w.segB : w.segA, &sout = (k & 1) ? w.segA : w.segB;
         DevBuf &pin = (k & 1) ? w.pairB : w.pairA, &pout = (k & 1) ? w.pairA : w.pairB;
@@ -2180,7 +2215,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                            pl.leaf_local ? w.part.as<double>() : (const double *)nullptr, w.pscr.as<double>(),
                            w.extE.as<double>(), pl.gr ? w.extX.as<double>() : (const double *)nullptr,
                            pl.gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>(), jls, njobs,
-                           pl.unl);
+                           pl.unl, pl.dig_lds ? nullptr : w.gdg.as<unsigned long long>(),
+                           pl.dig_lds ? nullptr : w.gmt.as<unsigned short>());
         if (prof) prof->stop(K_LEAF, ev, st);
     }
 }

@@ -194,3 +194,18 @@ def test_high_dimension_bichromatic_and_fp64(dfgt):
         for k, h in enumerate(hs):
             rel = _rel_err(G[k], oracle.naive_kde(q, x, h))
             assert rel.max() <= tol, (precision, h, rel.max())
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_five_dimensions_order_six(dfgt, eps):
+    """The 5-D workload's expansion order: p_max = 6 per dimension, 7,776
+    coefficients per moment vector (digit tables and local moments then live in
+    global memory, local ops run per node)."""
+    x = synth.c3(n=5000, seed=44)
+    hs = [synth.silverman_h(x) * s for s in (0.3, 3.0, 30.0)]
+    note(f"dfgt d=5 pmax=6 eps={eps}")
+    G, st = _run(dfgt, x, None, hs, eps, pmax=6)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+        assert rel.max() <= eps, (h, rel.max())
+    assert st["max_order"] >= 2
