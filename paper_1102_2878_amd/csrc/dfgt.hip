@@ -840,18 +840,21 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
                     }
                     __syncthreads();
                     for (int b = threadIdx.x; b < P; b += blockDim.x) {
-                        bool inside;
-                        digit_sum(b, d, pmax, p, &inside);
+                        // digits of b decoded once: offsets into each point's Hermite rows
+                        int off[kMaxD];
+                        bool inside = true;
+                        for (int k = d - 1, bi = b; k >= 0; --k) {
+                            const int dk = bi % pmax;
+                            bi /= pmax;
+                            inside = inside && dk < p;
+                            off[k] = k * pmax + dk;
+                        }
                         if (!inside) continue;
                         double sum = 0.0;
                         for (int j = 0; j < cnt; ++j) {
                             const double *row = Hx + (size_t)j * d * pmax;
-                            int bi = b;
-                            double prod = 1.0;
-                            for (int k = d - 1; k >= 0; --k) {
-                                prod *= row[k * pmax + bi % pmax];
-                                bi /= pmax;
-                            }
+                            double prod = row[off[d - 1]];
+                            for (int k = d - 2; k >= 0; --k) prod *= row[off[k]];
                             sum += prod;
                         }
                         acc[b] += coef_beta(b, d, pmax) * sum;
