@@ -48,15 +48,22 @@ LEAF = 32
 # 2D+1 FP32 VALU operations (D differences, D-1 fused multiply-adds + 1 multiply,
 # 1 add) and one v_exp_f32.  Peak pair rate = 256 CUs x 64 lanes x 2.4 GHz /
 # (2D+1 + EXP_SLOTS) VALU issue slots, EXP_SLOTS = issue cost of v_exp_f32 in
-# full-rate slots (transcendentals run at a quarter of the VALU rate).
+# full-rate slots (transcendentals run at a quarter of the VALU rate).  Rates
+# are also quoted in TFLOP/s at FLOPS_PER_PAIR = 3D+1 (D subtractions, D
+# squares, D-1 additions, the exponential, the accumulation).
 CUS, LANES, CLOCK = 256, 64, 2.4e9
 EXP_SLOTS = 4
 
-# HBM bytes per launch of k_leaf on this workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB device copy
-# (x2.0 and x1.0): profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
-# as profiled; set to None when k_leaf changes until the counters are retaken.
-K_LEAF_TRAFFIC_BYTES = 29.52e6 + 10.09e6
+# HBM bytes per launch of the mixed-precision exhaustive-tile kernel
+# (k_etile<2, false, false>) in one step of this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB
+# device copy: profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
+# as profiled; None when the kernel has changed since.
+K_ETILE_TRAFFIC_BYTES = 12.96e6 + 3.16e6
+
+
+def flops_per_pair(d):
+    return 3 * d + 1
 
 
 def base_peak_pairs(d):
@@ -249,23 +256,31 @@ def main():
     pairs = float(n) * n * len(hs)
     value = pairs / t_step
 
-    base_ms = agg_ms.get("leaf", 0.0)
-    base_launches = max(agg_launch.get("leaf", 0), 1)
+    # roofline of the exhaustive tiles (DFGTBase) in the timed step, from the
+    # HIP events around their launches on the stream they run on
+    et_ms = agg_ms.get("etile", 0.0)
+    et_launches = max(agg_launch.get("etile", 0), 1)
     dominant = max(agg_ms, key=agg_ms.get) if agg_ms else None
-    achieved = (base_pairs / (base_ms * 1e-3)) if base_ms > 0 else 0.0
+    pair_rate = (base_pairs / (et_ms * 1e-3)) if et_ms > 0 else 0.0
     peak = base_peak_pairs(d)
+    fpp = flops_per_pair(d)
     roofline = {
-        "kernel": "k_leaf (exhaustive leaf-leaf tiles of DFGTBase + far-field evaluation + local evaluation)",
+        "kernel": "k_etile (DFGTBase exhaustive leaf-leaf tiles, mixed precision)",
         "bound": "alu",
-        "achieved": achieved / 1e9,
-        "peak": peak / 1e9,
-        "unit": "Gpair/s",
-        "frac": achieved / peak,
-        "traffic": K_LEAF_TRAFFIC_BYTES,
-        "traffic_unit": "bytes per launch (HBM read + written)",
-        "avg_launch_ms": base_ms / base_launches,
-        "pairs_per_launch": base_pairs / base_launches,
+        "achieved": pair_rate * fpp / 1e12,
+        "peak": peak * fpp / 1e12,
+        "unit": "TFLOP/s",
+        "frac": pair_rate / peak,
+        "traffic": K_ETILE_TRAFFIC_BYTES,
+        "traffic_unit": "HBM bytes per launch (read + written)",
+        "flops_per_pair": fpp,
+        "pairs_per_s": pair_rate,
+        "peak_pairs_per_s": peak,
+        "avg_launch_ms": et_ms / et_launches,
+        "pairs_per_launch": base_pairs / et_launches,
         "dominant_kernel_in_step": dominant,
+        "dominant_kernel_note": "k_traverse is latency-bound (one wave per segment, one launch per tree level): "
+                                "it has no throughput roofline; see traversal.node_pairs_per_s",
     }
 
     out = {
@@ -290,14 +305,18 @@ def main():
         "speedup_vs_bruteforce": t_bf / t_step,
         "phases_ms": {"build_tree": t_build * 1e3, "step_with_events_and_stats": t_step_prof * 1e3,
                       **{f"kernel_{k}": v / args.steps for k, v in agg_ms.items() if not k.startswith("unused")}},
-        "traversal": {k: stats[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
-                                            "base_leaf_pairs", "base_point_pairs", "levels", "max_order",
-                                            "segments", "max_segment", "local_nodes", "max_local_ops")},
+        "traversal": {**{k: stats[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
+                                               "base_leaf_pairs", "base_point_pairs", "levels", "max_order",
+                                               "segments", "max_segment", "local_nodes", "max_local_ops")},
+                      "node_pairs_per_s": stats["node_pairs"] / (agg_ms.get("traverse", 0.0) / args.steps * 1e-3)
+                      if agg_ms.get("traverse", 0.0) > 0 else None,
+                      "us_per_level": agg_ms.get("traverse", 0.0) / args.steps / max(stats["levels"], 1) * 1e3},
         "roofline": roofline,
         "base_case_tiles": {
             "what": "one call with every leaf pair exhaustive (forced), bandwidth h*: the exhaustive-tile kernel",
             "pairs": base_case["pairs"], "k_etile_ms": base_case["k_etile_ms"],
             "pairs_per_s": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3),
+            "tflops": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) * fpp / 1e12,
             "frac_of_alu_peak": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) / base_peak_pairs(d),
         },
         "grad_ms": None,

@@ -102,8 +102,10 @@ typedef struct dfgt_stats {
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,
      * local evaluation, combine),
      * [2] exhaustive leaf-leaf sums of DFGTBase (matrix cores for D >= 8 in
-     * mixed precision, vector ALUs otherwise; [1] adds their results),
-     * [3] local-moment accumulation (D and T ops), [4] unused. */
+     * mixed precision, else the mixed-precision pass on the vector ALUs;
+     * [1] adds their results), [3] local-moment accumulation (D and T ops),
+     * [4] the exhaustive pairs summed in FP64 on the vector ALUs (all of them
+     * at precision FP64, else those the underflow guard flags). */
     double kernel_ms[5];
     int64_t kernel_launches[5];
 } dfgt_stats;

@@ -89,6 +89,7 @@ enum {
     C_LGRP,
     C_LOP,
     C_LNODE,
+    C_EF64,     // E groups flagged by the underflow guard (FP64 sums)
     C_N
 };
 
@@ -412,7 +413,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
             const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
             const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
             o.egrp[gE] = Group{q, sg.job, ebase, tE, fp64, prevE};
-            if (fp64 && o.want_stats) atomicAdd(&o.stats[S_FP64 * SP], 1ull);
+            if (fp64) atomicAdd(&o.cnt[C_EF64 * CP], 1);
         }
         if (okF) o.fgrp[gF] = Group{q, sg.job, fbase, tF, 0, prevF};
         if (okL) {
@@ -1316,73 +1317,177 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     }
 }
 
-constexpr int kEChunk = 256;   // E ops flattened per round
+constexpr int kEChunk = 256;   // E ops flattened per chunk
 constexpr int kMaxEGrp = 256;  // E groups of one (job, node) chain (at most one per level)
 
 // ---------------------------------------------------------------- exhaustive tiles on the vector ALUs
 // DFGTBase for every dimension (the matrix-core kernel below takes D >= 8 in
-// mixed precision).  One block of 256 threads per (job, query leaf): the
-// leaf's E chain is flattened 256 ops at a time (reference range and point
-// count, block-wide scan), and the reference points stream through LDS 256
-// per round.  Threads form 256 / slots groups of `slots` lanes, one lane per
-// query; group g takes points [g slots, (g+1) slots) of each round.  Per pair:
-// the FP64 scaled difference, then (mixed) FP32 exp2 of the rounded square with
-// FP32 partial sums over <= 64 terms and FP64 beyond, or FP64 throughout
-// (precision FP64, or the op's group flagged by the underflow guard).  Group
-// partials are added in group order.  Writes G_E (and with GR X_E, Y_E) per
-// query in tree order, which k_leaf adds to the rest.
-constexpr int kEStage = 2048;  // doubles of staged reference coordinates per round
+// mixed precision), in two passes over the same E lists: F64 = false takes the
+// pairs summed in mixed precision and writes G_E; F64 = true takes the pairs
+// summed in FP64 (precision FP64, or groups flagged by the underflow guard)
+// and writes G_E (precision FP64) or adds to it (it runs after the mixed pass
+// on the same stream).  Splitting them keeps FP64 exponentials out of the
+// mixed kernel's registers.
+// One block of 4 waves per (job, query leaf): the leaf's E chain is flattened
+// 256 ops at a time (reference range and point count, block-wide scan) into
+// one list of reference points, which the waves take in rounds of RPW points,
+// wave w rounds w, w + 4, ...; each wave stages its own round in LDS (scaled
+// by sig), so rounds need no block barrier.  Lanes of a wave: NG groups of
+// `need` lanes; a lane holds QPT queries (ql + need a) and group g takes the
+// staged points g, g + NG, ... (groups read neighbouring points: no LDS bank
+// conflicts).  In the mixed pass for D <= 5 a round is padded with
+// zero-weight points to 4 NG ceil(points per group / 4) entries, so every lane
+// runs the same trip count, unrolled by 4.
+// Mixed pairs: the FP64 scaled difference, FP32 exp2 of the rounded square,
+// FP32 partial sums over <= 64 terms, FP64 beyond.  The partials of the waves
+// and groups are added in a fixed order.  G_E (and with GR X_E, Y_E) are per
+// query in tree order; k_leaf adds them to the rest.
+constexpr int kEWaveStage = 768;  // doubles of staged reference coordinates per wave
+constexpr int kEPpl = 4;          // points staged per lane and round (at most)
+constexpr int kEMaxGroups = 16;   // point groups per wave (the padding is < 4 of them per group)
+constexpr int kEPadPts = 4 * kEMaxGroups;
+constexpr int kEUnroll = 4;
 
-// Accumulates the pairs of one query with staged points [j0, j1) (scaled by
-// sig: e = 2^{-|qs - xs|^2}), FP32 partials over 64 points, FP64 beyond.
+template <int DT, bool F64>
+struct ETileShape {
+    static constexpr int DS = DT > 0 ? DT : kMaxD;        // register arrays (runtime d only in the DT = 0 form)
+    static constexpr int QPT = (DT > 0 && !F64) ? 2 : 1;  // queries per lane
+    static constexpr bool PAD = DT > 0 && !F64;           // padded, unrolled loop
+};
+
+template <int DT, bool F64>
+__host__ __device__ constexpr int etile_rpw(int d) {
+    const int n = ETileShape<DT, F64>::PAD ? kEWaveStage / d - kEPadPts : kEWaveStage / d;
+    return n < 256 ? n : 256;
+}
+
+// Mixed pairs, padded rounds of t4 points per group (t4 a multiple of 4,
+// weight 0 on the padding).
 template <int DT, bool GR>
-__device__ __forceinline__ void etile_mixed(const double *__restrict__ stage, int j0, int j1, int d,
-                                            const double *qs, double &acc, double &xacc, double *yacc) {
-    constexpr int DS = DT > 0 ? DT : kMaxD;
-    for (int jb = j0; jb < j1; jb += 64) {
-        const int je = min(j1, jb + 64);
-        float ps = 0.0f, pt = 0.0f, py[DS];
-        if (GR)
-            for (int c = 0; c < d; ++c) py[c] = 0.0f;
-        for (int j = jb; j < je; ++j) {
-            const double *xr = stage + j * d;
-            double t = 0.0, dd[DS];
-            for (int c = 0; c < d; ++c) {
-                dd[c] = qs[c] - xr[c];
-                t = fma(dd[c], dd[c], t);
+__device__ __forceinline__ void etile_fast(const double *__restrict__ st, const float *__restrict__ pw, int g,
+                                           int ng, int t4, const double (&qs)[2][DT], double (&acc)[2],
+                                           double (&xacc)[2], double (&yacc)[2][DT]) {
+    for (int t0 = 0; t0 < t4; t0 += 64) {
+        const int te = min(t4, t0 + 64);  // <= 64 points of this lane: one FP32 partial
+        float ps[2], pt[2], py[2][DT];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            ps[a] = 0.0f;
+            pt[a] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < DT; ++c) py[a][c] = 0.0f;
+        }
+        for (int t = t0; t < te; t += kEUnroll) {
+            double xv[kEUnroll][DT];
+            float w[kEUnroll];
+#pragma unroll
+            for (int u = 0; u < kEUnroll; ++u) {
+                const int j = g + ng * (t + u);
+#pragma unroll
+                for (int c = 0; c < DT; ++c) xv[u][c] = st[j * DT + c];
+                w[u] = pw[j];
             }
-            const float tf = (float)t;
-            const float e = __builtin_amdgcn_exp2f(-tf);
-            ps += e;
-            if (GR) {
-                pt = fmaf(tf, e, pt);
-                for (int c = 0; c < d; ++c) py[c] = fmaf(e, (float)dd[c], py[c]);
+#pragma unroll
+            for (int u = 0; u < kEUnroll; ++u) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    double tt = 0.0, dd[DT];
+#pragma unroll
+                    for (int c = 0; c < DT; ++c) {
+                        dd[c] = qs[a][c] - xv[u][c];
+                        tt = fma(dd[c], dd[c], tt);
+                    }
+                    const float tf = (float)tt;
+                    const float e = __builtin_amdgcn_exp2f(-tf);
+                    if (!GR) {
+                        ps[a] = fmaf(w[u], e, ps[a]);
+                    } else {
+                        const float ew = w[u] * e;
+                        ps[a] += ew;
+                        pt[a] = fmaf(tf, ew, pt[a]);
+#pragma unroll
+                        for (int c = 0; c < DT; ++c) py[a][c] = fmaf(ew, (float)dd[c], py[a][c]);
+                    }
+                }
             }
         }
-        acc += (double)ps;
-        if (GR) {
-            xacc = fma(-2.0 * kLn2, (double)pt, xacc);
-            for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2, (double)py[c], yacc[c]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            acc[a] += (double)ps[a];
+            if (GR) {
+                xacc[a] = fma(-2.0 * kLn2, (double)pt[a], xacc[a]);
+#pragma unroll
+                for (int c = 0; c < DT; ++c) yacc[a][c] = fma(-2.0 * kSqrtLn2, (double)py[a][c], yacc[a][c]);
+            }
         }
     }
 }
 
-template <int DT, bool GR>
+// One lane's query against the staged points g, g + ng, ... < cnt (runtime d):
+// mixed pairs (F64 = false) or FP64 pairs (t in sig units, e = 2^-t).
+template <bool GR, bool F64>
+__device__ __forceinline__ void etile_strided(const double *__restrict__ st, int g, int ng, int cnt, int d,
+                                              const double *qs, double &acc, double &xacc, double *yacc) {
+    for (int t0 = g; t0 < cnt; t0 += 64 * ng) {
+        const int te = min(cnt, t0 + 64 * ng);  // <= 64 points of this lane: one FP32 partial
+        float ps = 0.0f, pt = 0.0f, py[kMaxD];
+        if (GR && !F64)
+            for (int c = 0; c < d; ++c) py[c] = 0.0f;
+        for (int j = t0; j < te; j += ng) {
+            const double *xr = st + j * d;
+            double t = 0.0, dd[kMaxD];
+            for (int c = 0; c < d; ++c) {
+                dd[c] = qs[c] - xr[c];
+                t = fma(dd[c], dd[c], t);
+            }
+            if (F64) {
+                const double e = exp(-t * kLn2);
+                acc += e;
+                if (GR) {
+                    xacc = fma(-2.0 * kLn2 * t, e, xacc);
+                    for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2 * e, dd[c], yacc[c]);
+                }
+            } else {
+                const float tf = (float)t;
+                const float e = __builtin_amdgcn_exp2f(-tf);
+                ps += e;
+                if (GR) {
+                    pt = fmaf(tf, e, pt);
+                    for (int c = 0; c < d; ++c) py[c] = fmaf(e, (float)dd[c], py[c]);
+                }
+            }
+        }
+        if (!F64) {
+            acc += (double)ps;
+            if (GR) {
+                xacc = fma(-2.0 * kLn2, (double)pt, xacc);
+                for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2, (double)py[c], yacc[c]);
+            }
+        }
+    }
+}
+
+template <int DT, bool GR, bool F64>
 __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
-                                               const int *__restrict__ headE, const int *__restrict__ overflow,
-                                               const int *__restrict__ jlstart, int njobs, int unl, int precision,
-                                               double *__restrict__ GE, double *__restrict__ GX,
-                                               double *__restrict__ GY) {
-    constexpr int DS = DT > 0 ? DT : kMaxD;  // register arrays (runtime d only in the DT = 0 form)
-    constexpr int kStage = DT > 0 ? 256 * DT : kEStage;
-    __shared__ int gS[kMaxEGrp], gC[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
-    __shared__ int oB[kEChunk], oN[kEChunk], oF[kEChunk], oCum[kEChunk];
-    __shared__ int wsum[4], nops_s, f64_s;
-    __shared__ double stage[kStage];
-    __shared__ unsigned char pflag[256];
-    __shared__ double red[256];
+                                               const int *__restrict__ headE, const int *__restrict__ cnt_dev,
+                                               const int *__restrict__ overflow, const int *__restrict__ jlstart,
+                                               int njobs, int unl, int precision, double *__restrict__ GE,
+                                               double *__restrict__ GX, double *__restrict__ GY) {
+    using Sh = ETileShape<DT, F64>;
+    constexpr int DS = Sh::DS, QPT = Sh::QPT;
+    constexpr bool PAD = Sh::PAD;
+    constexpr int kSP = PAD ? etile_rpw<DT, F64>(DT > 0 ? DT : 1) + kEPadPts : 1;  // padded entries per wave
+    __shared__ int gS[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
+    __shared__ int oB[kEChunk], oCum[kEChunk];
+    __shared__ int wsum[4], nops_s, take_s;
+    __shared__ double stage[4][kEWaveStage];
+    __shared__ float pwt[4][kSP];
+    __shared__ double red[4][64 * QPT];
     if (*overflow) return;
+    const bool all64 = precision == DFGT_PREC_FP64;
+    // the FP64 pass of a mixed-precision call has work only if the guard flagged a group
+    if (F64 && !all64 && cnt_dev[C_EF64 * CP] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int job, li;
     job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
@@ -1391,61 +1496,73 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
     const DevTree &R = trees[jb.rt];
     const int leaf = Q.leaves[li];
     const int d = DT > 0 ? DT : Q.d;
-    const int RP = min(256, kStage / d);  // reference points per round
+    const int RPW = etile_rpw<DT, F64>(d);  // reference points per wave and round
+    const int PPL = (RPW + 63) / 64;        // of which each lane stages <= PPL
     const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
     const size_t hq = (size_t)jb.noff + leaf;
     const int head = headE[hq];
-    if (head < 0) {  // no exhaustive pairs for this leaf
-        for (int i = tid; i < nq; i += blockDim.x) {
-            const size_t ei = (size_t)jb.qoff + qb0 + i;
-            GE[ei] = 0.0;
-            if (GR) {
-                GX[ei] = 0.0;
-                for (int c = 0; c < d; ++c) GY[ei * d + c] = 0.0;
-            }
-        }
-        return;
-    }
+    // groups of this pass: mixed pass the unflagged ones, FP64 pass the flagged
+    // ones (all of them at precision FP64)
     if (tid == 0) {
-        int n = 0, tot = 0;
+        int n = 0, tot = 0, any = 0;
         for (int gi = head; gi >= 0 && n < kMaxEGrp; gi = egrp[gi].next) {
             const Group gg = egrp[gi];
+            const int tk = F64 ? (all64 || gg.flags != 0) : (gg.flags == 0);
             gS[n] = gg.start;
-            gC[n] = gg.count;
-            gF[n] = gg.flags;
+            gF[n] = tk;
+            any |= tk;
             tot += gg.count;
             gCum[n++] = tot;
         }
         nops_s = tot;
+        take_s = any;
     }
     __syncthreads();
     const int nops = nops_s;
-    const bool all64 = precision == DFGT_PREC_FP64;
-    for (int qg = 0; qg < nq; qg += 256) {
-        const int nqg = min(256, nq - qg);
-        int slots = 1;
-        while (slots < nqg) slots <<= 1;
-        const int ngr = 256 / slots;
-        const int qi = tid % slots, grp = tid / slots;
-        const bool act = qi < nqg;
-        const int qpos = qb0 + qg + (act ? qi : 0);
-        double qs[DS];
-        for (int c = 0; c < d; ++c) qs[c] = Q.x[(size_t)qpos * d + c] * jb.sig;
-        double acc = 0.0, xacc = 0.0, yacc[DS];
-        if (GR)
-            for (int c = 0; c < d; ++c) yacc[c] = 0.0;
+    const bool add = F64 && !all64;  // the FP64 pass of a mixed call adds to the mixed pass's G_E
+    if (!take_s) {  // no pairs of this pass for this leaf
+        if (!add)
+            for (int i = tid; i < nq; i += blockDim.x) {
+                const size_t ei = (size_t)jb.qoff + qb0 + i;
+                GE[ei] = 0.0;
+                if (GR) {
+                    GX[ei] = 0.0;
+                    for (int c = 0; c < d; ++c) GY[ei * d + c] = 0.0;
+                }
+            }
+        return;
+    }
+    double *st = stage[wv];
+    float *pw = pwt[wv];
+    for (int qg = 0; qg < nq; qg += 64 * QPT) {
+        const int nqg = min(64 * QPT, nq - qg);
+        const int need = (nqg + QPT - 1) / QPT;     // lanes per group
+        const int NG = min(kEMaxGroups, 64 / need);  // groups per wave
+        const bool lact = lane < NG * need;
+        const int ql = lact ? lane % need : 0, g = lact ? lane / need : 0;
+        double qs[QPT][DS], acc[QPT], xacc[QPT], yacc[QPT][DS];
+#pragma unroll
+        for (int a = 0; a < QPT; ++a) {
+            const int qi = ql + need * a;
+            const int qpos = qb0 + qg + (qi < nqg ? qi : 0);
+            for (int c = 0; c < d; ++c) qs[a][c] = Q.x[(size_t)qpos * d + c] * jb.sig;
+            acc[a] = 0.0;
+            xacc[a] = 0.0;
+            if (GR)
+                for (int c = 0; c < d; ++c) yacc[a][c] = 0.0;
+        }
         for (int o0 = 0; o0 < nops; o0 += kEChunk) {
-            __syncthreads();
+            __syncthreads();  // the previous chunk's tables are no longer read
             const int o = o0 + tid;
             int np = 0;
             if (o < nops) {
                 int gi = 0;
                 while (o >= gCum[gi]) ++gi;
-                const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
-                oB[tid] = R.begin[r];
-                np = R.end[r] - R.begin[r];
-                oN[tid] = np;
-                oF[tid] = gF[gi];
+                if (gF[gi]) {  // a group of this pass
+                    const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
+                    oB[tid] = R.begin[r];
+                    np = R.end[r] - R.begin[r];
+                }
             }
             const int inc = wave_incl_scan(np);
             if (lane == 63) wsum[wv] = inc;
@@ -1456,66 +1573,57 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
             __syncthreads();
             const int nopc = min(kEChunk, nops - o0);
             const int tot = oCum[nopc - 1];
-            for (int p0 = 0; p0 < tot; p0 += RP) {
-                // stage this round's points, scaled by sig, and their precision flags
-                const int p = p0 + tid;
-                int fl = 0;
-                if (tid < RP && p < tot) {
-                    int lo = 0, hi = nopc - 1;  // first op with oCum > p
+            for (int p0 = wv * RPW; p0 < tot; p0 += 4 * RPW) {
+                // stage the round: lane l takes points l PPL + k, k < PPL
+                const int cnt = min(RPW, tot - p0);
+                int i = lane * PPL;
+                if (i < cnt) {
+                    int lo = 0, hi = nopc - 1;  // first op with oCum > p0 + i
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
-                        if (oCum[mid] > p) hi = mid;
+                        if (oCum[mid] > p0 + i) hi = mid;
                         else lo = mid + 1;
                     }
-                    const int row = oB[lo] + p - (lo ? oCum[lo - 1] : 0);
-                    for (int c = 0; c < d; ++c) stage[tid * d + c] = R.x[(size_t)row * d + c] * jb.sig;
-                    fl = (all64 || oF[lo] != 0) ? 1 : 0;
-                    pflag[tid] = (unsigned char)fl;
-                }
-                const int any64 = __syncthreads_or(fl);
-                const int cnt = min(RP, tot - p0);
-                const int j0 = grp * slots, j1 = min(cnt, j0 + slots);
-                if (act && j0 < j1) {
-                    if (!any64) {
-                        etile_mixed<DT, GR>(stage, j0, j1, d, qs, acc, xacc, yacc);
-                    } else {
-                        // a round with FP64 points (precision FP64, or groups flagged by
-                        // the underflow guard): pair by pair; t is in sig units, e = 2^-t
-                        for (int j = j0; j < j1; ++j) {
-                            const double *xr = stage + j * d;
-                            double t = 0.0, dd[DS];
-                            for (int c = 0; c < d; ++c) {
-                                dd[c] = qs[c] - xr[c];
-                                t = fma(dd[c], dd[c], t);
-                            }
-                            if (pflag[j]) {
-                                const double e = exp(-t * kLn2);
-                                acc += e;
-                                if (GR) {
-                                    xacc = fma(-2.0 * kLn2 * t, e, xacc);
-                                    for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2 * e, dd[c], yacc[c]);
-                                }
-                            } else {
-                                etile_mixed<DT, GR>(stage, j, j + 1, d, qs, acc, xacc, yacc);
-                            }
-                        }
+                    int op = lo;
+                    for (int k = 0; k < PPL && i < cnt; ++k, ++i) {
+                        const int p = p0 + i;
+                        while (oCum[op] <= p) ++op;
+                        const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
+                        for (int c = 0; c < d; ++c) st[i * d + c] = R.x[(size_t)row * d + c] * jb.sig;
+                        if constexpr (PAD) pw[i] = 1.0f;
                     }
                 }
-                __syncthreads();
+                if constexpr (PAD) {
+                    const int t4 = ((cnt + NG - 1) / NG + kEUnroll - 1) / kEUnroll * kEUnroll;
+                    // zero-weight padding up to NG t4 entries (< cnt + 4 NG <= RPW + kEPadPts)
+                    for (int i2 = cnt + lane; i2 < NG * t4; i2 += 64) {
+                        for (int c = 0; c < d; ++c) st[i2 * d + c] = 0.0;
+                        pw[i2] = 0.0f;
+                    }
+                    wave_sync();  // a wave's LDS accesses complete in order
+                    etile_fast<DT, GR>(st, pw, g, NG, t4, qs, acc, xacc, yacc);
+                } else {
+                    wave_sync();
+                    etile_strided<GR, F64>(st, g, NG, cnt, d, qs[0], acc[0], xacc[0], yacc[0]);
+                }
+                wave_sync();
             }
         }
-        // groups in order, one quantity at a time through red[]
-        const size_t ei = (size_t)jb.qoff + qb0 + qg + qi;
+        // partials of the waves and groups, added in (wave, group) order, one quantity at a time
         const int nred = GR ? 2 + d : 1;
         for (int v = 0; v < nred; ++v) {
-            red[tid] = v == 0 ? acc : (v == 1 ? xacc : yacc[v - 2]);
+#pragma unroll
+            for (int a = 0; a < QPT; ++a)
+                red[wv][lane * QPT + a] = v == 0 ? acc[a] : (v == 1 ? xacc[a] : yacc[a][v - 2]);
             __syncthreads();
-            if (grp == 0 && act) {
+            if (tid < nqg) {
+                const int a = tid / need, qi = tid % need;
                 double sum = 0.0;
-                for (int k = 0; k < ngr; ++k) sum += red[k * slots + qi];
-                if (v == 0) GE[ei] = sum;
-                else if (v == 1) GX[ei] = sum;
-                else GY[ei * d + (v - 2)] = sum;
+                for (int w = 0; w < 4; ++w)
+                    for (int k = 0; k < NG; ++k) sum += red[w][(k * need + qi) * QPT + a];
+                const size_t ei = (size_t)jb.qoff + qb0 + qg + tid;
+                double *dst = v == 0 ? &GE[ei] : (v == 1 ? &GX[ei] : &GY[ei * d + (v - 2)]);
+                *dst = add ? *dst + sum : sum;
             }
             __syncthreads();
         }
@@ -1796,7 +1904,7 @@ struct Profiler {
 thread_local Profiler g_prof;
 
 // kernel_ms slots of dfgt_stats
-enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_POST = 4 };
+enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
@@ -1850,12 +1958,16 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
 }
 
 template <bool GR>
-void launch_etile(int d, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd, const Group *egrp,
-                  const int *eops, const int *headE, const int *flag, const int *jls, int njobs, int unl,
-                  int precision, double *GE, double *GX, double *GY) {
-#define DFGT_ETILE(DV)                                                                                              \
-    hipLaunchKernelGGL((k_etile<DV, GR>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, jls, njobs,      \
-                       unl, precision, GE, GX, GY);                                                                \
+void launch_etile(bool f64pass, int d, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd,
+                  const Group *egrp, const int *eops, const int *headE, const int *cnt, const int *flag,
+                  const int *jls, int njobs, int unl, int precision, double *GE, double *GX, double *GY) {
+#define DFGT_ETILE(DV)                                                                                            \
+    if (f64pass)                                                                                                  \
+        hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
+                           jls, njobs, unl, precision, GE, GX, GY);                                               \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, cnt,      \
+                           flag, jls, njobs, unl, precision, GE, GX, GY);                                         \
     break;
     switch (d) {
     case 1: DFGT_ETILE(1)
@@ -2176,12 +2288,21 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
             auto fn = pl.gr ? launch_emfma<true> : launch_emfma<false>;
             fn((d + 3) / 4, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
                w.flag.as<int>(), jls, njobs, pl.unl, w.extE.as<double>(), gx, gy);
-        } else {
+        } else if (pl.precision != DFGT_PREC_FP64) {
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
-            fn(d, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.flag.as<int>(), jls,
-               njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
+            fn(false, d, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
+               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
         }
         if (prof) prof->stop(K_EMFMA, ev, ss);
+        if (!pl.emfma) {
+            // the FP64 pairs (all of them at precision FP64, else the groups the
+            // underflow guard flagged), added after the mixed pass
+            ev = prof ? prof->start(ss) : nullptr;
+            auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
+            fn(true, d, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
+               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
+            if (prof) prof->stop(K_EF64, ev, ss);
+        }
     }
     (void)hipEventRecord(w.join, w.side);
     // local moments: every D / T op in parallel, then per internal node
@@ -2278,7 +2399,7 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
     out->base_point_pairs = (int64_t)sv[S_BPTS];
     out->levels = pl.nlev;
     out->max_order = (int64_t)sv[S_MAXORD];
-    out->fp64_groups = (int64_t)sv[S_FP64];
+    out->fp64_groups = (int64_t)c[C_EF64];
     out->segments = (int64_t)sv[S_SEGS];
     out->max_segment = (int64_t)sv[S_MAXSEG];
     out->local_nodes = c[C_LNODE];

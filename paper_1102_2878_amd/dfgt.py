@@ -37,7 +37,7 @@ class Stats(C.Structure):
         "max_local_ops", "mfma_tiles")] + [("reserved", C.c_int64 * 1),
                                                                        ("kernel_ms", C.c_double * 5),
                                                                        ("kernel_launches", C.c_int64 * 5)]
-    KERNELS = ("traverse", "leaf", "etile", "local", "unused4")
+    KERNELS = ("traverse", "leaf", "etile", "local", "etile_fp64")
 
     def as_dict(self):
         d = {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm not in ("reserved", "kernel_ms",

@@ -209,3 +209,28 @@ def test_five_dimensions_order_six(dfgt, eps):
         rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
         assert rel.max() <= eps, (h, rel.max())
     assert st["max_order"] >= 2
+
+
+def test_underflow_guard_fp64_groups(dfgt):
+    """Sums below the FP32 range: a tight reference cluster and queries on a
+    ring at 13.5-14 h (exponents 91-98, each term under 2^-126) plus queries
+    inside the cluster.  The traversal flags the exhaustive groups of the far
+    leaves (lower bound < |R| 2^-100), whose pairs then take FP64
+    exponentials; the near leaves stay in mixed precision in the same call."""
+    rng = np.random.default_rng(26)
+    h = 0.01
+    x = rng.normal(0.0, 0.01, size=(1200, 2))
+    ang = rng.uniform(0.0, 2.0 * np.pi, 600)
+    rad = h * rng.uniform(13.5, 14.0, 600) + 0.04
+    far = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+    q = np.concatenate([far, rng.normal(0.0, 0.01, size=(400, 2))])
+    ref = oracle.naive_kde(q, x, h)
+    assert ref[:600].max() < 2.0 ** -100 and ref[:600].min() > 0.0
+    for force, tol in ((dfgt.FORCE_EXACT, 1e-5), (0, 1e-2)):
+        note(f"dfgt underflow guard force={force}")
+        G, st = _run(dfgt, x, q, [h], 1e-2, force=force)
+        if force:
+            assert st["fp64_groups"] > 0
+        rel = _rel_err(G[0], ref)
+        assert rel[:600].max() <= tol, (force, rel[:600].max())
+        assert rel[600:].max() <= tol, (force, rel[600:].max())
