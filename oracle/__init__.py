@@ -69,6 +69,8 @@ def lib():
         L.oracle_dfgt.argtypes = [_DP, i64, _DP, i64, i32, dbl, dbl, i32, i32, i32, i32, C.c_void_p,
                                   _DP, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_lscv.argtypes = [_DP, i64, i32, _DP, i32, i32, _DP, C.c_void_p]
+        L.oracle_lcv.argtypes = [_DP, i64, i32, _DP, i32, _DP, C.c_void_p]
+        L.oracle_kde_density.argtypes = [_DP, i64, _DP, i64, i32, dbl, _DP]
         L.oracle_num_threads.restype = i32
         _lib = L
     return _lib
@@ -316,6 +318,24 @@ def dfgt(q, r, h, eps, leaf_size=32, pmax=None, force=0, literal_f2l=False, G_ex
 
 
 # ---- Section 1, eq. (4) -------------------------------------------------------------------------
+def kde_density(q, r, h):
+    """Section 1 density estimate p_h(q) = G(q, R) / (|R| (2 pi h^2)^{D/2})."""
+    q, r = _pts(q), _pts(r)
+    out = np.empty(q.shape[0])
+    _check(lib().oracle_kde_density(q, q.shape[0], r, r.shape[0], q.shape[1], float(h), out), "kde_density")
+    return out
+
+
+def lcv(x, hs):
+    """(CV_LK(h), dCV_LK/dh) for each h: Section 1 likelihood cross-validation."""
+    x = _pts(x)
+    hs = np.ascontiguousarray(np.atleast_1d(hs), np.float64)
+    cv = np.empty(hs.shape[0])
+    dcv = np.empty(hs.shape[0])
+    _check(lib().oracle_lcv(x, x.shape[0], x.shape[1], hs, hs.shape[0], cv, _ptr(dcv)), "lcv")
+    return cv, dcv
+
+
 def lscv(x, hs, variant=0):
     """(CV_LS(h), dCV/dh) for each h, from exact sums at h and sqrt(2) h."""
     x = _pts(x)

@@ -1229,6 +1229,72 @@ int oracle_lscv(const double *x, int64_t n, int d, const double *hs, int nh, int
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Section 1, the kernel density estimate: p_h(q) = G(q, R) / (|R| V_Dh), with */
+/* V_Dh the integral of the kernel, (2 pi h^2)^{D/2} for the Gaussian.        */
+/* ------------------------------------------------------------------------ */
+int oracle_kde_density(const double *q, int64_t nq, const double *r, int64_t nr, int d, double h, double *out)
+{
+    if (nr < 1) return 1;
+    int rc = oracle_naive_kde(q, nq, r, nr, d, h, out);
+    if (rc) return rc;
+    const double PI = 3.14159265358979323846;
+    const double V = pow(2.0 * PI * h * h, d / 2.0);
+    for (int64_t i = 0; i < nq; ++i) out[i] /= (double)nr * V;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Section 1, likelihood cross-validation score:                              */
+/*   CV_LK(h) = (1/N) sum_j log p_{h,-j}(r_j),                                 */
+/*   p_{h,-j}(r_j) = S_j / ((N-1) V_Dh),  S_j = sum_{i != j} K_h(|r_j - r_i|)  */
+/* (the estimate from all points but r_j).  S_j is summed directly over        */
+/* i != j (Neumaier), not as G - 1.  dcv (may be NULL) receives dCV_LK/dh =    */
+/* (1/N) sum_j S_j'/S_j - D/h with S_j' = sum_{i != j} K |r_j - r_i|^2 / h^3.  */
+/* A point with S_j = 0 (underflow at tiny h) gives -inf.                      */
+/* ------------------------------------------------------------------------ */
+int oracle_lcv(const double *x, int64_t n, int d, const double *hs, int nh, double *cv, double *dcv)
+{
+    if (n < 2 || d < 1 || d > OR_MAXD || nh < 1) return 1;
+    const double PI = 3.14159265358979323846;
+    for (int k = 0; k < nh; ++k) {
+        const double h = hs[k];
+        if (!(h > 0.0)) return 1;
+        const double inv2h2 = 1.0 / (2.0 * h * h);
+        double acc = 0.0, dacc = 0.0;
+        int neg_inf = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : acc, dacc) reduction(| : neg_inf)
+        for (int64_t j = 0; j < n; ++j) {
+            double s = 0.0, c = 0.0, ds = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (i == j) continue;
+                double t = 0.0;
+                for (int m = 0; m < d; ++m) {
+                    double v = x[j * d + m] - x[i * d + m];
+                    t += v * v;
+                }
+                double kv = exp(-t * inv2h2);
+                double y = kv, u = s + y; /* Neumaier */
+                c += fabs(s) >= fabs(y) ? (s - u) + y : (y - u) + s;
+                s = u;
+                ds += kv * t / (h * h * h);
+            }
+            s += c;
+            if (s > 0.0) {
+                acc += log(s);
+                dacc += ds / s;
+            } else {
+                neg_inf = 1;
+            }
+        }
+        const double N = (double)n;
+        const double logV = 0.5 * d * log(2.0 * PI * h * h);
+        cv[k] = neg_inf ? -INFINITY : acc / N - log(N - 1.0) - logV;
+        if (dcv) dcv[k] = neg_inf ? NAN : dacc / N - d / h;
+    }
+    return 0;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

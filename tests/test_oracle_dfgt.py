@@ -134,6 +134,56 @@ def test_lscv_variants_differ_by_the_diagonal():
     assert cv1[0] - cv0[0] == pytest.approx(a * (n + S2) / n ** 2 - a * S2 / (n * (n - 1)), rel=1e-10)
 
 
+# ---- LCV and the density estimate (Section 1) ---------------------------------------------------
+def test_lcv_two_points_closed_form():
+    # each point's leave-one-out estimate is the other point's kernel:
+    # CV_LK = -d^2/(2h^2) - (D/2) log(2 pi h^2), dCV/dh = d^2/h^3 - D/h
+    for d in (1, 2, 5):
+        x = np.zeros((2, d))
+        x[1, -1] = 0.45
+        for h in (0.1, 0.8):
+            cv, dcv = oracle.lcv(x, h)
+            assert cv[0] == pytest.approx(-0.45 ** 2 / (2 * h * h) - 0.5 * d * np.log(2 * np.pi * h * h), rel=1e-13)
+            assert dcv[0] == pytest.approx(0.45 ** 2 / h ** 3 - d / h, rel=1e-12)
+
+
+def test_lcv_leave_one_out_and_duplicates():
+    # three points, two of them coincident: the duplicate pair contributes
+    # K = 1 to each other's estimate, the third point sees both at distance 1
+    x = np.array([[0.0, 0.0], [0.0, 0.0], [0.6, 0.8]])
+    h = 0.5
+    k = np.exp(-1.0 / (2 * h * h))
+    V = 2 * np.pi * h * h
+    ref = np.mean(np.log(np.array([1 + k, 1 + k, 2 * k]) / (2 * V)))
+    assert oracle.lcv(x, h)[0][0] == pytest.approx(ref, rel=1e-13)
+
+
+def test_lcv_gradient_vs_central_differences_and_underflow():
+    x = synth.c1(n=300, seed=21)
+    for h in (0.01, 0.05, 0.3):
+        cv, dcv = oracle.lcv(x, h)
+        dh = 1e-6 * h
+        fd = (oracle.lcv(x, h + dh)[0] - oracle.lcv(x, h - dh)[0]) / (2 * dh)
+        assert dcv[0] == pytest.approx(fd[0], rel=1e-6)
+    # an isolated point whose leave-one-out sum underflows: the score is -inf
+    y = np.array([[0.0], [0.001], [50.0]])
+    assert oracle.lcv(y, 0.01)[0][0] == -np.inf
+
+
+def test_density_integrates_to_one():
+    # the normalising constant V_Dh = (2 pi h^2)^{D/2}: trapezoid quadrature of
+    # the estimate over a box holding all the mass
+    r1 = np.array([[0.1], [0.35], [-0.4], [0.2]])
+    g = np.linspace(-4.0, 4.0, 8001)
+    p = oracle.kde_density(g[:, None], r1, 0.3)
+    assert np.trapezoid(p, g) == pytest.approx(1.0, rel=1e-10)
+    r2 = np.array([[0.1, -0.2], [0.4, 0.3], [-0.3, 0.0]])
+    g2 = np.linspace(-3.0, 3.0, 601)
+    X, Y = np.meshgrid(g2, g2, indexing="ij")
+    p2 = oracle.kde_density(np.stack([X.ravel(), Y.ravel()], 1), r2, 0.25).reshape(X.shape)
+    assert np.trapezoid(np.trapezoid(p2, g2, axis=1), g2) == pytest.approx(1.0, rel=1e-8)
+
+
 def test_final_point_bounds_are_tight_when_everything_is_pruned():
     # At a huge bandwidth every pair prunes with K(d^l) ~ K(d^u) ~ 1, so the
     # postponed bound changes pushed to the points pin G^l and G^u close to G.
