@@ -70,6 +70,33 @@ def base_peak_pairs(d):
     return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
 
 
+def per_bandwidth(torch, dfgt, x, hs, reps=3):
+    """Median ms per single-bandwidth call: DFGT, DFD ablation, brute force."""
+    R = dfgt.build_tree(x, leaf_size=LEAF)
+
+    def med(f):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[reps // 2] * 1e3
+
+    rows = []
+    for s, h in zip(SCALES, hs):
+        rows.append({
+            "h_over_hstar": s,
+            "dfgt_ms": med(lambda: dfgt.gauss_sum(R, R, [h], EPS)),
+            "dfd_ms": med(lambda: dfgt.gauss_sum(R, R, [h], EPS, force_method=dfgt.FORCE_CENTROID)),
+            "bruteforce_ms": med(lambda: dfgt.naive_sum(x, x, [h])),
+        })
+    return {"what": "single-bandwidth calls, tree built once, eps 1e-2: DFGT, the DFD ablation (only the "
+                    "centroid finite-difference prune), brute force", "rows": rows}
+
+
 def batched_bench(torch, dfgt, synth):
     """The 3-D batch: eager call, graph replays, brute force; returns details."""
     xs = [synth.c4_problem(k) for k in range(8)]
@@ -236,6 +263,12 @@ def main():
     base_case = {"pairs": st_x["base_point_pairs"], "k_etile_ms": st_x["kernel_ms"]["etile"]}
     del tree_x
 
+    # per-bandwidth comparison (the layout of the paper's Table 1 on the
+    # synthetic stand-in): DFGT, the DFD ablation (centroid finite-difference
+    # prune only, p_max = 1 rule of the same code) and the brute force, one
+    # bandwidth per call, tree built once
+    per_h = per_bandwidth(torch, dfgt, x, hs)
+
     # build alone
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -319,6 +352,7 @@ def main():
             "tflops": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) * fpp / 1e12,
             "frac_of_alu_peak": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) / base_peak_pairs(d),
         },
+        "per_bandwidth": per_h,
         "grad_ms": None,
     }
 

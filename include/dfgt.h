@@ -258,6 +258,51 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
 
 /* One problem of a batch: the sums over R for the queries of Q at n_h
  * bandwidths, into G_dev (n_h x NQ float64, caller-allocated, caller order). */
+/*
+ * Kernel density estimate of Section 1: p[k][i] = G~(q_i, R; h_k) / (N_R V_k),
+ * V_k = (2 pi h_k^2)^(D/2) the integral of the Gaussian kernel.  Same
+ * arguments, layout ([n_h][N_Q], user query order, FP64, caller-owned device
+ * memory) and per-query relative error bound eps as dfgt_gauss_sum.
+ */
+dfgt_status dfgt_kde_density(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                             const dfgt_options *opt, double *p_dev, dfgt_stats *stats, void *stream);
+
+/*
+ * Likelihood cross-validation score of Section 1 for every bandwidth h_k:
+ *     CV_LK(h) = (1/N) sum_j log p_{h,-j}(r_j),
+ *     p_{h,-j}(r_j) = (G~(r_j, R; h) - 1) / ((N - 1) (2 pi h^2)^(D/2)),
+ * the estimate at r_j from all points but r_j (G includes the self term 1).
+ * dcv_host (may be NULL) receives dCV_LK/dh from the gradient mode:
+ * (1/N) sum_j G'(r_j) / (G(r_j) - 1) - D/h.  The sums carry the relative
+ * error eps of G, so each leave-one-out sum is within eps G / (G - 1) of its
+ * value: the score is accurate where the points are not isolated at this
+ * bandwidth; a leave-one-out sum <= 0 (an isolated point, its sum underflowed
+ * or swamped by the error) makes the score -inf.  N >= 2, n_h <= 32767.
+ * Synchronises the stream.  The bandwidth maximising CV_LK is the
+ * likelihood-optimal one.
+ */
+dfgt_status dfgt_lcv_score(dfgt_tree R, const double *h_host, int32_t n_h, double eps, const dfgt_options *opt,
+                           double *cv_host, double *dcv_host, dfgt_stats *stats, void *stream);
+
+/*
+ * The bandwidth that minimises the LSCV score above over [h_lo, h_hi]
+ * (Section 4 sweeps its bandwidths around this minimiser h*, taking it from
+ * the least-squares cross-validation score).  Search: n_grid log-spaced
+ * bandwidths over the bracket, scored in one dfgt_lscv_score call (all 2 n_grid
+ * sums in one traversal); the bracket becomes the two grid cells around the
+ * smallest score (the first one on ties) and the search repeats until the
+ * bracket spans at most a factor (1 + rel_tol)^2.  The score is not convex in
+ * general: the grid finds the smallest score on the grid, and a minimiser at an
+ * end of [h_lo, h_hi] means the bracket should be widened.
+ *   h_star  receives the best bandwidth evaluated, cv_star (may be NULL) its
+ *           score, n_evals (may be NULL) the number of bandwidths scored.
+ * 0 < h_lo < h_hi, 4 <= n_grid <= 1024, 0 < rel_tol < 1, variant 0 or 1 (as in
+ * dfgt_lscv_score).  Synchronises the stream after every grid.
+ */
+dfgt_status dfgt_lscv_optimize(dfgt_tree R, double h_lo, double h_hi, double eps, int32_t variant, int32_t n_grid,
+                               double rel_tol, const dfgt_options *opt, double *h_star, double *cv_star,
+                               int32_t *n_evals, void *stream);
+
 typedef struct dfgt_problem {
     dfgt_tree Q;
     dfgt_tree R;          /* Q == R: the monochromatic case, self terms included */

@@ -291,6 +291,61 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
     DFGT_GUARD_END
 }
 
+dfgt_status dfgt_kde_density(dfgt_tree Q, dfgt_tree R, const double *h_host, int32_t n_h, double eps,
+                             const dfgt_options *opt, double *p_dev, dfgt_stats *stats, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(Q && R && p_dev, "dfgt_kde_density: NULL argument");
+    DFGT_TRY(check_pair(Q, R, eps, "dfgt_kde_density"));
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_kde_density"));
+    int precision, force, profile;
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_kde_density", &precision, &force, &profile, &cost_e));
+    DFGT_REQUIRE(profile == 0, "dfgt_kde_density: profiling is not supported here");
+    return run_density(Q, R, h_host, n_h, eps, precision, force, cost_e, p_dev, stats, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_lcv_score(dfgt_tree R, const double *h_host, int32_t n_h, double eps, const dfgt_options *opt,
+                           double *cv_host, double *dcv_host, dfgt_stats *stats, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(R && cv_host, "dfgt_lcv_score: NULL argument");
+    DFGT_REQUIRE(R->n >= 2, "dfgt_lcv_score: needs at least two points");
+    DFGT_TRY(check_pair(R, R, eps, "dfgt_lcv_score"));
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_lcv_score"));
+    DFGT_REQUIRE(n_h <= 32767, "dfgt_lcv_score: n_h must be <= 32767");
+    int precision, force, profile;
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_lcv_score", &precision, &force, &profile, &cost_e));
+    DFGT_REQUIRE(profile == 0, "dfgt_lcv_score: profiling is not supported here");
+    return run_lcv(R, h_host, n_h, eps, precision, force, cost_e, cv_host, dcv_host, stats, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_lscv_optimize(dfgt_tree R, double h_lo, double h_hi, double eps, int32_t variant, int32_t n_grid,
+                               double rel_tol, const dfgt_options *opt, double *h_star, double *cv_star,
+                               int32_t *n_evals, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(R && h_star, "dfgt_lscv_optimize: NULL argument");
+    DFGT_REQUIRE(R->n >= 2, "dfgt_lscv_optimize: needs at least two points");
+    DFGT_REQUIRE(variant == 0 || variant == 1, "dfgt_lscv_optimize: variant must be 0 or 1");
+    DFGT_REQUIRE(std::isfinite(h_lo) && std::isfinite(h_hi) && h_lo > 0.0 && h_hi > h_lo,
+                 "dfgt_lscv_optimize: need 0 < h_lo < h_hi (finite)");
+    DFGT_REQUIRE(n_grid >= 4 && n_grid <= 1024, "dfgt_lscv_optimize: n_grid must be in [4, 1024]");
+    DFGT_REQUIRE(std::isfinite(rel_tol) && rel_tol > 0.0 && rel_tol < 1.0,
+                 "dfgt_lscv_optimize: rel_tol must be in (0, 1)");
+    DFGT_TRY(check_pair(R, R, eps, "dfgt_lscv_optimize"));
+    int precision, force, profile;
+    double cost_e;
+    DFGT_TRY(call_options(R, opt, "dfgt_lscv_optimize", &precision, &force, &profile, &cost_e));
+    DFGT_REQUIRE(profile == 0, "dfgt_lscv_optimize: profiling is not supported here");
+    int ev = 0;
+    DFGT_TRY(run_lscv_optimize(R, h_lo, h_hi, eps, precision, force, cost_e, variant, n_grid, rel_tol, h_star,
+                               cv_star, &ev, (hipStream_t)stream));
+    if (n_evals) *n_evals = ev;
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
 static dfgt_status collect_problems(const dfgt_problem *probs, int32_t n, double eps, const char *who,
                                     std::vector<Problem> &out) {
     DFGT_REQUIRE(probs != nullptr && n >= 1, std::string(who) + ": need at least one problem");

@@ -216,6 +216,13 @@ dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh
                          int force, double cost_e, const double *dG, double *dh_host, double *dq, hipStream_t st);
 dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,
                      int variant, double *cv, double *dcv, dfgt_stats *stats, hipStream_t st);
+dfgt_status run_lcv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,
+                    double *cv, double *dcv, dfgt_stats *stats, hipStream_t st);
+dfgt_status run_density(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps, int precision,
+                        int force, double cost_e, double *p, dfgt_stats *stats, hipStream_t st);
+dfgt_status run_lscv_optimize(dfgt_tree_s *R, double h_lo, double h_hi, double eps, int precision, int force,
+                              double cost_e, int variant, int n_grid, double rel_tol, double *h_star,
+                              double *cv_star, int *n_evals, hipStream_t st);
 
 int default_pmax(int d);
 

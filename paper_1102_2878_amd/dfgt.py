@@ -80,6 +80,12 @@ def lib():
                                               C.POINTER(dbl), vp, vp]
         L.dfgt_lscv_score.argtypes = [vp, C.POINTER(dbl), i32, dbl, i32, C.POINTER(Options), C.POINTER(dbl),
                                       C.POINTER(dbl), C.POINTER(Stats), vp]
+        L.dfgt_kde_density.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp, C.POINTER(Stats),
+                                       vp]
+        L.dfgt_lcv_score.argtypes = [vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), C.POINTER(dbl),
+                                     C.POINTER(dbl), C.POINTER(Stats), vp]
+        L.dfgt_lscv_optimize.argtypes = [vp, dbl, dbl, dbl, i32, i32, dbl, C.POINTER(Options), C.POINTER(dbl),
+                                         C.POINTER(dbl), C.POINTER(i32), vp]
         L.dfgt_gauss_sum_batched.argtypes = [C.POINTER(Problem), i32, dbl, C.POINTER(Options), C.POINTER(Stats), vp]
         L.dfgt_batch_create.argtypes = [C.POINTER(Problem), i32, dbl, C.POINTER(Options), C.POINTER(Stats), vp,
                                         C.POINTER(vp)]
@@ -88,7 +94,9 @@ def lib():
         L.dfgt_batch_free.argtypes = [vp]
         for nm in ("dfgt_build_tree", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
                    "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
-                   "dfgt_gauss_sum_backward", "dfgt_lscv_score", "dfgt_gauss_sum_batched", "dfgt_batch_create",
+                   "dfgt_gauss_sum_backward", "dfgt_lscv_score", "dfgt_lscv_optimize", "dfgt_gauss_sum_batched",
+                   "dfgt_kde_density", "dfgt_lcv_score",
+                   "dfgt_batch_create",
                    "dfgt_batch_run", "dfgt_batch_check", "dfgt_batch_free"):
             getattr(L, nm).restype = C.c_int
         _lib = L
@@ -270,6 +278,41 @@ def lscv_score(R: Tree, h, eps, variant=1, grad=False, precision=PREC_MIXED, for
     return out[0] if len(out) == 1 else out
 
 
+def kde_density(Q: Tree, R: Tree, h, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False):
+    """dfgt_kde_density: (n_h, NQ) float64 tensor of density estimates [, stats]."""
+    torch = _torch()
+    hv, hp = _hvec(h)
+    p = torch.empty((hv.shape[0], Q.n), dtype=torch.float64, device="cuda")
+    o = _opts(precision=precision, force_method=force_method)
+    st = Stats() if stats else None
+    _check(lib().dfgt_kde_density(Q.handle, R.handle, hp, hv.shape[0], float(eps), C.byref(o), p.data_ptr(),
+                                  C.byref(st) if st is not None else None, _stream()))
+    return (p, st.as_dict()) if stats else p
+
+
+def lcv_score(R: Tree, h, eps, grad=False, precision=PREC_MIXED, force_method=FORCE_NONE):
+    """dfgt_lcv_score: cv (n_h,) numpy [, dcv/dh (n_h,)]."""
+    hv, hp = _hvec(h)
+    nh = hv.shape[0]
+    cv = np.empty(nh)
+    dcv = np.empty(nh) if grad else None
+    o = _opts(precision=precision, force_method=force_method)
+    _check(lib().dfgt_lcv_score(R.handle, hp, nh, float(eps), C.byref(o), cv.ctypes.data_as(C.POINTER(C.c_double)),
+                                dcv.ctypes.data_as(C.POINTER(C.c_double)) if dcv is not None else None, None,
+                                _stream()))
+    return (cv, dcv) if grad else cv
+
+
+def lscv_optimize(R: Tree, h_lo, h_hi, eps, variant=1, n_grid=16, rel_tol=1e-3, precision=PREC_MIXED,
+                  force_method=FORCE_NONE):
+    """dfgt_lscv_optimize: (h_star, cv_star, n_evals)."""
+    o = _opts(precision=precision, force_method=force_method)
+    hs, cv, ne = C.c_double(), C.c_double(), C.c_int32()
+    _check(lib().dfgt_lscv_optimize(R.handle, float(h_lo), float(h_hi), float(eps), int(variant), int(n_grid),
+                                    float(rel_tol), C.byref(o), C.byref(hs), C.byref(cv), C.byref(ne), _stream()))
+    return hs.value, cv.value, ne.value
+
+
 def _problem_array(problems):
     """[(Q, R, h)] -> (ctypes array, outputs, kept-alive host arrays)."""
     torch = _torch()
@@ -284,10 +327,11 @@ def _problem_array(problems):
     return arr, outs, keep
 
 
-def gauss_sum_batched(problems, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, profile=False):
+def gauss_sum_batched(problems, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False, profile=False,
+                      cost_exhaustive=0.0):
     """dfgt_gauss_sum_batched over [(Q, R, h)]: list of (n_h, NQ) tensors [, stats]."""
     arr, outs, keep = _problem_array(problems)
-    o = _opts(precision=precision, force_method=force_method, profile=profile)
+    o = _opts(precision=precision, force_method=force_method, profile=profile, cost_exhaustive=cost_exhaustive)
     stats = stats or profile
     st = Stats() if stats else None
     _check(lib().dfgt_gauss_sum_batched(arr, len(problems), float(eps), C.byref(o),
@@ -299,12 +343,13 @@ class Batch:
     """dfgt_batch_create / run / check / free: a captured sweep over [(Q, R, h)].
     ``G`` holds the output tensors, rewritten by every ``run()``."""
 
-    def __init__(self, problems, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False):
+    def __init__(self, problems, eps, precision=PREC_MIXED, force_method=FORCE_NONE, stats=False,
+                 cost_exhaustive=0.0):
         self.handle = None
         self._trees = [t for p in problems for t in p[:2]]
         arr, self.G, self._keep = _problem_array(problems)
         self._arr = arr
-        o = _opts(precision=precision, force_method=force_method)
+        o = _opts(precision=precision, force_method=force_method, cost_exhaustive=cost_exhaustive)
         st = Stats() if stats else None
         h = C.c_void_p()
         _check(lib().dfgt_batch_create(arr, len(problems), float(eps), C.byref(o),

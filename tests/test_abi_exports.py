@@ -64,3 +64,10 @@ def test_new_entry_points_reject_null_handles():
     assert rc == 1 and b"NULL" in L.dfgt_last_error()
     rc = L.dfgt_gauss_sum_backward(None, None, hv, 1, 1e-2, None, None, None, None, None)
     assert rc == 1 and b"NULL" in L.dfgt_last_error()
+    rc = L.dfgt_lcv_score(None, hv, 1, 1e-2, None, cv, None, None, None)
+    assert rc == 1 and b"NULL" in L.dfgt_last_error()
+    rc = L.dfgt_kde_density(None, None, hv, 1, 1e-2, None, None, None, None)
+    assert rc == 1 and b"NULL" in L.dfgt_last_error()
+    hs = ctypes.c_double()
+    rc = L.dfgt_lscv_optimize(None, 0.1, 1.0, 1e-2, 1, 16, 1e-3, None, ctypes.byref(hs), None, None, None)
+    assert rc == 1 and b"NULL" in L.dfgt_last_error()
