@@ -302,27 +302,61 @@ __device__ __forceinline__ int wave_excl(int v, int *total) {
 
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
-// One wave per segment.
-__device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Seg sg,
-                                 const int *__restrict__ pairs, int force, int gr, int leaf_local, int *dec,
-                                 double *kus, const TravOut &o) {
-    const int lane = threadIdx.x;
+// One wave per segment, kTravWaves segments per block.  Every segment appends
+// to shared lists (E, F, local ops, their groups, next-level pairs and
+// segments); the reservations of a block's segments are made together, one
+// atomic per list per block, because same-address device atomics serialise
+// (one per segment would cost ~20 ns each at thousands of segments a level).
+constexpr int kTravWaves = 4;
+enum { R_EOP = 0, R_EGRP, R_FOP, R_FGRP, R_LOP, R_LGRP, R_PAIR, R_SEG, R_N };
+enum { T_PAIRS = 0, T_SEGS, T_F, T_D, T_T, T_C, T_BLEAF, T_BPTS, T_N };  // block-summed statistics
+
+struct TravShared {
+    int req[kTravWaves][R_N];  // per-wave requests, then per-wave bases
+    unsigned long long st[kTravWaves][T_N];
+    unsigned long long maxseg[kTravWaves], maxord[kTravWaves];
+};
+
+// One block iteration: wave w of the block handles segment si (valid when
+// si < nseg; invalid waves take part in the block's reservation with nothing).
+__device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                 const Seg *__restrict__ segs, int si, bool valid, const int *__restrict__ pairs,
+                                 int force, int gr, int leaf_local, int *dec, double *kus, const TravOut &o,
+                                 TravShared &sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    Seg sg{0, 0, 0, 0, 0.0};
+    if (valid) sg = segs[si];
     const Job jb = jobs[sg.job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
     const int D = Q.d, pmax = Q.pmax;
     const int q = sg.q;
-    const bool qleaf = Q.left[q] < 0;
-    const double nQ = (double)(Q.end[q] - Q.begin[q]);
+    const bool qleaf = valid && Q.left[q] < 0;
+    const double nQ = valid ? (double)(Q.end[q] - Q.begin[q]) : 0.0;
 
-    // 1. lower bound over the whole list
+    // 1. lower bound over the whole list.  The first 64 pairs (all of them
+    // for most segments) keep their node data in registers for the passes
+    // below; pairs beyond reload it.
     double sl = 0.0;
+    int r0 = -1, m0 = METH_E, ord0 = 0, left0 = -1, right0 = -1;
+    double nR0 = 0.0, ku0 = 0.0;
+    PairGeom g0{0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = lane; i < sg.count; i += 64) {
         const int r = pairs[sg.start + i];
         const PairGeom g = pair_geom(Q, q, R, r);
         const double ku = exp(-g.su * jb.inv2h2);
-        kus[sg.start + i] = ku;  // reused by the decisions below
-        sl += (double)(R.end[r] - R.begin[r]) * ku;
+        const double nR = (double)(R.end[r] - R.begin[r]);
+        if (i < 64) {
+            r0 = r;
+            g0 = g;
+            ku0 = ku;
+            nR0 = nR;
+            left0 = R.left[r];
+            right0 = R.right[r];
+        } else {
+            kus[sg.start + i] = ku;  // reused by the decisions below
+        }
+        sl += nR * ku;
     }
     sl = wave_sum(sl);
     const double gl = fmax((sg.gl + sl) * (1.0 - 1e-12), jb.prior);
@@ -331,15 +365,16 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     int cE = 0, cF = 0, cL = 0, cN = 0, nT = 0, nC = 0, nD = 0, maxord = 0;
     double plo = 0.0, ept = 0.0, ccon = 0.0;
     for (int i = lane; i < sg.count; i += 64) {
-        const int r = pairs[sg.start + i];
-        const PairGeom g = pair_geom(Q, q, R, r);
-        const double nR = (double)(R.end[r] - R.begin[r]);
+        const bool first = i < 64;
+        const int r = first ? r0 : pairs[sg.start + i];
+        const PairGeom g = first ? g0 : pair_geom(Q, q, R, r);
+        const double nR = first ? nR0 : (double)(R.end[r] - R.begin[r]);
         const double tau = jb.eps_eff * nR * gl / jb.nR;
-        const double ku = kus[sg.start + i];
+        const double ku = first ? ku0 : kus[sg.start + i];
         int ord = 0;
         double kc = 0.0;
         const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, jb.cost_e, &ord, &kc);
-        const bool rleaf = R.left[r] < 0;
+        const bool rleaf = (first ? left0 : R.left[r]) < 0;
         if (m != METH_E) {
             plo += nR * ku;
             if (m == METH_F) ++cF;
@@ -362,7 +397,12 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         } else {
             cN += (qleaf || !rleaf) ? 2 : 1;
         }
-        dec[sg.start + i] = m | (ord << 4);
+        if (first) {
+            m0 = m;
+            ord0 = ord;
+        } else {
+            dec[sg.start + i] = m | (ord << 4);
+        }
     }
     int tE, tF, tL, tN;
     wave_excl(cE, &tE);
@@ -377,29 +417,84 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     int mo = maxord;
     for (int off = 32; off >= 1; off >>= 1) mo = max(mo, __shfl_xor(mo, off, 64));
 
-    // reserve contiguous output ranges and link the new groups into their
-    // chains.  The independent reservations go out from different lanes at
-    // once, then the chain links, then the group records: three round trips.
+    // 3. the block's reservations: per-wave requests, one atomic per list
     const int npair_out = qleaf ? tN : 2 * tN;
     const int nseg_out = tN > 0 ? (qleaf ? 1 : 2) : 0;
-    const size_t hq = (size_t)jb.noff + q;
-    int r1 = 0;
-    if (lane == 0 && tE) r1 = atomicAdd(&o.cnt[C_EOP * CP], tE);
-    if (lane == 1 && tE) r1 = atomicAdd(&o.cnt[C_EGRP * CP], 1);
-    if (lane == 2 && tF) r1 = atomicAdd(&o.cnt[C_FOP * CP], tF);
-    if (lane == 3 && tF) r1 = atomicAdd(&o.cnt[C_FGRP * CP], 1);
-    if (lane == 4 && tL) r1 = atomicAdd(&o.cnt[C_LOP * CP], tL);
-    if (lane == 5 && tL) r1 = atomicAdd(&o.cnt[C_LGRP * CP], 1);
-    if (lane == 6 && npair_out) r1 = atomicAdd(&o.lvl_next[C_PAIR * CP], npair_out);
-    if (lane == 7 && npair_out) r1 = atomicAdd(&o.lvl_next[C_SEG * CP], nseg_out);
-    const int ebase = __shfl(r1, 0, 64), gE = __shfl(r1, 1, 64);
-    const int fbase = __shfl(r1, 2, 64), gF = __shfl(r1, 3, 64);
-    const int lbase = __shfl(r1, 4, 64), gL = __shfl(r1, 5, 64);
-    const int cbase = __shfl(r1, 6, 64), sgi = __shfl(r1, 7, 64);
+    if (lane == 0) {
+        int *rq = sh.req[wv];
+        rq[R_EOP] = tE;
+        rq[R_EGRP] = tE ? 1 : 0;
+        rq[R_FOP] = tF;
+        rq[R_FGRP] = tF ? 1 : 0;
+        rq[R_LOP] = tL;
+        rq[R_LGRP] = tL ? 1 : 0;
+        rq[R_PAIR] = npair_out;
+        rq[R_SEG] = nseg_out;
+        if (o.want_stats) {
+            unsigned long long *t = sh.st[wv];
+            t[T_PAIRS] = valid ? (unsigned long long)sg.count : 0ull;
+            t[T_SEGS] = valid ? 1ull : 0ull;
+            t[T_F] = (unsigned long long)nFp;
+            t[T_D] = (unsigned long long)nDp;
+            t[T_T] = (unsigned long long)nTp;
+            t[T_C] = (unsigned long long)nCp;
+            t[T_BLEAF] = (unsigned long long)tE;
+            t[T_BPTS] = (unsigned long long)(nQ * ept);
+            sh.maxseg[wv] = valid ? (unsigned long long)sg.count : 0ull;
+            sh.maxord[wv] = (unsigned long long)mo;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < R_N) {
+        const int c = threadIdx.x;
+        int tot = 0;
+        for (int w = 0; w < kTravWaves; ++w) {
+            const int v = sh.req[w][c];
+            sh.req[w][c] = tot;
+            tot += v;
+        }
+        int base = 0;
+        if (tot) {
+            int *ctr = c == R_EOP   ? &o.cnt[C_EOP * CP]
+                       : c == R_EGRP ? &o.cnt[C_EGRP * CP]
+                       : c == R_FOP  ? &o.cnt[C_FOP * CP]
+                       : c == R_FGRP ? &o.cnt[C_FGRP * CP]
+                       : c == R_LOP  ? &o.cnt[C_LOP * CP]
+                       : c == R_LGRP ? &o.cnt[C_LGRP * CP]
+                       : c == R_PAIR ? &o.lvl_next[C_PAIR * CP]
+                                     : &o.lvl_next[C_SEG * CP];
+            base = atomicAdd(ctr, tot);
+        }
+        for (int w = 0; w < kTravWaves; ++w) sh.req[w][c] += base;
+    } else if (o.want_stats && threadIdx.x >= 64 && threadIdx.x < 64 + T_N) {
+        const int c = threadIdx.x - 64;
+        unsigned long long tot = 0;
+        for (int w = 0; w < kTravWaves; ++w) tot += sh.st[w][c];
+        const int sidx[T_N] = {S_PAIRS, S_SEGS, S_F, S_D, S_T, S_C, S_BLEAF, S_BPTS};
+        if (tot) atomicAdd(&o.stats[sidx[c] * SP], tot);
+    } else if (o.want_stats && threadIdx.x == 64 + T_N) {
+        unsigned long long ms = 0, mx = 0;
+        for (int w = 0; w < kTravWaves; ++w) {
+            ms = sh.maxseg[w] > ms ? sh.maxseg[w] : ms;
+            mx = sh.maxord[w] > mx ? sh.maxord[w] : mx;
+        }
+        if (ms) atomicMax(&o.stats[S_MAXSEG * SP], ms);
+        if (mx) atomicMax(&o.stats[S_MAXORD * SP], mx);
+    }
+    __syncthreads();
+    const int ebase = sh.req[wv][R_EOP], gE = sh.req[wv][R_EGRP];
+    const int fbase = sh.req[wv][R_FOP], gF = sh.req[wv][R_FGRP];
+    const int lbase = sh.req[wv][R_LOP], gL = sh.req[wv][R_LGRP];
+    const int cbase = sh.req[wv][R_PAIR], sgi = sh.req[wv][R_SEG];
+    __syncthreads();  // the table is rewritten by the next iteration
+    if (!valid) return;
+
+    // 4. link the new groups into their chains, then write the group records
     const bool okE = tE && ebase + tE <= o.cap.eop && gE < o.cap.grp;
     const bool okF = tF && fbase + tF <= o.cap.fop && gF < o.cap.grp;
     const bool okL = tL && lbase + tL <= o.cap.lop && gL < o.cap.grp;
     const bool okN = npair_out && cbase + npair_out <= o.cap.pair && sgi + nseg_out <= o.cap.seg;
+    const size_t hq = (size_t)jb.noff + q;
     int prev = -1;
     if (lane == 0 && okE) prev = atomicExch(&o.headE[hq], gE);
     if (lane == 1 && okF) prev = atomicExch(&o.headF[hq], gF);
@@ -433,34 +528,35 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         // plain read-modify-write, deterministic
         if (ccon != 0.0) o.cval[hq] += ccon;
     }
-    if (o.want_stats) {  // counters for dfgt_stats, one lane each (no return values)
-        if (lane == 8) atomicAdd(&o.stats[S_PAIRS * SP], (unsigned long long)sg.count);
-        if (lane == 9) atomicAdd(&o.stats[S_SEGS * SP], 1ull);
-        if (lane == 10) atomicMax(&o.stats[S_MAXSEG * SP], (unsigned long long)sg.count);
-        if (lane == 11 && nFp) atomicAdd(&o.stats[S_F * SP], (unsigned long long)nFp);
-        if (lane == 12 && nDp) atomicAdd(&o.stats[S_D * SP], (unsigned long long)nDp);
-        if (lane == 13 && nTp) atomicAdd(&o.stats[S_T * SP], (unsigned long long)nTp);
-        if (lane == 14 && nCp) atomicAdd(&o.stats[S_C * SP], (unsigned long long)nCp);
-        if (lane == 15 && tE) atomicAdd(&o.stats[S_BLEAF * SP], (unsigned long long)tE);
-        if (lane == 16 && tE) atomicAdd(&o.stats[S_BPTS * SP], (unsigned long long)(nQ * ept));
-        if (lane == 17 && mo) atomicMax(&o.stats[S_MAXORD * SP], (unsigned long long)mo);
-    }
 
-    // 3. write outputs in pair order
+    // 5. write outputs in pair order
     int eo = 0, fo = 0, lo = 0, no = 0;
     const int QL = qleaf ? q : Q.left[q], QR = qleaf ? q : Q.right[q];
     for (int c0 = 0; c0 < sg.count; c0 += 64) {
         const int i = c0 + lane;
-        int m = METH_E, ord = 0, r = -1, e = 0, f = 0, l = 0, n = 0;
+        int m = METH_E, ord = 0, r = -1, e = 0, f = 0, l = 0, n = 0, rl = -1, rr = -1;
         bool rleaf = true;
         if (i < sg.count) {
-            r = pairs[sg.start + i];
-            const int v = dec[sg.start + i];
-            m = v & 15;
-            ord = v >> 4;
-            rleaf = R.left[r] < 0;
+            int nRi;
+            if (c0 == 0) {
+                r = r0;
+                m = m0;
+                ord = ord0;
+                rl = left0;
+                rr = right0;
+                nRi = (int)nR0;
+            } else {
+                r = pairs[sg.start + i];
+                const int v = dec[sg.start + i];
+                m = v & 15;
+                ord = v >> 4;
+                rl = R.left[r];
+                rr = R.right[r];
+                nRi = R.end[r] - R.begin[r];
+            }
+            rleaf = rl < 0;
             if (m == METH_F) f = 1;
-            else if (m != METH_E) l = m == METH_D ? (R.end[r] - R.begin[r] + 63) / 64 : (ord == 1 ? 0 : 1);
+            else if (m != METH_E) l = m == METH_D ? (nRi + 63) / 64 : (ord == 1 ? 0 : 1);
             else if (qleaf && rleaf) e = 1;
             else n = (qleaf || !rleaf) ? 2 : 1;
         }
@@ -473,16 +569,16 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         if (n && okN) {
             const int p0 = cbase + no + xn;
             if (qleaf) {
-                o.npairs[p0] = R.left[r];
-                o.npairs[p0 + 1] = R.right[r];
+                o.npairs[p0] = rl;
+                o.npairs[p0 + 1] = rr;
             } else if (rleaf) {
                 o.npairs[p0] = r;
                 o.npairs[p0 + tN] = r;
             } else {
-                o.npairs[p0] = R.left[r];
-                o.npairs[p0 + 1] = R.right[r];
-                o.npairs[p0 + tN] = R.left[r];
-                o.npairs[p0 + tN + 1] = R.right[r];
+                o.npairs[p0] = rl;
+                o.npairs[p0 + 1] = rr;
+                o.npairs[p0 + tN] = rl;
+                o.npairs[p0 + tN + 1] = rr;
             }
         }
         eo += te;
@@ -498,14 +594,22 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
 
 // One level of the traversal; the segment count comes from the previous
 // level's counters (or nseg0 at level 0), so no host round trip is needed.
-__global__ __launch_bounds__(64) void k_traverse(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                                 const Seg *__restrict__ segs, const int *__restrict__ pairs,
-                                                 const int *__restrict__ lvl_in, int nseg0, int force, int gr,
-                                                 int leaf_local, int *dec, double *kus, TravOut o) {
+// Blocks of kTravWaves waves stride over the segments together.
+__global__ __launch_bounds__(64 * kTravWaves) void k_traverse(const DevTree *__restrict__ trees,
+                                                              const Job *__restrict__ jobs,
+                                                              const Seg *__restrict__ segs,
+                                                              const int *__restrict__ pairs,
+                                                              const int *__restrict__ lvl_in, int nseg0, int force,
+                                                              int gr, int leaf_local, int *dec, double *kus,
+                                                              TravOut o) {
+    __shared__ TravShared sh;
     if (*o.overflow) return;
     const int nseg = lvl_in ? min(lvl_in[C_SEG * CP], o.cap.seg) : nseg0;
-    for (int si = blockIdx.x; si < nseg; si += gridDim.x)
-        traverse_segment(trees, jobs, segs[si], pairs, force, gr, leaf_local, dec, kus, o);
+    const int wv = threadIdx.x >> 6;
+    for (int b0 = blockIdx.x * kTravWaves; b0 < nseg; b0 += gridDim.x * kTravWaves) {
+        const int si = b0 + wv;
+        traverse_segment(trees, jobs, segs, si, si < nseg, pairs, force, gr, leaf_local, dec, kus, o, sh);
+    }
 }
 
 // ---------------------------------------------------------------- local moments: D and T ops
@@ -2271,7 +2375,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                   w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
                   w.stats.as<unsigned long long>(),     w.cval.as<double>(), prof ? 1 : 0, w.cap};
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
-        hipLaunchKernelGGL(k_traverse, dim3(kTravGrid), dim3(64), 0, st, td, jd, sin.as<Seg>(), pin.as<int>(),
+        hipLaunchKernelGGL(k_traverse, dim3(kTravGrid / kTravWaves), dim3(64 * kTravWaves), 0, st, td, jd,
+                           sin.as<Seg>(), pin.as<int>(),
                            k == 0 ? (const int *)nullptr : lvl + (size_t)k * 2 * CP, njobs, pl.force,
                            pl.gr ? 1 : 0, pl.leaf_local ? 1 : 0, w.dec.as<int>(), w.kus.as<double>(), o);
         if (prof) prof->stop(K_TRAV, ev, st);

@@ -1,17 +1,23 @@
 // Mid-point kd-tree (Section 2.1, Alg. BuildKdTree) built level by level on the GPU.
 //
 // The recursion of the algorithm is unrolled breadth-first: every level is one
-// pass over all points.  Per level:
+// pass over all points, three kernels per level:
 //   k_flag      each point of a splittable node evaluates x[sd] <= sc against
 //               its node's split (widest dimension, lowest index on ties, FP64
-//               mid-point) and counts the left side;
-//   k_finalize  one block decides which nodes split (non-empty sides) and
-//               allocates their children in breadth-first order;
-//   scan        exclusive prefix sum of the left flags (stable ranks);
+//               mid-point); a block-wide exclusive scan of these left flags
+//               gives each point its rank in its block and the block its total;
+//   k_finalize  one block scans the block totals, counts each node's left side
+//               from the ranks at its first and last point, decides which nodes
+//               split (non-empty sides) and allocates their children in
+//               breadth-first order;
 //   k_scatter   moves every point of a split node to its stable position in
 //               the left or right child and folds its coordinates into the
 //               child's bounding box (exact min / max through ordered-integer
 //               atomics, so the result does not depend on arrival order).
+// Box folds reduce in the block first (LDS atomics over the block's nodes, a
+// contiguous id range) and issue one global atomic per (node, dimension) per
+// block: same-address device atomics serialise, and near the root every block
+// would otherwise hit the same few nodes.
 // The result is bit-identical to the recursive algorithm (same boxes, split
 // dimensions, split coordinates and permutation); only node numbering differs
 // (breadth-first instead of pre-order).
@@ -23,38 +29,8 @@
 namespace dfgt {
 namespace {
 
-constexpr int kTB = 256;
 constexpr long long kPosInfKey = 0x7ff0000000000000LL;                    // key of +inf
 constexpr long long kNegInfKey = (long long)0xfff0000000000000ULL ^ 0x7fffffffffffffffLL;  // key of -inf
-
-// Folds the coordinates of the active lanes into the boxes of their nodes.
-// Lanes sharing a node are reduced in-wave first; one lane per node issues the
-// atomics.  Min / max are exact, so the order of arrival does not matter.
-__device__ void wave_box_fold(bool active, int node, const double *v, int d, long long *lo_key,
-                              long long *hi_key) {
-    const int lane = threadIdx.x & 63;
-    unsigned long long pending = __ballot(active);
-    while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const int lead_node = __shfl(node, leader, 64);
-        const bool mine = active && node == lead_node;
-        for (int k = 0; k < d; ++k) {
-            long long kv = mine ? dbl_key(v[k]) : kPosInfKey;
-            long long kx = mine ? dbl_key(v[k]) : kNegInfKey;
-            for (int off = 32; off >= 1; off >>= 1) {
-                long long a = __shfl_xor(kv, off, 64);
-                long long b = __shfl_xor(kx, off, 64);
-                kv = a < kv ? a : kv;
-                kx = b > kx ? b : kx;
-            }
-            if (lane == leader) {
-                atomicMin(&lo_key[(size_t)lead_node * d + k], kv);
-                atomicMax(&hi_key[(size_t)lead_node * d + k], kx);
-            }
-        }
-        pending &= ~__ballot(mine);
-    }
-}
 
 __global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *perm, double *x, int32_t *pnode,
                        int *bad) {
@@ -70,7 +46,7 @@ __global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *pe
 }
 
 __global__ void k_init_root(long long *lo_key, long long *hi_key, int d, int32_t *begin, int32_t *end,
-                            int32_t *parent, int32_t *nleft, int n) {
+                            int32_t *parent, int n) {
     for (int k = threadIdx.x; k < d; k += blockDim.x) {
         lo_key[k] = kPosInfKey;
         hi_key[k] = kNegInfKey;
@@ -79,17 +55,97 @@ __global__ void k_init_root(long long *lo_key, long long *hi_key, int d, int32_t
         begin[0] = 0;
         end[0] = n;
         parent[0] = -1;
-        nleft[0] = 0;
     }
 }
 
-__global__ void k_root_box(const double *__restrict__ x, int n, int d, long long *lo_key, long long *hi_key) {
+constexpr int kLB = 256;         // points per block of the per-point level kernels
+constexpr int kFoldKeys = 1024;  // LDS keys per bound array of the block box fold
+
+struct FoldShared {
+    long long lo[kFoldKeys], hi[kFoldKeys];
+    int wmin[kLB / 64], wmax[kLB / 64];
+};
+
+// Folds the coordinates v of the active threads into the boxes of their nodes:
+// block-wide minimum / maximum per (node, dimension) in LDS, then one global
+// atomic each.  The block's nodes must span at most kFoldKeys / d consecutive
+// ids, else the waves fold on their own.  Every thread of the block calls it.
+__device__ void block_box_fold(bool active, int node, const double *v, int d, long long *lo_key,
+                               long long *hi_key, FoldShared &sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int mn = active ? node : 0x7fffffff, mx = active ? node : -1;
+    for (int off = 32; off >= 1; off >>= 1) {
+        mn = min(mn, __shfl_xor(mn, off, 64));
+        mx = max(mx, __shfl_xor(mx, off, 64));
+    }
+    if (lane == 0) {
+        sh.wmin[wv] = mn;
+        sh.wmax[wv] = mx;
+    }
+    __syncthreads();
+    mn = sh.wmin[0];
+    mx = sh.wmax[0];
+    for (int w = 1; w < kLB / 64; ++w) {
+        mn = min(mn, sh.wmin[w]);
+        mx = max(mx, sh.wmax[w]);
+    }
+    __syncthreads();  // the table is read before anyone returns or rewrites it
+    if (mx < 0) return;  // no active thread in the block
+    const int span = mx - mn + 1;
+    if ((long long)span * d > kFoldKeys) {
+        // the block's nodes are many and small: per-wave fold, one lane per node
+        unsigned long long pending = __ballot(active);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int lead_node = __shfl(node, leader, 64);
+            const bool mine = active && node == lead_node;
+            for (int k = 0; k < d; ++k) {
+                long long kv = mine ? dbl_key(v[k]) : kPosInfKey;
+                long long kx = mine ? dbl_key(v[k]) : kNegInfKey;
+                for (int off = 32; off >= 1; off >>= 1) {
+                    long long a = __shfl_xor(kv, off, 64);
+                    long long b = __shfl_xor(kx, off, 64);
+                    kv = a < kv ? a : kv;
+                    kx = b > kx ? b : kx;
+                }
+                if (lane == leader) {
+                    atomicMin(&lo_key[(size_t)lead_node * d + k], kv);
+                    atomicMax(&hi_key[(size_t)lead_node * d + k], kx);
+                }
+            }
+            pending &= ~__ballot(mine);
+        }
+        return;
+    }
+    const int nk = span * d;
+    for (int t = threadIdx.x; t < nk; t += kLB) {
+        sh.lo[t] = kPosInfKey;
+        sh.hi[t] = kNegInfKey;
+    }
+    __syncthreads();
+    if (active)
+        for (int k = 0; k < d; ++k) {
+            const long long key = dbl_key(v[k]);
+            atomicMin(&sh.lo[(node - mn) * d + k], key);
+            atomicMax(&sh.hi[(node - mn) * d + k], key);
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nk; t += kLB) {
+        const long long a = sh.lo[t], b = sh.hi[t];
+        if (a != kPosInfKey) atomicMin(&lo_key[(size_t)mn * d + t], a);
+        if (b != kNegInfKey) atomicMax(&hi_key[(size_t)mn * d + t], b);
+    }
+}
+
+__global__ __launch_bounds__(kLB) void k_root_box(const double *__restrict__ x, int n, int d, long long *lo_key,
+                                                  long long *hi_key) {
+    __shared__ FoldShared sh;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[kMaxD];
     const bool act = i < n;
     if (act)
         for (int k = 0; k < d; ++k) v[k] = x[(size_t)i * d + k];
-    wave_box_fold(act, 0, v, d, lo_key, hi_key);
+    block_box_fold(act, 0, v, d, lo_key, hi_key, sh);
 }
 
 // Split rule of one node; returns false if the node is a leaf before counting.
@@ -112,84 +168,126 @@ __device__ __forceinline__ bool node_split(const long long *lo_key, const long l
     return true;
 }
 
-__global__ void k_flag(const double *__restrict__ x, const int32_t *__restrict__ pnode, int n, int d, int leaf,
-                       const long long *__restrict__ lo_key, const long long *__restrict__ hi_key,
-                       const int32_t *__restrict__ begin, const int32_t *__restrict__ end, int32_t *flag,
-                       int32_t *nleft, const int *__restrict__ done) {
+// Exclusive block scan of one int per thread (kLB threads); *total gets the sum.
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int w = 0; w < kLB / 64; ++w) {
+        pre += w < wv ? wsum[w] : 0;
+        tot += wsum[w];
+    }
+    *total = tot;
+    return pre + inc - v;
+}
+
+// Left flags of the points of splittable nodes, their exclusive rank in the
+// block (rank[i]) and the block's total (bsum[block]).
+__global__ __launch_bounds__(kLB) void k_flag(const double *__restrict__ x, const int32_t *__restrict__ pnode, int n,
+                                              int d, int leaf, const long long *__restrict__ lo_key,
+                                              const long long *__restrict__ hi_key,
+                                              const int32_t *__restrict__ begin, const int32_t *__restrict__ end,
+                                              int32_t *flag, int32_t *rank, int32_t *bsum,
+                                              const int *__restrict__ done) {
+    __shared__ int wsum[kLB / 64];
     if (*done) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int f = 0, node = -1;
+    const int i = blockIdx.x * kLB + threadIdx.x;
+    int f = 0;
     if (i < n) {
-        node = pnode[i];
+        const int node = pnode[i];
         if (node >= 0) {
             int sd;
             double sc;
             if (node_split(lo_key, hi_key, node, d, end[node] - begin[node], leaf, &sd, &sc))
                 f = x[(size_t)i * d + sd] <= sc ? 1 : 0;
         }
+    }
+    int tot;
+    const int ex = block_excl_scan(f, wsum, &tot);
+    if (i < n) {
         flag[i] = f;
+        rank[i] = ex;
     }
-    // wave-aggregated count of left points per node
-    unsigned long long pending = __ballot(f != 0);
-    while (pending) {
-        const int leader = __ffsll((long long)pending) - 1;
-        const int ln = __shfl(node, leader, 64);
-        unsigned long long same = __ballot(f != 0 && node == ln);
-        if ((threadIdx.x & 63) == leader) atomicAdd(&nleft[ln], __popcll(same));
-        pending &= ~same;
-    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// One block: decide the splits of level nodes [lb, le) and allocate children
-// at le + 2 * (rank among splitting nodes).
+// One block: the exclusive scan of the block totals (boff), then the splits of
+// level nodes [lb, le): a node's left count is the difference of the global
+// left ranks at its end and begin; children are allocated at
+// le + 2 * (rank among splitting nodes).
 // Level bounds live on the device: level k is [lvs[2k], lvs[2k+1]); the
 // kernel writes level k+1's bounds, or sets *done when nothing splits (the
 // per-level kernels that follow then return at once).
-__global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs, int *done, int d, int leaf,
+__global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs, int *done, int d, int leaf, int n,
                                                    long long *lo_key, long long *hi_key, int32_t *begin,
                                                    int32_t *end, int32_t *left, int32_t *right, int32_t *parent,
-                                                   int32_t *sdim, double *scoord, int32_t *nleft) {
+                                                   int32_t *sdim, double *scoord, int32_t *nleft,
+                                                   const int32_t *__restrict__ rank, const int32_t *__restrict__ bsum,
+                                                   int nb, int32_t *boff) {
     __shared__ int warp_tot[16];
     __shared__ int carry_s;
     if (*done) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // 1. block offsets
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nb; c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        const int inc = wave_incl_scan(v);
+        if (lane == 63) warp_tot[w] = inc;
+        __syncthreads();
+        int wb = 0;
+        for (int k = 0; k < w; ++k) wb += warp_tot[k];
+        const int ex = carry_s + wb + inc - v;
+        __syncthreads();
+        if (i < nb) boff[i] = ex;
+        if (threadIdx.x == blockDim.x - 1) carry_s = ex + v;
+        __syncthreads();
+    }
+    const int total = carry_s;
+    __syncthreads();  // boff written by this block is visible to it from here
+    // global exclusive left rank at a position (n: the total)
+    auto grank = [&](int pos) { return pos >= n ? total : boff[pos / kLB] + rank[pos]; };
+    // 2. splits and children
     const int lb = lvs[2 * level], le = lvs[2 * level + 1];
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     for (int c0 = lb; c0 < le; c0 += blockDim.x) {
         const int node = c0 + threadIdx.x;
-        int split = 0, sd = -1;
+        int split = 0, sd = -1, nl = 0;
         double sc = 0.0;
         if (node < le) {
-            const int cnt = end[node] - begin[node];
+            const int b = begin[node], e = end[node], cnt = e - b;
             if (node_split(lo_key, hi_key, node, d, cnt, leaf, &sd, &sc)) {
-                const int nl = nleft[node];
+                nl = grank(e) - grank(b);
                 split = (nl > 0 && nl < cnt) ? 1 : 0;
             }
         }
         // block exclusive scan of split
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         int inc = wave_incl_scan(split);
         if (lane == 63) warp_tot[w] = inc;
         __syncthreads();
         int wbase = 0;
         for (int k = 0; k < w; ++k) wbase += warp_tot[k];
-        const int rank = carry_s + wbase + inc - split;
+        const int rk = carry_s + wbase + inc - split;
         if (node < le) {
             if (split) {
-                const int L = le + 2 * rank, R = L + 1;
-                const int b = begin[node], e = end[node], nl = nleft[node];
+                const int L = le + 2 * rk, R = L + 1;
+                const int b = begin[node], e = end[node];
                 left[node] = L;
                 right[node] = R;
                 sdim[node] = sd;
                 scoord[node] = sc;
+                nleft[node] = nl;
                 begin[L] = b;
                 end[L] = b + nl;
                 begin[R] = b + nl;
                 end[R] = e;
                 parent[L] = node;
                 parent[R] = node;
-                nleft[L] = 0;
-                nleft[R] = 0;
                 for (int k = 0; k < d; ++k) {
                     lo_key[(size_t)L * d + k] = kPosInfKey;
                     hi_key[(size_t)L * d + k] = kNegInfKey;
@@ -204,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
             }
         }
         __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) carry_s = rank + split;
+        if (threadIdx.x == blockDim.x - 1) carry_s = rk + split;
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -215,81 +313,17 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
     }
 }
 
-// --- exclusive scan of int32 flags (three phases) -----------------------------------
-constexpr int kScanItems = 1024;  // per block: 256 threads x 4
-
-__global__ void k_scan_blocks(const int32_t *__restrict__ in, int n, int32_t *__restrict__ block_sums,
-                              const int *__restrict__ done) {
-    __shared__ int wt[4];
+__global__ __launch_bounds__(kLB) void k_scatter(int n, int d, const int32_t *__restrict__ pnode_a,
+                                                 const int32_t *__restrict__ perm_a, const double *__restrict__ x_a,
+                                                 const int32_t *__restrict__ flag, const int32_t *__restrict__ rank,
+                                                 const int32_t *__restrict__ boff, const int32_t *__restrict__ begin,
+                                                 const int32_t *__restrict__ nleft, const int32_t *__restrict__ left,
+                                                 const int32_t *__restrict__ right, int32_t *pnode_b, int32_t *perm_b,
+                                                 double *x_b, long long *lo_key, long long *hi_key,
+                                                 const int *__restrict__ done) {
+    __shared__ FoldShared sh;
     if (*done) return;
-    const int base = blockIdx.x * kScanItems;
-    int s = 0;
-    for (int j = 0; j < 4; ++j) {
-        int i = base + threadIdx.x * 4 + j;
-        s += i < n ? in[i] : 0;
-    }
-    s = wave_sum_i(s);
-    if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = wt[0] + wt[1] + wt[2] + wt[3];
-}
-
-__global__ __launch_bounds__(1024) void k_scan_sums(int32_t *sums, int nb, const int *__restrict__ done) {
-    if (*done) return;
-    __shared__ int wt[16];
-    __shared__ int carry_s;
-    if (threadIdx.x == 0) carry_s = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < nb; c0 += blockDim.x) {
-        const int i = c0 + threadIdx.x;
-        const int v = i < nb ? sums[i] : 0;
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        int inc = wave_incl_scan(v);
-        if (lane == 63) wt[w] = inc;
-        __syncthreads();
-        int wb = 0;
-        for (int k = 0; k < w; ++k) wb += wt[k];
-        const int ex = carry_s + wb + inc - v;
-        __syncthreads();
-        if (i < nb) sums[i] = ex;
-        if (threadIdx.x == blockDim.x - 1) carry_s = ex + v;
-        __syncthreads();
-    }
-}
-
-__global__ void k_scan_final(const int32_t *__restrict__ in, int n, const int32_t *__restrict__ block_off,
-                             int32_t *__restrict__ out, const int *__restrict__ done) {
-    __shared__ int wt[4];
-    if (*done) return;
-    const int base = blockIdx.x * kScanItems;
-    int v[4], s = 0;
-    for (int j = 0; j < 4; ++j) {
-        int i = base + threadIdx.x * 4 + j;
-        v[j] = i < n ? in[i] : 0;
-        s += v[j];
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int inc = wave_incl_scan(s);
-    if (lane == 63) wt[w] = inc;
-    __syncthreads();
-    int wb = 0;
-    for (int k = 0; k < w; ++k) wb += wt[k];
-    int run = block_off[blockIdx.x] + wb + inc - s;
-    for (int j = 0; j < 4; ++j) {
-        int i = base + threadIdx.x * 4 + j;
-        if (i < n) out[i] = run;
-        run += v[j];
-    }
-}
-
-__global__ void k_scatter(int n, int d, const int32_t *__restrict__ pnode_a, const int32_t *__restrict__ perm_a,
-                          const double *__restrict__ x_a, const int32_t *__restrict__ flag,
-                          const int32_t *__restrict__ scan, const int32_t *__restrict__ begin,
-                          const int32_t *__restrict__ nleft, const int32_t *__restrict__ left,
-                          const int32_t *__restrict__ right, int32_t *pnode_b, int32_t *perm_b, double *x_b,
-                          long long *lo_key, long long *hi_key, const int *__restrict__ done) {
-    if (*done) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kLB + threadIdx.x;
     double v[kMaxD];
     int child = -1;
     bool act = false;
@@ -299,7 +333,8 @@ __global__ void k_scatter(int n, int d, const int32_t *__restrict__ pnode_a, con
         int dst = i;
         if (node >= 0 && left[node] >= 0) {
             const int b = begin[node];
-            const int rl = scan[i] - scan[b];
+            // left points of the node before i (global left ranks at i and b)
+            const int rl = (boff[i / kLB] + rank[i]) - (boff[b / kLB] + rank[b]);
             if (flag[i]) {
                 dst = b + rl;
                 child = left[node];
@@ -313,7 +348,7 @@ __global__ void k_scatter(int n, int d, const int32_t *__restrict__ pnode_a, con
         pnode_b[dst] = child;
         for (int k = 0; k < d; ++k) x_b[(size_t)dst * d + k] = v[k];
     }
-    wave_box_fold(act, child, v, d, lo_key, hi_key);
+    block_box_fold(act, child, v, d, lo_key, hi_key, sh);
 }
 
 __global__ void k_decode_boxes(int m, int d, const long long *__restrict__ lo_key,
@@ -368,7 +403,7 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
 
 // Scratch of the build, kept per host thread and reused across builds.
 struct BuildWs {
-    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, scan, bsums, lo_key, hi_key, nleft, counter, lvs;
+    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft, counter, lvs;
 };
 thread_local BuildWs g_build;
 
@@ -377,8 +412,8 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     const int cap = 2 * n + 1;
     BuildWs &w = g_build;
     DevBuf &perm_b = w.perm_b, &x_b = w.x_b, &pnode_a = w.pnode_a, &pnode_b = w.pnode_b, &flag = w.flag,
-           &scan = w.scan, &bsums = w.bsums, &lo_key = w.lo_key, &hi_key = w.hi_key, &nleft = w.nleft,
-           &counter = w.counter, &lvs_b = w.lvs;
+           &rank = w.rank, &bsums = w.bsums, &boff = w.boff, &lo_key = w.lo_key, &hi_key = w.hi_key,
+           &nleft = w.nleft, &counter = w.counter, &lvs_b = w.lvs;
     DFGT_TRY(alloc_spans(t->arena0, {{&t->perm, sizeof(int32_t) * n},
                                      {&t->x, sizeof(double) * (size_t)n * d},
                                      {&t->begin, sizeof(int32_t) * cap},
@@ -393,9 +428,10 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     DFGT_TRY(pnode_a.reserve(sizeof(int32_t) * n));
     DFGT_TRY(pnode_b.reserve(sizeof(int32_t) * n));
     DFGT_TRY(flag.reserve(sizeof(int32_t) * n));
-    DFGT_TRY(scan.reserve(sizeof(int32_t) * n));
-    const int nsb = (n + kScanItems - 1) / kScanItems;
-    DFGT_TRY(bsums.reserve(sizeof(int32_t) * (nsb + 1)));
+    DFGT_TRY(rank.reserve(sizeof(int32_t) * n));
+    const int gb = (n + kLB - 1) / kLB;  // blocks of the per-point level kernels
+    DFGT_TRY(bsums.reserve(sizeof(int32_t) * (gb + 1)));
+    DFGT_TRY(boff.reserve(sizeof(int32_t) * (gb + 1)));
     DFGT_TRY(lo_key.reserve(sizeof(long long) * (size_t)cap * d));
     DFGT_TRY(hi_key.reserve(sizeof(long long) * (size_t)cap * d));
     DFGT_TRY(nleft.reserve(sizeof(int32_t) * cap));
@@ -413,12 +449,10 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     const int lvs0[2] = {0, 1};
     DFGT_HIP(hipMemsetAsync(cnt_d, 0, sizeof(int) * 4, st));
     DFGT_HIP(hipMemcpyAsync(lvs, lvs0, sizeof(lvs0), hipMemcpyHostToDevice, st));
-    const int gb = (n + kTB - 1) / kTB;
-    hipLaunchKernelGGL(k_init, dim3(gb), dim3(kTB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
+    hipLaunchKernelGGL(k_init, dim3(gb), dim3(kLB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
     hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
-                       t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(),
-                       nleft.as<int32_t>(), n);
-    hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kTB), 0, st, xa, n, d, lo_key.as<long long>(),
+                       t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(), n);
+    hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kLB), 0, st, xa, n, d, lo_key.as<long long>(),
                        hi_key.as<long long>());
     DFGT_HIP(hipGetLastError());
 
@@ -436,23 +470,19 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
             int32_t *pin = (level & 1) ? pb : pa, *pout = (level & 1) ? pa : pb;
             double *xin = (level & 1) ? xb : xa, *xout = (level & 1) ? xa : xb;
             int32_t *nin = (level & 1) ? nb : na, *nout = (level & 1) ? na : nb;
-            hipLaunchKernelGGL(k_flag, dim3(gb), dim3(kTB), 0, st, xin, nin, n, d, leaf, lo_key.as<long long>(),
+            hipLaunchKernelGGL(k_flag, dim3(gb), dim3(kLB), 0, st, xin, nin, n, d, leaf, lo_key.as<long long>(),
                                hi_key.as<long long>(), t->begin.as<int32_t>(), t->end.as<int32_t>(),
-                               flag.as<int32_t>(), nleft.as<int32_t>(), cnt_d);
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, level, cap, lvs, cnt_d, d, leaf,
+                               flag.as<int32_t>(), rank.as<int32_t>(), bsums.as<int32_t>(), cnt_d);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, level, cap, lvs, cnt_d, d, leaf, n,
                                lo_key.as<long long>(), hi_key.as<long long>(), t->begin.as<int32_t>(),
                                t->end.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(),
                                t->parent.as<int32_t>(), t->sdim.as<int32_t>(), t->scoord.as<double>(),
-                               nleft.as<int32_t>());
-            hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n,
-                               bsums.as<int32_t>(), cnt_d);
-            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, bsums.as<int32_t>(), nsb, cnt_d);
-            hipLaunchKernelGGL(k_scan_final, dim3(nsb), dim3(256), 0, st, flag.as<int32_t>(), n,
-                               bsums.as<int32_t>(), scan.as<int32_t>(), cnt_d);
-            hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kTB), 0, st, n, d, nin, pin, xin, flag.as<int32_t>(),
-                               scan.as<int32_t>(), t->begin.as<int32_t>(), nleft.as<int32_t>(),
-                               t->left.as<int32_t>(), t->right.as<int32_t>(), nout, pout, xout,
-                               lo_key.as<long long>(), hi_key.as<long long>(), cnt_d);
+                               nleft.as<int32_t>(), rank.as<int32_t>(), bsums.as<int32_t>(), gb,
+                               boff.as<int32_t>());
+            hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kLB), 0, st, n, d, nin, pin, xin, flag.as<int32_t>(),
+                               rank.as<int32_t>(), boff.as<int32_t>(), t->begin.as<int32_t>(),
+                               nleft.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(), nout, pout,
+                               xout, lo_key.as<long long>(), hi_key.as<long long>(), cnt_d);
             DFGT_HIP(hipGetLastError());
         }
         int flags[2] = {0, 0};
