@@ -138,7 +138,10 @@ const char *dfgt_version(void);
 dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const dfgt_options *opt,
                             void *stream, dfgt_tree *out);
 
-/* Frees a tree handle (NULL is allowed). */
+/* Frees a tree handle (NULL is allowed).  Work already queued on the stream the
+ * tree was built on may still use it: its device memory is kept by the library
+ * and handed to a later build only after that stream reaches this point.  Work
+ * that uses the tree on other streams must have completed before the call. */
 dfgt_status dfgt_tree_free(dfgt_tree t);
 
 /* Sizes of a tree: points, dimension, nodes, levels, p_max. Any pointer may be NULL. */

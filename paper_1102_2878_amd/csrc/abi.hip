@@ -2,6 +2,7 @@
 // Every entry point catches C++ exceptions so none crosses the ABI.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -46,6 +47,78 @@ using namespace dfgt;
         return DFGT_EHIP;                                            \
     }
 
+namespace dfgt {
+
+namespace {
+struct Pooled {
+    void *p;
+    size_t bytes;
+    hipEvent_t ev;
+};
+struct ArenaPool {
+    std::mutex mu;
+    std::vector<Pooled> items;
+    std::vector<hipEvent_t> spare;  // events no pooled item holds
+    size_t total = 0;
+    ~ArenaPool() {
+        for (auto &it : items) {
+            (void)hipFree(it.p);
+            (void)hipEventDestroy(it.ev);
+        }
+        for (auto ev : spare) (void)hipEventDestroy(ev);
+    }
+};
+ArenaPool &arena_pool() {
+    static ArenaPool pool;
+    return pool;
+}
+constexpr size_t kPoolMaxBytes = size_t(2) << 30;
+}  // namespace
+
+void pool_put(DevBuf &b, hipStream_t st) {
+    if (!b.p) return;
+    ArenaPool &pl = arena_pool();
+    std::lock_guard<std::mutex> lk(pl.mu);
+    hipEvent_t ev = nullptr;
+    if (!pl.spare.empty()) {
+        ev = pl.spare.back();
+        pl.spare.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+    }
+    if (!ev || hipEventRecord(ev, st) != hipSuccess || pl.total + b.bytes > kPoolMaxBytes) {
+        if (ev) pl.spare.push_back(ev);
+        b.release();  // hipFree: synchronises, so the memory is idle before it is reused
+        return;
+    }
+    pl.items.push_back(Pooled{b.p, b.bytes, ev});
+    pl.total += b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+dfgt_status pool_get(DevBuf &b, size_t need, hipStream_t st) {
+    ArenaPool &pl = arena_pool();
+    std::lock_guard<std::mutex> lk(pl.mu);
+    int best = -1;
+    for (int i = 0; i < (int)pl.items.size(); ++i) {
+        const size_t sz = pl.items[i].bytes;
+        if (sz >= need && sz <= 4 * need + (size_t(1) << 20) && (best < 0 || sz < pl.items[best].bytes)) best = i;
+    }
+    if (best < 0) return DFGT_OK;  // the caller allocates
+    Pooled it = pl.items[best];
+    pl.items.erase(pl.items.begin() + best);
+    pl.total -= it.bytes;
+    DFGT_HIP(hipStreamWaitEvent(st, it.ev, 0));
+    pl.spare.push_back(it.ev);
+    b.release();
+    b.p = it.p;
+    b.bytes = it.bytes;
+    return DFGT_OK;
+}
+
+}  // namespace dfgt
+
 extern "C" {
 
 const char *dfgt_last_error(void) { return g_err.c_str(); }
@@ -80,6 +153,7 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
     t->precision = o.precision;
     t->force = o.force_method;
     hipStream_t st = (hipStream_t)stream;
+    t->stream = st;
     dfgt_status s = build_tree_device(t, pts_dev, st);
     if (s == DFGT_OK) s = compute_moments(t, st);
     if (s == DFGT_OK) {
@@ -126,6 +200,13 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
 
 dfgt_status dfgt_tree_free(dfgt_tree t) {
     DFGT_GUARD_BEGIN
+    if (t) {
+        // the arenas go to the pool of freed trees, after the work queued on
+        // the tree's stream
+        pool_put(t->arena0, t->stream);
+        pool_put(t->arena1, t->stream);
+        pool_put(t->arena2, t->stream);
+    }
     delete t;
     return DFGT_OK;
     DFGT_GUARD_END

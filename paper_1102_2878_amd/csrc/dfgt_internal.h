@@ -86,11 +86,25 @@ struct DevSpan {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Device memory of freed trees, handed to later builds: otherwise every build
+// pays hipMalloc (which stalls) and every free hipFree (which synchronises the
+// device).  pool_put keeps an allocation with an event recorded on the stream
+// whose queued work may still use it; pool_get makes the taking stream wait
+// for that event.  Thread-safe; at most a bounded number of bytes are kept.
+void pool_put(DevBuf &b, hipStream_t st);
+dfgt_status pool_get(DevBuf &b, size_t need, hipStream_t st);
+
 // Carves several spans out of one allocation (256-byte aligned pieces), so a
-// tree costs a few hipMalloc calls instead of one per array.
-inline dfgt_status alloc_spans(DevBuf &arena, std::initializer_list<std::pair<DevSpan *, size_t>> items) {
+// tree costs a few allocations instead of one per array.  With a pool stream,
+// a growing arena comes from the pool of freed trees.
+inline dfgt_status alloc_spans(DevBuf &arena, std::initializer_list<std::pair<DevSpan *, size_t>> items,
+                               hipStream_t pool_stream = nullptr, bool pooled = false) {
     size_t total = 0;
     for (auto &it : items) total += (it.second + 255) / 256 * 256;
+    if (pooled && total > arena.bytes) {
+        if (arena.p) pool_put(arena, pool_stream);
+        DFGT_TRY(pool_get(arena, total, pool_stream));
+    }
     DFGT_TRY(arena.reserve(total));
     char *base = static_cast<char *>(arena.p);
     size_t off = 0;
@@ -128,12 +142,14 @@ struct dfgt_tree_s {
     int32_t d = 0, leaf = 32, pmax = 1, P = 1, depth = 0, precision = 0, force = 0;
     int64_t m = 0, nleaves = 0;
     std::vector<int32_t> level_start;  // host copy: nodes of level l are [level_start[l], level_start[l+1])
+    std::vector<int32_t> level_max;    // host copy: the most points of a node of level l
     // arena0: point and node-capacity arrays; arena1: per-node and per-leaf
     // arrays sized after the build; arena2: moments, norms and the device view
     dfgt::DevBuf arena0, arena1, arena2;
     dfgt::DevSpan lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max,
-        lpath, lplen;
+        lpath, lplen, nleaves_dev;
     double max_nrm = 0.0;  // max |x|^2 (valid after dfgt_build_tree returns)
+    hipStream_t stream = nullptr;  // the stream the tree was built on
     dfgt::DevSpan view;    // a DevTree in device memory
     dfgt::DevTree host_view{};
 };

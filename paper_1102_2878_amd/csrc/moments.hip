@@ -6,9 +6,11 @@
 // the bandwidth: M_alpha(h) = (2h^2)^{-|alpha|/2} mu_alpha, applied on the fly by
 // every consumer, so one set of moments serves a whole bandwidth sweep.
 //
-// Leaves: AccumulateFarFieldMoment (one wave per leaf, one lane per coefficient,
-// points summed in tree order).  Internal nodes, bottom-up one level per
-// launch: TransFarToFar of both children, eq. (far_to_far_translation),
+// Small coefficient sets (p_max^D <= 64): AccumulateFarFieldMoment at every
+// node, one launch.  Otherwise leaves by AccumulateFarFieldMoment (one wave
+// per leaf, one lane per coefficient, points summed in tree order) and
+// internal nodes bottom-up one level per launch: TransFarToFar of both
+// children, eq. (far_to_far_translation),
 // applied as D one-dimensional shifts
 //   mu'_{..g..} = sum_{a <= g} mu_{..a..} delta_k^{g-a} / (g-a)!,  delta = child.c - parent.c,
 // which is the same operator as the paper's double loop (the coefficient
@@ -18,10 +20,13 @@
 namespace dfgt {
 namespace {
 
+constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
+
 __global__ __launch_bounds__(64) void k_p2m(const double *__restrict__ x, const double *__restrict__ ctr,
                                             const int32_t *__restrict__ begin, const int32_t *__restrict__ end,
-                                            const int32_t *__restrict__ leaves, int d, int pmax, int P,
-                                            double *__restrict__ mu) {
+                                            const int32_t *__restrict__ leaves, const int *__restrict__ nleaves,
+                                            int d, int pmax, int P, double *__restrict__ mu) {
+    if ((int)blockIdx.x >= *nleaves) return;
     const int node = leaves[blockIdx.x];
     const int b = begin[node], e = end[node];
     const double *c = ctr + (size_t)node * d;
@@ -49,14 +54,17 @@ __global__ __launch_bounds__(64) void k_p2m(const double *__restrict__ x, const 
 
 // One block per internal node of one level.  buf: 2*P doubles per block (LDS
 // when small, else a global scratch slice).
+// skip_le > 0: nodes of at most skip_le points already hold their moments.
 template <bool kLds>
 __global__ __launch_bounds__(256) void k_f2f(int lb, int le, const int32_t *__restrict__ left,
-                                             const int32_t *__restrict__ right, const double *__restrict__ ctr,
-                                             int d, int pmax, int P, double *__restrict__ mu,
-                                             double *__restrict__ gscratch) {
+                                             const int32_t *__restrict__ right, const int32_t *__restrict__ begin,
+                                             const int32_t *__restrict__ end, int skip_le,
+                                             const double *__restrict__ ctr, int d, int pmax, int P,
+                                             double *__restrict__ mu, double *__restrict__ gscratch) {
     extern __shared__ double smem[];
     const int node = lb + blockIdx.x;
     if (node >= le || left[node] < 0) return;
+    if (skip_le > 0 && end[node] - begin[node] <= skip_le) return;
     double *coef = smem;                  // pmax * pmax
     double *buf0 = kLds ? smem + pmax * pmax : gscratch + (size_t)blockIdx.x * 2 * P;
     double *buf1 = buf0 + P;
@@ -91,6 +99,77 @@ __global__ __launch_bounds__(256) void k_f2f(int lb, int le, const int32_t *__re
     }
 }
 
+// Small coefficient sets (p_max^D <= 64): the moments of every node straight
+// from its points, AccumulateFarFieldMoment applied at each node instead of
+// TransFarToFar between levels (the same sums, one launch instead of one per
+// level).  One wave per node; lane l takes the node's points l, l + 64, ... in
+// tree order and keeps all P partial sums in registers; the wave adds them in
+// a fixed butterfly order.  Internal nodes with more than kMomDirectMax points
+// are left to TransFarToFar from their children.
+constexpr int kMomDirectMax = 2048;
+
+template <int D, int PM>
+__global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict__ x, const double *__restrict__ ctr,
+                                                       const int32_t *__restrict__ begin,
+                                                       const int32_t *__restrict__ end,
+                                                       const int32_t *__restrict__ left, double *__restrict__ mu) {
+    constexpr int P = ipow_c(PM, D);
+    const int node = blockIdx.x;
+    const int b = begin[node], e = end[node];
+    if (e - b > kMomDirectMax && left[node] >= 0) return;
+    double c[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) c[k] = ctr[(size_t)node * D + k];
+    double acc[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) acc[i] = 0.0;
+    for (int j = b + (int)threadIdx.x; j < e; j += 64) {
+        double pw[D][PM];  // (x_k - c_k)^a / a!
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double dx = x[(size_t)j * D + k] - c[k];
+            pw[k][0] = 1.0;
+#pragma unroll
+            for (int a = 1; a < PM; ++a) pw[k][a] = pw[k][a - 1] * dx / (double)a;
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            double t = 1.0;
+            int r = i;
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                t *= pw[k][r % PM];
+                r /= PM;
+            }
+            acc[i] += t;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const double v = wave_sum(acc[i]);
+        if (threadIdx.x == i) mu[(size_t)node * P + i] = v;
+    }
+}
+
+// Launches the direct kernel when (D, p_max) has an instance; false otherwise.
+bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double *x, const double *ctr,
+                           const int32_t *begin, const int32_t *end, const int32_t *left, double *mu) {
+#define DFGT_MOM(DV, PV)                                                                                \
+    if (d == DV && pmax == PV) {                                                                        \
+        hipLaunchKernelGGL((k_moments_direct<DV, PV>), dim3(m), dim3(64), 0, st, x, ctr, begin, end,          \
+                           left, mu);                                                                   \
+        return true;                                                                                    \
+    }
+    DFGT_MOM(1, 1) DFGT_MOM(1, 2) DFGT_MOM(1, 4) DFGT_MOM(1, 6) DFGT_MOM(1, 8)
+    DFGT_MOM(2, 1) DFGT_MOM(2, 2) DFGT_MOM(2, 4) DFGT_MOM(2, 6) DFGT_MOM(2, 8)
+    DFGT_MOM(3, 1) DFGT_MOM(3, 2) DFGT_MOM(3, 4)
+    DFGT_MOM(4, 1) DFGT_MOM(4, 2)
+    DFGT_MOM(5, 1) DFGT_MOM(5, 2)
+    DFGT_MOM(6, 1) DFGT_MOM(6, 2)
+#undef DFGT_MOM
+    return false;
+}
+
 }  // namespace
 
 // Squared norms of the points (tree order) and their maximum (ordered-int max
@@ -113,19 +192,31 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
         DFGT_TRY(alloc_spans(t->arena2, {{&t->nrm, sizeof(double) * (size_t)n},
                                          {&t->nrm_max, sizeof(unsigned long long)},
                                          {&t->mu, sizeof(double) * (size_t)t->m * t->P},
-                                         {&t->view, sizeof(DevTree)}}));
+                                         {&t->view, sizeof(DevTree)}},
+                                st, true));
         DFGT_HIP(hipMemsetAsync(t->nrm_max.p, 0, sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_tree_sqnorm, dim3((n + 255) / 256), dim3(256), 0, st, t->x.as<double>(), n, t->d,
                            t->nrm.as<double>(), t->nrm_max.as<unsigned long long>());
         DFGT_HIP(hipGetLastError());
-        DFGT_HIP(hipMemcpyAsync(&t->max_nrm, t->nrm_max.p, sizeof(double), hipMemcpyDeviceToHost, st));
     }
     const int d = t->d, pmax = t->pmax, P = t->P;
     const int64_t m = t->m;
-    hipLaunchKernelGGL(k_p2m, dim3((unsigned)t->nleaves), dim3(64), 0, st, t->x.as<double>(), t->ctr.as<double>(),
-                       t->begin.as<int32_t>(), t->end.as<int32_t>(), t->leaves.as<int32_t>(), d, pmax, P,
-                       t->mu.as<double>());
+    // the leaf count and the largest squared norm come back in one sync at the end
+    struct Back {
+        int nl;
+        double mx;
+    };
+    static thread_local Back back;
+    const bool direct = launch_moments_direct(d, pmax, (int)m, st, t->x.as<double>(), t->ctr.as<double>(),
+                                              t->begin.as<int32_t>(), t->end.as<int32_t>(), t->left.as<int32_t>(),
+                                              t->mu.as<double>());
+    if (!direct)
+        hipLaunchKernelGGL(k_p2m, dim3((unsigned)((m + 1) / 2)), dim3(64), 0, st, t->x.as<double>(),
+                           t->ctr.as<double>(), t->begin.as<int32_t>(), t->end.as<int32_t>(), t->leaves.as<int32_t>(),
+                           t->nleaves_dev.as<int>(), d, pmax, P, t->mu.as<double>());
     DFGT_HIP(hipGetLastError());
+    // with the direct pass, only levels holding a node above its size limit translate
+    const int skip = direct ? kMomDirectMax : 0;
     const bool lds = (size_t)(2 * P + pmax * pmax) * sizeof(double) <= 48 * 1024;
     static thread_local DevBuf scratch;  // reused across builds (freeing it would stall the device)
     int maxw = 0;
@@ -135,19 +226,25 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     for (int l = t->depth - 2; l >= 0; --l) {
         const int lb = t->level_start[l], le = t->level_start[l + 1];
         if (le <= lb) continue;
+        if (direct && t->level_max[l] <= kMomDirectMax) continue;
         if (lds) {
             size_t sh = sizeof(double) * (2 * P + pmax * pmax);
             hipLaunchKernelGGL(k_f2f<true>, dim3(le - lb), dim3(256), sh, st, lb, le, t->left.as<int32_t>(),
-                               t->right.as<int32_t>(), t->ctr.as<double>(), d, pmax, P, t->mu.as<double>(),
-                               (double *)nullptr);
+                               t->right.as<int32_t>(), t->begin.as<int32_t>(), t->end.as<int32_t>(), skip,
+                               t->ctr.as<double>(), d, pmax, P, t->mu.as<double>(), (double *)nullptr);
         } else {
             size_t sh = sizeof(double) * (pmax * pmax);
             hipLaunchKernelGGL(k_f2f<false>, dim3(le - lb), dim3(256), sh, st, lb, le, t->left.as<int32_t>(),
-                               t->right.as<int32_t>(), t->ctr.as<double>(), d, pmax, P, t->mu.as<double>(),
-                               scratch.as<double>());
+                               t->right.as<int32_t>(), t->begin.as<int32_t>(), t->end.as<int32_t>(), skip,
+                               t->ctr.as<double>(), d, pmax, P, t->mu.as<double>(), scratch.as<double>());
         }
         DFGT_HIP(hipGetLastError());
     }
+    DFGT_HIP(hipMemcpyAsync(&back.nl, t->nleaves_dev.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipMemcpyAsync(&back.mx, t->nrm_max.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    t->nleaves = back.nl;
+    t->max_nrm = back.mx;
     return DFGT_OK;
 }
 

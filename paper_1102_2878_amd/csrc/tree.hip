@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
                                                    int32_t *end, int32_t *left, int32_t *right, int32_t *parent,
                                                    int32_t *sdim, double *scoord, int32_t *nleft,
                                                    const int32_t *__restrict__ rank, const int32_t *__restrict__ bsum,
-                                                   int nb, int32_t *boff) {
+                                                   int nb, int32_t *boff, int32_t *lmax) {
     __shared__ int warp_tot[16];
     __shared__ int carry_s;
     if (*done) return;
@@ -255,12 +255,14 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
     const int lb = lvs[2 * level], le = lvs[2 * level + 1];
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
+    int big = 0;  // the level's largest node
     for (int c0 = lb; c0 < le; c0 += blockDim.x) {
         const int node = c0 + threadIdx.x;
         int split = 0, sd = -1, nl = 0;
         double sc = 0.0;
         if (node < le) {
             const int b = begin[node], e = end[node], cnt = e - b;
+            big = max(big, cnt);
             if (node_split(lo_key, hi_key, node, d, cnt, leaf, &sd, &sc)) {
                 nl = grank(e) - grank(b);
                 split = (nl > 0 && nl < cnt) ? 1 : 0;
@@ -305,7 +307,12 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
         if (threadIdx.x == blockDim.x - 1) carry_s = rk + split;
         __syncthreads();
     }
+    for (int off = 32; off >= 1; off >>= 1) big = max(big, __shfl_xor(big, off, 64));
+    if (lane == 0) warp_tot[w] = big;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x / 64); ++k) big = max(big, warp_tot[k]);
+        lmax[level] = big;
         const int newc = 2 * carry_s;
         lvs[2 * level + 2] = le;
         lvs[2 * level + 3] = le + newc;
@@ -363,10 +370,11 @@ __global__ void k_decode_boxes(int m, int d, const long long *__restrict__ lo_ke
 
 // Root paths of the leaves: lpath[i][k] = k-th ancestor of leaf i (k = 0 is
 // the leaf), lplen[i] = path length.
-__global__ void k_leaf_paths(const int32_t *__restrict__ leaves, int nleaves, const int32_t *__restrict__ parent,
-                             int depth, int32_t *__restrict__ lpath, int32_t *__restrict__ lplen) {
+__global__ void k_leaf_paths(const int32_t *__restrict__ leaves, const int *__restrict__ nleaves,
+                             const int32_t *__restrict__ parent, int depth, int32_t *__restrict__ lpath,
+                             int32_t *__restrict__ lplen) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nleaves) return;
+    if (i >= *nleaves) return;
     int v = leaves[i], k = 0;
     while (v >= 0 && k < depth) {
         lpath[(size_t)i * depth + k++] = v;
@@ -403,7 +411,7 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
 
 // Scratch of the build, kept per host thread and reused across builds.
 struct BuildWs {
-    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft, counter, lvs;
+    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft, counter, lvs, lmax;
 };
 thread_local BuildWs g_build;
 
@@ -422,7 +430,8 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
                                      {&t->right, sizeof(int32_t) * cap},
                                      {&t->parent, sizeof(int32_t) * cap},
                                      {&t->sdim, sizeof(int32_t) * cap},
-                                     {&t->scoord, sizeof(double) * cap}}));
+                                     {&t->scoord, sizeof(double) * cap}},
+                         st, true));
     DFGT_TRY(perm_b.reserve(sizeof(int32_t) * n));
     DFGT_TRY(x_b.reserve(sizeof(double) * (size_t)n * d));
     DFGT_TRY(pnode_a.reserve(sizeof(int32_t) * n));
@@ -440,6 +449,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     // leaves fewer points on each side)
     const int max_levels = n + 1;
     DFGT_TRY(lvs_b.reserve(sizeof(int) * 2 * ((size_t)max_levels + 1)));
+    DFGT_TRY(w.lmax.reserve(sizeof(int) * ((size_t)max_levels + 1)));
 
     int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
     double *xa = t->x.as<double>(), *xb = x_b.as<double>();
@@ -464,6 +474,11 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     int level = 0, done = 0;
     int batch = 6;
     for (int q = n / std::max(leaf, 1); q > 1; q >>= 1) ++batch;
+    // a rebuild of the same shape (a benchmark loop, a sweep over data of one
+    // size) starts with the depth seen last time: usually one batch, one sync
+    static thread_local struct { int64_t n; int d, leaf, depth; } last{-1, 0, 0, 0};
+    if (last.n == n && last.d == d && last.leaf == leaf) batch = std::max(batch, last.depth + 2);
+    std::vector<int> hl;
     while (!done && level < max_levels) {
         const int stop = std::min(max_levels, level + batch);
         for (; level < stop; ++level) {
@@ -478,7 +493,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
                                t->end.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(),
                                t->parent.as<int32_t>(), t->sdim.as<int32_t>(), t->scoord.as<double>(),
                                nleft.as<int32_t>(), rank.as<int32_t>(), bsums.as<int32_t>(), gb,
-                               boff.as<int32_t>());
+                               boff.as<int32_t>(), w.lmax.as<int32_t>());
             hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kLB), 0, st, n, d, nin, pin, xin, flag.as<int32_t>(),
                                rank.as<int32_t>(), boff.as<int32_t>(), t->begin.as<int32_t>(),
                                nleft.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(), nout, pout,
@@ -486,7 +501,11 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
             DFGT_HIP(hipGetLastError());
         }
         int flags[2] = {0, 0};
+        hl.resize(2 * (size_t)(level + 1));
+        t->level_max.resize((size_t)level);
         DFGT_HIP(hipMemcpyAsync(flags, cnt_d, sizeof(flags), hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipMemcpyAsync(hl.data(), lvs, sizeof(int) * hl.size(), hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipMemcpyAsync(t->level_max.data(), w.lmax.p, sizeof(int) * level, hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
         if (flags[1]) {
             set_error("dfgt_build_tree: points contain a non-finite coordinate");
@@ -503,13 +522,13 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
         set_error("dfgt_build_tree: level limit reached (internal error)");
         return DFGT_EHIP;
     }
-    // level bounds: levels 0 .. K, K the first level without a split
-    std::vector<int> hl(2 * (size_t)(level + 1));
-    DFGT_HIP(hipMemcpy(hl.data(), lvs, sizeof(int) * hl.size(), hipMemcpyDeviceToHost));
+    // level bounds (read with the last batch's flags): levels 0 .. K, K the
+    // first level without a split
     int K = 0;
     while (K + 1 <= level && hl[2 * (size_t)K + 3] > hl[2 * (size_t)K + 1]) ++K;
     t->level_start.assign(1, 0);
     for (int k = 0; k <= K; ++k) t->level_start.push_back(hl[2 * (size_t)k + 1]);
+    t->level_max.resize((size_t)K + 1);
     const int le = hl[2 * (size_t)K + 1];
     if (K & 1) {
         pa = perm_b.as<int32_t>();
@@ -518,6 +537,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
     const int m = le;
     t->m = m;
     t->depth = (int)t->level_start.size() - 1;
+    last = {n, d, leaf, t->depth};
     // the final permutation / points live in pa / xa
     if (pa != t->perm.as<int32_t>()) {
         DFGT_HIP(hipMemcpyAsync(t->perm.p, pa, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
@@ -531,18 +551,20 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
                                      {&t->ctr, sizeof(double) * (size_t)m * d},
                                      {&t->leaves, sizeof(int32_t) * m},
                                      {&t->lpath, sizeof(int32_t) * (size_t)m * pstride},
-                                     {&t->lplen, sizeof(int32_t) * (size_t)m}}));
+                                     {&t->lplen, sizeof(int32_t) * (size_t)m},
+                                     {&t->nleaves_dev, sizeof(int)}},
+                         st, true));
     hipLaunchKernelGGL(k_decode_boxes, dim3((m * d + 255) / 256), dim3(256), 0, st, m, d, lo_key.as<long long>(),
                        hi_key.as<long long>(), t->lo.as<double>(), t->hi.as<double>(), t->ctr.as<double>());
+    int *nl_dev = t->nleaves_dev.as<int>();
     hipLaunchKernelGGL(k_collect_leaves, dim3(1), dim3(1024), 0, st, m, t->left.as<int32_t>(),
-                       t->leaves.as<int32_t>(), cnt_d + 2);
+                       t->leaves.as<int32_t>(), nl_dev);
     DFGT_HIP(hipGetLastError());
-    int nl = 0;
-    DFGT_HIP(hipMemcpyAsync(&nl, cnt_d + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipStreamSynchronize(st));
-    t->nleaves = nl;
+    // the leaf count stays on the device (at most (m + 1) / 2 leaves); the
+    // moments pass reads it back with its own results
     if (pstride > 0) {
-        hipLaunchKernelGGL(k_leaf_paths, dim3((nl + 255) / 256), dim3(256), 0, st, t->leaves.as<int32_t>(), nl,
+        const int ml = (m + 1) / 2;
+        hipLaunchKernelGGL(k_leaf_paths, dim3((ml + 255) / 256), dim3(256), 0, st, t->leaves.as<int32_t>(), nl_dev,
                            t->parent.as<int32_t>(), t->depth, t->lpath.as<int32_t>(), t->lplen.as<int32_t>());
         DFGT_HIP(hipGetLastError());
     }
