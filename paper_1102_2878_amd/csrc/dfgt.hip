@@ -1079,6 +1079,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     if (*overflow) return;
     __shared__ double cs_s;
     __shared__ int path[kMaxDepth];
+    __shared__ double cvl[kMaxDepth];
     __shared__ unsigned char lfl[kMaxDepth];
     __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg], ccnt[kMaxDepth + 1];
     __shared__ int nsg_s, nops_s, ntot_s, nops1_s, st_phase, st_gi, st_pi;
@@ -1135,6 +1136,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         const int v = Q.lpath[(size_t)li * Q.depth + k];
         path[k] = v;
         lfl[k] = lflag[jb.noff + v];
+        cvl[k] = cval[jb.noff + v];
         mine |= lfl[k];
     }
     for (int i = tid; i < ns; i += nthr) spow[i] = powi(s, i);
@@ -1143,7 +1145,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     // translating a constant expansion leaves it unchanged
     if (tid == 0) {
         double c = 0.0;
-        for (int k = plen - 1; k >= 0; --k) c += cval[jb.noff + path[k]];
+        for (int k = plen - 1; k >= 0; --k) c += cvl[k];
         cs_s = c;
     }
     __syncthreads();
@@ -1207,28 +1209,55 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     // the root down, each chain in its own order.  One thread per chain counts
     // and then copies its groups; if more than kMaxSeg groups result they are
     // flattened serially in batches instead.
+    // One walk: chain ch records its groups in its own region of the segment
+    // tables (kMaxSeg / (plen + 1) entries) while they fit; the regions are
+    // then packed in chain order.  A chain longer than its region sends the
+    // block down the two-walk path (count, then copy) below.
+    const int rsz = kMaxSeg / (plen + 1);
+    int longch = 0;
     for (int ch = tid; ch <= plen; ch += nthr) {
         int c = 0;
-        if (ch == 0) {
-            c = 0;  // exhaustive sums come from k_etile / k_emfma
-        } else {
-            for (int gi = headF[(size_t)jb.noff + path[plen - ch]]; gi >= 0; gi = fgrp[gi].next) ++c;
+        if (ch > 0) {  // chain 0 (exhaustive sums) comes from k_etile / k_emfma
+            for (int gi = headF[(size_t)jb.noff + path[plen - ch]]; gi >= 0;) {
+                const Group g = fgrp[gi];
+                if (c < rsz) {
+                    segS[ch * rsz + c] = g.start;
+                    segE[ch * rsz + c] = g.count;
+                }
+                ++c;
+                gi = g.next;
+            }
         }
         ccnt[ch] = c;
+        longch |= c > rsz ? 1 : 0;
     }
-    __syncthreads();
+    const bool packed = !__syncthreads_or(longch);
     if (tid == 0) {
         int t = 0;
         for (int k = 0; k <= plen; ++k) {
             const int c = ccnt[k];
+            if (packed)
+                for (int j = 0; j < c; ++j) {  // forward in-place packing: t <= k * rsz + j
+                    segT[t + j] = 1;
+                    segS[t + j] = segS[k * rsz + j];
+                    segE[t + j] = segE[k * rsz + j];
+                }
             ccnt[k] = t;
             t += c;
+        }
+        if (packed) {
+            int cum = 0;
+            for (int k = 0; k < t; ++k) {
+                cum += segE[k];
+                segE[k] = cum;
+            }
+            nops1_s = cum;
         }
         ntot_s = t;
     }
     __syncthreads();
     const bool single = ntot_s <= kMaxSeg;
-    if (single) {
+    if (single && !packed) {
         for (int ch = tid; ch <= plen; ch += nthr) {
             int o = ccnt[ch];
             if (ch == 0) {
