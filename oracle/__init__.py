@@ -41,6 +41,8 @@ def lib():
         L.oracle_naive_kde_rows.argtypes = [_DP, _I64P, i64, _DP, i64, i32, dbl, _DP]
         L.oracle_naive_kde_grad.argtypes = [_DP, i64, _DP, i64, i32, dbl, C.c_void_p, C.c_void_p,
                                             C.c_void_p]
+        L.oracle_naive_kde_weighted.argtypes = [_DP, i64, _DP, _DP, i64, i32, dbl, C.c_void_p, C.c_void_p,
+                                                C.c_void_p]
         L.oracle_build_kdtree.argtypes = [_DP, i64, i32, i32, i64, _I32P, _DP, _DP, _I64P, _I64P,
                                           _I32P, _I32P, _I32P, _DP, C.POINTER(i64)]
         L.oracle_mi_to_pos.argtypes = [C.POINTER(C.c_int), i32, i32]
@@ -124,6 +126,22 @@ def naive_kde_grad(q, r, h):
     gq = np.empty((n, d))
     _check(lib().oracle_naive_kde_grad(q, n, r, r.shape[0], d, float(h), _ptr(G), _ptr(gh), _ptr(gq)),
            "naive_kde_grad")
+    return G, gh, gq
+
+
+def naive_kde_weighted(q, r, w, h):
+    """(G_w, dG_w/dh, dG_w/dq) of the exact weighted sum G_w(q) = sum_j w_j K(q, r_j)
+    (the sums of Section 1 with a weight per reference point)."""
+    q, r = _pts(q), _pts(r)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if w.shape != (r.shape[0],):
+        raise ValueError("one weight per reference point")
+    n, d = q.shape
+    G = np.empty(n)
+    gh = np.empty(n)
+    gq = np.empty((n, d))
+    _check(lib().oracle_naive_kde_weighted(q, n, r, w, r.shape[0], d, float(h), _ptr(G), _ptr(gh), _ptr(gq)),
+           "naive_kde_weighted")
     return G, gh, gq
 
 

@@ -123,6 +123,47 @@ int oracle_naive_kde_grad(const double *q, int64_t nq, const double *r, int64_t 
     return 0;
 }
 
+/*
+ * Weighted kernel sums (the sums of Section 1 with a weight per reference
+ * point, as a weighted density estimate takes them), computed exactly:
+ *   G_w(q)    = sum_j w_j K_j,  K_j = exp(-||q - r_j||^2 / (2 h^2))
+ *   dG_w/dh   = h^-3 sum_j w_j K_j ||q - r_j||^2
+ *   dG_w/dq   = -h^-2 sum_j w_j K_j (q - r_j)
+ * The value sum is Neumaier-compensated.  Any output pointer may be NULL.
+ */
+int oracle_naive_kde_weighted(const double *q, int64_t nq, const double *r, const double *w, int64_t nr,
+                              int d, double h, double *G, double *dGdh, double *dGdq)
+{
+    if (nq < 0 || nr < 0 || d < 1 || d > OR_MAXD || !(h > 0.0)) return 1;
+    const double inv2h2 = 1.0 / (2.0 * h * h);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nq; ++i) {
+        const double *qi = q + i * d;
+        double sum = 0.0, comp = 0.0, gh = 0.0, gq[OR_MAXD];
+        for (int k = 0; k < d; ++k) gq[k] = 0.0;
+        for (int64_t j = 0; j < nr; ++j) {
+            const double *rj = r + j * d;
+            double d2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                double t = qi[k] - rj[k];
+                d2 += t * t;
+            }
+            const double v = w[j] * exp(-d2 * inv2h2);
+            double t = sum + v;
+            if (fabs(sum) >= fabs(v)) comp += (sum - t) + v;
+            else comp += (v - t) + sum;
+            sum = t;
+            gh += v * d2;
+            for (int k = 0; k < d; ++k) gq[k] += v * (qi[k] - rj[k]);
+        }
+        if (G) G[i] = sum + comp;
+        if (dGdh) dGdh[i] = gh / (h * h * h);
+        if (dGdq)
+            for (int k = 0; k < d; ++k) dGdq[i * d + k] = -gq[k] / (h * h);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Section 2.1, Alg. BuildKdTree: recursive mid-point kd-tree.                */
 /*   box     b[d].l = min, b[d].u = max over the node's points (A1: the text   */
