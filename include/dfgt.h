@@ -138,6 +138,26 @@ const char *dfgt_version(void);
 dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const dfgt_options *opt,
                             void *stream, dfgt_tree *out);
 
+/*
+ * Builds a reference tree whose points carry weights, for the weighted sums
+ * G_w(q) = sum_j w_j exp(-|q - r_j|^2 / 2h^2) (the kernel sums of Section 1
+ * with a weight per reference point; the moments of Section 3.3 take w_j as
+ * a factor of each point's term).  The per-query guarantee is unchanged:
+ * |G~_w(q) - G_w(q)| <= eps G_w(q), the bounds of Sections 3.4-3.7 taken with
+ * the node's weight W(R) = sum_{j in R} w_j in place of its point count.
+ *   w_dev    n float64 weights in the order of pts_dev, device memory, read
+ *            during the call only; every w_j >= 0 and finite, not all zero.
+ * Other arguments as dfgt_build_tree.  A weighted tree is a reference tree
+ * for dfgt_gauss_sum, dfgt_gauss_sum_grad, dfgt_gauss_backward, the batches
+ * and dfgt_kde_density (which then divides by W(R) instead of N_R); as a
+ * query tree its weights are ignored.  The cross-validation calls
+ * (dfgt_lscv_score, dfgt_lcv_score, dfgt_lscv_optimize) reject it.
+ * Errors: those of dfgt_build_tree; w_dev NULL, a negative or non-finite
+ * weight, or all weights zero -> DFGT_EINVAL.  Synchronises the stream.
+ */
+dfgt_status dfgt_build_tree_weighted(const double *pts_dev, const double *w_dev, int64_t n, int32_t d,
+                                     const dfgt_options *opt, void *stream, dfgt_tree *out);
+
 /* Frees a tree handle (NULL is allowed).  Work already queued on the stream the
  * tree was built on may still use it: its device memory is kept by the library
  * and handed to a later build only after that stream reaches this point.  Work
@@ -259,11 +279,10 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
                             const dfgt_options *opt, double *cv_host, double *dcv_host, dfgt_stats *stats,
                             void *stream);
 
-/* One problem of a batch: the sums over R for the queries of Q at n_h
- * bandwidths, into G_dev (n_h x NQ float64, caller-allocated, caller order). */
 /*
  * Kernel density estimate of Section 1: p[k][i] = G~(q_i, R; h_k) / (N_R V_k),
- * V_k = (2 pi h_k^2)^(D/2) the integral of the Gaussian kernel.  Same
+ * V_k = (2 pi h_k^2)^(D/2) the integral of the Gaussian kernel (for a weighted
+ * R: G~_w / (W(R) V_k), W(R) the sum of its weights).  Same
  * arguments, layout ([n_h][N_Q], user query order, FP64, caller-owned device
  * memory) and per-query relative error bound eps as dfgt_gauss_sum.
  */
@@ -306,6 +325,8 @@ dfgt_status dfgt_lscv_optimize(dfgt_tree R, double h_lo, double h_hi, double eps
                                double rel_tol, const dfgt_options *opt, double *h_star, double *cv_star,
                                int32_t *n_evals, void *stream);
 
+/* One problem of a batch: the sums over R for the queries of Q at n_h
+ * bandwidths, into G_dev (n_h x NQ float64, caller-allocated, caller order). */
 typedef struct dfgt_problem {
     dfgt_tree Q;
     dfgt_tree R;          /* Q == R: the monochromatic case, self terms included */

@@ -1,5 +1,6 @@
 // C ABI of libdfgt: argument validation, error strings, handle ownership.
 // Every entry point catches C++ exceptions so none crosses the ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -119,15 +120,105 @@ dfgt_status pool_get(DevBuf &b, size_t need, hipStream_t st) {
 
 }  // namespace dfgt
 
+namespace dfgt {
+namespace {
+// One pass over the weights: a block-wide fold, then one atomic per block and
+// quantity (same-address device atomics serialise).  flag |= 1 for a negative
+// or non-finite weight; *mx = the largest weight as its bit pattern (the order
+// of non-negative doubles is that of their bit patterns).
+__global__ __launch_bounds__(256) void k_check_weights(const double *__restrict__ w, long long n, int *flag,
+                                                       unsigned long long *mx) {
+    __shared__ int fs[4];
+    __shared__ unsigned long long ms[4];
+    int f = 0;
+    unsigned long long m = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double v = w[i];
+        if (!(v >= 0.0) || !isfinite(v)) f = 1;
+        else if (v > 0.0) m = max(m, (unsigned long long)__double_as_longlong(v));  // not -0.0's pattern
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        f |= __shfl_xor(f, off, 64);
+        m = max(m, (unsigned long long)__shfl_xor((long long)m, off, 64));
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        fs[wv] = f;
+        ms[wv] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 4; ++k) {
+            f |= fs[k];
+            m = max(m, ms[k]);
+        }
+        if (f) atomicOr(flag, f);
+        if (m) atomicMax(mx, m);
+    }
+}
+}  // namespace
+
+// *bad: 0 fine, 1 a negative or non-finite weight, 2 all weights zero; *wmax
+// the largest weight.
+static dfgt_status check_weights(const double *w, int64_t n, hipStream_t st, int *bad, double *wmax) {
+    struct Out {
+        int flag;
+        int pad;
+        unsigned long long mx;
+    };
+    static thread_local DevBuf buf;
+    static thread_local Out back;
+    DFGT_TRY(buf.reserve(sizeof(Out)));
+    Out *o = buf.as<Out>();
+    DFGT_HIP(hipMemsetAsync(o, 0, sizeof(Out), st));
+    const long long nb = std::min<long long>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_check_weights, dim3((unsigned)nb), dim3(256), 0, st, w, (long long)n, &o->flag, &o->mx);
+    DFGT_HIP(hipGetLastError());
+    DFGT_HIP(hipMemcpyAsync(&back, o, sizeof(Out), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipStreamSynchronize(st));
+    double mxv;
+    std::memcpy(&mxv, &back.mx, sizeof(double));
+    *wmax = mxv;
+    *bad = back.flag ? 1 : (back.mx == 0 ? 2 : 0);
+    return DFGT_OK;
+}
+
+}  // namespace dfgt
+
 extern "C" {
 
 const char *dfgt_last_error(void) { return g_err.c_str(); }
 
 const char *dfgt_version(void) { return "dfgt-mi355x 0.1 (gfx950)"; }
 
+static dfgt_status build_common(const double *pts_dev, const double *w_dev, double wmax, int64_t n, int32_t d,
+                                const dfgt_options *opt, void *stream, dfgt_tree *out);
+
 dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const dfgt_options *opt, void *stream,
                             dfgt_tree *out) {
     DFGT_GUARD_BEGIN
+    return build_common(pts_dev, nullptr, 1.0, n, d, opt, stream, out);
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_build_tree_weighted(const double *pts_dev, const double *w_dev, int64_t n, int32_t d,
+                                     const dfgt_options *opt, void *stream, dfgt_tree *out) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(out != nullptr, "dfgt_build_tree_weighted: out is NULL");
+    *out = nullptr;
+    DFGT_REQUIRE(w_dev != nullptr, "dfgt_build_tree_weighted: w_dev is NULL");
+    DFGT_REQUIRE(n >= 1 && n < (int64_t(1) << 30), "dfgt_build_tree_weighted: n must be in [1, 2^30)");
+    int bad = 0;
+    double wmax = 0.0;
+    DFGT_TRY(check_weights(w_dev, n, (hipStream_t)stream, &bad, &wmax));
+    DFGT_REQUIRE(bad != 1, "dfgt_build_tree_weighted: a weight is negative or not finite");
+    DFGT_REQUIRE(bad != 2, "dfgt_build_tree_weighted: all weights are zero");
+    return build_common(pts_dev, w_dev, wmax, n, d, opt, stream, out);
+    DFGT_GUARD_END
+}
+
+static dfgt_status build_common(const double *pts_dev, const double *w_dev, double wmax, int64_t n, int32_t d,
+                                const dfgt_options *opt, void *stream, dfgt_tree *out) {
     DFGT_REQUIRE(out != nullptr, "dfgt_build_tree: out is NULL");
     *out = nullptr;
     DFGT_REQUIRE(pts_dev != nullptr, "dfgt_build_tree: pts_dev is NULL");
@@ -152,9 +243,11 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
     t->P = (int)P;
     t->precision = o.precision;
     t->force = o.force_method;
+    t->weighted = w_dev != nullptr;
+    t->wscale = w_dev ? wmax : 1.0;
     hipStream_t st = (hipStream_t)stream;
     t->stream = st;
-    dfgt_status s = build_tree_device(t, pts_dev, st);
+    dfgt_status s = build_tree_device(t, pts_dev, w_dev, st);
     if (s == DFGT_OK) s = compute_moments(t, st);
     if (s == DFGT_OK) {
         DevTree v{};
@@ -180,6 +273,7 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
         v.nrm = t->nrm.as<double>();
         v.lpath = t->lpath.as<int32_t>();
         v.lplen = t->lplen.as<int32_t>();
+        v.w = t->w.as<double>();
         t->host_view = v;
         {  // the view's storage was carved out with the moments
             if (hipMemcpyAsync(t->view.p, &v, sizeof(DevTree), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -195,7 +289,6 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
     }
     *out = t;
     return DFGT_OK;
-    DFGT_GUARD_END
 }
 
 dfgt_status dfgt_tree_free(dfgt_tree t) {
@@ -359,6 +452,7 @@ dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, doub
     DFGT_GUARD_BEGIN
     DFGT_REQUIRE(R && cv_host, "dfgt_lscv_score: NULL argument");
     DFGT_REQUIRE(R->n >= 2, "dfgt_lscv_score: needs at least two points");
+    DFGT_REQUIRE(!R->weighted, "dfgt_lscv_score: cross-validation is defined for unweighted points");
     DFGT_REQUIRE(variant == 0 || variant == 1, "dfgt_lscv_score: variant must be 0 or 1");
     DFGT_TRY(check_pair(R, R, eps, "dfgt_lscv_score"));
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_lscv_score"));
@@ -391,6 +485,7 @@ dfgt_status dfgt_lcv_score(dfgt_tree R, const double *h_host, int32_t n_h, doubl
     DFGT_GUARD_BEGIN
     DFGT_REQUIRE(R && cv_host, "dfgt_lcv_score: NULL argument");
     DFGT_REQUIRE(R->n >= 2, "dfgt_lcv_score: needs at least two points");
+    DFGT_REQUIRE(!R->weighted, "dfgt_lcv_score: cross-validation is defined for unweighted points");
     DFGT_TRY(check_pair(R, R, eps, "dfgt_lcv_score"));
     DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_lcv_score"));
     DFGT_REQUIRE(n_h <= 32767, "dfgt_lcv_score: n_h must be <= 32767");
@@ -408,6 +503,7 @@ dfgt_status dfgt_lscv_optimize(dfgt_tree R, double h_lo, double h_hi, double eps
     DFGT_GUARD_BEGIN
     DFGT_REQUIRE(R && h_star, "dfgt_lscv_optimize: NULL argument");
     DFGT_REQUIRE(R->n >= 2, "dfgt_lscv_optimize: needs at least two points");
+    DFGT_REQUIRE(!R->weighted, "dfgt_lscv_optimize: cross-validation is defined for unweighted points");
     DFGT_REQUIRE(variant == 0 || variant == 1, "dfgt_lscv_optimize: variant must be 0 or 1");
     DFGT_REQUIRE(std::isfinite(h_lo) && std::isfinite(h_hi) && h_lo > 0.0 && h_hi > h_lo,
                  "dfgt_lscv_optimize: need 0 < h_lo < h_hi (finite)");

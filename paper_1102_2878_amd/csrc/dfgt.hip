@@ -47,7 +47,9 @@ enum { METH_E = 0, METH_F = 1, METH_D = 2, METH_T = 3 };
 struct Job {
     double h, s, inv2h2, sig;  // s = 1/(sqrt2 h); sig = sqrt(log2 e) s
     double eps_eff;            // eps minus the rounding budget of the exhaustive sums
-    double nR;                 // |R_total|
+    double nR;                 // W(R_total): the total reference weight (|R_total| unweighted), in stored units
+    double cntR;               // |R_total|
+    double wscale;             // stored weights are w / wscale (1 unweighted); outputs are multiplied back
     double prior;              // a known lower bound on every G(q) (1 when Q = R: the self term)
     int qt, rt;                // indices into the tree table
     long long qoff;            // offset of this job's per-query arrays
@@ -205,6 +207,9 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // ChooseBestMethod (Section 3.8) with costs c_F = D N_Q p_F^D, c_D = D N_R p_D^D,
 // c_T = D p_T^{2D}, c_E = D N_Q N_R; ties F, D, T, E.  T may also be chosen at
 // order 1 through the centroid bound |R| max(K(d^l)-K(d_c), K(d_c)-K(d^u)).
+// The error bounds take wR, the weight of R (its point count |R| when the
+// points carry no weights: each point's error is scaled by its weight); the
+// costs take the point count nR.
 // When that bound holds c_T = D, the least any method can cost; only F at
 // order 1 with N_Q = 1 or D at order 1 with N_R = 1 can tie it (and win the
 // tie), so the order searches are skipped.  ku = K(d^u).
@@ -214,22 +219,22 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // D and T use one order more than the value bound needs (at most p_max) and
 // the centroid form is not used; F is unchanged (its derivative series is the
 // far-field series of the derivative kernel, one Hermite index higher).
-__device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double tau,
-                      int pmax, int D, int force, int gr, double cost_e, int *order, double *kc_out) {
+__device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double wR,
+                      double tau, int pmax, int D, int force, int gr, double cost_e, int *order, double *kc_out) {
     if (force == DFGT_FORCE_EXACT) {
         *order = 0;
         return METH_E;
     }
     const double kl = exp(-g.sl * inv2h2), kc = exp(-g.sc * inv2h2);
     *kc_out = kc;
-    const double cb = nR * (fmax(kl - kc, kc - ku) + 1e-15 * kl);
+    const double cb = wR * (fmax(kl - kc, kc - ku) + 1e-15 * kl);
     const bool centroid = !gr && cb <= tau;
     if (centroid && force == DFGT_FORCE_NONE) {
-        if (nQ == 1.0 && order_far(g.wR / (2.0 * h), nR, tau, 1, D) == 1) {
+        if (nQ == 1.0 && order_far(g.wR / (2.0 * h), wR, tau, 1, D) == 1) {
             *order = 1;
             return METH_F;
         }
-        if (nR == 1.0 && order_far(g.wQ / (2.0 * h), nR, tau, 1, D) == 1) {
+        if (nR == 1.0 && order_far(g.wQ / (2.0 * h), wR, tau, 1, D) == 1) {
             *order = 1;
             return METH_D;
         }
@@ -237,9 +242,9 @@ __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, dou
         return METH_T;
     }
     const int pl = gr ? pmax - 1 : pmax;  // largest value order a local expansion may need
-    int pF = order_far(g.wR / (2.0 * h), nR, tau, pmax, D);
-    int pD = pl > 0 ? order_far(g.wQ / (2.0 * h), nR, tau, pl, D) : 0;
-    int pT = pl > 0 ? order_f2l(fmax(g.wQ, g.wR) / (2.0 * h), nR, tau, pl, D) : 0;
+    int pF = order_far(g.wR / (2.0 * h), wR, tau, pmax, D);
+    int pD = pl > 0 ? order_far(g.wQ / (2.0 * h), wR, tau, pl, D) : 0;
+    int pT = pl > 0 ? order_f2l(fmax(g.wQ, g.wR) / (2.0 * h), wR, tau, pl, D) : 0;
     if (gr) {
         pD = pD ? pD + 1 : 0;
         pT = pT ? pT + 1 : 0;
@@ -339,24 +344,26 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     // below; pairs beyond reload it.
     double sl = 0.0;
     int r0 = -1, m0 = METH_E, ord0 = 0, left0 = -1, right0 = -1;
-    double nR0 = 0.0, ku0 = 0.0;
+    double nR0 = 0.0, wR0 = 0.0, ku0 = 0.0;
     PairGeom g0{0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = lane; i < sg.count; i += 64) {
         const int r = pairs[sg.start + i];
         const PairGeom g = pair_geom(Q, q, R, r);
         const double ku = exp(-g.su * jb.inv2h2);
         const double nR = (double)(R.end[r] - R.begin[r]);
+        const double wR = R.w ? R.mu[(size_t)r * R.P] : nR;
         if (i < 64) {
             r0 = r;
             g0 = g;
             ku0 = ku;
             nR0 = nR;
+            wR0 = wR;
             left0 = R.left[r];
             right0 = R.right[r];
         } else {
             kus[sg.start + i] = ku;  // reused by the decisions below
         }
-        sl += nR * ku;
+        sl += wR * ku;
     }
     sl = wave_sum(sl);
     const double gl = fmax((sg.gl + sl) * (1.0 - 1e-12), jb.prior);
@@ -369,20 +376,21 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         const int r = first ? r0 : pairs[sg.start + i];
         const PairGeom g = first ? g0 : pair_geom(Q, q, R, r);
         const double nR = first ? nR0 : (double)(R.end[r] - R.begin[r]);
-        const double tau = jb.eps_eff * nR * gl / jb.nR;
+        const double wR = first ? wR0 : (R.w ? R.mu[(size_t)r * R.P] : nR);
+        const double tau = jb.eps_eff * wR * gl / jb.nR;
         const double ku = first ? ku0 : kus[sg.start + i];
         int ord = 0;
         double kc = 0.0;
-        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, tau, pmax, D, force, gr, jb.cost_e, &ord, &kc);
+        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, wR, tau, pmax, D, force, gr, jb.cost_e, &ord, &kc);
         const bool rleaf = (first ? left0 : R.left[r]) < 0;
         if (m != METH_E) {
-            plo += nR * ku;
+            plo += wR * ku;
             if (m == METH_F) ++cF;
             else if (m == METH_T && ord == 1) {
                 // order-1 far-to-local translation (the centroid form): its only
-                // term is L_0 += mu_0 e^{-|t0|^2} = |R| K(|Q.c - R.c|), a scalar
+                // term is L_0 += mu_0 e^{-|t0|^2} = W(R) K(|Q.c - R.c|), a scalar
                 // added to Q's constant term right here (no op)
-                ccon += nR * kc;
+                ccon += wR * kc;
                 ++nC;
             } else {
                 // a D op is emitted as one op per chunk of <= 64 reference points
@@ -503,10 +511,12 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     if (lane == 0) {
         bool over = (tE && !okE) || (tF && !okF) || (tL && !okL) || (npair_out && !okN);
         if (okE) {
-            // underflow guard: FP32 exp2 flushes terms below 2^-126; keep that
-            // absolute error below 2^-26 G by computing tiny sums in FP64.
+            // underflow guard: FP32 exp2 flushes terms below 2^-126 (and the
+            // weighted terms w e, w <= 1 in stored units, likewise); keep that
+            // absolute error, at most |R_total| 2^-126, below 2^-26 G by
+            // computing tiny sums in FP64.
             const double glb = jb.mono ? fmax(gl, 1.0) : gl;  // q is one of the references: G(q) >= 1
-            const int fp64 = glb < jb.nR * 0x1p-100 ? 1 : 0;
+            const int fp64 = glb < jb.cntR * 0x1p-100 ? 1 : 0;
             o.egrp[gE] = Group{q, sg.job, ebase, tE, fp64, prevE};
             if (fp64) atomicAdd(&o.cnt[C_EF64 * CP], 1);
         }
@@ -717,8 +727,8 @@ __device__ void wave_local_op(const DevTree &R, int r, int p, int m, int rb, int
                 hermite_polys(t, p + (GR ? 1 : 0), row + k * hs);
                 if (GR) Tx[lane * d + k] = t;
             }
-            const double e = tt > 745.0 ? 0.0 : exp(-tt);
-            for (int b = 0; b < p + (GR ? 1 : 0); ++b) row[b] *= e;  // the exponential rides on dimension 0
+            const double e = (tt > 745.0 ? 0.0 : exp(-tt)) * (R.w ? R.w[x0 + lane] : 1.0);
+            for (int b = 0; b < p + (GR ? 1 : 0); ++b) row[b] *= e;  // the weighted exponential rides on dimension 0
         }
         wave_sync();
         for (int b = lane; b < P; b += 64) {
@@ -940,7 +950,8 @@ __global__ __launch_bounds__(kLocBlock) void k_local_big(const DevTree *__restri
                             tt += t * t;
                             hermite_polys(t, p, row + k * pmax);
                         }
-                        const double e = tt > 745.0 ? 0.0 : exp(-tt);
+                        const double e =
+                            (tt > 745.0 ? 0.0 : exp(-tt)) * (R.w ? R.w[x0 + threadIdx.x] : 1.0);
                         for (int b = 0; b < p; ++b) row[b] *= e;
                     }
                     __syncthreads();
@@ -1405,8 +1416,17 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             }
             double gl = 0.0, xl = 0.0;
             if (any) {
-                double y[kMaxD];
-                for (int k = 0; k < d; ++k) y[k] = (qg[k] - lc[k]) * s;
+                // powers y_k^b (b < p_max) of the scaled offset from the leaf centre,
+                // in this thread's Hermite rows (free here), the same products as powi
+                double *yp = Hq;
+                for (int k = 0; k < d; ++k) {
+                    const double yk = (qg[k] - lc[k]) * s;
+                    double v = 1.0;
+                    for (int b = 0; b < pmax; ++b) {
+                        yp[k * hs + b] = v;
+                        v *= yk;
+                    }
+                }
                 for (int i = 0; i < P; ++i) {
                     const double a = acc[i];
                     const double aB = GR ? acc[P + i] : 0.0;
@@ -1414,7 +1434,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                     const unsigned long long ad = dg[i];
                     double prod = a, prodB = aB;
                     for (int k = 0; k < d; ++k) {
-                        const double yk = powi(y[k], dig_at(ad, k));
+                        const double yk = yp[k * hs + dig_at(ad, k)];
                         prod *= yk;
                         if (GR) prodB *= yk;
                     }
@@ -1426,7 +1446,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                 const int bc = dig_at(ad, c);
                                 if (bc == 0) continue;
                                 double dv = a * (double)bc;
-                                for (int k = 0; k < d; ++k) dv *= powi(y[k], dig_at(ad, k) - (k == c ? 1 : 0));
+                                for (int k = 0; k < d; ++k) dv *= yp[k * hs + dig_at(ad, k) - (k == c ? 1 : 0)];
                                 gq[c] += dv;
                             }
                     }
@@ -1435,15 +1455,16 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             const int dst = Q.perm[qpos];
             const size_t ei = (size_t)jb.qoff + qpos;
             if (extE) gsum += extE[ei];
-            jb.out[dst] = (gl + csum) + gsum;
+            const double ws = jb.wscale;
+            jb.out[dst] = ((gl + csum) + gsum) * ws;
             if (GR) {
                 if (extE) {
                     xsum += extX[ei];
                     for (int c = 0; c < d; ++c) gq[c] += extY[ei * d + c];
                 }
-                if (jb.outH) jb.outH[dst] = -(xl + xsum) / jb.h;
+                if (jb.outH) jb.outH[dst] = -(xl + xsum) / jb.h * ws;
                 if (jb.outQ)
-                    for (int c = 0; c < d; ++c) jb.outQ[(size_t)dst * d + c] = s * gq[c];
+                    for (int c = 0; c < d; ++c) jb.outQ[(size_t)dst * d + c] = s * gq[c] * ws;
             }
         }
         __syncthreads();
@@ -1557,10 +1578,12 @@ __device__ __forceinline__ void etile_fast(const double *__restrict__ st, const 
 }
 
 // One lane's query against the staged points g, g + ng, ... < cnt (runtime d):
-// mixed pairs (F64 = false) or FP64 pairs (t in sig units, e = 2^-t).
+// mixed pairs (F64 = false) or FP64 pairs (t in sig units, e = 2^-t), each
+// term times the staged point weight sw[j] (sw null: weight 1).
 template <bool GR, bool F64>
-__device__ __forceinline__ void etile_strided(const double *__restrict__ st, int g, int ng, int cnt, int d,
-                                              const double *qs, double &acc, double &xacc, double *yacc) {
+__device__ __forceinline__ void etile_strided(const double *__restrict__ st, const double *__restrict__ sw, int g,
+                                              int ng, int cnt, int d, const double *qs, double &acc, double &xacc,
+                                              double *yacc) {
     for (int t0 = g; t0 < cnt; t0 += 64 * ng) {
         const int te = min(cnt, t0 + 64 * ng);  // <= 64 points of this lane: one FP32 partial
         float ps = 0.0f, pt = 0.0f, py[kMaxD];
@@ -1574,7 +1597,7 @@ __device__ __forceinline__ void etile_strided(const double *__restrict__ st, int
                 t = fma(dd[c], dd[c], t);
             }
             if (F64) {
-                const double e = exp(-t * kLn2);
+                const double e = exp(-t * kLn2) * (sw ? sw[j] : 1.0);
                 acc += e;
                 if (GR) {
                     xacc = fma(-2.0 * kLn2 * t, e, xacc);
@@ -1582,7 +1605,7 @@ __device__ __forceinline__ void etile_strided(const double *__restrict__ st, int
                 }
             } else {
                 const float tf = (float)t;
-                const float e = __builtin_amdgcn_exp2f(-tf);
+                const float e = __builtin_amdgcn_exp2f(-tf) * (sw ? (float)sw[j] : 1.0f);
                 ps += e;
                 if (GR) {
                     pt = fmaf(tf, e, pt);
@@ -1616,6 +1639,7 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
     __shared__ int wsum[4], nops_s, take_s;
     __shared__ double stage[4][kEWaveStage];
     __shared__ float pwt[4][kSP];
+    __shared__ double swt[4][PAD ? 1 : 256];  // point weights of the strided form
     __shared__ double red[4][64 * QPT];
     if (*overflow) return;
     const bool all64 = precision == DFGT_PREC_FP64;
@@ -1667,6 +1691,7 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
     }
     double *st = stage[wv];
     float *pw = pwt[wv];
+    double *sw = swt[wv];
     for (int qg = 0; qg < nq; qg += 64 * QPT) {
         const int nqg = min(64 * QPT, nq - qg);
         const int need = (nqg + QPT - 1) / QPT;     // lanes per group
@@ -1723,7 +1748,8 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
                         while (oCum[op] <= p) ++op;
                         const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
                         for (int c = 0; c < d; ++c) st[i * d + c] = R.x[(size_t)row * d + c] * jb.sig;
-                        if constexpr (PAD) pw[i] = 1.0f;
+                        if constexpr (PAD) pw[i] = R.w ? (float)R.w[row] : 1.0f;
+                        else if (R.w) sw[i] = R.w[row];
                     }
                 }
                 if constexpr (PAD) {
@@ -1737,7 +1763,7 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
                     etile_fast<DT, GR>(st, pw, g, NG, t4, qs, acc, xacc, yacc);
                 } else {
                     wave_sync();
-                    etile_strided<GR, F64>(st, g, NG, cnt, d, qs[0], acc[0], xacc[0], yacc[0]);
+                    etile_strided<GR, F64>(st, R.w ? sw : nullptr, g, NG, cnt, d, qs[0], acc[0], xacc[0], yacc[0]);
                 }
                 wave_sync();
             }
@@ -1771,7 +1797,8 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
 // fragments (larger leaves repeat the walk per group of 64 queries).  Per
 // query (tree order) it writes G_E = sum e, and with GR also X_E and Y_E (the
 // quantities k_leaf defines) to GE, GX, GY, which k_leaf adds to the rest.
-// Groups flagged by the underflow guard take FP64 exponentials.
+// Groups flagged by the underflow guard are left to the FP64 pass of k_etile,
+// which adds their sums afterwards.
 template <bool GR, int NC>
 __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
@@ -1781,7 +1808,7 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
                                                double *__restrict__ GY) {
     constexpr int NT = (NC + 3) / 4;  // 16-dimension tiles of the gradient product
     __shared__ int gS[kMaxEGrp], gC[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
-    __shared__ int oB[kEChunk], oN[kEChunk], oF[kEChunk], oCum[kEChunk];
+    __shared__ int oB[kEChunk], oN[kEChunk], oCum[kEChunk];
     __shared__ int wsum[4], ngrp_s, nops_s;
     __shared__ double red[4][2][64];
     __shared__ double redY[GR ? 4 * NT * 256 : 1];
@@ -1796,7 +1823,9 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
     const int d = Q.d;
     const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
     const size_t hq = (size_t)jb.noff + leaf;
-    const double sc2 = jb.sig * jb.sig;  // t = sc2 |q - r|^2, e = 2^-t
+    // fragments and norms are scaled on load (q' = sig q, |q'|^2 = sig^2 |q|^2),
+    // so t = |q'|^2 + |r'|^2 - 2 q'.r' is the exponent of e = 2^-t directly
+    const double sig = jb.sig, sc2 = sig * sig;
     if (tid == 0) {
         int n = 0, tot = 0;
         for (int gi = headE[hq]; gi >= 0 && n < kMaxEGrp; gi = egrp[gi].next) {
@@ -1821,7 +1850,9 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
             qok[b] = nv > 0;
             if (qok[b]) {
                 load_frag<NC>(Q.x, qb0 + qg + 16 * b, nv, d, qf[b]);
-                qnv[b] = Q.nrm[qb0 + qg + 16 * b + min(lane & 15, nv - 1)];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) qf[b][c] *= sig;
+                qnv[b] = Q.nrm[qb0 + qg + 16 * b + min(lane & 15, nv - 1)] * sc2;
             } else {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) qf[b][c] = 0.0;
@@ -1844,12 +1875,13 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
             if (o < nops) {
                 int gi = 0;
                 while (o >= gCum[gi]) ++gi;
-                const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
-                const int rb = R.begin[r], rn = R.end[r] - rb;
-                oB[tid] = rb;
-                oN[tid] = rn;
-                oF[tid] = gF[gi];
-                nb = (rn + 15) >> 4;
+                if (gF[gi] == 0) {  // groups flagged by the underflow guard go to the FP64 pass
+                    const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
+                    const int rb = R.begin[r], rn = R.end[r] - rb;
+                    oB[tid] = rb;
+                    oN[tid] = rn;
+                    nb = (rn + 15) >> 4;
+                }
             }
             const int inc = wave_incl_scan(nb);
             if (lane == 63) wsum[wv] = inc;
@@ -1860,32 +1892,52 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
             __syncthreads();
             const int nopc = min(kEChunk, nops - o0);
             const int tb = oCum[nopc - 1];
+            // The wave's reference blocks are software-pipelined: the next
+            // block's fragment, norms and (GR) gradient operand are loaded
+            // while the current one is computed.
             int op = 0;
-            for (int blk = wv; blk < tb; blk += 4) {
+            double nrf[NC], nrnv[4], nb2[NT][4];
+            float nrw[4];
+            int nnv = 0;
+            auto fetch = [&](int blk) {
                 while (blk >= oCum[op]) ++op;
                 const int lb = blk - (op ? oCum[op - 1] : 0);
-                const int r0 = oB[op] + 16 * lb, nv = min(16, oN[op] - 16 * lb);
-                const bool f64 = oF[op] != 0;
-                double rf[NC];
-                load_frag<NC>(R.x, r0, nv, d, rf);
-                double rnv[4];
-                bool rok[4];
+                const int r0 = oB[op] + 16 * lb;
+                nnv = min(16, oN[op] - 16 * lb);
+                load_frag<NC>(R.x, r0, nnv, d, nrf);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int j = 4 * k + g;
-                    rok[k] = j < nv;
-                    rnv[k] = R.nrm[r0 + min(j, nv - 1)];
-                }
-                double b2[NT][4];
+                for (int k = 0; k < 4; ++k) nrnv[k] = R.nrm[r0 + min(4 * k + g, nnv - 1)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nrw[k] = R.w ? (float)R.w[r0 + min(4 * k + g, nnv - 1)] : 1.0f;
                 if (GR) {
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                         for (int c2 = 0; c2 < 4; ++c2) {
-                            const int row = r0 + min(4 * c2 + g, nv - 1), dim = 16 * nt + (lane & 15);
-                            b2[nt][c2] = dim < d ? R.x[(size_t)row * d + dim] : 0.0;
+                            const int row = r0 + min(4 * c2 + g, nnv - 1), dim = 16 * nt + (lane & 15);
+                            nb2[nt][c2] = dim < d ? R.x[(size_t)row * d + dim] : 0.0;
                         }
                 }
+            };
+            if (wv < tb) fetch(wv);
+            for (int blk = wv; blk < tb; blk += 4) {
+                const int nv = nnv;
+                double rf[NC], rnv[4], b2[NT][4];
+                float rw[4];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) rf[c] = nrf[c] * sig;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    rnv[k] = nrnv[k] * sc2;
+                    rw[k] = 4 * k + g < nv ? nrw[k] : 0.0f;  // weight 0 past the block's end
+                }
+                if (GR) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int c2 = 0; c2 < 4; ++c2) b2[nt][c2] = nb2[nt][c2];
+                }
+                if (blk + 4 < tb) fetch(blk + 4);
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     if (!qok[b]) continue;
@@ -1893,23 +1945,16 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
                     double ev[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const double t = fmax(fma(-2.0, dt[k], qnv[b] + rnv[k]), 0.0) * sc2;
-                        if (f64) {
-                            const double e = rok[k] ? exp(-t * kLn2) : 0.0;
-                            acc[b] += e;
-                            if (GR) at[b] = fma(t, e, at[b]);
-                            ev[k] = e;
-                        } else {
-                            const float e = rok[k] ? __builtin_amdgcn_exp2f(-(float)t) : 0.0f;
-                            // gradient mode: the sum of the kernel values multiplies x_q
-                            // in Y = x_q sum e - sum e x_r, so it is taken in FP64 like
-                            // the matrix-core sums of e x_r (FP32 partials would leave a
-                            // mismatch amplified by |x_q| / |q - r|)
-                            if (GR) acc[b] += (double)e;
-                            else ps[b] += e;
-                            if (GR) pt[b] = fmaf((float)t, e, pt[b]);
-                            ev[k] = (double)e;
-                        }
+                        const float t = fmaxf((float)fma(-2.0, dt[k], qnv[b] + rnv[k]), 0.0f);
+                        const float e = rw[k] * __builtin_amdgcn_exp2f(-t);
+                        // gradient mode: the sum of the kernel values multiplies x_q
+                        // in Y = x_q sum e - sum e x_r, so it is taken in FP64 like
+                        // the matrix-core sums of e x_r (FP32 partials would leave a
+                        // mismatch amplified by |x_q| / |q - r|)
+                        if (GR) acc[b] += (double)e;
+                        else ps[b] += e;
+                        if (GR) pt[b] = fmaf(t, e, pt[b]);
+                        ev[k] = (double)e;
                     }
                     if (GR) {
 #pragma unroll
@@ -2227,7 +2272,9 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.inv2h2 = 1.0 / (2.0 * q.h[k] * q.h[k]);
             j.sig = 1.2011224087864498 * j.s;  // sqrt(log2 e) s: e^{-x^2/2h^2} = 2^{-(sig x)^2}
             j.eps_eff = eps_eff;
-            j.nR = (double)q.R->n;
+            j.nR = q.R->wsum / q.R->wscale;
+            j.cntR = (double)q.R->n;
+            j.wscale = q.R->wscale;
             j.prior = 0.0;
             j.qt = qt;
             j.rt = rt;
@@ -2237,7 +2284,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.outH = pl.gr && grad->dGdh ? grad->dGdh + (size_t)k * q.Q->n : nullptr;
             j.outQ = pl.gr && grad->dGdq ? grad->dGdq + (size_t)k * q.Q->n * pl.d : nullptr;
             j.cost_e = cost_e;
-            j.mono = q.Q == q.R ? 1 : 0;
+            j.mono = q.Q == q.R && !q.R->weighted ? 1 : 0;  // the self term bounds G below by 1
             j.pad = 0;
             pl.jobs.push_back(j);
             nna += q.Q->m;
@@ -2428,7 +2475,7 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
         }
         if (prof) prof->stop(K_EMFMA, ev, ss);
-        if (!pl.emfma) {
+        {
             // the FP64 pairs (all of them at precision FP64, else the groups the
             // underflow guard flagged), added after the mixed pass
             ev = prof ? prof->start(ss) : nullptr;

@@ -130,7 +130,14 @@ struct DevTree {
     const double *nrm;                    // [n] squared norms |x|^2 in tree order
     const int32_t *lpath;                 // [nleaves][depth] ancestors of each leaf, the leaf first
     const int32_t *lplen;                 // [nleaves] path lengths
+    const double *w;                      // [n] point weights / max weight, tree order; null: all 1
 };
+
+// Weight of reference node r (its moment mu_0, the sum of its stored point
+// weights); its point count when the tree carries no weights.
+__device__ __forceinline__ double node_weight(const DevTree &R, int r) {
+    return R.w ? R.mu[(size_t)r * R.P] : (double)(R.end[r] - R.begin[r]);
+}
 
 }  // namespace dfgt
 
@@ -147,9 +154,12 @@ struct dfgt_tree_s {
     // arrays sized after the build; arena2: moments, norms and the device view
     dfgt::DevBuf arena0, arena1, arena2;
     dfgt::DevSpan lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, nrm_max,
-        lpath, lplen, nleaves_dev;
+        lpath, lplen, nleaves_dev, w;
     double max_nrm = 0.0;  // max |x|^2 (valid after dfgt_build_tree returns)
     hipStream_t stream = nullptr;  // the stream the tree was built on
+    bool weighted = false;         // points carry weights (dfgt_build_tree_weighted)
+    double wscale = 1.0;           // the largest weight: the tree stores w / wscale, in [0, 1]
+    double wsum = 0.0;             // sum of the caller's weights (n when unweighted)
     dfgt::DevSpan view;    // a DevTree in device memory
     dfgt::DevTree host_view{};
 };
@@ -197,7 +207,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 dfgt_status launch_naive(const double *q, int64_t nq, const double *r, int64_t nr, int d,
                          const double *h, int nh, int precision, double *G, hipStream_t st);
 // tree.hip
-dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st);
+dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w, hipStream_t st);
 // moments.hip
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st);
 // dfgt.hip

@@ -22,10 +22,11 @@ namespace {
 
 constexpr int ipow_c(int b, int e) { return e == 0 ? 1 : b * ipow_c(b, e - 1); }
 
-__global__ __launch_bounds__(64) void k_p2m(const double *__restrict__ x, const double *__restrict__ ctr,
-                                            const int32_t *__restrict__ begin, const int32_t *__restrict__ end,
-                                            const int32_t *__restrict__ leaves, const int *__restrict__ nleaves,
-                                            int d, int pmax, int P, double *__restrict__ mu) {
+__global__ __launch_bounds__(64) void k_p2m(const double *__restrict__ x, const double *__restrict__ wts,
+                                            const double *__restrict__ ctr, const int32_t *__restrict__ begin,
+                                            const int32_t *__restrict__ end, const int32_t *__restrict__ leaves,
+                                            const int *__restrict__ nleaves, int d, int pmax, int P,
+                                            double *__restrict__ mu) {
     if ((int)blockIdx.x >= *nleaves) return;
     const int node = leaves[blockIdx.x];
     const int b = begin[node], e = end[node];
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(64) void k_p2m(const double *__restrict__ x, const 
         }
         double s = 0.0;
         for (int j = b; j < e; ++j) {
-            double term = 1.0;
+            double term = wts ? wts[j] : 1.0;
             for (int k = 0; k < d; ++k) {
                 const double dx = x[(size_t)j * d + k] - c[k];
                 for (int t = 0; t < a[k]; ++t) term *= dx;
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(256) void k_f2f(int lb, int le, const int32_t *__re
 constexpr int kMomDirectMax = 2048;
 
 template <int D, int PM>
-__global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict__ x, const double *__restrict__ ctr,
+__global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict__ x, const double *__restrict__ wts,
+                                                       const double *__restrict__ ctr,
                                                        const int32_t *__restrict__ begin,
                                                        const int32_t *__restrict__ end,
                                                        const int32_t *__restrict__ left, double *__restrict__ mu) {
@@ -124,11 +126,11 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
 #pragma unroll
     for (int i = 0; i < P; ++i) acc[i] = 0.0;
     for (int j = b + (int)threadIdx.x; j < e; j += 64) {
-        double pw[D][PM];  // (x_k - c_k)^a / a!
+        double pw[D][PM];  // (x_k - c_k)^a / a!, the point's weight on dimension 0
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const double dx = x[(size_t)j * D + k] - c[k];
-            pw[k][0] = 1.0;
+            pw[k][0] = k == 0 && wts ? wts[j] : 1.0;
 #pragma unroll
             for (int a = 1; a < PM; ++a) pw[k][a] = pw[k][a - 1] * dx / (double)a;
         }
@@ -152,11 +154,12 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
 }
 
 // Launches the direct kernel when (D, p_max) has an instance; false otherwise.
-bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double *x, const double *ctr,
-                           const int32_t *begin, const int32_t *end, const int32_t *left, double *mu) {
+bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double *x, const double *wts,
+                           const double *ctr, const int32_t *begin, const int32_t *end, const int32_t *left,
+                           double *mu) {
 #define DFGT_MOM(DV, PV)                                                                                \
     if (d == DV && pmax == PV) {                                                                        \
-        hipLaunchKernelGGL((k_moments_direct<DV, PV>), dim3(m), dim3(64), 0, st, x, ctr, begin, end,          \
+        hipLaunchKernelGGL((k_moments_direct<DV, PV>), dim3(m), dim3(64), 0, st, x, wts, ctr, begin, end,     \
                            left, mu);                                                                   \
         return true;                                                                                    \
     }
@@ -204,14 +207,15 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     // the leaf count and the largest squared norm come back in one sync at the end
     struct Back {
         int nl;
-        double mx;
+        double mx, w0;
     };
     static thread_local Back back;
-    const bool direct = launch_moments_direct(d, pmax, (int)m, st, t->x.as<double>(), t->ctr.as<double>(),
+    const double *wts = t->w.as<double>();
+    const bool direct = launch_moments_direct(d, pmax, (int)m, st, t->x.as<double>(), wts, t->ctr.as<double>(),
                                               t->begin.as<int32_t>(), t->end.as<int32_t>(), t->left.as<int32_t>(),
                                               t->mu.as<double>());
     if (!direct)
-        hipLaunchKernelGGL(k_p2m, dim3((unsigned)((m + 1) / 2)), dim3(64), 0, st, t->x.as<double>(),
+        hipLaunchKernelGGL(k_p2m, dim3((unsigned)((m + 1) / 2)), dim3(64), 0, st, t->x.as<double>(), wts,
                            t->ctr.as<double>(), t->begin.as<int32_t>(), t->end.as<int32_t>(), t->leaves.as<int32_t>(),
                            t->nleaves_dev.as<int>(), d, pmax, P, t->mu.as<double>());
     DFGT_HIP(hipGetLastError());
@@ -242,9 +246,11 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     }
     DFGT_HIP(hipMemcpyAsync(&back.nl, t->nleaves_dev.p, sizeof(int), hipMemcpyDeviceToHost, st));
     DFGT_HIP(hipMemcpyAsync(&back.mx, t->nrm_max.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipMemcpyAsync(&back.w0, t->mu.p, sizeof(double), hipMemcpyDeviceToHost, st));  // root mu_0
     DFGT_HIP(hipStreamSynchronize(st));
     t->nleaves = back.nl;
     t->max_nrm = back.mx;
+    t->wsum = t->weighted ? back.w0 * t->wscale : (double)t->n;  // root mu_0 = sum of the stored weights
     return DFGT_OK;
 }
 

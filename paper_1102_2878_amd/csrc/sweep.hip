@@ -186,7 +186,7 @@ dfgt_status run_density(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh,
                         int force, double cost_e, double *p, dfgt_stats *stats, hipStream_t st) {
     SweepWs &w = g_sw;
     DFGT_TRY(run_gauss_sum(Q, R, h, nh, eps, precision, force, 0, cost_e, p, nullptr, stats, st));
-    const double pi = 3.14159265358979323846, D = (double)R->d, NR = (double)R->n;
+    const double pi = 3.14159265358979323846, D = (double)R->d, NR = R->wsum;  // W(R): n when unweighted
     std::vector<double> sc(nh);
     for (int k = 0; k < nh; ++k) sc[k] = 1.0 / (NR * std::pow(2.0 * pi * h[k] * h[k], 0.5 * D));
     DFGT_TRY(w.scale.reserve(sizeof(double) * nh));

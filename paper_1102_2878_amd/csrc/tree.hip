@@ -358,6 +358,13 @@ __global__ __launch_bounds__(kLB) void k_scatter(int n, int d, const int32_t *__
     block_box_fold(act, child, v, d, lo_key, hi_key, sh);
 }
 
+// Point weights in tree order, scaled into [0, 1]: w_tree[i] = w[perm[i]] * inv_max.
+__global__ void k_gather_weights(const double *__restrict__ w, const int32_t *__restrict__ perm, int n,
+                                 double inv_max, double *__restrict__ wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wt[i] = w[perm[i]] * inv_max;
+}
+
 __global__ void k_decode_boxes(int m, int d, const long long *__restrict__ lo_key,
                                const long long *__restrict__ hi_key, double *lo, double *hi, double *ctr) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -415,7 +422,7 @@ struct BuildWs {
 };
 thread_local BuildWs g_build;
 
-dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st) {
+dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *wts, hipStream_t st) {
     const int n = (int)t->n, d = t->d, leaf = t->leaf;
     const int cap = 2 * n + 1;
     BuildWs &w = g_build;
@@ -552,8 +559,16 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, hipStream_t st)
                                      {&t->leaves, sizeof(int32_t) * m},
                                      {&t->lpath, sizeof(int32_t) * (size_t)m * pstride},
                                      {&t->lplen, sizeof(int32_t) * (size_t)m},
-                                     {&t->nleaves_dev, sizeof(int)}},
+                                     {&t->nleaves_dev, sizeof(int)},
+                                     {&t->w, wts ? sizeof(double) * (size_t)n : 0}},
                          st, true));
+    if (wts) {
+        hipLaunchKernelGGL(k_gather_weights, dim3(gb), dim3(kLB), 0, st, wts, t->perm.as<int32_t>(), n,
+                           1.0 / t->wscale, t->w.as<double>());
+        DFGT_HIP(hipGetLastError());
+    } else {
+        t->w.p = nullptr;
+    }
     hipLaunchKernelGGL(k_decode_boxes, dim3((m * d + 255) / 256), dim3(256), 0, st, m, d, lo_key.as<long long>(),
                        hi_key.as<long long>(), t->lo.as<double>(), t->hi.as<double>(), t->ctr.as<double>());
     int *nl_dev = t->nleaves_dev.as<int>();

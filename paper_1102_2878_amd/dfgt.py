@@ -66,6 +66,7 @@ def lib():
         L.dfgt_last_error.restype = C.c_char_p
         L.dfgt_version.restype = C.c_char_p
         L.dfgt_build_tree.argtypes = [vp, i64, i32, C.POINTER(Options), vp, C.POINTER(vp)]
+        L.dfgt_build_tree_weighted.argtypes = [vp, vp, i64, i32, C.POINTER(Options), vp, C.POINTER(vp)]
         L.dfgt_tree_free.argtypes = [vp]
         L.dfgt_tree_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
                                      C.POINTER(i32)]
@@ -92,7 +93,7 @@ def lib():
         L.dfgt_batch_run.argtypes = [vp, vp]
         L.dfgt_batch_check.argtypes = [vp, vp]
         L.dfgt_batch_free.argtypes = [vp]
-        for nm in ("dfgt_build_tree", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
+        for nm in ("dfgt_build_tree", "dfgt_build_tree_weighted", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
                    "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
                    "dfgt_gauss_sum_backward", "dfgt_lscv_score", "dfgt_lscv_optimize", "dfgt_gauss_sum_batched",
                    "dfgt_kde_density", "dfgt_lcv_score",
@@ -157,13 +158,26 @@ class Tree:
         return tree_info(self)
 
 
-def build_tree(points, leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE) -> Tree:
-    """dfgt_build_tree: kd-tree (+ raw moments) of an (n, d) float64 CUDA tensor."""
+def build_tree(points, leaf_size=0, p_max=0, precision=PREC_MIXED, force_method=FORCE_NONE,
+               weights=None) -> Tree:
+    """dfgt_build_tree: kd-tree (+ raw moments) of an (n, d) float64 CUDA tensor.
+
+    weights: an (n,) float64 CUDA tensor of point weights >= 0 (dfgt_build_tree_weighted):
+    sums over this tree as the reference set are then sum_j w_j K(q, r_j)."""
     x = _dev_points(points)
     o = _opts(leaf_size, p_max, precision, force_method)
     h = C.c_void_p()
-    _check(lib().dfgt_build_tree(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(o), _stream(),
-                                 C.byref(h)))
+    if weights is None:
+        _check(lib().dfgt_build_tree(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], C.byref(o), _stream(),
+                                     C.byref(h)))
+        return Tree(h, x.shape[0], x.shape[1])
+    torch = _torch()
+    if not (isinstance(weights, torch.Tensor) and weights.is_cuda and weights.dtype == torch.float64
+            and weights.dim() == 1 and weights.shape[0] == x.shape[0]):
+        raise DfgtError("weights must be an (n,) float64 CUDA (HIP) tensor")
+    w = weights.contiguous()
+    _check(lib().dfgt_build_tree_weighted(C.c_void_p(x.data_ptr()), C.c_void_p(w.data_ptr()), x.shape[0],
+                                          x.shape[1], C.byref(o), _stream(), C.byref(h)))
     return Tree(h, x.shape[0], x.shape[1])
 
 

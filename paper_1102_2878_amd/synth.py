@@ -136,3 +136,26 @@ def subsample(x: np.ndarray, m: int, seed: int) -> np.ndarray:
     """Seeded index sample (without replacement) of m rows."""
     rng = _rng(seed + 7)
     return np.sort(rng.choice(x.shape[0], size=min(m, x.shape[0]), replace=False))
+
+
+def weights(n: int, seed: int, kind: str = "exp") -> np.ndarray:
+    """Seeded non-negative point weights for weighted sums.
+
+    ``exp``: exponential(1); ``wide``: log-uniform over [1e-6, 1e3];
+    ``sparse``: exponential(1) with about 30% zeros; ``int``: integers 0..3
+    (at least one non-zero)."""
+    rng = _rng(seed + 31)
+    if kind == "exp":
+        return rng.exponential(size=n)
+    if kind == "wide":
+        return _loguniform(rng, 1e-6, 1e3, n)
+    if kind == "sparse":
+        w = rng.exponential(size=n)
+        w[rng.random(n) < 0.3] = 0.0
+        w[0] = max(w[0], 1.0)
+        return w
+    if kind == "int":
+        w = rng.integers(0, 4, size=n).astype(np.float64)
+        w[0] = max(w[0], 1.0)
+        return w
+    raise ValueError(kind)
