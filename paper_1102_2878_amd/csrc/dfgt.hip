@@ -1065,6 +1065,67 @@ __global__ void k_fill_u32(unsigned *__restrict__ p, size_t n, unsigned v) {
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kSqrtLn2 = 0.83255461115769775635;
 
+// Far-field evaluation (EvalFarField, eq. primal) at one query for a
+// dimension and p_max fixed at compile time: the Hermite rows stay in
+// registers with s^a folded in (M_alpha h_alpha = mu_alpha prod_k s^{a_k}
+// H_{a_k}(t_k) e^{-|t|^2}), and the sum over the p^D coefficients of order < p
+// is taken one axis at a time, last axis innermost (the storage order), so a
+// coefficient costs one FMA.  Returns the polynomial part; *tt = |t|^2.
+template <int D, int PM, int K>
+struct FarAxis {
+    __device__ __forceinline__ static double run(const double *__restrict__ mu, const double (&hs)[D][PM], int p,
+                                                 int off) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = PM - 1; a >= 0; --a)
+            if (a < p) acc = fma(hs[K][a], FarAxis<D, PM, K + 1>::run(mu, hs, p, off * PM + a), acc);
+        return acc;
+    }
+};
+template <int D, int PM>
+struct FarAxis<D, PM, D> {
+    __device__ __forceinline__ static double run(const double *__restrict__ mu, const double (&)[D][PM], int,
+                                                 int off) {
+        return mu[off];
+    }
+};
+
+template <int D, int PM>
+__device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, const double *__restrict__ rc,
+                                                 const double *__restrict__ q, double s, int p, double *tt) {
+    double hs[D][PM];
+    double t2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double t = (q[k] - rc[k]) * s;
+        t2 += t * t;
+        double h0 = 1.0, h1 = 2.0 * t, sp = s;
+        hs[k][0] = 1.0;
+        if (PM > 1) hs[k][1] = h1 * s;
+#pragma unroll
+        for (int a = 1; a + 1 < PM; ++a) {
+            const double h2 = 2.0 * t * h1 - 2.0 * a * h0;
+            h0 = h1;
+            h1 = h2;
+            sp *= s;
+            hs[k][a + 1] = h2 * sp;  // sp = s^{a+1}
+        }
+    }
+    *tt = t2;
+    return FarAxis<D, PM, 0>::run(mu, hs, p, 0);
+}
+
+// (D, p_max) pairs with a compile-time far-field evaluation (the default p_max
+// of D = 1..5); 0 = none.
+__host__ __device__ inline int far_fixed_kind(int d, int pmax) {
+    if (d == 1 && pmax == 6) return 1;
+    if (d == 2 && pmax == 6) return 2;
+    if (d == 3 && pmax == 4) return 3;
+    if (d == 4 && pmax == 2) return 4;
+    if (d == 5 && pmax == 2) return 5;
+    return 0;
+}
+
 // Doubles of dynamic LDS k_leaf needs before the coefficient vectors.
 __host__ __device__ inline size_t leaf_lds_base(int nthr, int d, int pmax, int gr) {
     return (size_t)nthr * (1 + gr) + (size_t)d * (pmax - 1) + 1 + (size_t)nthr * d * (pmax + gr) +
@@ -1216,6 +1277,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const int ngr = nthr / slots;
     const int qi = tid % slots, tg = tid / slots;
     const double *lc = Q.ctr + (size_t)leaf * d;
+    const int fixed = far_fixed_kind(d, pmax);
     // op groups: the leaf's E chain, then the F chains of the path nodes from
     // the root down, each chain in its own order.  One thread per chain counts
     // and then copies its groups; if more than kMaxSeg groups result they are
@@ -1357,7 +1419,21 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 while (idx >= segE[sp]) ++sp;
                 const int off = idx - (sp ? segE[sp - 1] : 0);
                 const int type = segT[sp];
-                if (act) {  // every op here is a far-field evaluation
+                if (act && !GR && fixed) {  // far-field evaluation, registers only
+                    const Op op = fops[segS[sp] + off];
+                    const int r = op.r, p = op.meta & 255;
+                    const double *mu = R.mu + (size_t)r * P;
+                    const double *rc = R.ctr + (size_t)r * d;
+                    double tt = 0.0, w = 0.0;
+                    switch (fixed) {
+                    case 1: w = far_eval_fixed<1, 6>(mu, rc, qg, s, p, &tt); break;
+                    case 2: w = far_eval_fixed<2, 6>(mu, rc, qg, s, p, &tt); break;
+                    case 3: w = far_eval_fixed<3, 4>(mu, rc, qg, s, p, &tt); break;
+                    case 4: w = far_eval_fixed<4, 2>(mu, rc, qg, s, p, &tt); break;
+                    default: w = far_eval_fixed<5, 2>(mu, rc, qg, s, p, &tt); break;
+                    }
+                    if (tt <= 745.0) part = fma(exp(-tt), w, part);
+                } else if (act) {  // every op here is a far-field evaluation
                     const Op op = fops[segS[sp] + off];
                     const int r = op.r, p = op.meta & 255;
                     const double *mu = R.mu + (size_t)r * P;

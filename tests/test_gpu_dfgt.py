@@ -119,6 +119,21 @@ def test_forced_single_method(dfgt, force, key):
         assert st["prune_f"] + st["prune_d"] + st["prune_t"] + st["prune_centroid"] == 0
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("eps", [1e-2, 1e-5])
+def test_forced_far_field_each_dimension(dfgt, d, eps):
+    # far-field evaluation alone at every default p_max (the per-leaf kernel has a
+    # compile-time form for these (D, p_max) pairs), at a loose and a tight bound
+    x = synth.c3(n=3000, seed=29)[:, :d]
+    hs = [synth.silverman_h(x) * s for s in (1.0, 10.0, 100.0)]
+    note(f"dfgt force F d={d} eps={eps}")
+    G, st = _run(dfgt, x, None, hs, eps, force=1)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+        assert rel.max() <= eps, (d, h, rel.max())
+    assert st["prune_f"] > 0, st
+
+
 def test_ragged_leaf_sizes_and_tiny_inputs(dfgt):
     rng = np.random.default_rng(26)
     for n, leaf in ((1, 32), (2, 1), (33, 32), (257, 7), (1000, 100), (700, 300)):
