@@ -92,6 +92,9 @@ enum {
     C_LOP,
     C_LNODE,
     C_EF64,     // E groups flagged by the underflow guard (FP64 sums)
+    C_EHEAVY,   // (job, query leaf) items by exhaustive work: long lists, short lists, none
+    C_ENORM,
+    C_EEMPTY,
     C_N
 };
 
@@ -818,43 +821,94 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
 // Adds the op rows (PW doubles, coefficient i of L at i and of the tangent at
 // P + i) of one node's chain in chain order: acc += part[op].  Threads over
 // the PW entries.
-__device__ __forceinline__ void sum_chain_parts(int head, const Group *__restrict__ lgrp, const Op *__restrict__ lops,
-                                                const double *__restrict__ part, int P, int PW, double *acc) {
-    for (int i = threadIdx.x; i < PW; i += blockDim.x) {
-        double v = acc[i];
-        for (int gi = head; gi >= 0; gi = lgrp[gi].next) {
+// Adds the partial rows of one local-op chain (every op of its groups, in
+// chain order) to acc[PW], with the whole block.  Thread 0 flattens the chain
+// into gs / gc (group starts, cumulative op counts; a chain has at most one
+// group per level).  For PW <= the block size, G = blockDim / PW thread groups
+// take ops g, g + G, ... four loads at a time, and their partials, red[G][PW],
+// are added in group order: a fixed order, so the result is deterministic.
+// Every thread of the block calls it; ns holds two ints.
+__device__ void block_chain_parts(int head, const Group *__restrict__ lgrp, const double *__restrict__ part,
+                                  int PW, double *acc, int *gs, int *gc, int *ns, double *red) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    if (tid == 0) {
+        int n = 0, tot = 0;
+        for (int gi = head; gi >= 0 && n < kMaxDepth; gi = lgrp[gi].next) {
             const Group g = lgrp[gi];
-            for (int o = g.start; o < g.start + g.count; ++o) v += part[(size_t)o * PW + i];
+            gs[n] = g.start;
+            tot += g.count;
+            gc[n++] = tot;
         }
-        acc[i] = v;
+        ns[0] = n;
+        ns[1] = tot;
     }
+    __syncthreads();
+    const int nops = ns[1];
+    if (PW <= nthr) {
+        const int G = nthr / PW, i = tid % PW, g = tid / PW;
+        if (g < G) {
+            double v = 0.0;
+            int k = 0;
+            for (int o0 = g; o0 < nops; o0 += 4 * G) {
+                double t[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int o = o0 + u * G;
+                    t[u] = 0.0;
+                    if (o < nops) {
+                        while (o >= gc[k]) ++k;
+                        t[u] = part[(size_t)(gs[k] + o - (k ? gc[k - 1] : 0)) * PW + i];
+                    }
+                }
+                v += t[0];
+                v += t[1];
+                v += t[2];
+                v += t[3];
+            }
+            red[g * PW + i] = v;
+        }
+        __syncthreads();
+        if (tid < PW) {
+            double sum = acc[tid];
+            for (int gg = 0; gg < G; ++gg) sum += red[gg * PW + tid];
+            acc[tid] = sum;
+        }
+    } else {
+        const int ng = ns[0];
+        for (int i = tid; i < PW; i += nthr) {
+            double v = acc[i];
+            for (int k = 0, o = 0; k < ng; ++k)
+                for (; o < gc[k]; ++o) v += part[(size_t)(gs[k] + o - (k ? gc[k - 1] : 0)) * PW + i];
+            acc[i] = v;
+        }
+    }
+    __syncthreads();
 }
 
-// One wave per internal (Q, job) with local ops; L rows hold PW doubles.
-__global__ __launch_bounds__(64) void k_lreduce(const Job *__restrict__ jobs, const DevTree *__restrict__ trees,
-                                                const int *__restrict__ lnodes, const int *__restrict__ cnt,
-                                                const int *__restrict__ overflow, const int *__restrict__ headL,
-                                                const Group *__restrict__ lgrp, const Op *__restrict__ lops,
-                                                const double *__restrict__ part, int PW, double *L,
-                                                unsigned char *lflag) {
+// One block per internal (Q, job) with local ops; L rows hold PW doubles.
+// Dynamic LDS: acc[PW] | red[256].
+__global__ __launch_bounds__(256) void k_lreduce(const Job *__restrict__ jobs, const int *__restrict__ lnodes,
+                                                 const int *__restrict__ cnt, const int *__restrict__ overflow,
+                                                 const int *__restrict__ headL, const Group *__restrict__ lgrp,
+                                                 const double *__restrict__ part, int PW, double *L,
+                                                 unsigned char *lflag) {
     extern __shared__ double smem[];
+    __shared__ int gs[kMaxDepth], gc[kMaxDepth], ns[2];
     if (*overflow) return;
     const int nl = cnt[C_LNODE * CP];
-    const int P = trees[jobs[0].qt].P;
+    double *acc = smem, *red = smem + PW;
     for (int li = blockIdx.x; li < nl; li += gridDim.x) {
         const int q = lnodes[2 * li], job = lnodes[2 * li + 1];
         const size_t hq = (size_t)jobs[job].noff + q;
-        wave_sync();
-        for (int i = threadIdx.x; i < PW; i += blockDim.x) smem[i] = 0.0;
-        wave_sync();
-        sum_chain_parts(headL[hq], lgrp, lops, part, P, PW, smem);
-        wave_sync();
-        for (int i = threadIdx.x; i < PW; i += blockDim.x) L[hq * PW + i] = smem[i];
+        __syncthreads();  // the previous node's tables are no longer read
+        for (int i = threadIdx.x; i < PW; i += blockDim.x) acc[i] = 0.0;
+        __syncthreads();
+        block_chain_parts(headL[hq], lgrp, part, PW, acc, gs, gc, ns, red);
+        for (int i = threadIdx.x; i < PW; i += blockDim.x) L[hq * PW + i] = acc[i];
         if (threadIdx.x == 0) lflag[hq] = 1;
     }
 }
 
-// Marks, for every local op, the group it belongs to (k_lops needs the node).
 __global__ void k_lop_owner(const Group *__restrict__ lgrp, const int *__restrict__ cnt,
                             const int *__restrict__ overflow, int *lop_node) {
     if (*overflow) return;
@@ -1267,8 +1321,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         }
         if (leaf_local && headL[hq] >= 0) {  // the leaf's own local ops, from their partial rows
             __syncthreads();
-            sum_chain_parts(headL[hq], lgrp, lops, part, P, PW, acc);
-            __syncthreads();
+            // the segment tables and the Hermite rows are free until part 2
+            block_chain_parts(headL[hq], lgrp, part, PW, acc, segS, segE, ccnt, Hq_all);
         }
     }
     // 2. exhaustive and far-field parts
@@ -1550,6 +1604,69 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
 constexpr int kEChunk = 256;   // E ops flattened per chunk
 constexpr int kMaxEGrp = 256;  // E groups of one (job, node) chain (at most one per level)
 
+constexpr int kEHeavyOps = 64; // an item with at least this many E ops (mixed pass) is dispatched first
+
+// Dispatch order of the mixed pass's exhaustive tiles (longest first): the
+// items whose E chain holds >= kEHeavyOps ops of the mixed pass, then those
+// with fewer, then those with none.  A leaf with hundreds of reference leaves
+// keeps one block busy ~100 us; started in job order, such blocks began
+// midway through the launch and set its end.  One thread per item counts its
+// chain; each block appends its items to the three lists with one atomic per
+// list.  Which block takes an item does not change its sums.
+__global__ __launch_bounds__(256) void k_eorder(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                                const Group *__restrict__ egrp, const int *__restrict__ headE,
+                                                const int *__restrict__ overflow, const int *__restrict__ jlstart,
+                                                int njobs, int unl, int nitems, int *cnt, int *heavy, int *norm,
+                                                int *empty) {
+    __shared__ int wc[3][4], base[3];
+    if (*overflow) return;
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int ops = -1;  // -1: no item
+    if (item < nitems) {
+        int job, li;
+        job_leaf(jlstart, njobs, unl, item, &job, &li);
+        const Job jb = jobs[job];
+        const DevTree &Q = trees[jb.qt];
+        ops = 0;
+        int n = 0;
+        for (int gi = headE[(size_t)jb.noff + Q.leaves[li]]; gi >= 0 && n < kMaxEGrp; ++n) {
+            const Group g = egrp[gi];
+            if (g.flags == 0) ops += g.count;
+            gi = g.next;
+        }
+    }
+    const int cls = ops < 0 ? -1 : (ops >= kEHeavyOps ? 0 : (ops > 0 ? 1 : 2));
+    int rk[3];
+    for (int c = 0; c < 3; ++c) {
+        const int f = cls == c ? 1 : 0;
+        const int inc = wave_incl_scan(f);
+        rk[c] = inc - f;
+        if (lane == 63) wc[c][wv] = inc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        const int tot = wc[c][0] + wc[c][1] + wc[c][2] + wc[c][3];
+        base[c] = tot ? atomicAdd(&cnt[(C_EHEAVY + c) * CP], tot) : 0;
+    }
+    __syncthreads();
+    if (cls >= 0) {
+        int off = base[cls] + rk[cls];
+        for (int w = 0; w < wv; ++w) off += wc[cls][w];
+        (cls == 0 ? heavy : (cls == 1 ? norm : empty))[off] = item;
+    }
+}
+
+// Item of block b of the mixed pass in that order (order = null: in turn);
+// order holds the three lists, nitems entries each.
+__device__ __forceinline__ int etile_item(int b, const int *__restrict__ cnt, const int *__restrict__ order,
+                                          int nitems) {
+    if (!order) return b;
+    const int nh = cnt[C_EHEAVY * CP], nn = cnt[C_ENORM * CP];
+    return b < nh ? order[b] : (b < nh + nn ? order[nitems + b - nh] : order[2 * nitems + b - nh - nn]);
+}
+
 // ---------------------------------------------------------------- exhaustive tiles on the vector ALUs
 // DFGTBase for every dimension (the matrix-core kernel below takes D >= 8 in
 // mixed precision), in two passes over the same E lists: F64 = false takes the
@@ -1704,8 +1821,9 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
                                                const int *__restrict__ headE, const int *__restrict__ cnt_dev,
                                                const int *__restrict__ overflow, const int *__restrict__ jlstart,
-                                               int njobs, int unl, int precision, double *__restrict__ GE,
-                                               double *__restrict__ GX, double *__restrict__ GY) {
+                                               int njobs, int unl, int precision, const int *__restrict__ order,
+                                               int nitems, double *__restrict__ GE, double *__restrict__ GX,
+                                               double *__restrict__ GY) {
     using Sh = ETileShape<DT, F64>;
     constexpr int DS = Sh::DS, QPT = Sh::QPT;
     constexpr bool PAD = Sh::PAD;
@@ -1723,7 +1841,7 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
     if (F64 && !all64 && cnt_dev[C_EF64 * CP] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int job, li;
-    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
+    job_leaf(jlstart, njobs, unl, etile_item(blockIdx.x, cnt_dev, order, nitems), &job, &li);
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
@@ -2162,7 +2280,7 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
-        lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval, gdg, gmt;
+        lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval, gdg, gmt, eord;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
     int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
     // the exhaustive tiles run on a side stream beside the local-moment ops
@@ -2212,16 +2330,18 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
 }
 
 template <bool GR>
-void launch_etile(bool f64pass, int d, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd,
+void launch_etile(bool f64pass, int d, int nitems, hipStream_t st, const DevTree *td, const Job *jd,
                   const Group *egrp, const int *eops, const int *headE, const int *cnt, const int *flag,
-                  const int *jls, int njobs, int unl, int precision, double *GE, double *GX, double *GY) {
+                  const int *jls, int njobs, int unl, int precision, const int *order, double *GE, double *GX,
+                  double *GY) {
+    const dim3 grid((unsigned)nitems);
 #define DFGT_ETILE(DV)                                                                                            \
     if (f64pass)                                                                                                  \
         hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
-                           jls, njobs, unl, precision, GE, GX, GY);                                               \
+                           jls, njobs, unl, precision, (const int *)nullptr, nitems, GE, GX, GY);                 \
     else                                                                                                          \
         hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, cnt,      \
-                           flag, jls, njobs, unl, precision, GE, GX, GY);                                         \
+                           flag, jls, njobs, unl, precision, order, nitems, GE, GX, GY);                          \
     break;
     switch (d) {
     case 1: DFGT_ETILE(1)
@@ -2451,6 +2571,7 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<int>(w.lvl, (size_t)(pl.nlev + 1) * 2 * CP));
     // exhaustive sums per query (k_emfma or k_etile), added by k_leaf
     DFGT_TRY(grow<double>(w.extE, pl.nqa));
+    DFGT_TRY(grow<int>(w.eord, 3 * (size_t)pl.items));  // dispatch order of the exhaustive tiles
     if (pl.gr) {
         DFGT_TRY(grow<double>(w.extX, pl.nqa));
         DFGT_TRY(grow<double>(w.extY, pl.nqa * pl.d));
@@ -2546,9 +2667,13 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
             fn((d + 3) / 4, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
                w.flag.as<int>(), jls, njobs, pl.unl, w.extE.as<double>(), gx, gy);
         } else if (pl.precision != DFGT_PREC_FP64) {
+            int *ord = w.eord.as<int>();
+            hipLaunchKernelGGL(k_eorder, dim3((unsigned)((pl.items + 255) / 256)), dim3(256), 0, ss, td, jd,
+                               w.egrp.as<Group>(), headE, w.flag.as<int>(), jls, njobs, pl.unl, pl.items,
+                               w.cnt.as<int>(), ord, ord + pl.items, ord + 2 * (size_t)pl.items);
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
-            fn(false, d, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
+            fn(false, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
+               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, ord, w.extE.as<double>(), gx, gy);
         }
         if (prof) prof->stop(K_EMFMA, ev, ss);
         {
@@ -2556,8 +2681,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
             // underflow guard flagged), added after the mixed pass
             ev = prof ? prof->start(ss) : nullptr;
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
-            fn(true, d, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, w.extE.as<double>(), gx, gy);
+            fn(true, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
+               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, nullptr, w.extE.as<double>(), gx, gy);
             if (prof) prof->stop(K_EF64, ev, ss);
         }
     }
@@ -2572,10 +2697,9 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
             hipLaunchKernelGGL(klo, dim3(kLocalGrid), dim3(64 * pl.lop_waves), pl.lop_sh, st, td, jd,
                                w.lgrp.as<Group>(), w.lops.as<Op>(), w.lopnode.as<int>(), w.cnt.as<int>(),
                                w.flag.as<int>(), w.part.as<double>());
-            hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(64), sizeof(double) * PW, st, jd, td,
+            hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(256), sizeof(double) * (PW + 256), st, jd,
                                w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
-                               w.lops.as<Op>(), w.part.as<double>(), PW, w.L.as<double>(),
-                               w.lflag.as<unsigned char>());
+                               w.part.as<double>(), PW, w.L.as<double>(), w.lflag.as<unsigned char>());
         } else {
             hipLaunchKernelGGL(k_local_big, dim3(kLocalGrid), dim3(kLocBlock), pl.big_sh, st, td, jd,
                                w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
