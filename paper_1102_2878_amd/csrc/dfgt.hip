@@ -2280,7 +2280,15 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
-        lnodes, cnt, lvl, flag, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval, gdg, gmt, eord;
+        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval, gdg, gmt, eord;
+    // overflow flag, counters and per-level counts in one allocation: one fill,
+    // one copy back
+    DevBuf ctl;
+    DevSpan flag, cnt, lvl;
+    // pinned staging of the plan upload and the read back; the upload's
+    // copies are complete once `upev` has been reached
+    HostBuf up, back;
+    hipEvent_t upev = nullptr;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
     int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
     // the exhaustive tiles run on a side stream beside the local-moment ops
@@ -2297,6 +2305,7 @@ struct Workspace {
         return DFGT_OK;
     }
     ~Workspace() {
+        if (upev) (void)hipEventDestroy(upev);
         if (fork) (void)hipEventDestroy(fork);
         if (join) (void)hipEventDestroy(join);
         if (side) (void)hipStreamDestroy(side);
@@ -2565,10 +2574,10 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<unsigned>(w.lflag, (nna + 3) / 4));
     DFGT_TRY(grow<double>(w.cval, nna));
     DFGT_TRY(grow<int>(w.heads, 3 * nna));
-    DFGT_TRY(grow<int>(w.cnt, C_N * CP));
-    DFGT_TRY(grow<int>(w.flag, 1));
+    DFGT_TRY(alloc_spans(w.ctl, {{&w.flag, sizeof(int) * CP},
+                                 {&w.cnt, sizeof(int) * C_N * CP},
+                                 {&w.lvl, sizeof(int) * (size_t)(pl.nlev + 1) * 2 * CP}}));
     DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
-    DFGT_TRY(grow<int>(w.lvl, (size_t)(pl.nlev + 1) * 2 * CP));
     // exhaustive sums per query (k_emfma or k_etile), added by k_leaf
     DFGT_TRY(grow<double>(w.extE, pl.nqa));
     DFGT_TRY(grow<int>(w.eord, 3 * (size_t)pl.items));  // dispatch order of the exhaustive tiles
@@ -2603,13 +2612,23 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     return DFGT_OK;
 }
 
+// The plan's tables go through pinned staging (the previous upload's copies
+// must have left it first), so the copies do not block the host.
 dfgt_status upload_plan(const Plan &pl, Workspace &w, hipStream_t st) {
-    DFGT_HIP(hipMemcpyAsync(w.jobs.as<Job>() + pl.job_off, pl.jobs.data(), sizeof(Job) * pl.njobs,
-                            hipMemcpyHostToDevice, st));
-    DFGT_HIP(hipMemcpyAsync(w.trees.p, pl.trees.data(), sizeof(DevTree) * pl.trees.size(), hipMemcpyHostToDevice,
-                            st));
-    DFGT_HIP(hipMemcpyAsync(w.jls.as<int>() + pl.jls_off, pl.jls.data(), sizeof(int) * pl.jls.size(),
-                            hipMemcpyHostToDevice, st));
+    const size_t bj = sizeof(Job) * pl.njobs, bt = sizeof(DevTree) * pl.trees.size(),
+                 bl = sizeof(int) * pl.jls.size();
+    const size_t oj = 0, ot = (bj + 255) / 256 * 256, ol = ot + (bt + 255) / 256 * 256;
+    if (!w.upev) DFGT_HIP(hipEventCreateWithFlags(&w.upev, hipEventDisableTiming));
+    DFGT_HIP(hipEventSynchronize(w.upev));
+    DFGT_TRY(w.up.reserve(ol + bl));
+    char *h = w.up.as<char>();
+    std::memcpy(h + oj, pl.jobs.data(), bj);
+    std::memcpy(h + ot, pl.trees.data(), bt);
+    std::memcpy(h + ol, pl.jls.data(), bl);
+    DFGT_HIP(hipMemcpyAsync(w.jobs.as<Job>() + pl.job_off, h + oj, bj, hipMemcpyHostToDevice, st));
+    DFGT_HIP(hipMemcpyAsync(w.trees.p, h + ot, bt, hipMemcpyHostToDevice, st));
+    DFGT_HIP(hipMemcpyAsync(w.jls.as<int>() + pl.jls_off, h + ol, bl, hipMemcpyHostToDevice, st));
+    DFGT_HIP(hipEventRecord(w.upev, st));
     return DFGT_OK;
 }
 
@@ -2631,9 +2650,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
     fill_u32(w.lflag.p, (nna + 3) / 4, 0u, st);
     fill_u32(w.cval.p, 2 * nna, 0u, st);
     fill_u32(w.heads.p, 3 * nna, 0xffffffffu, st);
-    fill_u32(w.cnt.p, C_N * CP, 0u, st);
-    fill_u32(w.lvl.p, (size_t)(nlev + 1) * 2 * CP, 0u, st);
-    fill_u32(w.flag.p, 1, 0u, st);
+    // flag, counters and this plan's level counts: one contiguous region
+    fill_u32(w.ctl.p, ((char *)w.lvl.p - (char *)w.ctl.p) / 4 + (size_t)(nlev + 1) * 2 * CP, 0u, st);
     fill_u32(w.stats.p, 2 * S_N * SP, 0u, st);
     hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
     if (!pl.dig_lds)
@@ -2730,11 +2748,15 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
 // the capacities for a rerun.
 dfgt_status read_back(const Plan &pl, Workspace &w, hipStream_t st, int *overflow, int *c) {
     const int nlev = pl.nlev;
-    std::vector<int> hc((size_t)C_N * CP), hl((size_t)(nlev + 1) * 2 * CP);
-    DFGT_HIP(hipMemcpyAsync(overflow, w.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipMemcpyAsync(hc.data(), w.cnt.p, sizeof(int) * hc.size(), hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipMemcpyAsync(hl.data(), w.lvl.p, sizeof(int) * hl.size(), hipMemcpyDeviceToHost, st));
+    const char *base = (const char *)w.ctl.p;
+    const size_t oc = (const char *)w.cnt.p - base, ol = (const char *)w.lvl.p - base,
+                 total = ol + sizeof(int) * (size_t)(nlev + 1) * 2 * CP;
+    DFGT_TRY(w.back.reserve(total));
+    DFGT_HIP(hipMemcpyAsync(w.back.p, w.ctl.p, total, hipMemcpyDeviceToHost, st));
     DFGT_HIP(hipStreamSynchronize(st));
+    const char *hb = w.back.as<const char>();
+    *overflow = *(const int *)hb;
+    const int *hc = (const int *)(hb + oc), *hl = (const int *)(hb + ol);
     for (int k = 0; k < C_N; ++k) c[k] = hc[(size_t)k * CP];
     if (!*overflow && hl[((size_t)nlev * 2 + C_SEG) * CP] != 0) {
         set_error("dfgt_gauss_sum: internal error, node pairs left after the last level");

@@ -79,6 +79,35 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned host memory for small transfers (allocated with hipHostMalloc, so
+// copies run as DMA without a staging pass and do not block the host).
+// Contents are not preserved on growth.
+struct HostBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    dfgt_status reserve(size_t need) {
+        if (need <= bytes) return DFGT_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t nb = need < 4096 ? 4096 : need;
+        if (hipHostMalloc(&p, nb, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            set_error("hipHostMalloc of " + std::to_string(nb) + " bytes failed");
+            return DFGT_ENOMEM;
+        }
+        bytes = nb;
+        return DFGT_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
 // A typed view into device memory owned elsewhere (an arena).
 struct DevSpan {
     void *p = nullptr;

@@ -154,6 +154,14 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
 }
 
 // Launches the direct kernel when (D, p_max) has an instance; false otherwise.
+// The values the host needs after the build, side by side: leaf count, largest
+// squared norm, the root's mu_0.
+__global__ void k_gather_back(const int *nl, const double *mx, const double *mu, double *out) {
+    out[0] = (double)*nl;
+    out[1] = *mx;
+    out[2] = mu[0];
+}
+
 bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double *x, const double *wts,
                            const double *ctr, const int32_t *begin, const int32_t *end, const int32_t *left,
                            double *mu) {
@@ -204,12 +212,12 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     }
     const int d = t->d, pmax = t->pmax, P = t->P;
     const int64_t m = t->m;
-    // the leaf count and the largest squared norm come back in one sync at the end
-    struct Back {
-        int nl;
-        double mx, w0;
-    };
-    static thread_local Back back;
+    // the leaf count, the largest squared norm and the root's mu_0 come back in
+    // one copy and one sync at the end
+    static thread_local DevBuf back_d;
+    static thread_local HostBuf back_h;
+    DFGT_TRY(back_d.reserve(sizeof(double) * 3));
+    DFGT_TRY(back_h.reserve(sizeof(double) * 3));
     const double *wts = t->w.as<double>();
     const bool direct = launch_moments_direct(d, pmax, (int)m, st, t->x.as<double>(), wts, t->ctr.as<double>(),
                                               t->begin.as<int32_t>(), t->end.as<int32_t>(), t->left.as<int32_t>(),
@@ -244,13 +252,15 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
         }
         DFGT_HIP(hipGetLastError());
     }
-    DFGT_HIP(hipMemcpyAsync(&back.nl, t->nleaves_dev.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipMemcpyAsync(&back.mx, t->nrm_max.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipMemcpyAsync(&back.w0, t->mu.p, sizeof(double), hipMemcpyDeviceToHost, st));  // root mu_0
+    hipLaunchKernelGGL(k_gather_back, dim3(1), dim3(1), 0, st, t->nleaves_dev.as<int>(), t->nrm_max.as<double>(),
+                       t->mu.as<double>(), back_d.as<double>());
+    DFGT_HIP(hipGetLastError());
+    DFGT_HIP(hipMemcpyAsync(back_h.p, back_d.p, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
     DFGT_HIP(hipStreamSynchronize(st));
-    t->nleaves = back.nl;
-    t->max_nrm = back.mx;
-    t->wsum = t->weighted ? back.w0 * t->wscale : (double)t->n;  // root mu_0 = sum of the stored weights
+    const double *back = back_h.as<double>();
+    t->nleaves = (int64_t)back[0];
+    t->max_nrm = back[1];
+    t->wsum = t->weighted ? back[2] * t->wscale : (double)t->n;  // root mu_0 = sum of the stored weights
     return DFGT_OK;
 }
 

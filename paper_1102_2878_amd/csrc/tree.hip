@@ -45,16 +45,21 @@ __global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *pe
     }
 }
 
+// Also clears the build's flags (ctl[0..3]) and writes level 0's record
+// (ctl[4..]: per level start, end, largest node).
 __global__ void k_init_root(long long *lo_key, long long *hi_key, int d, int32_t *begin, int32_t *end,
-                            int32_t *parent, int n) {
+                            int32_t *parent, int n, int *ctl) {
     for (int k = threadIdx.x; k < d; k += blockDim.x) {
         lo_key[k] = kPosInfKey;
         hi_key[k] = kNegInfKey;
     }
+    if (threadIdx.x < 4) ctl[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         begin[0] = 0;
         end[0] = n;
         parent[0] = -1;
+        ctl[4] = 0;
+        ctl[5] = 1;
     }
 }
 
@@ -217,15 +222,16 @@ __global__ __launch_bounds__(kLB) void k_flag(const double *__restrict__ x, cons
 // level nodes [lb, le): a node's left count is the difference of the global
 // left ranks at its end and begin; children are allocated at
 // le + 2 * (rank among splitting nodes).
-// Level bounds live on the device: level k is [lvs[2k], lvs[2k+1]); the
-// kernel writes level k+1's bounds, or sets *done when nothing splits (the
-// per-level kernels that follow then return at once).
+// Level records live on the device: level k is nodes [lvs[3k], lvs[3k+1]),
+// lvs[3k+2] its largest node; the kernel writes level k's largest node and
+// level k+1's bounds, or sets *done when nothing splits (the per-level
+// kernels that follow then return at once).
 __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs, int *done, int d, int leaf, int n,
                                                    long long *lo_key, long long *hi_key, int32_t *begin,
                                                    int32_t *end, int32_t *left, int32_t *right, int32_t *parent,
                                                    int32_t *sdim, double *scoord, int32_t *nleft,
                                                    const int32_t *__restrict__ rank, const int32_t *__restrict__ bsum,
-                                                   int nb, int32_t *boff, int32_t *lmax) {
+                                                   int nb, int32_t *boff) {
     __shared__ int warp_tot[16];
     __shared__ int carry_s;
     if (*done) return;
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
     // global exclusive left rank at a position (n: the total)
     auto grank = [&](int pos) { return pos >= n ? total : boff[pos / kLB] + rank[pos]; };
     // 2. splits and children
-    const int lb = lvs[2 * level], le = lvs[2 * level + 1];
+    const int lb = lvs[3 * level], le = lvs[3 * level + 1];
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     int big = 0;  // the level's largest node
@@ -312,10 +318,10 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 1; k < (int)(blockDim.x / 64); ++k) big = max(big, warp_tot[k]);
-        lmax[level] = big;
+        lvs[3 * level + 2] = big;
         const int newc = 2 * carry_s;
-        lvs[2 * level + 2] = le;
-        lvs[2 * level + 3] = le + newc;
+        lvs[3 * level + 3] = le;
+        lvs[3 * level + 4] = le + newc;
         if (newc == 0 || le + newc > cap) *done = newc == 0 ? 1 : 2;  // 2: capacity exceeded (internal error)
     }
 }
@@ -418,7 +424,9 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
 
 // Scratch of the build, kept per host thread and reused across builds.
 struct BuildWs {
-    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft, counter, lvs, lmax;
+    DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft;
+    DevBuf ctl;   // [0] done flag, [1] non-finite flag, [2..3] unused, then per level start, end, largest node
+    HostBuf back;  // pinned copy of ctl
 };
 thread_local BuildWs g_build;
 
@@ -428,7 +436,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     BuildWs &w = g_build;
     DevBuf &perm_b = w.perm_b, &x_b = w.x_b, &pnode_a = w.pnode_a, &pnode_b = w.pnode_b, &flag = w.flag,
            &rank = w.rank, &bsums = w.bsums, &boff = w.boff, &lo_key = w.lo_key, &hi_key = w.hi_key,
-           &nleft = w.nleft, &counter = w.counter, &lvs_b = w.lvs;
+           &nleft = w.nleft;
     DFGT_TRY(alloc_spans(t->arena0, {{&t->perm, sizeof(int32_t) * n},
                                      {&t->x, sizeof(double) * (size_t)n * d},
                                      {&t->begin, sizeof(int32_t) * cap},
@@ -451,24 +459,19 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     DFGT_TRY(lo_key.reserve(sizeof(long long) * (size_t)cap * d));
     DFGT_TRY(hi_key.reserve(sizeof(long long) * (size_t)cap * d));
     DFGT_TRY(nleft.reserve(sizeof(int32_t) * cap));
-    DFGT_TRY(counter.reserve(sizeof(int) * 4));
-    // level bounds: a tree on n points has at most n levels (every split
+    // level records: a tree on n points has at most n levels (every split
     // leaves fewer points on each side)
     const int max_levels = n + 1;
-    DFGT_TRY(lvs_b.reserve(sizeof(int) * 2 * ((size_t)max_levels + 1)));
-    DFGT_TRY(w.lmax.reserve(sizeof(int) * ((size_t)max_levels + 1)));
+    DFGT_TRY(w.ctl.reserve(sizeof(int) * (4 + 3 * ((size_t)max_levels + 1))));
 
     int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
     double *xa = t->x.as<double>(), *xb = x_b.as<double>();
     int32_t *na = pnode_a.as<int32_t>(), *nb = pnode_b.as<int32_t>();
-    int *cnt_d = counter.as<int>();  // [0] done flag, [1] non-finite flag, [2] leaf count
-    int *lvs = lvs_b.as<int>();
-    const int lvs0[2] = {0, 1};
-    DFGT_HIP(hipMemsetAsync(cnt_d, 0, sizeof(int) * 4, st));
-    DFGT_HIP(hipMemcpyAsync(lvs, lvs0, sizeof(lvs0), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_init, dim3(gb), dim3(kLB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
+    int *cnt_d = w.ctl.as<int>();  // [0] done flag, [1] non-finite flag
+    int *lvs = cnt_d + 4;
     hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
-                       t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(), n);
+                       t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(), n, cnt_d);
+    hipLaunchKernelGGL(k_init, dim3(gb), dim3(kLB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
     hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kLB), 0, st, xa, n, d, lo_key.as<long long>(),
                        hi_key.as<long long>());
     DFGT_HIP(hipGetLastError());
@@ -485,7 +488,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     // size) starts with the depth seen last time: usually one batch, one sync
     static thread_local struct { int64_t n; int d, leaf, depth; } last{-1, 0, 0, 0};
     if (last.n == n && last.d == d && last.leaf == leaf) batch = std::max(batch, last.depth + 2);
-    std::vector<int> hl;
+    const int *hl = nullptr;  // level records in the pinned copy: start, end, largest node
     while (!done && level < max_levels) {
         const int stop = std::min(max_levels, level + batch);
         for (; level < stop; ++level) {
@@ -500,20 +503,20 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
                                t->end.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(),
                                t->parent.as<int32_t>(), t->sdim.as<int32_t>(), t->scoord.as<double>(),
                                nleft.as<int32_t>(), rank.as<int32_t>(), bsums.as<int32_t>(), gb,
-                               boff.as<int32_t>(), w.lmax.as<int32_t>());
+                               boff.as<int32_t>());
             hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(kLB), 0, st, n, d, nin, pin, xin, flag.as<int32_t>(),
                                rank.as<int32_t>(), boff.as<int32_t>(), t->begin.as<int32_t>(),
                                nleft.as<int32_t>(), t->left.as<int32_t>(), t->right.as<int32_t>(), nout, pout,
                                xout, lo_key.as<long long>(), hi_key.as<long long>(), cnt_d);
             DFGT_HIP(hipGetLastError());
         }
-        int flags[2] = {0, 0};
-        hl.resize(2 * (size_t)(level + 1));
-        t->level_max.resize((size_t)level);
-        DFGT_HIP(hipMemcpyAsync(flags, cnt_d, sizeof(flags), hipMemcpyDeviceToHost, st));
-        DFGT_HIP(hipMemcpyAsync(hl.data(), lvs, sizeof(int) * hl.size(), hipMemcpyDeviceToHost, st));
-        DFGT_HIP(hipMemcpyAsync(t->level_max.data(), w.lmax.p, sizeof(int) * level, hipMemcpyDeviceToHost, st));
+        // flags and the records of levels 0 .. level, one copy
+        const size_t nback = sizeof(int) * (4 + 3 * ((size_t)level + 1));
+        DFGT_TRY(w.back.reserve(nback));
+        DFGT_HIP(hipMemcpyAsync(w.back.p, cnt_d, nback, hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
+        const int *flags = w.back.as<int>();
+        hl = flags + 4;
         if (flags[1]) {
             set_error("dfgt_build_tree: points contain a non-finite coordinate");
             return DFGT_EINVAL;
@@ -532,11 +535,14 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     // level bounds (read with the last batch's flags): levels 0 .. K, K the
     // first level without a split
     int K = 0;
-    while (K + 1 <= level && hl[2 * (size_t)K + 3] > hl[2 * (size_t)K + 1]) ++K;
+    while (K + 1 <= level && hl[3 * (size_t)K + 4] > hl[3 * (size_t)K + 1]) ++K;
     t->level_start.assign(1, 0);
-    for (int k = 0; k <= K; ++k) t->level_start.push_back(hl[2 * (size_t)k + 1]);
-    t->level_max.resize((size_t)K + 1);
-    const int le = hl[2 * (size_t)K + 1];
+    t->level_max.assign((size_t)K + 1, 0);
+    for (int k = 0; k <= K; ++k) {
+        t->level_start.push_back(hl[3 * (size_t)k + 1]);
+        t->level_max[k] = hl[3 * (size_t)k + 2];
+    }
+    const int le = hl[3 * (size_t)K + 1];
     if (K & 1) {
         pa = perm_b.as<int32_t>();
         xa = x_b.as<double>();
