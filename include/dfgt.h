@@ -133,7 +133,11 @@ const char *dfgt_version(void);
  * The call also computes the node's raw far-field moments (Alg. DFGTInitR:
  * AccumulateFarFieldMoment at leaves, TransFarToFar upwards).
  * Errors: n < 1, d < 1 or d > 32, p_max^d > 8192, non-finite input, a
- * non-zero reserved field -> DFGT_EINVAL.  Synchronises the stream.
+ * non-zero reserved field -> DFGT_EINVAL.  The call waits for the tree's
+ * structure (it reads the levels back); the moments and the device view are
+ * still queued on the stream when it returns.  Work on the same stream sees
+ * them; work on another stream must wait for this one.  pts_dev is no longer
+ * read after the call returns.
  */
 dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const dfgt_options *opt,
                             void *stream, dfgt_tree *out);
@@ -153,7 +157,9 @@ dfgt_status dfgt_build_tree(const double *pts_dev, int64_t n, int32_t d, const d
  * query tree its weights are ignored.  The cross-validation calls
  * (dfgt_lscv_score, dfgt_lcv_score, dfgt_lscv_optimize) reject it.
  * Errors: those of dfgt_build_tree; w_dev NULL, a negative or non-finite
- * weight, or all weights zero -> DFGT_EINVAL.  Synchronises the stream.
+ * weight, or all weights zero -> DFGT_EINVAL.  Waits for the stream twice
+ * more than dfgt_build_tree (the weights' maximum, then their total), so
+ * w_dev is no longer read after the call returns.
  */
 dfgt_status dfgt_build_tree_weighted(const double *pts_dev, const double *w_dev, int64_t n, int32_t d,
                                      const dfgt_options *opt, void *stream, dfgt_tree *out);

@@ -122,6 +122,8 @@ dfgt_status pool_get(DevBuf &b, size_t need, hipStream_t st) {
 
 namespace dfgt {
 namespace {
+__global__ void k_store_view(DevTree v, DevTree *dst) { *dst = v; }
+
 // One pass over the weights: a block-wide fold, then one atomic per block and
 // quantity (same-address device atomics serialise).  flag |= 1 for a negative
 // or non-finite weight; *mx = the largest weight as its bit pattern (the order
@@ -275,12 +277,12 @@ static dfgt_status build_common(const double *pts_dev, const double *w_dev, doub
         v.lplen = t->lplen.as<int32_t>();
         v.w = t->w.as<double>();
         t->host_view = v;
-        {  // the view's storage was carved out with the moments
-            if (hipMemcpyAsync(t->view.p, &v, sizeof(DevTree), hipMemcpyHostToDevice, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess) {
-                set_error("dfgt_build_tree: copying the tree view failed");
-                s = DFGT_EHIP;
-            }
+        // the view's storage was carved out with the moments; it is written by
+        // a kernel that takes it as its argument, so the host does not wait
+        hipLaunchKernelGGL(k_store_view, dim3(1), dim3(1), 0, st, v, t->view.as<DevTree>());
+        if (hipGetLastError() != hipSuccess) {
+            set_error("dfgt_build_tree: writing the tree view failed");
+            s = DFGT_EHIP;
         }
     }
     if (s != DFGT_OK) {

@@ -154,14 +154,6 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
 }
 
 // Launches the direct kernel when (D, p_max) has an instance; false otherwise.
-// The values the host needs after the build, side by side: leaf count, largest
-// squared norm, the root's mu_0.
-__global__ void k_gather_back(const int *nl, const double *mx, const double *mu, double *out) {
-    out[0] = (double)*nl;
-    out[1] = *mx;
-    out[2] = mu[0];
-}
-
 bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double *x, const double *wts,
                            const double *ctr, const int32_t *begin, const int32_t *end, const int32_t *left,
                            double *mu) {
@@ -185,39 +177,31 @@ bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double 
 
 // Squared norms of the points (tree order) and their maximum (ordered-int max
 // of non-negative doubles); the matrix-core exhaustive tiles read them.
-__global__ void k_tree_sqnorm(const double *__restrict__ x, int n, int d, double *__restrict__ out,
-                              unsigned long long *__restrict__ mx) {
+__global__ void k_tree_sqnorm(const double *__restrict__ x, int n, int d, double *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     double v = 0.0;
-    if (i < n) {
-        for (int k = 0; k < d; ++k) v = fma(x[(size_t)i * d + k], x[(size_t)i * d + k], v);
-        out[i] = v;
-    }
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(mx, (unsigned long long)__double_as_longlong(v));
+    for (int k = 0; k < d; ++k) v = fma(x[(size_t)i * d + k], x[(size_t)i * d + k], v);
+    out[i] = v;
 }
 
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     {
         const int n = (int)t->n;
         DFGT_TRY(alloc_spans(t->arena2, {{&t->nrm, sizeof(double) * (size_t)n},
-                                         {&t->nrm_max, sizeof(unsigned long long)},
                                          {&t->mu, sizeof(double) * (size_t)t->m * t->P},
                                          {&t->view, sizeof(DevTree)}},
                                 st, true));
-        DFGT_HIP(hipMemsetAsync(t->nrm_max.p, 0, sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_tree_sqnorm, dim3((n + 255) / 256), dim3(256), 0, st, t->x.as<double>(), n, t->d,
-                           t->nrm.as<double>(), t->nrm_max.as<unsigned long long>());
+                           t->nrm.as<double>());
         DFGT_HIP(hipGetLastError());
     }
     const int d = t->d, pmax = t->pmax, P = t->P;
     const int64_t m = t->m;
-    // the leaf count, the largest squared norm and the root's mu_0 come back in
-    // one copy and one sync at the end
-    static thread_local DevBuf back_d;
+    // the build has the leaf count and the largest squared norm; only a
+    // weighted tree reads a value back (the root's mu_0, its total weight)
     static thread_local HostBuf back_h;
-    DFGT_TRY(back_d.reserve(sizeof(double) * 3));
-    DFGT_TRY(back_h.reserve(sizeof(double) * 3));
+    DFGT_TRY(back_h.reserve(sizeof(double)));
     const double *wts = t->w.as<double>();
     const bool direct = launch_moments_direct(d, pmax, (int)m, st, t->x.as<double>(), wts, t->ctr.as<double>(),
                                               t->begin.as<int32_t>(), t->end.as<int32_t>(), t->left.as<int32_t>(),
@@ -252,15 +236,13 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
         }
         DFGT_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_gather_back, dim3(1), dim3(1), 0, st, t->nleaves_dev.as<int>(), t->nrm_max.as<double>(),
-                       t->mu.as<double>(), back_d.as<double>());
-    DFGT_HIP(hipGetLastError());
-    DFGT_HIP(hipMemcpyAsync(back_h.p, back_d.p, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
-    DFGT_HIP(hipStreamSynchronize(st));
-    const double *back = back_h.as<double>();
-    t->nleaves = (int64_t)back[0];
-    t->max_nrm = back[1];
-    t->wsum = t->weighted ? back[2] * t->wscale : (double)t->n;  // root mu_0 = sum of the stored weights
+    if (t->weighted) {
+        DFGT_HIP(hipMemcpyAsync(back_h.p, t->mu.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        DFGT_HIP(hipStreamSynchronize(st));
+        t->wsum = back_h.as<double>()[0] * t->wscale;  // root mu_0 = sum of the stored weights
+    } else {
+        t->wsum = (double)t->n;
+    }
     return DFGT_OK;
 }
 

@@ -22,6 +22,7 @@
 // dimensions, split coordinates and permutation); only node numbering differs
 // (breadth-first instead of pre-order).
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "dfgt_internal.h"
@@ -142,15 +143,30 @@ __device__ void block_box_fold(bool active, int node, const double *v, int d, lo
     }
 }
 
+// The root's box, and the largest squared norm |x|^2 of the points (folded
+// per block, one atomic per block on its bit pattern: non-negative doubles
+// order like their patterns).
 __global__ __launch_bounds__(kLB) void k_root_box(const double *__restrict__ x, int n, int d, long long *lo_key,
-                                                  long long *hi_key) {
+                                                  long long *hi_key, unsigned long long *nrm_max) {
     __shared__ FoldShared sh;
+    __shared__ double wmx[kLB / 64];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[kMaxD];
     const bool act = i < n;
+    double nv = 0.0;
     if (act)
-        for (int k = 0; k < d; ++k) v[k] = x[(size_t)i * d + k];
-    block_box_fold(act, 0, v, d, lo_key, hi_key, sh);
+        for (int k = 0; k < d; ++k) {
+            v[k] = x[(size_t)i * d + k];
+            nv = fma(v[k], v[k], nv);
+        }
+    for (int off = 32; off >= 1; off >>= 1) nv = fmax(nv, __shfl_xor(nv, off, 64));
+    if ((threadIdx.x & 63) == 0) wmx[threadIdx.x >> 6] = nv;
+    block_box_fold(act, 0, v, d, lo_key, hi_key, sh);  // holds block barriers: wmx is complete after it
+    if (threadIdx.x == 0) {
+        double m = wmx[0];
+        for (int w = 1; w < kLB / 64; ++w) m = fmax(m, wmx[w]);
+        atomicMax(nrm_max, (unsigned long long)__double_as_longlong(m));
+    }
 }
 
 // Split rule of one node; returns false if the node is a leaf before counting.
@@ -425,7 +441,8 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
 // Scratch of the build, kept per host thread and reused across builds.
 struct BuildWs {
     DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft;
-    DevBuf ctl;   // [0] done flag, [1] non-finite flag, [2..3] unused, then per level start, end, largest node
+    DevBuf ctl;   // [0] done flag, [1] non-finite flag, [2..3] largest |x|^2 (bit pattern), then per level
+                  // start, end, largest node
     HostBuf back;  // pinned copy of ctl
 };
 thread_local BuildWs g_build;
@@ -467,13 +484,13 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
     double *xa = t->x.as<double>(), *xb = x_b.as<double>();
     int32_t *na = pnode_a.as<int32_t>(), *nb = pnode_b.as<int32_t>();
-    int *cnt_d = w.ctl.as<int>();  // [0] done flag, [1] non-finite flag
+    int *cnt_d = w.ctl.as<int>();  // [0] done flag, [1] non-finite flag, [2..3] largest |x|^2
     int *lvs = cnt_d + 4;
     hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
                        t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(), n, cnt_d);
     hipLaunchKernelGGL(k_init, dim3(gb), dim3(kLB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
     hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kLB), 0, st, xa, n, d, lo_key.as<long long>(),
-                       hi_key.as<long long>());
+                       hi_key.as<long long>(), reinterpret_cast<unsigned long long *>(cnt_d + 2));
     DFGT_HIP(hipGetLastError());
 
     // Levels are enqueued in batches without host round trips: the first
@@ -526,6 +543,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
             return DFGT_EHIP;
         }
         done = flags[0];
+        std::memcpy(&t->max_nrm, flags + 2, sizeof(double));
         batch = 4;
     }
     if (!done) {
@@ -549,6 +567,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     }
     const int m = le;
     t->m = m;
+    t->nleaves = (m + 1) / 2;  // every split makes two children
     t->depth = (int)t->level_start.size() - 1;
     last = {n, d, leaf, t->depth};
     // the final permutation / points live in pa / xa
