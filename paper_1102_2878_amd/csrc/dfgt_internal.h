@@ -182,7 +182,7 @@ struct dfgt_tree_s {
     // arena0: point and node-capacity arrays; arena1: per-node and per-leaf
     // arrays sized after the build; arena2: moments, norms and the device view
     dfgt::DevBuf arena0, arena1, arena2;
-    dfgt::DevSpan lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm,
+    dfgt::DevSpan lo, hi, ctr, begin, end, left, right, parent, sdim, scoord, leaves, x, perm, mu, nrm, mpart,
         lpath, lplen, nleaves_dev, w;
     double max_nrm = 0.0;  // max |x|^2 (valid after dfgt_build_tree returns)
     hipStream_t stream = nullptr;  // the stream the tree was built on

@@ -153,6 +153,122 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
     }
 }
 
+// Internal nodes above kMomDirectMax points (the top levels): the same direct
+// sums over chunks of kMomDirectMax points, one wave per (node, chunk) for all
+// these levels in one launch, then one block per node adds its chunks'
+// partial moments in chunk order.  Levels in the table: nodes [lb, le), nch
+// chunks per node (from the level's largest node), blocks [boff, boff + (le -
+// lb) nch) of the chunk launch; a node block b of the reduce launch maps the
+// same way with one block per node.
+constexpr int kMomLevels = 32;
+struct MomLevels {
+    int n;
+    int lb[kMomLevels], le[kMomLevels], nch[kMomLevels], boff[kMomLevels + 1], noff[kMomLevels + 1];
+};
+
+template <int D, int PM>
+__global__ __launch_bounds__(64) void k_moments_chunk(const double *__restrict__ x, const double *__restrict__ wts,
+                                                      const double *__restrict__ ctr,
+                                                      const int32_t *__restrict__ begin,
+                                                      const int32_t *__restrict__ end,
+                                                      const int32_t *__restrict__ left, MomLevels lv,
+                                                      double *__restrict__ part) {
+    constexpr int P = ipow_c(PM, D);
+    const int blk = blockIdx.x;
+    int l = 0;
+    while (blk >= lv.boff[l + 1]) ++l;
+    const int idx = blk - lv.boff[l], node = lv.lb[l] + idx / lv.nch[l], ch = idx % lv.nch[l];
+    const int b = begin[node], e = end[node];
+    if (e - b <= kMomDirectMax || left[node] < 0) return;  // k_moments_direct's node
+    const int cb = b + ch * kMomDirectMax, ce = min(e, cb + kMomDirectMax);
+    double c[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) c[k] = ctr[(size_t)node * D + k];
+    double acc[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) acc[i] = 0.0;
+    for (int j = cb + (int)threadIdx.x; j < ce; j += 64) {
+        double pw[D][PM];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double dx = x[(size_t)j * D + k] - c[k];
+            pw[k][0] = k == 0 && wts ? wts[j] : 1.0;
+#pragma unroll
+            for (int a = 1; a < PM; ++a) pw[k][a] = pw[k][a - 1] * dx / (double)a;
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            double t = 1.0;
+            int r = i;
+#pragma unroll
+            for (int k = D - 1; k >= 0; --k) {
+                t *= pw[k][r % PM];
+                r /= PM;
+            }
+            acc[i] += t;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const double v = wave_sum(acc[i]);
+        if (threadIdx.x == i) part[(size_t)blk * P + i] = v;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_moments_chunk_sum(const int32_t *__restrict__ begin,
+                                                          const int32_t *__restrict__ end,
+                                                          const int32_t *__restrict__ left, MomLevels lv, int P,
+                                                          const double *__restrict__ part, double *__restrict__ mu) {
+    const int nb = blockIdx.x;
+    int l = 0;
+    while (nb >= lv.noff[l + 1]) ++l;
+    const int node = lv.lb[l] + (nb - lv.noff[l]);
+    const int b = begin[node], e = end[node];
+    if (e - b <= kMomDirectMax || left[node] < 0) return;
+    const int nc = (e - b + kMomDirectMax - 1) / kMomDirectMax;  // chunks that hold points (<= nch)
+    const size_t p0 = (size_t)lv.boff[l] + (size_t)(nb - lv.noff[l]) * lv.nch[l];
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        double v = 0.0;
+        for (int k = 0; k < nc; ++k) v += part[(p0 + k) * P + i];
+        mu[(size_t)node * P + i] = v;
+    }
+}
+
+// Launches the chunked direct kernels when (D, p_max) has an instance.
+bool launch_moments_chunks(int d, int pmax, int P, const MomLevels &lv, hipStream_t st, const double *x,
+                           const double *wts, const double *ctr, const int32_t *begin, const int32_t *end,
+                           const int32_t *left, double *part, double *mu) {
+    const unsigned nblk = (unsigned)lv.boff[lv.n], nnode = (unsigned)lv.noff[lv.n];
+#define DFGT_MOMC(DV, PV)                                                                                       \
+    if (d == DV && pmax == PV) {                                                                                \
+        hipLaunchKernelGGL((k_moments_chunk<DV, PV>), dim3(nblk), dim3(64), 0, st, x, wts, ctr, begin, end, left, \
+                           lv, part);                                                                           \
+        hipLaunchKernelGGL(k_moments_chunk_sum, dim3(nnode), dim3(64), 0, st, begin, end, left, lv, P, part, mu);  \
+        return true;                                                                                            \
+    }
+    DFGT_MOMC(1, 1) DFGT_MOMC(1, 2) DFGT_MOMC(1, 4) DFGT_MOMC(1, 6) DFGT_MOMC(1, 8)
+    DFGT_MOMC(2, 1) DFGT_MOMC(2, 2) DFGT_MOMC(2, 4) DFGT_MOMC(2, 6) DFGT_MOMC(2, 8)
+    DFGT_MOMC(3, 1) DFGT_MOMC(3, 2) DFGT_MOMC(3, 4)
+    DFGT_MOMC(4, 1) DFGT_MOMC(4, 2)
+    DFGT_MOMC(5, 1) DFGT_MOMC(5, 2)
+    DFGT_MOMC(6, 1) DFGT_MOMC(6, 2)
+#undef DFGT_MOMC
+    return false;
+}
+
+// Whether (D, p_max) has direct-moment instances (the lists below).
+bool moments_direct_available(int d, int pmax) {
+    switch (d) {
+    case 1:
+    case 2: return pmax == 1 || pmax == 2 || pmax == 4 || pmax == 6 || pmax == 8;
+    case 3: return pmax == 1 || pmax == 2 || pmax == 4;
+    case 4:
+    case 5:
+    case 6: return pmax == 1 || pmax == 2;
+    default: return false;
+    }
+}
+
 // Launches the direct kernel when (D, p_max) has an instance; false otherwise.
 bool launch_moments_direct(int d, int pmax, int m, hipStream_t st, const double *x, const double *wts,
                            const double *ctr, const int32_t *begin, const int32_t *end, const int32_t *left,
@@ -186,11 +302,34 @@ __global__ void k_tree_sqnorm(const double *__restrict__ x, int n, int d, double
 }
 
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
+    // Levels holding a node above kMomDirectMax points take chunked direct sums
+    // (up to kMomLevels of them, and when (D, p_max) has a direct instance);
+    // any others translate.  The chunk partials live in the tree's own memory:
+    // the build returns with this work still queued.
+    const bool has_direct = moments_direct_available(t->d, t->pmax);
+    std::vector<char> chunked(t->level_start.size(), 0);
+    MomLevels lv{};
+    size_t nblk = 0;
+    for (int l = 0; has_direct && l + 1 < (int)t->level_start.size() && lv.n < kMomLevels; ++l) {
+        const int lb = t->level_start[l], le = t->level_start[l + 1];
+        if (le <= lb || t->level_max[l] <= kMomDirectMax) continue;
+        const int nch = (t->level_max[l] + kMomDirectMax - 1) / kMomDirectMax;
+        if (nblk + (size_t)(le - lb) * nch > (1u << 20)) break;  // the rest translate
+        lv.lb[lv.n] = lb;
+        lv.le[lv.n] = le;
+        lv.nch[lv.n] = nch;
+        lv.boff[lv.n] = (int)nblk;
+        lv.noff[lv.n + 1] = lv.noff[lv.n] + (le - lb);
+        nblk += (size_t)(le - lb) * nch;
+        lv.boff[++lv.n] = (int)nblk;
+        chunked[l] = 1;
+    }
     {
         const int n = (int)t->n;
         DFGT_TRY(alloc_spans(t->arena2, {{&t->nrm, sizeof(double) * (size_t)n},
                                          {&t->mu, sizeof(double) * (size_t)t->m * t->P},
-                                         {&t->view, sizeof(DevTree)}},
+                                         {&t->view, sizeof(DevTree)},
+                                         {&t->mpart, sizeof(double) * nblk * t->P}},
                                 st, true));
         hipLaunchKernelGGL(k_tree_sqnorm, dim3((n + 255) / 256), dim3(256), 0, st, t->x.as<double>(), n, t->d,
                            t->nrm.as<double>());
@@ -211,7 +350,11 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
                            t->ctr.as<double>(), t->begin.as<int32_t>(), t->end.as<int32_t>(), t->leaves.as<int32_t>(),
                            t->nleaves_dev.as<int>(), d, pmax, P, t->mu.as<double>());
     DFGT_HIP(hipGetLastError());
-    // with the direct pass, only levels holding a node above its size limit translate
+    if (direct && lv.n > 0) {
+        launch_moments_chunks(d, pmax, P, lv, st, t->x.as<double>(), wts, t->ctr.as<double>(), t->begin.as<int32_t>(),
+                              t->end.as<int32_t>(), t->left.as<int32_t>(), t->mpart.as<double>(), t->mu.as<double>());
+        DFGT_HIP(hipGetLastError());
+    }
     const int skip = direct ? kMomDirectMax : 0;
     const bool lds = (size_t)(2 * P + pmax * pmax) * sizeof(double) <= 48 * 1024;
     static thread_local DevBuf scratch;  // reused across builds (freeing it would stall the device)
@@ -222,7 +365,7 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     for (int l = t->depth - 2; l >= 0; --l) {
         const int lb = t->level_start[l], le = t->level_start[l + 1];
         if (le <= lb) continue;
-        if (direct && t->level_max[l] <= kMomDirectMax) continue;
+        if (direct && (t->level_max[l] <= kMomDirectMax || chunked[l])) continue;
         if (lds) {
             size_t sh = sizeof(double) * (2 * P + pmax * pmax);
             hipLaunchKernelGGL(k_f2f<true>, dim3(le - lb), dim3(256), sh, st, lb, le, t->left.as<int32_t>(),
@@ -236,6 +379,13 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
         }
         DFGT_HIP(hipGetLastError());
     }
+    // the global F2F scratch is shared by the builds of this thread: wait
+    // before another build can reuse it (the large-P path only)
+    bool used_scratch = false;
+    for (int l = t->depth - 2; l >= 0 && !lds; --l)
+        if (t->level_start[l + 1] > t->level_start[l] && !(direct && (t->level_max[l] <= kMomDirectMax || chunked[l])))
+            used_scratch = true;
+    if (used_scratch && !t->weighted) DFGT_HIP(hipStreamSynchronize(st));
     if (t->weighted) {
         DFGT_HIP(hipMemcpyAsync(back_h.p, t->mu.p, sizeof(double), hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
