@@ -2632,6 +2632,33 @@ dfgt_status upload_plan(const Plan &pl, Workspace &w, hipStream_t st) {
     return DFGT_OK;
 }
 
+// Several fills in one launch: region r is words[r] u32 values v[r] at p[r];
+// block b takes the kFillChunk words from b * kFillChunk of the regions laid
+// end to end.
+constexpr int kFillN = 6, kFillChunk = 4096;
+struct FillSet {
+    unsigned *p[kFillN];
+    unsigned long long words[kFillN], start[kFillN + 1];
+    unsigned v[kFillN];
+    int n;
+};
+__global__ void k_fill_many(FillSet fs) {
+    const unsigned long long c0 = (unsigned long long)blockIdx.x * kFillChunk;
+    for (int r = 0; r < fs.n; ++r) {
+        const unsigned long long lo = fs.start[r], hi = fs.start[r + 1];
+        if (hi <= c0 || lo >= c0 + kFillChunk) continue;
+        const unsigned long long a = lo > c0 ? lo : c0, b = hi < c0 + kFillChunk ? hi : c0 + kFillChunk;
+        for (unsigned long long i = a + threadIdx.x; i < b; i += blockDim.x) fs.p[r][i - lo] = fs.v[r];
+    }
+}
+void fill_many(FillSet fs, hipStream_t st) {
+    fs.start[0] = 0;
+    for (int r = 0; r < fs.n; ++r) fs.start[r + 1] = fs.start[r] + fs.words[r];
+    const unsigned long long tot = fs.start[fs.n];
+    const unsigned blocks = (unsigned)std::max<unsigned long long>((tot + kFillChunk - 1) / kFillChunk, 1);
+    hipLaunchKernelGGL(k_fill_many, dim3(blocks), dim3(256), 0, st, fs);
+}
+
 void fill_u32(void *p, size_t words, unsigned v, hipStream_t st) {
     const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill_u32, dim3(std::max(blocks, 1u)), dim3(256), 0, st, (unsigned *)p, words, v);
@@ -2647,12 +2674,22 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
     const Job *jd = w.jobs.as<Job>() + pl.job_off;
     const int *jls = w.jls.as<int>() + pl.jls_off;
     int *lvl = w.lvl.as<int>();
-    fill_u32(w.lflag.p, (nna + 3) / 4, 0u, st);
-    fill_u32(w.cval.p, 2 * nna, 0u, st);
-    fill_u32(w.heads.p, 3 * nna, 0xffffffffu, st);
-    // flag, counters and this plan's level counts: one contiguous region
-    fill_u32(w.ctl.p, ((char *)w.lvl.p - (char *)w.ctl.p) / 4 + (size_t)(nlev + 1) * 2 * CP, 0u, st);
-    fill_u32(w.stats.p, 2 * S_N * SP, 0u, st);
+    {  // node flags, centroid scalars, chain heads (-1), flag / counters / level counts, statistics
+        FillSet fs{};
+        fs.n = 5;
+        fs.p[0] = (unsigned *)w.lflag.p;
+        fs.words[0] = (nna + 3) / 4;
+        fs.p[1] = (unsigned *)w.cval.p;
+        fs.words[1] = 2 * nna;
+        fs.p[2] = (unsigned *)w.heads.p;
+        fs.words[2] = 3 * nna;
+        fs.v[2] = 0xffffffffu;
+        fs.p[3] = (unsigned *)w.ctl.p;
+        fs.words[3] = ((char *)w.lvl.p - (char *)w.ctl.p) / 4 + (size_t)(nlev + 1) * 2 * CP;
+        fs.p[4] = (unsigned *)w.stats.p;
+        fs.words[4] = 2 * S_N * SP;
+        fill_many(fs, st);
+    }
     hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
     if (!pl.dig_lds)
         hipLaunchKernelGGL(k_digits, dim3((P + 255) / 256), dim3(256), 0, st, w.gdg.as<unsigned long long>(),

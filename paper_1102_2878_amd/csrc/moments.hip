@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_f2f(int lb, int le, const int32_t *__re
 // tree order and keeps all P partial sums in registers; the wave adds them in
 // a fixed butterfly order.  Internal nodes with more than kMomDirectMax points
 // are left to TransFarToFar from their children.
-constexpr int kMomDirectMax = 2048;
+constexpr int kMomDirectMax = 512;
 
 template <int D, int PM>
 __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict__ x, const double *__restrict__ wts,
@@ -154,7 +154,8 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
 }
 
 // Internal nodes above kMomDirectMax points (the top levels): the same direct
-// sums over chunks of kMomDirectMax points, one wave per (node, chunk) for all
+// sums over chunks of kMomDirectMax points (a wave's sums take time in
+// proportion to its points, so chunks keep the launch short), one wave per (node, chunk) for all
 // these levels in one launch, then one block per node adds its chunks'
 // partial moments in chunk order.  Levels in the table: nodes [lb, le), nch
 // chunks per node (from the level's largest node), blocks [boff, boff + (le -
