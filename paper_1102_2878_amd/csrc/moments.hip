@@ -109,6 +109,29 @@ __global__ __launch_bounds__(256) void k_f2f(int lb, int le, const int32_t *__re
 // are left to TransFarToFar from their children.
 constexpr int kMomDirectMax = 512;
 
+// Sum over the 64 lanes of each of the P per-lane partials acc[i], written to
+// out[i]: the partials go through LDS (row per lane, padded against bank
+// conflicts) and lane i adds column i in lane order, four loads at a time.
+// A butterfly per coefficient would chain 6 P dependent cross-lane steps.
+template <int P>
+__device__ __forceinline__ void wave_sum_rows(const double (&acc)[P], double (*red)[P + 1], double *out) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < P; ++i) red[lane][i] = acc[i];
+    __syncthreads();
+    for (int i = lane; i < P; i += 64) {
+        double v = 0.0;
+        for (int r = 0; r < 64; r += 4) {
+            const double a = red[r][i], b = red[r + 1][i], c = red[r + 2][i], e = red[r + 3][i];
+            v += a;
+            v += b;
+            v += c;
+            v += e;
+        }
+        out[i] = v;
+    }
+}
+
 template <int D, int PM>
 __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict__ x, const double *__restrict__ wts,
                                                        const double *__restrict__ ctr,
@@ -146,11 +169,8 @@ __global__ __launch_bounds__(64) void k_moments_direct(const double *__restrict_
             acc[i] += t;
         }
     }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const double v = wave_sum(acc[i]);
-        if (threadIdx.x == i) mu[(size_t)node * P + i] = v;
-    }
+    __shared__ double red[64][P + 1];
+    wave_sum_rows<P>(acc, red, mu + (size_t)node * P);
 }
 
 // Internal nodes above kMomDirectMax points (the top levels): the same direct
@@ -209,11 +229,8 @@ __global__ __launch_bounds__(64) void k_moments_chunk(const double *__restrict__
             acc[i] += t;
         }
     }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const double v = wave_sum(acc[i]);
-        if (threadIdx.x == i) part[(size_t)blk * P + i] = v;
-    }
+    __shared__ double red[64][P + 1];
+    wave_sum_rows<P>(acc, red, part + (size_t)blk * P);
 }
 
 __global__ __launch_bounds__(64) void k_moments_chunk_sum(const int32_t *__restrict__ begin,
@@ -228,9 +245,17 @@ __global__ __launch_bounds__(64) void k_moments_chunk_sum(const int32_t *__restr
     if (e - b <= kMomDirectMax || left[node] < 0) return;
     const int nc = (e - b + kMomDirectMax - 1) / kMomDirectMax;  // chunks that hold points (<= nch)
     const size_t p0 = (size_t)lv.boff[l] + (size_t)(nb - lv.noff[l]) * lv.nch[l];
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {  // chunk order, four loads at a time
         double v = 0.0;
-        for (int k = 0; k < nc; ++k) v += part[(p0 + k) * P + i];
+        for (int k0 = 0; k0 < nc; k0 += 4) {
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t[u] = k0 + u < nc ? part[(p0 + k0 + u) * P + i] : 0.0;
+            v += t[0];
+            v += t[1];
+            v += t[2];
+            v += t[3];
+        }
         mu[(size_t)node * P + i] = v;
     }
 }
