@@ -428,6 +428,14 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     int mo = maxord;
     for (int off = 32; off >= 1; off >>= 1) mo = max(mo, __shfl_xor(mo, off, 64));
 
+    // The chain heads of (q, job): only this segment touches them at this level
+    // (one segment per (node, job) per level, levels in order), so the links
+    // below are a plain read and write; the read is issued here and completes
+    // behind the reservation.
+    const size_t hq = (size_t)jb.noff + q;
+    int head0 = -1;
+    if (valid && lane < 3) head0 = (lane == 0 ? o.headE : (lane == 1 ? o.headF : o.headL))[hq];
+
     // 3. the block's reservations: per-wave requests, one atomic per list
     const int npair_out = qleaf ? tN : 2 * tN;
     const int nseg_out = tN > 0 ? (qleaf ? 1 : 2) : 0;
@@ -505,12 +513,10 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     const bool okF = tF && fbase + tF <= o.cap.fop && gF < o.cap.grp;
     const bool okL = tL && lbase + tL <= o.cap.lop && gL < o.cap.grp;
     const bool okN = npair_out && cbase + npair_out <= o.cap.pair && sgi + nseg_out <= o.cap.seg;
-    const size_t hq = (size_t)jb.noff + q;
-    int prev = -1;
-    if (lane == 0 && okE) prev = atomicExch(&o.headE[hq], gE);
-    if (lane == 1 && okF) prev = atomicExch(&o.headF[hq], gF);
-    if (lane == 2 && okL) prev = atomicExch(&o.headL[hq], gL);
-    const int prevE = __shfl(prev, 0, 64), prevF = __shfl(prev, 1, 64), prevL = __shfl(prev, 2, 64);
+    if (lane == 0 && okE) o.headE[hq] = gE;
+    if (lane == 1 && okF) o.headF[hq] = gF;
+    if (lane == 2 && okL) o.headL[hq] = gL;
+    const int prevE = __shfl(head0, 0, 64), prevF = __shfl(head0, 1, 64), prevL = __shfl(head0, 2, 64);
     if (lane == 0) {
         bool over = (tE && !okE) || (tF && !okF) || (tL && !okL) || (npair_out && !okN);
         if (okE) {
