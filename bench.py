@@ -58,8 +58,8 @@ EXP_SLOTS = 4
 # (k_etile<2, false, false>) in one step of this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB
 # device copy: profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
-# as profiled; None when it has changed since (point weights were added).
-K_ETILE_TRAFFIC_BYTES = None
+# as profiled; None when it has changed since.
+K_ETILE_TRAFFIC_BYTES = 14.10e6 + 3.16e6
 
 
 def flops_per_pair(d):
