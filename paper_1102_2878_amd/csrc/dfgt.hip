@@ -1175,6 +1175,26 @@ __device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, 
     return FarAxis<D, PM, 0>::run(mu, hs, p, 0);
 }
 
+// Local-expansion evaluation (EvalLocalExpansion) at one query for the same
+// (D, p_max): sum_beta L_beta y^beta, y = (q - c) s, with the powers in
+// registers and the same axis-wise contraction (every coefficient: order p_max).
+template <int D, int PM>
+__device__ __forceinline__ double local_eval_fixed(const double *L, const double *__restrict__ q,
+                                                   const double *__restrict__ c, double s) {
+    double yp[D][PM];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double y = (q[k] - c[k]) * s;
+        double v = 1.0;
+#pragma unroll
+        for (int a = 0; a < PM; ++a) {
+            yp[k][a] = v;
+            v *= y;
+        }
+    }
+    return FarAxis<D, PM, 0>::run(L, yp, PM, 0);
+}
+
 // (D, p_max) pairs with a compile-time far-field evaluation (the default p_max
 // of D = 1..5); 0 = none.
 __host__ __device__ inline int far_fixed_kind(int d, int pmax) {
@@ -1186,9 +1206,11 @@ __host__ __device__ inline int far_fixed_kind(int d, int pmax) {
     return 0;
 }
 
-// Doubles of dynamic LDS k_leaf needs before the coefficient vectors.
-__host__ __device__ inline size_t leaf_lds_base(int nthr, int d, int pmax, int gr) {
-    return (size_t)nthr * (1 + gr) + (size_t)d * (pmax - 1) + 1 + (size_t)nthr * d * (pmax + gr) +
+// Doubles of dynamic LDS k_leaf needs before the coefficient vectors; rows =
+// 0 drops the per-thread Hermite rows (the compile-time (D, p_max) forms
+// without gradients keep them in registers).
+__host__ __device__ inline size_t leaf_lds_base(int nthr, int d, int pmax, int gr, int rows) {
+    return (size_t)nthr * (1 + gr) + (size_t)d * (pmax - 1) + 1 + (size_t)rows * nthr * d * (pmax + gr) +
            (size_t)nthr * d * gr;
 }
 
@@ -1228,15 +1250,17 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const double s = jb.s;
     const int ns = d * (pmax - 1) + 1;
     const size_t hq = (size_t)jb.noff + leaf;
-    // LDS: red[nthr] | redX[nthr] (GR) | spow[ns] | Hq[nthr][D][hs] | gq[nthr][D] (GR)
+    // LDS: red[nthr] | redX[nthr] (GR) | spow[ns] | Hq[nthr][D][hs] (not with fixed) | gq[nthr][D] (GR)
     //      | acc[PW] | tmp[PW] | tmp2[PW] | coef[D][pmax^2] | dg[P] (u64) | mt[P] (u16)
     //      (acc / tmp / tmp2 in a global scratch slice when P is large)
+    // fixed: far-field and local evaluation in registers (no Hermite rows)
+    const int fixed = GR ? 0 : far_fixed_kind(d, pmax);
     double *red = smem;
     double *redX = red + nthr;
     double *spow = redX + (GR ? nthr : 0);
     double *Hq_all = spow + ns;
     double *Hq = Hq_all + (size_t)tid * d * hs;
-    double *gq_all = Hq_all + (size_t)nthr * d * hs;
+    double *gq_all = Hq_all + (fixed ? 0 : (size_t)nthr * d * hs);
     double *gq = gq_all + (size_t)tid * d;
     double *tail = gq_all + (GR ? (size_t)nthr * d : 0);
     double *acc, *tmp, *tmp2, *coef;
@@ -1327,8 +1351,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
         }
         if (leaf_local && headL[hq] >= 0) {  // the leaf's own local ops, from their partial rows
             __syncthreads();
-            // the segment tables and the Hermite rows are free until part 2
-            block_chain_parts(headL[hq], lgrp, part, PW, acc, segS, segE, ccnt, Hq_all);
+            // the segment tables and the partial-sum rows are free until part 2
+            block_chain_parts(headL[hq], lgrp, part, PW, acc, segS, segE, ccnt, red);
         }
     }
     // 2. exhaustive and far-field parts
@@ -1337,7 +1361,6 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     const int ngr = nthr / slots;
     const int qi = tid % slots, tg = tid / slots;
     const double *lc = Q.ctr + (size_t)leaf * d;
-    const int fixed = far_fixed_kind(d, pmax);
     // op groups: the leaf's E chain, then the F chains of the path nodes from
     // the root down, each chain in its own order.  One thread per chain counts
     // and then copies its groups; if more than kMaxSeg groups result they are
@@ -1479,7 +1502,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 while (idx >= segE[sp]) ++sp;
                 const int off = idx - (sp ? segE[sp - 1] : 0);
                 const int type = segT[sp];
-                if (act && !GR && fixed) {  // far-field evaluation, registers only
+                if (act && fixed) {  // far-field evaluation, registers only
                     const Op op = fops[segS[sp] + off];
                     const int r = op.r, p = op.meta & 255;
                     const double *mu = R.mu + (size_t)r * P;
@@ -1551,7 +1574,15 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                     for (int c = 0; c < d; ++c) gq[c] += gq_all[(size_t)(k * slots + qi) * d + c];
             }
             double gl = 0.0, xl = 0.0;
-            if (any) {
+            if (any && fixed) {
+                switch (fixed) {
+                case 1: gl = local_eval_fixed<1, 6>(acc, qg, lc, s); break;
+                case 2: gl = local_eval_fixed<2, 6>(acc, qg, lc, s); break;
+                case 3: gl = local_eval_fixed<3, 4>(acc, qg, lc, s); break;
+                case 4: gl = local_eval_fixed<4, 2>(acc, qg, lc, s); break;
+                default: gl = local_eval_fixed<5, 2>(acc, qg, lc, s); break;
+                }
+            } else if (any) {
                 // powers y_k^b (b < p_max) of the scaled offset from the leaf centre,
                 // in this thread's Hermite rows (free here), the same products as powi
                 double *yp = Hq;
@@ -2550,9 +2581,10 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     } else {
         pl.big_sh = sizeof(double) * ((size_t)pmax * pmax + 2 * (size_t)d * pmax + 64 * (size_t)d * pmax);
     }
+    const int rows = (!g1 && far_fixed_kind(d, pmax)) ? 0 : 1;  // per-thread Hermite rows in LDS
     int nthr = 256;
-    while (nthr > 64 && sizeof(double) * leaf_lds_base(nthr, d, pmax, g1) > 40 * 1024) nthr >>= 1;
-    const size_t base = sizeof(double) * leaf_lds_base(nthr, d, pmax, g1);
+    while (nthr > 64 && sizeof(double) * leaf_lds_base(nthr, d, pmax, g1, rows) > 40 * 1024) nthr >>= 1;
+    const size_t base = sizeof(double) * leaf_lds_base(nthr, d, pmax, g1, rows);
     const size_t lds_dig = (sizeof(unsigned long long) + sizeof(unsigned short)) * (size_t)P;
     const size_t lds_coef = sizeof(double) * (size_t)d * pmax * pmax;
     const size_t lds_acc = sizeof(double) * 3 * (size_t)PW + lds_coef;
