@@ -780,8 +780,8 @@ constexpr int kMaxDepth = 256;  // deepest tree the per-leaf kernel walks
 // LDS per block: cb[P] | dg[P] (u64) | mt[P] (u16) | per wave: lop_wave_stride doubles
 template <bool GR>
 __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                              const Group *__restrict__ lgrp, const Op *__restrict__ lops,
-                                              const int *__restrict__ lop_node, const int *__restrict__ cnt,
+                                              const Op *__restrict__ lops, const int2 *__restrict__ lop_node,
+                                              const int *__restrict__ cnt,
                                               const int *__restrict__ overflow, double *__restrict__ part) {
     extern __shared__ double smem[];
     if (*overflow) return;
@@ -799,15 +799,29 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
     for (int i = tid; i < P; i += blockDim.x) cb[i] = coef_beta(i, d, pmax);
     __syncthreads();
     const int nops = min(cnt[C_LOP * CP], 0x7fffffff);
-    for (int oi = blockIdx.x * nwv + wv; oi < nops; oi += gridDim.x * nwv) {
-        const Op op = lops[oi];
-        const Group g = lgrp[lop_node[oi]];
-        const Job jb = jobs[g.job];
+    const int step = gridDim.x * nwv;
+    // each op's owner (node, job) comes with it, and the wave loads its next
+    // op while it works on the current one
+    int oi = blockIdx.x * nwv + wv;
+    Op op{0, 0};
+    int2 own{0, 0};
+    if (oi < nops) {
+        op = lops[oi];
+        own = lop_node[oi];
+    }
+    for (; oi < nops; oi += step) {
+        Op opn{0, 0};
+        int2 ownn{0, 0};
+        if (oi + step < nops) {
+            opn = lops[oi + step];
+            ownn = lop_node[oi + step];
+        }
+        const Job jb = jobs[own.y];
         const DevTree &Q = trees[jb.qt];
         const DevTree &R = trees[jb.rt];
         const int r = op.r, p = op.meta & 255, m = (op.meta >> 8) & 15, ch = op.meta >> 12;
         double *dst = part + (size_t)oi * PW;
-        const double *qc = Q.ctr + (size_t)g.q * d;
+        const double *qc = Q.ctr + (size_t)own.x * d;
         for (int i = lane; i < P; i += 64) {
             acc[i] = 0.0;
             if (GR) accB[i] = 0.0;
@@ -821,6 +835,8 @@ __global__ __launch_bounds__(256) void k_lops(const DevTree *__restrict__ trees,
             if (GR) dst[P + i] = accB[i];
         }
         wave_sync();
+        op = opn;
+        own = ownn;
     }
 }
 
@@ -916,12 +932,12 @@ __global__ __launch_bounds__(256) void k_lreduce(const Job *__restrict__ jobs, c
 }
 
 __global__ void k_lop_owner(const Group *__restrict__ lgrp, const int *__restrict__ cnt,
-                            const int *__restrict__ overflow, int *lop_node) {
+                            const int *__restrict__ overflow, int2 *lop_node) {
     if (*overflow) return;
     const int ng = cnt[C_LGRP * CP];
     for (int gi = blockIdx.x; gi < ng; gi += gridDim.x) {
         const Group g = lgrp[gi];
-        for (int o = threadIdx.x; o < g.count; o += blockDim.x) lop_node[g.start + o] = gi;
+        for (int o = threadIdx.x; o < g.count; o += blockDim.x) lop_node[g.start + o] = int2{g.q, g.job};
     }
 }
 
@@ -2637,7 +2653,7 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<Op>(w.fops, cap.fop));
     DFGT_TRY(grow<Op>(w.lops, cap.lop));
     if (pl.leaf_local) {
-        DFGT_TRY(grow<int>(w.lopnode, cap.lop));
+        DFGT_TRY(grow<int2>(w.lopnode, cap.lop));  // each local op's owner (node, job)
         DFGT_TRY(grow<double>(w.part, (size_t)cap.lop * pl.PW));
     } else {
         DFGT_TRY(grow<double>(w.lscr, (size_t)kLocalGrid * 3 * pl.P));
@@ -2785,10 +2801,10 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
         if (pl.leaf_local) {
             hipLaunchKernelGGL(k_lop_owner, dim3(kLocalGrid), dim3(64), 0, st, w.lgrp.as<Group>(), w.cnt.as<int>(),
-                               w.flag.as<int>(), w.lopnode.as<int>());
+                               w.flag.as<int>(), w.lopnode.as<int2>());
             auto klo = pl.gr ? k_lops<true> : k_lops<false>;
             hipLaunchKernelGGL(klo, dim3(kLocalGrid), dim3(64 * pl.lop_waves), pl.lop_sh, st, td, jd,
-                               w.lgrp.as<Group>(), w.lops.as<Op>(), w.lopnode.as<int>(), w.cnt.as<int>(),
+                               w.lops.as<Op>(), w.lopnode.as<int2>(), w.cnt.as<int>(),
                                w.flag.as<int>(), w.part.as<double>());
             hipLaunchKernelGGL(k_lreduce, dim3(kLocalGrid), dim3(256), sizeof(double) * (PW + 256), st, jd,
                                w.lnodes.as<int>(), w.cnt.as<int>(), w.flag.as<int>(), headL, w.lgrp.as<Group>(),
