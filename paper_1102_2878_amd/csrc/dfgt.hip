@@ -304,7 +304,7 @@ struct TravOut {
 
 __device__ __forceinline__ int wave_excl(int v, int *total) {
     int inc = wave_incl_scan(v);
-    *total = __shfl(inc, 63, 64);
+    *total = __builtin_amdgcn_readlane(inc, 63);
     return inc - v;
 }
 
@@ -425,8 +425,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     ccon = wave_sum(ccon);
     const double gl_child = sg.gl + plo * (1.0 - 1e-12);
     const int nFp = wave_sum_i(cF), nDp = wave_sum_i(nD), nTp = wave_sum_i(nT), nCp = wave_sum_i(nC);
-    int mo = maxord;
-    for (int off = 32; off >= 1; off >>= 1) mo = max(mo, __shfl_xor(mo, off, 64));
+    const int mo = wave_max_i(maxord);
 
     // The chain heads of (q, job): only this segment touches them at this level
     // (one segment per (node, job) per level, levels in order), so the links

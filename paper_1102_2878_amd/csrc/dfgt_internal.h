@@ -209,9 +209,53 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
-__device__ __forceinline__ int wave_sum_i(int v) {
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// DPP lane moves (GFX9 row controls: row_shr:n is 0x110 + n, row_bcast:15
+// 0x142, row_bcast:31 0x143); lanes without a source lane, and rows outside
+// ROWS, receive `old`.  They stay in the vector ALU: no LDS round trip, unlike
+// a shuffle.  Callers run with the whole wave active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_move64(long long old, long long v) {
+    const int lo = dpp_move<CTRL, ROWS>((int)old, (int)v);
+    const int hi = dpp_move<CTRL, ROWS>((int)(old >> 32), (int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Inclusive scan over the 64 lanes with an associative op: shifts by 1, 2, 4
+// and 8 inside rows of 16 lanes, then row 0's last lane into row 1 and row
+// 2's into row 3, then lane 31 into rows 2 and 3.  `id` is the op's identity.
+template <class T, class Op>
+__device__ __forceinline__ T wave_scan_dpp(T v, T id, Op op) {
+    if constexpr (sizeof(T) == 8) {
+        v = op(v, dpp_move64<0x111, 0xF>(id, v));
+        v = op(v, dpp_move64<0x112, 0xF>(id, v));
+        v = op(v, dpp_move64<0x114, 0xF>(id, v));
+        v = op(v, dpp_move64<0x118, 0xF>(id, v));
+        v = op(v, dpp_move64<0x142, 0xA>(id, v));
+        v = op(v, dpp_move64<0x143, 0xC>(id, v));
+    } else {
+        v = op(v, dpp_move<0x111, 0xF>(id, v));
+        v = op(v, dpp_move<0x112, 0xF>(id, v));
+        v = op(v, dpp_move<0x114, 0xF>(id, v));
+        v = op(v, dpp_move<0x118, 0xF>(id, v));
+        v = op(v, dpp_move<0x142, 0xA>(id, v));
+        v = op(v, dpp_move<0x143, 0xC>(id, v));
+    }
     return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    v = wave_scan_dpp(v, 0, [](int a, int b) { return a + b; });
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+    v = wave_scan_dpp(v, 0x7fffffff, [](int a, int b) { return a < b ? a : b; });
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    v = wave_scan_dpp(v, (int)0x80000000, [](int a, int b) { return a > b ? a : b; });
+    return __builtin_amdgcn_readlane(v, 63);
 }
 __device__ __forceinline__ double wave_min(double v) {
     for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
@@ -223,12 +267,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 // Inclusive prefix sum over the 64 lanes.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-    for (int off = 1; off < 64; off <<= 1) {
-        int t = __shfl_up(v, off, 64);
-        if (lane >= off) v += t;
-    }
-    return v;
+    return wave_scan_dpp(v, 0, [](int a, int b) { return a + b; });
 }
 
 // ---------------------------------------------------------------- host entry points per file

@@ -32,6 +32,10 @@ namespace {
 
 constexpr long long kPosInfKey = 0x7ff0000000000000LL;                    // key of +inf
 constexpr long long kNegInfKey = (long long)0xfff0000000000000ULL ^ 0x7fffffffffffffffLL;  // key of -inf
+// The build's control buffer: ctl[0] done (1) or capacity error (2), [1] a
+// non-finite coordinate, [2..3] the largest |x|^2 (bit pattern), [4] the
+// subtree phase could not run, [5..7] unused; then the level records.
+constexpr int kCtlHead = 8;
 
 __global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *perm, double *x, int32_t *pnode,
                        int *bad) {
@@ -46,21 +50,21 @@ __global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *pe
     }
 }
 
-// Also clears the build's flags (ctl[0..3]) and writes level 0's record
-// (ctl[4..]: per level start, end, largest node).
+// Also clears the build's flags (ctl[0..kCtlHead)) and writes level 0's
+// record (ctl[kCtlHead..]: per level start, end, largest node).
 __global__ void k_init_root(long long *lo_key, long long *hi_key, int d, int32_t *begin, int32_t *end,
                             int32_t *parent, int n, int *ctl) {
     for (int k = threadIdx.x; k < d; k += blockDim.x) {
         lo_key[k] = kPosInfKey;
         hi_key[k] = kNegInfKey;
     }
-    if (threadIdx.x < 4) ctl[threadIdx.x] = 0;
+    if (threadIdx.x < kCtlHead) ctl[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         begin[0] = 0;
         end[0] = n;
         parent[0] = -1;
-        ctl[4] = 0;
-        ctl[5] = 1;
+        ctl[kCtlHead] = 0;
+        ctl[kCtlHead + 1] = 1;
     }
 }
 
@@ -79,11 +83,7 @@ struct FoldShared {
 __device__ void block_box_fold(bool active, int node, const double *v, int d, long long *lo_key,
                                long long *hi_key, FoldShared &sh) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int mn = active ? node : 0x7fffffff, mx = active ? node : -1;
-    for (int off = 32; off >= 1; off >>= 1) {
-        mn = min(mn, __shfl_xor(mn, off, 64));
-        mx = max(mx, __shfl_xor(mx, off, 64));
-    }
+    int mn = wave_min_i(active ? node : 0x7fffffff), mx = wave_max_i(active ? node : -1);
     if (lane == 0) {
         sh.wmin[wv] = mn;
         sh.wmax[wv] = mx;
@@ -99,22 +99,18 @@ __device__ void block_box_fold(bool active, int node, const double *v, int d, lo
     if (mx < 0) return;  // no active thread in the block
     const int span = mx - mn + 1;
     if ((long long)span * d > kFoldKeys) {
-        // the block's nodes are many and small: per-wave fold, one lane per node
+        // the block's nodes are many and small: per-wave fold, one node at a
+        // time, reduced into lane 63
+        const auto kmin = [](long long a, long long b) { return a < b ? a : b; };
+        const auto kmax = [](long long a, long long b) { return a > b ? a : b; };
         unsigned long long pending = __ballot(active);
         while (pending) {
-            const int leader = __ffsll((long long)pending) - 1;
-            const int lead_node = __shfl(node, leader, 64);
+            const int lead_node = __builtin_amdgcn_readlane(node, __ffsll((long long)pending) - 1);
             const bool mine = active && node == lead_node;
             for (int k = 0; k < d; ++k) {
-                long long kv = mine ? dbl_key(v[k]) : kPosInfKey;
-                long long kx = mine ? dbl_key(v[k]) : kNegInfKey;
-                for (int off = 32; off >= 1; off >>= 1) {
-                    long long a = __shfl_xor(kv, off, 64);
-                    long long b = __shfl_xor(kx, off, 64);
-                    kv = a < kv ? a : kv;
-                    kx = b > kx ? b : kx;
-                }
-                if (lane == leader) {
+                const long long kv = wave_scan_dpp(mine ? dbl_key(v[k]) : kPosInfKey, kPosInfKey, kmin);
+                const long long kx = wave_scan_dpp(mine ? dbl_key(v[k]) : kNegInfKey, kNegInfKey, kmax);
+                if (lane == 63) {
                     atomicMin(&lo_key[(size_t)lead_node * d + k], kv);
                     atomicMax(&hi_key[(size_t)lead_node * d + k], kx);
                 }
@@ -240,15 +236,15 @@ __global__ __launch_bounds__(kLB) void k_flag(const double *__restrict__ x, cons
 // le + 2 * (rank among splitting nodes).
 // Level records live on the device: level k is nodes [lvs[3k], lvs[3k+1]),
 // lvs[3k+2] its largest node; the kernel writes level k's largest node and
-// level k+1's bounds, or sets *done when nothing splits (the per-level
-// kernels that follow then return at once).
+// level k+1's bounds and largest node, or sets *done when nothing splits (the
+// per-level kernels that follow then return at once).
 __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs, int *done, int d, int leaf, int n,
                                                    long long *lo_key, long long *hi_key, int32_t *begin,
                                                    int32_t *end, int32_t *left, int32_t *right, int32_t *parent,
                                                    int32_t *sdim, double *scoord, int32_t *nleft,
                                                    const int32_t *__restrict__ rank, const int32_t *__restrict__ bsum,
                                                    int nb, int32_t *boff) {
-    __shared__ int warp_tot[16];
+    __shared__ int warp_tot[16], warp_cb[16];
     __shared__ int carry_s;
     if (*done) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -277,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
     const int lb = lvs[3 * level], le = lvs[3 * level + 1];
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
-    int big = 0;  // the level's largest node
+    int big = 0, cbig = 0;  // the largest node of the level and of the next one
     for (int c0 = lb; c0 < le; c0 += blockDim.x) {
         const int node = c0 + threadIdx.x;
         int split = 0, sd = -1, nl = 0;
@@ -288,6 +284,7 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
             if (node_split(lo_key, hi_key, node, d, cnt, leaf, &sd, &sc)) {
                 nl = grank(e) - grank(b);
                 split = (nl > 0 && nl < cnt) ? 1 : 0;
+                if (split) cbig = max(cbig, max(nl, cnt - nl));
             }
         }
         // block exclusive scan of split
@@ -329,15 +326,23 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
         if (threadIdx.x == blockDim.x - 1) carry_s = rk + split;
         __syncthreads();
     }
-    for (int off = 32; off >= 1; off >>= 1) big = max(big, __shfl_xor(big, off, 64));
-    if (lane == 0) warp_tot[w] = big;
+    big = wave_max_i(big);
+    cbig = wave_max_i(cbig);
+    if (lane == 0) {
+        warp_tot[w] = big;
+        warp_cb[w] = cbig;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x / 64); ++k) big = max(big, warp_tot[k]);
+        for (int k = 1; k < (int)(blockDim.x / 64); ++k) {
+            big = max(big, warp_tot[k]);
+            cbig = max(cbig, warp_cb[k]);
+        }
         lvs[3 * level + 2] = big;
         const int newc = 2 * carry_s;
         lvs[3 * level + 3] = le;
         lvs[3 * level + 4] = le + newc;
+        lvs[3 * level + 5] = cbig;  // level + 1 rewrites the same value
         if (newc == 0 || le + newc > cap) *done = newc == 0 ? 1 : 2;  // 2: capacity exceeded (internal error)
     }
 }
@@ -436,16 +441,499 @@ __global__ void k_collect_leaves(int m, const int32_t *__restrict__ left, int32_
     if (threadIdx.x == 0) *count = carry_s;
 }
 
+// ---------------------------------------------------------------- subtree phase
+// Below a level whose nodes all hold at most smax points, the rest of the tree
+// is built per node: one block takes a frontier node's points into LDS and
+// applies the same rule level by level inside the block (left flags against
+// the FP64 mid-point of the widest dimension, a stable partition from a block
+// scan of the flags, a node that cannot split is a leaf, the children's boxes
+// as exact min / max of their points' ordered keys).  Its nodes are recorded
+// in local breadth-first order with their depth; k_subtree_scan gives every
+// depth its global breadth-first range, and k_subtree_emit writes each node
+// at its global id and the level records.  The tree is the one the
+// level-by-level kernels build: the same boxes, splits, permutation and
+// numbering.  The phase is all or nothing: if a frontier node holds more than
+// smax points, every block returns at once and sets ctl[4].
+// Scratch (per frontier node v with points [vb, vb + c)): node records at
+// slots [2 vb, 2 vb + 2c); per-depth counts, largest nodes and prefixes at
+// [vb, vb + c]; per frontier index its depth count, node count and vb.
+struct SubScratch {
+    int *rec;         // [slot][8]: begin, end, left, right, parent (local ids), split dim, depth, unused
+    double *rsc;      // [slot] split coordinate
+    long long *rkey;  // [slot][2 d] box keys, lo then hi
+    int *scnt, *smx, *spre;
+    int2 *sinfo;      // per frontier index: first point, number of depths
+    int *snode;       // per frontier index: number of nodes
+    int *tot, *mx;    // per depth: nodes and largest node over all subtrees
+};
+
+__host__ __device__ inline size_t sub_lds_bytes(int smax, int fmax, int d) {
+    return sizeof(double) * ((size_t)smax * d + fmax) + sizeof(long long) * (4 * (size_t)fmax * d) +
+           sizeof(int) * (6 * (size_t)smax + 1 + 12 * (size_t)fmax + 64);
+}
+
+// The split rule of node_split on a box held as keys.
+__device__ __forceinline__ bool key_split(const long long *lo, const long long *hi, int d, int cnt, int leaf,
+                                          int *sd_out, double *sc_out) {
+    if (cnt <= leaf) return false;
+    int sd = 0;
+    double wmax = key_dbl(hi[0]) - key_dbl(lo[0]);
+    for (int k = 1; k < d; ++k) {
+        const double w = key_dbl(hi[k]) - key_dbl(lo[k]);
+        if (w > wmax) {
+            wmax = w;
+            sd = k;
+        }
+    }
+    if (!(wmax > 0.0)) return false;
+    *sd_out = sd;
+    *sc_out = (key_dbl(lo[sd]) + key_dbl(hi[sd])) / 2.0;
+    return true;
+}
+
+// Exclusive scan of v[0..n) in place (n <= any, chunks of blockDim); returns
+// the total.  wsum holds blockDim / 64 + 1 ints.  Every thread calls it.
+__device__ int block_scan_inplace(int *v, int n, int *wsum) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int carry = 0;
+    for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+        const int i = c0 + threadIdx.x;
+        const int x = i < n ? v[i] : 0;
+        const int inc = wave_incl_scan(x);
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        int pre = carry, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            pre += w < wv ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        if (i < n) v[i] = pre + inc - x;
+        carry += tot;
+        __syncthreads();  // wsum is rewritten by the next chunk
+    }
+    return carry;
+}
+
+// Folds the ordered keys of the coordinates at xp into the boxes lo / hi[ch]
+// (LDS) for the wave's active lanes: the lanes of one box reduce by DPP scans
+// into lane 63, which updates it, so a box takes one atomic per dimension per
+// wave (same-address LDS atomics serialise).  D > 0 unrolls the dimensions;
+// D = 0 loops over d.  The whole wave calls it.
+template <int D>
+__device__ __forceinline__ void wave_fold_keys(bool act, int ch, const double *xp, int d, long long *lo,
+                                               long long *hi) {
+    const auto kmin = [](long long a, long long b) { return a < b ? a : b; };
+    const auto kmax = [](long long a, long long b) { return a > b ? a : b; };
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+        const int lc = __builtin_amdgcn_readlane(ch, __ffsll((long long)pending) - 1);
+        const bool mine = act && ch == lc;
+        if constexpr (D > 0) {
+            long long kv[D], kx[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const long long key = mine ? dbl_key(xp[k]) : 0;
+                kv[k] = wave_scan_dpp(mine ? key : kPosInfKey, kPosInfKey, kmin);
+                kx[k] = wave_scan_dpp(mine ? key : kNegInfKey, kNegInfKey, kmax);
+            }
+            if (lane == 63)
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    atomicMin(&lo[(size_t)lc * D + k], kv[k]);
+                    atomicMax(&hi[(size_t)lc * D + k], kx[k]);
+                }
+        } else {
+            for (int k = 0; k < d; ++k) {
+                const long long key = mine ? dbl_key(xp[k]) : 0;
+                const long long kv = wave_scan_dpp(mine ? key : kPosInfKey, kPosInfKey, kmin);
+                const long long kx = wave_scan_dpp(mine ? key : kNegInfKey, kNegInfKey, kmax);
+                if (lane == 63) {
+                    atomicMin(&lo[(size_t)lc * d + k], kv);
+                    atomicMax(&hi[(size_t)lc * d + k], kx);
+                }
+            }
+        }
+        pending &= ~__ballot(mine);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf, int smax, int fmax, int *ctl,
+                                                 const long long *__restrict__ lo_key,
+                                                 const long long *__restrict__ hi_key,
+                                                 const int32_t *__restrict__ begin, const int32_t *__restrict__ end,
+                                                 double *x_io, int32_t *perm_io, SubScratch sc) {
+    extern __shared__ double sm[];
+    const int *lvs = ctl + kCtlHead;
+    if (ctl[0]) return;  // the tree was complete before level L
+    const int fl0 = lvs[3 * L], fl1 = lvs[3 * L + 1];
+    const int biggest = L == 0 ? n : lvs[3 * L + 2];  // level L's largest node
+    if (biggest > smax) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl[4] = 1;
+        return;
+    }
+    // The subtree's points stay where they were loaded (X, P0); IDX[pos] is the
+    // point at a position of the current order, NOD[pos] the frontier index of
+    // its node (-1: a leaf).  Both are ping-ponged between depths.
+    // LDS: X[smax][d] | fsc[fmax] | klo[2][fmax][d] | khi[2][fmax][d] | P0[smax] | IDX[2][smax]
+    //      | NOD[2][smax] | RANK[smax + 1] | fb fe flid fpar [2][fmax] | fsd fcand fnl frk [fmax] | wsum[64]
+    double *X = sm;
+    double *fsc = X + (size_t)smax * d;
+    long long *klo = reinterpret_cast<long long *>(fsc + fmax);
+    long long *khi = klo + 2 * (size_t)fmax * d;
+    int *P0 = reinterpret_cast<int *>(khi + 2 * (size_t)fmax * d);
+    int *IDX = P0 + smax;
+    int *NOD = IDX + 2 * smax;
+    int *RANK = NOD + 2 * smax;
+    int *fb = RANK + smax + 1, *fe = fb + 2 * fmax, *flid = fe + 2 * fmax, *fpar = flid + 2 * fmax;
+    int *fsd = fpar + 2 * fmax, *fcand = fsd + fmax, *fnl = fcand + fmax, *frk = fnl + fmax;
+    int *wsum = frk + fmax;
+    const int tid = threadIdx.x, T = blockDim.x;
+    int deepest = 0;  // thread 0: the block's largest subtree depth count
+    for (int fi = blockIdx.x; fi < fl1 - fl0; fi += gridDim.x) {
+        __syncthreads();  // the previous subtree's LDS is no longer read
+        const int v = fl0 + fi, vb = begin[v], c = end[v] - vb;
+        for (int i = tid; i < c; i += T) {
+            for (int k = 0; k < d; ++k) X[(size_t)i * d + k] = x_io[(size_t)(vb + i) * d + k];
+            P0[i] = perm_io[vb + i];
+            IDX[i] = i;
+            NOD[i] = 0;
+        }
+        for (int k = tid; k < d; k += T) {
+            klo[k] = lo_key[(size_t)v * d + k];
+            khi[k] = hi_key[(size_t)v * d + k];
+        }
+        if (tid == 0) {
+            fb[0] = 0;
+            fe[0] = c;
+            flid[0] = 0;
+            fpar[0] = -1;
+        }
+        __syncthreads();
+        int nf = 1, cur = 0, depth = 0, next_lid = 1;
+        while (nf > 0) {
+            const int nx = cur ^ 1;
+            const int *Ic = IDX + cur * smax, *Nc = NOD + cur * smax;
+            int *In = IDX + nx * smax, *Nn = NOD + nx * smax;
+            const int *fbc = fb + cur * fmax, *fec = fe + cur * fmax, *flc = flid + cur * fmax,
+                      *fpc = fpar + cur * fmax;
+            int *fbn = fb + nx * fmax, *fen = fe + nx * fmax, *fln = flid + nx * fmax, *fpn = fpar + nx * fmax;
+            const long long *loc = klo + (size_t)cur * fmax * d, *hic = khi + (size_t)cur * fmax * d;
+            long long *lon = klo + (size_t)nx * fmax * d, *hin = khi + (size_t)nx * fmax * d;
+            // 1. the split rule of each frontier node, and the depth's statistics
+            int big = 0;
+            for (int f = tid; f < nf; f += T) {
+                const int cnt = fec[f] - fbc[f];
+                big = max(big, cnt);
+                int sd = -1;
+                double scd = 0.0;
+                fcand[f] = key_split(loc + (size_t)f * d, hic + (size_t)f * d, d, cnt, leaf, &sd, &scd) ? 1 : 0;
+                fsd[f] = sd;
+                fsc[f] = scd;
+            }
+            big = wave_max_i(big);
+            if ((tid & 63) == 0) wsum[tid >> 6] = big;
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 1; w < T / 64; ++w) big = max(big, wsum[w]);
+                sc.scnt[vb + depth] = nf;
+                sc.smx[vb + depth] = big;
+            }
+            // 2. left flags of the points of candidate nodes, exclusive ranks
+            for (int i = tid; i < c; i += T) {
+                const int f = Nc[i];
+                RANK[i] = (f >= 0 && fcand[f]) ? (X[(size_t)Ic[i] * d + fsd[f]] <= fsc[f] ? 1 : 0) : 0;
+            }
+            __syncthreads();  // also: wsum was read by thread 0
+            const int tl = block_scan_inplace(RANK, c, wsum);
+            if (tid == 0) RANK[c] = tl;
+            __syncthreads();
+            // 3. which nodes split (both sides non-empty), children in frontier order
+            for (int f = tid; f < nf; f += T) {
+                const int cnt = fec[f] - fbc[f];
+                const int nl = RANK[fec[f]] - RANK[fbc[f]];
+                fnl[f] = nl;
+                frk[f] = (fcand[f] && nl > 0 && nl < cnt) ? 1 : 0;
+            }
+            __syncthreads();
+            const int nsplit = block_scan_inplace(frk, nf, wsum);  // frk: rank among splitting nodes
+            for (int f = tid; f < nf; f += T) {
+                const int cnt = fec[f] - fbc[f];
+                const bool split = fcand[f] && fnl[f] > 0 && fnl[f] < cnt;
+                fcand[f] = split ? 1 : 0;
+                const int lid = flc[f], cl = next_lid + 2 * frk[f];
+                const size_t slot = 2 * (size_t)vb + lid;
+                int *r = sc.rec + slot * 8;
+                r[0] = vb + fbc[f];
+                r[1] = vb + fec[f];
+                r[2] = split ? cl : -1;
+                r[3] = split ? cl + 1 : -1;
+                r[4] = fpc[f];
+                r[5] = split ? fsd[f] : -1;
+                r[6] = depth;
+                sc.rsc[slot] = split ? fsc[f] : 0.0;
+                for (int k = 0; k < d; ++k) {
+                    sc.rkey[slot * 2 * d + k] = loc[(size_t)f * d + k];
+                    sc.rkey[slot * 2 * d + d + k] = hic[(size_t)f * d + k];
+                }
+                if (split) {
+                    const int c0 = 2 * frk[f];
+                    fbn[c0] = fbc[f];
+                    fen[c0] = fbc[f] + fnl[f];
+                    fbn[c0 + 1] = fbc[f] + fnl[f];
+                    fen[c0 + 1] = fec[f];
+                    fln[c0] = cl;
+                    fln[c0 + 1] = cl + 1;
+                    fpn[c0] = lid;
+                    fpn[c0 + 1] = lid;
+                    for (int k = 0; k < d; ++k) {
+                        lon[(size_t)c0 * d + k] = kPosInfKey;
+                        hin[(size_t)c0 * d + k] = kNegInfKey;
+                        lon[(size_t)(c0 + 1) * d + k] = kPosInfKey;
+                        hin[(size_t)(c0 + 1) * d + k] = kNegInfKey;
+                    }
+                }
+            }
+            __syncthreads();
+            // 4. stable partition into the children (other points keep their place)
+            for (int i = tid; i < c; i += T) {
+                const int f = Nc[i], o = Ic[i];
+                int pos = i, ch = -1;
+                if (f >= 0 && fcand[f]) {
+                    const int b = fbc[f];
+                    const int rl = RANK[i] - RANK[b];
+                    const bool left = X[(size_t)o * d + fsd[f]] <= fsc[f];
+                    pos = left ? b + rl : b + fnl[f] + (i - b - rl);
+                    ch = 2 * frk[f] + (left ? 0 : 1);
+                }
+                In[pos] = o;
+                Nn[pos] = ch;
+            }
+            __syncthreads();
+            // 5. the children's boxes, in the new order: a child's points are
+            // consecutive, so a wave mostly meets one or two children
+            if (nsplit > 0)
+                for (int i0 = 0; i0 < c; i0 += T) {  // whole waves: the fold shuffles
+                    const int i = i0 + tid;
+                    const int ch = i < c ? Nn[i] : -1;
+                    const double *xp = X + (size_t)(i < c ? In[i] : 0) * d;
+                    switch (d) {
+                        case 1: wave_fold_keys<1>(ch >= 0, ch, xp, d, lon, hin); break;
+                        case 2: wave_fold_keys<2>(ch >= 0, ch, xp, d, lon, hin); break;
+                        case 3: wave_fold_keys<3>(ch >= 0, ch, xp, d, lon, hin); break;
+                        case 4: wave_fold_keys<4>(ch >= 0, ch, xp, d, lon, hin); break;
+                        default: wave_fold_keys<0>(ch >= 0, ch, xp, d, lon, hin); break;
+                    }
+                }
+            __syncthreads();
+            cur = nx;
+            next_lid += 2 * nsplit;
+            nf = 2 * nsplit;
+            ++depth;
+        }
+        // the subtree's points in tree order, back in place
+        const int *Ic = IDX + cur * smax;
+        for (int i = tid; i < c; i += T) {
+            const int o = Ic[i];
+            for (int k = 0; k < d; ++k) x_io[(size_t)(vb + i) * d + k] = X[(size_t)o * d + k];
+            perm_io[vb + i] = P0[o];
+        }
+        if (tid == 0) {
+            sc.sinfo[fi] = make_int2(vb, depth);
+            sc.snode[fi] = next_lid;
+            deepest = max(deepest, depth);
+        }
+    }
+    if (tid == 0 && deepest > 0) atomicMax(&ctl[5], deepest);
+}
+
+// Per depth j of the subtrees: the exclusive prefix over the frontier of its
+// node counts (spre), the depth's total and its largest node.  A thread takes
+// up to kScanPer consecutive subtrees per pass, loaded together.
+constexpr int kScanPer = 8;
+__global__ __launch_bounds__(256) void k_subtree_scan(int L, const int *ctl, SubScratch sc) {
+    __shared__ int wsum[8], carry_s, big_s;
+    const int *lvs = ctl + kCtlHead;
+    const int J = ctl[5];
+    if (J == 0) return;  // the subtree phase did not run
+    const int F = lvs[3 * L + 1] - lvs[3 * L];
+    const int T = blockDim.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = T >> 6;
+    const int per = min(kScanPer, (F + T - 1) / T);
+    for (int j = blockIdx.x; j < J; j += gridDim.x) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry_s = 0;
+            big_s = 0;
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < F; c0 += per * T) {
+            const int f0 = c0 + threadIdx.x * per;
+            int vb[kScanPer], x[kScanPer];
+            int sum = 0, big = 0;
+#pragma unroll
+            for (int g = 0; g < kScanPer; ++g) {
+                const int fi = f0 + g;
+                const int2 inf = (g < per && fi < F) ? sc.sinfo[fi] : make_int2(-1, 0);
+                vb[g] = j < inf.y ? inf.x : -1;
+            }
+#pragma unroll
+            for (int g = 0; g < kScanPer; ++g) {
+                x[g] = vb[g] >= 0 ? sc.scnt[vb[g] + j] : 0;
+                big = max(big, vb[g] >= 0 ? sc.smx[vb[g] + j] : 0);
+                sum += x[g];
+            }
+            const int inc = wave_incl_scan(sum);
+            big = wave_max_i(big);
+            if (lane == 63) wsum[wv] = inc;
+            if (lane == 0) atomicMax(&big_s, big);
+            __syncthreads();
+            int run = carry_s, tot = 0;
+            for (int w = 0; w < nw; ++w) {
+                run += w < wv ? wsum[w] : 0;
+                tot += wsum[w];
+            }
+            run += inc - sum;
+#pragma unroll
+            for (int g = 0; g < kScanPer; ++g) {
+                if (vb[g] >= 0) sc.spre[vb[g] + j] = run;
+                run += x[g];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) carry_s += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            sc.tot[j] = carry_s;
+            sc.mx[j] = big_s;
+        }
+    }
+}
+
+// Writes every subtree node at its global breadth-first id.  Level L + j
+// starts after levels L .. L + j - 1 (their totals); block 0 also writes the
+// level records of levels L + 1 .. L + J (the last one empty) and marks the
+// tree complete.
+__global__ __launch_bounds__(256) void k_subtree_emit(int L, int d, int smax, int *ctl, SubScratch sc,
+                                                      int32_t *begin, int32_t *end, int32_t *left, int32_t *right,
+                                                      int32_t *parent, int32_t *sdim, double *scoord,
+                                                      long long *lo_key, long long *hi_key) {
+    extern __shared__ int sdi[];  // dstart[smax + 1] | gbase[smax + 1]
+    int *lvs = ctl + kCtlHead;
+    const int J = ctl[5];
+    if (J == 0) return;
+    const int fl0 = lvs[3 * L], fl1 = lvs[3 * L + 1];
+    int *dstart = sdi, *gbase = sdi + smax + 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        lvs[3 * L + 2] = sc.mx[0];  // level L's largest node (unset when L is 0)
+        int start = fl1;
+        for (int j = 1; j < J; ++j) {
+            lvs[3 * (L + j)] = start;
+            lvs[3 * (L + j) + 1] = start + sc.tot[j];
+            lvs[3 * (L + j) + 2] = sc.mx[j];
+            start += sc.tot[j];
+        }
+        lvs[3 * (L + J)] = start;
+        lvs[3 * (L + J) + 1] = start;
+        lvs[3 * (L + J) + 2] = 0;
+        ctl[6] = 1;  // the subtree phase built the tree
+        ctl[0] = 1;
+    }
+    for (int fi = blockIdx.x; fi < fl1 - fl0; fi += gridDim.x) {
+        __syncthreads();
+        const int v = fl0 + fi;
+        const int2 inf = sc.sinfo[fi];
+        const int vb = inf.x, nlev = inf.y, nloc = sc.snode[fi];
+        if (threadIdx.x == 0) {
+            int s0 = 0, start = fl1;
+            for (int j = 0; j < nlev; ++j) {
+                dstart[j] = s0;
+                gbase[j] = j == 0 ? v : start + sc.spre[vb + j];
+                if (j > 0) start += sc.tot[j];
+                s0 += sc.scnt[vb + j];
+            }
+            dstart[nlev] = s0;
+        }
+        __syncthreads();
+        for (int u = threadIdx.x; u < nloc; u += blockDim.x) {
+            const size_t slot = 2 * (size_t)vb + u;
+            const int *r = sc.rec + slot * 8;
+            const int j = r[6];
+            const int gid = gbase[j] + (u - dstart[j]);
+            begin[gid] = r[0];
+            end[gid] = r[1];
+            left[gid] = r[2] >= 0 ? gbase[j + 1] + (r[2] - dstart[j + 1]) : -1;
+            right[gid] = r[3] >= 0 ? gbase[j + 1] + (r[3] - dstart[j + 1]) : -1;
+            if (u > 0) parent[gid] = gbase[j - 1] + (r[4] - dstart[j - 1]);
+            sdim[gid] = r[5];
+            scoord[gid] = sc.rsc[slot];
+            for (int k = 0; k < d; ++k) {
+                lo_key[(size_t)gid * d + k] = sc.rkey[slot * 2 * d + k];
+                hi_key[(size_t)gid * d + k] = sc.rkey[slot * 2 * d + d + k];
+            }
+        }
+    }
+}
+
 }  // namespace
+
+// Subtree phase limits: frontier nodes of at most kSubMax points, at most
+// kSubLds bytes of LDS per block.
+constexpr int kSubMax = 1024;
+constexpr size_t kSubLds = 64 * 1024;
+
+struct SubParams {
+    int smax = 0, fmax = 0;  // smax 0: no subtree phase for this (d, leaf)
+    size_t lds = 0;
+};
+
+// A depth inside a subtree of at most smax points has at most
+// 2 floor(smax / (leaf + 1)) nodes: only nodes of more than leaf points split.
+SubParams sub_params(int d, int leaf) {
+    SubParams p;
+    for (int smax = kSubMax; smax >= 64; smax -= 64) {
+        const int fmax = std::max(1, 2 * (smax / (leaf + 1)));
+        const size_t lds = sub_lds_bytes(smax, fmax, d);
+        if (lds > kSubLds) continue;
+        if (smax >= 2 * (leaf + 1)) p = {smax, fmax, lds};
+        break;
+    }
+    return p;
+}
 
 // Scratch of the build, kept per host thread and reused across builds.
 struct BuildWs {
     DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft;
-    DevBuf ctl;   // [0] done flag, [1] non-finite flag, [2..3] largest |x|^2 (bit pattern), then per level
-                  // start, end, largest node
+    DevBuf ctl;   // kCtlHead flags, then per level start, end, largest node
+    DevBuf sub;   // the subtree phase's records
     HostBuf back;  // pinned copy of ctl
 };
 thread_local BuildWs g_build;
+
+// Carves the subtree phase's scratch for n points in d dimensions.
+dfgt_status sub_scratch(DevBuf &buf, int n, int d, int smax, SubScratch *sc) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t slots = 2 * (size_t)n;
+    const size_t o_rec = take(sizeof(int) * 8 * slots), o_rsc = take(sizeof(double) * slots),
+                 o_key = take(sizeof(long long) * 2 * d * slots);
+    const size_t o_info = take(sizeof(int2) * ((size_t)n + 1));
+    size_t o_i[6];
+    for (int k = 0; k < 4; ++k) o_i[k] = take(sizeof(int) * ((size_t)n + 1));
+    for (int k = 4; k < 6; ++k) o_i[k] = take(sizeof(int) * ((size_t)smax + 1));
+    DFGT_TRY(buf.reserve(off));
+    char *b = static_cast<char *>(buf.p);
+    sc->rec = reinterpret_cast<int *>(b + o_rec);
+    sc->rsc = reinterpret_cast<double *>(b + o_rsc);
+    sc->rkey = reinterpret_cast<long long *>(b + o_key);
+    sc->sinfo = reinterpret_cast<int2 *>(b + o_info);
+    int **ip[6] = {&sc->scnt, &sc->smx, &sc->spre, &sc->snode, &sc->tot, &sc->mx};
+    for (int k = 0; k < 6; ++k) *ip[k] = reinterpret_cast<int *>(b + o_i[k]);
+    return DFGT_OK;
+}
 
 dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *wts, hipStream_t st) {
     const int n = (int)t->n, d = t->d, leaf = t->leaf;
@@ -479,13 +967,13 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     // level records: a tree on n points has at most n levels (every split
     // leaves fewer points on each side)
     const int max_levels = n + 1;
-    DFGT_TRY(w.ctl.reserve(sizeof(int) * (4 + 3 * ((size_t)max_levels + 1))));
+    DFGT_TRY(w.ctl.reserve(sizeof(int) * (kCtlHead + 3 * ((size_t)max_levels + 1))));
 
     int32_t *pa = t->perm.as<int32_t>(), *pb = perm_b.as<int32_t>();
     double *xa = t->x.as<double>(), *xb = x_b.as<double>();
     int32_t *na = pnode_a.as<int32_t>(), *nb = pnode_b.as<int32_t>();
-    int *cnt_d = w.ctl.as<int>();  // [0] done flag, [1] non-finite flag, [2..3] largest |x|^2
-    int *lvs = cnt_d + 4;
+    int *cnt_d = w.ctl.as<int>();  // flags (kCtlHead), then the level records
+    int *lvs = cnt_d + kCtlHead;
     hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
                        t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(), n, cnt_d);
     hipLaunchKernelGGL(k_init, dim3(gb), dim3(kLB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
@@ -502,12 +990,36 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     int batch = 6;
     for (int q = n / std::max(leaf, 1); q > 1; q >>= 1) ++batch;
     // a rebuild of the same shape (a benchmark loop, a sweep over data of one
-    // size) starts with the depth seen last time: usually one batch, one sync
-    static thread_local struct { int64_t n; int d, leaf, depth; } last{-1, 0, 0, 0};
-    if (last.n == n && last.d == d && last.leaf == leaf) batch = std::max(batch, last.depth + 2);
+    // size) starts with the depth and the subtree level seen last time
+    static thread_local struct { int64_t n; int d, leaf, depth, sw; } last{-1, 0, 0, 0, -1};
+    const bool same = last.n == n && last.d == d && last.leaf == leaf;
+    if (same) batch = std::max(batch, last.depth + 2);
+    // The subtree phase is tried once, at level `target`: the level learnt from
+    // the last build of this shape, else the level where a balanced tree's
+    // nodes hold a quarter of smax.  If a node there may hold more than smax
+    // points, the device leaves everything untouched and the levels go on one
+    // by one.
+    const SubParams sp = sub_params(d, leaf);
+    int target = -1, sub_level = -1;
+    SubScratch sc{};
+    if (sp.smax) {
+        if (same) {
+            target = last.sw;
+        } else if (n <= sp.smax) {
+            target = 0;
+        } else {
+            target = 1;
+            while ((n >> target) > sp.smax / 4) ++target;
+        }
+        if (target >= max_levels) target = -1;
+        if (target >= 0) DFGT_TRY(sub_scratch(w.sub, n, d, sp.smax, &sc));
+    }
     const int *hl = nullptr;  // level records in the pinned copy: start, end, largest node
+    int lread = 0;            // records 0 .. lread are in hl
+    bool sub_done = false;
     while (!done && level < max_levels) {
-        const int stop = std::min(max_levels, level + batch);
+        const bool try_sub = target >= level;
+        const int stop = try_sub ? target : std::min(max_levels, level + batch);
         for (; level < stop; ++level) {
             int32_t *pin = (level & 1) ? pb : pa, *pout = (level & 1) ? pa : pb;
             double *xin = (level & 1) ? xb : xa, *xout = (level & 1) ? xa : xb;
@@ -527,13 +1039,35 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
                                xout, lo_key.as<long long>(), hi_key.as<long long>(), cnt_d);
             DFGT_HIP(hipGetLastError());
         }
-        // flags and the records of levels 0 .. level, one copy
-        const size_t nback = sizeof(int) * (4 + 3 * ((size_t)level + 1));
+        lread = level;
+        if (try_sub) {
+            // the frontier (level `target`) has at most 2^target nodes; its
+            // subtrees are at most smax deep
+            const int L = target;
+            const int grid = (int)std::min<long long>(2048, 1LL << std::min(L, 20));
+            int32_t *pio = (L & 1) ? pb : pa;
+            double *xio = (L & 1) ? xb : xa;
+            hipLaunchKernelGGL(k_subtree, dim3(grid), dim3(1024), sp.lds, st, L, n, d, leaf, sp.smax, sp.fmax, cnt_d,
+                               lo_key.as<long long>(), hi_key.as<long long>(), t->begin.as<int32_t>(),
+                               t->end.as<int32_t>(), xio, pio, sc);
+            hipLaunchKernelGGL(k_subtree_scan, dim3(32), dim3(256), 0, st, L, cnt_d, sc);
+            hipLaunchKernelGGL(k_subtree_emit, dim3(grid), dim3(256), sizeof(int) * 2 * ((size_t)sp.smax + 1), st, L,
+                               d, sp.smax, cnt_d, sc, t->begin.as<int32_t>(), t->end.as<int32_t>(),
+                               t->left.as<int32_t>(), t->right.as<int32_t>(), t->parent.as<int32_t>(),
+                               t->sdim.as<int32_t>(), t->scoord.as<double>(), lo_key.as<long long>(),
+                               hi_key.as<long long>());
+            DFGT_HIP(hipGetLastError());
+            lread = std::min(max_levels, L + sp.smax + 1);
+            target = -1;
+            sub_level = L;
+        }
+        // flags and the records of levels 0 .. lread, one copy
+        const size_t nback = sizeof(int) * (kCtlHead + 3 * ((size_t)lread + 1));
         DFGT_TRY(w.back.reserve(nback));
         DFGT_HIP(hipMemcpyAsync(w.back.p, cnt_d, nback, hipMemcpyDeviceToHost, st));
         DFGT_HIP(hipStreamSynchronize(st));
         const int *flags = w.back.as<int>();
-        hl = flags + 4;
+        hl = flags + kCtlHead;
         if (flags[1]) {
             set_error("dfgt_build_tree: points contain a non-finite coordinate");
             return DFGT_EINVAL;
@@ -543,8 +1077,9 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
             return DFGT_EHIP;
         }
         done = flags[0];
+        sub_done = flags[6] != 0;
         std::memcpy(&t->max_nrm, flags + 2, sizeof(double));
-        batch = 4;
+        if (!try_sub) batch = 4;  // after a declined subtree phase the first batch still applies
     }
     if (!done) {
         set_error("dfgt_build_tree: level limit reached (internal error)");
@@ -553,7 +1088,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     // level bounds (read with the last batch's flags): levels 0 .. K, K the
     // first level without a split
     int K = 0;
-    while (K + 1 <= level && hl[3 * (size_t)K + 4] > hl[3 * (size_t)K + 1]) ++K;
+    while (K + 1 <= lread && hl[3 * (size_t)K + 4] > hl[3 * (size_t)K + 1]) ++K;
     t->level_start.assign(1, 0);
     t->level_max.assign((size_t)K + 1, 0);
     for (int k = 0; k <= K; ++k) {
@@ -561,7 +1096,8 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
         t->level_max[k] = hl[3 * (size_t)k + 2];
     }
     const int le = hl[3 * (size_t)K + 1];
-    if (K & 1) {
+    // the subtree phase leaves the points where its frontier had them
+    if ((sub_done ? sub_level : K) & 1) {
         pa = perm_b.as<int32_t>();
         xa = x_b.as<double>();
     }
@@ -569,7 +1105,15 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     t->m = m;
     t->nleaves = (m + 1) / 2;  // every split makes two children
     t->depth = (int)t->level_start.size() - 1;
-    last = {n, d, leaf, t->depth};
+    // the first level whose nodes all hold at most smax points
+    int sw = -1;
+    if (sp.smax)
+        for (int L = 0; L <= K; ++L)
+            if ((L == 0 ? n : t->level_max[L]) <= sp.smax) {
+                sw = L;
+                break;
+            }
+    last = {n, d, leaf, t->depth, sw};
     // the final permutation / points live in pa / xa
     if (pa != t->perm.as<int32_t>()) {
         DFGT_HIP(hipMemcpyAsync(t->perm.p, pa, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));

@@ -15,11 +15,26 @@ def note(msg):
     sys.stdout.flush()
 
 
-def compare_trees(gpu, ora):
+def compare_trees(gpu, ora, depth=None):
     """Walks the breadth-first GPU tree and the pre-order oracle tree together and
-    asserts bit-identical structure; returns the number of nodes compared."""
+    asserts bit-identical structure; returns the number of nodes compared.  Also
+    checks that the GPU ids are breadth-first (children left then right, level
+    by level) and, given the tree's reported depth, the number of levels."""
     assert np.array_equal(gpu["perm"], ora["perm"]), "tree permutations differ"
     assert gpu["n_nodes"] == ora["n_nodes"], (gpu["n_nodes"], ora["n_nodes"])
+    level, order = [0], [0]
+    levels = 0
+    while level:
+        levels += 1
+        nxt = []
+        for v in level:
+            if gpu["left"][v] >= 0:
+                nxt += [int(gpu["left"][v]), int(gpu["right"][v])]
+        order += nxt
+        level = nxt
+    assert order == list(range(gpu["n_nodes"])), "node ids are not breadth-first"
+    if depth is not None:
+        assert levels == depth, (levels, depth)
     stack = [(0, 0)]
     seen = 0
     while stack:

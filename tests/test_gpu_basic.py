@@ -72,7 +72,47 @@ def test_tree_bit_exact_random(dfgt, d, leaf):
     x = rng.standard_normal((1500, d)) * rng.uniform(0.1, 2.0, size=d)
     note(f"tree d={d} leaf={leaf}")
     t = dfgt.build_tree(cuda(x), leaf_size=leaf)
-    compare_trees(dfgt.tree_export(t), oracle.build_kdtree(x, leaf))
+    compare_trees(dfgt.tree_export(t), oracle.build_kdtree(x, leaf), t.info()["depth"])
+
+
+def test_tree_rebuilds_of_one_shape(dfgt):
+    # A rebuild of the same (n, d, leaf) hands the lower levels to the per-node
+    # phase from the level learnt on the previous build; other data of that
+    # shape may not allow it there, and the build then goes on level by level.
+    for seed in (11, 12, 13):
+        x = synth.c2(n=20000, seed=seed)
+        ref = oracle.build_kdtree(x, 32)
+        for rep in range(2):
+            note(f"tree rebuild seed={seed} rep={rep}")
+            t = dfgt.build_tree(cuda(x), leaf_size=32)
+            compare_trees(dfgt.tree_export(t), ref, t.info()["depth"])
+    # sizes around the per-node phase's node limits (512 points at D=1 with
+    # leaf 1, 960 at D=2 with leaf 8, 320 at D=16 with leaf 32; a whole tree in
+    # one block up to them) and far above them
+    rng = np.random.default_rng(14)
+    for n in (320, 321, 512, 513, 960, 961, 5000):
+        for d, leaf in ((1, 1), (2, 8), (16, 32)):
+            x = rng.standard_normal((n, d))
+            ref = oracle.build_kdtree(x, leaf)
+            for rep in range(2):
+                note(f"tree sizes n={n} d={d} leaf={leaf} rep={rep}")
+                t = dfgt.build_tree(cuda(x), leaf_size=leaf)
+                compare_trees(dfgt.tree_export(t), ref, t.info()["depth"])
+
+
+def test_tree_deep_chain(dfgt):
+    # 1.5^-k: every mid-point split cuts off the two or so largest points, so
+    # the tree is a chain about n / 2 levels deep.  Its big nodes reach far
+    # below any balanced-tree level, so the first build goes level by level
+    # to the end; the rebuild starts the per-node phase at the level where the
+    # chain's node fits (about 220), and that phase then runs some 480 levels
+    # deep in one block.
+    x = (1.5 ** -np.arange(1400.0))[::-1].reshape(-1, 1).copy()
+    ref = oracle.build_kdtree(x, 4)
+    for rep in range(2):
+        note(f"tree chain rep={rep}")
+        t = dfgt.build_tree(cuda(x), leaf_size=4)
+        compare_trees(dfgt.tree_export(t), ref, t.info()["depth"])
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
@@ -83,7 +123,7 @@ def test_tree_bit_exact_workloads(dfgt, name):
     note(f"tree workload {name} n={x.shape[0]}")
     t = dfgt.build_tree(cuda(x), leaf_size=32)
     info = t.info()
-    compare_trees(dfgt.tree_export(t), oracle.build_kdtree(x, 32))
+    compare_trees(dfgt.tree_export(t), oracle.build_kdtree(x, 32), info["depth"])
     assert info["n"] == x.shape[0]
 
 
@@ -100,7 +140,7 @@ def test_tree_degenerate_inputs(dfgt):
         for leaf in (1, 8, 32):
             note(f"tree degenerate {name} leaf={leaf}")
             t = dfgt.build_tree(cuda(x), leaf_size=leaf)
-            compare_trees(dfgt.tree_export(t), oracle.build_kdtree(x, leaf))
+            compare_trees(dfgt.tree_export(t), oracle.build_kdtree(x, leaf), t.info()["depth"])
 
 
 @pytest.mark.parametrize("d,pmax", [(1, 8), (2, 6), (3, 4), (5, 2), (5, 4), (16, 1)])
