@@ -469,7 +469,7 @@ struct SubScratch {
 
 __host__ __device__ inline size_t sub_lds_bytes(int smax, int fmax, int d) {
     return sizeof(double) * ((size_t)smax * d + fmax) + sizeof(long long) * (4 * (size_t)fmax * d) +
-           sizeof(int) * (6 * (size_t)smax + 1 + 12 * (size_t)fmax + 64);
+           sizeof(int) * (6 * (size_t)smax + 1 + 12 * (size_t)fmax + 128);
 }
 
 // The split rule of node_split on a box held as keys.
@@ -514,50 +514,6 @@ __device__ int block_scan_inplace(int *v, int n, int *wsum) {
     return carry;
 }
 
-// Folds the ordered keys of the coordinates at xp into the boxes lo / hi[ch]
-// (LDS) for the wave's active lanes: the lanes of one box reduce by DPP scans
-// into lane 63, which updates it, so a box takes one atomic per dimension per
-// wave (same-address LDS atomics serialise).  D > 0 unrolls the dimensions;
-// D = 0 loops over d.  The whole wave calls it.
-template <int D>
-__device__ __forceinline__ void wave_fold_keys(bool act, int ch, const double *xp, int d, long long *lo,
-                                               long long *hi) {
-    const auto kmin = [](long long a, long long b) { return a < b ? a : b; };
-    const auto kmax = [](long long a, long long b) { return a > b ? a : b; };
-    const int lane = threadIdx.x & 63;
-    unsigned long long pending = __ballot(act);
-    while (pending) {
-        const int lc = __builtin_amdgcn_readlane(ch, __ffsll((long long)pending) - 1);
-        const bool mine = act && ch == lc;
-        if constexpr (D > 0) {
-            long long kv[D], kx[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const long long key = mine ? dbl_key(xp[k]) : 0;
-                kv[k] = wave_scan_dpp(mine ? key : kPosInfKey, kPosInfKey, kmin);
-                kx[k] = wave_scan_dpp(mine ? key : kNegInfKey, kNegInfKey, kmax);
-            }
-            if (lane == 63)
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    atomicMin(&lo[(size_t)lc * D + k], kv[k]);
-                    atomicMax(&hi[(size_t)lc * D + k], kx[k]);
-                }
-        } else {
-            for (int k = 0; k < d; ++k) {
-                const long long key = mine ? dbl_key(xp[k]) : 0;
-                const long long kv = wave_scan_dpp(mine ? key : kPosInfKey, kPosInfKey, kmin);
-                const long long kx = wave_scan_dpp(mine ? key : kNegInfKey, kNegInfKey, kmax);
-                if (lane == 63) {
-                    atomicMin(&lo[(size_t)lc * d + k], kv);
-                    atomicMax(&hi[(size_t)lc * d + k], kx);
-                }
-            }
-        }
-        pending &= ~__ballot(mine);
-    }
-}
-
 __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf, int smax, int fmax, int *ctl,
                                                  const long long *__restrict__ lo_key,
                                                  const long long *__restrict__ hi_key,
@@ -577,6 +533,7 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
     // its node (-1: a leaf).  Both are ping-ponged between depths.
     // LDS: X[smax][d] | fsc[fmax] | klo[2][fmax][d] | khi[2][fmax][d] | P0[smax] | IDX[2][smax]
     //      | NOD[2][smax] | RANK[smax + 1] | fb fe flid fpar [2][fmax] | fsd fcand fnl frk [fmax] | wsum[64]
+    //      | wbig[64]
     double *X = sm;
     double *fsc = X + (size_t)smax * d;
     long long *klo = reinterpret_cast<long long *>(fsc + fmax);
@@ -587,7 +544,7 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
     int *RANK = NOD + 2 * smax;
     int *fb = RANK + smax + 1, *fe = fb + 2 * fmax, *flid = fe + 2 * fmax, *fpar = flid + 2 * fmax;
     int *fsd = fpar + 2 * fmax, *fcand = fsd + fmax, *fnl = fcand + fmax, *frk = fnl + fmax;
-    int *wsum = frk + fmax;
+    int *wsum = frk + fmax, *wbig = wsum + 64;
     const int tid = threadIdx.x, T = blockDim.x;
     int deepest = 0;  // thread 0: the block's largest subtree depth count
     for (int fi = blockIdx.x; fi < fl1 - fl0; fi += gridDim.x) {
@@ -620,6 +577,9 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
             int *fbn = fb + nx * fmax, *fen = fe + nx * fmax, *fln = flid + nx * fmax, *fpn = fpar + nx * fmax;
             const long long *loc = klo + (size_t)cur * fmax * d, *hic = khi + (size_t)cur * fmax * d;
             long long *lon = klo + (size_t)nx * fmax * d, *hin = khi + (size_t)nx * fmax * d;
+            // A frontier of at most 64 nodes (the usual case) is handled by wave 0
+            // alone: no block-wide scan over the nodes.
+            const bool one = nf <= 64;
             // 1. the split rule of each frontier node, and the depth's statistics
             int big = 0;
             for (int f = tid; f < nf; f += T) {
@@ -631,37 +591,59 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
                 fsd[f] = sd;
                 fsc[f] = scd;
             }
-            big = wave_max_i(big);
-            if ((tid & 63) == 0) wsum[tid >> 6] = big;
+            if (one) {
+                if (tid < 64) {
+                    big = wave_max_i(big);
+                    if (tid == 0) {
+                        sc.scnt[vb + depth] = nf;
+                        sc.smx[vb + depth] = big;
+                    }
+                }
+            } else {
+                big = wave_max_i(big);
+                if ((tid & 63) == 0) wbig[tid >> 6] = big;
+            }
             __syncthreads();
-            if (tid == 0) {
-                for (int w = 1; w < T / 64; ++w) big = max(big, wsum[w]);
+            if (!one && tid == 0) {
+                for (int w = 1; w < T / 64; ++w) big = max(big, wbig[w]);
                 sc.scnt[vb + depth] = nf;
                 sc.smx[vb + depth] = big;
             }
-            // 2. left flags of the points of candidate nodes, exclusive ranks
-            for (int i = tid; i < c; i += T) {
-                const int f = Nc[i];
-                RANK[i] = (f >= 0 && fcand[f]) ? (X[(size_t)Ic[i] * d + fsd[f]] <= fsc[f] ? 1 : 0) : 0;
+            // 2. left flags of the points of candidate nodes, their exclusive
+            // ranks (RANK[c]: the total)
+            {
+                const int lane = tid & 63, wv = tid >> 6, nw = T >> 6;
+                int carry = 0;
+                for (int i0 = 0; i0 < c; i0 += T) {
+                    const int i = i0 + tid;
+                    int fl = 0;
+                    if (i < c) {
+                        const int f = Nc[i];
+                        if (f >= 0 && fcand[f]) fl = X[(size_t)Ic[i] * d + fsd[f]] <= fsc[f] ? 1 : 0;
+                    }
+                    const int inc = wave_incl_scan(fl);
+                    if (lane == 63) wsum[wv] = inc;
+                    __syncthreads();
+                    int pre = carry, tot = 0;
+                    for (int w = 0; w < nw; ++w) {
+                        pre += w < wv ? wsum[w] : 0;
+                        tot += wsum[w];
+                    }
+                    if (i < c) RANK[i] = pre + inc - fl;
+                    carry += tot;
+                    __syncthreads();  // wsum is rewritten by the next chunk
+                }
+                if (tid == 0) RANK[c] = carry;
             }
-            __syncthreads();  // also: wsum was read by thread 0
-            const int tl = block_scan_inplace(RANK, c, wsum);
-            if (tid == 0) RANK[c] = tl;
             __syncthreads();
-            // 3. which nodes split (both sides non-empty), children in frontier order
-            for (int f = tid; f < nf; f += T) {
-                const int cnt = fec[f] - fbc[f];
-                const int nl = RANK[fec[f]] - RANK[fbc[f]];
+            // 3. which nodes split (both sides non-empty), children in frontier
+            // order: node f's record, and its children at 2 rk, 2 rk + 1 with rk
+            // its rank among the splitting nodes
+            auto settle = [&](int f, bool split, int nl, int rk) {
                 fnl[f] = nl;
-                frk[f] = (fcand[f] && nl > 0 && nl < cnt) ? 1 : 0;
-            }
-            __syncthreads();
-            const int nsplit = block_scan_inplace(frk, nf, wsum);  // frk: rank among splitting nodes
-            for (int f = tid; f < nf; f += T) {
-                const int cnt = fec[f] - fbc[f];
-                const bool split = fcand[f] && fnl[f] > 0 && fnl[f] < cnt;
+                frk[f] = rk;
                 fcand[f] = split ? 1 : 0;
-                const int lid = flc[f], cl = next_lid + 2 * frk[f];
+                const int lid = flc[f], cl = next_lid + 2 * rk;
                 const size_t slot = 2 * (size_t)vb + lid;
                 int *r = sc.rec + slot * 8;
                 r[0] = vb + fbc[f];
@@ -677,10 +659,10 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
                     sc.rkey[slot * 2 * d + d + k] = hic[(size_t)f * d + k];
                 }
                 if (split) {
-                    const int c0 = 2 * frk[f];
+                    const int c0 = 2 * rk;
                     fbn[c0] = fbc[f];
-                    fen[c0] = fbc[f] + fnl[f];
-                    fbn[c0 + 1] = fbc[f] + fnl[f];
+                    fen[c0] = fbc[f] + nl;
+                    fbn[c0 + 1] = fbc[f] + nl;
                     fen[c0 + 1] = fec[f];
                     fln[c0] = cl;
                     fln[c0 + 1] = cl + 1;
@@ -693,8 +675,39 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
                         hin[(size_t)(c0 + 1) * d + k] = kNegInfKey;
                     }
                 }
+            };
+            auto left_count = [&](int f, bool *split) {
+                const int cnt = fec[f] - fbc[f];
+                const int nl = RANK[fec[f]] - RANK[fbc[f]];
+                *split = fcand[f] && nl > 0 && nl < cnt;
+                return nl;
+            };
+            int nsplit;
+            if (one) {
+                if (tid < 64) {
+                    bool split = false;
+                    const int nl = tid < nf ? left_count(tid, &split) : 0;
+                    const int inc = wave_incl_scan(split ? 1 : 0);
+                    if (tid < nf) settle(tid, split, nl, inc - (split ? 1 : 0));
+                    if (tid == 63) wsum[0] = inc;
+                }
+                __syncthreads();
+                nsplit = wsum[0];
+            } else {
+                for (int f = tid; f < nf; f += T) {
+                    bool split;
+                    fnl[f] = left_count(f, &split);
+                    frk[f] = split ? 1 : 0;
+                }
+                __syncthreads();
+                nsplit = block_scan_inplace(frk, nf, wsum);  // frk: rank among splitting nodes
+                for (int f = tid; f < nf; f += T) {
+                    bool split;
+                    const int nl = left_count(f, &split);
+                    settle(f, split, nl, frk[f]);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             // 4. stable partition into the children (other points keep their place)
             for (int i = tid; i < c; i += T) {
                 const int f = Nc[i], o = Ic[i];
@@ -710,21 +723,66 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
                 Nn[pos] = ch;
             }
             __syncthreads();
-            // 5. the children's boxes, in the new order: a child's points are
-            // consecutive, so a wave mostly meets one or two children
-            if (nsplit > 0)
-                for (int i0 = 0; i0 < c; i0 += T) {  // whole waves: the fold shuffles
-                    const int i = i0 + tid;
-                    const int ch = i < c ? Nn[i] : -1;
-                    const double *xp = X + (size_t)(i < c ? In[i] : 0) * d;
-                    switch (d) {
-                        case 1: wave_fold_keys<1>(ch >= 0, ch, xp, d, lon, hin); break;
-                        case 2: wave_fold_keys<2>(ch >= 0, ch, xp, d, lon, hin); break;
-                        case 3: wave_fold_keys<3>(ch >= 0, ch, xp, d, lon, hin); break;
-                        case 4: wave_fold_keys<4>(ch >= 0, ch, xp, d, lon, hin); break;
-                        default: wave_fold_keys<0>(ch >= 0, ch, xp, d, lon, hin); break;
+            // 5. the children's boxes.  A child's points are consecutive in the
+            // new order: a thread walks a few consecutive positions, folds each
+            // run of one child in registers and updates that child's box once
+            // per run (same-address LDS atomics serialise).
+            if (nsplit > 0) {
+                constexpr int kRun = 8;  // c <= 1024: 128 threads of 8 positions cover it
+                const int CH = min(kRun, max(4, (c + 127) >> 7));
+                const int p0 = tid * CH;
+                if (p0 < c) {
+                    int chs[kRun], ids[kRun];
+#pragma unroll
+                    for (int q = 0; q < kRun; ++q) {
+                        const bool in = q < CH && p0 + q < c;
+                        chs[q] = in ? Nn[p0 + q] : -1;
+                        ids[q] = in ? In[p0 + q] : 0;
+                    }
+                    for (int k = 0; k < d; ++k) {
+                        long long key[kRun];
+#pragma unroll
+                        for (int q = 0; q < kRun; ++q) key[q] = chs[q] >= 0 ? dbl_key(X[(size_t)ids[q] * d + k]) : 0;
+                        // the first run is kept aside and folded at the end with
+                        // the last one; runs in between (a child shorter than
+                        // the thread's positions) fold as they end
+                        int run = chs[0];
+                        bool first = true;
+                        long long fv = kPosInfKey, fx = kNegInfKey, kv = kPosInfKey, kx = kNegInfKey;
+#pragma unroll
+                        for (int q = 0; q < kRun; ++q) {
+                            if (chs[q] != run) {
+                                if (first) {
+                                    fv = kv;
+                                    fx = kx;
+                                    first = false;
+                                } else if (run >= 0) {
+                                    atomicMin(&lon[(size_t)run * d + k], kv);
+                                    atomicMax(&hin[(size_t)run * d + k], kx);
+                                }
+                                run = chs[q];
+                                kv = kPosInfKey;
+                                kx = kNegInfKey;
+                            }
+                            if (chs[q] >= 0) {
+                                kv = key[q] < kv ? key[q] : kv;
+                                kx = key[q] > kx ? key[q] : kx;
+                            }
+                        }
+                        if (first) {
+                            fv = kv;
+                            fx = kx;
+                        } else if (run >= 0) {
+                            atomicMin(&lon[(size_t)run * d + k], kv);
+                            atomicMax(&hin[(size_t)run * d + k], kx);
+                        }
+                        if (chs[0] >= 0) {
+                            atomicMin(&lon[(size_t)chs[0] * d + k], fv);
+                            atomicMax(&hin[(size_t)chs[0] * d + k], fx);
+                        }
                     }
                 }
+            }
             __syncthreads();
             cur = nx;
             next_lid += 2 * nsplit;
@@ -991,7 +1049,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     for (int q = n / std::max(leaf, 1); q > 1; q >>= 1) ++batch;
     // a rebuild of the same shape (a benchmark loop, a sweep over data of one
     // size) starts with the depth and the subtree level seen last time
-    static thread_local struct { int64_t n; int d, leaf, depth, sw; } last{-1, 0, 0, 0, -1};
+    static thread_local struct { int64_t n; int d, leaf, depth, sw, nsw; } last{-1, 0, 0, 0, -1, 0};
     const bool same = last.n == n && last.d == d && last.leaf == leaf;
     if (same) batch = std::max(batch, last.depth + 2);
     // The subtree phase is tried once, at level `target`: the level learnt from
@@ -1041,10 +1099,12 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
         }
         lread = level;
         if (try_sub) {
-            // the frontier (level `target`) has at most 2^target nodes; its
-            // subtrees are at most smax deep
+            // the frontier (level `target`) has at most 2^target nodes, as many
+            // as last time for a rebuild of the same shape (the blocks stride
+            // over whatever it holds); its subtrees are at most smax deep
             const int L = target;
-            const int grid = (int)std::min<long long>(2048, 1LL << std::min(L, 20));
+            int grid = (int)std::min<long long>(2048, 1LL << std::min(L, 20));
+            if (same && last.nsw > 0) grid = std::min(grid, last.nsw);
             int32_t *pio = (L & 1) ? pb : pa;
             double *xio = (L & 1) ? xb : xa;
             hipLaunchKernelGGL(k_subtree, dim3(grid), dim3(1024), sp.lds, st, L, n, d, leaf, sp.smax, sp.fmax, cnt_d,
@@ -1113,7 +1173,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
                 sw = L;
                 break;
             }
-    last = {n, d, leaf, t->depth, sw};
+    last = {n, d, leaf, t->depth, sw, sw >= 0 ? t->level_start[sw + 1] - t->level_start[sw] : 0};
     // the final permutation / points live in pa / xa
     if (pa != t->perm.as<int32_t>()) {
         DFGT_HIP(hipMemcpyAsync(t->perm.p, pa, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
