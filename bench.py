@@ -59,7 +59,7 @@ EXP_SLOTS = 4
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB
 # device copy: profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
 # as profiled; None when it has changed since.
-K_ETILE_TRAFFIC_BYTES = 14.10e6 + 3.16e6
+K_ETILE_TRAFFIC_BYTES = 14.09e6 + 3.16e6
 
 
 def flops_per_pair(d):
