@@ -34,7 +34,8 @@ constexpr long long kPosInfKey = 0x7ff0000000000000LL;                    // key
 constexpr long long kNegInfKey = (long long)0xfff0000000000000ULL ^ 0x7fffffffffffffffLL;  // key of -inf
 // The build's control buffer: ctl[0] done (1) or capacity error (2), [1] a
 // non-finite coordinate, [2..3] the largest |x|^2 (bit pattern), [4] the
-// subtree phase could not run, [5..7] unused; then the level records.
+// subtree phase could not run, [5] its deepest subtree, [6] it built the
+// tree, [7] unused; then the level records.
 constexpr int kCtlHead = 8;
 
 __global__ void k_init(const double *__restrict__ pts, int n, int d, int32_t *perm, double *x, int32_t *pnode,
@@ -139,29 +140,114 @@ __device__ void block_box_fold(bool active, int node, const double *v, int d, lo
     }
 }
 
-// The root's box, and the largest squared norm |x|^2 of the points (folded
-// per block, one atomic per block on its bit pattern: non-negative doubles
-// order like their patterns).
-__global__ __launch_bounds__(kLB) void k_root_box(const double *__restrict__ x, int n, int d, long long *lo_key,
-                                                  long long *hi_key, unsigned long long *nrm_max) {
-    __shared__ FoldShared sh;
-    __shared__ double wmx[kLB / 64];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double v[kMaxD];
-    const bool act = i < n;
+// The root's box, and the largest squared norm |x|^2 of the points.  Each
+// block folds its points (grid-stride) into one partial per bound: wave-wide
+// DPP minima / maxima of the ordered keys, then across the block's waves.
+// The partials go to part[block][2 d + 1] (lo keys, hi keys, the |x|^2 bit
+// pattern: non-negative doubles order like their patterns); k_root_fold
+// folds them.  Same-address device atomics serialise, so an atomic per block
+// and bound cost more than the pass itself, and a last-block fold would need
+// a device-scope release per block, which writes back the XCD's L2.
+constexpr int kRootBlocks = 1024;
+__global__ __launch_bounds__(kLB) void k_root_box(const double *__restrict__ x, int n, int d, long long *part) {
+    __shared__ long long slo[kLB / 64][4], shi[kLB / 64][4];
+    const auto kmin = [](long long a, long long b) { return a < b ? a : b; };
+    const auto kmax = [](long long a, long long b) { return a > b ? a : b; };
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, P = 2 * d + 1;
+    const int i0 = blockIdx.x * kLB + threadIdx.x, stride = gridDim.x * kLB;
+    // |x|^2, FMA-accumulated over the dimensions in order
     double nv = 0.0;
-    if (act)
+    for (int i = i0; i < n; i += stride) {
+        double s2 = 0.0;
         for (int k = 0; k < d; ++k) {
-            v[k] = x[(size_t)i * d + k];
-            nv = fma(v[k], v[k], nv);
+            const double v = x[(size_t)i * d + k];
+            s2 = fma(v, v, s2);
         }
-    for (int off = 32; off >= 1; off >>= 1) nv = fmax(nv, __shfl_xor(nv, off, 64));
-    if ((threadIdx.x & 63) == 0) wmx[threadIdx.x >> 6] = nv;
-    block_box_fold(act, 0, v, d, lo_key, hi_key, sh);  // holds block barriers: wmx is complete after it
-    if (threadIdx.x == 0) {
-        double m = wmx[0];
-        for (int w = 1; w < kLB / 64; ++w) m = fmax(m, wmx[w]);
-        atomicMax(nrm_max, (unsigned long long)__double_as_longlong(m));
+        nv = fmax(nv, s2);
+    }
+    // keys, four dimensions per pass; the last slot of a pass carries |x|^2
+    for (int k0 = 0; k0 <= d; k0 += 4) {
+        long long lo[4], hi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lo[j] = kPosInfKey;
+            hi[j] = kNegInfKey;
+        }
+        for (int i = i0; i < n; i += stride)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (k0 + j < d) {
+                    const long long key = dbl_key(x[(size_t)i * d + k0 + j]);
+                    lo[j] = key < lo[j] ? key : lo[j];
+                    hi[j] = key > hi[j] ? key : hi[j];
+                } else if (k0 + j == d) {
+                    hi[j] = (long long)__double_as_longlong(nv);  // the same for every point pass
+                }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lo[j] = wave_scan_dpp(lo[j], kPosInfKey, kmin);
+            hi[j] = wave_scan_dpp(hi[j], kNegInfKey, kmax);
+        }
+        if (lane == 63)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                slo[wv][j] = lo[j];
+                shi[wv][j] = hi[j];
+            }
+        __syncthreads();
+        if (threadIdx.x < 4 && k0 + (int)threadIdx.x <= d) {
+            const int j = threadIdx.x, k = k0 + j;
+            long long a = slo[0][j], b = shi[0][j];
+            for (int w = 1; w < kLB / 64; ++w) {
+                a = kmin(a, slo[w][j]);
+                b = kmax(b, shi[w][j]);
+            }
+            if (k < d) {
+                part[(size_t)blockIdx.x * P + k] = a;
+                part[(size_t)blockIdx.x * P + d + k] = b;
+            } else {
+                part[(size_t)blockIdx.x * P + 2 * d] = b < 0 ? 0 : b;  // no point in the block: 0
+            }
+        }
+        __syncthreads();  // slo / shi are rewritten by the next pass
+    }
+}
+
+// Folds the G block partials of k_root_box into the root's bounds and the
+// largest |x|^2 (one block; the kernel boundary makes the partials visible).
+__global__ __launch_bounds__(kLB) void k_root_fold(const long long *__restrict__ part, int G, int d,
+                                                   long long *lo_key, long long *hi_key,
+                                                   unsigned long long *nrm_max) {
+    __shared__ long long sred[kLB / 64][4];
+    const auto kmin = [](long long a, long long b) { return a < b ? a : b; };
+    const auto kmax = [](long long a, long long b) { return a > b ? a : b; };
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, P = 2 * d + 1;
+    for (int j0 = 0; j0 < P; j0 += 4) {
+        long long acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = j0 + j < d ? kPosInfKey : kNegInfKey;
+        for (int b = threadIdx.x; b < G; b += kLB)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j0 + j < P) {
+                    const long long v = part[(size_t)b * P + j0 + j];
+                    acc[j] = j0 + j < d ? kmin(acc[j], v) : kmax(acc[j], v);
+                }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            acc[j] = j0 + j < d ? wave_scan_dpp(acc[j], kPosInfKey, kmin) : wave_scan_dpp(acc[j], kNegInfKey, kmax);
+            if (lane == 63) sred[wv][j] = acc[j];
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && j0 + (int)threadIdx.x < P) {
+            const int j = j0 + threadIdx.x;
+            long long a = sred[0][threadIdx.x];
+            for (int w = 1; w < kLB / 64; ++w) a = j < d ? kmin(a, sred[w][threadIdx.x]) : kmax(a, sred[w][threadIdx.x]);
+            if (j < d) lo_key[j] = a;
+            else if (j < 2 * d) hi_key[j - d] = a;
+            else *nrm_max = (unsigned long long)a;
+        }
+        __syncthreads();  // sred is rewritten by the next pass
     }
 }
 
@@ -209,16 +295,23 @@ __global__ __launch_bounds__(kLB) void k_flag(const double *__restrict__ x, cons
                                               int32_t *flag, int32_t *rank, int32_t *bsum,
                                               const int *__restrict__ done) {
     __shared__ int wsum[kLB / 64];
-    if (*done) return;
     const int i = blockIdx.x * kLB + threadIdx.x;
+    // the point's node and first coordinates are loaded with the done flag
+    // (all in bounds either way): one round trip fewer before the split rule
+    const int dn = *done;
+    const int node = i < n ? pnode[i] : -1;
+    double xs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xs[k] = (i < n && k < d) ? x[(size_t)i * d + k] : 0.0;
+    if (dn) return;
     int f = 0;
-    if (i < n) {
-        const int node = pnode[i];
-        if (node >= 0) {
-            int sd;
-            double sc;
-            if (node_split(lo_key, hi_key, node, d, end[node] - begin[node], leaf, &sd, &sc))
-                f = x[(size_t)i * d + sd] <= sc ? 1 : 0;
+    if (node >= 0) {
+        int sd;
+        double sc;
+        if (node_split(lo_key, hi_key, node, d, end[node] - begin[node], leaf, &sd, &sc)) {
+            const double xv = sd == 0 ? xs[0] : sd == 1 ? xs[1] : sd == 2 ? xs[2] : sd == 3 ? xs[3]
+                                                                                        : x[(size_t)i * d + sd];
+            f = xv <= sc ? 1 : 0;
         }
     }
     int tot;
@@ -229,6 +322,8 @@ __global__ __launch_bounds__(kLB) void k_flag(const double *__restrict__ x, cons
     }
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
+
+constexpr int kFinOffLds = 4096;  // block offsets k_finalize keeps in LDS (n <= 2^20)
 
 // One block: the exclusive scan of the block totals (boff), then the splits of
 // level nodes [lb, le): a node's left count is the difference of the global
@@ -246,14 +341,32 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
                                                    int nb, int32_t *boff) {
     __shared__ int warp_tot[16], warp_cb[16];
     __shared__ int carry_s;
-    if (*done) return;
+    __shared__ int boff_s[kFinOffLds];  // the first kFinOffLds block offsets
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // Loads that do not wait for the block-offset scan go first: the level's
+    // bounds and the first block sums with the done flag, then the first
+    // chunk's node ranges, split rules and the flag ranks at both ends.
+    const int dn = *done;
+    const int lb = lvs[3 * level], le = lvs[3 * level + 1];
+    const int v0 = (int)threadIdx.x < nb ? bsum[threadIdx.x] : 0;
+    if (dn) return;  // the level records past the last level are not valid
+    const int node0 = lb + threadIdx.x;
+    int b0 = 0, e0 = 0, sd0 = -1, rb0 = 0, re0 = 0;
+    double sc0 = 0.0;
+    bool cand0 = false;
+    if (node0 < le) {
+        b0 = begin[node0];
+        e0 = end[node0];
+        rb0 = rank[b0];  // a node is never empty: b0 < e0 <= n
+        re0 = e0 < n ? rank[e0] : 0;
+        cand0 = node_split(lo_key, hi_key, node0, d, e0 - b0, leaf, &sd0, &sc0);
+    }
     // 1. block offsets
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     for (int c0 = 0; c0 < nb; c0 += blockDim.x) {
         const int i = c0 + threadIdx.x;
-        const int v = i < nb ? bsum[i] : 0;
+        const int v = c0 == 0 ? v0 : (i < nb ? bsum[i] : 0);
         const int inc = wave_incl_scan(v);
         if (lane == 63) warp_tot[w] = inc;
         __syncthreads();
@@ -261,28 +374,48 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
         for (int k = 0; k < w; ++k) wb += warp_tot[k];
         const int ex = carry_s + wb + inc - v;
         __syncthreads();
-        if (i < nb) boff[i] = ex;
+        if (i < nb) {
+            boff[i] = ex;
+            if (i < kFinOffLds) boff_s[i] = ex;
+        }
         if (threadIdx.x == blockDim.x - 1) carry_s = ex + v;
         __syncthreads();
     }
     const int total = carry_s;
     __syncthreads();  // boff written by this block is visible to it from here
-    // global exclusive left rank at a position (n: the total)
-    auto grank = [&](int pos) { return pos >= n ? total : boff[pos / kLB] + rank[pos]; };
+    auto boffv = [&](int blk) { return blk < kFinOffLds ? boff_s[blk] : boff[blk]; };
     // 2. splits and children
-    const int lb = lvs[3 * level], le = lvs[3 * level + 1];
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     int big = 0, cbig = 0;  // the largest node of the level and of the next one
     for (int c0 = lb; c0 < le; c0 += blockDim.x) {
         const int node = c0 + threadIdx.x;
-        int split = 0, sd = -1, nl = 0;
+        int split = 0, sd = -1, nl = 0, b = 0, e = 0;
         double sc = 0.0;
         if (node < le) {
-            const int b = begin[node], e = end[node], cnt = e - b;
+            int rb, re;
+            bool cand;
+            if (c0 == lb) {
+                b = b0;
+                e = e0;
+                rb = rb0;
+                re = re0;
+                cand = cand0;
+                sd = sd0;
+                sc = sc0;
+            } else {
+                b = begin[node];
+                e = end[node];
+                rb = rank[b];
+                re = e < n ? rank[e] : 0;
+                cand = node_split(lo_key, hi_key, node, d, e - b, leaf, &sd, &sc);
+            }
+            const int cnt = e - b;
             big = max(big, cnt);
-            if (node_split(lo_key, hi_key, node, d, cnt, leaf, &sd, &sc)) {
-                nl = grank(e) - grank(b);
+            if (cand) {
+                // global exclusive left ranks at the node's end and begin (n: the total)
+                const int ge = e >= n ? total : boffv(e / kLB) + re;
+                nl = ge - (boffv(b / kLB) + rb);
                 split = (nl > 0 && nl < cnt) ? 1 : 0;
                 if (split) cbig = max(cbig, max(nl, cnt - nl));
             }
@@ -297,7 +430,6 @@ __global__ __launch_bounds__(1024) void k_finalize(int level, int cap, int *lvs,
         if (node < le) {
             if (split) {
                 const int L = le + 2 * rk, R = L + 1;
-                const int b = begin[node], e = end[node];
                 left[node] = L;
                 right[node] = R;
                 sdim[node] = sd;
@@ -963,6 +1095,7 @@ struct BuildWs {
     DevBuf perm_b, x_b, pnode_a, pnode_b, flag, rank, bsums, boff, lo_key, hi_key, nleft;
     DevBuf ctl;   // kCtlHead flags, then per level start, end, largest node
     DevBuf sub;   // the subtree phase's records
+    DevBuf rpart; // the root box's per-block partials
     HostBuf back;  // pinned copy of ctl
 };
 thread_local BuildWs g_build;
@@ -1035,8 +1168,12 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, lo_key.as<long long>(), hi_key.as<long long>(), d,
                        t->begin.as<int32_t>(), t->end.as<int32_t>(), t->parent.as<int32_t>(), n, cnt_d);
     hipLaunchKernelGGL(k_init, dim3(gb), dim3(kLB), 0, st, pts, n, d, pa, xa, na, cnt_d + 1);
-    hipLaunchKernelGGL(k_root_box, dim3(gb), dim3(kLB), 0, st, xa, n, d, lo_key.as<long long>(),
-                       hi_key.as<long long>(), reinterpret_cast<unsigned long long *>(cnt_d + 2));
+    const int grb = std::min(gb, kRootBlocks);
+    DFGT_TRY(w.rpart.reserve(sizeof(long long) * (size_t)grb * (2 * d + 1)));
+    hipLaunchKernelGGL(k_root_box, dim3(grb), dim3(kLB), 0, st, xa, n, d, w.rpart.as<long long>());
+    hipLaunchKernelGGL(k_root_fold, dim3(1), dim3(kLB), 0, st, w.rpart.as<long long>(), grb, d,
+                       lo_key.as<long long>(), hi_key.as<long long>(),
+                       reinterpret_cast<unsigned long long *>(cnt_d + 2));
     DFGT_HIP(hipGetLastError());
 
     // Levels are enqueued in batches without host round trips: the first
