@@ -650,7 +650,8 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
                                                  const long long *__restrict__ lo_key,
                                                  const long long *__restrict__ hi_key,
                                                  const int32_t *__restrict__ begin, const int32_t *__restrict__ end,
-                                                 double *x_io, int32_t *perm_io, SubScratch sc) {
+                                                 const double *x_io, const int32_t *perm_io, double *x_out,
+                                                 int32_t *perm_out, SubScratch sc) {
     extern __shared__ double sm[];
     const int *lvs = ctl + kCtlHead;
     if (ctl[0]) return;  // the tree was complete before level L
@@ -921,12 +922,12 @@ __global__ __launch_bounds__(1024) void k_subtree(int L, int n, int d, int leaf,
             nf = 2 * nsplit;
             ++depth;
         }
-        // the subtree's points in tree order, back in place
+        // the subtree's points in tree order, into the tree's point buffer
         const int *Ic = IDX + cur * smax;
         for (int i = tid; i < c; i += T) {
             const int o = Ic[i];
-            for (int k = 0; k < d; ++k) x_io[(size_t)(vb + i) * d + k] = X[(size_t)o * d + k];
-            perm_io[vb + i] = P0[o];
+            for (int k = 0; k < d; ++k) x_out[(size_t)(vb + i) * d + k] = X[(size_t)o * d + k];
+            perm_out[vb + i] = P0[o];
         }
         if (tid == 0) {
             sc.sinfo[fi] = make_int2(vb, depth);
@@ -1003,14 +1004,25 @@ __global__ __launch_bounds__(256) void k_subtree_scan(int L, const int *ctl, Sub
 // starts after levels L .. L + j - 1 (their totals); block 0 also writes the
 // level records of levels L + 1 .. L + J (the last one empty) and marks the
 // tree complete.
-__global__ __launch_bounds__(256) void k_subtree_emit(int L, int d, int smax, int *ctl, SubScratch sc,
+__global__ __launch_bounds__(256) void k_subtree_emit(int L, int n, int d, int smax, int *ctl, SubScratch sc,
                                                       int32_t *begin, int32_t *end, int32_t *left, int32_t *right,
                                                       int32_t *parent, int32_t *sdim, double *scoord,
-                                                      long long *lo_key, long long *hi_key) {
+                                                      long long *lo_key, long long *hi_key,
+                                                      const int32_t *__restrict__ pnode, const double *x_in,
+                                                      const int32_t *perm_in, double *x_out, int32_t *perm_out) {
     extern __shared__ int sdi[];  // dstart[smax + 1] | gbase[smax + 1]
     int *lvs = ctl + kCtlHead;
     const int J = ctl[5];
     if (J == 0) return;
+    // k_subtree wrote the frontier's points to the tree's buffer; when the
+    // level kernels left the points in the other one, the points of earlier
+    // leaves (no node at level L) follow them there
+    if (x_in != x_out)
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+            if (pnode[i] < 0) {
+                for (int k = 0; k < d; ++k) x_out[(size_t)i * d + k] = x_in[(size_t)i * d + k];
+                perm_out[i] = perm_in[i];
+            }
     const int fl0 = lvs[3 * L], fl1 = lvs[3 * L + 1];
     int *dstart = sdi, *gbase = sdi + smax + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1195,7 +1207,7 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
     // points, the device leaves everything untouched and the levels go on one
     // by one.
     const SubParams sp = sub_params(d, leaf);
-    int target = -1, sub_level = -1;
+    int target = -1;
     SubScratch sc{};
     if (sp.smax) {
         if (same) {
@@ -1242,21 +1254,22 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
             const int L = target;
             int grid = (int)std::min<long long>(2048, 1LL << std::min(L, 20));
             if (same && last.nsw > 0) grid = std::min(grid, last.nsw);
-            int32_t *pio = (L & 1) ? pb : pa;
+            // the points of level L are in buffer L % 2; the phase leaves the
+            // tree's points in buffer 0 (t->x, t->perm)
+            int32_t *pio = (L & 1) ? pb : pa, *nio = (L & 1) ? nb : na;
             double *xio = (L & 1) ? xb : xa;
             hipLaunchKernelGGL(k_subtree, dim3(grid), dim3(1024), sp.lds, st, L, n, d, leaf, sp.smax, sp.fmax, cnt_d,
                                lo_key.as<long long>(), hi_key.as<long long>(), t->begin.as<int32_t>(),
-                               t->end.as<int32_t>(), xio, pio, sc);
+                               t->end.as<int32_t>(), xio, pio, xa, pa, sc);
             hipLaunchKernelGGL(k_subtree_scan, dim3(32), dim3(256), 0, st, L, cnt_d, sc);
             hipLaunchKernelGGL(k_subtree_emit, dim3(grid), dim3(256), sizeof(int) * 2 * ((size_t)sp.smax + 1), st, L,
-                               d, sp.smax, cnt_d, sc, t->begin.as<int32_t>(), t->end.as<int32_t>(),
+                               n, d, sp.smax, cnt_d, sc, t->begin.as<int32_t>(), t->end.as<int32_t>(),
                                t->left.as<int32_t>(), t->right.as<int32_t>(), t->parent.as<int32_t>(),
                                t->sdim.as<int32_t>(), t->scoord.as<double>(), lo_key.as<long long>(),
-                               hi_key.as<long long>());
+                               hi_key.as<long long>(), nio, xio, pio, xa, pa);
             DFGT_HIP(hipGetLastError());
             lread = std::min(max_levels, L + sp.smax + 1);
             target = -1;
-            sub_level = L;
         }
         // flags and the records of levels 0 .. lread, one copy
         const size_t nback = sizeof(int) * (kCtlHead + 3 * ((size_t)lread + 1));
@@ -1293,8 +1306,8 @@ dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w
         t->level_max[k] = hl[3 * (size_t)k + 2];
     }
     const int le = hl[3 * (size_t)K + 1];
-    // the subtree phase leaves the points where its frontier had them
-    if ((sub_done ? sub_level : K) & 1) {
+    // the level kernels leave the points in buffer K % 2, the subtree phase in buffer 0
+    if (!sub_done && (K & 1)) {
         pa = perm_b.as<int32_t>();
         xa = x_b.as<double>();
     }
