@@ -65,7 +65,7 @@ def test_naive_full_size_sampled(dfgt):
     np.testing.assert_allclose(G[rows], ref, rtol=MIXED_RTOL)
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 5, 16])
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 16, 32])
 @pytest.mark.parametrize("leaf", [1, 4, 32])
 def test_tree_bit_exact_random(dfgt, d, leaf):
     rng = np.random.default_rng(100 * d + leaf)
@@ -98,6 +98,19 @@ def test_tree_rebuilds_of_one_shape(dfgt):
                 note(f"tree sizes n={n} d={d} leaf={leaf} rep={rep}")
                 t = dfgt.build_tree(cuda(x), leaf_size=leaf)
                 compare_trees(dfgt.tree_export(t), ref, t.info()["depth"])
+
+
+def test_tree_large_frontier(dfgt):
+    # 1.5M uniform 2-D points: the first build guesses level 13 for the
+    # per-node phase, where 8192 nodes share its 2048 blocks (several subtrees
+    # per block); the rebuild starts at level 11, the first whose nodes hold
+    # at most 1024 points (2048 nodes)
+    x = np.random.default_rng(15).uniform(size=(1_500_000, 2))
+    ref = oracle.build_kdtree(x, 32)
+    for rep in range(2):
+        note(f"tree large frontier rep={rep}")
+        t = dfgt.build_tree(cuda(x), leaf_size=32)
+        compare_trees(dfgt.tree_export(t), ref, t.info()["depth"])
 
 
 def test_tree_deep_chain(dfgt):
