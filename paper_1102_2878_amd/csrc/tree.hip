@@ -17,7 +17,11 @@
 // Box folds reduce in the block first (LDS atomics over the block's nodes, a
 // contiguous id range) and issue one global atomic per (node, dimension) per
 // block: same-address device atomics serialise, and near the root every block
-// would otherwise hit the same few nodes.
+// would otherwise hit the same few nodes.  The root's box comes from block
+// partials folded by one block (k_root_box, k_root_fold).
+// Below the first level whose nodes all fit in a block's LDS the rest of the
+// tree is built per node, one block per subtree (k_subtree, k_subtree_scan,
+// k_subtree_emit below): the same rule, the same result.
 // The result is bit-identical to the recursive algorithm (same boxes, split
 // dimensions, split coordinates and permutation); only node numbering differs
 // (breadth-first instead of pre-order).
