@@ -9,13 +9,17 @@ One step = the whole hot path over that input, resident in HBM:
   kd-tree build + raw moments (dfgt_build_tree)  ->  DFGT for all seven
   bandwidths in one traversal (dfgt_gauss_sum).
 value = N_Q * N_R * 7 / (seconds per step)  [query x reference pairs / s].
+The kd-tree leaf size is picked before anything is timed by
+dfgt_tune_leaf_size on this workload (--leaf N fixes it instead); the choice
+and every candidate's time are in config.leaf_tuning.
 The plain tiled brute-force GPU sum (dfgt_naive_sum) over the same seven
 bandwidths is timed alongside.
 
 batched: the 3-D batch, 8 clustered problems of 10k..200k points, each swept
 over 64 log-spaced bandwidths h_S x 10^{-3..3} at h and sqrt(2) h (the LSCV
 pair): 1024 sums in one traversal, eager and as a captured graph replay,
-beside the brute force over the same 1024 sums.
+beside the brute force over the same 1024 sums; its leaf size is tuned on the
+largest problem.
 
 grad_ms (the metric's second part): the backward pass on the 16-D workload,
 200,000 points (8 latent clusters embedded + N(0, 0.01 I) noise), eps 1e-4,
@@ -42,7 +46,6 @@ sys.path.insert(0, ROOT)
 METRIC = "query×ref pairs/s at rel-err 1e-2 (dual-tree vs brute-force GPU) + grad ms"
 SCALES = [1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0, 1000.0]
 EPS = 1e-2
-LEAF = 32
 
 # Exhaustive-tile roofline (bound "alu"): the algorithmic work per point pair is
 # 2D+1 FP32 VALU operations (D differences, D-1 fused multiply-adds + 1 multiply,
@@ -70,9 +73,9 @@ def base_peak_pairs(d):
     return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
 
 
-def per_bandwidth(torch, dfgt, x, hs, reps=3):
+def per_bandwidth(torch, dfgt, x, hs, leaf, reps=3):
     """Median ms per single-bandwidth call: DFGT, DFD ablation, brute force."""
-    R = dfgt.build_tree(x, leaf_size=LEAF)
+    R = dfgt.build_tree(x, leaf_size=leaf)
 
     def med(f):
         f()
@@ -97,13 +100,23 @@ def per_bandwidth(torch, dfgt, x, hs, reps=3):
                     "centroid finite-difference prune), brute force", "rows": rows}
 
 
-def batched_bench(torch, dfgt, synth):
-    """The 3-D batch: eager call, graph replays, brute force; returns details."""
+def batched_bench(torch, dfgt, synth, leaf):
+    """The 3-D batch: eager call, graph replays, brute force; returns details.
+
+    leaf 0: the leaf size comes from dfgt_tune_leaf_size on the largest problem
+    at 16 of its bandwidths (outside the timed region)."""
     xs = [synth.c4_problem(k) for k in range(8)]
     xd = [torch.as_tensor(x, device="cuda") for x in xs]
     torch.cuda.synchronize()
+    tuning = None
+    if leaf == 0:
+        big = int(np.argmax([len(x) for x in xs]))
+        hb = synth.silverman_h(xs[big]) * np.geomspace(1e-3, 1e3, 16)
+        leaf, tms = dfgt.tune_leaf_size(xd[big], hb, EPS, reps=2)
+        tuning = {"on": f"the largest problem (N = {len(xs[big])}), 16 log-spaced bandwidths, 2 repetitions",
+                  "candidates_ms": {str(k): v for k, v in tms.items()}}
     t0 = time.perf_counter()
-    trees = [dfgt.build_tree(x, leaf_size=LEAF) for x in xd]
+    trees = [dfgt.build_tree(x, leaf_size=leaf) for x in xd]
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     probs = []
@@ -136,7 +149,8 @@ def batched_bench(torch, dfgt, synth):
     pairs = float(sum(x.shape[0] ** 2 for x in xs)) * 128
     return {
         "workload": "3-D, 8 clustered problems N = 10k..200k (sum 690k), 64 log-spaced h x {1, sqrt2}, eps 1e-2",
-        "sums": 8 * 128, "build_ms": t_build * 1e3, "eager_ms": t_eager * 1e3, "graph_replay_ms": t_graph * 1e3,
+        "sums": 8 * 128, "leaf_size": leaf, "leaf_tuning": tuning,
+        "build_ms": t_build * 1e3, "eager_ms": t_eager * 1e3, "graph_replay_ms": t_graph * 1e3,
         "pairs_per_s_graph": pairs / t_graph, "bruteforce_ms": t_bf * 1e3, "bruteforce_pairs_per_s": pairs / t_bf,
         "speedup_vs_bruteforce": t_bf / t_graph, "max_rel_err_vs_bruteforce": worst,
         "node_pairs": b.stats["node_pairs"], "base_point_pairs": b.stats["base_point_pairs"],
@@ -202,6 +216,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--grad-leaf", type=int, default=128)
+    ap.add_argument("--leaf", type=int, default=0,
+                    help="leaf size of the 2-D and batched workloads; 0 = dfgt_tune_leaf_size picks it (untimed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -224,8 +240,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the leaf size: tuned on this workload before anything is timed
+    leaf = args.leaf
+    leaf_tuning = None
+    if leaf == 0:
+        leaf, tms = dfgt.tune_leaf_size(x, hs, EPS, reps=3)
+        leaf_tuning = {"on": "this workload (build + the 7-bandwidth sums), 3 repetitions",
+                       "candidates_ms": {str(k): v for k, v in tms.items()}}
+
     def step(profile):
-        t = dfgt.build_tree(x, leaf_size=LEAF)
+        t = dfgt.build_tree(x, leaf_size=leaf)
         if not profile:
             return dfgt.gauss_sum(t, t, hs, EPS), None
         return dfgt.gauss_sum(t, t, hs, EPS, stats=True, profile=True)
@@ -257,7 +281,7 @@ def main():
     stats = st
 
     # base-case tiles inside the per-leaf kernel: every leaf pair exhaustive at h*
-    _, st_x = dfgt.gauss_sum(tree_x := dfgt.build_tree(x, leaf_size=LEAF), tree_x, [hstar], EPS,
+    _, st_x = dfgt.gauss_sum(tree_x := dfgt.build_tree(x, leaf_size=leaf), tree_x, [hstar], EPS,
                              force_method=dfgt.FORCE_EXACT, stats=True, profile=True)
     _, st_x = dfgt.gauss_sum(tree_x, tree_x, [hstar], EPS, force_method=dfgt.FORCE_EXACT, stats=True, profile=True)
     base_case = {"pairs": st_x["base_point_pairs"], "k_etile_ms": st_x["kernel_ms"]["etile"]}
@@ -267,12 +291,12 @@ def main():
     # synthetic stand-in): DFGT, the DFD ablation (centroid finite-difference
     # prune only, p_max = 1 rule of the same code) and the brute force, one
     # bandwidth per call, tree built once
-    per_h = per_bandwidth(torch, dfgt, x, hs)
+    per_h = per_bandwidth(torch, dfgt, x, hs, leaf)
 
     # build alone
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dfgt.build_tree(x, leaf_size=LEAF)
+        dfgt.build_tree(x, leaf_size=leaf)
     torch.cuda.synchronize()
     t_build = (time.perf_counter() - t0) / args.steps
 
@@ -332,7 +356,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "2-D clustered mixture, 50,000 points (Q = R), 7 bandwidths h* x 10^-3..10^3, eps 1e-2",
-            "n": n, "d": d, "n_bandwidths": len(hs), "eps": EPS, "h_star": hstar, "leaf_size": LEAF,
+            "n": n, "d": d, "n_bandwidths": len(hs), "eps": EPS, "h_star": hstar, "leaf_size": leaf,
+            "leaf_tuning": leaf_tuning,
             "p_max": 6,
         },
         "bruteforce_gpu": {"value": pairs / t_bf, "unit": "pairs/s", "ms_per_sweep": t_bf * 1e3},
@@ -358,7 +383,7 @@ def main():
     }
 
     if not args.no_batched:
-        out["batched"] = batched_bench(torch, dfgt, synth)
+        out["batched"] = batched_bench(torch, dfgt, synth, args.leaf)
     if not args.no_grad:
         out["grad_ms"], out["grad"] = grad_bench(args, torch, dfgt, synth)
 

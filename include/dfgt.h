@@ -353,6 +353,29 @@ dfgt_status dfgt_gauss_sum_batched(const dfgt_problem *probs, int32_t n_probs, d
                                    const dfgt_options *opt, dfgt_stats *stats, void *stream);
 
 /*
+ * Leaf-size tuning: the kd-tree leaf threshold of Alg. BuildKdTree trades
+ * tree depth (traversal levels, build levels, expansions) against exhaustive
+ * leaf-leaf work (DFGTBase), and the best value depends on the data, D and the
+ * bandwidths.  For each candidate in DFGT_TUNE_LEAVES the call times, with HIP
+ * events on the stream, `reps` repetitions of a tree build on pts_dev (n x d,
+ * float64, device) plus the monochromatic sums dfgt_gauss_sum(T, T, h_host,
+ * n_h, eps) (after one untimed repetition), and returns the candidate with the
+ * smallest median time in *leaf_out.  ms_out (may be NULL) receives the
+ * DFGT_N_TUNE_LEAVES medians in milliseconds, in the order of the list.  opt
+ * supplies the other build and sum options (its leaf_size is ignored).  The
+ * sums of every candidate satisfy the same error bound; the choice only
+ * affects time, and timing noise can make it differ between calls.  Allocates
+ * an n_h x n output buffer for the duration of the call and synchronises the
+ * stream after every repetition.  1 <= reps <= 100; other errors as those of
+ * dfgt_build_tree and dfgt_gauss_sum.
+ */
+#define DFGT_N_TUNE_LEAVES 5
+#define DFGT_TUNE_LEAVES {16, 32, 64, 128, 256}
+dfgt_status dfgt_tune_leaf_size(const double *pts_dev, int64_t n, int32_t d, const double *h_host, int32_t n_h,
+                                double eps, const dfgt_options *opt, int32_t reps, void *stream,
+                                int32_t *leaf_out, double *ms_out);
+
+/*
  * A batch captured as a HIP graph, for callers that repeat the same sweep (or
  * must not pay per-launch host overhead): dfgt_batch_create runs the batch
  * once eagerly (which sizes every internal buffer; stats, if given, are that

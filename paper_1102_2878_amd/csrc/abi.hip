@@ -525,6 +525,66 @@ dfgt_status dfgt_lscv_optimize(dfgt_tree R, double h_lo, double h_hi, double eps
     DFGT_GUARD_END
 }
 
+dfgt_status dfgt_tune_leaf_size(const double *pts_dev, int64_t n, int32_t d, const double *h_host, int32_t n_h,
+                                double eps, const dfgt_options *opt, int32_t reps, void *stream,
+                                int32_t *leaf_out, double *ms_out) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(leaf_out != nullptr, "dfgt_tune_leaf_size: leaf_out is NULL");
+    DFGT_REQUIRE(reps >= 1 && reps <= 100, "dfgt_tune_leaf_size: reps must be in [1, 100]");
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_tune_leaf_size"));
+    DFGT_REQUIRE(n >= 1 && n < (int64_t(1) << 30), "dfgt_tune_leaf_size: n must be in [1, 2^30)");
+    hipStream_t st = (hipStream_t)stream;
+    // the output buffer and the two events, released on every exit
+    struct Res {
+        double *G = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Res() {
+            if (G) (void)hipFree(G);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } res;
+    DFGT_REQUIRE(hipMalloc(&res.G, sizeof(double) * (size_t)n_h * (size_t)n) == hipSuccess,
+                 "dfgt_tune_leaf_size: hipMalloc of the output buffer failed");
+    DFGT_HIP(hipEventCreate(&res.e0));
+    DFGT_HIP(hipEventCreate(&res.e1));
+    dfgt_options o{};
+    if (opt) o = *opt;
+    const int leaves[DFGT_N_TUNE_LEAVES] = DFGT_TUNE_LEAVES;
+    double best = 0.0;
+    int best_leaf = 0;
+    for (int c = 0; c < DFGT_N_TUNE_LEAVES; ++c) {
+        o.leaf_size = leaves[c];
+        std::vector<float> t;
+        for (int r = 0; r <= reps; ++r) {
+            DFGT_HIP(hipEventRecord(res.e0, st));
+            dfgt_tree T = nullptr;
+            DFGT_TRY(dfgt_build_tree(pts_dev, n, d, &o, stream, &T));
+            const dfgt_status sum = dfgt_gauss_sum(T, T, h_host, n_h, eps, &o, res.G, nullptr, stream);
+            if (sum != DFGT_OK) {
+                (void)dfgt_tree_free(T);
+                return sum;
+            }
+            DFGT_HIP(hipEventRecord(res.e1, st));
+            DFGT_HIP(hipEventSynchronize(res.e1));
+            DFGT_TRY(dfgt_tree_free(T));
+            float ms = 0.0f;
+            DFGT_HIP(hipEventElapsedTime(&ms, res.e0, res.e1));
+            if (r > 0) t.push_back(ms);  // the first repetition sizes the workspaces
+        }
+        std::sort(t.begin(), t.end());
+        const double med = t.size() % 2 ? t[t.size() / 2] : 0.5 * ((double)t[t.size() / 2 - 1] + t[t.size() / 2]);
+        if (ms_out) ms_out[c] = med;
+        if (best_leaf == 0 || med < best) {
+            best = med;
+            best_leaf = leaves[c];
+        }
+    }
+    *leaf_out = best_leaf;
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
 static dfgt_status collect_problems(const dfgt_problem *probs, int32_t n, double eps, const char *who,
                                     std::vector<Problem> &out) {
     DFGT_REQUIRE(probs != nullptr && n >= 1, std::string(who) + ": need at least one problem");

@@ -87,6 +87,8 @@ def lib():
                                      C.POINTER(dbl), C.POINTER(Stats), vp]
         L.dfgt_lscv_optimize.argtypes = [vp, dbl, dbl, dbl, i32, i32, dbl, C.POINTER(Options), C.POINTER(dbl),
                                          C.POINTER(dbl), C.POINTER(i32), vp]
+        L.dfgt_tune_leaf_size.argtypes = [vp, i64, i32, C.POINTER(dbl), i32, dbl, C.POINTER(Options), i32, vp,
+                                          C.POINTER(i32), C.POINTER(dbl)]
         L.dfgt_gauss_sum_batched.argtypes = [C.POINTER(Problem), i32, dbl, C.POINTER(Options), C.POINTER(Stats), vp]
         L.dfgt_batch_create.argtypes = [C.POINTER(Problem), i32, dbl, C.POINTER(Options), C.POINTER(Stats), vp,
                                         C.POINTER(vp)]
@@ -315,6 +317,22 @@ def lcv_score(R: Tree, h, eps, grad=False, precision=PREC_MIXED, force_method=FO
                                 dcv.ctypes.data_as(C.POINTER(C.c_double)) if dcv is not None else None, None,
                                 _stream()))
     return (cv, dcv) if grad else cv
+
+
+TUNE_LEAVES = (16, 32, 64, 128, 256)
+
+
+def tune_leaf_size(points, h, eps, reps=3, p_max=0, precision=PREC_MIXED, cost_exhaustive=0.0):
+    """dfgt_tune_leaf_size: (leaf, {candidate: median ms of build + monochromatic sums})."""
+    x = _dev_points(points)
+    hv, hp = _hvec(h)
+    o = _opts(0, p_max, precision, FORCE_NONE)
+    o.cost_exhaustive = float(cost_exhaustive)
+    leaf = C.c_int32()
+    ms = (C.c_double * len(TUNE_LEAVES))()
+    _check(lib().dfgt_tune_leaf_size(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], hp, hv.shape[0], float(eps),
+                                     C.byref(o), int(reps), _stream(), C.byref(leaf), ms))
+    return leaf.value, dict(zip(TUNE_LEAVES, list(ms)))
 
 
 def lscv_optimize(R: Tree, h_lo, h_hi, eps, variant=1, n_grid=16, rel_tol=1e-3, precision=PREC_MIXED,

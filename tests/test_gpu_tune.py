@@ -1,0 +1,49 @@
+"""GPU tests of dfgt_tune_leaf_size: it returns one of its candidates (the one
+with the smallest reported time), every candidate's sums run, and the sums of
+a tree built with the returned leaf size hold the error bound against the
+oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1102_2878_amd import synth
+from tests.gpu_util import cuda, note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dfgt():
+    from paper_1102_2878_amd import dfgt as m
+    return m
+
+
+@pytest.mark.parametrize("maker,n", [("c2", 20000), ("c3", 8000)])
+def test_tune_leaf_size(dfgt, maker, n):
+    x = getattr(synth, maker)(n=n, seed=61)
+    hs = [synth.silverman_h(x) * s for s in (0.1, 1.0, 10.0)]
+    note(f"tune leaf {maker}")
+    leaf, ms = dfgt.tune_leaf_size(cuda(x), hs, 1e-2, reps=2)
+    assert leaf in dfgt.TUNE_LEAVES
+    assert set(ms) == set(dfgt.TUNE_LEAVES)
+    assert all(np.isfinite(v) and v > 0 for v in ms.values())
+    assert ms[leaf] == min(ms.values())
+    t = dfgt.build_tree(cuda(x), leaf_size=leaf)
+    G = dfgt.gauss_sum(t, t, hs, 1e-2).cpu().numpy()
+    rows = synth.subsample(x, 300, 3)
+    for k, h in enumerate(hs):
+        ref = oracle.naive_kde_rows(x, rows, x, h)
+        assert (np.abs(G[k][rows] - ref) / ref).max() <= 1e-2
+
+
+def test_tune_leaf_size_small_and_rejections(dfgt):
+    # fewer points than most candidates: single-leaf trees are timed too
+    x = synth.c1(n=100, seed=62)
+    h = synth.silverman_h(x)
+    note("tune leaf small")
+    leaf, ms = dfgt.tune_leaf_size(cuda(x), [h], 1e-2, reps=1)
+    assert leaf in dfgt.TUNE_LEAVES
+    with pytest.raises(dfgt.DfgtError, match="reps"):
+        dfgt.tune_leaf_size(cuda(x), [h], 1e-2, reps=0)
+    with pytest.raises(dfgt.DfgtError, match="bandwidths"):
+        dfgt.tune_leaf_size(cuda(x), [-h], 1e-2)
