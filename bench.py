@@ -62,7 +62,7 @@ EXP_SLOTS = 4
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB
 # device copy: profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
 # as profiled; None when it has changed since.
-K_ETILE_TRAFFIC_BYTES = 14.09e6 + 3.16e6
+K_ETILE_TRAFFIC_BYTES = {64: 10.50e6 + 2.99e6, 128: 8.74e6 + 2.90e6}  # by leaf size; others: not measured (null)
 
 
 def flops_per_pair(d):
@@ -280,12 +280,17 @@ def main():
     t_step_prof = (time.perf_counter() - t0) / args.steps
     stats = st
 
-    # base-case tiles inside the per-leaf kernel: every leaf pair exhaustive at h*
-    _, st_x = dfgt.gauss_sum(tree_x := dfgt.build_tree(x, leaf_size=leaf), tree_x, [hstar], EPS,
-                             force_method=dfgt.FORCE_EXACT, stats=True, profile=True)
-    _, st_x = dfgt.gauss_sum(tree_x, tree_x, [hstar], EPS, force_method=dfgt.FORCE_EXACT, stats=True, profile=True)
-    base_case = {"pairs": st_x["base_point_pairs"], "k_etile_ms": st_x["kernel_ms"]["etile"]}
-    del tree_x
+    # base-case tiles: one call with every leaf pair exhaustive at h*, at the
+    # tuned leaf size and at leaf 32 (one block per query leaf: 1,563 leaves
+    # give every CU work, where the 391 leaves of leaf 128 leave it partly idle)
+    base_cases = {}
+    for bl in sorted({leaf, 32}):
+        tree_x = dfgt.build_tree(x, leaf_size=bl)
+        for _ in range(2):
+            _, st_x = dfgt.gauss_sum(tree_x, tree_x, [hstar], EPS, force_method=dfgt.FORCE_EXACT, stats=True,
+                                     profile=True)
+        base_cases[bl] = {"pairs": st_x["base_point_pairs"], "k_etile_ms": st_x["kernel_ms"]["etile"]}
+        del tree_x
 
     # per-bandwidth comparison (the layout of the paper's Table 1 on the
     # synthetic stand-in): DFGT, the DFD ablation (centroid finite-difference
@@ -329,7 +334,7 @@ def main():
         "peak": peak * fpp / 1e12,
         "unit": "TFLOP/s",
         "frac": pair_rate / peak,
-        "traffic": K_ETILE_TRAFFIC_BYTES,
+        "traffic": K_ETILE_TRAFFIC_BYTES.get(leaf),
         "traffic_unit": "HBM bytes per launch (read + written)",
         "flops_per_pair": fpp,
         "pairs_per_s": pair_rate,
@@ -372,11 +377,14 @@ def main():
                       "us_per_level": agg_ms.get("traverse", 0.0) / args.steps / max(stats["levels"], 1) * 1e3},
         "roofline": roofline,
         "base_case_tiles": {
-            "what": "one call with every leaf pair exhaustive (forced), bandwidth h*: the exhaustive-tile kernel",
-            "pairs": base_case["pairs"], "k_etile_ms": base_case["k_etile_ms"],
-            "pairs_per_s": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3),
-            "tflops": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) * fpp / 1e12,
-            "frac_of_alu_peak": base_case["pairs"] / (base_case["k_etile_ms"] * 1e-3) / base_peak_pairs(d),
+            "what": "one call with every leaf pair exhaustive (forced), bandwidth h*: the exhaustive-tile kernel "
+                    "(one block per query leaf), at the tuned leaf size and at leaf 32",
+            **{f"leaf_{bl}": {
+                "pairs": bc["pairs"], "k_etile_ms": bc["k_etile_ms"],
+                "pairs_per_s": bc["pairs"] / (bc["k_etile_ms"] * 1e-3),
+                "tflops": bc["pairs"] / (bc["k_etile_ms"] * 1e-3) * fpp / 1e12,
+                "frac_of_alu_peak": bc["pairs"] / (bc["k_etile_ms"] * 1e-3) / base_peak_pairs(d),
+            } for bl, bc in base_cases.items()},
         },
         "per_bandwidth": per_h,
         "grad_ms": None,
