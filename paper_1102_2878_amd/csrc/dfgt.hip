@@ -1239,8 +1239,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const unsigned char *__restrict__ lflag, int precision, int acc_in_lds,
                                               int leaf_local, const int *__restrict__ overflow,
                                               const double *__restrict__ part, double *__restrict__ gscratch,
-                                              const double *__restrict__ extE, const double *__restrict__ extX,
-                                              const double *__restrict__ extY, const double *__restrict__ cval,
+                                              double *__restrict__ stG, double *__restrict__ stX,
+                                              double *__restrict__ stQ, const double *__restrict__ cval,
                                               const int *__restrict__ jlstart, int njobs, int unl,
                                               const unsigned long long *__restrict__ gdg,
                                               const unsigned short *__restrict__ gmt) {
@@ -1634,22 +1634,55 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                     }
                 }
             }
-            const int dst = Q.perm[qpos];
+            // everything but the exhaustive sums; k_leaf_finish adds those once
+            // the tiles' stream has joined, and writes the caller's outputs
             const size_t ei = (size_t)jb.qoff + qpos;
-            if (extE) gsum += extE[ei];
-            const double ws = jb.wscale;
-            jb.out[dst] = ((gl + csum) + gsum) * ws;
+            stG[ei] = (gl + csum) + gsum;
             if (GR) {
-                if (extE) {
-                    xsum += extX[ei];
-                    for (int c = 0; c < d; ++c) gq[c] += extY[ei * d + c];
-                }
-                if (jb.outH) jb.outH[dst] = -(xl + xsum) / jb.h * ws;
-                if (jb.outQ)
-                    for (int c = 0; c < d; ++c) jb.outQ[(size_t)dst * d + c] = s * gq[c] * ws;
+                stX[ei] = xl + xsum;
+                for (int c = 0; c < d; ++c) stQ[ei * d + c] = gq[c];
             }
         }
         __syncthreads();
+    }
+}
+
+// The outputs of every (job, query): k_leaf's partial sums plus the
+// exhaustive leaf-leaf sums (G, and in gradient mode the dG/dh and dG/dq
+// parts), scaled back by the job's weight scale, in the caller's order.
+// k_leaf runs on the main stream beside the exhaustive tiles on the side
+// stream (when the tiles take longer than the local moments, k_leaf fills the
+// idle compute units); this pass waits for both.  One thread per query slot;
+// its job is found by bisection on the slot offsets.
+template <bool GR>
+__global__ __launch_bounds__(256) void k_leaf_finish(const DevTree *__restrict__ trees,
+                                                     const Job *__restrict__ jobs, int njobs, long long nqa,
+                                                     const int *__restrict__ overflow,
+                                                     const double *__restrict__ stG, const double *__restrict__ stX,
+                                                     const double *__restrict__ stQ, const double *__restrict__ extE,
+                                                     const double *__restrict__ extX,
+                                                     const double *__restrict__ extY) {
+    if (*overflow) return;
+    const long long ei = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ei >= nqa) return;
+    int lo = 0, hi = njobs;  // jobs[lo].qoff <= ei < jobs[hi].qoff
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].qoff <= ei) lo = mid;
+        else hi = mid;
+    }
+    const Job &jb = jobs[lo];
+    const DevTree &Q = trees[jb.qt];
+    const int qpos = (int)(ei - jb.qoff);
+    const int dst = Q.perm[qpos];
+    const double ws = jb.wscale;
+    jb.out[dst] = (stG[ei] + extE[ei]) * ws;
+    if (GR) {
+        const int d = Q.d;
+        if (jb.outH) jb.outH[dst] = -(stX[ei] + extX[ei]) / jb.h * ws;
+        if (jb.outQ)
+            for (int c = 0; c < d; ++c)
+                jb.outQ[(size_t)dst * d + c] = jb.s * (stQ[ei * d + c] + extY[ei * d + c]) * ws;
     }
 }
 
@@ -2332,7 +2365,7 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
-        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, cval, gdg, gmt, eord;
+        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, stG, stX, stQ, cval, gdg, gmt, eord;
     // overflow flag, counters and per-level counts in one allocation: one fill,
     // one copy back
     DevBuf ctl;
@@ -2633,10 +2666,13 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
     // exhaustive sums per query (k_emfma or k_etile), added by k_leaf
     DFGT_TRY(grow<double>(w.extE, pl.nqa));
+    DFGT_TRY(grow<double>(w.stG, pl.nqa));
     DFGT_TRY(grow<int>(w.eord, 3 * (size_t)pl.items));  // dispatch order of the exhaustive tiles
     if (pl.gr) {
         DFGT_TRY(grow<double>(w.extX, pl.nqa));
         DFGT_TRY(grow<double>(w.extY, pl.nqa * pl.d));
+        DFGT_TRY(grow<double>(w.stX, pl.nqa));
+        DFGT_TRY(grow<double>(w.stQ, pl.nqa * pl.d));
     }
     DFGT_TRY(grow<Seg>(w.segA, cap.seg));
     DFGT_TRY(grow<Seg>(w.segB, cap.seg));
@@ -2763,7 +2799,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
         if (prof) prof->stop(K_TRAV, ev, st);
     }
     // exhaustive leaf-leaf sums (DFGTBase) on the side stream, concurrent with
-    // the local-moment ops below (they share no buffers); joined before k_leaf
+    // the local-moment ops and k_leaf below (they share no buffers); joined
+    // before k_leaf_finish
     (void)hipEventRecord(w.fork, st);
     (void)hipStreamWaitEvent(w.side, w.fork, 0);
     {
@@ -2816,8 +2853,7 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
         }
         if (prof) prof->stop(K_LOCAL, ev, st);
     }
-    // everything per (job, query leaf)
-    (void)hipStreamWaitEvent(st, w.join, 0);
+    // everything per (job, query leaf) but the exhaustive sums, beside the tiles
     {
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
         auto kl = pl.gr ? k_leaf<true> : k_leaf<false>;
@@ -2826,11 +2862,22 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                            w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),
                            pl.precision, pl.acc_lds ? 1 : 0, pl.leaf_local ? 1 : 0, w.flag.as<int>(),
                            pl.leaf_local ? w.part.as<double>() : (const double *)nullptr, w.pscr.as<double>(),
-                           w.extE.as<double>(), pl.gr ? w.extX.as<double>() : (const double *)nullptr,
-                           pl.gr ? w.extY.as<double>() : (const double *)nullptr, w.cval.as<double>(), jls, njobs,
+                           w.stG.as<double>(), pl.gr ? w.stX.as<double>() : nullptr,
+                           pl.gr ? w.stQ.as<double>() : nullptr, w.cval.as<double>(), jls, njobs,
                            pl.unl, pl.dig_lds ? nullptr : w.gdg.as<unsigned long long>(),
                            pl.dig_lds ? nullptr : w.gmt.as<unsigned short>());
         if (prof) prof->stop(K_LEAF, ev, st);
+    }
+    // the outputs, once the tiles' stream has joined
+    (void)hipStreamWaitEvent(st, w.join, 0);
+    {
+        auto kf = pl.gr ? k_leaf_finish<true> : k_leaf_finish<false>;
+        hipLaunchKernelGGL(kf, dim3((unsigned)((pl.nqa + 255) / 256)), dim3(256), 0, st, td, jd, njobs,
+                           (long long)pl.nqa, w.flag.as<int>(), w.stG.as<double>(),
+                           pl.gr ? w.stX.as<double>() : (const double *)nullptr,
+                           pl.gr ? w.stQ.as<double>() : (const double *)nullptr, w.extE.as<double>(),
+                           pl.gr ? w.extX.as<double>() : (const double *)nullptr,
+                           pl.gr ? w.extY.as<double>() : (const double *)nullptr);
     }
 }
 
