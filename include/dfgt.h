@@ -359,8 +359,9 @@ dfgt_status dfgt_gauss_sum_batched(const dfgt_problem *probs, int32_t n_probs, d
  * bandwidths.  For each candidate in DFGT_TUNE_LEAVES the call times, with HIP
  * events on the stream, `reps` repetitions of a tree build on pts_dev (n x d,
  * float64, device) plus the monochromatic sums dfgt_gauss_sum(T, T, h_host,
- * n_h, eps) (after one untimed repetition), and returns the candidate with the
- * smallest median time in *leaf_out.  ms_out (may be NULL) receives the
+ * n_h, eps) (after one untimed repetition), and returns in *leaf_out the
+ * smallest candidate whose median time is within 2% of the fastest one (so
+ * near-ties resolve the same way from call to call).  ms_out (may be NULL) receives the
  * DFGT_N_TUNE_LEAVES medians in milliseconds, in the order of the list.  opt
  * supplies the other build and sum options (its leaf_size is ignored).  The
  * sums of every candidate satisfy the same error bound; the choice only

@@ -551,8 +551,8 @@ dfgt_status dfgt_tune_leaf_size(const double *pts_dev, int64_t n, int32_t d, con
     dfgt_options o{};
     if (opt) o = *opt;
     const int leaves[DFGT_N_TUNE_LEAVES] = DFGT_TUNE_LEAVES;
-    double best = 0.0;
-    int best_leaf = 0;
+    constexpr double kTuneTie = 0.02;
+    double med[DFGT_N_TUNE_LEAVES], best = 0.0;
     for (int c = 0; c < DFGT_N_TUNE_LEAVES; ++c) {
         o.leaf_size = leaves[c];
         std::vector<float> t;
@@ -573,14 +573,17 @@ dfgt_status dfgt_tune_leaf_size(const double *pts_dev, int64_t n, int32_t d, con
             if (r > 0) t.push_back(ms);  // the first repetition sizes the workspaces
         }
         std::sort(t.begin(), t.end());
-        const double med = t.size() % 2 ? t[t.size() / 2] : 0.5 * ((double)t[t.size() / 2 - 1] + t[t.size() / 2]);
-        if (ms_out) ms_out[c] = med;
-        if (best_leaf == 0 || med < best) {
-            best = med;
-            best_leaf = leaves[c];
-        }
+        med[c] = t.size() % 2 ? t[t.size() / 2] : 0.5 * ((double)t[t.size() / 2 - 1] + t[t.size() / 2]);
+        if (ms_out) ms_out[c] = med[c];
+        best = c == 0 ? med[c] : std::min(best, med[c]);
     }
-    *leaf_out = best_leaf;
+    // the smallest leaf size within kTuneTie of the fastest: near-ties (timing
+    // noise) resolve the same way from call to call
+    for (int c = 0; c < DFGT_N_TUNE_LEAVES; ++c)
+        if (med[c] <= best * (1.0 + kTuneTie)) {
+            *leaf_out = leaves[c];
+            break;
+        }
     return DFGT_OK;
     DFGT_GUARD_END
 }

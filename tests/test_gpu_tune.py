@@ -1,5 +1,5 @@
-"""GPU tests of dfgt_tune_leaf_size: it returns one of its candidates (the one
-with the smallest reported time), every candidate's sums run, and the sums of
+"""GPU tests of dfgt_tune_leaf_size: it returns one of its candidates (the
+smallest within 2% of the fastest reported time), every candidate's sums run, and the sums of
 a tree built with the returned leaf size hold the error bound against the
 oracle."""
 import numpy as np
@@ -27,7 +27,9 @@ def test_tune_leaf_size(dfgt, maker, n):
     assert leaf in dfgt.TUNE_LEAVES
     assert set(ms) == set(dfgt.TUNE_LEAVES)
     assert all(np.isfinite(v) and v > 0 for v in ms.values())
-    assert ms[leaf] == min(ms.values())
+    # the smallest candidate within 2% of the fastest
+    best = min(ms.values())
+    assert leaf == min(k for k, v in ms.items() if v <= best * 1.02)
     t = dfgt.build_tree(cuda(x), leaf_size=leaf)
     G = dfgt.gauss_sum(t, t, hs, 1e-2).cpu().numpy()
     rows = synth.subsample(x, 300, 3)
