@@ -2565,7 +2565,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.nR = q.R->wsum / q.R->wscale;
             j.cntR = (double)q.R->n;
             j.wscale = q.R->wscale;
-            j.prior = 0.0;
+            j.prior = q.Q == q.R && !q.R->weighted ? 1.0 : 0.0;  // the self term: G(q) >= 1
             j.qt = qt;
             j.rt = rt;
             j.qoff = nqa;
