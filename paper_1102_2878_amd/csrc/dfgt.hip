@@ -1760,10 +1760,10 @@ __device__ __forceinline__ int etile_item(int b, const int *__restrict__ cnt, co
 // and writes G_E (precision FP64) or adds to it (it runs after the mixed pass
 // on the same stream).  Splitting them keeps FP64 exponentials out of the
 // mixed kernel's registers.
-// One block of 4 waves per (job, query leaf): the leaf's E chain is flattened
-// 256 ops at a time (reference range and point count, block-wide scan) into
-// one list of reference points, which the waves take in rounds of RPW points,
-// wave w rounds w, w + 4, ...; each wave stages its own round in LDS (scaled
+// One block of kEWaves waves per (job, query leaf): the leaf's E chain is
+// flattened 64 kEWaves ops at a time (reference range and point count,
+// block-wide scan) into one list of reference points, which the waves take in
+// rounds of RPW points, wave w rounds w, w + kEWaves, ...; each wave stages its own round in LDS (scaled
 // by sig), so rounds need no block barrier.  Lanes of a wave: NG groups of
 // `need` lanes; a lane holds QPT queries (ql + need a) and group g takes the
 // staged points g, g + NG, ... (groups read neighbouring points: no LDS bank
@@ -1774,11 +1774,16 @@ __device__ __forceinline__ int etile_item(int b, const int *__restrict__ cnt, co
 // FP32 partial sums over <= 64 terms, FP64 beyond.  The partials of the waves
 // and groups are added in a fixed order.  G_E (and with GR X_E, Y_E) are per
 // query in tree order; k_leaf adds them to the rest.
-constexpr int kEWaveStage = 768;  // doubles of staged reference coordinates per wave
+constexpr int kEWaveStage = 512;  // doubles of staged reference coordinates per wave
 constexpr int kEPpl = 4;          // points staged per lane and round (at most)
 constexpr int kEMaxGroups = 16;   // point groups per wave (the padding is < 4 of them per group)
 constexpr int kEPadPts = 4 * kEMaxGroups;
 constexpr int kEUnroll = 4;
+// Waves per block.  A query leaf's rounds are dealt to the block's waves, so
+// a leaf with hundreds of reference leaves, which sets the end of the launch,
+// finishes sooner with more waves; 8 waves with 512-double stages keep a
+// block under 64 KB of LDS (two blocks per CU).
+constexpr int kEWaves = 8;
 
 template <int DT, bool F64>
 struct ETileShape {
@@ -1902,7 +1907,7 @@ __device__ __forceinline__ void etile_strided(const double *__restrict__ st, con
 }
 
 template <int DT, bool GR, bool F64>
-__global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+__global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
                                                const int *__restrict__ headE, const int *__restrict__ cnt_dev,
                                                const int *__restrict__ overflow, const int *__restrict__ jlstart,
@@ -1914,12 +1919,13 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
     constexpr bool PAD = Sh::PAD;
     constexpr int kSP = PAD ? etile_rpw<DT, F64>(DT > 0 ? DT : 1) + kEPadPts : 1;  // padded entries per wave
     __shared__ int gS[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
-    __shared__ int oB[kEChunk], oCum[kEChunk];
-    __shared__ int wsum[4], nops_s, take_s;
-    __shared__ double stage[4][kEWaveStage];
-    __shared__ float pwt[4][kSP];
-    __shared__ double swt[4][PAD ? 1 : 256];  // point weights of the strided form
-    __shared__ double red[4][64 * QPT];
+    constexpr int NW = kEWaves, kCh = 64 * kEWaves;  // E ops flattened per chunk: one per thread
+    __shared__ int oB[kCh], oCum[kCh];
+    __shared__ int wsum[NW], nops_s, take_s;
+    __shared__ double stage[NW][kEWaveStage];
+    __shared__ float pwt[NW][kSP];
+    __shared__ double swt[NW][PAD ? 1 : 256];  // point weights of the strided form
+    __shared__ double red[NW][64 * QPT];
     if (*overflow) return;
     const bool all64 = precision == DFGT_PREC_FP64;
     // the FP64 pass of a mixed-precision call has work only if the guard flagged a group
@@ -1988,7 +1994,7 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
             if (GR)
                 for (int c = 0; c < d; ++c) yacc[a][c] = 0.0;
         }
-        for (int o0 = 0; o0 < nops; o0 += kEChunk) {
+        for (int o0 = 0; o0 < nops; o0 += kCh) {
             __syncthreads();  // the previous chunk's tables are no longer read
             const int o = o0 + tid;
             int np = 0;
@@ -2008,9 +2014,9 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
             for (int w = 0; w < wv; ++w) pre += wsum[w];
             oCum[tid] = pre + inc;
             __syncthreads();
-            const int nopc = min(kEChunk, nops - o0);
+            const int nopc = min(kCh, nops - o0);
             const int tot = oCum[nopc - 1];
-            for (int p0 = wv * RPW; p0 < tot; p0 += 4 * RPW) {
+            for (int p0 = wv * RPW; p0 < tot; p0 += NW * RPW) {
                 // stage the round: lane l takes points l PPL + k, k < PPL
                 const int cnt = min(RPW, tot - p0);
                 int i = lane * PPL;
@@ -2057,7 +2063,7 @@ __global__ __launch_bounds__(256) void k_etile(const DevTree *__restrict__ trees
             if (tid < nqg) {
                 const int a = tid / need, qi = tid % need;
                 double sum = 0.0;
-                for (int w = 0; w < 4; ++w)
+                for (int w = 0; w < NW; ++w)
                     for (int k = 0; k < NG; ++k) sum += red[w][(k * need + qi) * QPT + a];
                 const size_t ei = (size_t)jb.qoff + qb0 + qg + tid;
                 double *dst = v == 0 ? &GE[ei] : (v == 1 ? &GX[ei] : &GY[ei * d + (v - 2)]);
@@ -2431,10 +2437,10 @@ void launch_etile(bool f64pass, int d, int nitems, hipStream_t st, const DevTree
     const dim3 grid((unsigned)nitems);
 #define DFGT_ETILE(DV)                                                                                            \
     if (f64pass)                                                                                                  \
-        hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
+        hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
                            jls, njobs, unl, precision, (const int *)nullptr, nitems, GE, GX, GY);                 \
     else                                                                                                          \
-        hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, cnt,      \
+        hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,      \
                            flag, jls, njobs, unl, precision, order, nitems, GE, GX, GY);                          \
     break;
     switch (d) {
