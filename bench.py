@@ -62,7 +62,7 @@ EXP_SLOTS = 4
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB
 # device copy: profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
 # as profiled; None when it has changed since.
-K_ETILE_TRAFFIC_BYTES = {64: 9.86e6 + 2.99e6, 128: 8.37e6 + 2.90e6}  # by leaf size; others: not measured (null)
+K_ETILE_TRAFFIC_BYTES = {64: 9.90e6 + 2.99e6, 128: 8.41e6 + 2.90e6}  # by leaf size; others: not measured (null)
 
 
 def flops_per_pair(d):
