@@ -398,10 +398,14 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        rng_rows = synth.subsample(x_host, 64, 99)
+        # rate estimate: one untimed call starts the oracle's threads, then a small sample over
+        # every bandwidth (the cost per pair depends on h)
+        oracle.naive_kde_rows(x_host, synth.subsample(x_host, 64, 98), x_host, hs[3])
+        rng_rows = synth.subsample(x_host, 256, 99)
         t0 = time.perf_counter()
-        oracle.naive_kde_rows(x_host, rng_rows, x_host, hs[3])
-        rate = len(rng_rows) * n / max(time.perf_counter() - t0, 1e-6)
+        for h in hs:
+            oracle.naive_kde_rows(x_host, rng_rows, x_host, h)
+        rate = len(rng_rows) * n * len(hs) / max(time.perf_counter() - t0, 1e-6)
         m = int(min(n, max(64, args.cpu_seconds * rate / (n * len(hs)))))
         rows = synth.subsample(x_host, m, 100)
         t0 = time.perf_counter()
