@@ -96,7 +96,9 @@ typedef struct dfgt_stats {
     int64_t max_local_ops;  /* most local-moment ops of one (node, bandwidth) */
     int64_t mfma_tiles;     /* parts of the call whose exhaustive sums ran on the
                                matrix cores (D >= 8, mixed precision), else 0 */
-    int64_t reserved[1];
+    int64_t parts;          /* job parts the call ran in turn (the jobs of a call
+                               whose traversal buffers would exceed the memory
+                               budget are split; 1 = not split) */
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,
@@ -348,6 +350,12 @@ typedef struct dfgt_problem {
  * query of every problem and bandwidth; results do not depend on the other
  * jobs of the batch (bitwise).  Options and errors as dfgt_gauss_sum; at most
  * 2^20 (problem, bandwidth) jobs.
+ * Memory: when the traversal buffers of all jobs would exceed a budget of
+ * min(device memory / 8, free memory / 2), at least 1 GiB, the jobs are split
+ * into parts that run in turn on the same buffers (stats->parts).  The
+ * environment variable DFGT_MEMORY_BUDGET_MB, when set to a positive number of
+ * MiB, replaces that budget (a test knob that forces the split; results are
+ * bitwise the same however the jobs are split).
  */
 dfgt_status dfgt_gauss_sum_batched(const dfgt_problem *probs, int32_t n_probs, double eps,
                                    const dfgt_options *opt, dfgt_stats *stats, void *stream);

@@ -41,6 +41,7 @@ def lib():
         L.oracle_naive_kde_rows.argtypes = [_DP, _I64P, i64, _DP, i64, i32, dbl, _DP]
         L.oracle_naive_kde_grad.argtypes = [_DP, i64, _DP, i64, i32, dbl, C.c_void_p, C.c_void_p,
                                             C.c_void_p]
+        L.oracle_naive_kde_qscale.argtypes = [_DP, i64, _DP, i64, i32, dbl, _DP]
         L.oracle_naive_kde_weighted.argtypes = [_DP, i64, _DP, _DP, i64, i32, dbl, C.c_void_p, C.c_void_p,
                                                 C.c_void_p]
         L.oracle_build_kdtree.argtypes = [_DP, i64, i32, i32, i64, _I32P, _DP, _DP, _I64P, _I64P,
@@ -127,6 +128,16 @@ def naive_kde_grad(q, r, h):
     _check(lib().oracle_naive_kde_grad(q, n, r, r.shape[0], d, float(h), _ptr(G), _ptr(gh), _ptr(gq)),
            "naive_kde_grad")
     return G, gh, gq
+
+
+def naive_kde_qscale(q, r, h):
+    """h^-2 sum_j K_j |q_i - r_j|: the sum of the norms of the terms of dG/dq
+    (an upper bound on |dG/dq|, the unit of its relative error)."""
+    q, r = _pts(q), _pts(r)
+    out = np.empty(q.shape[0])
+    _check(lib().oracle_naive_kde_qscale(q, q.shape[0], r, r.shape[0], q.shape[1], float(h), out),
+           "naive_kde_qscale")
+    return out
 
 
 def naive_kde_weighted(q, r, w, h):

@@ -124,6 +124,36 @@ int oracle_naive_kde_grad(const double *q, int64_t nq, const double *r, int64_t 
 }
 
 /*
+ * Scale of the query gradient (not in the paper; the differentiation form of
+ * the method): the sum of the norms of the terms of dG/dq,
+ *   out(q) = h^-2 sum_j K_j ||q - r_j||,
+ * which bounds ||dG/dq|| from above (triangle inequality) and is the unit in
+ * which the relative error of a computed dG/dq is measured.
+ */
+int oracle_naive_kde_qscale(const double *q, int64_t nq, const double *r, int64_t nr, int d, double h,
+                            double *out)
+{
+    if (nq < 0 || nr < 0 || d < 1 || d > OR_MAXD || !(h > 0.0)) return 1;
+    const double inv2h2 = 1.0 / (2.0 * h * h);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nq; ++i) {
+        const double *qi = q + i * d;
+        double acc = 0.0;
+        for (int64_t j = 0; j < nr; ++j) {
+            const double *rj = r + j * d;
+            double d2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                double t = qi[k] - rj[k];
+                d2 += t * t;
+            }
+            acc += exp(-d2 * inv2h2) * sqrt(d2);
+        }
+        out[i] = acc / (h * h);
+    }
+    return 0;
+}
+
+/*
  * Weighted kernel sums (the sums of Section 1 with a weight per reference
  * point, as a weighted density estimate takes them), computed exactly:
  *   G_w(q)    = sum_j w_j K_j,  K_j = exp(-||q - r_j||^2 / (2 h^2))

@@ -34,6 +34,7 @@
 // bitwise reproducible and independent of the other jobs in the batch.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "etile.h"
@@ -1661,8 +1662,13 @@ __global__ __launch_bounds__(256) void k_leaf_finish(const DevTree *__restrict__
                                                      const double *__restrict__ stG, const double *__restrict__ stX,
                                                      const double *__restrict__ stQ, const double *__restrict__ extE,
                                                      const double *__restrict__ extX,
-                                                     const double *__restrict__ extY) {
-    if (*overflow) return;
+                                                     const double *__restrict__ extY, int *__restrict__ sticky) {
+    if (*overflow) {
+        // a batch of several parts clears the flag per part: the sticky word
+        // keeps whether any part overflowed
+        if (blockIdx.x == 0 && threadIdx.x == 0) *sticky = 1;
+        return;
+    }
     const long long ei = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (ei >= nqa) return;
     int lo = 0, hi = njobs;  // jobs[lo].qoff <= ei < jobs[hi].qoff
@@ -2375,6 +2381,8 @@ struct Workspace {
     // overflow flag, counters and per-level counts in one allocation: one fill,
     // one copy back
     DevBuf ctl;
+    // set when any part of the call overflowed (cleared by the first part only)
+    DevBuf sticky;
     DevSpan flag, cnt, lvl;
     // pinned staging of the plan upload and the read back; the upload's
     // copies are complete once `upev` has been reached
@@ -2382,6 +2390,7 @@ struct Workspace {
     hipEvent_t upev = nullptr;
     Caps cap{0, 0, 0, 0, 0, 0, 0};
     int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
+    size_t part_budget = 0;  // the memory budget part_jobs was learned under
     // the exhaustive tiles run on a side stream beside the local-moment ops
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -2515,8 +2524,15 @@ size_t plan_bytes(const Plan &pl, const Caps &c) {
     return b;
 }
 
-// Memory one call may size its traversal buffers to before it splits its jobs.
+// Memory one call may size its traversal buffers to before it splits its jobs:
+// min(total / 8, free / 2), at least 1 GiB.  DFGT_MEMORY_BUDGET_MB, when set to
+// a positive number, replaces it (no floor): a test knob that forces the
+// split into parts on small inputs.
 size_t memory_budget() {
+    if (const char *ev = std::getenv("DFGT_MEMORY_BUDGET_MB")) {
+        const long long mb = std::atoll(ev);
+        if (mb > 0) return (size_t)mb << 20;
+    }
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return (size_t)16 << 30;
     return std::max<size_t>((size_t)1 << 30, std::min(tot / 8, fr / 2));
@@ -2670,6 +2686,7 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
                                  {&w.cnt, sizeof(int) * C_N * CP},
                                  {&w.lvl, sizeof(int) * (size_t)(pl.nlev + 1) * 2 * CP}}));
     DFGT_TRY(grow<unsigned long long>(w.stats, S_N * SP));
+    DFGT_TRY(grow<int>(w.sticky, 64));
     // exhaustive sums per query (k_emfma or k_etile), added by k_leaf
     DFGT_TRY(grow<double>(w.extE, pl.nqa));
     DFGT_TRY(grow<double>(w.stG, pl.nqa));
@@ -2761,7 +2778,7 @@ void fill_u32(void *p, size_t words, unsigned v, hipStream_t st) {
 
 // The whole launch sequence of one call: no host synchronisation, no
 // allocation, no memset or host copy, so it can be captured in a graph.
-void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
+void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool first_part) {
     const size_t nna = pl.nna;
     const int nlev = pl.nlev, njobs = pl.njobs, d = pl.d, pmax = pl.pmax, P = pl.P, PW = pl.PW;
     int *headE = w.heads.as<int>(), *headF = headE + nna, *headL = headF + nna;
@@ -2783,6 +2800,11 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
         fs.words[3] = ((char *)w.lvl.p - (char *)w.ctl.p) / 4 + (size_t)(nlev + 1) * 2 * CP;
         fs.p[4] = (unsigned *)w.stats.p;
         fs.words[4] = 2 * S_N * SP;
+        if (first_part) {
+            fs.p[5] = (unsigned *)w.sticky.p;
+            fs.words[5] = 1;
+            fs.n = 6;
+        }
         fill_many(fs, st);
     }
     hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
@@ -2883,7 +2905,7 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof) {
                            pl.gr ? w.stX.as<double>() : (const double *)nullptr,
                            pl.gr ? w.stQ.as<double>() : (const double *)nullptr, w.extE.as<double>(),
                            pl.gr ? w.extX.as<double>() : (const double *)nullptr,
-                           pl.gr ? w.extY.as<double>() : (const double *)nullptr);
+                           pl.gr ? w.extY.as<double>() : (const double *)nullptr, w.sticky.as<int>());
     }
 }
 
@@ -2959,14 +2981,23 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
 // When the capacities a rerun would need exceed the memory budget and the
 // plan has more than one job, *too_big is set instead (capacities unchanged).
 dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stats_out, hipStream_t st,
-                     bool *too_big) {
+                     size_t budget, bool *too_big) {
     Profiler &prof = g_prof;
     *too_big = false;
     Caps &cap = w.cap;
-    if (cap.pair == 0) cap = Caps{1 << 19, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 18, 1 << 18};
-    cap.pair = std::max(cap.pair, 4 * pl.njobs);
-    cap.seg = std::max(cap.seg, 4 * pl.njobs);
-    const size_t budget = memory_budget();
+    Caps least{1 << 19, 1 << 20, 1 << 20, 1 << 20, 1 << 20, 1 << 18, 1 << 18};  // the starting capacities
+    least.pair = std::max(least.pair, 4 * pl.njobs);
+    least.seg = std::max(least.seg, 4 * pl.njobs);
+    if (cap.pair == 0) cap = least;
+    cap.pair = std::max(cap.pair, least.pair);
+    cap.seg = std::max(cap.seg, least.seg);
+    // split before running when the plan exceeds the budget even at the
+    // starting capacities (capacities grown by earlier calls do not count:
+    // they are what other plans needed)
+    if (pl.njobs > 1 && plan_bytes(pl, least) > budget) {
+        *too_big = true;
+        return DFGT_OK;
+    }
     int c[C_N] = {0};
     int overflow = 1;
     for (int attempt = 0; attempt < 12 && overflow; ++attempt) {
@@ -2974,7 +3005,7 @@ dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stat
         DFGT_TRY(upload_plan(pl, w, st));
         prof.begin_call(profile != 0);
         // stats are gathered whenever a caller asks for them
-        enqueue(pl, w, st, (profile || stats_out) ? &prof : nullptr);
+        enqueue(pl, w, st, (profile || stats_out) ? &prof : nullptr, true);
         DFGT_HIP(hipGetLastError());
         const Caps before = cap;
         DFGT_TRY(read_back(pl, w, st, &overflow, c));
@@ -3019,6 +3050,11 @@ void add_stats(dfgt_stats *a, const dfgt_stats &b) {
 dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *stats_out, hipStream_t st,
                        std::vector<Plan> *parts) {
     std::vector<Plan> todo;
+    const size_t budget = memory_budget();
+    if (budget != w.part_budget) {  // a part size learned under another budget does not apply
+        w.part_jobs = 0;
+        w.part_budget = budget;
+    }
     // start from the part size a previous call had to split to (a guess that
     // is only ever refined: parts that still do not fit are halved again)
     const int pj = w.part_jobs > 0 ? w.part_jobs : full.njobs;
@@ -3030,7 +3066,7 @@ dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *
         todo.erase(todo.begin());
         bool too_big = false;
         dfgt_stats one{};
-        DFGT_TRY(run_plan(pl, w, profile, stats_out ? &one : nullptr, st, &too_big));
+        DFGT_TRY(run_plan(pl, w, profile, stats_out ? &one : nullptr, st, budget, &too_big));
         if (too_big) {
             const int mid = pl.njobs / 2;
             w.part_jobs = w.part_jobs > 0 ? std::min(w.part_jobs, pl.njobs - mid) : pl.njobs - mid;
@@ -3041,6 +3077,7 @@ dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *
         if (stats_out) add_stats(stats_out, one);
         parts->push_back(std::move(pl));
     }
+    if (stats_out) stats_out->parts = (int64_t)parts->size();
     return DFGT_OK;
 }
 
@@ -3110,7 +3147,7 @@ dfgt_status batch_create(const Problem *pr, int np, double eps, int precision, i
     if (s == DFGT_OK && hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) s = DFGT_EHIP;
     if (s == DFGT_OK && hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) s = DFGT_EHIP;
     if (s == DFGT_OK) {
-        for (const Plan &p : b->parts) enqueue(p, b->w, b->cs, nullptr);
+        for (size_t k = 0; k < b->parts.size(); ++k) enqueue(b->parts[k], b->w, b->cs, nullptr, k == 0);
         const hipError_t le = hipGetLastError();
         const hipError_t ce = hipStreamEndCapture(b->cs, &b->graph);
         if (le != hipSuccess || ce != hipSuccess) s = DFGT_EHIP;
@@ -3132,7 +3169,7 @@ dfgt_status batch_run(dfgt_batch_s *b, hipStream_t st) {
 
 dfgt_status batch_check(dfgt_batch_s *b, hipStream_t st) {
     int overflow = 0;
-    DFGT_HIP(hipMemcpyAsync(&overflow, b->w.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFGT_HIP(hipMemcpyAsync(&overflow, b->w.sticky.p, sizeof(int), hipMemcpyDeviceToHost, st));
     DFGT_HIP(hipStreamSynchronize(st));
     if (overflow) {
         set_error("dfgt_batch: the last run overflowed its traversal buffers (were the trees changed?)");

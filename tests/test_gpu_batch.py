@@ -94,6 +94,90 @@ def test_graph_replays_match_eager(dfgt):
         torch.cuda.synchronize()
 
 
+def _problems_3d(dfgt, sizes, nbase, leaf=32):
+    probs, data = [], []
+    for i, n in enumerate(sizes):
+        x = synth.c4_problem(i)
+        if n < x.shape[0]:
+            x = x[synth.subsample(x, n, 70 + i)]
+        t = dfgt.build_tree(cuda(x), leaf_size=leaf)
+        base = synth.silverman_h(x) * np.geomspace(1e-3, 1e3, nbase)
+        probs.append((t, t, np.concatenate([base, np.sqrt(2.0) * base])))
+        data.append(x)
+    return probs, data
+
+
+def test_split_into_parts_matches_unsplit(dfgt, monkeypatch):
+    """A memory budget too small for the whole batch splits its jobs into parts
+    that run in turn on the same buffers (eager) or one after another in the
+    captured graph.  Jobs only read their own lists, so every part layout
+    gives the unsplit result bitwise; it is also within eps of the oracle."""
+    probs, data = _problems_3d(dfgt, (1500, 4000, 9000), 6)
+    note("batch split: unsplit reference")
+    ref, st0 = dfgt.gauss_sum_batched(probs, 1e-2, stats=True)
+    ref = [G.cpu().numpy() for G in ref]
+    assert st0["parts"] == 1
+    monkeypatch.setenv("DFGT_MEMORY_BUDGET_MB", "48")
+    note("batch split: eager, 48 MiB budget")
+    outs, st = dfgt.gauss_sum_batched(probs, 1e-2, stats=True)
+    assert st["parts"] >= 3, st["parts"]
+    for G, R in zip(outs, ref):
+        assert G.cpu().numpy().tobytes() == R.tobytes()
+    note("batch split: graph capture, 48 MiB budget")
+    b = dfgt.Batch(probs, 1e-2, stats=True)
+    assert b.stats["parts"] >= 3, b.stats["parts"]
+    import torch
+    for rep in range(3):
+        note(f"batch split: graph replay {rep}")
+        for G in b.G:
+            G.fill_(-1.0)
+        b.run()
+        b.check()
+        for G, R in zip(b.G, ref):
+            assert G.cpu().numpy().tobytes() == R.tobytes(), rep
+        dfgt.gauss_sum(probs[0][0], probs[0][0], [0.05], 1e-2)
+        torch.cuda.synchronize()
+    monkeypatch.delenv("DFGT_MEMORY_BUDGET_MB")
+    for (t, _, h), G, x in zip(probs, ref, data):
+        rows = synth.subsample(x, 300, 9)
+        for k in range(0, len(h), 3):
+            r = oracle.naive_kde_rows(x, rows, x, h[k])
+            assert np.max(np.abs(G[k][rows] - r) / r) <= 1e-2, (x.shape, h[k])
+
+
+def test_full_size_3d_batch_sampled(dfgt):
+    """The 3-D batch at its full size and in the bench's launch configuration:
+    8 clustered problems of 10k..200k points, 64 log-spaced bandwidths
+    h_S x 10^{-3..3} each at h and sqrt(2) h (1024 sums), leaf size 128, the
+    jobs split into as many parts as the default memory budget needs.  The
+    captured graph's replay equals the eager call bitwise; 200 seeded rows per
+    problem at 16 seeded bandwidths are within eps of the oracle."""
+    import torch
+    probs, data = _problems_3d(dfgt, synth.C4_SIZES, 64, leaf=128)
+    note("batch 3-D full size: eager")
+    eager, st = dfgt.gauss_sum_batched(probs, 1e-2, stats=True)
+    torch.cuda.synchronize()
+    note(f"batch 3-D full size: graph capture ({st['parts']} parts eager)")
+    b = dfgt.Batch(probs, 1e-2)
+    for G in b.G:
+        G.fill_(-1.0)
+    note("batch 3-D full size: graph replay")
+    b.run()
+    b.check()
+    for G, E in zip(b.G, eager):
+        assert torch.equal(G, E)
+    del b
+    rng = np.random.default_rng(404)
+    for k, ((t, _, h), G, x) in enumerate(zip(probs, eager, data)):
+        rows = synth.subsample(x, 200, 80 + k)
+        cols = np.sort(rng.choice(len(h), size=16, replace=False))
+        Gs = G[:, torch.as_tensor(rows, device=G.device)].cpu().numpy()
+        for j in cols:
+            r = oracle.naive_kde_rows(x, rows, x, h[j])
+            rel = np.abs(Gs[j] - r) / r
+            assert rel.max() <= 1e-2, (x.shape, h[j], rel.max())
+
+
 def test_batch_rejects_mixed_dimensions(dfgt):
     t2 = dfgt.build_tree(cuda(synth.c1(n=500, seed=3)))
     t3 = dfgt.build_tree(cuda(synth.c3(n=500, seed=3)[:, :3].copy()))

@@ -226,6 +226,28 @@ def test_five_dimensions_order_six(dfgt, eps):
     assert st["max_order"] >= 2
 
 
+@pytest.mark.parametrize("pmax,eps", [(6, 1e-2), (6, 1e-4), (2, 1e-2), (2, 1e-4)])
+def test_full_size_c3_sampled(dfgt, pmax, eps):
+    """The 5-D workload at full size: 100,000 points, the paper's seven
+    bandwidths h* x 10^{-3..3}, expansion orders up to 6 per dimension (7,776
+    coefficients) and the paper's default 2; 300 seeded query rows against all
+    references, within eps of the oracle."""
+    x = synth.c3()
+    h0 = json.load(open(HSTAR))["c3"]["h_star"]
+    hs = [h0 * s for s in SCALES]
+    rows = synth.subsample(x, 300, 45)
+    note(f"dfgt c3 100k pmax={pmax} eps={eps}")
+    R = dfgt.build_tree(cuda(x), p_max=pmax)
+    G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True)
+    G = G.cpu().numpy()
+    for k, h in enumerate(hs):
+        ref = oracle.naive_kde_rows(x, rows, x, h)
+        rel = _rel_err(G[k][rows], ref)
+        assert rel.max() <= eps, (h, rel.max())
+        assert np.all(np.isfinite(G[k]))
+    assert st["max_order"] >= 2
+
+
 def test_underflow_guard_fp64_groups(dfgt):
     """Sums below the FP32 range: a tight reference cluster and queries on a
     ring at 13.5-14 h (exponents 91-98, each term under 2^-126) plus queries

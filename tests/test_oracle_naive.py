@@ -115,3 +115,45 @@ def test_coincident_points_zero_gradient():
     x = np.tile(np.array([[1.0, 2.0]]), (9, 1))
     _, gh, gq = oracle.naive_kde_grad(x, x, 0.3)
     assert np.all(gh == 0) and np.all(gq == 0)
+
+
+def test_qscale_single_reference_closed_form():
+    """One reference at distance rho: h^-2 e^{-rho^2/2h^2} rho."""
+    q = np.array([[0.1, -0.2, 0.3]])
+    r = np.array([[0.4, 0.2, 0.3]])
+    h = 0.7
+    rho = 0.5
+    np.testing.assert_allclose(oracle.naive_kde_qscale(q, r, h), [np.exp(-rho ** 2 / (2 * h * h)) * rho / h ** 2],
+                               rtol=1e-14)
+
+
+def test_qscale_equals_gradient_norm_on_one_side():
+    """In one dimension with every reference on one side of the query, every
+    term of dG/dq has the same sign, so the sum of their norms is |dG/dq|
+    (the oracle's analytic gradient, pinned by mpmath and differences)."""
+    rng = np.random.default_rng(61)
+    r = rng.uniform(0.0, 1.0, size=(300, 1))
+    q = np.array([[-0.05], [-0.3], [1.2]])
+    for h in (0.05, 0.4, 3.0):
+        _, _, gq = oracle.naive_kde_grad(q, r, h)
+        np.testing.assert_allclose(oracle.naive_kde_qscale(q, r, h), np.abs(gq[:, 0]), rtol=1e-13)
+
+
+def test_qscale_sphere_and_inequalities():
+    """References on a sphere of radius rho around q: N K(rho) rho / h^2
+    exactly.  In general |dG/dq| <= qscale <= sqrt(G h^3 dG/dh) / h^2
+    (triangle and Cauchy-Schwarz inequalities against the pinned gradient)."""
+    rng = np.random.default_rng(62)
+    q = np.array([[0.3, 0.6]])
+    ang = rng.uniform(0.0, 2 * np.pi, 200)
+    rho, h = 0.25, 0.2
+    r = q + rho * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    np.testing.assert_allclose(oracle.naive_kde_qscale(q, r, h), [200 * np.exp(-rho ** 2 / (2 * h * h)) * rho / h ** 2],
+                               rtol=1e-12)
+    x = synth.c1(n=800, seed=63)
+    qs = x[:50]
+    for h in (0.01, 0.1, 1.0):
+        G, gh, gq = oracle.naive_kde_grad(qs, x, h)
+        s = oracle.naive_kde_qscale(qs, x, h)
+        assert np.all(np.linalg.norm(gq, axis=1) <= s * (1 + 1e-12))
+        assert np.all(s <= np.sqrt(G * gh * h ** 3) / h ** 2 * (1 + 1e-12))
