@@ -212,6 +212,27 @@ dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev,
                            double *G_dev, void *stream);
 
 /*
+ * dfgt_naive_sum without any device allocation, for callers that cannot
+ * allocate (code running under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * dfgt_naive_sum; the chunk partials, the bandwidth table and the norm tables
+ * of the matrix-core form live in one fixed 64 MiB device region that the
+ * library holds on every GPU it runs on until the process ends.  Limit:
+ *   n_h * nq + nq + nr + n_h (rounded up to 32 each, + 32) <= 8 * 2^20 doubles,
+ * else DFGT_EINVAL without touching the device.  Below the limit the
+ * reference points are split into as many chunks as fit (as many as
+ * dfgt_naive_sum takes when they fit, and then the result is bitwise the
+ * same).  The region is shared by every call on that GPU and keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Asynchronous on the
+ * stream, except that d >= 8 in mixed precision waits for the stream once
+ * (the norm maxima decide whether the matrix-core form is exact enough).
+ */
+dfgt_status dfgt_naive_sum_noalloc(const double *q_dev, int64_t nq, const double *r_dev, int64_t nr,
+                                   int32_t d, const double *h_host, int32_t n_h, int32_t precision,
+                                   double *G_dev, void *stream);
+
+/*
  * Dual-tree fast Gauss transform, Section 3.9 (DFGTMain):
  *     G_dev[k*NQ + i] ~= sum_j exp(-||q_i - r_j||^2 / (2 h_k^2))
  * for every query i in the caller's order, with |G~ - G| <= eps * G for every

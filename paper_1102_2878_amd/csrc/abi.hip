@@ -370,6 +370,21 @@ dfgt_status dfgt_naive_sum(const double *q_dev, int64_t nq, const double *r_dev,
     DFGT_GUARD_END
 }
 
+dfgt_status dfgt_naive_sum_noalloc(const double *q_dev, int64_t nq, const double *r_dev, int64_t nr, int32_t d,
+                                   const double *h_host, int32_t n_h, int32_t precision, double *G_dev,
+                                   void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(q_dev && r_dev && G_dev, "dfgt_naive_sum_noalloc: NULL device pointer");
+    DFGT_REQUIRE(nq >= 1 && nq < (int64_t(1) << 30) && nr >= 1 && nr < (int64_t(1) << 30),
+                 "dfgt_naive_sum_noalloc: nq and nr must be in [1, 2^30)");
+    DFGT_REQUIRE(d >= 1 && d <= kMaxD, "dfgt_naive_sum_noalloc: d must be in [1, 32]");
+    DFGT_REQUIRE(precision == DFGT_PREC_MIXED || precision == DFGT_PREC_FP64,
+                 "dfgt_naive_sum_noalloc: unknown precision");
+    DFGT_TRY(check_bandwidths(h_host, n_h, "dfgt_naive_sum_noalloc"));
+    return launch_naive_noalloc(q_dev, nq, r_dev, nr, d, h_host, n_h, precision, G_dev, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
 // Options of a summation call: precision and force default to the tree's.
 static dfgt_status call_options(const dfgt_tree_s *R, const dfgt_options *opt, const char *who, int *precision,
                                 int *force, int *profile, double *cost_e) {

@@ -274,6 +274,10 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 // naive.hip
 dfgt_status launch_naive(const double *q, int64_t nq, const double *r, int64_t nr, int d,
                          const double *h, int nh, int precision, double *G, hipStream_t st);
+// The same sums with every buffer carved from a fixed device region (no allocation).
+dfgt_status launch_naive_noalloc(const double *q, int64_t nq, const double *r, int64_t nr, int d,
+                                 const double *h, int nh, int precision, double *G, hipStream_t st);
+size_t naive_noalloc_limit();  // doubles in that region
 // tree.hip
 dfgt_status build_tree_device(dfgt_tree_s *t, const double *pts, const double *w, hipStream_t st);
 // moments.hip

@@ -9,8 +9,12 @@
 // then in FP64.  Partial sums per chunk are reduced in chunk order, so results
 // are bitwise reproducible.
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "etile.h"
 
@@ -270,6 +274,59 @@ __global__ void k_reduce_chunks(const double *__restrict__ part, int nq, int nch
 // called from one host thread at a time).
 thread_local DevBuf g_part, g_h, g_qn, g_rn, g_mx;
 
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+// Device memory of one brute-force call: chunk partials, the bandwidths, the
+// norm tables of the matrix-core form and their maxima.
+struct NaiveBufs {
+    double *part, *h, *qn, *rn;
+    unsigned long long *mx;
+};
+
+// Where a call's buffers come from: the thread's growing workspace (pool =
+// null), or a fixed region of `cap` doubles carved in a fixed layout (no
+// allocation).  part_doubles(n) sizes the partials for n doubles.
+struct NaiveSpace {
+    double *pool = nullptr;
+    size_t cap = 0;
+    // doubles before the partials: bandwidths, norms, maxima (256-byte aligned pieces)
+    static size_t round(size_t n) { return (n + 31) / 32 * 32; }
+    size_t head(int nq, int nr, int nh) const { return round(nh) + round(nq) + round(nr) + 32; }
+    // the most partial doubles this space can give (SIZE_MAX: unbounded)
+    size_t part_max(int nq, int nr, int nh) const {
+        if (!pool) return SIZE_MAX;
+        const size_t h0 = head(nq, nr, nh);
+        return cap > h0 ? cap - h0 : 0;
+    }
+    dfgt_status get(int nq, int nr, int nh, size_t part_doubles, bool norms, NaiveBufs *b) const {
+        if (!pool) {
+            DFGT_TRY(g_h.reserve(sizeof(double) * nh));
+            DFGT_TRY(g_part.reserve(sizeof(double) * part_doubles));
+            if (norms) {
+                DFGT_TRY(g_qn.reserve(sizeof(double) * nq));
+                DFGT_TRY(g_rn.reserve(sizeof(double) * nr));
+                DFGT_TRY(g_mx.reserve(2 * sizeof(unsigned long long)));
+            }
+            *b = NaiveBufs{g_part.as<double>(), g_h.as<double>(), g_qn.as<double>(), g_rn.as<double>(),
+                           g_mx.as<unsigned long long>()};
+            return DFGT_OK;
+        }
+        double *p = pool;
+        b->h = p;
+        p += round(nh);
+        b->qn = p;
+        p += round(nq);
+        b->rn = p;
+        p += round(nr);
+        b->mx = reinterpret_cast<unsigned long long *>(p);
+        p += 32;
+        b->part = p;
+        return DFGT_OK;
+    }
+};
+
 template <int NC>
 void launch_mfma(dim3 grid, hipStream_t st, const double *q, const double *qn, int nq, const double *r,
                  const double *rn, int nr, int d, const double *hd, int fp64, int chunk_len, int nchunks,
@@ -282,17 +339,16 @@ void launch_mfma(dim3 grid, hipStream_t st, const double *q, const double *qn, i
 // the exact-difference VALU kernels); *use is false when s^2 (|q|^2 + |r|^2)
 // could exceed 2^26 for the smallest bandwidth (rounding of the expanded
 // squared distance then above ~1e-7).
+bool mfma_shape(int d, int precision) { return d >= 8 && d <= 32 && precision == DFGT_PREC_MIXED; }
+
 dfgt_status prepare_mfma(const double *q, int nq, const double *r, int nr, int d, const double *h_host, int nh,
-                         int precision, hipStream_t st, bool *use) {
+                         int precision, const NaiveBufs &b, hipStream_t st, bool *use) {
     *use = false;
-    if (d < 8 || d > 32 || precision != DFGT_PREC_MIXED) return DFGT_OK;
-    DFGT_TRY(g_qn.reserve(sizeof(double) * nq));
-    DFGT_TRY(g_rn.reserve(sizeof(double) * nr));
-    DFGT_TRY(g_mx.reserve(2 * sizeof(unsigned long long)));
-    DFGT_HIP(hipMemsetAsync(g_mx.p, 0, 2 * sizeof(unsigned long long), st));
-    unsigned long long *mx = g_mx.as<unsigned long long>();
-    hipLaunchKernelGGL(k_sqnorm, dim3((nq + 255) / 256), dim3(256), 0, st, q, nq, d, g_qn.as<double>(), mx);
-    hipLaunchKernelGGL(k_sqnorm, dim3((nr + 255) / 256), dim3(256), 0, st, r, nr, d, g_rn.as<double>(), mx + 1);
+    if (!mfma_shape(d, precision)) return DFGT_OK;
+    unsigned long long *mx = b.mx;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, mx, 2);
+    hipLaunchKernelGGL(k_sqnorm, dim3((nq + 255) / 256), dim3(256), 0, st, q, nq, d, b.qn, mx);
+    hipLaunchKernelGGL(k_sqnorm, dim3((nr + 255) / 256), dim3(256), 0, st, r, nr, d, b.rn, mx + 1);
     DFGT_HIP(hipGetLastError());
     unsigned long long hm[2];
     DFGT_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, st));
@@ -306,44 +362,54 @@ dfgt_status prepare_mfma(const double *q, int nq, const double *r, int nr, int d
     return DFGT_OK;
 }
 
-}  // namespace
+// Reference chunks of one launch: enough (query tile, chunk, bandwidth) blocks
+// to fill 256 CUs several times over, at most one per `unit` references and at
+// most `most` (the partials' room); chunk lengths are multiples of `unit`.
+// Returns the chunk count and its length in *len.
+int split_chunks(int tiles, int nh, int nr, int unit, long long most, int *len) {
+    int nc = (4096 + tiles * nh - 1) / (tiles * nh);
+    nc = std::min(nc, (nr + unit - 1) / unit);
+    if (most < nc) nc = (int)std::max<long long>(most, 1);
+    nc = std::max(nc, 1);
+    int cl = (nr + nc - 1) / nc;
+    cl = (cl + unit - 1) / unit * unit;
+    *len = cl;
+    return (nr + cl - 1) / cl;
+}
 
-dfgt_status launch_naive(const double *q, int64_t nq64, const double *r, int64_t nr64, int d,
-                         const double *h_host, int nh, int precision, double *G, hipStream_t st) {
+dfgt_status naive_run(const double *q, int64_t nq64, const double *r, int64_t nr64, int d, const double *h_host,
+                      int nh, int precision, double *G, hipStream_t st, const NaiveSpace &sp) {
     const int nq = (int)nq64, nr = (int)nr64;
-    DFGT_TRY(g_h.reserve(sizeof(double) * nh));
-    DFGT_HIP(hipMemcpyAsync(g_h.p, h_host, sizeof(double) * nh, hipMemcpyHostToDevice, st));
+    const size_t pmax = sp.part_max(nq, nr, nh);
+    const long long most = pmax == SIZE_MAX ? (1LL << 40) : (long long)(pmax / ((size_t)nq * nh));
+    if (most < 1) {
+        set_error("dfgt_naive_sum_noalloc: n_h x nq + nq + nr exceeds the scratch region");
+        return DFGT_EINVAL;
+    }
     int qpt = 1;
     bool specialised = precision == DFGT_PREC_MIXED && (d == 1 || d == 2 || d == 3 || d == 5);
     if (specialised) qpt = 2;
     const int bx = (nq + kBlock * qpt - 1) / (kBlock * qpt);
-    // enough blocks to fill 256 CUs several times over
-    int nchunks = (4096 + bx * nh - 1) / (bx * nh);
-    const int max_chunks = (nr + kTile - 1) / kTile;
-    if (nchunks > max_chunks) nchunks = max_chunks;
-    if (nchunks < 1) nchunks = 1;
-    int chunk_len = (nr + nchunks - 1) / nchunks;
-    chunk_len = (chunk_len + kInner - 1) / kInner * kInner;
-    nchunks = (nr + chunk_len - 1) / chunk_len;
-    DFGT_TRY(g_part.reserve(sizeof(double) * (size_t)nchunks * nq * nh));
-    double *part = g_part.as<double>();
-    const double *hd = g_h.as<double>();
+    int chunk_len = 0;
+    const int nchunks = split_chunks(bx, nh, nr, kInner, std::min<long long>(most, (nr + kTile - 1) / kTile),
+                                     &chunk_len);
+    const bool norms = mfma_shape(d, precision);
+    const int mbx = (nq + 63) / 64;
+    int mlen = 0;
+    const int mch = norms ? split_chunks(mbx, nh, nr, 64, most, &mlen) : 0;
+    NaiveBufs b{};
+    DFGT_TRY(sp.get(nq, nr, nh, (size_t)std::max(nchunks, mch) * nq * nh, norms, &b));
+    DFGT_HIP(hipMemcpyAsync(b.h, h_host, sizeof(double) * nh, hipMemcpyHostToDevice, st));
+    double *part = b.part;
+    const double *hd = b.h;
     dim3 grid(bx, nchunks, nh);
     bool mfma = false;
-    DFGT_TRY(prepare_mfma(q, nq, r, nr, d, h_host, nh, precision, st, &mfma));
+    DFGT_TRY(prepare_mfma(q, nq, r, nr, d, h_host, nh, precision, b, st, &mfma));
     if (mfma) {
-        const int mbx = (nq + 63) / 64;
-        int mch = (4096 + mbx * nh - 1) / (mbx * nh);
-        const int mmax = (nr + 63) / 64;
-        mch = std::max(1, std::min(mch, mmax));
-        int mlen = (nr + mch - 1) / mch;
-        mlen = (mlen + 63) / 64 * 64;
-        mch = (nr + mlen - 1) / mlen;
-        DFGT_TRY(g_part.reserve(sizeof(double) * (size_t)mch * nq * nh));
         dim3 mg(mbx, mch, nh);
         const int fp = precision == DFGT_PREC_FP64 ? 1 : 0;
-        const double *qn = g_qn.as<double>(), *rn = g_rn.as<double>();
-        double *mp = g_part.as<double>();
+        const double *qn = b.qn, *rn = b.rn;
+        double *mp = b.part;
         switch ((d + 3) / 4) {
         case 2: launch_mfma<2>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
         case 3: launch_mfma<3>(mg, st, q, qn, nq, r, rn, nr, d, hd, fp, mlen, mch, mp); break;
@@ -384,6 +450,59 @@ dfgt_status launch_naive(const double *q, int64_t nq64, const double *r, int64_t
                        G);
     DFGT_HIP(hipGetLastError());
     return DFGT_OK;
+}
+
+// The no-allocation form's region: chunk partials, bandwidths and norm tables
+// of the calls of every thread on this GPU (each device holds its own copy).
+constexpr size_t kScratchDoubles = size_t(8) << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (host code never uses the symbol itself).
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+dfgt_status scratch_region(double **out) {
+    int dev = 0;
+    DFGT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("dfgt_naive_sum_noalloc: device index out of range");
+        return DFGT_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("dfgt_naive_sum_noalloc: hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return DFGT_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<double *>(g_scratch_ptr[dev]);
+    return DFGT_OK;
+}
+
+}  // namespace
+
+dfgt_status launch_naive(const double *q, int64_t nq, const double *r, int64_t nr, int d, const double *h_host,
+                         int nh, int precision, double *G, hipStream_t st) {
+    return naive_run(q, nq, r, nr, d, h_host, nh, precision, G, st, NaiveSpace{});
+}
+
+size_t naive_noalloc_limit() { return kScratchDoubles; }
+
+dfgt_status launch_naive_noalloc(const double *q, int64_t nq, const double *r, int64_t nr, int d,
+                                 const double *h_host, int nh, int precision, double *G, hipStream_t st) {
+    NaiveSpace sp;
+    DFGT_TRY(scratch_region(&sp.pool));
+    sp.cap = kScratchDoubles;
+    if (sp.head((int)nq, (int)nr, nh) + (size_t)nq * nh > sp.cap) {
+        set_error("dfgt_naive_sum_noalloc: n_h x nq + nq + nr + n_h exceeds the " +
+                  std::to_string(kScratchDoubles >> 17) + " MiB scratch region");
+        return DFGT_EINVAL;
+    }
+    return naive_run(q, nq, r, nr, d, h_host, nh, precision, G, st, sp);
 }
 
 }  // namespace dfgt

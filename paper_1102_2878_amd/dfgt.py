@@ -72,6 +72,7 @@ def lib():
         L.dfgt_tree_export.argtypes = [vp] + [vp] * 9
         L.dfgt_tree_moments.argtypes = [vp, vp]
         L.dfgt_naive_sum.argtypes = [vp, i64, vp, i64, i32, C.POINTER(dbl), i32, i32, vp, vp]
+        L.dfgt_naive_sum_noalloc.argtypes = [vp, i64, vp, i64, i32, C.POINTER(dbl), i32, i32, vp, vp]
         L.dfgt_gauss_sum.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp,
                                      C.POINTER(Stats), vp]
         L.dfgt_gauss_sum_grad.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp, vp, vp,
@@ -95,7 +96,7 @@ def lib():
         L.dfgt_batch_check.argtypes = [vp, vp]
         L.dfgt_batch_free.argtypes = [vp]
         for nm in ("dfgt_build_tree", "dfgt_build_tree_weighted", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
-                   "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
+                   "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_naive_sum_noalloc", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
                    "dfgt_gauss_sum_backward", "dfgt_lscv_score", "dfgt_lscv_optimize", "dfgt_gauss_sum_batched",
                    "dfgt_kde_density", "dfgt_lcv_score",
                    "dfgt_batch_create",
@@ -219,6 +220,21 @@ def naive_sum(q, r, h, precision=PREC_MIXED, out=None):
     _check(lib().dfgt_naive_sum(C.c_void_p(q.data_ptr()), q.shape[0], C.c_void_p(r.data_ptr()), r.shape[0],
                                 q.shape[1], hp, hv.shape[0], int(precision), C.c_void_p(out.data_ptr()),
                                 _stream()))
+    return out
+
+
+def naive_sum_noalloc(q, r, h, precision=PREC_MIXED, out=None):
+    """dfgt_naive_sum_noalloc: the brute-force sums with no device allocation in
+    the library (a fixed 64 MiB region); returns an (n_h, nq) float64 CUDA tensor
+    (allocated here by torch unless `out` is given)."""
+    torch = _torch()
+    q, r = _dev_points(q), _dev_points(r)
+    hv, hp = _hvec(h)
+    if out is None:
+        out = torch.empty((hv.shape[0], q.shape[0]), dtype=torch.float64, device=q.device)
+    _check(lib().dfgt_naive_sum_noalloc(C.c_void_p(q.data_ptr()), q.shape[0], C.c_void_p(r.data_ptr()),
+                                        r.shape[0], q.shape[1], hp, hv.shape[0], int(precision),
+                                        C.c_void_p(out.data_ptr()), _stream()))
     return out
 
 
