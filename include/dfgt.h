@@ -290,6 +290,23 @@ dfgt_status dfgt_gauss_sum_backward(dfgt_tree Q, dfgt_tree R, const double *h_ho
                                     double *dq_dev, void *stream);
 
 /*
+ * Vector-Jacobian product of derivatives already computed by
+ * dfgt_gauss_sum_grad (the saved context of a forward pass in gradient mode):
+ *     dh_host[k] = sum_i dG_dev[k*nq + i] * dGdh_dev[k*nq + i]              (may be NULL)
+ *     dq_dev[i*d + c] = sum_k dG_dev[k*nq + i] * dGdq_dev[(k*nq + i)*d + c]  (may be NULL)
+ * So a caller that keeps the forward's G~ and derivatives differentiates
+ * exactly the approximation it returned (the same traversal, the same
+ * interaction lists), with no second traversal.  Layouts as in
+ * dfgt_gauss_sum_grad; all device buffers caller-owned.  Sums are taken in a
+ * fixed order (repeated calls give the same bits).  Synchronises the stream
+ * when dh_host is given.  Errors: NULL dG_dev, both outputs NULL, an output
+ * without its derivative array, n_h < 1, nq < 1 or d outside [1, 32] ->
+ * DFGT_EINVAL.
+ */
+dfgt_status dfgt_gauss_sum_vjp(int32_t n_h, int64_t nq, int32_t d, const double *dG_dev, const double *dGdh_dev,
+                               const double *dGdq_dev, double *dh_host, double *dq_dev, void *stream);
+
+/*
  * Least-squares cross-validation score of Section 1 (the LSCV criterion used
  * to choose h), for every bandwidth h_k of h_host, from DFGT sums over R at
  * h_k and at sqrt(2) h_k (a Gaussian convolved with itself has bandwidth
@@ -301,8 +318,11 @@ dfgt_status dfgt_gauss_sum_backward(dfgt_tree Q, dfgt_tree R, const double *h_ho
  *              diagonal terms):
  *     cv = a (N + S(sqrt2 h)) / N^2 - 2 b S(h) / (N (N-1))
  * cv_host[n_h] receives the scores; dcv_host[n_h] (may be NULL) receives
- * d cv / d h from the gradient mode.  Each S carries an error of at most
- * eps * (S + N).  N >= 2 and n_h <= 32767.  Synchronises the stream.
+ * d cv / d h from the gradient mode.  The sums G~(x_i) - 1 are computed as
+ * leave-one-out sums (each point's own term left out, the pruning tolerance
+ * scaled by a lower bound on G - 1), each within eps of its own value, so
+ * each S carries an error of at most eps * S.  N >= 2 and n_h <= 32767.
+ * Synchronises the stream.
  */
 dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, double eps, int32_t variant,
                             const dfgt_options *opt, double *cv_host, double *dcv_host, dfgt_stats *stats,
@@ -324,11 +344,12 @@ dfgt_status dfgt_kde_density(dfgt_tree Q, dfgt_tree R, const double *h_host, int
  *     p_{h,-j}(r_j) = (G~(r_j, R; h) - 1) / ((N - 1) (2 pi h^2)^(D/2)),
  * the estimate at r_j from all points but r_j (G includes the self term 1).
  * dcv_host (may be NULL) receives dCV_LK/dh from the gradient mode:
- * (1/N) sum_j G'(r_j) / (G(r_j) - 1) - D/h.  The sums carry the relative
- * error eps of G, so each leave-one-out sum is within eps G / (G - 1) of its
- * value: the score is accurate where the points are not isolated at this
- * bandwidth; a leave-one-out sum <= 0 (an isolated point, its sum underflowed
- * or swamped by the error) makes the score -inf.  N >= 2, n_h <= 32767.
+ * (1/N) sum_j G'(r_j) / (G(r_j) - 1) - D/h.  The leave-one-out sums are
+ * computed as such (each point's own term left out, the pruning tolerance
+ * scaled by a lower bound on G - 1), each within eps of its own value however
+ * isolated the point, so each log term is within -log(1 - eps).  A
+ * leave-one-out sum that underflows FP64 to 0 makes the score -inf.
+ * N >= 2, n_h <= 32767.
  * Synchronises the stream.  The bandwidth maximising CV_LK is the
  * likelihood-optimal one.
  */
@@ -371,9 +392,10 @@ typedef struct dfgt_problem {
  * query of every problem and bandwidth; results do not depend on the other
  * jobs of the batch (bitwise).  Options and errors as dfgt_gauss_sum; at most
  * 2^20 (problem, bandwidth) jobs.
- * Memory: when the traversal buffers of all jobs would exceed a budget of
- * min(device memory / 8, free memory / 2), at least 1 GiB, the jobs are split
- * into parts that run in turn on the same buffers (stats->parts).  The
+ * Memory: when the traversal buffers of all jobs would exceed a budget of a
+ * quarter of the device's memory (at least 1 GiB), or cannot be allocated,
+ * the jobs are split into parts that run in turn on the same buffers
+ * (stats->parts).  The
  * environment variable DFGT_MEMORY_BUDGET_MB, when set to a positive number of
  * MiB, replaces that budget (a test knob that forces the split; results are
  * bitwise the same however the jobs are split).

@@ -463,6 +463,19 @@ dfgt_status dfgt_gauss_sum_backward(dfgt_tree Q, dfgt_tree R, const double *h_ho
     DFGT_GUARD_END
 }
 
+dfgt_status dfgt_gauss_sum_vjp(int32_t n_h, int64_t nq, int32_t d, const double *dG_dev, const double *dGdh_dev,
+                               const double *dGdq_dev, double *dh_host, double *dq_dev, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(dG_dev, "dfgt_gauss_sum_vjp: NULL dG_dev");
+    DFGT_REQUIRE(n_h >= 1 && nq >= 1 && nq < (int64_t(1) << 31) && d >= 1 && d <= kMaxD,
+                 "dfgt_gauss_sum_vjp: n_h, nq or d out of range");
+    DFGT_REQUIRE(dh_host || dq_dev, "dfgt_gauss_sum_vjp: both gradient outputs are NULL");
+    DFGT_REQUIRE(!dh_host || dGdh_dev, "dfgt_gauss_sum_vjp: dh_host needs dGdh_dev");
+    DFGT_REQUIRE(!dq_dev || dGdq_dev, "dfgt_gauss_sum_vjp: dq_dev needs dGdq_dev");
+    return run_vjp(n_h, nq, d, dG_dev, dGdh_dev, dGdq_dev, dh_host, dq_dev, (hipStream_t)stream);
+    DFGT_GUARD_END
+}
+
 dfgt_status dfgt_lscv_score(dfgt_tree R, const double *h_host, int32_t n_h, double eps, int32_t variant,
                             const dfgt_options *opt, double *cv_host, double *dcv_host, dfgt_stats *stats,
                             void *stream) {

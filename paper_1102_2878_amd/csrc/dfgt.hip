@@ -59,7 +59,10 @@ struct Job {
     double *outH, *outQ;       // gradient mode: dG/dh [N_Q] and dG/dq [N_Q][D] (caller order), or null
     double cost_e;             // weight of the exhaustive cost in ChooseBestMethod
     int mono;                  // Q and R are the same point set
-    int pad;
+    int loo;                   // leave-one-out: Q = R and each query's own point is left out of its sum
+    double a32;                // largest |a| + |b| (sig units, coordinates relative to the query
+                               // leaf's centre) for which FP32 differences keep the exhaustive
+                               // sums within their rounding budget; <= 0: FP64 differences only
 };
 
 struct Seg {
@@ -299,6 +302,9 @@ struct TravOut {
     int *overflow;
     unsigned long long *stats;
     double *cval;    // [job][node] constant local terms from order-1 translations
+    unsigned char *selfE;  // [job][leaf] leave-one-out: the leaf's pair with itself is exhaustive
+                           // (k_leaf adds the leaf's sums from k_selfpre)
+    const double *selfmin; // [job][leaf] leave-one-out: a lower bound on the leaf's sums
     int want_stats;  // collect dfgt_stats counters
     Caps cap;
 };
@@ -356,6 +362,9 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         const double ku = exp(-g.su * jb.inv2h2);
         const double nR = (double)(R.end[r] - R.begin[r]);
         const double wR = R.w ? R.mu[(size_t)r * R.P] : nR;
+        // leave-one-out: the pair of a node with itself covers each query's own
+        // point, which its sum leaves out
+        const double wL = (jb.loo && r == q) ? wR - 1.0 : wR;
         if (i < 64) {
             r0 = r;
             g0 = g;
@@ -367,10 +376,11 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         } else {
             kus[sg.start + i] = ku;  // reused by the decisions below
         }
-        sl += wR * ku;
+        sl += wL * ku;
     }
     sl = wave_sum(sl);
-    const double gl = fmax((sg.gl + sl) * (1.0 - 1e-12), jb.prior);
+    double gl = fmax((sg.gl + sl) * (1.0 - 1e-12), jb.prior);
+    if (jb.loo && qleaf) gl = fmax(gl, o.selfmin[(size_t)jb.noff + q]);  // the leaf's own leave-one-out sums
 
     // 2. decisions and counts
     int cE = 0, cF = 0, cL = 0, cN = 0, nT = 0, nC = 0, nD = 0, maxord = 0;
@@ -387,8 +397,11 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         double kc = 0.0;
         const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, wR, tau, pmax, D, force, gr, jb.cost_e, &ord, &kc);
         const bool rleaf = (first ? left0 : R.left[r]) < 0;
+        const bool self = jb.loo && r == q;
         if (m != METH_E) {
-            plo += wR * ku;
+            plo += (self ? wR - 1.0 : wR) * ku;
+            // the approximation covers every query's own point (K = 1): left out here
+            if (self) ccon -= 1.0;
             if (m == METH_F) ++cF;
             else if (m == METH_T && ord == 1) {
                 // order-1 far-to-local translation (the centroid form): its only
@@ -404,7 +417,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
             }
             maxord = max(maxord, ord);
         } else if (qleaf && rleaf) {
-            ++cE;
+            if (!self) ++cE;  // a leaf's pair with itself is summed by k_selfsum
             ept += nR;
         } else {
             cN += (qleaf || !rleaf) ? 2 : 1;
@@ -576,8 +589,10 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
             rleaf = rl < 0;
             if (m == METH_F) f = 1;
             else if (m != METH_E) l = m == METH_D ? (nRi + 63) / 64 : (ord == 1 ? 0 : 1);
-            else if (qleaf && rleaf) e = 1;
-            else n = (qleaf || !rleaf) ? 2 : 1;
+            else if (qleaf && rleaf) {
+                if (jb.loo && r == q) o.selfE[hq] = 1;
+                else e = 1;
+            } else n = (qleaf || !rleaf) ? 2 : 1;
         }
         int te, tf, tl, tn;
         const int xe = wave_excl(e, &te), xf = wave_excl(f, &tf), xl = wave_excl(l, &tl), xn = wave_excl(n, &tn);
@@ -1244,7 +1259,10 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               double *__restrict__ stQ, const double *__restrict__ cval,
                                               const int *__restrict__ jlstart, int njobs, int unl,
                                               const unsigned long long *__restrict__ gdg,
-                                              const unsigned short *__restrict__ gmt) {
+                                              const unsigned short *__restrict__ gmt,
+                                              const unsigned char *__restrict__ selfE,
+                                              const double *__restrict__ selfG, const double *__restrict__ selfX,
+                                              const double *__restrict__ selfY) {
     extern __shared__ double smem[];
     if (*overflow) return;
     __shared__ double cs_s;
@@ -1638,10 +1656,12 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
             // everything but the exhaustive sums; k_leaf_finish adds those once
             // the tiles' stream has joined, and writes the caller's outputs
             const size_t ei = (size_t)jb.qoff + qpos;
-            stG[ei] = (gl + csum) + gsum;
+            // leave-one-out: the leaf's exhaustive pair with itself (from k_selfpre)
+            const bool self = selfE && selfE[hq];
+            stG[ei] = (gl + csum) + gsum + (self ? selfG[ei] : 0.0);
             if (GR) {
-                stX[ei] = xl + xsum;
-                for (int c = 0; c < d; ++c) stQ[ei * d + c] = gq[c];
+                stX[ei] = xl + xsum + (self ? selfX[ei] : 0.0);
+                for (int c = 0; c < d; ++c) stQ[ei * d + c] = gq[c] + (self ? selfY[ei * d + c] : 0.0);
             }
         }
         __syncthreads();
@@ -1866,6 +1886,50 @@ __device__ __forceinline__ void etile_fast(const double *__restrict__ st, const 
     }
 }
 
+// Mixed pairs with FP32 differences: points staged as NF4 float4 each (the
+// first DT components the coordinates relative to the query leaf's centre,
+// scaled by sig; the last component of the last float4 the weight), padded
+// rounds of t4 points per group as in etile_fast.
+template <int DT, int NF4>
+__device__ __forceinline__ void etile_fast32(const float4 *__restrict__ st, int g, int ng, int t4,
+                                             const float (&qs)[2][DT], double (&acc)[2]) {
+    for (int t0 = 0; t0 < t4; t0 += 64) {
+        const int te = min(t4, t0 + 64);  // <= 64 points of this lane: one FP32 partial
+        float ps[2] = {0.0f, 0.0f};
+        for (int t = t0; t < te; t += kEUnroll) {
+            float xv[kEUnroll][4 * NF4];
+#pragma unroll
+            for (int u = 0; u < kEUnroll; ++u) {
+                const int j = g + ng * (t + u);
+#pragma unroll
+                for (int f = 0; f < NF4; ++f) {
+                    const float4 v = st[j * NF4 + f];
+                    xv[u][4 * f] = v.x;
+                    xv[u][4 * f + 1] = v.y;
+                    xv[u][4 * f + 2] = v.z;
+                    xv[u][4 * f + 3] = v.w;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kEUnroll; ++u) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float d0 = qs[a][0] - xv[u][0];
+                    float tt = d0 * d0;
+#pragma unroll
+                    for (int c = 1; c < DT; ++c) {
+                        const float dc = qs[a][c] - xv[u][c];
+                        tt = fmaf(dc, dc, tt);
+                    }
+                    ps[a] = fmaf(xv[u][4 * NF4 - 1], __builtin_amdgcn_exp2f(-tt), ps[a]);
+                }
+            }
+        }
+        acc[0] += (double)ps[0];
+        acc[1] += (double)ps[1];
+    }
+}
+
 // One lane's query against the staged points g, g + ng, ... < cnt (runtime d):
 // mixed pairs (F64 = false) or FP64 pairs (t in sig units, e = 2^-t), each
 // term times the staged point weight sw[j] (sw null: weight 1).
@@ -1913,22 +1977,29 @@ __device__ __forceinline__ void etile_strided(const double *__restrict__ st, con
 }
 
 template <int DT, bool GR, bool F64>
-__global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                               const Group *__restrict__ egrp, const int *__restrict__ eops,
-                                               const int *__restrict__ headE, const int *__restrict__ cnt_dev,
-                                               const int *__restrict__ overflow, const int *__restrict__ jlstart,
-                                               int njobs, int unl, int precision, const int *__restrict__ order,
-                                               int nitems, double *__restrict__ GE, double *__restrict__ GX,
-                                               double *__restrict__ GY) {
+__device__ __forceinline__ void etile_body(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                           const Group *__restrict__ egrp, const int *__restrict__ eops,
+                                           const int *__restrict__ headE, const int *__restrict__ cnt_dev,
+                                           const int *__restrict__ overflow, const int *__restrict__ jlstart,
+                                           int njobs, int unl, int precision, const int *__restrict__ order,
+                                           int nitems, double *__restrict__ GE, double *__restrict__ GX,
+                                           double *__restrict__ GY) {
     using Sh = ETileShape<DT, F64>;
     constexpr int DS = Sh::DS, QPT = Sh::QPT;
     constexpr bool PAD = Sh::PAD;
     constexpr int kSP = PAD ? etile_rpw<DT, F64>(DT > 0 ? DT : 1) + kEPadPts : 1;  // padded entries per wave
+    // FP32-difference form (value sums in mixed precision, D <= 5): NF4 float4
+    // per staged point, RPW32 points per wave and round
+    constexpr bool F32D = PAD && !GR && DT <= 3;
+    constexpr int NF4 = DT <= 3 ? 1 : 2;
+    constexpr int RPW32 = kEWaveStage / (2 * NF4) - kEPadPts;
+    constexpr int PPL32 = (RPW32 + 63) / 64;
     __shared__ int gS[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
     constexpr int NW = kEWaves, kCh = 64 * kEWaves;  // E ops flattened per chunk: one per thread
     __shared__ int oB[kCh], oCum[kCh];
     __shared__ int wsum[NW], nops_s, take_s;
-    __shared__ double stage[NW][kEWaveStage];
+    __shared__ double wb2[NW];
+    __shared__ __align__(16) double stage[NW][kEWaveStage];
     __shared__ float pwt[NW][kSP];
     __shared__ double swt[NW][PAD ? 1 : 256];  // point weights of the strided form
     __shared__ double red[NW][64 * QPT];
@@ -1981,8 +2052,20 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
         return;
     }
     double *st = stage[wv];
+    float4 *st4 = reinterpret_cast<float4 *>(stage[wv]);
     float *pw = pwt[wv];
     double *sw = swt[wv];
+    // the query leaf's centre and half-diagonal (sig units) for the FP32 form
+    const bool try32 = F32D && jb.a32 > 0.0;
+    double qc[DS];
+    double qhalf = 0.0;
+    if (try32)
+        for (int c = 0; c < d; ++c) {
+            qc[c] = Q.ctr[(size_t)leaf * d + c];
+            const double hw = 0.5 * (Q.hi[(size_t)leaf * d + c] - Q.lo[(size_t)leaf * d + c]);
+            qhalf = fma(hw, hw, qhalf);
+        }
+    qhalf = std::sqrt(qhalf) * jb.sig;
     for (int qg = 0; qg < nq; qg += 64 * QPT) {
         const int nqg = min(64 * QPT, nq - qg);
         const int need = (nqg + QPT - 1) / QPT;     // lanes per group
@@ -1990,11 +2073,14 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
         const bool lact = lane < NG * need;
         const int ql = lact ? lane % need : 0, g = lact ? lane / need : 0;
         double qs[QPT][DS], acc[QPT], xacc[QPT], yacc[QPT][DS];
+        float qs32[2][DS];
 #pragma unroll
         for (int a = 0; a < QPT; ++a) {
             const int qi = ql + need * a;
             const int qpos = qb0 + qg + (qi < nqg ? qi : 0);
             for (int c = 0; c < d; ++c) qs[a][c] = Q.x[(size_t)qpos * d + c] * jb.sig;
+            if (try32)
+                for (int c = 0; c < d; ++c) qs32[a][c] = (float)((Q.x[(size_t)qpos * d + c] - qc[c]) * jb.sig);
             acc[a] = 0.0;
             xacc[a] = 0.0;
             if (GR)
@@ -2004,6 +2090,7 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
             __syncthreads();  // the previous chunk's tables are no longer read
             const int o = o0 + tid;
             int np = 0;
+            double b2 = 0.0;  // squared distance of the op's farthest box corner from the leaf centre
             if (o < nops) {
                 int gi = 0;
                 while (o >= gCum[gi]) ++gi;
@@ -2011,21 +2098,41 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
                     const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
                     oB[tid] = R.begin[r];
                     np = R.end[r] - R.begin[r];
+                    if (try32)
+                        for (int c = 0; c < d; ++c) {
+                            const double l = R.lo[(size_t)r * d + c] - qc[c], h = R.hi[(size_t)r * d + c] - qc[c];
+                            b2 += fmax(l * l, h * h);
+                        }
                 }
             }
             const int inc = wave_incl_scan(np);
             if (lane == 63) wsum[wv] = inc;
+            if (try32) {
+                b2 = wave_max(b2);
+                if (lane == 0) wb2[wv] = b2;
+            }
             __syncthreads();
             int pre = 0;
             for (int w = 0; w < wv; ++w) pre += wsum[w];
             oCum[tid] = pre + inc;
+            // FP32 differences for this chunk when every pair's |a| + |b| is within the budget
+            bool use32 = false;
+            if (try32) {
+                double m = 0.0;
+                for (int w = 0; w < NW; ++w) m = fmax(m, wb2[w]);
+                use32 = qhalf + std::sqrt(m) * jb.sig <= jb.a32;
+            }
             __syncthreads();
             const int nopc = min(kCh, nops - o0);
             const int tot = oCum[nopc - 1];
-            for (int p0 = wv * RPW; p0 < tot; p0 += NW * RPW) {
+            // rounds short enough that every wave of the block gets one (a short E list
+            // would otherwise leave waves idle); multiples of 16 points
+            const int RPWc = min(use32 ? RPW32 : RPW, max(16, (tot + 16 * NW - 1) / (16 * NW) * 16));
+            const int PPLc = (RPWc + 63) / 64;
+            for (int p0 = wv * RPWc; p0 < tot; p0 += NW * RPWc) {
                 // stage the round: lane l takes points l PPL + k, k < PPL
-                const int cnt = min(RPW, tot - p0);
-                int i = lane * PPL;
+                const int cnt = min(RPWc, tot - p0);
+                int i = lane * PPLc;
                 if (i < cnt) {
                     int lo = 0, hi = nopc - 1;  // first op with oCum > p0 + i
                     while (lo < hi) {
@@ -2034,24 +2141,42 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
                         else lo = mid + 1;
                     }
                     int op = lo;
-                    for (int k = 0; k < PPL && i < cnt; ++k, ++i) {
+                    for (int k = 0; k < PPLc && i < cnt; ++k, ++i) {
                         const int p = p0 + i;
                         while (oCum[op] <= p) ++op;
                         const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
-                        for (int c = 0; c < d; ++c) st[i * d + c] = R.x[(size_t)row * d + c] * jb.sig;
-                        if constexpr (PAD) pw[i] = R.w ? (float)R.w[row] : 1.0f;
-                        else if (R.w) sw[i] = R.w[row];
+                        if (F32D && use32) {
+                            float v[4 * NF4];
+#pragma unroll
+                            for (int c = 0; c < 4 * NF4; ++c)
+                                v[c] = c < DS ? (float)((R.x[(size_t)row * DS + c] - qc[c]) * jb.sig) : 0.0f;
+                            v[4 * NF4 - 1] = R.w ? (float)R.w[row] : 1.0f;
+#pragma unroll
+                            for (int f = 0; f < NF4; ++f)
+                                st4[i * NF4 + f] = make_float4(v[4 * f], v[4 * f + 1], v[4 * f + 2], v[4 * f + 3]);
+                        } else {
+                            for (int c = 0; c < d; ++c) st[i * d + c] = R.x[(size_t)row * d + c] * jb.sig;
+                            if constexpr (PAD) pw[i] = R.w ? (float)R.w[row] : 1.0f;
+                            else if (R.w) sw[i] = R.w[row];
+                        }
                     }
                 }
                 if constexpr (PAD) {
                     const int t4 = ((cnt + NG - 1) / NG + kEUnroll - 1) / kEUnroll * kEUnroll;
                     // zero-weight padding up to NG t4 entries (< cnt + 4 NG <= RPW + kEPadPts)
-                    for (int i2 = cnt + lane; i2 < NG * t4; i2 += 64) {
-                        for (int c = 0; c < d; ++c) st[i2 * d + c] = 0.0;
-                        pw[i2] = 0.0f;
+                    if (F32D && use32) {
+                        for (int i2 = cnt + lane; i2 < NG * t4; i2 += 64)
+                            for (int f = 0; f < NF4; ++f) st4[i2 * NF4 + f] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        wave_sync();  // a wave's LDS accesses complete in order
+                        if constexpr (F32D) etile_fast32<DT, NF4>(st4, g, NG, t4, qs32, acc);
+                    } else {
+                        for (int i2 = cnt + lane; i2 < NG * t4; i2 += 64) {
+                            for (int c = 0; c < d; ++c) st[i2 * d + c] = 0.0;
+                            pw[i2] = 0.0f;
+                        }
+                        wave_sync();  // a wave's LDS accesses complete in order
+                        etile_fast<DT, GR>(st, pw, g, NG, t4, qs, acc, xacc, yacc);
                     }
-                    wave_sync();  // a wave's LDS accesses complete in order
-                    etile_fast<DT, GR>(st, pw, g, NG, t4, qs, acc, xacc, yacc);
                 } else {
                     wave_sync();
                     etile_strided<GR, F64>(st, R.w ? sw : nullptr, g, NG, cnt, d, qs[0], acc[0], xacc[0], yacc[0]);
@@ -2078,6 +2203,95 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
             __syncthreads();
         }
     }
+}
+
+template <int DT, bool GR, bool F64>
+__global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                                        const Group *__restrict__ egrp, const int *__restrict__ eops,
+                                                        const int *__restrict__ headE, const int *__restrict__ cnt_dev,
+                                                        const int *__restrict__ overflow,
+                                                        const int *__restrict__ jlstart, int njobs, int unl,
+                                                        int precision, const int *__restrict__ order, int nitems,
+                                                        double *__restrict__ GE, double *__restrict__ GX,
+                                                        double *__restrict__ GY) {
+    etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, precision,
+                            order, nitems, GE, GX, GY);
+}
+
+// The 3-D mixed-precision value pass, held to 128 VGPRs (four waves per SIMD,
+// two 8-wave blocks per CU; it fits without spills): left to itself the
+// compiler takes ~165 and a CU runs one block.
+template <int DT, bool GR, bool F64>
+__global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_etile_o4(
+    const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Group *__restrict__ egrp,
+    const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,
+    const int *__restrict__ overflow, const int *__restrict__ jlstart, int njobs, int unl, int precision,
+    const int *__restrict__ order, int nitems, double *__restrict__ GE, double *__restrict__ GX,
+    double *__restrict__ GY) {
+    etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, precision,
+                            order, nitems, GE, GX, GY);
+}
+
+// Leave-one-out sums of every query leaf with itself, before the traversal:
+// for each query i of the leaf, sum_{j in leaf, j != i} e^{-|x_i - x_j|^2 / 2h^2}
+// in FP64 (and with GR the X_E and Y_E parts, in the exhaustive tiles' units).
+// Their minimum over the leaf, scaled by (1 - 1e-12) against rounding, is a
+// lower bound on every leave-one-out sum of the leaf (the other parts are
+// >= 0): the traversal's G^l for the leaf's segments, where the bounds from
+// box distances are weak (in high dimensions they underflow).  When the
+// leaf's pair with itself ends exhaustive, k_leaf adds these sums (the pair
+// is not listed as an exhaustive op).  One block per (job, query leaf), one
+// thread per query; jobs without leave-one-out return at once.
+template <bool GR>
+__global__ __launch_bounds__(256) void k_selfpre(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                                 const int *__restrict__ jlstart, int njobs, int unl,
+                                                 double *__restrict__ selfG, double *__restrict__ selfX,
+                                                 double *__restrict__ selfY, double *__restrict__ selfmin) {
+    __shared__ double red[256];
+    int job, li;
+    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
+    const Job jb = jobs[job];
+    if (!jb.loo) return;
+    const DevTree &Q = trees[jb.qt];
+    const int leaf = Q.leaves[li];
+    const int qb = Q.begin[leaf], nq = Q.end[leaf] - qb, d = Q.d;
+    const double sig = jb.sig;
+    double mn = INFINITY;
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+        const double *xi = Q.x + (size_t)(qb + i) * d;
+        double acc = 0.0, xacc = 0.0, yacc[kMaxD];
+        if (GR)
+            for (int c = 0; c < d; ++c) yacc[c] = 0.0;
+        for (int j = 0; j < nq; ++j) {
+            if (j == i) continue;
+            const double *xj = Q.x + (size_t)(qb + j) * d;
+            double t = 0.0, dd[kMaxD];
+            for (int c = 0; c < d; ++c) {
+                dd[c] = xi[c] * sig - xj[c] * sig;
+                t = fma(dd[c], dd[c], t);
+            }
+            const double e = exp(-t * kLn2);
+            acc += e;
+            if (GR) {
+                xacc = fma(-2.0 * kLn2 * t, e, xacc);
+                for (int c = 0; c < d; ++c) yacc[c] = fma(-2.0 * kSqrtLn2 * e, dd[c], yacc[c]);
+            }
+        }
+        const size_t ei = (size_t)jb.qoff + qb + i;
+        selfG[ei] = acc;
+        if (GR) {
+            selfX[ei] = xacc;
+            for (int c = 0; c < d; ++c) selfY[ei * d + c] = yacc[c];
+        }
+        mn = fmin(mn, acc);
+    }
+    red[threadIdx.x] = mn;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) selfmin[(size_t)jb.noff + leaf] = nq > 1 ? red[0] * (1.0 - 1e-12) : 0.0;
 }
 
 // ---------------------------------------------------------------- exhaustive tiles on the matrix cores
@@ -2377,7 +2591,8 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
-        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, stG, stX, stQ, cval, gdg, gmt, eord;
+        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, stG, stX, stQ, cval, gdg, gmt, eord, selfE,
+        selfG, selfX, selfY, selfmin;
     // overflow flag, counters and per-level counts in one allocation: one fill,
     // one copy back
     DevBuf ctl;
@@ -2445,12 +2660,16 @@ void launch_etile(bool f64pass, int d, int nitems, hipStream_t st, const DevTree
                   double *GY) {
     const dim3 grid((unsigned)nitems);
 #define DFGT_ETILE(DV)                                                                                            \
-    if (f64pass)                                                                                                  \
+    if (f64pass) {                                                                                                \
         hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
                            jls, njobs, unl, precision, (const int *)nullptr, nitems, GE, GX, GY);                 \
-    else                                                                                                          \
+    } else if constexpr (DV == 3 && !GR) {                                                                        \
+        hipLaunchKernelGGL((k_etile_o4<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,   \
+                           flag, jls, njobs, unl, precision, order, nitems, GE, GX, GY);                          \
+    } else {                                                                                                      \
         hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,      \
                            flag, jls, njobs, unl, precision, order, nitems, GE, GX, GY);                          \
+    }                                                                                                             \
     break;
     switch (d) {
     case 1: DFGT_ETILE(1)
@@ -2470,7 +2689,7 @@ struct Plan {
     std::vector<DevTree> trees;
     std::vector<int> jls;  // per-job prefix of (job, query leaf) items
     int njobs = 0, nlev = 0, d = 0, pmax = 0, P = 0, PW = 0, precision = 0, force = 0, items = 0;
-    bool gr = false, leaf_local = true, emfma = false, acc_lds = true, dig_lds = true;
+    bool gr = false, leaf_local = true, emfma = false, acc_lds = true, dig_lds = true, loo = false;
     size_t nna = 0, nqa = 0;  // node slots and query slots over all jobs
     int leaf_threads = 256, lop_waves = 4;
     size_t leaf_sh = 0, lop_sh = 0, big_sh = 0;
@@ -2524,18 +2743,43 @@ size_t plan_bytes(const Plan &pl, const Caps &c) {
     return b;
 }
 
+// Rounding of the exhaustive sums with FP32 coordinate differences, per term
+// K = 2^-t, t = |a - b|^2, where a = (q - c) sig and b = (r - c) sig are rounded
+// to FP32 (c the query leaf's centre, u = 2^-24): each staged coordinate
+// carries u |a_k| (u |b_k|), each difference u |a_k - b_k| more, and the
+// FP32 sum of D squares D u t, so to first order
+//     |dt| <= u ((D + 2) t + 2 |a - b| (|a| + |b|)).
+// Terms that matter have t <= 126 (smaller ones flush, the underflow guard's
+// share), so the relative error of a term is at most
+//     ln2 u ((D + 2) 126 + 2 sqrt(126) A) + 2^-22 (exp2) + u (the weight),
+// A = max |a| + |b| over the pairs, plus 63 u for FP32 partial sums of <= 64
+// positive terms.  Returns the largest A that keeps the total within
+// eps_round (<= 0: none).
+double etile_a32(double eps_round, int d) {
+    const double u = 0x1p-24, ln2 = 0.69314718055994530942;
+    const double rest = eps_round - 0x1p-22 - 64.0 * u;
+    const double a = (rest / (ln2 * u) - (d + 2) * 126.0) / (2.0 * std::sqrt(126.0));
+    return a > 0.0 ? a : 0.0;
+}
+
 // Memory one call may size its traversal buffers to before it splits its jobs:
-// min(total / 8, free / 2), at least 1 GiB.  DFGT_MEMORY_BUDGET_MB, when set to
-// a positive number, replaces it (no floor): a test knob that forces the
-// split into parts on small inputs.
+// a quarter of the device's memory, at least 1 GiB.  It depends on the device
+// only, so repeated calls split the same way (a budget that followed the free
+// memory changed as the workspace grew, and every change re-learnt the split
+// with reruns).  An allocation that fails splits the jobs as well.
+// DFGT_MEMORY_BUDGET_MB, when set to a positive number, replaces it (no
+// floor): a test knob that forces the split into parts on small inputs.
 size_t memory_budget() {
     if (const char *ev = std::getenv("DFGT_MEMORY_BUDGET_MB")) {
         const long long mb = std::atoll(ev);
         if (mb > 0) return (size_t)mb << 20;
     }
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess || tot == 0) return (size_t)16 << 30;
-    return std::max<size_t>((size_t)1 << 30, std::min(tot / 8, fr / 2));
+    static size_t total = 0;
+    if (total == 0) {
+        size_t fr = 0, tot = 0;
+        total = hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0 ? tot : ((size_t)64 << 30);
+    }
+    return std::max<size_t>((size_t)1 << 30, total / 4);
 }
 
 dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int force, double cost_e,
@@ -2551,9 +2795,12 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     if (precision == DFGT_PREC_MIXED && eps > 0.0 && eps < 2e-5) precision = DFGT_PREC_FP64;
     pl.precision = precision;
     // Rounding budget of the exhaustive sums (the global-error theorem takes
-    // them as exact): mixed precision <= 1e-5 relative, FP64 ~1e-13.
-    const double eps_round = precision == DFGT_PREC_FP64 ? 1e-12 : 1e-5;
+    // them as exact): FP64 ~1e-13; mixed precision 1e-5 relative, or 1e-4 when
+    // eps >= 2e-3 (then FP32 coordinate differences fit in it for nearby
+    // leaves, see etile_a32).
+    const double eps_round = precision == DFGT_PREC_FP64 ? 1e-12 : (eps >= 2e-3 ? 1e-4 : 1e-5);
     const double eps_eff = eps > 2.0 * eps_round ? eps - eps_round : 0.0;
+    const double a32 = precision == DFGT_PREC_MIXED && grad == nullptr ? etile_a32(eps_round, t0->d) : 0.0;
     // a query leaf's own local ops are applied inside k_leaf when its per-wave
     // scratch fits; otherwise they go through the node kernels
     pl.leaf_local = pl.P <= 512;
@@ -2587,7 +2834,9 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.nR = q.R->wsum / q.R->wscale;
             j.cntR = (double)q.R->n;
             j.wscale = q.R->wscale;
-            j.prior = q.Q == q.R && !q.R->weighted ? 1.0 : 0.0;  // the self term: G(q) >= 1
+            const bool loo = q.loo && q.Q == q.R && !q.R->weighted;
+            // the self term: G(q) >= 1 (left out of leave-one-out sums)
+            j.prior = q.Q == q.R && !q.R->weighted && !loo ? 1.0 : 0.0;
             j.qt = qt;
             j.rt = rt;
             j.qoff = nqa;
@@ -2596,8 +2845,10 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.outH = pl.gr && grad->dGdh ? grad->dGdh + (size_t)k * q.Q->n : nullptr;
             j.outQ = pl.gr && grad->dGdq ? grad->dGdq + (size_t)k * q.Q->n * pl.d : nullptr;
             j.cost_e = cost_e;
-            j.mono = q.Q == q.R && !q.R->weighted ? 1 : 0;  // the self term bounds G below by 1
-            j.pad = 0;
+            j.mono = q.Q == q.R && !q.R->weighted && !loo ? 1 : 0;  // the self term bounds G below by 1
+            j.loo = loo ? 1 : 0;
+            pl.loo = pl.loo || loo;
+            j.a32 = a32;
             pl.jobs.push_back(j);
             nna += q.Q->m;
             nqa += q.Q->n;
@@ -2681,6 +2932,15 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<double>(w.L, nna * pl.PW));
     DFGT_TRY(grow<unsigned>(w.lflag, (nna + 3) / 4));
     DFGT_TRY(grow<double>(w.cval, nna));
+    if (pl.loo) {
+        DFGT_TRY(grow<unsigned>(w.selfE, (nna + 3) / 4));
+        DFGT_TRY(grow<double>(w.selfmin, nna));
+        DFGT_TRY(grow<double>(w.selfG, pl.nqa));
+        if (pl.gr) {
+            DFGT_TRY(grow<double>(w.selfX, pl.nqa));
+            DFGT_TRY(grow<double>(w.selfY, pl.nqa * pl.d));
+        }
+    }
     DFGT_TRY(grow<int>(w.heads, 3 * nna));
     DFGT_TRY(alloc_spans(w.ctl, {{&w.flag, sizeof(int) * CP},
                                  {&w.cnt, sizeof(int) * C_N * CP},
@@ -2747,7 +3007,7 @@ dfgt_status upload_plan(const Plan &pl, Workspace &w, hipStream_t st) {
 // Several fills in one launch: region r is words[r] u32 values v[r] at p[r];
 // block b takes the kFillChunk words from b * kFillChunk of the regions laid
 // end to end.
-constexpr int kFillN = 6, kFillChunk = 4096;
+constexpr int kFillN = 8, kFillChunk = 4096;
 struct FillSet {
     unsigned *p[kFillN];
     unsigned long long words[kFillN], start[kFillN + 1];
@@ -2801,13 +3061,22 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
         fs.p[4] = (unsigned *)w.stats.p;
         fs.words[4] = 2 * S_N * SP;
         if (first_part) {
-            fs.p[5] = (unsigned *)w.sticky.p;
-            fs.words[5] = 1;
-            fs.n = 6;
+            fs.p[fs.n] = (unsigned *)w.sticky.p;
+            fs.words[fs.n++] = 1;
+        }
+        if (pl.loo) {
+            fs.p[fs.n] = (unsigned *)w.selfE.p;
+            fs.words[fs.n++] = (nna + 3) / 4;
         }
         fill_many(fs, st);
     }
     hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
+    if (pl.loo) {  // leave-one-out: every leaf's sums with itself, the traversal's lower bound for its leaves
+        auto kp = pl.gr ? k_selfpre<true> : k_selfpre<false>;
+        hipLaunchKernelGGL(kp, dim3((unsigned)pl.items), dim3(256), 0, st, td, jd, jls, njobs, pl.unl,
+                           w.selfG.as<double>(), pl.gr ? w.selfX.as<double>() : nullptr,
+                           pl.gr ? w.selfY.as<double>() : nullptr, w.selfmin.as<double>());
+    }
     if (!pl.dig_lds)
         hipLaunchKernelGGL(k_digits, dim3((P + 255) / 256), dim3(256), 0, st, w.gdg.as<unsigned long long>(),
                            w.gmt.as<unsigned short>(), P, d, pmax);
@@ -2818,7 +3087,9 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
                   w.fgrp.as<Group>(), w.fops.as<Op>(),  w.lgrp.as<Group>(), w.lops.as<Op>(),
                   w.lnodes.as<int>(), headE,            headF,              headL,
                   w.cnt.as<int>(),  lvl + (size_t)(k + 1) * 2 * CP,         w.flag.as<int>(),
-                  w.stats.as<unsigned long long>(),     w.cval.as<double>(), prof ? 1 : 0, w.cap};
+                  w.stats.as<unsigned long long>(),     w.cval.as<double>(),
+                  pl.loo ? w.selfE.as<unsigned char>() : nullptr, pl.loo ? w.selfmin.as<double>() : nullptr,
+                  prof ? 1 : 0, w.cap};
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
         hipLaunchKernelGGL(k_traverse, dim3(kTravGrid / kTravWaves), dim3(64 * kTravWaves), 0, st, td, jd,
                            sin.as<Seg>(), pin.as<int>(),
@@ -2893,7 +3164,9 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
                            w.stG.as<double>(), pl.gr ? w.stX.as<double>() : nullptr,
                            pl.gr ? w.stQ.as<double>() : nullptr, w.cval.as<double>(), jls, njobs,
                            pl.unl, pl.dig_lds ? nullptr : w.gdg.as<unsigned long long>(),
-                           pl.dig_lds ? nullptr : w.gmt.as<unsigned short>());
+                           pl.dig_lds ? nullptr : w.gmt.as<unsigned short>(),
+                           pl.loo ? w.selfE.as<unsigned char>() : nullptr, w.selfG.as<double>(),
+                           w.selfX.as<double>(), w.selfY.as<double>());
         if (prof) prof->stop(K_LEAF, ev, st);
     }
     // the outputs, once the tiles' stream has joined
@@ -3000,8 +3273,16 @@ dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stat
     }
     int c[C_N] = {0};
     int overflow = 1;
+    const Caps entry = cap;
     for (int attempt = 0; attempt < 12 && overflow; ++attempt) {
-        DFGT_TRY(alloc_plan(pl, w));
+        const dfgt_status as = alloc_plan(pl, w);
+        if (as == DFGT_ENOMEM && pl.njobs > 1) {  // the device cannot hold this part: split it
+            clear_error();
+            cap = entry;
+            *too_big = true;
+            return DFGT_OK;
+        }
+        DFGT_TRY(as);
         DFGT_TRY(upload_plan(pl, w, st));
         prof.begin_call(profile != 0);
         // stats are gathered whenever a caller asks for them
@@ -3093,8 +3374,9 @@ dfgt_status run_gauss_multi(const Problem *pr, int np, double eps, int precision
 
 dfgt_status run_gauss_sum(dfgt_tree_s *Qh, dfgt_tree_s *Rh, const double *h, int nh, double eps, int precision,
                           int force, int profile, double cost_e, double *G, const GradOut *grad,
-                          dfgt_stats *stats_out, hipStream_t st) {
-    const Problem pr{Qh, Rh, h, nh, G};
+                          dfgt_stats *stats_out, hipStream_t st, bool loo) {
+    Problem pr{Qh, Rh, h, nh, G};
+    pr.loo = loo ? 1 : 0;
     return run_gauss_multi(&pr, 1, eps, precision, force, profile, cost_e, grad, stats_out, st);
 }
 

@@ -295,6 +295,7 @@ struct Problem {
     const double *h;
     int nh;
     double *G;
+    int loo = 0;  // Q == R: leave each query's own point out of its sums (G - 1, computed as such)
 };
 // Several problems (same D and p_max) and all their bandwidths in one traversal.
 dfgt_status run_gauss_multi(const Problem *pr, int np, double eps, int precision, int force, int profile,
@@ -305,13 +306,18 @@ dfgt_status batch_create(const Problem *pr, int np, double eps, int precision, i
 dfgt_status batch_run(dfgt_batch_s *b, hipStream_t st);
 dfgt_status batch_check(dfgt_batch_s *b, hipStream_t st);
 // cost_e: weight of the exhaustive cost in ChooseBestMethod (1 = the paper's model).
+// loo: leave-one-out sums (Q == R unweighted): G~ approximates G - 1 to eps (G - 1).
 dfgt_status run_gauss_sum(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps,
                           int precision, int force, int profile, double cost_e, double *G, const GradOut *grad,
-                          dfgt_stats *stats, hipStream_t st);
+                          dfgt_stats *stats, hipStream_t st, bool loo = false);
 
 // sweep.hip
 dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh, double eps, int precision,
                          int force, double cost_e, const double *dG, double *dh_host, double *dq, hipStream_t st);
+// Vector-Jacobian product of saved derivatives: dh[k] = sum_i dG[k][i] dGdh[k][i] (host),
+// dq[i][c] = sum_k dG[k][i] dGdq[k][i][c]; fixed summation order.
+dfgt_status run_vjp(int nh, int64_t nq, int d, const double *dG, const double *dGdh, const double *dGdq,
+                    double *dh_host, double *dq, hipStream_t st);
 dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,
                      int variant, double *cv, double *dcv, dfgt_stats *stats, hipStream_t st);
 dfgt_status run_lcv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,

@@ -119,6 +119,18 @@ dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh
     return DFGT_OK;
 }
 
+dfgt_status run_vjp(int nh, int64_t nq, int d, const double *dG, const double *dGdh, const double *dGdq,
+                    double *dh_host, double *dq, hipStream_t st) {
+    if (dq) {
+        const long long tot = (long long)nq * d;
+        hipLaunchKernelGGL(k_dq, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dG, dGdq, nh, (long long)nq, d,
+                           dq);
+        DFGT_HIP(hipGetLastError());
+    }
+    if (dh_host) DFGT_TRY(row_sums(dG, dGdh, 0.0, (long long)nq, nh, dh_host, st));
+    return DFGT_OK;
+}
+
 dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int precision, int force, double cost_e,
                      int variant, double *cv, double *dcv, dfgt_stats *stats, hipStream_t st) {
     SweepWs &w = g_sw;
@@ -134,11 +146,12 @@ dfgt_status run_lscv(dfgt_tree_s *R, const double *h, int nh, double eps, int pr
     DFGT_TRY(w.G.reserve(sizeof(double) * nj * n));
     if (dcv) DFGT_TRY(w.dGdh.reserve(sizeof(double) * nj * n));
     GradOut go{dcv ? w.dGdh.as<double>() : nullptr, nullptr};
+    // leave-one-out sums G_j(x_i) - 1, each within eps of its own value
     DFGT_TRY(run_gauss_sum(R, R, hh.data(), nj, eps, precision, force, 0, cost_e, w.G.as<double>(),
-                           dcv ? &go : nullptr, stats, st));
-    // S_j = sum_i (G_j(x_i) - 1): the sums without their self terms
+                           dcv ? &go : nullptr, stats, st, true));
+    // S_j = sum_i (G_j(x_i) - 1)
     std::vector<double> S(nj), dS(nj, 0.0);
-    DFGT_TRY(row_sums(w.G.as<double>(), nullptr, 1.0, (long long)n, nj, S.data(), st));
+    DFGT_TRY(row_sums(w.G.as<double>(), nullptr, 0.0, (long long)n, nj, S.data(), st));
     if (dcv) DFGT_TRY(row_sums(w.dGdh.as<double>(), nullptr, 0.0, (long long)n, nj, dS.data(), st));
     const double N = (double)n, D = (double)R->d, pi = 3.14159265358979323846;
     for (int k = 0; k < nh; ++k) {
@@ -167,12 +180,13 @@ dfgt_status run_lcv(dfgt_tree_s *R, const double *h, int nh, double eps, int pre
     DFGT_TRY(w.G.reserve(sizeof(double) * nh * n));
     if (dcv) DFGT_TRY(w.dGdh.reserve(sizeof(double) * nh * n));
     GradOut go{dcv ? w.dGdh.as<double>() : nullptr, nullptr};
+    // leave-one-out sums G(r_j) - 1, each within eps of its own value
     DFGT_TRY(run_gauss_sum(R, R, h, nh, eps, precision, force, 0, cost_e, w.G.as<double>(), dcv ? &go : nullptr,
-                           stats, st));
-    // sum_j log(G(r_j) - 1): the leave-one-out sums (the self term is 1)
+                           stats, st, true));
+    // sum_j log(G(r_j) - 1)
     std::vector<double> L(nh), dL(nh, 0.0);
-    DFGT_TRY(row_sums(w.G.as<double>(), nullptr, 1.0, (long long)n, nh, L.data(), st, ROW_LOG));
-    if (dcv) DFGT_TRY(row_sums(w.G.as<double>(), w.dGdh.as<double>(), 1.0, (long long)n, nh, dL.data(), st, ROW_RATIO));
+    DFGT_TRY(row_sums(w.G.as<double>(), nullptr, 0.0, (long long)n, nh, L.data(), st, ROW_LOG));
+    if (dcv) DFGT_TRY(row_sums(w.G.as<double>(), w.dGdh.as<double>(), 0.0, (long long)n, nh, dL.data(), st, ROW_RATIO));
     const double N = (double)n, D = (double)R->d, pi = 3.14159265358979323846;
     for (int k = 0; k < nh; ++k) {
         const double logV = 0.5 * D * std::log(2.0 * pi * h[k] * h[k]);

@@ -79,6 +79,7 @@ def lib():
                                           C.POINTER(Stats), vp]
         L.dfgt_gauss_sum_backward.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp,
                                               C.POINTER(dbl), vp, vp]
+        L.dfgt_gauss_sum_vjp.argtypes = [i32, i64, i32, vp, vp, vp, C.POINTER(dbl), vp, vp]
         L.dfgt_lscv_score.argtypes = [vp, C.POINTER(dbl), i32, dbl, i32, C.POINTER(Options), C.POINTER(dbl),
                                       C.POINTER(dbl), C.POINTER(Stats), vp]
         L.dfgt_kde_density.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp, C.POINTER(Stats),
@@ -97,7 +98,7 @@ def lib():
         L.dfgt_batch_free.argtypes = [vp]
         for nm in ("dfgt_build_tree", "dfgt_build_tree_weighted", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
                    "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_naive_sum_noalloc", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
-                   "dfgt_gauss_sum_backward", "dfgt_lscv_score", "dfgt_lscv_optimize", "dfgt_gauss_sum_batched",
+                   "dfgt_gauss_sum_backward", "dfgt_gauss_sum_vjp", "dfgt_lscv_score", "dfgt_lscv_optimize", "dfgt_gauss_sum_batched",
                    "dfgt_kde_density", "dfgt_lcv_score",
                    "dfgt_batch_create",
                    "dfgt_batch_run", "dfgt_batch_check", "dfgt_batch_free"):
@@ -289,6 +290,21 @@ def gauss_sum_backward(Q: Tree, R: Tree, h, eps, dG, want_dh=True, want_dq=True,
     _check(lib().dfgt_gauss_sum_backward(Q.handle, R.handle, hp, nh, float(eps), C.byref(o), _vp(dG),
                                          dh.ctypes.data_as(C.POINTER(C.c_double)) if dh is not None else None,
                                          _vp(dq), _stream()))
+    return dh, dq
+
+
+def gauss_sum_vjp(dG, dGdh=None, dGdq=None):
+    """dfgt_gauss_sum_vjp: (dh numpy (n_h,) or None, dq CUDA tensor (NQ, d) or None) from saved
+    derivatives of dfgt_gauss_sum_grad."""
+    torch = _torch()
+    dG = dG.to(dtype=torch.float64).contiguous()
+    nh, nq = dG.shape
+    d = dGdq.shape[2] if dGdq is not None else 1
+    dh = np.empty(nh) if dGdh is not None else None
+    dq = torch.empty((nq, d), dtype=torch.float64, device=dG.device) if dGdq is not None else None
+    _check(lib().dfgt_gauss_sum_vjp(nh, nq, d, _vp(dG), _vp(dGdh), _vp(dGdq),
+                                    dh.ctypes.data_as(C.POINTER(C.c_double)) if dh is not None else None,
+                                    _vp(dq), _stream()))
     return dh, dq
 
 

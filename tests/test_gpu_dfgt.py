@@ -248,6 +248,24 @@ def test_full_size_c3_sampled(dfgt, pmax, eps):
     assert st["max_order"] >= 2
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_exhaustive_rounding_budget(dfgt, d):
+    """Every leaf pair exhaustive at eps = 1e-2: the leaf sums may spend a
+    rounding budget of 1e-4 relative (FP32 coordinate differences relative to
+    the query leaf's centre where the staged coordinates are small enough,
+    FP64 differences elsewhere), so every query is within 1e-4 of the exact
+    sum; bandwidths from a fraction of a leaf's width to many leaf widths put
+    both forms in the same call."""
+    x = synth.c3(n=6000, seed=61)[:, :d].copy()
+    hs = [synth.silverman_h(x) * s for s in (0.01, 0.1, 1.0, 10.0)]
+    note(f"dfgt exhaustive rounding budget d={d}")
+    for leaf in (32, 128):
+        G, st = _run(dfgt, x, None, hs, 1e-2, leaf=leaf, force=5)
+        for k, h in enumerate(hs):
+            rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+            assert rel.max() <= 1e-4, (d, leaf, h, rel.max())
+
+
 def test_underflow_guard_fp64_groups(dfgt):
     """Sums below the FP32 range: a tight reference cluster and queries on a
     ring at 13.5-14 h (exponents 91-98, each term under 2^-126) plus queries
