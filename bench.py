@@ -1,32 +1,30 @@
 """Benchmark of the MI355X dual-tree fast Gauss transform on one GPU.
 
-Workload (the 2-D clustered configuration): 50,000 points, D = 2, 32
-anisotropic Gaussian clusters + 10% uniform background, Q = R; seven
-bandwidths h* x 10^{-3..3} (h* = the LSCV optimum, tests/golden/hstar.json);
-relative error eps = 1e-2 on every query.
+Headline workload (the batched configuration): eight 3-D clustered problems
+of 10k, 20k, 40k, 60k, 80k, 120k, 160k and 200k points (Q = R each), every
+problem swept over 64 log-spaced bandwidths h_S x 10^{-3..3} at h and sqrt(2) h
+(the pair the least-squares cross-validation score needs): 1,024 Gaussian
+sums with relative error eps = 1e-2 on every query, in one traversal, captured
+once as a HIP graph (dfgt_batch_create) and replayed.
 
-One step = the whole hot path over that input, resident in HBM:
-  kd-tree build + raw moments (dfgt_build_tree)  ->  DFGT for all seven
-  bandwidths in one traversal (dfgt_gauss_sum).
-value = N_Q * N_R * 7 / (seconds per step)  [query x reference pairs / s].
-The kd-tree leaf size is picked before anything is timed by
-dfgt_tune_leaf_size on this workload (--leaf N fixes it instead); the choice
-and every candidate's time are in config.leaf_tuning.
-The plain tiled brute-force GPU sum (dfgt_naive_sum) over the same seven
-bandwidths is timed alongside.
+One step = one replay of that graph over inputs resident in HBM (the trees,
+built once beforehand, are timed separately as build_ms).
+value = sum_k N_k^2 x 128 / (seconds per step)  [query x reference pairs / s].
+The leaf size is picked before anything is timed by dfgt_tune_leaf_size on
+the largest problem (--leaf N fixes it instead).  The same 1,024 sums as one
+eager dfgt_gauss_sum_batched call, and the plain tiled brute-force GPU sum
+(dfgt_naive_sum) over them, are timed alongside.
 
-batched: the 3-D batch, 8 clustered problems of 10k..200k points, each swept
-over 64 log-spaced bandwidths h_S x 10^{-3..3} at h and sqrt(2) h (the LSCV
-pair): 1024 sums in one traversal, eager and as a captured graph replay,
-beside the brute force over the same 1024 sums; its leaf size is tuned on the
-largest problem.
-
-grad_ms (the metric's second part): the backward pass on the 16-D workload,
-200,000 points (8 latent clusters embedded + N(0, 0.01 I) noise), eps 1e-4,
-bandwidths {h_S, h*} (h* of its seeded 5,000-point subsample,
-tests/golden/hstar.json): dfgt_lscv_score with dCV/dh (sums at h and sqrt(2) h
-with their h-derivatives) plus dfgt_gauss_sum_backward for dG/dq, tree built
-once outside the timed region.
+Secondary workloads in the same line:
+  c2    2-D, 50,000 points, 7 bandwidths h* x 10^{-3..3}: tree build + sums
+        per step, the brute force, single-bandwidth calls (DFGT, the DFD
+        ablation, brute force) and every leaf pair forced exhaustive;
+  c3    5-D, 100,000 points, the same 7 scales of its h*, expansion orders 6
+        and 2 per dimension at eps 1e-2 and 1e-4, beside the brute force;
+  grad  16-D, 200,000 points, eps 1e-4: dfgt_lscv_score with dCV/dh plus the
+        dG/dq backward (grad_ms).
+Every workload's error is checked against the oracle's exact sums on seeded
+query rows; the CPU baseline is the oracle itself timed on the host's cores.
 
 Prints ONE JSON line.  --gpus must be 1 (this build targets one GPU).
 """
@@ -47,64 +45,54 @@ METRIC = "query×ref pairs/s at rel-err 1e-2 (dual-tree vs brute-force GPU) + gr
 SCALES = [1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0, 1000.0]
 EPS = 1e-2
 
-# Exhaustive-tile roofline (bound "alu"): the algorithmic work per point pair is
-# 2D+1 FP32 VALU operations (D differences, D-1 fused multiply-adds + 1 multiply,
-# 1 add) and one v_exp_f32.  Peak pair rate = 256 CUs x 64 lanes x 2.4 GHz /
-# (2D+1 + EXP_SLOTS) VALU issue slots, EXP_SLOTS = issue cost of v_exp_f32 in
-# full-rate slots (transcendentals run at a quarter of the VALU rate).  Rates
-# are also quoted in TFLOP/s at FLOPS_PER_PAIR = 3D+1 (D subtractions, D
-# squares, D-1 additions, the exponential, the accumulation).
-CUS, LANES, CLOCK = 256, 64, 2.4e9
-EXP_SLOTS = 4
-
-# HBM bytes per launch of the mixed-precision exhaustive-tile kernel
-# (k_etile<2, false, false>) in one step of this workload, from two rocprofv3
-# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the counters of a 256 MiB
-# device copy: profiles/dfgt_c2_sweep_hbm_traffic.md.  Valid for the kernel
-# as profiled; None when it has changed since.
-K_ETILE_TRAFFIC_BYTES = {64: 9.90e6 + 2.99e6, 128: 8.41e6 + 2.90e6}  # by leaf size; others: not measured (null)
+# Roofline of the exhaustive leaf-leaf tiles (DFGTBase), the dominant kernel:
+# the algorithmic work per point pair is 3D + 2 flops (D differences, D
+# squares, D - 1 additions, the exponential, the weighted accumulation as a
+# multiply-add), priced against MI355X's published FP32 vector peak.
+FP32_PEAK = 157.3e12
+CUS, CLOCK = 256, 2.4e9
+# Issue-slot model of the same work, from a throughput probe on the MI355X
+# (lane-operations per CU-clock: FP32 FMA 98.6, v_exp_f32 27.9, measured
+# serially, not co-issued): a pair takes 2D + 1 FP32 VALU slots and one exp.
+FMA_RATE, EXP_RATE = 98.6, 27.9
 
 
 def flops_per_pair(d):
-    return 3 * d + 1
+    return 3 * d + 2
 
 
-def base_peak_pairs(d):
-    return CUS * LANES * CLOCK / (2 * d + 1 + EXP_SLOTS)
+def slot_peak_pairs(d):
+    return CUS * CLOCK / ((2 * d + 1) / FMA_RATE + 1.0 / EXP_RATE)
 
 
-def per_bandwidth(torch, dfgt, x, hs, leaf, reps=3):
-    """Median ms per single-bandwidth call: DFGT, DFD ablation, brute force."""
-    R = dfgt.build_tree(x, leaf_size=leaf)
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
-    def med(f):
+
+def median_ms(torch, f, reps=3):
+    f()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
         f()
         torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            f()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        return sorted(ts)[reps // 2] * 1e3
-
-    rows = []
-    for s, h in zip(SCALES, hs):
-        rows.append({
-            "h_over_hstar": s,
-            "dfgt_ms": med(lambda: dfgt.gauss_sum(R, R, [h], EPS)),
-            "dfd_ms": med(lambda: dfgt.gauss_sum(R, R, [h], EPS, force_method=dfgt.FORCE_CENTROID)),
-            "bruteforce_ms": med(lambda: dfgt.naive_sum(x, x, [h])),
-        })
-    return {"what": "single-bandwidth calls, tree built once, eps 1e-2: DFGT, the DFD ablation (only the "
-                    "centroid finite-difference prune), brute force", "rows": rows}
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[reps // 2] * 1e3
 
 
-def batched_bench(torch, dfgt, synth, leaf):
-    """The 3-D batch: eager call, graph replays, brute force; returns details.
+def rel_err(G, ref):
+    return float(np.max(np.abs(G - ref) / ref))
 
-    leaf 0: the leaf size comes from dfgt_tune_leaf_size on the largest problem
-    at 16 of its bandwidths (outside the timed region)."""
+
+# ------------------------------------------------------------------ 3-D batch (headline)
+def batched_setup(torch, dfgt, synth, leaf):
     xs = [synth.c4_problem(k) for k in range(8)]
     xd = [torch.as_tensor(x, device="cuda") for x in xs]
     torch.cuda.synchronize()
@@ -115,6 +103,8 @@ def batched_bench(torch, dfgt, synth, leaf):
         leaf, tms = dfgt.tune_leaf_size(xd[big], hb, EPS, reps=2)
         tuning = {"on": f"the largest problem (N = {len(xs[big])}), 16 log-spaced bandwidths, 2 repetitions",
                   "candidates_ms": {str(k): v for k, v in tms.items()}}
+    dfgt.build_tree(xd[0], leaf_size=leaf)  # warm the build path
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     trees = [dfgt.build_tree(x, leaf_size=leaf) for x in xd]
     torch.cuda.synchronize()
@@ -123,22 +113,14 @@ def batched_bench(torch, dfgt, synth, leaf):
     for x, t in zip(xs, trees):
         base = synth.silverman_h(x) * np.geomspace(1e-3, 1e3, 64)
         probs.append((t, t, np.concatenate([base, np.sqrt(2.0) * base])))
-    dfgt.gauss_sum_batched(probs, EPS)
+    return xs, xd, trees, probs, leaf, tuning, t_build
+
+
+def batched_extras(torch, dfgt, xd, probs, b):
+    """Eager call, per-kernel event times of one eager call, brute force."""
+    t_eager = median_ms(torch, lambda: dfgt.gauss_sum_batched(probs, EPS))
+    _, st = dfgt.gauss_sum_batched(probs, EPS, stats=True, profile=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dfgt.gauss_sum_batched(probs, EPS)
-    torch.cuda.synchronize()
-    t_eager = time.perf_counter() - t0
-    b = dfgt.Batch(probs, EPS, stats=True)
-    b.run()
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.run()
-    torch.cuda.synchronize()
-    t_graph = (time.perf_counter() - t0) / reps
-    b.check()
     t0 = time.perf_counter()
     worst = 0.0
     for x, (t, _, h), G in zip(xd, probs, b.G):
@@ -146,19 +128,103 @@ def batched_bench(torch, dfgt, synth, leaf):
         worst = max(worst, float(((G - Gb).abs() / Gb).max()))
     torch.cuda.synchronize()
     t_bf = time.perf_counter() - t0
-    pairs = float(sum(x.shape[0] ** 2 for x in xs)) * 128
-    return {
-        "workload": "3-D, 8 clustered problems N = 10k..200k (sum 690k), 64 log-spaced h x {1, sqrt2}, eps 1e-2",
-        "sums": 8 * 128, "leaf_size": leaf, "leaf_tuning": tuning,
-        "build_ms": t_build * 1e3, "eager_ms": t_eager * 1e3, "graph_replay_ms": t_graph * 1e3,
-        "pairs_per_s_graph": pairs / t_graph, "bruteforce_ms": t_bf * 1e3, "bruteforce_pairs_per_s": pairs / t_bf,
-        "speedup_vs_bruteforce": t_bf / t_graph, "max_rel_err_vs_bruteforce": worst,
-        "node_pairs": b.stats["node_pairs"], "base_point_pairs": b.stats["base_point_pairs"],
+    return t_eager, st, t_bf, worst
+
+
+# ------------------------------------------------------------------ 2-D sweep
+def c2_bench(torch, dfgt, synth, args):
+    hstar = json.load(open(os.path.join(ROOT, "tests", "golden", "hstar.json")))["c2"]["h_star"]
+    hs = [hstar * s for s in SCALES]
+    xh = synth.c2()
+    n = xh.shape[0]
+    x = torch.as_tensor(xh, device="cuda")
+    leaf, tuning = args.leaf, None
+    if leaf == 0:
+        leaf, tms = dfgt.tune_leaf_size(x, hs, EPS, reps=3)
+        tuning = {"on": "this workload (build + the 7-bandwidth sums), 3 repetitions",
+                  "candidates_ms": {str(k): v for k, v in tms.items()}}
+
+    def step():
+        t = dfgt.build_tree(x, leaf_size=leaf)
+        return dfgt.gauss_sum(t, t, hs, EPS)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        G = step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    R = dfgt.build_tree(x, leaf_size=leaf)
+    _, st = dfgt.gauss_sum(R, R, hs, EPS, stats=True, profile=True)
+    _, st = dfgt.gauss_sum(R, R, hs, EPS, stats=True, profile=True)
+    t_build = median_ms(torch, lambda: dfgt.build_tree(x, leaf_size=leaf), reps=5)
+    t_bf = median_ms(torch, lambda: dfgt.naive_sum(x, x, hs), reps=3)
+    forced = {}
+    for bl in sorted({leaf, 32}):
+        tx = dfgt.build_tree(x, leaf_size=bl)
+        for scale in (1.0, 10.0):
+            for _ in range(2):
+                _, sx = dfgt.gauss_sum(tx, tx, [hstar * scale], EPS, force_method=dfgt.FORCE_EXACT, profile=True)
+            rate = sx["base_point_pairs"] / (sx["kernel_ms"]["etile"] * 1e-3)
+            forced[f"leaf_{bl}_h{scale:g}hstar"] = {
+                "pairs": sx["base_point_pairs"], "k_etile_ms": sx["kernel_ms"]["etile"], "pairs_per_s": rate,
+                "frac_fp32_peak": rate * flops_per_pair(2) / FP32_PEAK, "frac_issue_slots": rate / slot_peak_pairs(2)}
+    rows = []
+    for s, h in zip(SCALES, hs):
+        rows.append({"h_over_hstar": s,
+                     "dfgt_ms": median_ms(torch, lambda: dfgt.gauss_sum(R, R, [h], EPS)),
+                     "dfd_ms": median_ms(torch, lambda: dfgt.gauss_sum(R, R, [h], EPS,
+                                                                      force_method=dfgt.FORCE_CENTROID)),
+                     "bruteforce_ms": median_ms(torch, lambda: dfgt.naive_sum(x, x, [h]))})
+    pairs = float(n) * n * len(hs)
+    out = {
+        "workload": "2-D clustered mixture, 50,000 points (Q = R), 7 bandwidths h* x 10^-3..10^3, eps 1e-2; "
+                    "step = tree build + sums",
+        "h_star": hstar, "leaf_size": leaf, "leaf_tuning": tuning, "p_max": 6,
+        "ms_per_step": t_step * 1e3, "pairs_per_s": pairs / t_step,
+        "bruteforce_ms": t_bf, "bruteforce_pairs_per_s": pairs / (t_bf * 1e-3),
+        "speedup_vs_bruteforce": t_bf / (t_step * 1e3),
+        "build_ms": t_build, "kernel_ms": st["kernel_ms"], "kernel_launches": st["kernel_launches"],
+        "traversal": {k: st[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
+                                         "base_leaf_pairs", "base_point_pairs", "levels", "segments")},
+        "exhaustive_tile_rate": {
+            "pairs_per_s": st["base_point_pairs"] / (st["kernel_ms"]["etile"] * 1e-3),
+            "frac_fp32_peak": st["base_point_pairs"] / (st["kernel_ms"]["etile"] * 1e-3) * flops_per_pair(2)
+            / FP32_PEAK},
+        "forced_exhaustive": forced,
+        "per_bandwidth": {"what": "single-bandwidth calls, tree built once: DFGT, the DFD ablation (only the "
+                                  "centroid finite-difference prune), brute force", "rows": rows},
     }
+    return xh, hs, G, out
 
 
-def grad_bench(args, torch, dfgt, synth):
-    """Backward on the 16-D workload; returns (ms, details)."""
+# ------------------------------------------------------------------ 5-D workload
+def c3_bench(torch, dfgt, synth, oracle):
+    hstar = json.load(open(os.path.join(ROOT, "tests", "golden", "hstar.json")))["c3"]["h_star"]
+    hs = [hstar * s for s in SCALES]
+    xh = synth.c3()
+    x = torch.as_tensor(xh, device="cuda")
+    rows = synth.subsample(xh, 300, 45)
+    ref = np.stack([oracle.naive_kde_rows(xh, rows, xh, h) for h in hs])
+    t_bf = median_ms(torch, lambda: dfgt.naive_sum(x, x, hs), reps=3)
+    out = {"workload": "5-D correlated mixture + 5% Student-t outliers, 100,000 points (Q = R), 7 bandwidths "
+                       "h* x 10^-3..10^3", "h_star": hstar, "bruteforce_ms": t_bf, "rows": []}
+    for pmax in (6, 2):
+        R = dfgt.build_tree(x, p_max=pmax)
+        for eps in (1e-2, 1e-4):
+            ms = median_ms(torch, lambda: dfgt.gauss_sum(R, R, hs, eps))
+            G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True)
+            err = rel_err(G.cpu().numpy()[:, rows], ref)
+            out["rows"].append({"p_max": pmax, "eps": eps, "ms": ms, "speedup_vs_bruteforce": t_bf / ms,
+                                "max_rel_err_oracle": err, "oracle_rows": len(rows),
+                                "base_point_pairs": st["base_point_pairs"], "max_order": st["max_order"]})
+    return out
+
+
+# ------------------------------------------------------------------ 16-D gradients
+def grad_bench(args, torch, dfgt, synth, oracle):
     hj = json.load(open(os.path.join(ROOT, "tests", "golden", "hstar.json")))
     x5 = synth.c5()
     n5, d5 = x5.shape
@@ -180,23 +246,33 @@ def grad_bench(args, torch, dfgt, synth):
         cv, dcv, dq = one()
     torch.cuda.synchronize()
     t_grad = (time.perf_counter() - t0) / args.grad_steps
-    # where the time goes: one profiled gradient-mode call over the four LSCV sums
     hh = hs5 + [np.sqrt(2.0) * h for h in hs5]
     _, _, _, st = dfgt.gauss_sum_grad(R, R, hh, eps5, dq=False, stats=True, profile=True)
     em_ms = st["kernel_ms"]["etile"]
     pairs = st["base_point_pairs"]
-    # matrix-core roofline of the exhaustive tiles in gradient mode: per pair
-    # 2 D flops for q.r plus 2 D for the kernel-weighted reference sums
-    flops = pairs * 4.0 * d5
-    peak = 78.6e12
+    flops = pairs * 4.0 * d5  # q.r and the kernel-weighted reference sums, 2 D each
+    # oracle check of G, dG/dh and dG/dq on seeded query rows against all 200,000 references
+    G, Gh, Gq = dfgt.gauss_sum_grad(R, R, hs5, eps5)
+    rows = synth.subsample(x5, 200, 56)
+    idx = torch.as_tensor(rows, device="cuda")
+    G, Gh, Gq = G[:, idx].cpu().numpy(), Gh[:, idx].cpu().numpy(), Gq[:, idx].cpu().numpy()
+    errs = {"G": 0.0, "dGdh": 0.0, "dGdq": 0.0}
+    for k, h in enumerate(hs5):
+        g, gh, gq = oracle.naive_kde_grad(x5[rows], x5, h)
+        qs = oracle.naive_kde_qscale(x5[rows], x5, h)
+        errs["G"] = max(errs["G"], rel_err(G[k], g))
+        errs["dGdh"] = max(errs["dGdh"], float(np.max(np.abs(Gh[k] - gh) / gh)))
+        errs["dGdq"] = max(errs["dGdq"], float(np.max(np.linalg.norm(Gq[k] - gq, axis=1) / qs)))
     det = {
         "workload": f"16-D clustered, {n5} points (Q = R), bandwidths h_S, h* (+ sqrt2 h for LSCV), eps {eps5}",
         "h": hs5, "leaf_size": args.grad_leaf, "steps": args.grad_steps,
         "cv": [float(v) for v in cv], "dcv_dh": [float(v) for v in dcv],
         "lscv_grad_call": {"kernel_ms": st["kernel_ms"], "base_point_pairs": pairs, "node_pairs": st["node_pairs"]},
+        "max_rel_err_oracle": {**errs, "rows": len(rows), "units": "G and dG/dh relative to themselves, dG/dq "
+                               "relative to h^-2 sum_j K_j |q - r_j|"},
         "roofline_emfma": {"bound": "mfma", "achieved": flops / (em_ms * 1e-3) / 1e12 if em_ms > 0 else None,
-                           "peak": peak / 1e12, "unit": "TFLOP/s",
-                           "frac": flops / (em_ms * 1e-3) / peak if em_ms > 0 else None,
+                           "peak": 78.6, "unit": "TFLOP/s",
+                           "frac": flops / (em_ms * 1e-3) / 78.6e12 if em_ms > 0 else None,
                            "flops_per_pair": 4 * d5, "dtype": "f64"},
     }
     return t_grad * 1e3, det
@@ -207,17 +283,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--cpu-rows", type=int, default=200, help="oracle query rows per problem for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-grad", action="store_true", help="skip the 16-D backward timing")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 3-D batched sweep")
+    ap.add_argument("--no-secondary", action="store_true", help="only the headline (3-D batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a kernel of known traffic that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     ap.add_argument("--grad-steps", type=int, default=3)
     ap.add_argument("--grad-leaf", type=int, default=128)
     ap.add_argument("--leaf", type=int, default=0,
-                    help="leaf size of the 2-D and batched workloads; 0 = dfgt_tune_leaf_size picks it (untimed)")
+                    help="leaf size of the 3-D and 2-D workloads; 0 = dfgt_tune_leaf_size picks it (untimed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -227,12 +302,6 @@ def main():
 
     from paper_1102_2878_amd import dfgt, synth
 
-    hstar = json.load(open(os.path.join(ROOT, "tests", "golden", "hstar.json")))["c2"]["h_star"]
-    hs = [hstar * s for s in SCALES]
-    x_host = synth.c2()
-    n, d = x_host.shape
-    x = torch.as_tensor(x_host, device="cuda")
-    torch.cuda.synchronize()
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -240,112 +309,47 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # the leaf size: tuned on this workload before anything is timed
-    leaf = args.leaf
-    leaf_tuning = None
-    if leaf == 0:
-        leaf, tms = dfgt.tune_leaf_size(x, hs, EPS, reps=3)
-        leaf_tuning = {"on": "this workload (build + the 7-bandwidth sums), 3 repetitions",
-                       "candidates_ms": {str(k): v for k, v in tms.items()}}
-
-    def step(profile):
-        t = dfgt.build_tree(x, leaf_size=leaf)
-        if not profile:
-            return dfgt.gauss_sum(t, t, hs, EPS), None
-        return dfgt.gauss_sum(t, t, hs, EPS, stats=True, profile=True)
-
+    # ---- headline: the captured 3-D batch
+    xs, xd, trees, probs, leaf, tuning, t_build = batched_setup(torch, dfgt, synth, args.leaf)
+    b = dfgt.Batch(probs, EPS, stats=True)
     for _ in range(args.warmup):
-        step(False)
+        b.run()
     torch.cuda.synchronize()
-
-    # timed region: K steps exactly as a caller runs them (no events, no stats)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        G, _ = step(False)
+        b.run()
     torch.cuda.synchronize()
     t_step = (time.perf_counter() - t0) / args.steps
-
-    # the same steps with HIP events around every launch, for the per-kernel breakdown
-    agg_ms = {}
-    agg_launch = {}
-    base_pairs = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = step(True)
-        for k, v in st["kernel_ms"].items():
-            agg_ms[k] = agg_ms.get(k, 0.0) + v
-            agg_launch[k] = agg_launch.get(k, 0) + st["kernel_launches"][k]
-        base_pairs += st["base_point_pairs"]
-    torch.cuda.synchronize()
-    t_step_prof = (time.perf_counter() - t0) / args.steps
-    stats = st
-
-    # base-case tiles: one call with every leaf pair exhaustive at h*, at the
-    # tuned leaf size and at leaf 32 (one block per query leaf: 1,563 leaves
-    # give every CU work, where the 391 leaves of leaf 128 leave it partly idle)
-    base_cases = {}
-    for bl in sorted({leaf, 32}):
-        tree_x = dfgt.build_tree(x, leaf_size=bl)
-        for _ in range(2):
-            _, st_x = dfgt.gauss_sum(tree_x, tree_x, [hstar], EPS, force_method=dfgt.FORCE_EXACT, stats=True,
-                                     profile=True)
-        base_cases[bl] = {"pairs": st_x["base_point_pairs"], "k_etile_ms": st_x["kernel_ms"]["etile"]}
-        del tree_x
-
-    # per-bandwidth comparison (the layout of the paper's Table 1 on the
-    # synthetic stand-in): DFGT, the DFD ablation (centroid finite-difference
-    # prune only, p_max = 1 rule of the same code) and the brute force, one
-    # bandwidth per call, tree built once
-    per_h = per_bandwidth(torch, dfgt, x, hs, leaf)
-
-    # build alone
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dfgt.build_tree(x, leaf_size=leaf)
-    torch.cuda.synchronize()
-    t_build = (time.perf_counter() - t0) / args.steps
-
-    # brute-force comparator, same inputs and bandwidths
-    for _ in range(max(1, args.warmup)):
-        dfgt.naive_sum(x, x, hs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        Gb = dfgt.naive_sum(x, x, hs)
-    torch.cuda.synchronize()
-    t_bf = (time.perf_counter() - t0) / args.steps
-
-    pairs = float(n) * n * len(hs)
+    b.check()
+    pairs = float(sum(x.shape[0] ** 2 for x in xs)) * 128
     value = pairs / t_step
+    t_eager, st, t_bf, worst_bf = batched_extras(torch, dfgt, xd, probs, b)
 
-    # roofline of the exhaustive tiles (DFGTBase) in the timed step, from the
-    # HIP events around their launches on the stream they run on
-    et_ms = agg_ms.get("etile", 0.0)
-    et_launches = max(agg_launch.get("etile", 0), 1)
-    dominant = max(agg_ms, key=agg_ms.get) if agg_ms else None
-    pair_rate = (base_pairs / (et_ms * 1e-3)) if et_ms > 0 else 0.0
-    peak = base_peak_pairs(d)
-    fpp = flops_per_pair(d)
+    # roofline of the dominant kernel, the exhaustive tiles: the HIP events
+    # around its launches on the stream it runs on (a side stream, beside the
+    # local-moment and per-leaf kernels) in one eager call of the same jobs
+    km, kl = st["kernel_ms"], st["kernel_launches"]
+    et_ms, et_n = km["etile"], max(kl["etile"], 1)
+    ep = st["base_point_pairs"]
+    rate = ep / (et_ms * 1e-3)
     roofline = {
-        "kernel": "k_etile (DFGTBase exhaustive leaf-leaf tiles, mixed precision; on a side stream beside the "
-                  "local-moment kernels, timed as it runs there)",
+        "kernel": "k_etile (DFGTBase exhaustive leaf-leaf tiles, D = 3, mixed precision)",
         "bound": "alu",
-        "achieved": pair_rate * fpp / 1e12,
-        "peak": peak * fpp / 1e12,
+        "achieved": rate * flops_per_pair(3) / 1e12,
+        "peak": FP32_PEAK / 1e12,
         "unit": "TFLOP/s",
-        "frac": pair_rate / peak,
-        "traffic": K_ETILE_TRAFFIC_BYTES.get(leaf),
-        "traffic_unit": "HBM bytes per launch (read + written)",
-        "flops_per_pair": fpp,
-        "pairs_per_s": pair_rate,
-        "peak_pairs_per_s": peak,
-        "avg_launch_ms": et_ms / et_launches,
-        "pairs_per_launch": base_pairs / et_launches,
-        "dominant_kernel_in_step": dominant,
-        "dominant_kernel_note": "k_traverse is latency-bound (one wave per segment, one launch per tree level): "
-                                "it has no throughput roofline; see traversal.node_pairs_per_s",
+        "frac": rate * flops_per_pair(3) / FP32_PEAK,
+        "traffic": None,
+        "traffic_note": "HBM bytes per launch are not measured in this run (rocprofv3 FETCH_SIZE / WRITE_SIZE "
+                        "summaries: profiles/)",
+        "flops_per_pair": flops_per_pair(3),
+        "pairs_per_launch": ep / et_n,
+        "avg_launch_ms": et_ms / et_n,
+        "pairs_per_s": rate,
+        "issue_slot_frac": rate / slot_peak_pairs(3),
+        "issue_slot_peak_pairs_per_s": slot_peak_pairs(3),
+        "kernel_ms_of_one_eager_call": km,
     }
-
     out = {
         "metric": METRIC,
         "value": value,
@@ -360,66 +364,54 @@ def main():
         "dtype": "f32-exp/f64-sum",
         "data": "synthetic",
         "config": {
-            "workload": "2-D clustered mixture, 50,000 points (Q = R), 7 bandwidths h* x 10^-3..10^3, eps 1e-2",
-            "n": n, "d": d, "n_bandwidths": len(hs), "eps": EPS, "h_star": hstar, "leaf_size": leaf,
-            "leaf_tuning": leaf_tuning,
-            "p_max": 6,
+            "workload": "3-D batch: 8 clustered problems N = 10k..200k (sum 690k, Q = R), 64 log-spaced "
+                        "bandwidths h_S x 10^-3..10^3 at h and sqrt2 h (1,024 sums), eps 1e-2, one captured "
+                        "graph replayed per step",
+            "problems": [int(x.shape[0]) for x in xs], "d": 3, "sums": 1024, "eps": EPS, "leaf_size": leaf,
+            "leaf_tuning": tuning, "p_max": 4, "parts": b.stats["parts"],
         },
-        "bruteforce_gpu": {"value": pairs / t_bf, "unit": "pairs/s", "ms_per_sweep": t_bf * 1e3},
+        "build_ms": t_build * 1e3,
+        "eager_ms": t_eager,
+        "bruteforce_gpu": {"value": pairs / t_bf, "unit": "pairs/s", "ms": t_bf * 1e3},
         "speedup_vs_bruteforce": t_bf / t_step,
-        "phases_ms": {"build_tree": t_build * 1e3, "step_with_events_and_stats": t_step_prof * 1e3,
-                      **{f"kernel_{k}": v / args.steps for k, v in agg_ms.items() if not k.startswith("unused")}},
-        "traversal": {**{k: stats[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
-                                               "base_leaf_pairs", "base_point_pairs", "levels", "max_order",
-                                               "segments", "max_segment", "local_nodes", "max_local_ops")},
-                      "node_pairs_per_s": stats["node_pairs"] / (agg_ms.get("traverse", 0.0) / args.steps * 1e-3)
-                      if agg_ms.get("traverse", 0.0) > 0 else None,
-                      "us_per_level": agg_ms.get("traverse", 0.0) / args.steps / max(stats["levels"], 1) * 1e3},
+        "max_rel_err_vs_bruteforce": worst_bf,
+        "traversal": {k: st[k] for k in ("node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid",
+                                         "base_leaf_pairs", "base_point_pairs", "levels", "segments")},
         "roofline": roofline,
-        "base_case_tiles": {
-            "what": "one call with every leaf pair exhaustive (forced), bandwidth h*: the exhaustive-tile kernel "
-                    "(one block per query leaf), at the tuned leaf size and at leaf 32",
-            **{f"leaf_{bl}": {
-                "pairs": bc["pairs"], "k_etile_ms": bc["k_etile_ms"],
-                "pairs_per_s": bc["pairs"] / (bc["k_etile_ms"] * 1e-3),
-                "tflops": bc["pairs"] / (bc["k_etile_ms"] * 1e-3) * fpp / 1e12,
-                "frac_of_alu_peak": bc["pairs"] / (bc["k_etile_ms"] * 1e-3) / base_peak_pairs(d),
-            } for bl, bc in base_cases.items()},
-        },
-        "per_bandwidth": per_h,
         "grad_ms": None,
     }
 
-    if not args.no_batched:
-        out["batched"] = batched_bench(torch, dfgt, synth, args.leaf)
-    if not args.no_grad:
-        out["grad_ms"], out["grad"] = grad_bench(args, torch, dfgt, synth)
+    import oracle
 
     if not args.no_cpu_baseline:
-        import oracle
-
-        # rate estimate: one untimed call starts the oracle's threads, then a small sample over
-        # every bandwidth (the cost per pair depends on h)
-        oracle.naive_kde_rows(x_host, synth.subsample(x_host, 64, 98), x_host, hs[3])
-        rng_rows = synth.subsample(x_host, 256, 99)
+        # the oracle on the host cores over seeded query rows of every problem, each row against all its
+        # references at all 128 bandwidths; the same rows check the replay's sums
+        oracle.naive_kde_rows(xs[0], synth.subsample(xs[0], 16, 97), xs[0], 0.01)
         t0 = time.perf_counter()
-        for h in hs:
-            oracle.naive_kde_rows(x_host, rng_rows, x_host, h)
-        rate = len(rng_rows) * n * len(hs) / max(time.perf_counter() - t0, 1e-6)
-        m = int(min(n, max(64, args.cpu_seconds * rate / (n * len(hs)))))
-        rows = synth.subsample(x_host, m, 100)
-        t0 = time.perf_counter()
-        ref = np.stack([oracle.naive_kde_rows(x_host, rows, x_host, h) for h in hs])
+        worst, npairs = 0.0, 0.0
+        for k, (x, (t, _, h), G) in enumerate(zip(xs, probs, b.G)):
+            rows = synth.subsample(x, args.cpu_rows, 90 + k)
+            ref = np.stack([oracle.naive_kde_rows(x, rows, x, hk) for hk in h])
+            Gs = G[:, torch.as_tensor(rows, device=G.device)].cpu().numpy()
+            worst = max(worst, rel_err(Gs, ref))
+            npairs += len(rows) * x.shape[0] * len(h)
         t_cpu = time.perf_counter() - t0
-        Gs = G.cpu().numpy()[:, rows]
-        Gbs = Gb.cpu().numpy()[:, rows]
         out["cpu_baseline"] = {
-            "value": m * n * len(hs) / t_cpu, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{m} query rows x {n} references x {len(hs)} bandwidths (seeded subsample), {t_cpu:.1f} s",
+            "value": npairs / t_cpu, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{args.cpu_rows} seeded query rows per problem x all its references x all 128 bandwidths "
+                      f"(8 problems), {t_cpu:.1f} s",
         }
-        out["max_rel_err_sampled"] = {"dfgt": float(np.max(np.abs(Gs - ref) / ref)),
-                                      "bruteforce_gpu": float(np.max(np.abs(Gbs - ref) / ref)),
-                                      "rows": m}
+        out["max_rel_err_oracle"] = {"value": worst, "rows_per_problem": args.cpu_rows, "bandwidths": 128}
+
+    if not args.no_secondary:
+        xh2, hs2, G2, c2 = c2_bench(torch, dfgt, synth, args)
+        rows2 = synth.subsample(xh2, 400, 28)
+        ref2 = np.stack([oracle.naive_kde_rows(xh2, rows2, xh2, h) for h in hs2])
+        c2["max_rel_err_oracle"] = {"value": rel_err(G2.cpu().numpy()[:, rows2], ref2), "rows": len(rows2)}
+        out["c2"] = c2
+        out["c3"] = c3_bench(torch, dfgt, synth, oracle)
+        out["grad_ms"], out["grad"] = grad_bench(args, torch, dfgt, synth, oracle)
     print(json.dumps(out), flush=True)
 
 

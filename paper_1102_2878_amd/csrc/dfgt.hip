@@ -671,6 +671,81 @@ __device__ __forceinline__ double coef_beta(int i, int d, int pmax) {
     return (bs & 1) ? -f : f;
 }
 
+// Direct local accumulation (D ops, value sums) at the default (D, p_max) of
+// D = 1..5 as a contraction over points: with F_j[f] = e_j prod_{k<D-1}
+// H_{f_k}(t_jk) (f the digits of axes 0..D-2) and B_j[l] = H_l(t_j,D-1), the
+// coefficient beta = f p_max + l gets c_beta sum_j F_j[f] B_j[l], one
+// multiply-add per point and coefficient (the general loop takes D loads and
+// products).  Points go 32 at a time: lane j builds F_j and B_j in registers
+// and stores them to the wave's scratch (32 (PM^(D-1) + PM) doubles, within the
+// general loop's 64 D PM); lanes then take coefficients.  The products and
+// their order per point are the general loop's: ((e H_0) H_1 ...) H_{D-1}.
+__host__ __device__ inline int direct_kind(int d, int pmax) {
+    if ((d == 1 || d == 2) && pmax == 6) return d;
+    if (d == 3 && pmax == 4) return 3;
+    if ((d == 4 || d == 5) && pmax == 2) return d;
+    return 0;
+}
+
+template <int D, int PM>
+__device__ __forceinline__ void direct_op(const DevTree &R, int p, int rb, int re, const double *qc, double s, int P,
+                                          const unsigned short *mt, const double *cb, double *acc, double *Hx,
+                                          int lane) {
+    constexpr int NF = D == 1 ? 1 : (D == 2 ? PM : (D == 3 ? PM * PM : (D == 4 ? PM * PM * PM : PM * PM * PM * PM)));
+    double *Fx = Hx, *Bx = Hx + 32 * NF;
+    for (int x0 = rb; x0 < re; x0 += 32) {
+        const int cnt = min(32, re - x0);
+        if (lane < cnt) {
+            double t[D], tt = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                t[k] = (qc[k] - R.x[(size_t)(x0 + lane) * D + k]) * s;
+                tt += t[k] * t[k];
+            }
+            const double e = (tt > 745.0 ? 0.0 : exp(-tt)) * (R.w ? R.w[x0 + lane] : 1.0);
+            double H[D][PM];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                H[k][0] = 1.0;
+#pragma unroll
+                for (int b = 1; b < PM; ++b) {  // Hermite polynomials; orders >= p carry no term
+                    const double hb = b == 1 ? 2.0 * t[k] : 2.0 * t[k] * H[k][b - 1] - 2.0 * (b - 1) * H[k][b - 2];
+                    H[k][b] = hb;
+                }
+#pragma unroll
+                for (int b = 1; b < PM; ++b)
+                    if (b >= p) H[k][b] = 0.0;
+            }
+            double F[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                double v = e;
+                int rem = f, st = NF;
+#pragma unroll
+                for (int k = 0; k + 1 < D; ++k) {
+                    st /= PM;
+                    v *= H[k][rem / st];
+                    rem %= st;
+                }
+                F[f] = v;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Fx[lane * NF + f] = F[f];
+#pragma unroll
+            for (int b = 0; b < PM; ++b) Bx[lane * PM + b] = H[D - 1][b];
+        }
+        wave_sync();
+        for (int b = lane; b < P; b += 64) {
+            if ((mt[b] >> 8) >= p) continue;
+            const int f = b / PM, l = b - f * PM;
+            double sum = 0.0;
+            for (int j = 0; j < cnt; ++j) sum = fma(Fx[j * NF + f], Bx[j * PM + l], sum);
+            acc[b] += cb[b] * sum;
+        }
+        wave_sync();
+    }
+}
+
 // One D or T op applied by one wave to the local moments acc[P] about qc; a D
 // op covers reference points [rb, re) of node r.
 // With GR the wave also accumulates the tangent moments accB[P] that carry the
@@ -739,6 +814,16 @@ __device__ void wave_local_op(const DevTree &R, int r, int p, int m, int rb, int
         }
         wave_sync();
         return;
+    }
+    if constexpr (!GR) {
+        switch (direct_kind(d, pmax)) {
+        case 1: direct_op<1, 6>(R, p, rb, re, qc, s, P, mt, cb, acc, Hx, lane); return;
+        case 2: direct_op<2, 6>(R, p, rb, re, qc, s, P, mt, cb, acc, Hx, lane); return;
+        case 3: direct_op<3, 4>(R, p, rb, re, qc, s, P, mt, cb, acc, Hx, lane); return;
+        case 4: direct_op<4, 2>(R, p, rb, re, qc, s, P, mt, cb, acc, Hx, lane); return;
+        case 5: direct_op<5, 2>(R, p, rb, re, qc, s, P, mt, cb, acc, Hx, lane); return;
+        default: break;
+        }
     }
     for (int x0 = rb; x0 < re; x0 += 64) {
         const int cnt = min(64, re - x0);
