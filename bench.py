@@ -20,7 +20,8 @@ Secondary workloads in the same line:
         per step, the brute force, single-bandwidth calls (DFGT, the DFD
         ablation, brute force) and every leaf pair forced exhaustive;
   c3    5-D, 100,000 points, the same 7 scales of its h*, expansion orders 6
-        and 2 per dimension at eps 1e-2 and 1e-4, beside the brute force;
+        and 2 per dimension at eps 1e-2 and 1e-4 (leaf size tuned per order),
+        beside the brute force;
   grad  16-D, 200,000 points, eps 1e-4: dfgt_lscv_score with dCV/dh plus the
         dG/dq backward (grad_ms).
 Every workload's error is checked against the oracle's exact sums on seeded
@@ -212,12 +213,14 @@ def c3_bench(torch, dfgt, synth, oracle):
     out = {"workload": "5-D correlated mixture + 5% Student-t outliers, 100,000 points (Q = R), 7 bandwidths "
                        "h* x 10^-3..10^3", "h_star": hstar, "bruteforce_ms": t_bf, "rows": []}
     for pmax in (6, 2):
-        R = dfgt.build_tree(x, p_max=pmax)
+        leaf, _ = dfgt.tune_leaf_size(x, hs, 1e-2, reps=1, p_max=pmax)
+        R = dfgt.build_tree(x, p_max=pmax, leaf_size=leaf)
         for eps in (1e-2, 1e-4):
             ms = median_ms(torch, lambda: dfgt.gauss_sum(R, R, hs, eps))
             G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True)
             err = rel_err(G.cpu().numpy()[:, rows], ref)
-            out["rows"].append({"p_max": pmax, "eps": eps, "ms": ms, "speedup_vs_bruteforce": t_bf / ms,
+            out["rows"].append({"p_max": pmax, "eps": eps, "leaf_size": leaf, "ms": ms,
+                                "speedup_vs_bruteforce": t_bf / ms,
                                 "max_rel_err_oracle": err, "oracle_rows": len(rows),
                                 "base_point_pairs": st["base_point_pairs"], "max_order": st["max_order"]})
     return out

@@ -68,13 +68,15 @@ typedef struct dfgt_options {
                              launches on the caller's stream and reports the
                              per-kernel time in dfgt_stats (adds a few us per
                              launch); 0: off */
-    float cost_exhaustive; /* weight of the exhaustive cost c_E = D N_Q N_R in
-                              ChooseBestMethod (Section 3.8) relative to the
-                              series costs; 0 = 1, the paper's model.  Smaller
-                              values reflect that an exhaustive pair costs less
-                              on the GPU than a series term.  Any value keeps
-                              the error guarantee (it only picks among methods
-                              whose bounds hold) */
+    float cost_exhaustive; /* multiplier of the exhaustive cost c_E = D N_Q N_R in
+                              ChooseBestMethod (Section 3.8); 0 = 1.  The series
+                              costs carry this GPU's measured weights per unit
+                              (far-field 2, direct local 3, far-to-local 3 in
+                              exhaustive pairs; 50, 320, 50 when p_max^D > 512);
+                              with all weights 1 the model is the paper's.
+                              Smaller values choose exhaustive sums more often.
+                              Any value keeps the error guarantee (it only picks
+                              among methods whose bounds hold) */
     int32_t reserved[2];  /* must be zero */
 } dfgt_options;
 
@@ -99,6 +101,11 @@ typedef struct dfgt_stats {
     int64_t parts;          /* job parts the call ran in turn (the jobs of a call
                                whose traversal buffers would exceed the memory
                                budget are split; 1 = not split) */
+    int64_t work_f;         /* algorithmic work of the pruned pairs (the cost
+                               formulas of ChooseBestMethod, Section 3.8, without
+                               their factor D): far-field sum N_Q p^D, */
+    int64_t work_d;         /* direct local sum N_R p^D, */
+    int64_t work_t;         /* far-to-local sum D p^2D (order >= 2) */
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,

@@ -58,6 +58,7 @@ struct Job {
     double *out;               // caller's output for this job (caller order)
     double *outH, *outQ;       // gradient mode: dG/dh [N_Q] and dG/dq [N_Q][D] (caller order), or null
     double cost_e;             // weight of the exhaustive cost in ChooseBestMethod
+    double wF, wD, wT;         // GPU weights of the far-field, direct-local and far-to-local costs
     int mono;                  // Q and R are the same point set
     int loo;                   // leave-one-out: Q = R and each query's own point is left out of its sum
     double a32;                // largest |a| + |b| (sig units, coordinates relative to the query
@@ -121,6 +122,9 @@ enum {
     S_SEGS,
     S_MAXSEG,
     S_MAXLOPS,
+    S_FW,  // algorithmic work of the pruned pairs: F sum N_Q p^D, D sum N_R p^D, T sum D p^2D
+    S_DW,
+    S_TW,
     S_N
 };
 
@@ -227,7 +231,8 @@ __device__ __forceinline__ PairGeom pair_geom(const DevTree &Q, int q, const Dev
 // the centroid form is not used; F is unchanged (its derivative series is the
 // far-field series of the derivative kernel, one Hermite index higher).
 __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, double nQ, double nR, double wR,
-                      double tau, int pmax, int D, int force, int gr, double cost_e, int *order, double *kc_out) {
+                      double tau, int pmax, int D, int force, int gr, const Job &jb, int *order, double *kc_out) {
+    const double cost_e = jb.cost_e;
     if (force == DFGT_FORCE_EXACT) {
         *order = 0;
         return METH_E;
@@ -265,9 +270,9 @@ __device__ int choose(const PairGeom &g, double h, double inv2h2, double ku, dou
         pT = centroid ? 1 : 0;
     }
     const double inf = INFINITY;
-    const double cF = pF ? D * nQ * powi((double)pF, D) : inf;
-    const double cD = pD ? D * nR * powi((double)pD, D) : inf;
-    const double cT = pT ? D * powi((double)pT, 2 * D) : inf;
+    const double cF = pF ? jb.wF * D * nQ * powi((double)pF, D) : inf;
+    const double cD = pD ? jb.wD * D * nR * powi((double)pD, D) : inf;
+    const double cT = pT ? jb.wT * D * powi((double)pT, 2 * D) : inf;
     const double cE = cost_e * D * nQ * nR;
     const double mn = fmin(fmin(cF, cD), fmin(cT, cE));
     if (pF && cF == mn) {
@@ -324,7 +329,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 // (one per segment would cost ~20 ns each at thousands of segments a level).
 constexpr int kTravWaves = 4;
 enum { R_EOP = 0, R_EGRP, R_FOP, R_FGRP, R_LOP, R_LGRP, R_PAIR, R_SEG, R_N };
-enum { T_PAIRS = 0, T_SEGS, T_F, T_D, T_T, T_C, T_BLEAF, T_BPTS, T_N };  // block-summed statistics
+enum { T_PAIRS = 0, T_SEGS, T_F, T_D, T_T, T_C, T_BLEAF, T_BPTS, T_FW, T_DW, T_TW, T_N };  // block-summed statistics
 
 struct TravShared {
     int req[kTravWaves][R_N];  // per-wave requests, then per-wave bases
@@ -384,7 +389,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
 
     // 2. decisions and counts
     int cE = 0, cF = 0, cL = 0, cN = 0, nT = 0, nC = 0, nD = 0, maxord = 0;
-    double plo = 0.0, ept = 0.0, ccon = 0.0;
+    double plo = 0.0, ept = 0.0, ccon = 0.0, wkF = 0.0, wkD = 0.0, wkT = 0.0;
     for (int i = lane; i < sg.count; i += 64) {
         const bool first = i < 64;
         const int r = first ? r0 : pairs[sg.start + i];
@@ -395,13 +400,19 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         const double ku = first ? ku0 : kus[sg.start + i];
         int ord = 0;
         double kc = 0.0;
-        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, wR, tau, pmax, D, force, gr, jb.cost_e, &ord, &kc);
+        const int m = choose(g, jb.h, jb.inv2h2, ku, nQ, nR, wR, tau, pmax, D, force, gr, jb, &ord, &kc);
         const bool rleaf = (first ? left0 : R.left[r]) < 0;
         const bool self = jb.loo && r == q;
         if (m != METH_E) {
             plo += (self ? wR - 1.0 : wR) * ku;
             // the approximation covers every query's own point (K = 1): left out here
             if (self) ccon -= 1.0;
+            if (o.want_stats) {
+                const double pd = powi((double)ord, D);
+                if (m == METH_F) wkF += nQ * pd;
+                else if (m == METH_D) wkD += nR * pd;
+                else if (ord > 1) wkT += D * pd * pd;
+            }
             if (m == METH_F) ++cF;
             else if (m == METH_T && ord == 1) {
                 // order-1 far-to-local translation (the centroid form): its only
@@ -437,6 +448,11 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
     plo = wave_sum(plo);
     ept = wave_sum(ept);
     ccon = wave_sum(ccon);
+    if (o.want_stats) {
+        wkF = wave_sum(wkF);
+        wkD = wave_sum(wkD);
+        wkT = wave_sum(wkT);
+    }
     const double gl_child = sg.gl + plo * (1.0 - 1e-12);
     const int nFp = wave_sum_i(cF), nDp = wave_sum_i(nD), nTp = wave_sum_i(nT), nCp = wave_sum_i(nC);
     const int mo = wave_max_i(maxord);
@@ -472,6 +488,9 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
             t[T_C] = (unsigned long long)nCp;
             t[T_BLEAF] = (unsigned long long)tE;
             t[T_BPTS] = (unsigned long long)(nQ * ept);
+            t[T_FW] = (unsigned long long)wkF;
+            t[T_DW] = (unsigned long long)wkD;
+            t[T_TW] = (unsigned long long)wkT;
             sh.maxseg[wv] = valid ? (unsigned long long)sg.count : 0ull;
             sh.maxord[wv] = (unsigned long long)mo;
         }
@@ -502,7 +521,7 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
         const int c = threadIdx.x - 64;
         unsigned long long tot = 0;
         for (int w = 0; w < kTravWaves; ++w) tot += sh.st[w][c];
-        const int sidx[T_N] = {S_PAIRS, S_SEGS, S_F, S_D, S_T, S_C, S_BLEAF, S_BPTS};
+        const int sidx[T_N] = {S_PAIRS, S_SEGS, S_F, S_D, S_T, S_C, S_BLEAF, S_BPTS, S_FW, S_DW, S_TW};
         if (tot) atomicAdd(&o.stats[sidx[c] * SP], tot);
     } else if (o.want_stats && threadIdx.x == 64 + T_N) {
         unsigned long long ms = 0, mx = 0;
@@ -2889,6 +2908,19 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     // a query leaf's own local ops are applied inside k_leaf when its per-wave
     // scratch fits; otherwise they go through the node kernels
     pl.leaf_local = pl.P <= 512;
+    // Cost of a unit of each summarisation method relative to one exhaustive
+    // pair on this GPU.  calibrate_costs.py times forced-method calls with HIP
+    // events over their work counters: far-field evaluation 1.9-5.7 per query x
+    // coefficient, direct local accumulation 4.2-7.0 per point x coefficient
+    // for p_max^D <= 512 (D = 2, 3, 5); with larger coefficient vectors (the
+    // global-memory local-op kernel) 26, 163 and 23 for translation.  Those
+    // per-unit times include fixed costs that do not scale with the work, and
+    // whole-workload timings (2-D sweep, 3-D batch, 5-D at orders 2 and 6)
+    // are fastest at about half the small-vector figures and twice the large
+    // ones.  Any weights keep the error guarantee: they only choose among
+    // methods whose bounds hold.
+    const double wF = pl.leaf_local ? 2.0 : 50.0, wD = pl.leaf_local ? 3.0 : 320.0,
+                 wT = pl.leaf_local ? 3.0 : 50.0;
     if (pl.gr && !pl.leaf_local) {
         set_error("dfgt_gauss_sum_grad: gradients need p_max^d <= 512");
         return DFGT_EINVAL;
@@ -2930,6 +2962,9 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.outH = pl.gr && grad->dGdh ? grad->dGdh + (size_t)k * q.Q->n : nullptr;
             j.outQ = pl.gr && grad->dGdq ? grad->dGdq + (size_t)k * q.Q->n * pl.d : nullptr;
             j.cost_e = cost_e;
+            j.wF = wF;
+            j.wD = wD;
+            j.wT = wT;
             j.mono = q.Q == q.R && !q.R->weighted && !loo ? 1 : 0;  // the self term bounds G below by 1
             j.loo = loo ? 1 : 0;
             pl.loo = pl.loo || loo;
@@ -3330,6 +3365,9 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
     out->max_segment = (int64_t)sv[S_MAXSEG];
     out->local_nodes = c[C_LNODE];
     out->max_local_ops = (int64_t)sv[S_MAXLOPS];
+    out->work_f = (int64_t)sv[S_FW];
+    out->work_d = (int64_t)sv[S_DW];
+    out->work_t = (int64_t)sv[S_TW];
     out->mfma_tiles = pl.emfma ? 1 : 0;
     if (prof && prof->on) prof->collect(out);
     return DFGT_OK;
@@ -3405,6 +3443,9 @@ void add_stats(dfgt_stats *a, const dfgt_stats &b) {
     a->local_nodes += b.local_nodes;
     a->max_local_ops = std::max(a->max_local_ops, b.max_local_ops);
     a->mfma_tiles += b.mfma_tiles;
+    a->work_f += b.work_f;
+    a->work_d += b.work_d;
+    a->work_t += b.work_t;
     for (int k = 0; k < 5; ++k) {
         a->kernel_ms[k] += b.kernel_ms[k];
         a->kernel_launches[k] += b.kernel_launches[k];

@@ -34,7 +34,7 @@ class Stats(C.Structure):
     _fields_ = [(nm, C.c_int64) for nm in (
         "node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid", "base_leaf_pairs",
         "base_point_pairs", "levels", "max_order", "fp64_groups", "segments", "max_segment", "local_nodes",
-        "max_local_ops", "mfma_tiles", "parts")] + [("kernel_ms", C.c_double * 5),
+        "max_local_ops", "mfma_tiles", "parts", "work_f", "work_d", "work_t")] + [("kernel_ms", C.c_double * 5),
                                                                        ("kernel_launches", C.c_int64 * 5)]
     KERNELS = ("traverse", "leaf", "etile", "local", "etile_fp64")
 

@@ -32,10 +32,11 @@ def _rel_err(G, ref):
     return np.abs(G - ref) / ref
 
 
-def _run(dfgt, x, q, hs, eps, leaf=32, precision=0, force=0, pmax=0):
+def _run(dfgt, x, q, hs, eps, leaf=32, precision=0, force=0, pmax=0, ce=0.0):
     R = dfgt.build_tree(cuda(x), leaf_size=leaf, p_max=pmax)
     Q = R if q is None else dfgt.build_tree(cuda(q), leaf_size=leaf, p_max=pmax)
-    G, st = dfgt.gauss_sum(Q, R, hs, eps, precision=precision, force_method=force, stats=True)
+    G, st = dfgt.gauss_sum(Q, R, hs, eps, precision=precision, force_method=force, stats=True,
+                           cost_exhaustive=ce)
     return G.cpu().numpy(), st
 
 
@@ -127,7 +128,8 @@ def test_forced_far_field_each_dimension(dfgt, d, eps):
     x = synth.c3(n=3000, seed=29)[:, :d]
     hs = [synth.silverman_h(x) * s for s in (1.0, 10.0, 100.0)]
     note(f"dfgt force F d={d} eps={eps}")
-    G, st = _run(dfgt, x, None, hs, eps, force=1)
+    # exhaustive pairs priced high, so far-field evaluation is taken wherever its bound holds
+    G, st = _run(dfgt, x, None, hs, eps, force=1, ce=100.0)
     for k, h in enumerate(hs):
         rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
         assert rel.max() <= eps, (d, h, rel.max())
@@ -219,33 +221,40 @@ def test_five_dimensions_order_six(dfgt, eps):
     x = synth.c3(n=5000, seed=44)
     hs = [synth.silverman_h(x) * s for s in (0.3, 3.0, 30.0)]
     note(f"dfgt d=5 pmax=6 eps={eps}")
-    G, st = _run(dfgt, x, None, hs, eps, pmax=6)
+    R = dfgt.build_tree(cuda(x), p_max=6)
+    # exhaustive pairs priced high, so the traversal takes the high orders
+    G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True, cost_exhaustive=100.0)
+    G = G.cpu().numpy()
     for k, h in enumerate(hs):
         rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
         assert rel.max() <= eps, (h, rel.max())
     assert st["max_order"] >= 2
 
 
-@pytest.mark.parametrize("pmax,eps", [(6, 1e-2), (6, 1e-4), (2, 1e-2), (2, 1e-4)])
-def test_full_size_c3_sampled(dfgt, pmax, eps):
+@pytest.mark.parametrize("pmax,eps,ce", [(6, 1e-2, 0.0), (6, 1e-4, 0.0), (2, 1e-2, 0.0), (2, 1e-4, 0.0),
+                                         (6, 1e-2, 100.0), (6, 1e-4, 100.0)])
+def test_full_size_c3_sampled(dfgt, pmax, eps, ce):
     """The 5-D workload at full size: 100,000 points, the paper's seven
     bandwidths h* x 10^{-3..3}, expansion orders up to 6 per dimension (7,776
     coefficients) and the paper's default 2; 300 seeded query rows against all
-    references, within eps of the oracle."""
+    references, within eps of the oracle.  With the default cost weights (the
+    bench's configuration) and with exhaustive pairs priced 100 times higher,
+    which makes the traversal choose high-order expansions."""
     x = synth.c3()
     h0 = json.load(open(HSTAR))["c3"]["h_star"]
     hs = [h0 * s for s in SCALES]
     rows = synth.subsample(x, 300, 45)
-    note(f"dfgt c3 100k pmax={pmax} eps={eps}")
+    note(f"dfgt c3 100k pmax={pmax} eps={eps} cost_exhaustive={ce}")
     R = dfgt.build_tree(cuda(x), p_max=pmax)
-    G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True)
+    G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True, cost_exhaustive=ce)
     G = G.cpu().numpy()
     for k, h in enumerate(hs):
         ref = oracle.naive_kde_rows(x, rows, x, h)
         rel = _rel_err(G[k][rows], ref)
         assert rel.max() <= eps, (h, rel.max())
         assert np.all(np.isfinite(G[k]))
-    assert st["max_order"] >= 2
+    if ce > 0:
+        assert st["max_order"] >= 4, st["max_order"]
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 5])
