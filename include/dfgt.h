@@ -26,6 +26,7 @@
 #ifndef DFGT_H
 #define DFGT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -37,6 +38,9 @@ typedef enum dfgt_status {
     DFGT_EINVAL = 1, /* an argument is out of range (message says which) */
     DFGT_ENOMEM = 2, /* device or host allocation failed */
     DFGT_EHIP = 3,   /* a HIP runtime call failed */
+    DFGT_EQUEUE = 4, /* the traversal's lists outgrew their buffers after every retry
+                        (eager calls grow and rerun up to 12 times), or a captured
+                        batch's replay overflowed them (dfgt_batch_check) */
     DFGT_EBOUND = 5  /* the error guarantee cannot be certified for this input */
 } dfgt_status;
 
@@ -196,6 +200,38 @@ dfgt_status dfgt_tree_export(dfgt_tree t, int32_t *perm_host, double *lo_host, d
                              int32_t *begin_host, int32_t *end_host, int32_t *left_host,
                              int32_t *right_host, int32_t *split_dim_host,
                              double *split_coord_host);
+
+/*
+ * The tree's permutation on the device: perm_dev[k] = the caller's index of
+ * the k-th point in tree order (n int32, caller-allocated device memory).
+ * Enqueued on stream after the tree's own work (the tree's build stream
+ * is made to wait first when it differs).  Errors: NULL argument -> EINVAL.
+ */
+dfgt_status dfgt_tree_perm(dfgt_tree t, int32_t *perm_dev, void *stream);
+
+/*
+ * Device memory from the caller's allocator.  With alloc != NULL, the
+ * library's growing workspaces (traversal lists, per-node and per-query
+ * buffers, brute-force partials) and tree arenas come from
+ * alloc(bytes, ctx) and return through free(ptr, bytes, ctx) instead of
+ * hipMalloc / hipFree, e.g. torch's caching allocator, so that a caller's
+ * steady state allocates nothing from the runtime.  alloc must return device
+ * memory of the current device, 256-byte aligned, or NULL (-> DFGT_ENOMEM);
+ * both must be callable from any thread that calls the library.
+ * dfgt_set_allocator(NULL, NULL, NULL) goes back to hipMalloc for new
+ * buffers.  A buffer goes back through the free of the setting that made it
+ * only while that setting is still the current one: after any later
+ * dfgt_set_allocator call it is dropped without a free call, since the old
+ * allocator may no longer exist.  So call dfgt_release_workspace, and free
+ * trees built under the hook, before changing it.  dfgt_release_workspace
+ * waits for the device, then frees the calling thread's workspace buffers
+ * (traversal, sweep, brute-force and tree-build scratch); later calls
+ * allocate again.  Trees keep their own memory until dfgt_tree_free.
+ */
+typedef void *(*dfgt_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*dfgt_free_fn)(void *ptr, size_t bytes, void *ctx);
+dfgt_status dfgt_set_allocator(dfgt_alloc_fn alloc, dfgt_free_fn free_fn, void *ctx);
+dfgt_status dfgt_release_workspace(void);
 
 /*
  * Raw (bandwidth-free) far-field moments of every node (test hook):
@@ -442,8 +478,8 @@ dfgt_status dfgt_tune_leaf_size(const double *pts_dev, int64_t n, int32_t d, con
  * that owns its workspace.  dfgt_batch_run replays it asynchronously on
  * stream, rewriting every G_dev.  The trees, bandwidths and output buffers are
  * fixed at creation: keep them alive and unchanged until dfgt_batch_free.
- * dfgt_batch_check synchronises the stream and reports DFGT_EBOUND if the
- * last run overflowed its buffers (which unchanged inputs cannot cause).
+ * dfgt_batch_check synchronises the stream and reports DFGT_EQUEUE if any part
+ * of the last run overflowed its buffers (which unchanged inputs cannot cause).
  */
 typedef struct dfgt_batch_s *dfgt_batch;
 dfgt_status dfgt_batch_create(const dfgt_problem *probs, int32_t n_probs, double eps, const dfgt_options *opt,

@@ -18,6 +18,16 @@ thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
+namespace {
+std::mutex g_hook_mu;
+AllocHook g_hook;
+}  // namespace
+
+AllocHook alloc_hook() {
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    return g_hook;
+}
+
 int default_pmax(int d) {
     // p_max of the paper's experiments (Section 3.9)
     if (d <= 2) return 6;
@@ -78,6 +88,10 @@ constexpr size_t kPoolMaxBytes = size_t(2) << 30;
 
 void pool_put(DevBuf &b, hipStream_t st) {
     if (!b.p) return;
+    if (b.hfree) {  // memory of the caller's allocator goes back to it, not to the pool
+        b.release();
+        return;
+    }
     ArenaPool &pl = arena_pool();
     std::lock_guard<std::mutex> lk(pl.mu);
     hipEvent_t ev = nullptr;
@@ -162,16 +176,17 @@ __global__ __launch_bounds__(256) void k_check_weights(const double *__restrict_
 
 // *bad: 0 fine, 1 a negative or non-finite weight, 2 all weights zero; *wmax
 // the largest weight.
+static thread_local DevBuf g_wcheck;  // check_weights' flag and maximum
+
 static dfgt_status check_weights(const double *w, int64_t n, hipStream_t st, int *bad, double *wmax) {
     struct Out {
         int flag;
         int pad;
         unsigned long long mx;
     };
-    static thread_local DevBuf buf;
     static thread_local Out back;
-    DFGT_TRY(buf.reserve(sizeof(Out)));
-    Out *o = buf.as<Out>();
+    DFGT_TRY(g_wcheck.reserve(sizeof(Out)));
+    Out *o = g_wcheck.as<Out>();
     DFGT_HIP(hipMemsetAsync(o, 0, sizeof(Out), st));
     const long long nb = std::min<long long>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(k_check_weights, dim3((unsigned)nb), dim3(256), 0, st, w, (long long)n, &o->flag, &o->mx);
@@ -337,6 +352,47 @@ dfgt_status dfgt_tree_export(dfgt_tree t, int32_t *perm, double *lo, double *hi,
     };
     for (auto &it : items)
         if (it.dst) DFGT_HIP(hipMemcpy(it.dst, it.src->p, it.bytes, hipMemcpyDeviceToHost));
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_tree_perm(dfgt_tree t, int32_t *perm_dev, void *stream) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE(t != nullptr && perm_dev != nullptr, "dfgt_tree_perm: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (t->stream != st) {  // the tree's own work first
+        hipEvent_t ev;
+        DFGT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        const hipError_t e1 = hipEventRecord(ev, t->stream);
+        const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(st, ev, 0) : e1;
+        (void)hipEventDestroy(ev);
+        DFGT_HIP(e2);
+    }
+    DFGT_HIP(hipMemcpyAsync(perm_dev, t->perm.p, sizeof(int32_t) * (size_t)t->n, hipMemcpyDeviceToDevice, st));
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_set_allocator(dfgt_alloc_fn alloc, dfgt_free_fn free_fn, void *ctx) {
+    DFGT_GUARD_BEGIN
+    DFGT_REQUIRE((alloc == nullptr) == (free_fn == nullptr), "dfgt_set_allocator: give both functions or neither");
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    g_hook.alloc = alloc;
+    g_hook.free = free_fn;
+    g_hook.ctx = ctx;
+    g_hook.gen += 1;
+    return DFGT_OK;
+    DFGT_GUARD_END
+}
+
+dfgt_status dfgt_release_workspace(void) {
+    DFGT_GUARD_BEGIN
+    DFGT_HIP(hipDeviceSynchronize());  // no queued work may still use the buffers
+    release_sum_workspace();
+    release_sweep_workspace();
+    release_naive_workspace();
+    release_build_workspace();
+    g_wcheck.release();
     return DFGT_OK;
     DFGT_GUARD_END
 }

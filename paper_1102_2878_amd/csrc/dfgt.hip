@@ -3420,8 +3420,8 @@ dfgt_status run_plan(const Plan &pl, Workspace &w, int profile, dfgt_stats *stat
         }
     }
     if (overflow) {
-        set_error("dfgt_gauss_sum: traversal buffers could not be sized");
-        return DFGT_ENOMEM;
+        set_error("dfgt_gauss_sum: the traversal's lists outgrew their buffers after 12 retries");
+        return DFGT_EQUEUE;
     }
     if (stats_out) DFGT_TRY(fill_stats(pl, w, c, &prof, stats_out, st));
     return DFGT_OK;
@@ -3489,6 +3489,18 @@ dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *
 }
 
 }  // namespace
+
+void release_sum_workspace() {
+    Workspace &w = g_ws;
+    DevBuf *bufs[] = {&w.jobs, &w.trees, &w.jls, &w.L, &w.lflag, &w.heads, &w.segA, &w.segB, &w.pairA, &w.pairB,
+                      &w.dec, &w.kus, &w.egrp, &w.eops, &w.fgrp, &w.fops, &w.lgrp, &w.lops, &w.lnodes, &w.stats,
+                      &w.lscr, &w.pscr, &w.lopnode, &w.part, &w.extE, &w.extX, &w.extY, &w.stG, &w.stX, &w.stQ,
+                      &w.cval, &w.gdg, &w.gmt, &w.eord, &w.selfE, &w.selfG, &w.selfX, &w.selfY, &w.selfmin,
+                      &w.ctl, &w.sticky};
+    for (DevBuf *b : bufs) b->release();
+    w.cap = Caps{0, 0, 0, 0, 0, 0, 0};
+    w.part_jobs = 0;
+}
 
 dfgt_status run_gauss_multi(const Problem *pr, int np, double eps, int precision, int force, int profile,
                             double cost_e, const GradOut *grad, dfgt_stats *stats_out, hipStream_t st) {
@@ -3581,7 +3593,7 @@ dfgt_status batch_check(dfgt_batch_s *b, hipStream_t st) {
     DFGT_HIP(hipStreamSynchronize(st));
     if (overflow) {
         set_error("dfgt_batch: the last run overflowed its traversal buffers (were the trees changed?)");
-        return DFGT_EBOUND;
+        return DFGT_EQUEUE;
     }
     return DFGT_OK;
 }

@@ -50,25 +50,55 @@ struct Status {
     } while (0)
 
 // ---------------------------------------------------------------- device buffers
+// The caller's allocator (dfgt_set_allocator), or none: hipMalloc.  `gen`
+// changes with every dfgt_set_allocator call; a buffer goes back to the
+// allocator that made it only while that allocator is still the current one
+// (a buffer freed later, e.g. at process exit after the caller's allocator is
+// gone, is left to the process).
+struct AllocHook {
+    dfgt_alloc_fn alloc = nullptr;
+    dfgt_free_fn free = nullptr;
+    void *ctx = nullptr;
+    unsigned gen = 0;
+};
+AllocHook alloc_hook();
+
 // A device allocation owned by host code; freed in the destructor.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    dfgt_free_fn hfree = nullptr;  // set when the caller's allocator made p
+    void *hctx = nullptr;
+    unsigned hgen = 0;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (!hfree) (void)hipFree(p);
+            else if (alloc_hook().gen == hgen) hfree(p, bytes, hctx);
+        }
         p = nullptr;
         bytes = 0;
+        hfree = nullptr;
     }
     // Ensures at least `need` bytes (contents are not preserved on growth).
     dfgt_status reserve(size_t need) {
         if (need <= bytes) return DFGT_OK;
         release();
         size_t nb = need < 256 ? 256 : need;
-        if (hipMalloc(&p, nb) != hipSuccess) {
+        const AllocHook h = alloc_hook();
+        if (h.alloc) {
+            p = h.alloc(nb, h.ctx);
+            if (!p) {
+                set_error("the caller's allocator returned NULL for " + std::to_string(nb) + " bytes");
+                return DFGT_ENOMEM;
+            }
+            hfree = h.free;
+            hctx = h.ctx;
+            hgen = h.gen;
+        } else if (hipMalloc(&p, nb) != hipSuccess) {
             p = nullptr;
             set_error("hipMalloc of " + std::to_string(nb) + " bytes failed");
             return DFGT_ENOMEM;
@@ -271,6 +301,12 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 }
 
 // ---------------------------------------------------------------- host entry points per file
+// Frees the calling thread's workspace buffers of each file (dfgt_release_workspace).
+void release_sum_workspace();    // dfgt.hip
+void release_sweep_workspace();  // sweep.hip
+void release_naive_workspace();  // naive.hip
+void release_build_workspace();  // moments.hip
+
 // naive.hip
 dfgt_status launch_naive(const double *q, int64_t nq, const double *r, int64_t nr, int d,
                          const double *h, int nh, int precision, double *G, hipStream_t st);

@@ -327,6 +327,12 @@ __global__ void k_tree_sqnorm(const double *__restrict__ x, int n, int d, double
     out[i] = v;
 }
 
+// Per-node F2F scratch of the moment sweep when a level's tables do not fit in
+// LDS; reused across builds of a thread (freeing it would stall the device).
+static thread_local DevBuf g_mscratch;
+
+void release_build_workspace() { g_mscratch.release(); }
+
 dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     // Levels holding a node above kMomDirectMax points take chunked direct sums
     // (up to kMomLevels of them, and when (D, p_max) has a direct instance);
@@ -383,11 +389,10 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
     }
     const int skip = direct ? kMomDirectMax : 0;
     const bool lds = (size_t)(2 * P + pmax * pmax) * sizeof(double) <= 48 * 1024;
-    static thread_local DevBuf scratch;  // reused across builds (freeing it would stall the device)
     int maxw = 0;
     for (int l = 0; l + 1 < (int)t->level_start.size(); ++l)
         maxw = std::max(maxw, t->level_start[l + 1] - t->level_start[l]);
-    if (!lds) DFGT_TRY(scratch.reserve(sizeof(double) * (size_t)maxw * 2 * P));
+    if (!lds) DFGT_TRY(g_mscratch.reserve(sizeof(double) * (size_t)maxw * 2 * P));
     for (int l = t->depth - 2; l >= 0; --l) {
         const int lb = t->level_start[l], le = t->level_start[l + 1];
         if (le <= lb) continue;
@@ -401,7 +406,7 @@ dfgt_status compute_moments(dfgt_tree_s *t, hipStream_t st) {
             size_t sh = sizeof(double) * (pmax * pmax);
             hipLaunchKernelGGL(k_f2f<false>, dim3(le - lb), dim3(256), sh, st, lb, le, t->left.as<int32_t>(),
                                t->right.as<int32_t>(), t->begin.as<int32_t>(), t->end.as<int32_t>(), skip,
-                               t->ctr.as<double>(), d, pmax, P, t->mu.as<double>(), scratch.as<double>());
+                               t->ctr.as<double>(), d, pmax, P, t->mu.as<double>(), g_mscratch.as<double>());
         }
         DFGT_HIP(hipGetLastError());
     }

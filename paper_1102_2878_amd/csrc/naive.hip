@@ -492,6 +492,10 @@ dfgt_status launch_naive(const double *q, int64_t nq, const double *r, int64_t n
 
 size_t naive_noalloc_limit() { return kScratchDoubles; }
 
+void release_naive_workspace() {
+    for (DevBuf *b : {&g_part, &g_h, &g_qn, &g_rn, &g_mx}) b->release();
+}
+
 dfgt_status launch_naive_noalloc(const double *q, int64_t nq, const double *r, int64_t nr, int d,
                                  const double *h_host, int nh, int precision, double *G, hipStream_t st) {
     NaiveSpace sp;

@@ -119,6 +119,11 @@ dfgt_status run_backward(dfgt_tree_s *Q, dfgt_tree_s *R, const double *h, int nh
     return DFGT_OK;
 }
 
+void release_sweep_workspace() {
+    SweepWs &w = g_sw;
+    for (DevBuf *b : {&w.G, &w.dGdh, &w.dGdq, &w.part, &w.sums, &w.scale}) b->release();
+}
+
 dfgt_status run_vjp(int nh, int64_t nq, int d, const double *dG, const double *dGdh, const double *dGdq,
                     double *dh_host, double *dq, hipStream_t st) {
     if (dq) {

@@ -71,6 +71,9 @@ def lib():
                                      C.POINTER(i32)]
         L.dfgt_tree_export.argtypes = [vp] + [vp] * 9
         L.dfgt_tree_moments.argtypes = [vp, vp]
+        L.dfgt_tree_perm.argtypes = [vp, vp, vp]
+        L.dfgt_set_allocator.argtypes = [vp, vp, vp]
+        L.dfgt_release_workspace.argtypes = []
         L.dfgt_naive_sum.argtypes = [vp, i64, vp, i64, i32, C.POINTER(dbl), i32, i32, vp, vp]
         L.dfgt_naive_sum_noalloc.argtypes = [vp, i64, vp, i64, i32, C.POINTER(dbl), i32, i32, vp, vp]
         L.dfgt_gauss_sum.argtypes = [vp, vp, C.POINTER(dbl), i32, dbl, C.POINTER(Options), vp,
@@ -97,7 +100,8 @@ def lib():
         L.dfgt_batch_check.argtypes = [vp, vp]
         L.dfgt_batch_free.argtypes = [vp]
         for nm in ("dfgt_build_tree", "dfgt_build_tree_weighted", "dfgt_tree_free", "dfgt_tree_info", "dfgt_tree_export",
-                   "dfgt_tree_moments", "dfgt_naive_sum", "dfgt_naive_sum_noalloc", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
+                   "dfgt_tree_moments", "dfgt_tree_perm", "dfgt_set_allocator", "dfgt_release_workspace",
+                   "dfgt_naive_sum", "dfgt_naive_sum_noalloc", "dfgt_gauss_sum", "dfgt_gauss_sum_grad",
                    "dfgt_gauss_sum_backward", "dfgt_gauss_sum_vjp", "dfgt_lscv_score", "dfgt_lscv_optimize", "dfgt_gauss_sum_batched",
                    "dfgt_kde_density", "dfgt_lcv_score",
                    "dfgt_batch_create",
@@ -201,6 +205,49 @@ def tree_export(t: Tree):
     _check(lib().dfgt_tree_export(t.handle, *[out[k].ctypes.data_as(C.c_void_p) for k in order]))
     out["n_nodes"] = m
     return out
+
+
+def tree_perm(t: Tree):
+    """dfgt_tree_perm: the permutation as an (n,) int32 CUDA tensor (tree position -> caller index)."""
+    torch = _torch()
+    out = torch.empty(t.n, dtype=torch.int32, device="cuda")
+    _check(lib().dfgt_tree_perm(t.handle, C.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+_hooks = None
+
+
+def use_torch_allocator(on=True):
+    """dfgt_set_allocator with torch's caching allocator (on the current stream at
+    allocation time), or back to hipMalloc (on=False).  The library's workspaces
+    are released first, so no buffer outlives the allocator that made it; at
+    interpreter exit they are released and the hook removed."""
+    global _hooks
+    import atexit
+    torch = _torch()
+    _check(lib().dfgt_release_workspace())
+    if not on:
+        _check(lib().dfgt_set_allocator(None, None, None))
+        _hooks = None
+        return
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=torch.cuda.current_stream())
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))  # kept alive as long as the library may call them
+    _check(lib().dfgt_set_allocator(C.cast(hooks[0], C.c_void_p), C.cast(hooks[1], C.c_void_p), None))
+    if _hooks is None:
+        atexit.register(lambda: use_torch_allocator(False) if _hooks is not None else None)
+    _hooks = hooks
 
 
 def tree_moments(t: Tree):

@@ -180,3 +180,41 @@ def test_invalid_input_rejected(dfgt):
     x = np.array([[0.0, np.nan], [1.0, 2.0]])
     with pytest.raises(dfgt.DfgtError, match="non-finite"):
         dfgt.build_tree(cuda(x))
+
+
+def test_tree_perm_on_device():
+    from paper_1102_2878_amd import dfgt
+    x = synth.c2(n=20000, seed=91)
+    note("tree perm on device")
+    t = dfgt.build_tree(cuda(x), leaf_size=64)
+    perm = dfgt.tree_perm(t).cpu().numpy()
+    assert np.array_equal(perm, dfgt.tree_export(t)["perm"])
+    assert np.array_equal(np.sort(perm), np.arange(x.shape[0]))
+
+
+def test_caller_allocator():
+    """With torch's caching allocator installed, the sums' workspaces come from it
+    (torch's allocated bytes grow) and the results are bitwise those of the
+    hipMalloc workspaces; releasing the workspace returns the memory to torch."""
+    import torch
+
+    from paper_1102_2878_amd import dfgt
+    x = synth.c2(n=20000, seed=92)
+    hs = [synth.silverman_h(x) * s for s in (0.1, 1.0, 10.0)]
+    note("caller allocator")
+    t = dfgt.build_tree(cuda(x))
+    ref = dfgt.gauss_sum(t, t, hs, 1e-2).cpu().numpy()
+    torch.cuda.synchronize()
+    dfgt.use_torch_allocator(True)
+    try:
+        before = torch.cuda.memory_allocated()
+        G = dfgt.gauss_sum(t, t, hs, 1e-2).cpu().numpy()
+        during = torch.cuda.memory_allocated()
+        assert during > before + (1 << 20), (before, during)
+        assert G.tobytes() == ref.tobytes()
+        dfgt.lib().dfgt_release_workspace()
+        assert torch.cuda.memory_allocated() < during
+    finally:
+        dfgt.use_torch_allocator(False)
+    G2 = dfgt.gauss_sum(t, t, hs, 1e-2).cpu().numpy()
+    assert G2.tobytes() == ref.tobytes()
