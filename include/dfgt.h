@@ -110,6 +110,14 @@ typedef struct dfgt_stats {
                                their factor D): far-field sum N_Q p^D, */
     int64_t work_d;         /* direct local sum N_R p^D, */
     int64_t work_t;         /* far-to-local sum D p^2D (order >= 2) */
+    int64_t e_items[6];     /* (query leaf, bandwidth) items of the mixed exhaustive
+                               pass: [0] >= 64 reference leaves in the E list,
+                               [1] fewer, [2] none; for value sums with D <= 7
+                               (matrix-core tiles) [0], [1] count the items with
+                               FP32 products, [4], [5] those with FP64 products
+                               and [3] those whose query leaf is too wide against
+                               h for either (vector-ALU tiles); all 0 at
+                               precision FP64 or with D >= 8 */
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,

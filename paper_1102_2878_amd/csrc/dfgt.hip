@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "etile.h"
 #include "series.h"
@@ -64,6 +65,8 @@ struct Job {
     double a32;                // largest |a| + |b| (sig units, coordinates relative to the query
                                // leaf's centre) for which FP32 differences keep the exhaustive
                                // sums within their rounding budget; <= 0: FP64 differences only
+    double r32;                // largest query-leaf half-diagonal (sig units) for which the
+                               // matrix-core tiles' FP32 products keep that budget; <= 0: FP64
 };
 
 struct Seg {
@@ -100,6 +103,10 @@ enum {
     C_EHEAVY,   // (job, query leaf) items by exhaustive work: long lists, short lists, none
     C_ENORM,
     C_EEMPTY,
+    C_EWIDE,    // items left to the vector-ALU tiles by the matrix-core pass (query leaf wide against h)
+    C_EHEAVY64, // items of the matrix-core pass with FP64 products: long lists, short lists
+    C_ENORM64,
+    C_ECH,      // entries of the flattened E chains (k_eorder)
     C_N
 };
 
@@ -1821,65 +1828,129 @@ constexpr int kMaxEGrp = 256;  // E groups of one (job, node) chain (at most one
 
 constexpr int kEHeavyOps = 64; // an item with at least this many E ops (mixed pass) is dispatched first
 
+// Matrix-core exhaustive tiles (k_etile_mx*, below): block shape and the
+// query-leaf and reference radii (sig units) of their two product precisions.
+constexpr int kMxWaves = 8;
+constexpr int kMxOps = 64 * kMxWaves;  // E ops flattened per chunk: one per thread
+constexpr int kMxQ = 128;              // queries held per pass over the chain
+constexpr double kMxWideQ = 4096.0;    // 2^12
+constexpr double kMxFarB = 8192.0;     // 2^13
+constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 form
+
 // Dispatch order of the mixed pass's exhaustive tiles (longest first): the
 // items whose E chain holds >= kEHeavyOps ops of the mixed pass, then those
 // with fewer, then those with none.  A leaf with hundreds of reference leaves
 // keeps one block busy ~100 us; started in job order, such blocks began
-// midway through the launch and set its end.  One thread per item counts its
-// chain; each block appends its items to the three lists with one atomic per
-// list.  Which block takes an item does not change its sums.
+// midway through the launch and set its end.  lists holds six lists of
+// nitems entries: [0] heavy, [1] short, [2] none, and with mx (the
+// matrix-core pass) [3] items whose query leaf's half-diagonal exceeds
+// kMxWideQ in sig units (the vector-ALU tiles take them), [4] heavy and [5]
+// short items beyond Job::r32 (FP64 products); lists 0 and 1 then hold the
+// items with FP32 products.
+// One thread per item counts its chain and copies the (start, count) of its
+// mixed-pass groups, in chain order, to eglist at an offset reserved per block
+// (ehdr[item] = (offset, groups), offset -1 when eglist is full); each block
+// appends its items to the lists with one atomic per list.  Which block takes
+// an item does not change its sums.
 __global__ __launch_bounds__(256) void k_eorder(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                 const Group *__restrict__ egrp, const int *__restrict__ headE,
                                                 const int *__restrict__ overflow, const int *__restrict__ jlstart,
-                                                int njobs, int unl, int nitems, int *cnt, int *heavy, int *norm,
-                                                int *empty) {
-    __shared__ int wc[3][4], base[3];
+                                                int njobs, int unl, int nitems, int mx, int *cnt,
+                                                int *__restrict__ lists, int2 *__restrict__ ehdr,
+                                                int2 *__restrict__ eglist, int egcap) {
+    constexpr int NL = 6;
+    __shared__ int wc[NL][4], base[NL], wg[4], gbase;
     if (*overflow) return;
     const int item = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int ops = -1;  // -1: no item
+    int cls = -1;  // no item
+    int ng = 0;    // groups of the mixed pass in the item's chain
+    int head = -1;
     if (item < nitems) {
         int job, li;
         job_leaf(jlstart, njobs, unl, item, &job, &li);
         const Job jb = jobs[job];
         const DevTree &Q = trees[jb.qt];
-        ops = 0;
-        int n = 0;
-        for (int gi = headE[(size_t)jb.noff + Q.leaves[li]]; gi >= 0 && n < kMaxEGrp; ++n) {
+        const int leaf = Q.leaves[li];
+        head = headE[(size_t)jb.noff + leaf];
+        int ops = 0, n = 0;
+        for (int gi = head; gi >= 0 && n < kMaxEGrp; ++n) {
             const Group g = egrp[gi];
-            if (g.flags == 0) ops += g.count;
+            if (g.flags == 0) {
+                ops += g.count;
+                ++ng;
+            }
             gi = g.next;
         }
+        cls = ops >= kEHeavyOps ? 0 : (ops > 0 ? 1 : 2);
+        if (mx && ops > 0) {  // the query leaf's half-diagonal in sig units picks the form
+            double hd = 0.0;
+            for (int c = 0; c < Q.d; ++c) {
+                const double hw = 0.5 * (Q.hi[(size_t)leaf * Q.d + c] - Q.lo[(size_t)leaf * Q.d + c]);
+                hd = fma(hw, hw, hd);
+            }
+            const double rho = std::sqrt(hd) * jb.sig;
+            if (rho > kMxWideQ) cls = 3;
+            else if (!(rho <= jb.r32)) cls += 4;
+        }
     }
-    const int cls = ops < 0 ? -1 : (ops >= kEHeavyOps ? 0 : (ops > 0 ? 1 : 2));
-    int rk[3];
-    for (int c = 0; c < 3; ++c) {
+    int rk[NL];
+    for (int c = 0; c < NL; ++c) {
         const int f = cls == c ? 1 : 0;
         const int inc = wave_incl_scan(f);
         rk[c] = inc - f;
         if (lane == 63) wc[c][wv] = inc;
     }
+    const int incg = wave_incl_scan(ng);
+    if (lane == 63) wg[wv] = incg;
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < NL) {
         const int c = threadIdx.x;
         const int tot = wc[c][0] + wc[c][1] + wc[c][2] + wc[c][3];
         base[c] = tot ? atomicAdd(&cnt[(C_EHEAVY + c) * CP], tot) : 0;
+    } else if (threadIdx.x == 64) {
+        const int tot = wg[0] + wg[1] + wg[2] + wg[3];
+        gbase = tot ? atomicAdd(&cnt[C_ECH * CP], tot) : 0;
     }
     __syncthreads();
     if (cls >= 0) {
         int off = base[cls] + rk[cls];
         for (int w = 0; w < wv; ++w) off += wc[cls][w];
-        (cls == 0 ? heavy : (cls == 1 ? norm : empty))[off] = item;
+        lists[(size_t)cls * nitems + off] = item;
+        // the chain's groups of the mixed pass, flattened in chain order, so
+        // the tile kernels read them at once instead of following the links
+        int go = gbase + incg - ng;
+        for (int w = 0; w < wv; ++w) go += wg[w];
+        if (go + ng <= egcap) {
+            int k = 0, n = 0;
+            for (int gi = head; gi >= 0 && n < kMaxEGrp; ++n) {
+                const Group g = egrp[gi];
+                if (g.flags == 0) eglist[go + k++] = make_int2(g.start, g.count);
+                gi = g.next;
+            }
+            ehdr[item] = make_int2(go, ng);
+        } else {
+            ehdr[item] = make_int2(-1, 0);  // list full: the kernels follow the links
+        }
     }
 }
 
 // Item of block b of the mixed pass in that order (order = null: in turn);
-// order holds the three lists, nitems entries each.
+// order holds k_eorder's six lists, nitems entries each.  sel = 0 takes lists
+// 0, 1, 2 in turn, sel = 1 list 3, sel = 2 lists 4, 5; -1: no item.
 __device__ __forceinline__ int etile_item(int b, const int *__restrict__ cnt, const int *__restrict__ order,
-                                          int nitems) {
+                                          int nitems, int sel) {
     if (!order) return b;
-    const int nh = cnt[C_EHEAVY * CP], nn = cnt[C_ENORM * CP];
-    return b < nh ? order[b] : (b < nh + nn ? order[nitems + b - nh] : order[2 * nitems + b - nh - nn]);
+    if (sel == 1) return b < cnt[C_EWIDE * CP] ? order[3 * (size_t)nitems + b] : -1;
+    if (sel == 2) {
+        const int nh = cnt[C_EHEAVY64 * CP], nn = cnt[C_ENORM64 * CP];
+        if (b < nh) return order[4 * (size_t)nitems + b];
+        return b < nh + nn ? order[5 * (size_t)nitems + b - nh] : -1;
+    }
+    const int nh = cnt[C_EHEAVY * CP], nn = cnt[C_ENORM * CP], ne = cnt[C_EEMPTY * CP];
+    if (b < nh) return order[b];
+    if (b < nh + nn) return order[nitems + b - nh];
+    return b < nh + nn + ne ? order[2 * (size_t)nitems + b - nh - nn] : -1;
 }
 
 // ---------------------------------------------------------------- exhaustive tiles on the vector ALUs
@@ -2086,7 +2157,7 @@ __device__ __forceinline__ void etile_body(const DevTree *__restrict__ trees, co
                                            const int *__restrict__ headE, const int *__restrict__ cnt_dev,
                                            const int *__restrict__ overflow, const int *__restrict__ jlstart,
                                            int njobs, int unl, int precision, const int *__restrict__ order,
-                                           int nitems, double *__restrict__ GE, double *__restrict__ GX,
+                                           int nitems, int sel, double *__restrict__ GE, double *__restrict__ GX,
                                            double *__restrict__ GY) {
     using Sh = ETileShape<DT, F64>;
     constexpr int DS = Sh::DS, QPT = Sh::QPT;
@@ -2112,8 +2183,10 @@ __device__ __forceinline__ void etile_body(const DevTree *__restrict__ trees, co
     // the FP64 pass of a mixed-precision call has work only if the guard flagged a group
     if (F64 && !all64 && cnt_dev[C_EF64 * CP] == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int item = etile_item(blockIdx.x, cnt_dev, order, nitems, sel);
+    if (item < 0) return;
     int job, li;
-    job_leaf(jlstart, njobs, unl, etile_item(blockIdx.x, cnt_dev, order, nitems), &job, &li);
+    job_leaf(jlstart, njobs, unl, item, &job, &li);
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
@@ -2316,10 +2389,10 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
                                                         const int *__restrict__ overflow,
                                                         const int *__restrict__ jlstart, int njobs, int unl,
                                                         int precision, const int *__restrict__ order, int nitems,
-                                                        double *__restrict__ GE, double *__restrict__ GX,
+                                                        int sel, double *__restrict__ GE, double *__restrict__ GX,
                                                         double *__restrict__ GY) {
     etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, precision,
-                            order, nitems, GE, GX, GY);
+                            order, nitems, sel, GE, GX, GY);
 }
 
 // The 3-D mixed-precision value pass, held to 128 VGPRs (four waves per SIMD,
@@ -2330,11 +2403,366 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
     const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Group *__restrict__ egrp,
     const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,
     const int *__restrict__ overflow, const int *__restrict__ jlstart, int njobs, int unl, int precision,
-    const int *__restrict__ order, int nitems, double *__restrict__ GE, double *__restrict__ GX,
+    const int *__restrict__ order, int nitems, int sel, double *__restrict__ GE, double *__restrict__ GX,
     double *__restrict__ GY) {
     etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, precision,
-                            order, nitems, GE, GX, GY);
+                            order, nitems, sel, GE, GX, GY);
 }
+
+// ---------------------------------------------------------------- exhaustive tiles on the matrix cores, D <= 7
+// The mixed pass of the value sums (DFGTBase, Section 3.9) as a contraction.
+// Coordinates are taken relative to the query leaf's box centre c and scaled
+// by sig: a = sig (q - c), b = sig (r - c), so that t = |a - b|^2 and the
+// kernel value is 2^-t.  With the K = 4 NC operand rows
+//     A_i = (a_i, 1, 0, ...),   B_j = (2 b_j, -|b_j|^2, 0, ...),   C_i = -|a_i|^2
+// NC v_mfma_*_16x16x4 instructions give -t for a block of 16 queries x 16
+// references.  The lanes take the hardware exp2 of -t (rounded to FP32 once
+// in the FP64 form) and add w_j 2^-t into FP32 partials of <= 64 terms; the
+// partials are reduced across lanes and added in FP64, in a fixed order.
+// Two precisions of the product, chosen per item by k_eorder from the query
+// leaf's half-diagonal rho in sig units:
+//   FP32 (rho <= Job::r32): a reference is staged only when
+//     |b| <= rho + 12; the others have t >= 144 (terms below the FP32 flush
+//     the mixed sums already allow for) and are staged with weight 0.  Then
+//     A = |a| + |b| <= 2 rho + 12, and the FP32 rounding of the operands and
+//     of the four multiply-adds moves t by at most 6.5 u A^2 (u = 2^-24);
+//     r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) + 64 u (weight, partials)
+//     within the rounding budget.
+//   FP64 (rho <= kMxWideQ): a reference with |b| > kMxFarB is staged with
+//     weight 0 (t >= (kMxFarB - kMxWideQ)^2 = 2^24); the FP64 rounding of t,
+//     ~12 2^-53 A^2 with A <= 3 2^12, stays below 2e-7, under the FP32
+//     rounding of t itself.
+//   Wider leaves go to the vector-ALU tiles.
+// One block of kMxWaves waves per (job, query leaf) item, taken in the order
+// k_eorder made (heavy items first); the item's chain comes flattened from
+// k_eorder.  The leaf's queries, kMxQ at a time, are held as operands by the
+// waves: up to 4 blocks of 16 by every wave, or, with more blocks, the first
+// half by waves 0-3 and the rest by waves 4-7.  The E chain is flattened
+// kMxOps ops at a time into one list of reference points (only the groups of
+// this pass: those the underflow guard flagged go to the FP64 pass); the
+// block stages RND of them at a time in LDS as operand rows (structure of
+// arrays: lane l reads row 4c + l / 16 of point l % 16, conflict-free), and
+// the waves holding a set of query blocks take the round's 16-point blocks in
+// turn.
+// Operand layouts of v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32 (lane l,
+// g = l / 16): A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k; result
+// register r holds D[4 r + g][l % 16] (FP64) or D[4 g + r][l % 16] (FP32).
+// Here A = 16 queries x 4 rows, B = 4 rows x 16 references.
+
+template <typename T, int NC>
+struct MxShape {
+    static constexpr int K = 4 * NC;                 // operand rows
+    static constexpr int RND = NC == 1 ? 1024 : 512;  // staged reference points per round
+};
+template <typename T>
+struct MxVec;
+template <>
+struct MxVec<double> {
+    typedef v4d type;
+    __device__ static type mfma(double a, double b, type c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int r, int g) { return 4 * r + g; }
+};
+template <>
+struct MxVec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    __device__ static type mfma(float a, float b, type c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int r, int g) { return 4 * g + r; }
+};
+
+template <typename T, int NC>
+__device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                              const Group *__restrict__ egrp, const int *__restrict__ eops,
+                                              const int *__restrict__ headE, const int *__restrict__ cnt_dev,
+                                              const int *__restrict__ overflow, const int *__restrict__ jlstart,
+                                              int njobs, int unl, const int *__restrict__ order, int nitems,
+                                              int sel, const int2 *__restrict__ ehdr,
+                                              const int2 *__restrict__ eglist, double *__restrict__ GE) {
+    constexpr int K = MxShape<T, NC>::K, RND = MxShape<T, NC>::RND;
+    typedef MxVec<T> V;
+    typedef typename V::type VT;
+    __shared__ int gS[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
+    __shared__ int oB[kMxOps], oCum[kMxOps];
+    __shared__ int wsum[kMxWaves], nops_s, take_s;
+    __shared__ T sB[K][RND];              // reference operand rows of the round
+    __shared__ float sW[RND];             // reference weights (0: padding or a zero term)
+    __shared__ double sA[K][kMxQ];        // query operand rows of the pass
+    __shared__ double sN[kMxQ];           // |a|^2 of the pass's queries
+    __shared__ double sQ[kMxWaves][64];   // per-wave FP64 sums per query of its set
+    if (*overflow) return;
+    const int item = etile_item(blockIdx.x, cnt_dev, order, nitems, sel);
+    if (item < 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, col = lane & 15;
+    int job, li;
+    job_leaf(jlstart, njobs, unl, item, &job, &li);
+    const Job jb = jobs[job];
+    const DevTree &Q = trees[jb.qt];
+    const DevTree &R = trees[jb.rt];
+    const int leaf = Q.leaves[li];
+    const int d = Q.d;
+    const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
+    const size_t hq = (size_t)jb.noff + leaf;
+    const int2 eh = ehdr[item];
+    if (eh.x >= 0) {  // the chain's mixed-pass groups as k_eorder listed them
+        const int ng = eh.y;
+        if (tid < ng) {
+            const int2 e = eglist[eh.x + tid];
+            gS[tid] = e.x;
+            gF[tid] = 1;
+            gCum[tid] = e.y;
+        }
+        __syncthreads();
+        if (ng <= 64) {
+            if (wv == 0) {
+                const int inc = wave_incl_scan(lane < ng ? gCum[lane] : 0);
+                if (lane < ng) gCum[lane] = inc;
+                if (lane == 63) {
+                    nops_s = inc;
+                    take_s = ng > 0;
+                }
+            }
+        } else if (tid == 0) {
+            for (int k = 1; k < ng; ++k) gCum[k] += gCum[k - 1];
+            nops_s = gCum[ng - 1];
+            take_s = 1;
+        }
+    } else if (tid == 0) {  // follow the chain's links
+        int n = 0, tot = 0, any = 0;
+        for (int gi = headE[hq]; gi >= 0 && n < kMaxEGrp; gi = egrp[gi].next) {
+            const Group gg = egrp[gi];
+            const int tk = gg.flags == 0;
+            gS[n] = gg.start;
+            gF[n] = tk;
+            any |= tk;
+            tot += gg.count;
+            gCum[n++] = tot;
+        }
+        nops_s = tot;
+        take_s = any;
+    }
+    __syncthreads();
+    const int nops = nops_s;
+    if (!take_s) {  // no pairs of this pass for this leaf
+        for (int i = tid; i < nq; i += blockDim.x) GE[(size_t)jb.qoff + qb0 + i] = 0.0;
+        return;
+    }
+    const double sig = jb.sig;
+    double qc[K];
+    double rho = 0.0;  // the leaf's half-diagonal in sig units
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        qc[k] = 0.0;
+        if (k < d) {
+            qc[k] = Q.ctr[(size_t)leaf * d + k];
+            const double hw = 0.5 * (Q.hi[(size_t)leaf * d + k] - Q.lo[(size_t)leaf * d + k]);
+            rho = fma(hw, hw, rho);
+        }
+    }
+    rho = std::sqrt(rho) * sig;
+    // squared staging radius: beyond it a term is zero to the form's precision
+    const double bcut = std::is_same<T, float>::value ? (rho + kMxNear32) * (rho + kMxNear32) : kMxFarB * kMxFarB;
+    for (int qs = 0; qs < nq; qs += kMxQ) {
+        const int nqs = min(kMxQ, nq - qs);
+        const int nqb = (nqs + 15) >> 4;  // query blocks of the pass
+        const bool two = nqb > 4;         // two sets of query blocks, waves 0-3 and 4-7
+        const int nb0 = two ? (nqb + 1) >> 1 : nqb;
+        const int set = two ? wv >> 2 : 0;
+        const int stride = two ? kMxWaves / 2 : kMxWaves, phase = two ? wv & 3 : wv;
+        const int bb = set ? nb0 : 0;  // the set's first query block
+        const int nvb = __builtin_amdgcn_readfirstlane(set ? nqb - nb0 : nb0);
+        __syncthreads();  // the previous pass's sums are read
+        if (tid < kMxQ) {  // the pass's query operand rows and norms
+            double nrm = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                double a = 0.0;
+                if (k < d && tid < nqs) a = (Q.x[(size_t)(qb0 + qs + tid) * d + k] - qc[k]) * sig;
+                if (k < d) nrm = fma(a, a, nrm);
+                sA[k][tid] = k < d ? a : (k == d ? 1.0 : 0.0);
+            }
+            sN[tid] = nrm;
+        }
+        sQ[wv][lane] = 0.0;
+        __syncthreads();
+        T Af[4][NC];
+        VT Cf[4];
+        float acc[4][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int qb = bb + b;  // <= 7: inside the arrays even past the set
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Af[b][c] = (T)sA[4 * c + g][16 * qb + col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Cf[b][r] = (T)-sN[16 * qb + V::row(r, g)];
+                acc[b][r] = 0.0f;
+            }
+        }
+        // FP32 partials into the wave's FP64 sums: across the 16 reference
+        // columns (lanes of one g), then into LDS by the column-0 lanes
+        auto flush = [&]() {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (b >= nvb) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double v = (double)acc[b][r];
+                    acc[b][r] = 0.0f;
+                    v += __shfl_xor(v, 1, 64);
+                    v += __shfl_xor(v, 2, 64);
+                    v += __shfl_xor(v, 4, 64);
+                    v += __shfl_xor(v, 8, 64);
+                    if (col == 0) sQ[wv][16 * b + V::row(r, g)] += v;
+                }
+            }
+        };
+        int nblk = 0;  // reference blocks in the wave's current partials
+        for (int o0 = 0; o0 < nops; o0 += kMxOps) {
+            __syncthreads();  // the previous chunk's tables are no longer read
+            const int o = o0 + tid;
+            int np = 0;
+            if (o < nops) {
+                int gi = 0;
+                while (o >= gCum[gi]) ++gi;
+                if (gF[gi]) {
+                    const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
+                    oB[tid] = R.begin[r];
+                    np = R.end[r] - R.begin[r];
+                }
+            }
+            const int inc = wave_incl_scan(np);
+            if (lane == 63) wsum[wv] = inc;
+            __syncthreads();
+            int pre = 0;
+            for (int w = 0; w < wv; ++w) pre += wsum[w];
+            oCum[tid] = pre + inc;
+            __syncthreads();
+            const int nopc = min(kMxOps, nops - o0);
+            const int tot = oCum[nopc - 1];
+            for (int p0 = 0; p0 < tot; p0 += RND) {
+                const int cnt = min(RND, tot - p0), cntp = (cnt + 15) & ~15;
+                for (int j0 = 64 * wv; j0 < cntp; j0 += 64 * kMxWaves) {
+                    // the wave's 64 consecutive points: the op of the first by a
+                    // search every lane does alike, the rest by a short walk
+                    int op = 0;
+                    if (j0 < cnt) {
+                        int lo = 0, hi = nopc - 1;  // first op with oCum > p0 + j0
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (oCum[mid] > p0 + j0) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        op = lo;
+                    }
+                    const int jj = j0 + lane;
+                    if (jj >= cntp) continue;
+                    double bk[K];
+                    double nb = 0.0;
+                    float w = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) bk[k] = 0.0;
+                    if (jj < cnt) {
+                        const int p = p0 + jj;
+                        while (oCum[op] <= p) ++op;
+                        const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            if (k < d) {
+                                bk[k] = (R.x[(size_t)row * d + k] - qc[k]) * sig;
+                                nb = fma(bk[k], bk[k], nb);
+                            }
+                        w = R.w ? (float)R.w[row] : 1.0f;
+                        if (nb > bcut) {  // a zero term
+                            w = 0.0f;
+                            nb = 0.0;
+#pragma unroll
+                            for (int k = 0; k < K; ++k) bk[k] = 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (k <= d) sB[k][jj] = (T)(k < d ? 2.0 * bk[k] : -nb);
+                    sW[jj] = w;
+                }
+                __syncthreads();
+                // the wave's blocks of the round against its NB query blocks:
+                // all NB products are issued before their exponentials
+                auto blocks = [&](auto nbc) {
+                    constexpr int NB = decltype(nbc)::value;
+                    for (int rb = phase; rb < (cntp >> 4); rb += stride) {
+                        const int j = 16 * rb + col;
+                        T bv[NC];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) bv[c] = 4 * c + g <= d ? sB[4 * c + g][j] : (T)0;
+                        const float wj = sW[j];
+                        VT t[NB];
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            t[b] = Cf[b];
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) t[b] = V::mfma(Af[b][c], bv[c], t[b]);
+                        }
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                acc[b][r] = fmaf(wj, __builtin_amdgcn_exp2f((float)t[b][r]), acc[b][r]);
+                        if (++nblk == 64) {
+                            flush();
+                            nblk = 0;
+                        }
+                    }
+                };
+                switch (nvb) {
+                case 1: blocks(std::integral_constant<int, 1>{}); break;
+                case 2: blocks(std::integral_constant<int, 2>{}); break;
+                case 3: blocks(std::integral_constant<int, 3>{}); break;
+                default: blocks(std::integral_constant<int, 4>{}); break;
+                }
+                __syncthreads();  // the round is read before the next one is staged
+            }
+        }
+        flush();
+        __syncthreads();
+        if (tid < nqs) {  // the sums of the waves of the query's set, in wave order
+            const int s = two && (tid >> 4) >= nb0 ? 1 : 0;
+            const int lq = tid - (s ? 16 * nb0 : 0);
+            const int w0 = two ? 4 * s : 0, w1 = two ? w0 + 4 : kMxWaves;
+            double sum = 0.0;
+            for (int w = w0; w < w1; ++w) sum += sQ[w][lq];
+            GE[(size_t)jb.qoff + qb0 + qs + tid] = sum;
+        }
+    }
+}
+
+// The four forms: FP32 or FP64 products, one or two operand chunks (D <= 3,
+// D <= 7).  The FP64 form with one chunk is held to 128 VGPRs (four waves per
+// SIMD; its few spills sit outside the block loop); with two chunks the cap
+// would spill the query operands of the block loop.
+#define DFGT_MX_ARGS                                                                                             \
+    const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Group *__restrict__ egrp,             \
+        const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,            \
+        const int *__restrict__ overflow, const int *__restrict__ jlstart, int njobs, int unl,                   \
+        const int *__restrict__ order, int nitems, int sel, const int2 *__restrict__ ehdr,                       \
+        const int2 *__restrict__ eglist, double *__restrict__ GE
+#define DFGT_MX_PASS trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, order, nitems, sel, ehdr, eglist, GE
+__global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx32_1(DFGT_MX_ARGS) {
+    etile_mx_body<float, 1>(DFGT_MX_PASS);
+}
+__global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx32_2(DFGT_MX_ARGS) {
+    etile_mx_body<float, 2>(DFGT_MX_PASS);
+}
+__global__ __launch_bounds__(64 * kMxWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_etile_mx64_1(DFGT_MX_ARGS) {
+    etile_mx_body<double, 1>(DFGT_MX_PASS);
+}
+__global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx64_2(DFGT_MX_ARGS) {
+    etile_mx_body<double, 2>(DFGT_MX_PASS);
+}
+#undef DFGT_MX_ARGS
+#undef DFGT_MX_PASS
 
 // Leave-one-out sums of every query leaf with itself, before the traversal:
 // for each query i of the leaf, sum_{j in leaf, j != i} e^{-|x_i - x_j|^2 / 2h^2}
@@ -2695,8 +3123,8 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
-        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, stG, stX, stQ, cval, gdg, gmt, eord, selfE,
-        selfG, selfX, selfY, selfmin;
+        lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, stG, stX, stQ, cval, gdg, gmt, eord, ehdr,
+        eglist, selfE, selfG, selfX, selfY, selfmin;
     // overflow flag, counters and per-level counts in one allocation: one fill,
     // one copy back
     DevBuf ctl;
@@ -2757,22 +3185,24 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
 #undef DFGT_EMFMA
 }
 
+// sel (mixed pass only): 0 = every item in k_eorder's order, 1 = only the
+// items it listed as wide (the rest taken by k_etile_mx).
 template <bool GR>
 void launch_etile(bool f64pass, int d, int nitems, hipStream_t st, const DevTree *td, const Job *jd,
                   const Group *egrp, const int *eops, const int *headE, const int *cnt, const int *flag,
-                  const int *jls, int njobs, int unl, int precision, const int *order, double *GE, double *GX,
-                  double *GY) {
+                  const int *jls, int njobs, int unl, int precision, const int *order, int sel, double *GE,
+                  double *GX, double *GY) {
     const dim3 grid((unsigned)nitems);
 #define DFGT_ETILE(DV)                                                                                            \
     if (f64pass) {                                                                                                \
         hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
-                           jls, njobs, unl, precision, (const int *)nullptr, nitems, GE, GX, GY);                 \
+                           jls, njobs, unl, precision, (const int *)nullptr, nitems, 0, GE, GX, GY);              \
     } else if constexpr (DV == 3 && !GR) {                                                                        \
         hipLaunchKernelGGL((k_etile_o4<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,   \
-                           flag, jls, njobs, unl, precision, order, nitems, GE, GX, GY);                          \
+                           flag, jls, njobs, unl, precision, order, nitems, sel, GE, GX, GY);                     \
     } else {                                                                                                      \
         hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,      \
-                           flag, jls, njobs, unl, precision, order, nitems, GE, GX, GY);                          \
+                           flag, jls, njobs, unl, precision, order, nitems, sel, GE, GX, GY);                     \
     }                                                                                                             \
     break;
     switch (d) {
@@ -2840,7 +3270,9 @@ size_t plan_bytes(const Plan &pl, const Caps &c) {
     size_t b = pl.nna * (sizeof(double) * pl.PW + 1 + sizeof(double) + 3 * sizeof(int));
     if (pl.emfma) b += pl.nqa * sizeof(double) * (pl.gr ? 2 + pl.d : 1);
     b += (size_t)c.seg * 2 * sizeof(Seg) + (size_t)c.pair * (3 * sizeof(int) + sizeof(double));
-    b += (size_t)c.grp * 3 * sizeof(Group) + (size_t)c.lnode * 2 * sizeof(int) + (size_t)c.eop * sizeof(int);
+    b += (size_t)c.grp * (3 * sizeof(Group) + sizeof(int2)) + (size_t)c.lnode * 2 * sizeof(int) +
+         (size_t)c.eop * sizeof(int);
+    b += (size_t)pl.items * (6 * sizeof(int) + sizeof(int2));
     b += (size_t)c.fop * sizeof(Op) + (size_t)c.lop * sizeof(Op);
     if (pl.leaf_local) b += (size_t)c.lop * (sizeof(int) + sizeof(double) * pl.PW);
     if (!pl.acc_lds) b += (size_t)pl.items * 3 * pl.PW * sizeof(double);
@@ -2864,6 +3296,20 @@ double etile_a32(double eps_round, int d) {
     const double rest = eps_round - 0x1p-22 - 64.0 * u;
     const double a = (rest / (ln2 * u) - (d + 2) * 126.0) / (2.0 * std::sqrt(126.0));
     return a > 0.0 ? a : 0.0;
+}
+
+// Largest query-leaf half-diagonal rho (sig units) for the FP32 products of
+// the matrix-core tiles: their staged pairs have |a| + |b| <= A = 2 rho +
+// kMxNear32, t moves by at most 6.5 u A^2 (u = 2^-24: operand roundings and
+// four FP32 multiply-adds), and a term's relative error ln2 6.5 u A^2 +
+// 2^-22 (exp2) + u (the weight), plus 63 u for the FP32 partial sums, must
+// stay within eps_round.  Returns 0 when no rho > 0 does (FP64 products).
+double mx_r32(double eps_round) {
+    const double u = 0x1p-24, ln2 = 0.69314718055994530942;
+    const double rest = eps_round - 0x1p-22 - 64.0 * u;
+    if (rest <= 0.0) return 0.0;
+    const double r = 0.5 * (std::sqrt(rest / (6.5 * ln2 * u)) - kMxNear32);
+    return r > 0.0 ? r : 0.0;
 }
 
 // Memory one call may size its traversal buffers to before it splits its jobs:
@@ -2905,6 +3351,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     const double eps_round = precision == DFGT_PREC_FP64 ? 1e-12 : (eps >= 2e-3 ? 1e-4 : 1e-5);
     const double eps_eff = eps > 2.0 * eps_round ? eps - eps_round : 0.0;
     const double a32 = precision == DFGT_PREC_MIXED && grad == nullptr ? etile_a32(eps_round, t0->d) : 0.0;
+    const double r32 = precision == DFGT_PREC_MIXED && grad == nullptr ? mx_r32(eps_round) : 0.0;
     // a query leaf's own local ops are applied inside k_leaf when its per-wave
     // scratch fits; otherwise they go through the node kernels
     pl.leaf_local = pl.P <= 512;
@@ -2969,6 +3416,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.loo = loo ? 1 : 0;
             pl.loo = pl.loo || loo;
             j.a32 = a32;
+            j.r32 = r32;
             pl.jobs.push_back(j);
             nna += q.Q->m;
             nqa += q.Q->n;
@@ -3070,7 +3518,9 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     // exhaustive sums per query (k_emfma or k_etile), added by k_leaf
     DFGT_TRY(grow<double>(w.extE, pl.nqa));
     DFGT_TRY(grow<double>(w.stG, pl.nqa));
-    DFGT_TRY(grow<int>(w.eord, 3 * (size_t)pl.items));  // dispatch order of the exhaustive tiles
+    DFGT_TRY(grow<int>(w.eord, 6 * (size_t)pl.items));  // dispatch order of the exhaustive tiles
+    DFGT_TRY(grow<int2>(w.ehdr, pl.items));                // and each item's flattened E chain
+    DFGT_TRY(grow<int2>(w.eglist, cap.grp));
     if (pl.gr) {
         DFGT_TRY(grow<double>(w.extX, pl.nqa));
         DFGT_TRY(grow<double>(w.extY, pl.nqa * pl.d));
@@ -3231,13 +3681,26 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
             fn((d + 3) / 4, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
                w.flag.as<int>(), jls, njobs, pl.unl, w.extE.as<double>(), gx, gy);
         } else if (pl.precision != DFGT_PREC_FP64) {
+            // value sums with D <= 7 on the matrix cores, but for items whose
+            // query leaf is wide against h (vector-ALU tiles)
+            const bool mx = !pl.gr && d <= 7;
             int *ord = w.eord.as<int>();
             hipLaunchKernelGGL(k_eorder, dim3((unsigned)((pl.items + 255) / 256)), dim3(256), 0, ss, td, jd,
                                w.egrp.as<Group>(), headE, w.flag.as<int>(), jls, njobs, pl.unl, pl.items,
-                               w.cnt.as<int>(), ord, ord + pl.items, ord + 2 * (size_t)pl.items);
+                               mx ? 1 : 0, w.cnt.as<int>(), ord, w.ehdr.as<int2>(), w.eglist.as<int2>(),
+                               w.cap.grp);
+            if (mx) {  // FP32 products (and the items without pairs), then FP64 products
+                auto k32 = d <= 3 ? k_etile_mx32_1 : k_etile_mx32_2;
+                auto k64 = d <= 3 ? k_etile_mx64_1 : k_etile_mx64_2;
+                for (int sel : {0, 2})
+                    hipLaunchKernelGGL(sel == 0 ? k32 : k64, dim3((unsigned)pl.items), dim3(64 * kMxWaves), 0, ss,
+                                       td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
+                                       w.flag.as<int>(), jls, njobs, pl.unl, ord, pl.items, sel,
+                                       w.ehdr.as<int2>(), w.eglist.as<int2>(), w.extE.as<double>());
+            }
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
             fn(false, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, ord, w.extE.as<double>(), gx, gy);
+               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, ord, mx ? 1 : 0, w.extE.as<double>(), gx, gy);
         }
         if (prof) prof->stop(K_EMFMA, ev, ss);
         {
@@ -3246,7 +3709,7 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
             ev = prof ? prof->start(ss) : nullptr;
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
             fn(true, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, nullptr, w.extE.as<double>(), gx, gy);
+               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, nullptr, 0, w.extE.as<double>(), gx, gy);
             if (prof) prof->stop(K_EF64, ev, ss);
         }
     }
@@ -3368,6 +3831,7 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
     out->work_f = (int64_t)sv[S_FW];
     out->work_d = (int64_t)sv[S_DW];
     out->work_t = (int64_t)sv[S_TW];
+    for (int k = 0; k < 6; ++k) out->e_items[k] = (int64_t)c[C_EHEAVY + k];
     out->mfma_tiles = pl.emfma ? 1 : 0;
     if (prof && prof->on) prof->collect(out);
     return DFGT_OK;
@@ -3446,6 +3910,7 @@ void add_stats(dfgt_stats *a, const dfgt_stats &b) {
     a->work_f += b.work_f;
     a->work_d += b.work_d;
     a->work_t += b.work_t;
+    for (int k = 0; k < 6; ++k) a->e_items[k] += b.e_items[k];
     for (int k = 0; k < 5; ++k) {
         a->kernel_ms[k] += b.kernel_ms[k];
         a->kernel_launches[k] += b.kernel_launches[k];
@@ -3495,7 +3960,7 @@ void release_sum_workspace() {
     DevBuf *bufs[] = {&w.jobs, &w.trees, &w.jls, &w.L, &w.lflag, &w.heads, &w.segA, &w.segB, &w.pairA, &w.pairB,
                       &w.dec, &w.kus, &w.egrp, &w.eops, &w.fgrp, &w.fops, &w.lgrp, &w.lops, &w.lnodes, &w.stats,
                       &w.lscr, &w.pscr, &w.lopnode, &w.part, &w.extE, &w.extX, &w.extY, &w.stG, &w.stX, &w.stQ,
-                      &w.cval, &w.gdg, &w.gmt, &w.eord, &w.selfE, &w.selfG, &w.selfX, &w.selfY, &w.selfmin,
+                      &w.cval, &w.gdg, &w.gmt, &w.eord, &w.ehdr, &w.eglist, &w.selfE, &w.selfG, &w.selfX, &w.selfY, &w.selfmin,
                       &w.ctl, &w.sticky};
     for (DevBuf *b : bufs) b->release();
     w.cap = Caps{0, 0, 0, 0, 0, 0, 0};
