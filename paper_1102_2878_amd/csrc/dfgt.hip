@@ -1227,6 +1227,29 @@ __global__ void k_digits(unsigned long long *dg, unsigned short *mt, int P, int 
 }
 
 // Level-0 frontier: one segment (Q root, {R root}) per job.
+// Per-item record, computed once per call by k_items so that the per-item
+// kernels read an item's job, query leaf and its point range with one load
+// instead of a binary search over the job offsets.
+struct __align__(16) ItemRec {
+    int job, li, leaf, qb0;  // job, leaf rank in the query tree, leaf node, first point
+    int nq, pad0, pad1, pad2;  // points of the leaf
+};
+
+__global__ __launch_bounds__(256) void k_items(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
+                                               const int *__restrict__ jlstart, int njobs, int unl, int nitems,
+                                               ItemRec *__restrict__ rec) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= nitems) return;
+    ItemRec r;
+    job_leaf(jlstart, njobs, unl, item, &r.job, &r.li);
+    const DevTree &Q = trees[jobs[r.job].qt];
+    r.leaf = Q.leaves[r.li];
+    r.qb0 = Q.begin[r.leaf];
+    r.nq = Q.end[r.leaf] - r.qb0;
+    r.pad0 = r.pad1 = r.pad2 = 0;
+    rec[item] = r;
+}
+
 __global__ void k_seed(Seg *__restrict__ segs, int *__restrict__ pairs, int njobs) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= njobs) return;
@@ -1368,7 +1391,7 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                                               const double *__restrict__ part, double *__restrict__ gscratch,
                                               double *__restrict__ stG, double *__restrict__ stX,
                                               double *__restrict__ stQ, const double *__restrict__ cval,
-                                              const int *__restrict__ jlstart, int njobs, int unl,
+                                              const ItemRec *__restrict__ irec,
                                               const unsigned long long *__restrict__ gdg,
                                               const unsigned short *__restrict__ gmt,
                                               const unsigned char *__restrict__ selfE,
@@ -1382,12 +1405,12 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     __shared__ unsigned char lfl[kMaxDepth];
     __shared__ int segT[kMaxSeg], segS[kMaxSeg], segE[kMaxSeg], ccnt[kMaxDepth + 1];
     __shared__ int nsg_s, nops_s, ntot_s, nops1_s, st_phase, st_gi, st_pi;
-    int job, li;
-    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
+    const ItemRec ir = irec[blockIdx.x];
+    const int job = ir.job, li = ir.li;
     const Job jb = jobs[job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
-    const int leaf = Q.leaves[li];
+    const int leaf = ir.leaf;
     const int d = Q.d, pmax = Q.pmax, P = Q.P;
     const int PW = GR ? 2 * P : P;
     const int hs = pmax + (GR ? 1 : 0);
@@ -1854,8 +1877,8 @@ constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 f
 // an item does not change its sums.
 __global__ __launch_bounds__(256) void k_eorder(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                 const Group *__restrict__ egrp, const int *__restrict__ headE,
-                                                const int *__restrict__ overflow, const int *__restrict__ jlstart,
-                                                int njobs, int unl, int nitems, int mx, int *cnt,
+                                                const int *__restrict__ overflow, const ItemRec *__restrict__ irec,
+                                                int nitems, int mx, int *cnt,
                                                 int *__restrict__ lists, int2 *__restrict__ ehdr,
                                                 int2 *__restrict__ eglist, int egcap) {
     constexpr int NL = 6;
@@ -1867,11 +1890,10 @@ __global__ __launch_bounds__(256) void k_eorder(const DevTree *__restrict__ tree
     int ng = 0;    // groups of the mixed pass in the item's chain
     int head = -1;
     if (item < nitems) {
-        int job, li;
-        job_leaf(jlstart, njobs, unl, item, &job, &li);
-        const Job jb = jobs[job];
+        const ItemRec ir = irec[item];
+        const Job jb = jobs[ir.job];
         const DevTree &Q = trees[jb.qt];
-        const int leaf = Q.leaves[li];
+        const int leaf = ir.leaf;
         head = headE[(size_t)jb.noff + leaf];
         int ops = 0, n = 0;
         for (int gi = head; gi >= 0 && n < kMaxEGrp; ++n) {
@@ -2155,8 +2177,8 @@ template <int DT, bool GR, bool F64>
 __device__ __forceinline__ void etile_body(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                            const Group *__restrict__ egrp, const int *__restrict__ eops,
                                            const int *__restrict__ headE, const int *__restrict__ cnt_dev,
-                                           const int *__restrict__ overflow, const int *__restrict__ jlstart,
-                                           int njobs, int unl, int precision, const int *__restrict__ order,
+                                           const int *__restrict__ overflow, const ItemRec *__restrict__ irec,
+                                           int precision, const int *__restrict__ order,
                                            int nitems, int sel, double *__restrict__ GE, double *__restrict__ GX,
                                            double *__restrict__ GY) {
     using Sh = ETileShape<DT, F64>;
@@ -2185,12 +2207,11 @@ __device__ __forceinline__ void etile_body(const DevTree *__restrict__ trees, co
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int item = etile_item(blockIdx.x, cnt_dev, order, nitems, sel);
     if (item < 0) return;
-    int job, li;
-    job_leaf(jlstart, njobs, unl, item, &job, &li);
-    const Job jb = jobs[job];
+    const ItemRec ir = irec[item];
+    const Job jb = jobs[ir.job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
-    const int leaf = Q.leaves[li];
+    const int leaf = ir.leaf;
     const int d = DT > 0 ? DT : Q.d;
     const int RPW = etile_rpw<DT, F64>(d);  // reference points per wave and round
     const int PPL = (RPW + 63) / 64;        // of which each lane stages <= PPL
@@ -2387,11 +2408,11 @@ __global__ __launch_bounds__(64 * kEWaves) void k_etile(const DevTree *__restric
                                                         const Group *__restrict__ egrp, const int *__restrict__ eops,
                                                         const int *__restrict__ headE, const int *__restrict__ cnt_dev,
                                                         const int *__restrict__ overflow,
-                                                        const int *__restrict__ jlstart, int njobs, int unl,
+                                                        const ItemRec *__restrict__ irec,
                                                         int precision, const int *__restrict__ order, int nitems,
                                                         int sel, double *__restrict__ GE, double *__restrict__ GX,
                                                         double *__restrict__ GY) {
-    etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, precision,
+    etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, irec, precision,
                             order, nitems, sel, GE, GX, GY);
 }
 
@@ -2402,10 +2423,10 @@ template <int DT, bool GR, bool F64>
 __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_etile_o4(
     const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Group *__restrict__ egrp,
     const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,
-    const int *__restrict__ overflow, const int *__restrict__ jlstart, int njobs, int unl, int precision,
+    const int *__restrict__ overflow, const ItemRec *__restrict__ irec, int precision,
     const int *__restrict__ order, int nitems, int sel, double *__restrict__ GE, double *__restrict__ GX,
     double *__restrict__ GY) {
-    etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, precision,
+    etile_body<DT, GR, F64>(trees, jobs, egrp, eops, headE, cnt_dev, overflow, irec, precision,
                             order, nitems, sel, GE, GX, GY);
 }
 
@@ -2451,8 +2472,11 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 
 template <typename T, int NC>
 struct MxShape {
-    static constexpr int K = 4 * NC;                 // operand rows
-    static constexpr int RND = NC == 1 ? 1024 : 512;  // staged reference points per round
+    static constexpr int K = 4 * NC;  // operand rows
+    static constexpr int DX = K - 1;  // coordinates a point can have
+    // staged reference points per round (two buffers), per thread at most PPT
+    static constexpr int RND = (NC == 1 ? 1024 : 512) * 4 / (int)sizeof(T);
+    static constexpr int PPT = RND >= 64 * kMxWaves ? RND / (64 * kMxWaves) : 1;
 };
 template <typename T>
 struct MxVec;
@@ -2477,18 +2501,19 @@ template <typename T, int NC>
 __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                               const Group *__restrict__ egrp, const int *__restrict__ eops,
                                               const int *__restrict__ headE, const int *__restrict__ cnt_dev,
-                                              const int *__restrict__ overflow, const int *__restrict__ jlstart,
-                                              int njobs, int unl, const int *__restrict__ order, int nitems,
+                                              const int *__restrict__ overflow, const ItemRec *__restrict__ irec,
+                                              const int *__restrict__ order, int nitems,
                                               int sel, const int2 *__restrict__ ehdr,
                                               const int2 *__restrict__ eglist, double *__restrict__ GE) {
-    constexpr int K = MxShape<T, NC>::K, RND = MxShape<T, NC>::RND;
+    constexpr int K = MxShape<T, NC>::K, RND = MxShape<T, NC>::RND, PPT = MxShape<T, NC>::PPT;
+    constexpr int DX = MxShape<T, NC>::DX;
     typedef MxVec<T> V;
     typedef typename V::type VT;
     __shared__ int gS[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
     __shared__ int oB[kMxOps], oCum[kMxOps];
     __shared__ int wsum[kMxWaves], nops_s, take_s;
-    __shared__ T sB[K][RND];              // reference operand rows of the round
-    __shared__ float sW[RND];             // reference weights (0: padding or a zero term)
+    __shared__ T sB[2][K][RND];           // reference operand rows of a round, two buffers
+    __shared__ float sW[2][RND];          // reference weights (0: padding or a zero term)
     __shared__ double sA[K][kMxQ];        // query operand rows of the pass
     __shared__ double sN[kMxQ];           // |a|^2 of the pass's queries
     __shared__ double sQ[kMxWaves][64];   // per-wave FP64 sums per query of its set
@@ -2496,16 +2521,15 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     const int item = etile_item(blockIdx.x, cnt_dev, order, nitems, sel);
     if (item < 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, col = lane & 15;
-    int job, li;
-    job_leaf(jlstart, njobs, unl, item, &job, &li);
-    const Job jb = jobs[job];
+    const ItemRec ir = irec[item];
+    const int2 eh = ehdr[item];
+    const Job jb = jobs[ir.job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
-    const int leaf = Q.leaves[li];
+    const int leaf = ir.leaf;
     const int d = Q.d;
-    const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
+    const int qb0 = ir.qb0, nq = ir.nq;
     const size_t hq = (size_t)jb.noff + leaf;
-    const int2 eh = ehdr[item];
     if (eh.x >= 0) {  // the chain's mixed-pass groups as k_eorder listed them
         const int ng = eh.y;
         if (tid < ng) {
@@ -2642,12 +2666,22 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             __syncthreads();
             const int nopc = min(kMxOps, nops - o0);
             const int tot = oCum[nopc - 1];
-            for (int p0 = 0; p0 < tot; p0 += RND) {
-                const int cnt = min(RND, tot - p0), cntp = (cnt + 15) & ~15;
-                for (int j0 = 64 * wv; j0 < cntp; j0 += 64 * kMxWaves) {
+            // Rounds are double-buffered: a round's points are loaded into
+            // registers before the previous round is computed and written to
+            // the other buffer after it, so one barrier per round publishes
+            // the next buffer and retires the current one.
+            double px[PPT][DX];
+            float pw[PPT];
+            auto load_round = [&](int p0) {
+                const int cnt = min(RND, tot - p0);
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
                     // the wave's 64 consecutive points: the op of the first by a
                     // search every lane does alike, the rest by a short walk
-                    int op = 0;
+                    const int j0 = 64 * kMxWaves * k + 64 * wv, jj = j0 + lane;
+                    pw[k] = -1.0f;  // no point
+#pragma unroll
+                    for (int c = 0; c < DX; ++c) px[k][c] = 0.0;
                     if (j0 < cnt) {
                         int lo = 0, hi = nopc - 1;  // first op with oCum > p0 + j0
                         while (lo < hi) {
@@ -2655,39 +2689,56 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                             if (oCum[mid] > p0 + j0) hi = mid;
                             else lo = mid + 1;
                         }
-                        op = lo;
-                    }
-                    const int jj = j0 + lane;
-                    if (jj >= cntp) continue;
-                    double bk[K];
-                    double nb = 0.0;
-                    float w = 0.0f;
+                        if (jj < cnt) {
+                            const int p = p0 + jj;
+                            int op = lo;
+                            while (oCum[op] <= p) ++op;
+                            const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
 #pragma unroll
-                    for (int k = 0; k < K; ++k) bk[k] = 0.0;
-                    if (jj < cnt) {
-                        const int p = p0 + jj;
-                        while (oCum[op] <= p) ++op;
-                        const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
-#pragma unroll
-                        for (int k = 0; k < K; ++k)
-                            if (k < d) {
-                                bk[k] = (R.x[(size_t)row * d + k] - qc[k]) * sig;
-                                nb = fma(bk[k], bk[k], nb);
-                            }
-                        w = R.w ? (float)R.w[row] : 1.0f;
-                        if (nb > bcut) {  // a zero term
-                            w = 0.0f;
-                            nb = 0.0;
-#pragma unroll
-                            for (int k = 0; k < K; ++k) bk[k] = 0.0;
+                            for (int c = 0; c < DX; ++c)
+                                if (c < d) px[k][c] = R.x[(size_t)row * d + c];
+                            pw[k] = R.w ? (float)R.w[row] : 1.0f;
                         }
                     }
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        if (k <= d) sB[k][jj] = (T)(k < d ? 2.0 * bk[k] : -nb);
-                    sW[jj] = w;
                 }
-                __syncthreads();
+            };
+            auto store_round = [&](int buf, int p0) {
+                const int cntp = (min(RND, tot - p0) + 15) & ~15;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int jj = 64 * kMxWaves * k + 64 * wv + lane;
+                    if (jj >= cntp || jj >= RND) continue;
+                    double bk[DX];
+                    double nb = 0.0;
+                    float w = pw[k] < 0.0f ? 0.0f : pw[k];
+#pragma unroll
+                    for (int c = 0; c < DX; ++c) {
+                        bk[c] = 0.0;
+                        if (c < d && pw[k] >= 0.0f) {
+                            bk[c] = (px[k][c] - qc[c]) * sig;
+                            nb = fma(bk[c], bk[c], nb);
+                        }
+                    }
+                    if (nb > bcut) {  // a zero term
+                        w = 0.0f;
+                        nb = 0.0;
+#pragma unroll
+                        for (int c = 0; c < DX; ++c) bk[c] = 0.0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        if (c <= d) sB[buf][c][jj] = (T)(c < d ? 2.0 * bk[c] : -nb);
+                    sW[buf][jj] = w;
+                }
+            };
+            load_round(0);
+            store_round(0, 0);
+            __syncthreads();
+            int buf = 0;
+            for (int p0 = 0; p0 < tot; p0 += RND, buf ^= 1) {
+                const int cntp = (min(RND, tot - p0) + 15) & ~15;
+                const bool more = p0 + RND < tot;
+                if (more) load_round(p0 + RND);
                 // the wave's blocks of the round against its NB query blocks:
                 // all NB products are issued before their exponentials
                 auto blocks = [&](auto nbc) {
@@ -2696,8 +2747,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                         const int j = 16 * rb + col;
                         T bv[NC];
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) bv[c] = 4 * c + g <= d ? sB[4 * c + g][j] : (T)0;
-                        const float wj = sW[j];
+                        for (int c = 0; c < NC; ++c) bv[c] = 4 * c + g <= d ? sB[buf][4 * c + g][j] : (T)0;
+                        const float wj = sW[buf][j];
                         VT t[NB];
 #pragma unroll
                         for (int b = 0; b < NB; ++b) {
@@ -2722,7 +2773,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                 case 3: blocks(std::integral_constant<int, 3>{}); break;
                 default: blocks(std::integral_constant<int, 4>{}); break;
                 }
-                __syncthreads();  // the round is read before the next one is staged
+                if (more) store_round(buf ^ 1, p0 + RND);
+                __syncthreads();  // the next buffer is written, this one read
             }
         }
         flush();
@@ -2745,10 +2797,10 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
 #define DFGT_MX_ARGS                                                                                             \
     const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Group *__restrict__ egrp,             \
         const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,            \
-        const int *__restrict__ overflow, const int *__restrict__ jlstart, int njobs, int unl,                   \
+        const int *__restrict__ overflow, const ItemRec *__restrict__ irec,                                     \
         const int *__restrict__ order, int nitems, int sel, const int2 *__restrict__ ehdr,                       \
         const int2 *__restrict__ eglist, double *__restrict__ GE
-#define DFGT_MX_PASS trees, jobs, egrp, eops, headE, cnt_dev, overflow, jlstart, njobs, unl, order, nitems, sel, ehdr, eglist, GE
+#define DFGT_MX_PASS trees, jobs, egrp, eops, headE, cnt_dev, overflow, irec, order, nitems, sel, ehdr, eglist, GE
 __global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx32_1(DFGT_MX_ARGS) {
     etile_mx_body<float, 1>(DFGT_MX_PASS);
 }
@@ -2776,17 +2828,16 @@ __global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx64_2(DFGT_MX_ARGS) {
 // thread per query; jobs without leave-one-out return at once.
 template <bool GR>
 __global__ __launch_bounds__(256) void k_selfpre(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
-                                                 const int *__restrict__ jlstart, int njobs, int unl,
+                                                 const ItemRec *__restrict__ irec,
                                                  double *__restrict__ selfG, double *__restrict__ selfX,
                                                  double *__restrict__ selfY, double *__restrict__ selfmin) {
     __shared__ double red[256];
-    int job, li;
-    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
-    const Job jb = jobs[job];
+    const ItemRec ir = irec[blockIdx.x];
+    const Job jb = jobs[ir.job];
     if (!jb.loo) return;
     const DevTree &Q = trees[jb.qt];
-    const int leaf = Q.leaves[li];
-    const int qb = Q.begin[leaf], nq = Q.end[leaf] - qb, d = Q.d;
+    const int leaf = ir.leaf;
+    const int qb = ir.qb0, nq = ir.nq, d = Q.d;
     const double sig = jb.sig;
     double mn = INFINITY;
     for (int i = threadIdx.x; i < nq; i += blockDim.x) {
@@ -2840,7 +2891,7 @@ template <bool GR, int NC>
 __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                                const Group *__restrict__ egrp, const int *__restrict__ eops,
                                                const int *__restrict__ headE, const int *__restrict__ overflow,
-                                               const int *__restrict__ jlstart, int njobs, int unl,
+                                               const ItemRec *__restrict__ irec,
                                                double *__restrict__ GE, double *__restrict__ GX,
                                                double *__restrict__ GY) {
     constexpr int NT = (NC + 3) / 4;  // 16-dimension tiles of the gradient product
@@ -2851,14 +2902,13 @@ __global__ __launch_bounds__(256) void k_emfma(const DevTree *__restrict__ trees
     __shared__ double redY[GR ? 4 * NT * 256 : 1];
     if (*overflow) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4;
-    int job, li;
-    job_leaf(jlstart, njobs, unl, blockIdx.x, &job, &li);
-    const Job jb = jobs[job];
+    const ItemRec ir = irec[blockIdx.x];
+    const Job jb = jobs[ir.job];
     const DevTree &Q = trees[jb.qt];
     const DevTree &R = trees[jb.rt];
-    const int leaf = Q.leaves[li];
+    const int leaf = ir.leaf;
     const int d = Q.d;
-    const int qb0 = Q.begin[leaf], nq = Q.end[leaf] - qb0;
+    const int qb0 = ir.qb0, nq = ir.nq;
     const size_t hq = (size_t)jb.noff + leaf;
     // fragments and norms are scaled on load (q' = sig q, |q'|^2 = sig^2 |q|^2),
     // so t = |q'|^2 + |r'|^2 - 2 q'.r' is the exponent of e = 2^-t directly
@@ -3124,7 +3174,7 @@ enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
         lnodes, stats, lscr, pscr, lopnode, part, extE, extX, extY, stG, stX, stQ, cval, gdg, gmt, eord, ehdr,
-        eglist, selfE, selfG, selfX, selfY, selfmin;
+        eglist, irec, selfE, selfG, selfX, selfY, selfmin;
     // overflow flag, counters and per-level counts in one allocation: one fill,
     // one copy back
     DevBuf ctl;
@@ -3167,11 +3217,11 @@ constexpr int kLocalGrid = 2048;
 
 template <bool GR>
 void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Job *jd, const Group *egrp,
-                  const int *eops, const int *headE, const int *flag, const int *jls, int njobs, int unl,
-                  double *GE, double *GX, double *GY) {
+                  const int *eops, const int *headE, const int *flag, const ItemRec *irec, double *GE,
+                  double *GX, double *GY) {
 #define DFGT_EMFMA(NCV)                                                                                     \
-    hipLaunchKernelGGL((k_emfma<GR, NCV>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, jls, njobs, \
-                       unl, GE, GX, GY);                                                                    \
+    hipLaunchKernelGGL((k_emfma<GR, NCV>), grid, dim3(256), 0, st, td, jd, egrp, eops, headE, flag, irec, GE, \
+                       GX, GY);                                                                             \
     break;
     switch (nc) {
     case 2: DFGT_EMFMA(2)
@@ -3190,19 +3240,19 @@ void launch_emfma(int nc, dim3 grid, hipStream_t st, const DevTree *td, const Jo
 template <bool GR>
 void launch_etile(bool f64pass, int d, int nitems, hipStream_t st, const DevTree *td, const Job *jd,
                   const Group *egrp, const int *eops, const int *headE, const int *cnt, const int *flag,
-                  const int *jls, int njobs, int unl, int precision, const int *order, int sel, double *GE,
-                  double *GX, double *GY) {
+                  const ItemRec *irec, int precision, const int *order, int sel, double *GE, double *GX,
+                  double *GY) {
     const dim3 grid((unsigned)nitems);
 #define DFGT_ETILE(DV)                                                                                            \
     if (f64pass) {                                                                                                \
         hipLaunchKernelGGL((k_etile<DV, GR, true>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt, flag, \
-                           jls, njobs, unl, precision, (const int *)nullptr, nitems, 0, GE, GX, GY);              \
+                           irec, precision, (const int *)nullptr, nitems, 0, GE, GX, GY);                          \
     } else if constexpr (DV == 3 && !GR) {                                                                        \
         hipLaunchKernelGGL((k_etile_o4<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,   \
-                           flag, jls, njobs, unl, precision, order, nitems, sel, GE, GX, GY);                     \
+                           flag, irec, precision, order, nitems, sel, GE, GX, GY);                                \
     } else {                                                                                                      \
         hipLaunchKernelGGL((k_etile<DV, GR, false>), grid, dim3(64 * kEWaves), 0, st, td, jd, egrp, eops, headE, cnt,      \
-                           flag, jls, njobs, unl, precision, order, nitems, sel, GE, GX, GY);                     \
+                           flag, irec, precision, order, nitems, sel, GE, GX, GY);                                \
     }                                                                                                             \
     break;
     switch (d) {
@@ -3272,7 +3322,7 @@ size_t plan_bytes(const Plan &pl, const Caps &c) {
     b += (size_t)c.seg * 2 * sizeof(Seg) + (size_t)c.pair * (3 * sizeof(int) + sizeof(double));
     b += (size_t)c.grp * (3 * sizeof(Group) + sizeof(int2)) + (size_t)c.lnode * 2 * sizeof(int) +
          (size_t)c.eop * sizeof(int);
-    b += (size_t)pl.items * (6 * sizeof(int) + sizeof(int2));
+    b += (size_t)pl.items * (6 * sizeof(int) + sizeof(int2) + sizeof(ItemRec));
     b += (size_t)c.fop * sizeof(Op) + (size_t)c.lop * sizeof(Op);
     if (pl.leaf_local) b += (size_t)c.lop * (sizeof(int) + sizeof(double) * pl.PW);
     if (!pl.acc_lds) b += (size_t)pl.items * 3 * pl.PW * sizeof(double);
@@ -3520,6 +3570,7 @@ dfgt_status alloc_plan(const Plan &pl, Workspace &w) {
     DFGT_TRY(grow<double>(w.stG, pl.nqa));
     DFGT_TRY(grow<int>(w.eord, 6 * (size_t)pl.items));  // dispatch order of the exhaustive tiles
     DFGT_TRY(grow<int2>(w.ehdr, pl.items));                // and each item's flattened E chain
+    DFGT_TRY(grow<ItemRec>(w.irec, pl.items));
     DFGT_TRY(grow<int2>(w.eglist, cap.grp));
     if (pl.gr) {
         DFGT_TRY(grow<double>(w.extX, pl.nqa));
@@ -3640,10 +3691,13 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
         }
         fill_many(fs, st);
     }
+    const ItemRec *irec = w.irec.as<ItemRec>();
+    hipLaunchKernelGGL(k_items, dim3((unsigned)((pl.items + 255) / 256)), dim3(256), 0, st, td, jd, jls, njobs, pl.unl,
+                       pl.items, w.irec.as<ItemRec>());
     hipLaunchKernelGGL(k_seed, dim3((njobs + 255) / 256), dim3(256), 0, st, w.segA.as<Seg>(), w.pairA.as<int>(), njobs);
     if (pl.loo) {  // leave-one-out: every leaf's sums with itself, the traversal's lower bound for its leaves
         auto kp = pl.gr ? k_selfpre<true> : k_selfpre<false>;
-        hipLaunchKernelGGL(kp, dim3((unsigned)pl.items), dim3(256), 0, st, td, jd, jls, njobs, pl.unl,
+        hipLaunchKernelGGL(kp, dim3((unsigned)pl.items), dim3(256), 0, st, td, jd, irec,
                            w.selfG.as<double>(), pl.gr ? w.selfX.as<double>() : nullptr,
                            pl.gr ? w.selfY.as<double>() : nullptr, w.selfmin.as<double>());
     }
@@ -3679,14 +3733,14 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
         if (pl.emfma) {
             auto fn = pl.gr ? launch_emfma<true> : launch_emfma<false>;
             fn((d + 3) / 4, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
-               w.flag.as<int>(), jls, njobs, pl.unl, w.extE.as<double>(), gx, gy);
+               w.flag.as<int>(), irec, w.extE.as<double>(), gx, gy);
         } else if (pl.precision != DFGT_PREC_FP64) {
             // value sums with D <= 7 on the matrix cores, but for items whose
             // query leaf is wide against h (vector-ALU tiles)
             const bool mx = !pl.gr && d <= 7;
             int *ord = w.eord.as<int>();
             hipLaunchKernelGGL(k_eorder, dim3((unsigned)((pl.items + 255) / 256)), dim3(256), 0, ss, td, jd,
-                               w.egrp.as<Group>(), headE, w.flag.as<int>(), jls, njobs, pl.unl, pl.items,
+                               w.egrp.as<Group>(), headE, w.flag.as<int>(), irec, pl.items,
                                mx ? 1 : 0, w.cnt.as<int>(), ord, w.ehdr.as<int2>(), w.eglist.as<int2>(),
                                w.cap.grp);
             if (mx) {  // FP32 products (and the items without pairs), then FP64 products
@@ -3695,12 +3749,12 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
                 for (int sel : {0, 2})
                     hipLaunchKernelGGL(sel == 0 ? k32 : k64, dim3((unsigned)pl.items), dim3(64 * kMxWaves), 0, ss,
                                        td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-                                       w.flag.as<int>(), jls, njobs, pl.unl, ord, pl.items, sel,
+                                       w.flag.as<int>(), irec, ord, pl.items, sel,
                                        w.ehdr.as<int2>(), w.eglist.as<int2>(), w.extE.as<double>());
             }
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
             fn(false, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, ord, mx ? 1 : 0, w.extE.as<double>(), gx, gy);
+               w.flag.as<int>(), irec, pl.precision, ord, mx ? 1 : 0, w.extE.as<double>(), gx, gy);
         }
         if (prof) prof->stop(K_EMFMA, ev, ss);
         {
@@ -3709,7 +3763,7 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
             ev = prof ? prof->start(ss) : nullptr;
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
             fn(true, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-               w.flag.as<int>(), jls, njobs, pl.unl, pl.precision, nullptr, 0, w.extE.as<double>(), gx, gy);
+               w.flag.as<int>(), irec, pl.precision, nullptr, 0, w.extE.as<double>(), gx, gy);
             if (prof) prof->stop(K_EF64, ev, ss);
         }
     }
@@ -3745,8 +3799,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
                            pl.precision, pl.acc_lds ? 1 : 0, pl.leaf_local ? 1 : 0, w.flag.as<int>(),
                            pl.leaf_local ? w.part.as<double>() : (const double *)nullptr, w.pscr.as<double>(),
                            w.stG.as<double>(), pl.gr ? w.stX.as<double>() : nullptr,
-                           pl.gr ? w.stQ.as<double>() : nullptr, w.cval.as<double>(), jls, njobs,
-                           pl.unl, pl.dig_lds ? nullptr : w.gdg.as<unsigned long long>(),
+                           pl.gr ? w.stQ.as<double>() : nullptr, w.cval.as<double>(), irec,
+                           pl.dig_lds ? nullptr : w.gdg.as<unsigned long long>(),
                            pl.dig_lds ? nullptr : w.gmt.as<unsigned short>(),
                            pl.loo ? w.selfE.as<unsigned char>() : nullptr, w.selfG.as<double>(),
                            w.selfX.as<double>(), w.selfY.as<double>());
@@ -3960,7 +4014,7 @@ void release_sum_workspace() {
     DevBuf *bufs[] = {&w.jobs, &w.trees, &w.jls, &w.L, &w.lflag, &w.heads, &w.segA, &w.segB, &w.pairA, &w.pairB,
                       &w.dec, &w.kus, &w.egrp, &w.eops, &w.fgrp, &w.fops, &w.lgrp, &w.lops, &w.lnodes, &w.stats,
                       &w.lscr, &w.pscr, &w.lopnode, &w.part, &w.extE, &w.extX, &w.extY, &w.stG, &w.stX, &w.stQ,
-                      &w.cval, &w.gdg, &w.gmt, &w.eord, &w.ehdr, &w.eglist, &w.selfE, &w.selfG, &w.selfX, &w.selfY, &w.selfmin,
+                      &w.cval, &w.gdg, &w.gmt, &w.eord, &w.ehdr, &w.eglist, &w.irec, &w.selfE, &w.selfG, &w.selfX, &w.selfY, &w.selfmin,
                       &w.ctl, &w.sticky};
     for (DevBuf *b : bufs) b->release();
     w.cap = Caps{0, 0, 0, 0, 0, 0, 0};
