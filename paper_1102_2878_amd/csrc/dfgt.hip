@@ -1853,9 +1853,9 @@ constexpr int kEHeavyOps = 64; // an item with at least this many E ops (mixed p
 
 // Matrix-core exhaustive tiles (k_etile_mx*, below): block shape and the
 // query-leaf and reference radii (sig units) of their two product precisions.
-constexpr int kMxWaves = 8;
+constexpr int kMxWaves = 4;
 constexpr int kMxOps = 64 * kMxWaves;  // E ops flattened per chunk: one per thread
-constexpr int kMxQ = 128;              // queries held per pass over the chain
+constexpr int kMxQ = 64 * kMxWaves;    // queries held per pass over the chain (4 blocks per wave)
 constexpr double kMxWideQ = 4096.0;    // 2^12
 constexpr double kMxFarB = 8192.0;     // 2^13
 constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 form
@@ -2457,8 +2457,8 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 // One block of kMxWaves waves per (job, query leaf) item, taken in the order
 // k_eorder made (heavy items first); the item's chain comes flattened from
 // k_eorder.  The leaf's queries, kMxQ at a time, are held as operands by the
-// waves: up to 4 blocks of 16 by every wave, or, with more blocks, the first
-// half by waves 0-3 and the rest by waves 4-7.  The E chain is flattened
+// waves: the 16-query blocks form the fewest sets of <= 4 blocks, and each
+// set is held by every nsets-th wave.  The E chain is flattened
 // kMxOps ops at a time into one list of reference points (only the groups of
 // this pass: those the underflow guard flagged go to the FP64 pass); the
 // block stages RND of them at a time in LDS as operand rows (structure of
@@ -2475,7 +2475,7 @@ struct MxShape {
     static constexpr int K = 4 * NC;  // operand rows
     static constexpr int DX = K - 1;  // coordinates a point can have
     // staged reference points per round (two buffers), per thread at most PPT
-    static constexpr int RND = (NC == 1 ? 1024 : 512) * 4 / (int)sizeof(T);
+    static constexpr int RND = (NC == 1 ? 128 : 64) * kMxWaves * 4 / (int)sizeof(T);
     static constexpr int PPT = RND >= 64 * kMxWaves ? RND / (64 * kMxWaves) : 1;
 };
 template <typename T>
@@ -2591,12 +2591,13 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     for (int qs = 0; qs < nq; qs += kMxQ) {
         const int nqs = min(kMxQ, nq - qs);
         const int nqb = (nqs + 15) >> 4;  // query blocks of the pass
-        const bool two = nqb > 4;         // two sets of query blocks, waves 0-3 and 4-7
-        const int nb0 = two ? (nqb + 1) >> 1 : nqb;
-        const int set = two ? wv >> 2 : 0;
-        const int stride = two ? kMxWaves / 2 : kMxWaves, phase = two ? wv & 3 : wv;
-        const int bb = set ? nb0 : 0;  // the set's first query block
-        const int nvb = __builtin_amdgcn_readfirstlane(set ? nqb - nb0 : nb0);
+        // nsets sets of <= 4 query blocks, as equal as can be; wave w holds set
+        // w % nsets and takes every stride-th reference block from phase on
+        const int nsets = (nqb + 3) >> 2;
+        const int set = wv % nsets;
+        const int stride = (kMxWaves - set + nsets - 1) / nsets, phase = wv / nsets;
+        const int bb = set * nqb / nsets;  // the set's first query block
+        const int nvb = __builtin_amdgcn_readfirstlane((set + 1) * nqb / nsets - bb);
         __syncthreads();  // the previous pass's sums are read
         if (tid < kMxQ) {  // the pass's query operand rows and norms
             double nrm = 0.0;
@@ -2616,7 +2617,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
         float acc[4][4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int qb = bb + b;  // <= 7: inside the arrays even past the set
+            const int qb = min(bb + b, kMxQ / 16 - 1);  // blocks past the set are never used
 #pragma unroll
             for (int c = 0; c < NC; ++c) Af[b][c] = (T)sA[4 * c + g][16 * qb + col];
 #pragma unroll
@@ -2780,11 +2781,11 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
         flush();
         __syncthreads();
         if (tid < nqs) {  // the sums of the waves of the query's set, in wave order
-            const int s = two && (tid >> 4) >= nb0 ? 1 : 0;
-            const int lq = tid - (s ? 16 * nb0 : 0);
-            const int w0 = two ? 4 * s : 0, w1 = two ? w0 + 4 : kMxWaves;
+            int s = 0;
+            while ((s + 1) * nqb / nsets <= (tid >> 4)) ++s;
+            const int lq = tid - 16 * (s * nqb / nsets);
             double sum = 0.0;
-            for (int w = w0; w < w1; ++w) sum += sQ[w][lq];
+            for (int w = s; w < kMxWaves; w += nsets) sum += sQ[w][lq];
             GE[(size_t)jb.qoff + qb0 + qs + tid] = sum;
         }
     }
