@@ -2627,7 +2627,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             }
         }
         // FP32 partials into the wave's FP64 sums: across the 16 reference
-        // columns (lanes of one g), then into LDS by the column-0 lanes
+        // columns (the lanes of one g, a DPP row) by an FP64 scan whose last
+        // lane holds the row's sum, then into LDS by the column-15 lanes
         auto flush = [&]() {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -2636,11 +2637,11 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                 for (int r = 0; r < 4; ++r) {
                     double v = (double)acc[b][r];
                     acc[b][r] = 0.0f;
-                    v += __shfl_xor(v, 1, 64);
-                    v += __shfl_xor(v, 2, 64);
-                    v += __shfl_xor(v, 4, 64);
-                    v += __shfl_xor(v, 8, 64);
-                    if (col == 0) sQ[wv][16 * b + V::row(r, g)] += v;
+                    v += __longlong_as_double(dpp_move64<0x111, 0xF>(0, __double_as_longlong(v)));
+                    v += __longlong_as_double(dpp_move64<0x112, 0xF>(0, __double_as_longlong(v)));
+                    v += __longlong_as_double(dpp_move64<0x114, 0xF>(0, __double_as_longlong(v)));
+                    v += __longlong_as_double(dpp_move64<0x118, 0xF>(0, __double_as_longlong(v)));
+                    if (col == 15) sQ[wv][16 * b + V::row(r, g)] += v;
                 }
             }
         };
