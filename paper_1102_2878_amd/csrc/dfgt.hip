@@ -1856,6 +1856,7 @@ constexpr int kEHeavyOps = 64; // an item with at least this many E ops (mixed p
 constexpr int kMxWaves = 4;
 constexpr int kMxOps = 64 * kMxWaves;  // E ops flattened per chunk: one per thread
 constexpr int kMxQ = 64 * kMxWaves;    // queries held per pass over the chain (4 blocks per wave)
+constexpr int kMxSeg = 1024;           // 64-point segments of a chunk with a table entry
 constexpr double kMxWideQ = 4096.0;    // 2^12
 constexpr double kMxFarB = 8192.0;     // 2^13
 constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 form
@@ -2511,6 +2512,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     typedef typename V::type VT;
     __shared__ int gS[kMaxEGrp], gF[kMaxEGrp], gCum[kMaxEGrp];
     __shared__ int oB[kMxOps], oCum[kMxOps];
+    __shared__ unsigned char segop[kMxSeg];  // op holding the chunk's point 64 s
     __shared__ int wsum[kMxWaves], nops_s, take_s;
     __shared__ T sB[2][K][RND];           // reference operand rows of a round, two buffers
     __shared__ float sW[2][RND];          // reference weights (0: padding or a zero term)
@@ -2593,7 +2595,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
         const int nqb = (nqs + 15) >> 4;  // query blocks of the pass
         // nsets sets of <= 4 query blocks, as equal as can be; wave w holds set
         // w % nsets and takes every stride-th reference block from phase on
-        const int nsets = (nqb + 3) >> 2;
+        // (nsets divides the wave count, so every set has as many waves)
+        const int nsets = nqb <= 4 ? 1 : (nqb <= 8 ? 2 : kMxWaves);
         const int set = wv % nsets;
         const int stride = (kMxWaves - set + nsets - 1) / nsets, phase = wv / nsets;
         const int bb = set * nqb / nsets;  // the set's first query block
@@ -2665,6 +2668,9 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             int pre = 0;
             for (int w = 0; w < wv; ++w) pre += wsum[w];
             oCum[tid] = pre + inc;
+            // the op of every 64-point segment's first point: op tid holds the
+            // segments that start in [pre + inc - np, pre + inc)
+            for (int sg = (pre + inc - np + 63) >> 6; sg < kMxSeg && (sg << 6) < pre + inc; ++sg) segop[sg] = tid;
             __syncthreads();
             const int nopc = min(kMxOps, nops - o0);
             const int tot = oCum[nopc - 1];
@@ -2678,18 +2684,22 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                 const int cnt = min(RND, tot - p0);
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    // the wave's 64 consecutive points: the op of the first by a
-                    // search every lane does alike, the rest by a short walk
+                    // the wave's 64 consecutive points: the op of the first from
+                    // the segment table (a search beyond it), the rest by a short walk
                     const int j0 = 64 * kMxWaves * k + 64 * wv, jj = j0 + lane;
                     pw[k] = -1.0f;  // no point
 #pragma unroll
                     for (int c = 0; c < DX; ++c) px[k][c] = 0.0;
                     if (j0 < cnt) {
                         int lo = 0, hi = nopc - 1;  // first op with oCum > p0 + j0
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (oCum[mid] > p0 + j0) hi = mid;
-                            else lo = mid + 1;
+                        if (((p0 + j0) >> 6) < kMxSeg) {
+                            lo = segop[(p0 + j0) >> 6];  // RND and p0 are multiples of 64
+                        } else {
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (oCum[mid] > p0 + j0) hi = mid;
+                                else lo = mid + 1;
+                            }
                         }
                         if (jj < cnt) {
                             const int p = p0 + jj;
