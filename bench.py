@@ -10,8 +10,8 @@ once as a HIP graph (dfgt_batch_create) and replayed.
 One step = one replay of that graph over inputs resident in HBM (the trees,
 built once beforehand, are timed separately as build_ms).
 value = sum_k N_k^2 x 128 / (seconds per step)  [query x reference pairs / s].
-The leaf size is picked before anything is timed by dfgt_tune_leaf_size on
-the largest problem (--leaf N fixes it instead).  The same 1,024 sums as one
+The leaf size is picked before anything is timed, by timing the eager
+batched call at each candidate leaf size (--leaf N fixes it instead).  The same 1,024 sums as one
 eager dfgt_gauss_sum_batched call, and the plain tiled brute-force GPU sum
 (dfgt_naive_sum) over them, are timed alongside.
 
@@ -54,8 +54,11 @@ FP32_PEAK = 157.3e12
 CUS, CLOCK = 256, 2.4e9
 # Issue-slot model of the same work, from a throughput probe on the MI355X
 # (lane-operations per CU-clock: FP32 FMA 98.6, v_exp_f32 27.9, measured
-# serially, not co-issued): a pair takes 2D + 1 FP32 VALU slots and one exp.
+# serially, not co-issued): on the vector ALUs a pair takes 2D + 1 FP32 VALU
+# slots and one exp; in the matrix-core tiles (squared distances from MFMA)
+# one FMA and one exp.
 FMA_RATE, EXP_RATE = 98.6, 27.9
+LEAF_CANDIDATES = (64, 128, 256)
 
 
 def flops_per_pair(d):
@@ -64,6 +67,32 @@ def flops_per_pair(d):
 
 def slot_peak_pairs(d):
     return CUS * CLOCK / ((2 * d + 1) / FMA_RATE + 1.0 / EXP_RATE)
+
+
+def slot_peak_pairs_mx():
+    # matrix-core tiles: the vector ALU issues one exp2 and one FMA per pair
+    return CUS * CLOCK / (1.0 / FMA_RATE + 1.0 / EXP_RATE)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_etile_mx32_3d_batch_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1102_2878_amd", "csrc", "dfgt.hip")
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, when the kernel source is still the one
+    the counters were taken on (else None)."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None, "no rocprofv3 traffic summary"
+    rec = {ln.split(":", 1)[0].strip(): ln.split(":", 1)[1].strip() for ln in txt.splitlines() if ":" in ln}
+    if rec.get("dfgt.hip sha256 at measurement") != src:
+        return None, "the kernel source changed since the FETCH_SIZE / WRITE_SIZE counters were taken"
+    return float(rec["traffic_bytes_per_launch"]), ("rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, scaled by a "
+                                                    "256 MiB copy: profiles/k_etile_mx32_3d_batch_hbm_traffic.md")
 
 
 def cpu_model():
@@ -98,11 +127,27 @@ def batched_setup(torch, dfgt, synth, leaf):
     xd = [torch.as_tensor(x, device="cuda") for x in xs]
     torch.cuda.synchronize()
     tuning = None
+
+    def problems(lf):
+        trees = [dfgt.build_tree(x, leaf_size=lf) for x in xd]
+        out = []
+        for x, t in zip(xs, trees):
+            base = synth.silverman_h(x) * np.geomspace(1e-3, 1e3, 64)
+            out.append((t, t, np.concatenate([base, np.sqrt(2.0) * base])))
+        return out
+
     if leaf == 0:
-        big = int(np.argmax([len(x) for x in xs]))
-        hb = synth.silverman_h(xs[big]) * np.geomspace(1e-3, 1e3, 16)
-        leaf, tms = dfgt.tune_leaf_size(xd[big], hb, EPS, reps=2)
-        tuning = {"on": f"the largest problem (N = {len(xs[big])}), 16 log-spaced bandwidths, 2 repetitions",
+        # the workload itself decides: the eager batched call per candidate
+        # (median of 3 after a warm-up call), the smallest leaf within 2% of
+        # the fastest
+        tms = {}
+        for lf in LEAF_CANDIDATES:
+            pr = problems(lf)
+            tms[lf] = median_ms(torch, lambda: dfgt.gauss_sum_batched(pr, EPS), reps=3)
+            del pr
+        best = min(tms.values())
+        leaf = min(lf for lf, v in tms.items() if v <= 1.02 * best)
+        tuning = {"on": "this workload (the eager batched call, median of 3 after a warm-up)",
                   "candidates_ms": {str(k): v for k, v in tms.items()}}
     dfgt.build_tree(xd[0], leaf_size=leaf)  # warm the build path
     torch.cuda.synchronize()
@@ -328,29 +373,33 @@ def main():
     value = pairs / t_step
     t_eager, st, t_bf, worst_bf = batched_extras(torch, dfgt, xd, probs, b)
 
-    # roofline of the dominant kernel, the exhaustive tiles: the HIP events
-    # around its launches on the stream it runs on (a side stream, beside the
-    # local-moment and per-leaf kernels) in one eager call of the same jobs
+    # roofline of the dominant kernel, the matrix-core exhaustive tiles with
+    # FP32 products (k_etile_mx32_1): the HIP events around its launch on the
+    # stream it runs on (a side stream, beside the local-moment and per-leaf
+    # kernels) in one eager call of the same jobs, over the pairs it computed
     km, kl = st["kernel_ms"], st["kernel_launches"]
-    et_ms, et_n = km["etile"], max(kl["etile"], 1)
-    ep = st["base_point_pairs"]
+    et_ms, et_n = km["etile_mx32"], max(kl["etile_mx32"], 1)
+    traffic, traffic_note = recorded_traffic()
+    ep = st["e_pairs"]["fp32"]
     rate = ep / (et_ms * 1e-3)
     roofline = {
-        "kernel": "k_etile (DFGTBase exhaustive leaf-leaf tiles, D = 3, mixed precision)",
+        "kernel": "k_etile_mx32_1 (DFGTBase exhaustive leaf-leaf tiles, D = 3: squared distances from "
+                  "v_mfma_f32_16x16x4f32, exp2 and the weighted sums on the vector ALUs)",
         "bound": "alu",
         "achieved": rate * flops_per_pair(3) / 1e12,
         "peak": FP32_PEAK / 1e12,
         "unit": "TFLOP/s",
         "frac": rate * flops_per_pair(3) / FP32_PEAK,
-        "traffic": None,
-        "traffic_note": "HBM bytes per launch are not measured in this run (rocprofv3 FETCH_SIZE / WRITE_SIZE "
-                        "summaries: profiles/)",
+        "traffic": traffic,
+        "traffic_note": traffic_note,
         "flops_per_pair": flops_per_pair(3),
         "pairs_per_launch": ep / et_n,
         "avg_launch_ms": et_ms / et_n,
         "pairs_per_s": rate,
-        "issue_slot_frac": rate / slot_peak_pairs(3),
-        "issue_slot_peak_pairs_per_s": slot_peak_pairs(3),
+        "issue_slot_frac": rate / slot_peak_pairs_mx(),
+        "issue_slot_peak_pairs_per_s": slot_peak_pairs_mx(),
+        "issue_slot_model": "per pair one v_exp_f32 and one FMA on the vector ALU, the matrix cores overlapped",
+        "pairs_fp64_products": st["e_pairs"]["fp64"],
         "kernel_ms_of_one_eager_call": km,
     }
     out = {

@@ -118,17 +118,22 @@ typedef struct dfgt_stats {
                                and [3] those whose query leaf is too wide against
                                h for either (vector-ALU tiles); all 0 at
                                precision FP64 or with D >= 8 */
+    int64_t e_pairs[2];     /* exhaustive point pairs of the matrix-core tiles with
+                               FP32 [0] and FP64 [1] products (D <= 7 value sums) */
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,
      * local evaluation, combine),
-     * [2] exhaustive leaf-leaf sums of DFGTBase (matrix cores for D >= 8 in
-     * mixed precision, else the mixed-precision pass on the vector ALUs;
-     * [1] adds their results), [3] local-moment accumulation (D and T ops),
+     * [2] the mixed-precision pass of the exhaustive leaf-leaf sums of
+     * DFGTBase (its dispatch order and every tile launch of the pass: matrix
+     * cores for value sums with D <= 7 or D >= 8, else the vector ALUs; [1]
+     * adds their results), [3] local-moment accumulation (D and T ops),
      * [4] the exhaustive pairs summed in FP64 on the vector ALUs (all of them
-     * at precision FP64, else those the underflow guard flags). */
-    double kernel_ms[5];
-    int64_t kernel_launches[5];
+     * at precision FP64, else those the underflow guard flags),
+     * [5] of [2], the launch of the matrix-core tiles with FP32 products alone
+     * (the e_pairs[0] pairs). */
+    double kernel_ms[6];
+    int64_t kernel_launches[6];
 } dfgt_stats;
 
 typedef struct dfgt_tree_s *dfgt_tree;

@@ -132,6 +132,8 @@ enum {
     S_FW,  // algorithmic work of the pruned pairs: F sum N_Q p^D, D sum N_R p^D, T sum D p^2D
     S_DW,
     S_TW,
+    S_EP32,  // exhaustive pairs of the matrix-core tiles with FP32 products
+    S_EP64,  // ... with FP64 products
     S_N
 };
 
@@ -2505,7 +2507,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                                               const int *__restrict__ overflow, const ItemRec *__restrict__ irec,
                                               const int *__restrict__ order, int nitems,
                                               int sel, const int2 *__restrict__ ehdr,
-                                              const int2 *__restrict__ eglist, double *__restrict__ GE) {
+                                              const int2 *__restrict__ eglist, unsigned long long *__restrict__ npairs,
+                                              double *__restrict__ GE) {
     constexpr int K = MxShape<T, NC>::K, RND = MxShape<T, NC>::RND, PPT = MxShape<T, NC>::PPT;
     constexpr int DX = MxShape<T, NC>::DX;
     typedef MxVec<T> V;
@@ -2582,8 +2585,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     for (int k = 0; k < K; ++k) {
         qc[k] = 0.0;
         if (k < d) {
-            qc[k] = Q.ctr[(size_t)leaf * d + k];
-            const double hw = 0.5 * (Q.hi[(size_t)leaf * d + k] - Q.lo[(size_t)leaf * d + k]);
+            qc[k] = ldg(Q.ctr + (size_t)leaf * d + k);
+            const double hw = 0.5 * (ldg(Q.hi + (size_t)leaf * d + k) - ldg(Q.lo + (size_t)leaf * d + k));
             rho = fma(hw, hw, rho);
         }
     }
@@ -2607,7 +2610,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 double a = 0.0;
-                if (k < d && tid < nqs) a = (Q.x[(size_t)(qb0 + qs + tid) * d + k] - qc[k]) * sig;
+                if (k < d && tid < nqs) a = (ldg(Q.x + (size_t)(qb0 + qs + tid) * d + k) - qc[k]) * sig;
                 if (k < d) nrm = fma(a, a, nrm);
                 sA[k][tid] = k < d ? a : (k == d ? 1.0 : 0.0);
             }
@@ -2649,6 +2652,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             }
         };
         int nblk = 0;  // reference blocks in the wave's current partials
+        long long ptot = 0;  // reference points of the pass
         for (int o0 = 0; o0 < nops; o0 += kMxOps) {
             __syncthreads();  // the previous chunk's tables are no longer read
             const int o = o0 + tid;
@@ -2658,8 +2662,9 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                 while (o >= gCum[gi]) ++gi;
                 if (gF[gi]) {
                     const int r = eops[gS[gi] + o - (gi ? gCum[gi - 1] : 0)];
-                    oB[tid] = R.begin[r];
-                    np = R.end[r] - R.begin[r];
+                    const int rb0 = ldg(R.begin + r);
+                    oB[tid] = rb0;
+                    np = ldg(R.end + r) - rb0;
                 }
             }
             const int inc = wave_incl_scan(np);
@@ -2674,6 +2679,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             __syncthreads();
             const int nopc = min(kMxOps, nops - o0);
             const int tot = oCum[nopc - 1];
+            ptot += tot;
             // Rounds are double-buffered: a round's points are loaded into
             // registers before the previous round is computed and written to
             // the other buffer after it, so one barrier per round publishes
@@ -2708,8 +2714,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                             const int row = oB[op] + p - (op ? oCum[op - 1] : 0);
 #pragma unroll
                             for (int c = 0; c < DX; ++c)
-                                if (c < d) px[k][c] = R.x[(size_t)row * d + c];
-                            pw[k] = R.w ? (float)R.w[row] : 1.0f;
+                                if (c < d) px[k][c] = ldg(R.x + (size_t)row * d + c);
+                            pw[k] = R.w ? (float)ldg(R.w + row) : 1.0f;
                         }
                     }
                 }
@@ -2799,6 +2805,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             for (int w = s; w < kMxWaves; w += nsets) sum += sQ[w][lq];
             GE[(size_t)jb.qoff + qb0 + qs + tid] = sum;
         }
+        if (tid == 0 && npairs) atomicAdd(npairs, (unsigned long long)(nqs * ptot));
     }
 }
 
@@ -2811,8 +2818,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
         const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,            \
         const int *__restrict__ overflow, const ItemRec *__restrict__ irec,                                     \
         const int *__restrict__ order, int nitems, int sel, const int2 *__restrict__ ehdr,                       \
-        const int2 *__restrict__ eglist, double *__restrict__ GE
-#define DFGT_MX_PASS trees, jobs, egrp, eops, headE, cnt_dev, overflow, irec, order, nitems, sel, ehdr, eglist, GE
+        const int2 *__restrict__ eglist, unsigned long long *__restrict__ npairs, double *__restrict__ GE
+#define DFGT_MX_PASS trees, jobs, egrp, eops, headE, cnt_dev, overflow, irec, order, nitems, sel, ehdr, eglist, npairs, GE
 __global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx32_1(DFGT_MX_ARGS) {
     etile_mx_body<float, 1>(DFGT_MX_PASS);
 }
@@ -3165,7 +3172,7 @@ struct Profiler {
     }
     // Call after the stream has been synchronised.
     void collect(dfgt_stats *s) {
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 6; ++k) {
             s->kernel_ms[k] = 0.0;
             s->kernel_launches[k] = 0;
         }
@@ -3181,7 +3188,7 @@ struct Profiler {
 thread_local Profiler g_prof;
 
 // kernel_ms slots of dfgt_stats
-enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4 };
+enum { K_TRAV = 0, K_LEAF = 1, K_EMFMA = 2, K_LOCAL = 3, K_EF64 = 4, K_MX32 = 5 };
 
 struct Workspace {
     DevBuf jobs, trees, jls, L, lflag, heads, segA, segB, pairA, pairB, dec, kus, egrp, eops, fgrp, fops, lgrp, lops,
@@ -3200,6 +3207,7 @@ struct Workspace {
     Caps cap{0, 0, 0, 0, 0, 0, 0};
     int part_jobs = 0;  // jobs per part learned from the last split (0 = none yet)
     size_t part_budget = 0;  // the memory budget part_jobs was learned under
+    double part_ipj = 0.0;   // (query leaf) items per job of the plan it was learned on
     // the exhaustive tiles run on a side stream beside the local-moment ops
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -3758,11 +3766,16 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
             if (mx) {  // FP32 products (and the items without pairs), then FP64 products
                 auto k32 = d <= 3 ? k_etile_mx32_1 : k_etile_mx32_2;
                 auto k64 = d <= 3 ? k_etile_mx64_1 : k_etile_mx64_2;
-                for (int sel : {0, 2})
+                unsigned long long *sp = w.stats.as<unsigned long long>();
+                for (int sel : {0, 2}) {
+                    hipEvent_t e2 = prof && sel == 0 ? prof->start(ss) : nullptr;
                     hipLaunchKernelGGL(sel == 0 ? k32 : k64, dim3((unsigned)pl.items), dim3(64 * kMxWaves), 0, ss,
                                        td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
-                                       w.flag.as<int>(), irec, ord, pl.items, sel,
-                                       w.ehdr.as<int2>(), w.eglist.as<int2>(), w.extE.as<double>());
+                                       w.flag.as<int>(), irec, ord, pl.items, sel, w.ehdr.as<int2>(),
+                                       w.eglist.as<int2>(), sp + (size_t)(sel == 0 ? S_EP32 : S_EP64) * SP,
+                                       w.extE.as<double>());
+                    if (e2) prof->stop(K_MX32, e2, ss);
+                }
             }
             auto fn = pl.gr ? launch_etile<true> : launch_etile<false>;
             fn(false, d, pl.items, ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE, w.cnt.as<int>(),
@@ -3897,6 +3910,8 @@ dfgt_status fill_stats(const Plan &pl, Workspace &w, const int *c, Profiler *pro
     out->work_f = (int64_t)sv[S_FW];
     out->work_d = (int64_t)sv[S_DW];
     out->work_t = (int64_t)sv[S_TW];
+    out->e_pairs[0] = (int64_t)sv[S_EP32];
+    out->e_pairs[1] = (int64_t)sv[S_EP64];
     for (int k = 0; k < 6; ++k) out->e_items[k] = (int64_t)c[C_EHEAVY + k];
     out->mfma_tiles = pl.emfma ? 1 : 0;
     if (prof && prof->on) prof->collect(out);
@@ -3977,7 +3992,8 @@ void add_stats(dfgt_stats *a, const dfgt_stats &b) {
     a->work_d += b.work_d;
     a->work_t += b.work_t;
     for (int k = 0; k < 6; ++k) a->e_items[k] += b.e_items[k];
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 2; ++k) a->e_pairs[k] += b.e_pairs[k];
+    for (int k = 0; k < 6; ++k) {
         a->kernel_ms[k] += b.kernel_ms[k];
         a->kernel_launches[k] += b.kernel_launches[k];
     }
@@ -3989,7 +4005,10 @@ dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *
                        std::vector<Plan> *parts) {
     std::vector<Plan> todo;
     const size_t budget = memory_budget();
-    if (budget != w.part_budget) {  // a part size learned under another budget does not apply
+    const double ipj = (double)full.items / std::max(full.njobs, 1);
+    // a part size learned under another budget, or on jobs with more items
+    // (larger lists), does not apply
+    if (budget != w.part_budget || ipj < 0.9 * w.part_ipj) {
         w.part_jobs = 0;
         w.part_budget = budget;
     }
@@ -4008,6 +4027,7 @@ dfgt_status run_chunks(const Plan &full, Workspace &w, int profile, dfgt_stats *
         if (too_big) {
             const int mid = pl.njobs / 2;
             w.part_jobs = w.part_jobs > 0 ? std::min(w.part_jobs, pl.njobs - mid) : pl.njobs - mid;
+            w.part_ipj = ipj;
             todo.insert(todo.begin(), sub_plan(pl, mid, pl.njobs));
             todo.insert(todo.begin(), sub_plan(pl, 0, mid));
             continue;

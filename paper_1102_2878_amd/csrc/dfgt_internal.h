@@ -239,6 +239,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+// Load through a pointer that device code read from memory (a DevTree field):
+// left to itself the compiler cannot tell that it addresses global memory and
+// emits a FLAT load, whose completion also gates every later wait for LDS
+// results, so a prefetch issued before LDS work would stall at its first LDS
+// wait.  The cast makes it a global load.
+template <class T>
+__device__ __forceinline__ T ldg(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
 // DPP lane moves (GFX9 row controls: row_shr:n is 0x110 + n, row_bcast:15
 // 0x142, row_bcast:31 0x143); lanes without a source lane, and rows outside
 // ROWS, receive `old`.  They stay in the vector ALU: no LDS round trip, unlike

@@ -35,13 +35,16 @@ class Stats(C.Structure):
         "node_pairs", "prune_f", "prune_d", "prune_t", "prune_centroid", "base_leaf_pairs",
         "base_point_pairs", "levels", "max_order", "fp64_groups", "segments", "max_segment", "local_nodes",
         "max_local_ops", "mfma_tiles", "parts", "work_f", "work_d", "work_t")] + [("e_items", C.c_int64 * 6),
-                                                                       ("kernel_ms", C.c_double * 5),
-                                                                       ("kernel_launches", C.c_int64 * 5)]
-    KERNELS = ("traverse", "leaf", "etile", "local", "etile_fp64")
+                                                                       ("e_pairs", C.c_int64 * 2),
+                                                                       ("kernel_ms", C.c_double * 6),
+                                                                       ("kernel_launches", C.c_int64 * 6)]
+    KERNELS = ("traverse", "leaf", "etile", "local", "etile_fp64", "etile_mx32")
 
     def as_dict(self):
         d = {nm: int(getattr(self, nm)) for nm, _ in self._fields_ if nm not in ("reserved", "kernel_ms",
-                                                                                 "kernel_launches", "e_items")}
+                                                                                 "kernel_launches", "e_items",
+                                                                                 "e_pairs")}
+        d["e_pairs"] = {"fp32": int(self.e_pairs[0]), "fp64": int(self.e_pairs[1])}
         d["e_items"] = dict(zip(("heavy", "short", "none", "wide", "heavy_fp64", "short_fp64"),
                                 [int(v) for v in self.e_items]))
         d["kernel_ms"] = dict(zip(self.KERNELS, list(self.kernel_ms)))

@@ -145,18 +145,23 @@ def test_split_into_parts_matches_unsplit(dfgt, monkeypatch):
             assert np.max(np.abs(G[k][rows] - r) / r) <= 1e-2, (x.shape, h[k])
 
 
-def test_full_size_3d_batch_sampled(dfgt):
-    """The 3-D batch at its full size and in the bench's launch configuration:
+@pytest.mark.parametrize("leaf", [128, 256])
+def test_full_size_3d_batch_sampled(dfgt, leaf):
+    """The 3-D batch at its full size and in the bench's launch configurations:
     8 clustered problems of 10k..200k points, 64 log-spaced bandwidths
-    h_S x 10^{-3..3} each at h and sqrt(2) h (1024 sums), leaf size 128, the
-    jobs split into as many parts as the default memory budget needs.  The
-    captured graph's replay equals the eager call bitwise; 200 seeded rows per
-    problem at 16 seeded bandwidths are within eps of the oracle."""
+    h_S x 10^{-3..3} each at h and sqrt(2) h (1024 sums), leaf size 128 or 256
+    (the candidates the bench picks between), the jobs split into as many parts
+    as the default memory budget needs.  The captured graph's replay equals the
+    eager call bitwise; 200 seeded rows per problem at 16 seeded bandwidths are
+    within eps of the oracle; both product precisions of the matrix-core tiles
+    take part."""
     import torch
-    probs, data = _problems_3d(dfgt, synth.C4_SIZES, 64, leaf=128)
-    note("batch 3-D full size: eager")
+    probs, data = _problems_3d(dfgt, synth.C4_SIZES, 64, leaf=leaf)
+    note(f"batch 3-D full size, leaf {leaf}: eager")
     eager, st = dfgt.gauss_sum_batched(probs, 1e-2, stats=True)
     torch.cuda.synchronize()
+    assert st["e_pairs"]["fp32"] > 0 and st["e_pairs"]["fp64"] > 0, st["e_pairs"]
+    assert st["e_pairs"]["fp32"] + st["e_pairs"]["fp64"] <= st["base_point_pairs"]
     note(f"batch 3-D full size: graph capture ({st['parts']} parts eager)")
     b = dfgt.Batch(probs, 1e-2)
     for G in b.G:

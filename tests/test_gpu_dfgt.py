@@ -260,16 +260,18 @@ def test_full_size_c3_sampled(dfgt, pmax, eps, ce):
 @pytest.mark.parametrize("d", [1, 2, 3, 5])
 def test_exhaustive_rounding_budget(dfgt, d):
     """Every leaf pair exhaustive at eps = 1e-2: the leaf sums may spend a
-    rounding budget of 1e-4 relative (FP32 coordinate differences relative to
-    the query leaf's centre where the staged coordinates are small enough,
-    FP64 differences elsewhere), so every query is within 1e-4 of the exact
-    sum; bandwidths from a fraction of a leaf's width to many leaf widths put
-    both forms in the same call."""
+    rounding budget of 1e-4 relative, so every query is within 1e-4 of the
+    exact sum.  The matrix-core tiles take FP32 products where the query leaf's
+    half-diagonal is within r32 sig units and FP64 products elsewhere;
+    bandwidths from a fraction of a leaf's width to many leaf widths put both
+    in the same call, and leaves of 256 points put their largest operand
+    magnitudes at the FP32 bound."""
     x = synth.c3(n=6000, seed=61)[:, :d].copy()
-    hs = [synth.silverman_h(x) * s for s in (0.01, 0.1, 1.0, 10.0)]
+    hs = [synth.silverman_h(x) * s for s in (0.01, 0.1, 0.3, 1.0, 10.0)]
     note(f"dfgt exhaustive rounding budget d={d}")
-    for leaf in (32, 128):
+    for leaf in (32, 128, 256):
         G, st = _run(dfgt, x, None, hs, 1e-2, leaf=leaf, force=5)
+        assert st["e_pairs"]["fp32"] > 0 and st["e_pairs"]["fp64"] > 0, (d, leaf, st["e_pairs"])
         for k, h in enumerate(hs):
             rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
             assert rel.max() <= 1e-4, (d, leaf, h, rel.max())
