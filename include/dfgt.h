@@ -112,21 +112,21 @@ typedef struct dfgt_stats {
     int64_t work_t;         /* far-to-local sum D p^2D (order >= 2) */
     int64_t e_items[6];     /* (query leaf, bandwidth) items of the mixed exhaustive
                                pass: [0] >= 64 reference leaves in the E list,
-                               [1] fewer, [2] none; for value sums with D <= 7
+                               [1] fewer, [2] none; for value sums with 3 <= D <= 7
                                (matrix-core tiles) [0], [1] count the items with
                                FP32 products, [4], [5] those with FP64 products
                                and [3] those whose query leaf is too wide against
                                h for either (vector-ALU tiles); all 0 at
                                precision FP64 or with D >= 8 */
     int64_t e_pairs[2];     /* exhaustive point pairs of the matrix-core tiles with
-                               FP32 [0] and FP64 [1] products (D <= 7 value sums) */
+                               FP32 [0] and FP64 [1] products (value sums, 3 <= D <= 7) */
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,
      * local evaluation, combine),
      * [2] the mixed-precision pass of the exhaustive leaf-leaf sums of
      * DFGTBase (its dispatch order and every tile launch of the pass: matrix
-     * cores for value sums with D <= 7 or D >= 8, else the vector ALUs; [1]
+     * cores for value sums with 3 <= D <= 7 or D >= 8, else the vector ALUs; [1]
      * adds their results), [3] local-moment accumulation (D and T ops),
      * [4] the exhaustive pairs summed in FP64 on the vector ALUs (all of them
      * at precision FP64, else those the underflow guard flags),

@@ -2433,7 +2433,7 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
                             order, nitems, sel, GE, GX, GY);
 }
 
-// ---------------------------------------------------------------- exhaustive tiles on the matrix cores, D <= 7
+// ---------------------------------------------------------------- exhaustive tiles on the matrix cores, 3 <= D <= 7
 // The mixed pass of the value sums (DFGTBase, Section 3.9) as a contraction.
 // Coordinates are taken relative to the query leaf's box centre c and scaled
 // by sig: a = sig (q - c), b = sig (r - c), so that t = |a - b|^2 and the
@@ -3755,9 +3755,12 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
             fn((d + 3) / 4, dim3(pl.items), ss, td, jd, w.egrp.as<Group>(), w.eops.as<int>(), headE,
                w.flag.as<int>(), irec, w.extE.as<double>(), gx, gy);
         } else if (pl.precision != DFGT_PREC_FP64) {
-            // value sums with D <= 7 on the matrix cores, but for items whose
-            // query leaf is wide against h (vector-ALU tiles)
-            const bool mx = !pl.gr && d <= 7;
+            // value sums with 3 <= D <= 7 on the matrix cores, but for items
+            // whose query leaf is wide against h (vector-ALU tiles); with D <= 2
+            // the vector-ALU tiles' 2D + 1 FMAs per pair cost less than the
+            // matrix-core tiles' staging and reductions (2-D sweep: 0.29 ms
+            // against 0.41 ms of tiles)
+            const bool mx = !pl.gr && d >= 3 && d <= 7;
             int *ord = w.eord.as<int>();
             hipLaunchKernelGGL(k_eorder, dim3((unsigned)((pl.items + 255) / 256)), dim3(256), 0, ss, td, jd,
                                w.egrp.as<Group>(), headE, w.flag.as<int>(), irec, pl.items,

@@ -261,8 +261,9 @@ def test_full_size_c3_sampled(dfgt, pmax, eps, ce):
 def test_exhaustive_rounding_budget(dfgt, d):
     """Every leaf pair exhaustive at eps = 1e-2: the leaf sums may spend a
     rounding budget of 1e-4 relative, so every query is within 1e-4 of the
-    exact sum.  The matrix-core tiles take FP32 products where the query leaf's
-    half-diagonal is within r32 sig units and FP64 products elsewhere;
+    exact sum.  For D >= 3 the matrix-core tiles take FP32 products where the
+    query leaf's half-diagonal is within r32 sig units and FP64 products
+    elsewhere (D <= 2: vector-ALU tiles, FP32 or FP64 differences);
     bandwidths from a fraction of a leaf's width to many leaf widths put both
     in the same call, and leaves of 256 points put their largest operand
     magnitudes at the FP32 bound."""
@@ -271,7 +272,10 @@ def test_exhaustive_rounding_budget(dfgt, d):
     note(f"dfgt exhaustive rounding budget d={d}")
     for leaf in (32, 128, 256):
         G, st = _run(dfgt, x, None, hs, 1e-2, leaf=leaf, force=5)
-        assert st["e_pairs"]["fp32"] > 0 and st["e_pairs"]["fp64"] > 0, (d, leaf, st["e_pairs"])
+        if d >= 3:  # the matrix-core tiles take value sums with 3 <= D <= 7
+            assert st["e_pairs"]["fp32"] > 0 and st["e_pairs"]["fp64"] > 0, (d, leaf, st["e_pairs"])
+        else:
+            assert st["e_pairs"]["fp32"] == 0 and st["e_pairs"]["fp64"] == 0, (d, leaf, st["e_pairs"])
         for k, h in enumerate(hs):
             rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
             assert rel.max() <= 1e-4, (d, leaf, h, rel.max())
