@@ -1860,8 +1860,7 @@ constexpr int kMxOps = 64 * kMxWaves;  // E ops flattened per chunk: one per thr
 constexpr int kMxQ = 64 * kMxWaves;    // queries held per pass over the chain (4 blocks per wave)
 constexpr int kMxSeg = 1024;           // 64-point segments of a chunk with a table entry
 constexpr double kMxWideQ = 4096.0;    // 2^12
-constexpr double kMxFarB = 8192.0;     // 2^13
-constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 form
+constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 form; box gap in the FP64 form
 
 // Dispatch order of the mixed pass's exhaustive tiles (longest first): the
 // items whose E chain holds >= kEHeavyOps ops of the mixed pass, then those
@@ -2452,10 +2451,15 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 //     of the four multiply-adds moves t by at most 6.5 u A^2 (u = 2^-24);
 //     r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) + 64 u (weight, partials)
 //     within the rounding budget.
-//   FP64 (rho <= kMxWideQ): a reference with |b| > kMxFarB is staged with
-//     weight 0 (t >= (kMxFarB - kMxWideQ)^2 = 2^24); the FP64 rounding of t,
-//     ~12 2^-53 A^2 with A <= 3 2^12, stays below 2e-7, under the FP32
-//     rounding of t itself.
+//   FP64 (rho <= kMxWideQ): a reference is staged only when its distance to
+//     the query leaf's bounding box is <= 12 (in sig units): the others have
+//     t >= 144 for every query of the leaf, as above.  The kept points are
+//     packed at the front of each wave's 64-point region of the round (a
+//     ballot gives their ranks), padded to a multiple of 16; those big leaves
+//     see many such far references, which are then neither multiplied nor
+//     exponentiated.  Then A <= 2 rho + 12 <= 2^13 + 12 and the FP64 rounding
+//     of t, ~12 2^-53 A^2, stays below 1e-7, under the FP32 rounding of t
+//     itself.
 //   Wider leaves go to the vector-ALU tiles.
 // One block of kMxWaves waves per (job, query leaf) item, taken in the order
 // k_eorder made (heavy items first); the item's chain comes flattened from
@@ -2522,6 +2526,10 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     __shared__ double sA[K][kMxQ];        // query operand rows of the pass
     __shared__ double sN[kMxQ];           // |a|^2 of the pass's queries
     __shared__ double sQ[kMxWaves][64];   // per-wave FP64 sums per query of its set
+    __shared__ double sHw[K];             // FP64 form: the leaf box's half-widths in sig units
+    __shared__ int sCnt[2][kMxWaves];     // FP64 form: kept points of each wave's region, padded to 16
+    constexpr bool PACK = std::is_same<T, double>::value;
+    static_assert(!PACK || PPT == 1, "the FP64 form stages one point per thread and round");
     if (*overflow) return;
     const int item = etile_item(blockIdx.x, cnt_dev, order, nitems, sel);
     if (item < 0) return;
@@ -2588,11 +2596,12 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             qc[k] = ldg(Q.ctr + (size_t)leaf * d + k);
             const double hw = 0.5 * (ldg(Q.hi + (size_t)leaf * d + k) - ldg(Q.lo + (size_t)leaf * d + k));
             rho = fma(hw, hw, rho);
+            if (PACK && tid == 0) sHw[k] = hw * sig;
         }
     }
     rho = std::sqrt(rho) * sig;
     // squared staging radius: beyond it a term is zero to the form's precision
-    const double bcut = std::is_same<T, float>::value ? (rho + kMxNear32) * (rho + kMxNear32) : kMxFarB * kMxFarB;
+    const double bcut = (rho + kMxNear32) * (rho + kMxNear32);
     for (int qs = 0; qs < nq; qs += kMxQ) {
         const int nqs = min(kMxQ, nq - qs);
         const int nqb = (nqs + 15) >> 4;  // query blocks of the pass
@@ -2721,6 +2730,40 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                 }
             };
             auto store_round = [&](int buf, int p0) {
+                if constexpr (PACK) {  // the kept points at the front of the wave's region
+                    const int j0 = 64 * wv;
+                    bool keep = pw[0] >= 0.0f;
+                    double bk[DX];
+                    double nb = 0.0, gap = 0.0;  // |b|^2, squared distance to the leaf box
+#pragma unroll
+                    for (int c = 0; c < DX; ++c) {
+                        bk[c] = 0.0;
+                        if (c < d && keep) {
+                            bk[c] = (px[0][c] - qc[c]) * sig;
+                            nb = fma(bk[c], bk[c], nb);
+                            const double o = fmax(0.0, fabs(bk[c]) - sHw[c]);
+                            gap = fma(o, o, gap);
+                        }
+                    }
+                    keep = keep && gap <= kMxNear32 * kMxNear32;
+                    const unsigned long long m = __ballot(keep);
+                    const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    const int nk = __popcll(m), nk16 = (nk + 15) & ~15;
+                    if (keep) {
+#pragma unroll
+                        for (int c = 0; c < K; ++c)
+                            if (c <= d) sB[buf][c][j0 + rank] = c < d ? 2.0 * bk[c] : -nb;
+                        sW[buf][j0 + rank] = pw[0];
+                    }
+                    if (lane >= nk && lane < nk16) {  // zero-weight padding of the last block
+#pragma unroll
+                        for (int c = 0; c < K; ++c)
+                            if (c <= d) sB[buf][c][j0 + lane] = 0.0;
+                        sW[buf][j0 + lane] = 0.0f;
+                    }
+                    if (lane == 0) sCnt[buf][wv] = nk16;
+                    return;
+                }
                 const int cntp = (min(RND, tot - p0) + 15) & ~15;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
@@ -2754,15 +2797,41 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             __syncthreads();
             int buf = 0;
             for (int p0 = 0; p0 < tot; p0 += RND, buf ^= 1) {
-                const int cntp = (min(RND, tot - p0) + 15) & ~15;
+                // 16-point blocks of the round; the FP64 form's lie in the
+                // waves' regions, nbw[w] of them from 64 w on
+                int nbw[kMxWaves], nrb;
+                if constexpr (PACK) {
+                    nrb = 0;
+#pragma unroll
+                    for (int w = 0; w < kMxWaves; ++w) {
+                        nbw[w] = __builtin_amdgcn_readfirstlane(sCnt[buf][w] >> 4);
+                        nrb += nbw[w];
+                    }
+                } else {
+                    nrb = (min(RND, tot - p0) + 15) >> 4;
+                }
                 const bool more = p0 + RND < tot;
                 if (more) load_round(p0 + RND);
                 // the wave's blocks of the round against its NB query blocks:
                 // all NB products are issued before their exponentials
                 auto blocks = [&](auto nbc) {
                     constexpr int NB = decltype(nbc)::value;
-                    for (int rb = phase; rb < (cntp >> 4); rb += stride) {
-                        const int j = 16 * rb + col;
+                    for (int rb = phase; rb < nrb; rb += stride) {
+                        int j = 16 * rb + col;
+                        if constexpr (PACK) {
+                            int r = rb, w = 0;
+                            bool found = false;
+#pragma unroll
+                            for (int q = 0; q < kMxWaves - 1; ++q) {
+                                if (!found && r >= nbw[q]) {
+                                    r -= nbw[q];
+                                    w = q + 1;
+                                } else {
+                                    found = true;
+                                }
+                            }
+                            j = 64 * w + 16 * r + col;
+                        }
                         T bv[NC];
 #pragma unroll
                         for (int c = 0; c < NC; ++c) bv[c] = 4 * c + g <= d ? sB[buf][4 * c + g][j] : (T)0;
