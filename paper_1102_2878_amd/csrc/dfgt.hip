@@ -2521,7 +2521,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     __shared__ int oB[kMxOps], oCum[kMxOps];
     __shared__ unsigned char segop[kMxSeg];  // op holding the chunk's point 64 s
     __shared__ int wsum[kMxWaves], nops_s, take_s;
-    __shared__ T sB[2][K][RND];           // reference operand rows of a round, two buffers
+    __shared__ T sB[2][K][RND];           // reference operand rows of a round, two buffers (rows past D + 1 zero)
     __shared__ float sW[2][RND];          // reference weights (0: padding or a zero term)
     __shared__ double sA[K][kMxQ];        // query operand rows of the pass
     __shared__ double sN[kMxQ];           // |a|^2 of the pass's queries
@@ -2533,7 +2533,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     if (*overflow) return;
     const int item = etile_item(blockIdx.x, cnt_dev, order, nitems, sel);
     if (item < 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, col = lane & 15;
+    const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, col = lane & 15;
     const ItemRec ir = irec[item];
     const int2 eh = ehdr[item];
     const Job jb = jobs[ir.job];
@@ -2581,7 +2581,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
         take_s = any;
     }
     __syncthreads();
-    const int nops = nops_s;
+    const int nops = __builtin_amdgcn_readfirstlane(nops_s);
     if (!take_s) {  // no pairs of this pass for this leaf
         for (int i = tid; i < nq; i += blockDim.x) GE[(size_t)jb.qoff + qb0 + i] = 0.0;
         return;
@@ -2687,7 +2687,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             for (int sg = (pre + inc - np + 63) >> 6; sg < kMxSeg && (sg << 6) < pre + inc; ++sg) segop[sg] = tid;
             __syncthreads();
             const int nopc = min(kMxOps, nops - o0);
-            const int tot = oCum[nopc - 1];
+            const int tot = __builtin_amdgcn_readfirstlane(oCum[nopc - 1]);
             ptot += tot;
             // Rounds are double-buffered: a round's points are loaded into
             // registers before the previous round is computed and written to
@@ -2752,13 +2752,13 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                     if (keep) {
 #pragma unroll
                         for (int c = 0; c < K; ++c)
-                            if (c <= d) sB[buf][c][j0 + rank] = c < d ? 2.0 * bk[c] : -nb;
+                            sB[buf][c][j0 + rank] = c < d ? 2.0 * bk[c] : (c == d ? -nb : 0.0);
                         sW[buf][j0 + rank] = pw[0];
                     }
                     if (lane >= nk && lane < nk16) {  // zero-weight padding of the last block
 #pragma unroll
                         for (int c = 0; c < K; ++c)
-                            if (c <= d) sB[buf][c][j0 + lane] = 0.0;
+                            sB[buf][c][j0 + lane] = 0.0;
                         sW[buf][j0 + lane] = 0.0f;
                     }
                     if (lane == 0) sCnt[buf][wv] = nk16;
@@ -2788,7 +2788,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                     }
 #pragma unroll
                     for (int c = 0; c < K; ++c)
-                        if (c <= d) sB[buf][c][jj] = (T)(c < d ? 2.0 * bk[c] : -nb);
+                        sB[buf][c][jj] = (T)(c < d ? 2.0 * bk[c] : (c == d ? -nb : 0.0));
                     sW[buf][jj] = w;
                 }
             };
@@ -2834,7 +2834,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                         }
                         T bv[NC];
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) bv[c] = 4 * c + g <= d ? sB[buf][4 * c + g][j] : (T)0;
+                        for (int c = 0; c < NC; ++c) bv[c] = sB[buf][4 * c + g][j];
                         const float wj = sW[buf][j];
                         VT t[NB];
 #pragma unroll
