@@ -2449,7 +2449,7 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 //     the mixed sums already allow for) and are staged with weight 0.  Then
 //     A = |a| + |b| <= 2 rho + 12, and the FP32 rounding of the operands and
 //     of the four multiply-adds moves t by at most 6.5 u A^2 (u = 2^-24);
-//     r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) + 64 u (weight, partials)
+//     r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) + 68 u (weight, partials)
 //     within the rounding budget.
 //   FP64 (rho <= kMxWideQ): a reference is staged only when its distance to
 //     the query leaf's bounding box is <= 12 (in sig units): the others have
@@ -2642,21 +2642,23 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
             }
         }
         // FP32 partials into the wave's FP64 sums: across the 16 reference
-        // columns (the lanes of one g, a DPP row) by an FP64 scan whose last
-        // lane holds the row's sum, then into LDS by the column-15 lanes
+        // columns (the lanes of one g, a DPP row) by an FP32 scan whose last
+        // lane holds the row's sum (four more roundings per term, one
+        // v_add_f32 with a DPP source each), then into LDS in FP64 by the
+        // column-15 lanes
         auto flush = [&]() {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (b >= nvb) continue;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    double v = (double)acc[b][r];
+                    float v = acc[b][r];
                     acc[b][r] = 0.0f;
-                    v += __longlong_as_double(dpp_move64<0x111, 0xF>(0, __double_as_longlong(v)));
-                    v += __longlong_as_double(dpp_move64<0x112, 0xF>(0, __double_as_longlong(v)));
-                    v += __longlong_as_double(dpp_move64<0x114, 0xF>(0, __double_as_longlong(v)));
-                    v += __longlong_as_double(dpp_move64<0x118, 0xF>(0, __double_as_longlong(v)));
-                    if (col == 15) sQ[wv][16 * b + V::row(r, g)] += v;
+                    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+                    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+                    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+                    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+                    if (col == 15) sQ[wv][16 * b + V::row(r, g)] += (double)v;
                 }
             }
         };
@@ -3441,11 +3443,12 @@ double etile_a32(double eps_round, int d) {
 // the matrix-core tiles: their staged pairs have |a| + |b| <= A = 2 rho +
 // kMxNear32, t moves by at most 6.5 u A^2 (u = 2^-24: operand roundings and
 // four FP32 multiply-adds), and a term's relative error ln2 6.5 u A^2 +
-// 2^-22 (exp2) + u (the weight), plus 63 u for the FP32 partial sums, must
-// stay within eps_round.  Returns 0 when no rho > 0 does (FP64 products).
+// 2^-22 (exp2) + u (the weight), plus 67 u for the FP32 partial sums (63
+// within a lane, 4 across the lanes of a row), must stay within eps_round.
+// Returns 0 when no rho > 0 does (FP64 products).
 double mx_r32(double eps_round) {
     const double u = 0x1p-24, ln2 = 0.69314718055994530942;
-    const double rest = eps_round - 0x1p-22 - 64.0 * u;
+    const double rest = eps_round - 0x1p-22 - 68.0 * u;
     if (rest <= 0.0) return 0.0;
     const double r = 0.5 * (std::sqrt(rest / (6.5 * ln2 * u)) - kMxNear32);
     return r > 0.0 ? r : 0.0;
