@@ -2882,8 +2882,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
 
 // The four forms: FP32 or FP64 products, one or two operand chunks (D <= 3,
 // D <= 7).  The FP64 form with one chunk is held to 128 VGPRs (four waves per
-// SIMD; its few spills sit outside the block loop); with two chunks the cap
-// would spill the query operands of the block loop.
+// SIMD; its few spills sit outside the block loop), with two chunks to 168
+// (three waves instead of two; its spills sit outside the loops too).
 #define DFGT_MX_ARGS                                                                                             \
     const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Group *__restrict__ egrp,             \
         const int *__restrict__ eops, const int *__restrict__ headE, const int *__restrict__ cnt_dev,            \
@@ -2900,7 +2900,7 @@ __global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx32_2(DFGT_MX_ARGS) {
 __global__ __launch_bounds__(64 * kMxWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_etile_mx64_1(DFGT_MX_ARGS) {
     etile_mx_body<double, 1>(DFGT_MX_PASS);
 }
-__global__ __launch_bounds__(64 * kMxWaves) void k_etile_mx64_2(DFGT_MX_ARGS) {
+__global__ __launch_bounds__(64 * kMxWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_etile_mx64_2(DFGT_MX_ARGS) {
     etile_mx_body<double, 2>(DFGT_MX_PASS);
 }
 #undef DFGT_MX_ARGS
