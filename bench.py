@@ -258,9 +258,9 @@ def c3_bench(torch, dfgt, synth, oracle):
     out = {"workload": "5-D correlated mixture + 5% Student-t outliers, 100,000 points (Q = R), 7 bandwidths "
                        "h* x 10^-3..10^3", "h_star": hstar, "bruteforce_ms": t_bf, "rows": []}
     for pmax in (6, 2):
-        leaf, _ = dfgt.tune_leaf_size(x, hs, 1e-2, reps=1, p_max=pmax)
-        R = dfgt.build_tree(x, p_max=pmax, leaf_size=leaf)
         for eps in (1e-2, 1e-4):
+            leaf, _ = dfgt.tune_leaf_size(x, hs, eps, reps=1, p_max=pmax)
+            R = dfgt.build_tree(x, p_max=pmax, leaf_size=leaf)
             ms = median_ms(torch, lambda: dfgt.gauss_sum(R, R, hs, eps))
             G, st = dfgt.gauss_sum(R, R, hs, eps, stats=True)
             err = rel_err(G.cpu().numpy()[:, rows], ref)
