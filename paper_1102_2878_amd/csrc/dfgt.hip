@@ -705,9 +705,12 @@ __device__ __forceinline__ double coef_beta(int i, int d, int pmax) {
 // coefficient beta = f p_max + l gets c_beta sum_j F_j[f] B_j[l], one
 // multiply-add per point and coefficient (the general loop takes D loads and
 // products).  Points go 32 at a time: lane j builds F_j and B_j in registers
-// and stores them to the wave's scratch (32 (PM^(D-1) + PM) doubles, within the
-// general loop's 64 D PM); lanes then take coefficients.  The products and
-// their order per point are the general loop's: ((e H_0) H_1 ...) H_{D-1}.
+// and stores them to the wave's scratch (32 (PM^(D-1) + PM) doubles plus one
+// pad per row, within the general loop's 64 D PM); lanes then take
+// coefficients.  The rows have odd strides in doubles: with the even strides
+// PM^(D-1) and PM every lane's store of a row element hits the same LDS banks
+// (32 ways at stride 16).  The products and their order per point are the
+// general loop's: ((e H_0) H_1 ...) H_{D-1}.
 __host__ __device__ inline int direct_kind(int d, int pmax) {
     if ((d == 1 || d == 2) && pmax == 6) return d;
     if (d == 3 && pmax == 4) return 3;
@@ -720,7 +723,8 @@ __device__ __forceinline__ void direct_op(const DevTree &R, int p, int rb, int r
                                           const unsigned short *mt, const double *cb, double *acc, double *Hx,
                                           int lane) {
     constexpr int NF = D == 1 ? 1 : (D == 2 ? PM : (D == 3 ? PM * PM : (D == 4 ? PM * PM * PM : PM * PM * PM * PM)));
-    double *Fx = Hx, *Bx = Hx + 32 * NF;
+    constexpr int NFS = NF | 1, PMS = PM | 1;  // odd row strides
+    double *Fx = Hx, *Bx = Hx + 32 * NFS;
     for (int x0 = rb; x0 < re; x0 += 32) {
         const int cnt = min(32, re - x0);
         if (lane < cnt) {
@@ -758,16 +762,16 @@ __device__ __forceinline__ void direct_op(const DevTree &R, int p, int rb, int r
                 F[f] = v;
             }
 #pragma unroll
-            for (int f = 0; f < NF; ++f) Fx[lane * NF + f] = F[f];
+            for (int f = 0; f < NF; ++f) Fx[lane * NFS + f] = F[f];
 #pragma unroll
-            for (int b = 0; b < PM; ++b) Bx[lane * PM + b] = H[D - 1][b];
+            for (int b = 0; b < PM; ++b) Bx[lane * PMS + b] = H[D - 1][b];
         }
         wave_sync();
         for (int b = lane; b < P; b += 64) {
             if ((mt[b] >> 8) >= p) continue;
             const int f = b / PM, l = b - f * PM;
             double sum = 0.0;
-            for (int j = 0; j < cnt; ++j) sum = fma(Fx[j * NF + f], Bx[j * PM + l], sum);
+            for (int j = 0; j < cnt; ++j) sum = fma(Fx[j * NFS + f], Bx[j * PMS + l], sum);
             acc[b] += cb[b] * sum;
         }
         wave_sync();
