@@ -83,6 +83,7 @@ struct Group {
 struct Op {
     int r, meta;  // meta = order | (method << 8)
 };
+static_assert(sizeof(Op) == 8 && offsetof(Op, meta) == 4, "k_leaf reads an Op as one 64-bit word");
 
 // counters: the first two are reset per level, the others accumulate.  Every
 // counter and statistic sits in its own 128-byte line (CP / SP stride), so the
@@ -1302,33 +1303,35 @@ constexpr double kSqrtLn2 = 0.83255461115769775635;
 // H_{a_k}(t_k) e^{-|t|^2}), and the sum over the p^D coefficients of order < p
 // is taken one axis at a time, last axis innermost (the storage order), so a
 // coefficient costs one FMA.  Returns the polynomial part; *tt = |t|^2.
-template <int D, int PM, int K>
+// U: mu is wave-uniform (one op per wave) and read with scalar loads.
+template <int D, int PM, int K, bool U = false>
 struct FarAxis {
     __device__ __forceinline__ static double run(const double *__restrict__ mu, const double (&hs)[D][PM], int p,
                                                  int off) {
         double acc = 0.0;
 #pragma unroll
         for (int a = PM - 1; a >= 0; --a)
-            if (a < p) acc = fma(hs[K][a], FarAxis<D, PM, K + 1>::run(mu, hs, p, off * PM + a), acc);
+            if (a < p) acc = fma(hs[K][a], FarAxis<D, PM, K + 1, U>::run(mu, hs, p, off * PM + a), acc);
         return acc;
     }
 };
-template <int D, int PM>
-struct FarAxis<D, PM, D> {
+template <int D, int PM, bool U>
+struct FarAxis<D, PM, D, U> {
     __device__ __forceinline__ static double run(const double *__restrict__ mu, const double (&)[D][PM], int,
                                                  int off) {
-        return mu[off];
+        if constexpr (U) return ldc(mu + off);
+        else return mu[off];
     }
 };
 
-template <int D, int PM>
+template <int D, int PM, bool U = false>
 __device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, const double *__restrict__ rc,
                                                  const double *__restrict__ q, double s, int p, double *tt) {
     double hs[D][PM];
     double t2 = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double t = (q[k] - rc[k]) * s;
+        const double t = (q[k] - (U ? ldc(rc + k) : rc[k])) * s;
         t2 += t * t;
         double h0 = 1.0, h1 = 2.0 * t, sp = s;
         hs[k][0] = 1.0;
@@ -1343,7 +1346,7 @@ __device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, 
         }
     }
     *tt = t2;
-    return FarAxis<D, PM, 0>::run(mu, hs, p, 0);
+    return FarAxis<D, PM, 0, U>::run(mu, hs, p, 0);
 }
 
 // Local-expansion evaluation (EvalLocalExpansion) at one query for the same
@@ -1676,7 +1679,22 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                 while (idx >= segE[sp]) ++sp;
                 const int off = idx - (sp ? segE[sp - 1] : 0);
                 const int type = segT[sp];
-                if (act && fixed) {  // far-field evaluation, registers only
+                if (fixed && slots >= 64) {  // one op per wave: its moments by scalar loads
+                    const long long ov =
+                        ldc(reinterpret_cast<const long long *>(fops) + __builtin_amdgcn_readfirstlane(segS[sp] + off));
+                    const int r = (int)ov, p = (int)(ov >> 32) & 255;  // Op {r, meta}
+                    const double *mu = uniform_ptr(R.mu) + (size_t)r * P;
+                    const double *rc = uniform_ptr(R.ctr) + (size_t)r * d;
+                    double tt = 0.0, w = 0.0;
+                    switch (fixed) {
+                    case 1: w = far_eval_fixed<1, 6, true>(mu, rc, qg, s, p, &tt); break;
+                    case 2: w = far_eval_fixed<2, 6, true>(mu, rc, qg, s, p, &tt); break;
+                    case 3: w = far_eval_fixed<3, 4, true>(mu, rc, qg, s, p, &tt); break;
+                    case 4: w = far_eval_fixed<4, 2, true>(mu, rc, qg, s, p, &tt); break;
+                    default: w = far_eval_fixed<5, 2, true>(mu, rc, qg, s, p, &tt); break;
+                    }
+                    if (act && tt <= 745.0) part = fma(exp(-tt), w, part);
+                } else if (act && fixed) {  // far-field evaluation, registers only
                     const Op op = fops[segS[sp] + off];
                     const int r = op.r, p = op.meta & 255;
                     const double *mu = R.mu + (size_t)r * P;

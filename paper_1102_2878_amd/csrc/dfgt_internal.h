@@ -249,6 +249,23 @@ __device__ __forceinline__ T ldg(const T *p) {
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// A wave-uniform load through the constant address space, which the compiler
+// issues as a scalar load (s_load) into SGPRs: for data no kernel writes while
+// the caller runs, at an address every lane of the wave holds (see
+// uniform_ptr).
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+// The first active lane's copy of a pointer the wave's lanes share, in SGPRs.
+template <typename T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (const T *)(((unsigned long long)hi << 32) | lo);
+}
+
 // DPP lane moves (GFX9 row controls: row_shr:n is 0x110 + n, row_bcast:15
 // 0x142, row_bcast:31 0x143); lanes without a source lane, and rows outside
 // ROWS, receive `old`.  They stay in the vector ALU: no LDS round trip, unlike
