@@ -657,14 +657,13 @@ __device__ void traverse_segment(const DevTree *__restrict__ trees, const Job *_
 
 // One level of the traversal; the segment count comes from the previous
 // level's counters (or nseg0 at level 0), so no host round trip is needed.
-// Blocks of kTravWaves waves stride over the segments together.
-__global__ __launch_bounds__(64 * kTravWaves) void k_traverse(const DevTree *__restrict__ trees,
-                                                              const Job *__restrict__ jobs,
-                                                              const Seg *__restrict__ segs,
-                                                              const int *__restrict__ pairs,
-                                                              const int *__restrict__ lvl_in, int nseg0, int force,
-                                                              int gr, int leaf_local, int *dec, double *kus,
-                                                              TravOut o) {
+// Blocks of kTravWaves waves stride over the segments together.  Held to 168
+// VGPRs (three waves per SIMD instead of two; a few spills): the kernel waits
+// on chains of dependent loads, and more waves hide more of them.
+__global__ __launch_bounds__(64 * kTravWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_traverse(
+    const DevTree *__restrict__ trees, const Job *__restrict__ jobs, const Seg *__restrict__ segs,
+    const int *__restrict__ pairs, const int *__restrict__ lvl_in, int nseg0, int force, int gr, int leaf_local,
+    int *dec, double *kus, TravOut o) {
     __shared__ TravShared sh;
     if (*o.overflow) return;
     const int nseg = lvl_in ? min(lvl_in[C_SEG * CP], o.cap.seg) : nseg0;
