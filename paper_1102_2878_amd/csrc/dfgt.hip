@@ -1348,6 +1348,64 @@ __device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, 
     return FarAxis<D, PM, 0, U>::run(mu, hs, p, 0);
 }
 
+// Far-field evaluation (EvalFarField, eq. primal) for a dimension D fixed at
+// compile time and a runtime p_max (<= 16) and order p, for an op the whole
+// wave evaluates (its moments mu read with scalar loads): the p^D
+// coefficients of order < p are visited in storage order (axis D - 1
+// fastest) by an odometer over axes 0 .. D - 2 that keeps the products of
+// their Hermite values as prefix products, so a coefficient costs one FMA;
+// the generic loop visits all p_max^D positions with D LDS reads and
+// products each.  Hs: the lane's Hermite rows (axis k at k hs) with s^a
+// folded in.  Returns the polynomial part.
+template <int D>
+__device__ __forceinline__ double far_eval_odometer(const double *__restrict__ mu, const double *Hs, int hs,
+                                                    int pmax, int p) {
+    const double *hl = Hs + (D - 1) * hs;  // the last axis' values
+    int al[D > 1 ? D - 1 : 1], st[D > 1 ? D - 1 : 1];
+    double pre[D > 1 ? D - 1 : 1];  // pre[k] = prod_{j <= k} Hs[j][al[j]]
+    int stride = pmax;
+#pragma unroll
+    for (int k = D - 2; k >= 0; --k) {
+        st[k] = stride;
+        stride *= pmax;
+    }
+    double pr = 1.0;
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k) {
+        al[k] = 0;
+        pr *= Hs[k * hs];
+        pre[k] = pr;
+    }
+    int i = 0;
+    double w = 0.0;
+    for (;;) {
+        double inner = 0.0;
+        for (int a = 0; a < p; ++a) inner = fma(ldc(mu + i + a), hl[a], inner);
+        w = D > 1 ? fma(pre[D > 1 ? D - 2 : 0], inner, w) : inner;
+        // next position: the lowest of axes D - 2 .. 0 that can advance does,
+        // the axes after it return to 0
+        int kpos = -1;
+#pragma unroll
+        for (int k = D - 2; k >= 0; --k) {
+            if (kpos < 0) {
+                if (al[k] + 1 < p) {
+                    ++al[k];
+                    i += st[k];
+                    kpos = k;
+                } else {
+                    i -= al[k] * st[k];
+                    al[k] = 0;
+                }
+            }
+        }
+        if (kpos < 0) break;
+#pragma unroll
+        for (int k = 0; k < D - 1; ++k)
+            if (k >= kpos) pre[k] = (k ? pre[k > 0 ? k - 1 : 0] : 1.0) * Hs[k * hs + al[k]];
+    }
+    return w;
+}
+
 // Local-expansion evaluation (EvalLocalExpansion) at one query for the same
 // (D, p_max): sum_beta L_beta y^beta, y = (q - c) s, with the powers in
 // registers and the same axis-wise contraction (every coefficient: order p_max).
@@ -1387,7 +1445,10 @@ __host__ __device__ inline size_t leaf_lds_base(int nthr, int d, int pmax, int g
            (size_t)nthr * d * gr;
 }
 
-template <bool GR>
+// GEN: the form for value sums at a (D, p_max) without a compile-time
+// far-field evaluation (far_fixed_kind 0); its odometer evaluation would
+// raise the register count of the other forms.
+template <bool GR, bool GEN = false>
 __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees, const Job *__restrict__ jobs,
                                               const Group *__restrict__ egrp, const int *__restrict__ eops,
                                               const Group *__restrict__ fgrp, const Op *__restrict__ fops,
@@ -1430,7 +1491,8 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
     //      | acc[PW] | tmp[PW] | tmp2[PW] | coef[D][pmax^2] | dg[P] (u64) | mt[P] (u16)
     //      (acc / tmp / tmp2 in a global scratch slice when P is large)
     // fixed: far-field and local evaluation in registers (no Hermite rows)
-    const int fixed = GR ? 0 : far_fixed_kind(d, pmax);
+    static_assert(!(GR && GEN), "the general far-field form is for value sums");
+    const int fixed = GR || GEN ? 0 : far_fixed_kind(d, pmax);
     double *red = smem;
     double *redX = red + nthr;
     double *spow = redX + (GR ? nthr : 0);
@@ -1707,6 +1769,39 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                     default: w = far_eval_fixed<5, 2>(mu, rc, qg, s, p, &tt); break;
                     }
                     if (tt <= 745.0) part = fma(exp(-tt), w, part);
+                } else if (GEN && slots >= 64) {  // one op per wave, general (D, p_max): moments by scalar loads
+                    const long long ov =
+                        ldc(reinterpret_cast<const long long *>(fops) + __builtin_amdgcn_readfirstlane(segS[sp] + off));
+                    const int r = (int)ov, p = (int)(ov >> 32) & 255;  // Op {r, meta}
+                    const double *mu = uniform_ptr(R.mu) + (size_t)r * P;
+                    const double *rc = uniform_ptr(R.ctr) + (size_t)r * d;
+                    double tt = 0.0;
+                    for (int k = 0; k < d; ++k) {
+                        const double t = (qg[k] - ldc(rc + k)) * s;
+                        tt += t * t;
+                        hermite_polys(t, p, Hq + k * hs);
+                        for (int a = 1; a < p; ++a) Hq[k * hs + a] *= spow[a];  // s^a folded in
+                    }
+                    double w = 0.0;
+                    switch (d) {
+                    case 2: w = far_eval_odometer<2>(mu, Hq, hs, pmax, p); break;
+                    case 3: w = far_eval_odometer<3>(mu, Hq, hs, pmax, p); break;
+                    case 4: w = far_eval_odometer<4>(mu, Hq, hs, pmax, p); break;
+                    case 5: w = far_eval_odometer<5>(mu, Hq, hs, pmax, p); break;
+                    case 6: w = far_eval_odometer<6>(mu, Hq, hs, pmax, p); break;
+                    case 7: w = far_eval_odometer<7>(mu, Hq, hs, pmax, p); break;
+                    case 8: w = far_eval_odometer<8>(mu, Hq, hs, pmax, p); break;
+                    default:  // every position with D LDS reads and products
+                        for (int i = 0; i < P; ++i) {
+                            const int meta = mt[i];
+                            if ((meta >> 8) >= p) continue;
+                            const unsigned long long ad = dg[i];
+                            double prod = ldc(mu + i);
+                            for (int k = 0; k < d; ++k) prod *= Hq[k * hs + dig_at(ad, k)];
+                            w += prod;
+                        }
+                    }
+                    if (act && tt <= 745.0) part = fma(exp(-tt), w, part);
                 } else if (act) {  // every op here is a far-field evaluation
                     const Op op = fops[segS[sp] + off];
                     const int r = op.r, p = op.meta & 255;
@@ -3913,7 +4008,8 @@ void enqueue(const Plan &pl, Workspace &w, hipStream_t st, Profiler *prof, bool 
     // everything per (job, query leaf) but the exhaustive sums, beside the tiles
     {
         hipEvent_t ev = prof ? prof->start(st) : nullptr;
-        auto kl = pl.gr ? k_leaf<true> : k_leaf<false>;
+        auto kl = pl.gr ? k_leaf<true, false>
+                        : (far_fixed_kind(pl.d, pl.pmax) ? k_leaf<false, false> : k_leaf<false, true>);
         hipLaunchKernelGGL(kl, dim3(pl.items), dim3(pl.leaf_threads), pl.leaf_sh, st, td, jd, w.egrp.as<Group>(),
                            w.eops.as<int>(), w.fgrp.as<Group>(), w.fops.as<Op>(), w.lgrp.as<Group>(),
                            w.lops.as<Op>(), headE, headF, headL, w.L.as<double>(), w.lflag.as<unsigned char>(),

@@ -136,6 +136,23 @@ def test_forced_far_field_each_dimension(dfgt, d, eps):
     assert st["prune_f"] > 0, st
 
 
+@pytest.mark.parametrize("d,pmax", [(3, 6), (4, 4), (5, 3), (6, 3), (8, 2), (10, 2)])
+@pytest.mark.parametrize("eps", [1e-2, 1e-5])
+def test_forced_far_field_general_orders(dfgt, d, pmax, eps):
+    # far-field evaluation alone at (D, p_max) pairs without a compile-time form:
+    # leaves of up to 128 queries, so a wave evaluates one op for 64 queries
+    # (the odometer over the p^D coefficients, D <= 8; the generic loop above)
+    x = synth.c3(n=3000, seed=31 + d)
+    x = np.concatenate([x] * ((d + 4) // 5), axis=1)[:, :d] if d > 5 else x[:, :d]
+    hs = [synth.silverman_h(x) * s for s in (1.0, 10.0, 100.0)]
+    note(f"dfgt force F d={d} pmax={pmax} eps={eps}")
+    G, st = _run(dfgt, x, None, hs, eps, leaf=128, force=1, pmax=pmax, ce=100.0)
+    for k, h in enumerate(hs):
+        rel = _rel_err(G[k], oracle.naive_kde(x, x, h))
+        assert rel.max() <= eps, (d, pmax, h, rel.max())
+    assert st["prune_f"] > 0, st
+
+
 def test_ragged_leaf_sizes_and_tiny_inputs(dfgt):
     rng = np.random.default_rng(26)
     for n, leaf in ((1, 32), (2, 1), (33, 32), (257, 7), (1000, 100), (700, 300)):
