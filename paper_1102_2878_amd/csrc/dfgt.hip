@@ -67,6 +67,8 @@ struct Job {
                                // sums within their rounding budget; <= 0: FP64 differences only
     double r32;                // largest query-leaf half-diagonal (sig units) for which the
                                // matrix-core tiles' FP32 products keep that budget; <= 0: FP64
+    double win;                // staging window of the matrix-core tiles (sig units): references
+                               // farther than win from the query leaf are left out (t >= win^2)
 };
 
 struct Seg {
@@ -1976,7 +1978,7 @@ constexpr int kMxOps = 64 * kMxWaves;  // E ops flattened per chunk: one per thr
 constexpr int kMxQ = 64 * kMxWaves;    // queries held per pass over the chain (4 blocks per wave)
 constexpr int kMxSeg = 1024;           // 64-point segments of a chunk with a table entry
 constexpr double kMxWideQ = 4096.0;    // 2^12
-constexpr double kMxNear32 = 12.0;     // staged radius beyond rho in the FP32 form; box gap in the FP64 form
+constexpr double kMxNear32 = 12.0;     // staging window when G has no lower bound (t >= 144 left out)
 
 // Dispatch order of the mixed pass's exhaustive tiles (longest first): the
 // items whose E chain holds >= kEHeavyOps ops of the mixed pass, then those
@@ -2560,20 +2562,24 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 // partials are reduced across lanes and added in FP64, in a fixed order.
 // Two precisions of the product, chosen per item by k_eorder from the query
 // leaf's half-diagonal rho in sig units:
-//   FP32 (rho <= Job::r32): a reference is staged only when
-//     |b| <= rho + 12; the others have t >= 144 (terms below the FP32 flush
-//     the mixed sums already allow for) and are staged with weight 0.  Then
-//     A = |a| + |b| <= 2 rho + 12, and the FP32 rounding of the operands and
-//     of the four multiply-adds moves t by at most 6.5 u A^2 (u = 2^-24);
-//     r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) + 68 u (weight, partials)
-//     within the rounding budget.
+// Staging window W = Job::win: a reference farther than W (sig units) from
+// the query leaf has t >= W^2 for every query and is left out.  W = 12 in
+// general (terms below 2^-144, under the FP32 flush the mixed sums already
+// allow for); when Q = R, unweighted and not leave-one-out, every G(q) >= 1
+// (the self term) and the at most N_R left-out terms stay within a share
+// eps_round / 50 of G(q) for W^2 = log2(N_R / (eps_round / 50)) (W ~ 6).
+//   FP32 (rho <= Job::r32): a reference is staged only when |b| <= rho + W,
+//     the others with weight 0.  Then A = |a| + |b| <= 2 rho + W, and the
+//     FP32 rounding of the operands and of the four multiply-adds moves t by
+//     at most 6.5 u A^2 (u = 2^-24); r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) +
+//     68 u (weight, partials), plus the window's share, within the rounding
+//     budget.
 //   FP64 (rho <= kMxWideQ): a reference is staged only when its distance to
-//     the query leaf's bounding box is <= 12 (in sig units): the others have
-//     t >= 144 for every query of the leaf, as above.  The kept points are
+//     the query leaf's bounding box is <= W.  The kept points are
 //     packed at the front of each wave's 64-point region of the round (a
 //     ballot gives their ranks), padded to a multiple of 16; those big leaves
 //     see many such far references, which are then neither multiplied nor
-//     exponentiated.  Then A <= 2 rho + 12 <= 2^13 + 12 and the FP64 rounding
+//     exponentiated.  Then A <= 2 rho + W <= 2^13 + 12 and the FP64 rounding
 //     of t, ~12 2^-53 A^2, stays below 1e-7, under the FP32 rounding of t
 //     itself.
 //   Wider leaves go to the vector-ALU tiles.
@@ -2717,7 +2723,8 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     }
     rho = std::sqrt(rho) * sig;
     // squared staging radius: beyond it a term is zero to the form's precision
-    const double bcut = (rho + kMxNear32) * (rho + kMxNear32);
+    const double win = jb.win;
+    const double bcut = (rho + win) * (rho + win);
     for (int qs = 0; qs < nq; qs += kMxQ) {
         const int nqs = min(kMxQ, nq - qs);
         const int nqb = (nqs + 15) >> 4;  // query blocks of the pass
@@ -2863,7 +2870,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                             gap = fma(o, o, gap);
                         }
                     }
-                    keep = keep && gap <= kMxNear32 * kMxNear32;
+                    keep = keep && gap <= win * win;
                     const unsigned long long m = __ballot(keep);
                     const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                     const int nk = __popcll(m), nk16 = (nk + 15) & ~15;
@@ -3555,18 +3562,33 @@ double etile_a32(double eps_round, int d) {
     return a > 0.0 ? a : 0.0;
 }
 
+// Share of the rounding budget of the mixed exhaustive sums given to the
+// references the matrix-core tiles leave out when G(q) >= 1.
+constexpr double kMxDropShare = 1.0 / 50.0;
+
+// Staging window (sig units) of the matrix-core tiles: with G(q) >= 1 (the
+// self term of a monochromatic, unweighted sum) the at most n_r left-out
+// terms, each below 2^-W^2, stay within eps_round kMxDropShare of G(q) when
+// W^2 = log2(n_r / (eps_round kMxDropShare)); otherwise kMxNear32.
+double mx_window(double eps_round, bool g_ge_1, double n_r) {
+    if (!g_ge_1 || !(eps_round > 0.0)) return kMxNear32;
+    const double w = std::sqrt(std::log2(std::max(n_r, 1.0) / (eps_round * kMxDropShare)));
+    return std::min(w, kMxNear32);
+}
+
 // Largest query-leaf half-diagonal rho (sig units) for the FP32 products of
-// the matrix-core tiles: their staged pairs have |a| + |b| <= A = 2 rho +
-// kMxNear32, t moves by at most 6.5 u A^2 (u = 2^-24: operand roundings and
-// four FP32 multiply-adds), and a term's relative error ln2 6.5 u A^2 +
-// 2^-22 (exp2) + u (the weight), plus 67 u for the FP32 partial sums (63
-// within a lane, 4 across the lanes of a row), must stay within eps_round.
+// the matrix-core tiles with staging window win: their staged pairs have
+// |a| + |b| <= A = 2 rho + win, t moves by at most 6.5 u A^2 (u = 2^-24:
+// operand roundings and four FP32 multiply-adds), and a term's relative
+// error ln2 6.5 u A^2 + 2^-22 (exp2) + u (the weight), plus 67 u for the FP32
+// partial sums (63 within a lane, 4 across the lanes of a row), plus the
+// left-out terms' share when win < kMxNear32, must stay within eps_round.
 // Returns 0 when no rho > 0 does (FP64 products).
-double mx_r32(double eps_round) {
+double mx_r32(double eps_round, double win) {
     const double u = 0x1p-24, ln2 = 0.69314718055994530942;
-    const double rest = eps_round - 0x1p-22 - 68.0 * u;
+    const double rest = eps_round - 0x1p-22 - 68.0 * u - (win < kMxNear32 ? eps_round * kMxDropShare : 0.0);
     if (rest <= 0.0) return 0.0;
-    const double r = 0.5 * (std::sqrt(rest / (6.5 * ln2 * u)) - kMxNear32);
+    const double r = 0.5 * (std::sqrt(rest / (6.5 * ln2 * u)) - win);
     return r > 0.0 ? r : 0.0;
 }
 
@@ -3609,7 +3631,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
     const double eps_round = precision == DFGT_PREC_FP64 ? 1e-12 : (eps >= 2e-3 ? 1e-4 : 1e-5);
     const double eps_eff = eps > 2.0 * eps_round ? eps - eps_round : 0.0;
     const double a32 = precision == DFGT_PREC_MIXED && grad == nullptr ? etile_a32(eps_round, t0->d) : 0.0;
-    const double r32 = precision == DFGT_PREC_MIXED && grad == nullptr ? mx_r32(eps_round) : 0.0;
+    const bool mxr = precision == DFGT_PREC_MIXED && grad == nullptr;  // FP32 products possible
     // a query leaf's own local ops are applied inside k_leaf when its per-wave
     // scratch fits; otherwise they go through the node kernels
     pl.leaf_local = pl.P <= 512;
@@ -3674,7 +3696,8 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             j.loo = loo ? 1 : 0;
             pl.loo = pl.loo || loo;
             j.a32 = a32;
-            j.r32 = r32;
+            j.win = precision == DFGT_PREC_MIXED ? mx_window(eps_round, j.mono != 0, j.cntR) : kMxNear32;
+            j.r32 = mxr ? mx_r32(eps_round, j.win) : 0.0;
             pl.jobs.push_back(j);
             nna += q.Q->m;
             nqa += q.Q->n;
