@@ -1359,7 +1359,9 @@ __device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, 
 // the generic loop visits all p_max^D positions with D LDS reads and
 // products each.  Hs: the lane's Hermite rows (axis k at k hs) with s^a
 // folded in.  Returns the polynomial part.
-template <int D>
+// SC: the coefficients are read with scalar loads (moments no kernel writes
+// meanwhile); otherwise with ordinary loads (the block's own local moments).
+template <int D, bool SC = true>
 __device__ __forceinline__ double far_eval_odometer(const double *__restrict__ mu, const double *Hs, int hs,
                                                     int pmax, int p) {
     const double *hl = Hs + (D - 1) * hs;  // the last axis' values
@@ -1382,7 +1384,7 @@ __device__ __forceinline__ double far_eval_odometer(const double *__restrict__ m
     double w = 0.0;
     for (;;) {
         double inner = 0.0;
-        for (int a = 0; a < p; ++a) inner = fma(ldc(mu + i + a), hl[a], inner);
+        for (int a = 0; a < p; ++a) inner = fma(SC ? ldc(mu + i + a) : mu[i + a], hl[a], inner);
         w = D > 1 ? fma(pre[D > 1 ? D - 2 : 0], inner, w) : inner;
         // next position: the lowest of axes D - 2 .. 0 that can advance does,
         // the axes after it return to 0
@@ -1882,7 +1884,21 @@ __global__ __launch_bounds__(256) void k_leaf(const DevTree *__restrict__ trees,
                         v *= yk;
                     }
                 }
-                for (int i = 0; i < P; ++i) {
+                // the GEN form (value sums, D <= 8): every coefficient by the
+                // odometer, one FMA each (the same polynomial, summed in
+                // storage order)
+                if (GEN && d >= 2 && d <= 8) {
+                    switch (d) {
+                    case 2: gl = far_eval_odometer<2, false>(acc, yp, hs, pmax, pmax); break;
+                    case 3: gl = far_eval_odometer<3, false>(acc, yp, hs, pmax, pmax); break;
+                    case 4: gl = far_eval_odometer<4, false>(acc, yp, hs, pmax, pmax); break;
+                    case 5: gl = far_eval_odometer<5, false>(acc, yp, hs, pmax, pmax); break;
+                    case 6: gl = far_eval_odometer<6, false>(acc, yp, hs, pmax, pmax); break;
+                    case 7: gl = far_eval_odometer<7, false>(acc, yp, hs, pmax, pmax); break;
+                    default: gl = far_eval_odometer<8, false>(acc, yp, hs, pmax, pmax); break;
+                    }
+                }
+                for (int i = 0; i < P && !(GEN && d >= 2 && d <= 8); ++i) {
                     const double a = acc[i];
                     const double aB = GR ? acc[P + i] : 0.0;
                     if (a == 0.0 && aB == 0.0) continue;
