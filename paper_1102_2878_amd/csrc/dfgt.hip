@@ -1350,17 +1350,20 @@ __device__ __forceinline__ double far_eval_fixed(const double *__restrict__ mu, 
     return FarAxis<D, PM, 0, U>::run(mu, hs, p, 0);
 }
 
-// Far-field evaluation (EvalFarField, eq. primal) for a dimension D fixed at
-// compile time and a runtime p_max (<= 16) and order p, for an op the whole
-// wave evaluates (its moments mu read with scalar loads): the p^D
-// coefficients of order < p are visited in storage order (axis D - 1
-// fastest) by an odometer over axes 0 .. D - 2 that keeps the products of
-// their Hermite values as prefix products, so a coefficient costs one FMA;
-// the generic loop visits all p_max^D positions with D LDS reads and
-// products each.  Hs: the lane's Hermite rows (axis k at k hs) with s^a
-// folded in.  Returns the polynomial part.
-// SC: the coefficients are read with scalar loads (moments no kernel writes
-// meanwhile); otherwise with ordinary loads (the block's own local moments).
+// sum over alpha in [0, p)^D of mu[alpha] prod_k Hs[k][alpha_k], for a
+// dimension D fixed at compile time and a runtime p_max (<= 16, the radix of
+// the storage order) and p <= p_max.  Far-field evaluation (EvalFarField, eq.
+// primal): mu the op's moments, Hs the lane's Hermite rows with s^a folded
+// in, p the op's order.  Local-expansion evaluation (EvalLocalExpansion): mu
+// the leaf's local moments, Hs the lane's power rows, p = p_max.  The
+// coefficients are visited in storage order (axis D - 1 fastest) by an
+// odometer over axes 0 .. D - 2 that keeps the products of their row values
+// as prefix products, so a coefficient costs one FMA; the generic loop visits
+// all p_max^D positions with D LDS reads and products each.  Rows: axis k at
+// Hs + k hs.
+// SC: mu is read with scalar loads (an op the whole wave evaluates, moments
+// no kernel writes meanwhile); otherwise with ordinary loads (the block's
+// own local moments).
 template <int D, bool SC = true>
 __device__ __forceinline__ double far_eval_odometer(const double *__restrict__ mu, const double *Hs, int hs,
                                                     int pmax, int p) {
@@ -1386,8 +1389,8 @@ __device__ __forceinline__ double far_eval_odometer(const double *__restrict__ m
         double inner = 0.0;
         for (int a = 0; a < p; ++a) inner = fma(SC ? ldc(mu + i + a) : mu[i + a], hl[a], inner);
         w = D > 1 ? fma(pre[D > 1 ? D - 2 : 0], inner, w) : inner;
-        // next position: the lowest of axes D - 2 .. 0 that can advance does,
-        // the axes after it return to 0
+        // next position: the fastest of axes D - 2 .. 0 that can still advance
+        // does, and the faster ones return to 0
         int kpos = -1;
 #pragma unroll
         for (int k = D - 2; k >= 0; --k) {
