@@ -2574,11 +2574,13 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 // Coordinates are taken relative to the query leaf's box centre c and scaled
 // by sig: a = sig (q - c), b = sig (r - c), so that t = |a - b|^2 and the
 // kernel value is 2^-t.  With the K = 4 NC operand rows
-//     A_i = (a_i, 1, 0, ...),   B_j = (2 b_j, -|b_j|^2, 0, ...),   C_i = -|a_i|^2
-// NC v_mfma_*_16x16x4 instructions give -t for a block of 16 queries x 16
-// references.  The lanes take the hardware exp2 of -t (rounded to FP32 once
-// in the FP64 form) and add w_j 2^-t into FP32 partials of <= 64 terms; the
-// partials are reduced across lanes and added in FP64, in a fixed order.
+//     A_i = (a_i, 1, 0, ...),   B_j = (2 b_j, log2 w_j - |b_j|^2, 0, ...),   C_i = -|a_i|^2
+// NC v_mfma_*_16x16x4 instructions give log2 w_j - t for a block of 16
+// queries x 16 references (a reference of weight 0 has -1e30 in place of
+// log2 w_j - |b_j|^2).  The lanes take the hardware exp2 of it (rounded to
+// FP32 once in the FP64 form), w_j 2^-t, and add it into FP32 partials of
+// <= 64 terms; the partials are reduced across lanes and added in FP64, in
+// a fixed order.
 // Two precisions of the product, chosen per item by k_eorder from the query
 // leaf's half-diagonal rho in sig units:
 // Staging window W = Job::win: a reference farther than W (sig units) from
@@ -2591,7 +2593,8 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 //     the others with weight 0.  Then A = |a| + |b| <= 2 rho + W, and the
 //     FP32 rounding of the operands and of the four multiply-adds moves t by
 //     at most 6.5 u A^2 (u = 2^-24); r32 keeps ln2 6.5 u A^2 + 2^-22 (exp2) +
-//     68 u (weight, partials), plus the window's share, within the rounding
+//     68 u (weight, partials), plus the window's share and, for a weighted
+//     tree, ln2 126 u for log2 w in the rounded row, within the rounding
 //     budget.
 //   FP64 (rho <= kMxWideQ): a reference is staged only when its distance to
 //     the query leaf's bounding box is <= W.  The kept points are
@@ -2617,6 +2620,16 @@ __global__ __launch_bounds__(64 * kEWaves) __attribute__((amdgpu_waves_per_eu(4)
 // g = l / 16): A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k; result
 // register r holds D[4 r + g][l % 16] (FP64) or D[4 g + r][l % 16] (FP32).
 // Here A = 16 queries x 4 rows, B = 4 rows x 16 references.
+
+// The operand row of a reference's weight: log2 w (0 for the unit weights
+// of an unweighted tree), or kMxZeroRow for a weight of 0 or below 2^-126
+// (a term under the FP32 flush), which sends the products to -1e30 and the
+// exponential to 0 without an infinity.
+constexpr double kMxZeroRow = -1e30;
+__device__ __forceinline__ double mx_log2w(float w) {
+    if (w == 1.0f) return 0.0;
+    return w >= 0x1p-126f ? log2((double)w) : kMxZeroRow;
+}
 
 template <typename T, int NC>
 struct MxShape {
@@ -2663,7 +2676,6 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
     __shared__ unsigned char segop[kMxSeg];  // op holding the chunk's point 64 s
     __shared__ int wsum[kMxWaves], nops_s, take_s;
     __shared__ T sB[2][K][RND];           // reference operand rows of a round, two buffers (rows past D + 1 zero)
-    __shared__ float sW[2][RND];          // reference weights (0: padding or a zero term)
     __shared__ double sA[K][kMxQ];        // query operand rows of the pass
     __shared__ double sN[kMxQ];           // |a|^2 of the pass's queries
     __shared__ double sQ[kMxWaves][64];   // per-wave FP64 sums per query of its set
@@ -2894,16 +2906,13 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                     const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                     const int nk = __popcll(m), nk16 = (nk + 15) & ~15;
                     if (keep) {
+                        const double nl = mx_log2w(pw[0]) - nb;
 #pragma unroll
-                        for (int c = 0; c < K; ++c)
-                            sB[buf][c][j0 + rank] = c < d ? 2.0 * bk[c] : (c == d ? -nb : 0.0);
-                        sW[buf][j0 + rank] = pw[0];
+                        for (int c = 0; c < K; ++c) sB[buf][c][j0 + rank] = c < d ? 2.0 * bk[c] : (c == d ? nl : 0.0);
                     }
                     if (lane >= nk && lane < nk16) {  // zero-weight padding of the last block
 #pragma unroll
-                        for (int c = 0; c < K; ++c)
-                            sB[buf][c][j0 + lane] = 0.0;
-                        sW[buf][j0 + lane] = 0.0f;
+                        for (int c = 0; c < K; ++c) sB[buf][c][j0 + lane] = c == d ? kMxZeroRow : 0.0;
                     }
                     if (lane == 0) sCnt[buf][wv] = nk16;
                     return;
@@ -2930,10 +2939,9 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
 #pragma unroll
                         for (int c = 0; c < DX; ++c) bk[c] = 0.0;
                     }
+                    const double nl = mx_log2w(w) - nb;
 #pragma unroll
-                    for (int c = 0; c < K; ++c)
-                        sB[buf][c][jj] = (T)(c < d ? 2.0 * bk[c] : (c == d ? -nb : 0.0));
-                    sW[buf][jj] = w;
+                    for (int c = 0; c < K; ++c) sB[buf][c][jj] = (T)(c < d ? 2.0 * bk[c] : (c == d ? nl : 0.0));
                 }
             };
             load_round(0);
@@ -2979,7 +2987,6 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                         T bv[NC];
 #pragma unroll
                         for (int c = 0; c < NC; ++c) bv[c] = sB[buf][4 * c + g][j];
-                        const float wj = sW[buf][j];
                         VT t[NB];
 #pragma unroll
                         for (int b = 0; b < NB; ++b) {
@@ -2991,7 +2998,7 @@ __device__ __forceinline__ void etile_mx_body(const DevTree *__restrict__ trees,
                         for (int b = 0; b < NB; ++b)
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                acc[b][r] = fmaf(wj, __builtin_amdgcn_exp2f((float)t[b][r]), acc[b][r]);
+                                acc[b][r] += __builtin_amdgcn_exp2f((float)t[b][r]);
                         if (++nblk == 64) {
                             flush();
                             nblk = 0;
@@ -3602,10 +3609,13 @@ double mx_window(double eps_round, bool g_ge_1, double n_r) {
 // error ln2 6.5 u A^2 + 2^-22 (exp2) + u (the weight), plus 67 u for the FP32
 // partial sums (63 within a lane, 4 across the lanes of a row), plus the
 // left-out terms' share when win < kMxNear32, must stay within eps_round.
-// Returns 0 when no rho > 0 does (FP64 products).
-double mx_r32(double eps_round, double win) {
+// A weighted tree adds log2 w (|log2 w| <= 126) to the -|b|^2 row before it
+// is rounded: ln2 126 u more.  Returns 0 when no rho > 0 does (FP64
+// products).
+double mx_r32(double eps_round, double win, bool weighted) {
     const double u = 0x1p-24, ln2 = 0.69314718055994530942;
-    const double rest = eps_round - 0x1p-22 - 68.0 * u - (win < kMxNear32 ? eps_round * kMxDropShare : 0.0);
+    const double rest = eps_round - 0x1p-22 - 68.0 * u - (win < kMxNear32 ? eps_round * kMxDropShare : 0.0) -
+                        (weighted ? ln2 * 126.0 * u : 0.0);
     if (rest <= 0.0) return 0.0;
     const double r = 0.5 * (std::sqrt(rest / (6.5 * ln2 * u)) - win);
     return r > 0.0 ? r : 0.0;
@@ -3716,7 +3726,7 @@ dfgt_status make_plan(const Problem *pr, int np, double eps, int precision, int 
             pl.loo = pl.loo || loo;
             j.a32 = a32;
             j.win = precision == DFGT_PREC_MIXED ? mx_window(eps_round, j.mono != 0, j.cntR) : kMxNear32;
-            j.r32 = mxr ? mx_r32(eps_round, j.win) : 0.0;
+            j.r32 = mxr ? mx_r32(eps_round, j.win, q.R->weighted) : 0.0;
             pl.jobs.push_back(j);
             nna += q.Q->m;
             nqa += q.Q->n;
