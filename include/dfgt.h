@@ -119,7 +119,9 @@ typedef struct dfgt_stats {
                                h for either (vector-ALU tiles); all 0 at
                                precision FP64 or with D >= 8 */
     int64_t e_pairs[2];     /* exhaustive point pairs of the matrix-core tiles with
-                               FP32 [0] and FP64 [1] products (value sums, 3 <= D <= 7) */
+                               FP32 [0] and FP64 [1] products (value sums, 3 <= D <= 7),
+                               counting the references the tiles leave out as beyond
+                               their staging window (terms below the rounding budget) */
     /* With dfgt_options.profile = 1: summed event time (ms) and launch count
      * per kernel: [0] traversal (bounds, ChooseBestMethod, list emission),
      * [1] per-query-leaf kernel (far-field evaluation, local-to-local walk,
