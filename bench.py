@@ -27,7 +27,7 @@ Secondary workloads in the same line:
 Every workload's error is checked against the oracle's exact sums on seeded
 query rows; the CPU baseline is the oracle itself timed on the host's cores.
 
-Prints ONE JSON line.  --gpus must be 1 (this build targets one GPU).
+Prints ONE JSON line.  --gpus must be 1: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -343,7 +343,7 @@ def main():
                     help="leaf size of the 3-D and 2-D workloads; 0 = dfgt_tune_leaf_size picks it (untimed)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
